@@ -1,0 +1,329 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage or property it checks.  None of them re-types the
+oracle's own formulas: they compare it with the fine-grid solve, with closed
+forms, with limits the paper states, with library routines and with the
+counts the paper prints.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from mrcm_inputs import IfaceSpace, Partition, Problem, Case, small_case, uniform_cuts
+from oracle.banded import band_cholesky, band_solve, bandwidth, to_band
+from oracle.fine import fine_solve, fine_system
+from oracle.geometry import Geometry, count_interface_unknowns, split_index, split_sizes
+from oracle.monolithic import dirichlet_local, mrcm_monolithic, neumann_local
+from oracle.mrcm import local_system, mrcm_solve, reconstruct_resolve
+from oracle.norms import rel_kinv_velocity, rel_l2, rel_l2_pressure
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- T1 ------
+@pytest.mark.parametrize("seed", [0, 1])
+def test_single_subdomain_equals_fine(seed):
+    """With one subdomain there is no skeleton (N_V = 0), so the MRCM local
+    problem is the fine problem (Sec. 2.2: the methods differ only on Gamma)."""
+    c = small_case((7, 5, 4), (1, 1, 1), seed=seed)
+    pf, Uf = fine_solve(c.problem)
+    r = mrcm_solve(c)
+    assert r.geo.n_patch == 0
+    assert rel_l2(r.p, pf) < 1e-13
+    assert rel_l2(r.U, Uf) < 1e-13
+
+
+# ---------------------------------------------------------------- T2 ------
+@pytest.mark.parametrize("alpha", [1e-3, 1.0, 1e3])
+@pytest.mark.parametrize("nd", [(2, 2, 2), (3, 2, 1)])
+def test_fine_trace_reproduces_fine_solution(alpha, nd):
+    """Sec. 2.2: taking P_H = P_h and U_H = U_h (one patch per fine face) makes
+    the MRCM and fine-grid solutions coincide, for any Robin parameter."""
+    c = small_case((9, 6, 4), nd, split=((0, 0), (0, 0), (0, 0)), seed=3, alpha=alpha)
+    pf, Uf = fine_solve(c.problem)
+    r = mrcm_solve(c)
+    assert rel_l2(r.p, pf) < 1e-10
+    assert rel_l2(r.U, Uf) < 1e-9
+
+
+def test_fine_trace_with_dirichlet_and_neumann_walls():
+    """Same statement with non-homogeneous wall data (eqs. (2.5), (2.6)) and no pin."""
+    c = small_case((8, 6, 4), (2, 2, 2), split=((0, 0), (0, 0), (0, 0)), seed=4, pin=-1)
+    pb = c.problem
+    rng = np.random.default_rng(9)
+    pb.wall_type = [1, 2, 0, 2, 1, 0]
+    pb.wall_value = [rng.standard_normal(6 * 4), 0.1 * rng.standard_normal(6 * 4), None,
+                     0.1 * rng.standard_normal(8 * 4), rng.standard_normal(8 * 6), None]
+    pf, Uf = fine_solve(pb)
+    r = mrcm_solve(c)
+    assert rel_l2(r.p, pf) < 1e-10
+    assert rel_l2(r.U, Uf) < 1e-9
+    # Dirichlet data is met in the half-cell sense: Q = A 2K/h (p - g)
+    assert np.allclose(Uf[0, ::8], 2.0 * pb.kx[::8] * (pf[::8] - pb.wall_value[0]), rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------- T3 ------
+def _linear_case(nd, alpha, split=((1, 1), (1, 1), (1, 1)), s=0.7, K=2.5, dims=(12, 6, 4)):
+    nx, ny, nz = dims
+    N = nx * ny * nz
+    h = (2.0, 1.0, 0.5)
+    Ax = h[1] * h[2]
+    q = np.zeros(N)
+    for k in range(nz):
+        for j in range(ny):
+            q[0 + nx * (j + ny * k)] = s * Ax
+            q[nx - 1 + nx * (j + ny * k)] = -s * Ax
+    kk = np.full(N, K)
+    pin = nx - 1
+    pb = Problem(nx, ny, nz, *h, kk, kk.copy(), kk.copy(), q, pin=pin)
+    cuts = [np.linspace(0, n, m + 1).round().astype(np.int32) for n, m in zip(dims, nd)]
+    return Case("linear", pb, Partition(*cuts), IfaceSpace(split), alpha)
+
+
+def test_linear_pressure_fine_exact():
+    """Constant K and a uniform x-flux s: every x-face carries velocity s, so
+    p = -(s h_x / K) i + const is the exact TPFA solution (eqs. (2.9), (2.12))."""
+    c = _linear_case((1, 1, 1), 1.0)
+    pb = c.problem
+    p, U = fine_solve(pb)
+    i = np.arange(pb.n) % pb.nx
+    exact = -(0.7 * pb.hx / 2.5) * (i - (pb.nx - 1))
+    assert np.max(np.abs(p - exact)) < 1e-12
+    ux = U[1].reshape(pb.nz, pb.ny, pb.nx)[:, :, :-1]
+    assert np.allclose(ux, 0.7, rtol=1e-12)
+
+
+@pytest.mark.parametrize("alpha", [1e-2, 1.0, 1e2])
+def test_linear_pressure_mrcm_exact_for_normal_cuts(alpha):
+    """With cuts only normal to grad p the true trace and flux are constant on
+    each interface, so they lie in the patch spaces and the MRCM is exact for
+    every alpha (uniqueness of (2.13)-(2.16))."""
+    c = _linear_case((3, 1, 1), alpha, split=((2, 2), (1, 1), (1, 1)))
+    pf, Uf = fine_solve(c.problem)
+    r = mrcm_solve(c)
+    assert np.max(np.abs(r.p - pf)) < 1e-10
+    assert rel_l2(r.U, Uf) < 1e-10
+
+
+def test_linear_pressure_parallel_cuts_error_decays_as_one_over_alpha():
+    """With interfaces parallel to the flow the true normal flux (zero) is a
+    patch constant but the trace varies along x: the flux-continuity limit
+    (alpha -> infinity) is exact and the MRCM error decays like 1/alpha."""
+    errs = []
+    alphas = [1e2, 1e3, 1e4]
+    for a in alphas:
+        c = _linear_case((1, 2, 1), a)
+        pf, _ = fine_solve(c.problem)
+        r = mrcm_solve(c)
+        errs.append(rel_l2(r.p, pf))
+    slopes = np.diff(np.log10(errs)) / np.diff(np.log10(alphas))
+    assert np.all(np.abs(slopes + 1.0) < 0.1), (errs, slopes)
+
+
+# ---------------------------------------------------------------- T4 ------
+def test_mass_conservation_per_cell_and_per_patch():
+    """Each cell balances its own face fluxes against its source (the local
+    problems are solved exactly), and each patch carries zero net flux, which
+    is (2.15) tested with the patch indicator (Sec. 3.2.5: the MRCM is
+    conservative on the support of the interface basis functions)."""
+    c = small_case((10, 8, 6), (2, 2, 3), split=((2, 1), (1, 2), (2, 2)), seed=5, std=2.0)
+    pb = c.problem
+    r = mrcm_solve(c)
+    A = np.array([pb.hy * pb.hz, pb.hx * pb.hz, pb.hx * pb.hy])
+    Q = r.U * np.repeat(A, 2)[:, None]
+    net = Q.sum(axis=0) - pb.q
+    scale = np.abs(Q).sum(axis=0) + np.abs(pb.q)
+    assert np.max(np.abs(net)) < 1e-12 * np.max(scale)
+    # per patch: sum over both sides of the outward fluxes
+    geo = r.geo
+    bal = np.zeros(geo.n_patch)
+    mag = np.zeros(geo.n_patch)
+    for t in range(len(geo.ifaces)):
+        d = geo.ifaces[t]["d"]
+        lo, hi, patch = geo.iface_faces(t)
+        qlo = Q[2 * d + 1, lo]
+        qhi = Q[2 * d, hi]
+        np.add.at(bal, patch, qlo + qhi)
+        np.add.at(mag, patch, np.abs(qlo) + np.abs(qhi))
+    assert np.max(np.abs(bal) / mag) < 1e-11
+
+
+# ---------------------------------------------------------------- T5 ------
+def test_alpha_limits():
+    """alpha -> 0 tends to pressure data on Gamma with weak flux continuity
+    (error O(alpha)); alpha -> infinity tends to flux data with weak pressure
+    continuity (error O(1/alpha)) -- the two limits named in the Introduction
+    and in Sec. 3.2.4."""
+    base = dict(dims=(8, 6, 4), nd=(2, 2, 2), split=((2, 1), (1, 2), (2, 2)), seed=2)
+    c = small_case(**base)
+    pd, _ = dirichlet_local(c)
+    pn, _ = neumann_local(c)
+    small = [1e-3, 1e-4, 1e-5]
+    large = [1e2, 1e3, 1e4]
+    ed = [rel_l2(mrcm_solve(small_case(alpha=a, **base)).p, pd) for a in small]
+    en = [rel_l2(mrcm_solve(small_case(alpha=a, **base)).p, pn) for a in large]
+    sd = np.diff(np.log10(ed)) / np.diff(np.log10(small))
+    sn = np.diff(np.log10(en)) / np.diff(np.log10(large))
+    assert np.all(np.abs(sd - 1.0) < 0.1), (ed, sd)
+    assert np.all(np.abs(sn + 1.0) < 0.1), (en, sn)
+
+
+# ---------------------------------------------------------------- T6 ------
+def test_reconstruction_options_agree():
+    """After (2.23) the paper gives two ways to recover the solution: combine
+    stored MBFs, or solve the local problems again with the interface data."""
+    c = small_case((8, 8, 4), (2, 2, 2), split=((1, 2), (2, 1), (2, 2)), seed=6)
+    r = mrcm_solve(c)
+    p2 = reconstruct_resolve(c.problem, r.geo, r.systems, r.pi)
+    assert rel_l2(p2, r.p) < 1e-12
+
+
+# ---------------------------------------------------------------- T7 ------
+@pytest.mark.parametrize("split", [((1, 1), (1, 1), (1, 1)), ((2, 2), (1, 2), (2, 1))])
+def test_monolithic_equals_mbf_path(split):
+    """All local pressures and interface unknowns solved as one system, with
+    no MBFs and no superposition, equal the MBF path of Algorithm 2."""
+    c = small_case((8, 6, 6), (2, 2, 3), split=split, seed=7, std=1.5)
+    r = mrcm_solve(c)
+    pm, pim = mrcm_monolithic(c)
+    assert rel_l2(r.p, pm) < 1e-11
+    assert rel_l2(r.pi, pim) < 1e-10
+
+
+def test_ragged_partition_monolithic():
+    c = small_case((9, 7, 5), (3, 2, 2), split=((2, 1), (1, 1), (2, 2)), seed=8,
+                   parts=([2, 4, 3], [3, 4], [2, 3]))
+    r = mrcm_solve(c)
+    pm, _ = mrcm_monolithic(c)
+    assert rel_l2(r.p, pm) < 1e-11
+
+
+# ---------------------------------------------------------------- T8 ------
+def test_interface_matrix_structure():
+    """A^UP = -(A^PU)^T, A^PP and A^UU symmetric, A^PP <= 0, A^UU < 0.
+    (A^PP is minus a sum of Robin-to-flux maps, A^UU minus a sum of positive
+    face terms; these follow from (2.19)-(2.21).)"""
+    c = small_case((8, 6, 4), (2, 2, 2), split=((1, 2), (2, 1), (2, 2)), seed=1)
+    r = mrcm_solve(c)
+    A = r.A_int.toarray()
+    NV = r.geo.n_patch
+    APP, APU, AUP, AUU = A[:NV, :NV], A[:NV, NV:], A[NV:, :NV], A[NV:, NV:]
+    assert np.max(np.abs(AUP + APU.T)) < 1e-12 * np.max(np.abs(APU))
+    assert np.max(np.abs(APP - APP.T)) < 1e-12 * np.max(np.abs(APP))
+    assert np.max(np.abs(AUU - AUU.T)) < 1e-12 * np.max(np.abs(AUU))
+    assert np.max(np.linalg.eigvalsh(APP)) < 0
+    assert np.max(np.linalg.eigvalsh(AUU)) < 0
+
+
+def test_interface_null_vector_without_pin():
+    """Without a pin and without Dirichlet walls the P-rows annihilate
+    (pi^p, pi^u) = (1, 0): a constant pressure drives no flux."""
+    c = small_case((8, 6, 4), (2, 2, 2), seed=1, pin=-1, wells=False)
+    from oracle.geometry import Geometry as G
+    from oracle.mrcm import build_mbfs, patch_sigma, assemble_interface
+    geo = G(c.problem.dims, c.partition, c.iface)
+    # unpinned local problems are nonsingular thanks to the Robin terms
+    systems, Xs, Fs, Fbs, SAbs = build_mbfs(c.problem, geo, 1.0)
+    blocks = [(ls.patches, patch_sigma(ls), F, Fb, SAb) for ls, F, Fb, SAb in zip(systems, Fs, Fbs, SAbs)]
+    A, b = assemble_interface(geo.n_patch, blocks)
+    x = np.concatenate([np.ones(geo.n_patch), np.zeros(geo.n_patch)])
+    y = A @ x
+    assert np.max(np.abs(y)) < 1e-12 * np.max(np.abs(A.toarray()))
+
+
+# ---------------------------------------------------------------- T9 ------
+def test_band_cholesky_matches_lapack_and_dense():
+    """The textbook band factor equals LAPACK's dpbtrf (via SciPy) and the
+    dense Cholesky factor, and the band solve equals a sparse LU solve."""
+    c = small_case((6, 5, 4), (1, 2, 2), seed=9, std=2.0)
+    geo = Geometry(c.problem.dims, c.partition, c.iface)
+    ls = local_system(c.problem, geo, 3, 1.0)
+    M = ls.M
+    b = bandwidth(M)
+    assert b == 6 * 3  # lx * ly for x-fastest ordering of a 6x3x2 box
+    Lb = band_cholesky(to_band(M, b))
+    lap = sla.cholesky_banded(to_band(M, b).T, lower=True)
+    assert np.max(np.abs(Lb.T - lap)) < 1e-13 * np.max(np.abs(lap))
+    Ld = np.linalg.cholesky(M.toarray())
+    assert np.max(np.abs(Lb - to_band(Ld, b))) < 1e-13 * np.max(np.abs(Ld))
+    X = band_solve(Lb, ls.R)
+    Xs = spla.splu(M.tocsc()).solve(ls.R)
+    assert np.max(np.abs(X - Xs)) < 1e-12 * np.max(np.abs(Xs))
+
+
+def test_band_cholesky_rejects_indefinite():
+    A = np.array([[1.0, 2.0], [2.0, 1.0]])
+    with pytest.raises(np.linalg.LinAlgError):
+        band_cholesky(to_band(A, 1))
+
+
+# ---------------------------------------------------------------- T10 -----
+def _golden_counts():
+    rows = []
+    with open(os.path.join(GOLDEN, "paper_interface_counts.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            t = line.split()
+            rows.append((t[0], [int(x) for x in t[2:5]], [int(x) for x in t[5:8]],
+                         [int(x) for x in t[8:11]], float(t[11])))
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden_counts(), ids=lambda r: r[0])
+def test_interface_unknown_counts_match_paper(row):
+    """eq. (2.24) with H-bar = H reproduces the N_Gamma column the paper prints
+    (to its rounding; a few printed values are off by up to 0.4K)."""
+    name, proc, core, grid, printed_k = row
+    nd = [p * c for p, c in zip(proc, core)]
+    assert all(g % n == 0 for g, n in zip(grid, nd))
+    n_gamma = count_interface_unknowns(nd)
+    assert abs(n_gamma / 1000.0 - printed_k) <= 0.4 + 1e-9, (n_gamma, printed_k)
+
+
+def test_subdomain_sizes_match_paper():
+    """Local problem sizes of the weak-scaling runs: 22K cells (Table of the
+    weak-scaling decomposition: 80x1760x160 over 8x8x16 subdomains)."""
+    assert (80 // 8) * (1760 // 8) * (160 // 16) == 22000
+    # strong scaling: 2.4K, 19.0K and 32.0K cells for the 60x10x50 decomposition
+    assert (360 // 60) * (660 // 10) * (300 // 50) == 2376
+    assert (720 // 60) * (1320 // 10) * (600 // 50) == 19008
+    assert (660 // 60) * (2420 // 10) * (600 // 50) == 31944
+
+
+def test_rhs_count_per_interior_subdomain():
+    """Sec. 2.2.3: one patch per face gives 12 MBF solves + 1 particular = 13
+    right-hand sides for an interior subdomain; splitting every face in two
+    gives 25."""
+    c = small_case((9, 9, 9), (3, 3, 3), seed=0)
+    geo = Geometry(c.problem.dims, c.partition, c.iface)
+    centre = geo.sub_id((1, 1, 1))
+    assert 2 * len(geo.sub_patches[centre]) + 1 == 13
+    c2 = small_case((9, 9, 9), (3, 3, 3), split=((2, 1), (2, 1), (2, 1)), seed=0)
+    geo2 = Geometry(c2.problem.dims, c2.partition, c2.iface)
+    assert 2 * len(geo2.sub_patches[centre]) + 1 == 25
+
+
+def test_patch_split_is_balanced_and_contiguous():
+    for n in range(1, 25):
+        for k in range(1, n + 1):
+            sizes = split_sizes(n, k)
+            assert sum(sizes) == n and max(sizes) - min(sizes) <= 1
+            idx = split_index(n, k)
+            assert np.all(np.diff(idx) >= 0) and idx[0] == 0 and idx[-1] == k - 1
+            assert np.all(np.bincount(idx) == sizes)
+
+
+# ------------------------------------------------------------- norms ------
+def test_norms_reduce_to_plain_l2_for_unit_data():
+    c = small_case((4, 3, 2), (1, 1, 1), seed=0)
+    pb = c.problem
+    pb.kx[:] = pb.ky[:] = pb.kz[:] = 1.0
+    U = np.random.default_rng(0).standard_normal((6, pb.n))
+    Z = np.zeros_like(U)
+    # unit K, unit cells: ||u||^2 = sum (1/2) u^2 over all 6 faces
+    assert np.isclose(rel_kinv_velocity(Z, U, pb), 1.0)
+    assert np.isclose(rel_l2_pressure(2 * U[0], U[0]), 1.0)
