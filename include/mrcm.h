@@ -1,0 +1,242 @@
+/*
+ * mrcm.h -- C ABI of the MI355X (gfx950) implementation of the Multiscale
+ * Robin Coupled Method (MRCM): batched construction of the Multiscale Basis
+ * Functions (MBFs), assembly and solution of the interface coupling system,
+ * and reconstruction of the pressure and velocity fields.
+ *
+ * Problem statement: single-phase Darcy flow, eqs. (2.3)-(2.6) of the paper
+ * with a diagonal, anisotropic (mobility-scaled) permeability K-hat, on a
+ * Cartesian grid discretised by two-point fluxes, eqs. (2.9)-(2.12).  The MRCM
+ * is Algorithm 2 ("Pseudocode for the DD Multiscale mixed method"): local
+ * Robin problems (2.13)/(2.14), weak continuity (2.15)/(2.16), interface
+ * system (2.18)-(2.22), reconstruction (2.23), MBF systems (2.25)/(2.26).
+ *
+ * General conventions
+ *  - Cells are indexed c = i + nx*(j + ny*k) (x fastest).  Faces of a cell are
+ *    ordered -x, +x, -y, +y, -z, +z.
+ *  - Pointers marked [dev] are device pointers (HIP global memory) that must
+ *    stay valid until the work enqueued on `stream` has completed.  Pointers
+ *    marked [host] are read or written before the call returns.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *  - All floating point arguments and results are IEEE double.
+ *  - Errors: every entry point returns an mrcm_status.  Argument errors are
+ *    detected on the host before anything is enqueued (MRCM_EINVAL, with a
+ *    message in mrcm_last_error()).  Numerical failures are raised through a
+ *    device status word that the call reads back at its end (one stream
+ *    synchronisation).  No C++ exception crosses the ABI.
+ *  - Handles are not thread-safe; distinct handles may be used concurrently on
+ *    distinct streams.  Destroy functions synchronise the handle's last stream.
+ */
+#ifndef MRCM_H
+#define MRCM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MRCM_OK = 0,
+  MRCM_EINVAL = -1,        /* invalid argument (message in mrcm_last_error) */
+  MRCM_ENOMEM = -2,        /* device allocation failed */
+  MRCM_ENOTSPD = -3,       /* non-positive pivot in a local factorisation */
+  MRCM_ENOCONV = -4,       /* iterative refinement did not reach its tolerance */
+  MRCM_ESINGULAR = -5,     /* zero pivot in the interface factorisation */
+  MRCM_EHIP = -6,          /* HIP runtime error */
+  MRCM_EUNSUPPORTED = -7   /* valid request outside this build's limits */
+} mrcm_status;
+
+/* Wall boundary types (eqs. (2.5), (2.6)). */
+enum { MRCM_WALL_NOFLOW = 0, MRCM_WALL_DIRICHLET = 1, MRCM_WALL_NEUMANN = 2 };
+
+/* Precision of the local factorisations. */
+enum { MRCM_FP64 = 0,          /* FP64 band Cholesky and solves */
+       MRCM_FP32_IR = 1 };     /* FP32 factor of the Jacobi-scaled matrix + FP64 refinement */
+
+/*
+ * The Darcy problem (Sec. 2.1).  All arrays have N = nx*ny*nz entries.
+ *  kx, ky, kz  [dev] diagonal of K-hat per cell; must be positive and finite.
+ *  q           [dev] total volumetric source rate per cell (f times cell volume).
+ *  wall_type   per wall, -x..+z: MRCM_WALL_*.
+ *  wall_value  [dev] per wall: NULL (all zero) or the wall's data, indexed by
+ *              the two in-plane cell coordinates, lower axis fastest
+ *              (-x/+x: j + ny*k; -y/+y: i + nx*k; -z/+z: i + nx*j).  Dirichlet:
+ *              pressure g_p; Neumann: outward normal velocity g_u.
+ *  pin_cell    cell whose pressure is fixed to 0 (gauge), or -1.  Required when
+ *              no wall is Dirichlet.
+ */
+typedef struct {
+  int32_t nx, ny, nz;
+  double hx, hy, hz;
+  const double *kx, *ky, *kz;
+  const double *q;
+  int32_t wall_type[6];
+  const double *wall_value[6];
+  int64_t pin_cell;
+} mrcm_problem;
+
+/*
+ * Non-overlapping tensor-product partition (Sec. 2.2).  Subdomain
+ * l = sx + ndx*(sy + ndy*sz) covers cut_x[sx] <= i < cut_x[sx+1], etc.
+ *  cut_x/y/z [host] ndx+1 / ndy+1 / ndz+1 strictly increasing offsets from 0
+ *            to nx / ny / nz.
+ */
+typedef struct {
+  int32_t ndx, ndy, ndz;
+  const int32_t *cut_x, *cut_y, *cut_z;
+} mrcm_partition;
+
+/*
+ * Interface space V_H (Sec. 2.2.2, piecewise constants on patches obtained by
+ * condensing fine faces).  For an interface normal to axis d with tangential
+ * axes a < b, (na, nb) patches split it along a and b; n cells split into k
+ * patches give the first (n mod k) patches ceil(n/k) cells and the rest
+ * floor(n/k).  (0, 0) asks for one patch per fine face.
+ *  uniform_split[d] = {na, nb} for every interface normal to axis d.
+ *  split [host] optional override, one {na, nb} per interface, or NULL.
+ *        Interfaces are listed x-normal, then y-normal, then z-normal, each in
+ *        increasing order of the lower subdomain id.  Patches are numbered in
+ *        the same order, pa + na*pb within an interface; the interface
+ *        unknowns are X = (pi^p_0 .. pi^p_{NV-1}, pi^u_0 .. pi^u_{NV-1}).
+ */
+typedef struct {
+  int32_t uniform_split[3][2];
+  const int32_t *split;
+} mrcm_iface_space;
+
+/*
+ * alpha        Robin parameter, eq. (3.1): beta_f = alpha * H_d / K_d(c) per side,
+ *              H_d the own subdomain's extent along the face normal (physical
+ *              length) and K_d(c) the own cell's permeability; alpha > 0.
+ * precision    MRCM_FP64 or MRCM_FP32_IR.
+ * ir_tol       FP32_IR: stop when every column's relative FP64 residual
+ *              ||R - M X|| / ||R|| is at most ir_tol (<= 0 selects 1e-13).
+ * ir_max_iter  FP32_IR: refinement sweeps before MRCM_ENOCONV (<= 0: 30).
+ */
+typedef struct {
+  double alpha;
+  int32_t precision;
+  double ir_tol;
+  int32_t ir_max_iter;
+} mrcm_options;
+
+typedef struct mrcm_mbfs mrcm_mbfs;           /* local factors, MBFs, Gamma-flux blocks */
+typedef struct mrcm_interface mrcm_interface; /* interface band matrix and right-hand side */
+
+typedef struct {
+  int32_t n_sub;          /* subdomains */
+  int32_t n_patch;        /* patches N_V; the interface system has 2*N_V unknowns */
+  int64_t n_cells;        /* N */
+  int64_t n_mbfs;         /* sum over subdomains of 2|I^l| (MBF solves, particular solves excluded) */
+  int64_t n_rhs;          /* sum over subdomains of 2|I^l| + 1 */
+  int32_t max_band;       /* largest local bandwidth b_l */
+  int32_t max_rhs;        /* largest m_l */
+  int32_t precision;
+  int32_t ir_iters;       /* refinement sweeps of the last build (FP32_IR) */
+  double ir_residual;     /* largest relative column residual after the last build */
+  double factor_flops;    /* sum_l sum_k (b_k^2 + 2 b_k + 1), the band Cholesky count */
+  double solve_flops;     /* sum_l 4 N_l b_l m_l (forward + backward band solves) */
+  int64_t device_bytes;   /* device memory held by the handle */
+} mrcm_info;
+
+/* Per-subdomain layout, for tests and tools.  The local row ordering puts the
+ * box's shortest axis fastest: r = t0 + n0*(t1 + n1*t2), t_k the cell
+ * coordinate along axis ax[k] relative to lo[ax[k]], ties broken by lower axis
+ * id; the lower bandwidth is b = n0*n1. */
+typedef struct {
+  int32_t lo[3], ext[3];
+  int32_t ax[3];
+  int32_t n_cells, band, n_rhs, n_patch;
+  int32_t pin_local;      /* local row of the pinned cell, or -1 */
+} mrcm_subdomain_info;
+
+/*
+ * Loop 1 of Algorithm 2: for every subdomain, assemble the local matrix
+ * A^H_l (TPFA inside, Robin terms on Gamma, wall terms), factorise it once
+ * (band Cholesky), and solve the 2|I^l| + 1 systems (2.25)/(2.26); then
+ * reduce the MBF fluxes over each patch into the blocks
+ *   F[i,col]  = sum_{f in i} Q_f[col],   Fb[i,col] = sum_{f in i} beta_f Q_f[col]
+ * with Q_f = T_f (p_c - G_f), T_f = A_d / (h_d/(2 K_d(c)) + beta_f).
+ * Right-hand-side columns: 0 particular problem (G = 0); 1..n P-type MBFs
+ * (G = 1 on patch j); n+1..2n U-type MBFs (G = -sigma beta_f on patch j);
+ * sigma = +1 on the lower side of an interface, -1 on the upper.
+ *
+ * *out: NULL to create a handle; or a handle from an earlier call with the
+ * same grid, walls, pin, partition, interface space and options, which is
+ * rebuilt in place for the new coefficient arrays without any allocation.
+ * Errors: MRCM_EINVAL (arguments, non-positive or non-finite K),
+ * MRCM_EUNSUPPORTED (a local bandwidth or right-hand-side count beyond the
+ * kernels' limits), MRCM_ENOTSPD (subdomain id in mrcm_last_error),
+ * MRCM_ENOCONV (FP32_IR), MRCM_ENOMEM, MRCM_EHIP.  On error a handle created
+ * by this call is destroyed and *out is left unchanged.
+ */
+mrcm_status mrcm_build_mbfs(const mrcm_problem *problem, const mrcm_partition *partition,
+                            const mrcm_iface_space *iface, const mrcm_options *options,
+                            void *stream, mrcm_mbfs **out);
+
+/*
+ * Interface assembly (Algorithm 2, "Assembly"; eqs. (2.18)-(2.22)).  For patch
+ * i shared by subdomains s (two of them):
+ *   P-row: sum_s sum_{j in I^s} (F^s[i,P_j] pi^p_j + F^s[i,U_j] pi^u_j) = -sum_s F^s[i,0]
+ *   U-row: sum_s sigma^s_i sum_j (Fb^s[i,P_j] pi^p_j + Fb^s[i,U_j] pi^u_j)
+ *          - (sum_s sum_{f in i} A_f beta^s_f) pi^u_i = -sum_s sigma^s_i Fb^s[i,0]
+ * Each entry receives at most two contributions, so the result is bitwise
+ * reproducible.  The matrix is stored as a band after a reverse Cuthill-McKee
+ * ordering of the patches.  *out: NULL to create, or a handle from an earlier
+ * call on the same mbfs geometry (reused without allocation).
+ */
+mrcm_status mrcm_assemble_interface(const mrcm_mbfs *mbfs, void *stream, mrcm_interface **out);
+
+/*
+ * InterfaceSolver of Algorithm 2: solves A^int X = b^int in FP64 by band LU
+ * without pivoting (the system is, up to the sign of its P-rows, symmetric
+ * quasi-definite, so every ordering admits such a factorisation), followed by
+ * `refine` steps of FP64 iterative refinement against the unfactored matrix.
+ * X [dev] 2*N_V doubles, pi^p then pi^u.  rel_residual [host] or NULL:
+ * ||b - A X|| / ||b|| after refinement.  Errors: MRCM_ESINGULAR.
+ */
+mrcm_status mrcm_solve_interface(mrcm_interface *iface, int32_t refine, void *stream,
+                                 double *X, double *rel_residual);
+
+/*
+ * Loop 2 of Algorithm 2 by the combination (2.23): p^l = X_l [1, pi^p_{I^l}, pi^u_{I^l}].
+ * Velocities (per cell, outward normal, own side) follow (2.12) inside a
+ * subdomain, Q_f / A_d = T_f (p_c - G_f(pi)) / A_d with
+ * G_f = pi^p_i - sigma beta_f pi^u_i on Gamma, and the wall rules on the walls.
+ * X [dev] 2*N_V interface unknowns; p [dev] N; U [dev] 6*N, face-major
+ * (U[f*N + c]).
+ */
+mrcm_status mrcm_reconstruct(const mrcm_mbfs *mbfs, const double *X, void *stream,
+                             double *p, double *U);
+
+mrcm_status mrcm_query(const mrcm_mbfs *mbfs, mrcm_info *info /* [host] */);
+mrcm_status mrcm_get_subdomain(const mrcm_mbfs *mbfs, int32_t l, mrcm_subdomain_info *info /* [host] */);
+
+/* Copies for tests and tools (synchronous; [host] outputs).
+ *  mrcm_copy_mbfs:    X_l, row-major [n_cells][n_rhs] in the local row ordering.
+ *  mrcm_copy_flux:    F and Fb [n_patch][n_rhs], SAb [n_patch] (sum A beta per patch).
+ *  mrcm_copy_factor:  Cholesky factor L of A^H_l (of the Jacobi-scaled matrix
+ *                     D^-1/2 A D^-1/2 for MRCM_FP32_IR) in the local row order,
+ *                     by column, [n_cells][band+1] with entry (j, t) = L[j+t][j],
+ *                     converted to double.
+ */
+mrcm_status mrcm_copy_mbfs(const mrcm_mbfs *mbfs, int32_t l, double *X);
+mrcm_status mrcm_copy_flux(const mrcm_mbfs *mbfs, int32_t l, double *F, double *Fb, double *SAb);
+mrcm_status mrcm_copy_factor(const mrcm_mbfs *mbfs, int32_t l, double *Lband);
+
+/* Interface system introspection: n = 2*N_V, bandwidth of the stored band.
+ * mrcm_copy_interface: the assembled (unfactored) matrix as dense row-major
+ * [n][n] in the natural unknown order (pi^p then pi^u), and b [n]. */
+mrcm_status mrcm_interface_dims(const mrcm_interface *iface, int32_t *n, int32_t *bandwidth);
+mrcm_status mrcm_copy_interface(const mrcm_interface *iface, double *A, double *b);
+
+void mrcm_mbfs_destroy(mrcm_mbfs *mbfs);
+void mrcm_interface_destroy(mrcm_interface *iface);
+const char *mrcm_status_string(mrcm_status status);
+const char *mrcm_last_error(void);   /* thread-local detail of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRCM_H */

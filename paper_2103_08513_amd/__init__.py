@@ -1,0 +1,243 @@
+"""MI355X (gfx950) implementation of the Multiscale Robin Coupled Method.
+
+Python binding of the C ABI in ``include/mrcm.h``: it marshals torch device
+tensors (FP64, contiguous) and the current HIP stream into the library calls
+``mrcm_build_mbfs``, ``mrcm_assemble_interface``, ``mrcm_solve_interface``
+and ``mrcm_reconstruct``.  Every step of the method runs in the library's
+kernels; importing this package does not need a GPU, but every call does.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_double, c_int32, c_void_p
+
+import numpy as np
+
+from . import _lib
+from ._lib import CInfo, CIfaceSpace, COptions, CPartition, CProblem, CSubInfo, MRCMError
+
+FP64 = 0
+FP32_IR = 1
+
+__all__ = ["MRCM", "MRCMError", "FP64", "FP32_IR", "build_mbfs", "assemble_interface",
+           "solve_interface", "reconstruct", "library"]
+
+
+def library():
+    return _lib.load()
+
+
+def _dev_ptr(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on the HIP device")
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor on the HIP device")
+    return c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+class MRCM:
+    """One MRCM configuration (grid, walls, pin, partition, interface space,
+    Robin parameter, precision) and its device handles.
+
+    ``problem`` / ``partition`` / ``iface`` are the data classes of
+    ``mrcm_inputs`` (or any objects with the same attributes)."""
+
+    def __init__(self, problem, partition, iface, alpha=1.0, precision=FP64, ir_tol=1e-13,
+                 ir_max_iter=30, device="cuda"):
+        import torch
+        self.lib = library()
+        self.device = torch.device(device)
+        self.pb = problem
+        self.nv = None
+        self._mbfs = c_void_p()
+        self._iface = c_void_p()
+        self._keep = []
+        nx, ny, nz = problem.nx, problem.ny, problem.nz
+        cp = CProblem()
+        cp.nx, cp.ny, cp.nz = nx, ny, nz
+        cp.hx, cp.hy, cp.hz = problem.hx, problem.hy, problem.hz
+        for f in range(6):
+            cp.wall_type[f] = int(problem.wall_type[f])
+            cp.wall_value[f] = None
+        cp.pin_cell = int(problem.pin)
+        self._cp = cp
+        self._wall_tensors = [None] * 6
+        for f in range(6):
+            v = problem.wall_value[f]
+            if v is not None:
+                t = torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64), device=self.device)
+                self._wall_tensors[f] = t
+                cp.wall_value[f] = t.data_ptr()
+        cuts = [np.ascontiguousarray(c, dtype=np.int32) for c in partition.cuts]
+        self._keep += cuts
+        part = CPartition()
+        part.ndx, part.ndy, part.ndz = (len(c) - 1 for c in cuts)
+        part.cut_x, part.cut_y, part.cut_z = (c.ctypes.data_as(ctypes.POINTER(c_int32)) for c in cuts)
+        self._part = part
+        ifs = CIfaceSpace()
+        for d in range(3):
+            ifs.uniform_split[d][0] = int(iface.uniform_split[d][0])
+            ifs.uniform_split[d][1] = int(iface.uniform_split[d][1])
+        if iface.split is not None:
+            sp = np.ascontiguousarray(iface.split, dtype=np.int32).reshape(-1)
+            self._keep.append(sp)
+            ifs.split = sp.ctypes.data_as(ctypes.POINTER(c_int32))
+        else:
+            ifs.split = None
+        self._ifs = ifs
+        opt = COptions()
+        opt.alpha = float(alpha)
+        opt.precision = int(precision)
+        opt.ir_tol = float(ir_tol)
+        opt.ir_max_iter = int(ir_max_iter)
+        self._opt = opt
+
+    # -- the four steps of Algorithm 2 ------------------------------------
+    def build_mbfs(self, kx, ky, kz, q, stream=None):
+        cp = self._cp
+        cp.kx = _dev_ptr(kx, "kx").value
+        cp.ky = _dev_ptr(ky, "ky").value
+        cp.kz = _dev_ptr(kz, "kz").value
+        cp.q = _dev_ptr(q, "q").value
+        self._inputs = (kx, ky, kz, q)
+        code = self.lib.mrcm_build_mbfs(byref(cp), byref(self._part), byref(self._ifs),
+                                        byref(self._opt), _stream_ptr(stream), byref(self._mbfs))
+        _lib.check(code, "mrcm_build_mbfs")
+        return self
+
+    def assemble_interface(self, stream=None):
+        code = self.lib.mrcm_assemble_interface(self._mbfs, _stream_ptr(stream), byref(self._iface))
+        _lib.check(code, "mrcm_assemble_interface")
+        return self
+
+    def solve_interface(self, X=None, refine=1, stream=None):
+        import torch
+        info = self.info()
+        nv = info.n_patch
+        if X is None:
+            X = torch.empty(2 * nv, dtype=torch.float64, device=self.device)
+        res = c_double(0.0)
+        code = self.lib.mrcm_solve_interface(self._iface, int(refine), _stream_ptr(stream),
+                                             _dev_ptr(X, "X") if nv > 0 else None, byref(res))
+        _lib.check(code, "mrcm_solve_interface")
+        self.interface_residual = res.value
+        return X
+
+    def reconstruct(self, X, p=None, U=None, stream=None):
+        import torch
+        N = self.pb.nx * self.pb.ny * self.pb.nz
+        if p is None:
+            p = torch.empty(N, dtype=torch.float64, device=self.device)
+        if U is None:
+            U = torch.empty(6 * N, dtype=torch.float64, device=self.device)
+        xp = _dev_ptr(X, "X") if X is not None and X.numel() > 0 else None
+        code = self.lib.mrcm_reconstruct(self._mbfs, xp, _stream_ptr(stream), _dev_ptr(p, "p"),
+                                         _dev_ptr(U, "U"))
+        _lib.check(code, "mrcm_reconstruct")
+        return p, U.view(6, N)
+
+    def solve(self, kx, ky, kz, q, refine=1, stream=None):
+        """Whole MRCM: MBFs, interface assembly and solve, reconstruction."""
+        self.build_mbfs(kx, ky, kz, q, stream)
+        self.assemble_interface(stream)
+        X = self.solve_interface(refine=refine, stream=stream)
+        return self.reconstruct(X, stream=stream) + (X,)
+
+    # -- introspection ------------------------------------------------------
+    def info(self):
+        inf = CInfo()
+        _lib.check(self.lib.mrcm_query(self._mbfs, byref(inf)), "mrcm_query")
+        return inf
+
+    def subdomain(self, l):
+        si = CSubInfo()
+        _lib.check(self.lib.mrcm_get_subdomain(self._mbfs, int(l), byref(si)), "mrcm_get_subdomain")
+        return si
+
+    def local_order(self, l):
+        """Box-local x-fastest index of each library row of subdomain l."""
+        si = self.subdomain(l)
+        ext = list(si.ext)
+        ax = list(si.ax)
+        n = [ext[a] for a in ax]
+        r = np.arange(si.n_cells)
+        t = [r % n[0], (r // n[0]) % n[1], r // (n[0] * n[1])]
+        x = [None, None, None]
+        for k in range(3):
+            x[ax[k]] = t[k]
+        return x[0] + ext[0] * (x[1] + ext[1] * x[2])
+
+    def copy_mbfs(self, l):
+        si = self.subdomain(l)
+        out = np.empty((si.n_cells, si.n_rhs))
+        _lib.check(self.lib.mrcm_copy_mbfs(self._mbfs, int(l), out.ctypes.data_as(c_void_p)), "mrcm_copy_mbfs")
+        return out
+
+    def copy_flux(self, l):
+        si = self.subdomain(l)
+        F = np.empty((si.n_patch, si.n_rhs))
+        Fb = np.empty((si.n_patch, si.n_rhs))
+        SAb = np.empty(si.n_patch)
+        _lib.check(self.lib.mrcm_copy_flux(self._mbfs, int(l), F.ctypes.data_as(c_void_p),
+                                           Fb.ctypes.data_as(c_void_p), SAb.ctypes.data_as(c_void_p)),
+                   "mrcm_copy_flux")
+        return F, Fb, SAb
+
+    def copy_factor(self, l):
+        si = self.subdomain(l)
+        out = np.empty((si.n_cells, si.band + 1))
+        _lib.check(self.lib.mrcm_copy_factor(self._mbfs, int(l), out.ctypes.data_as(c_void_p)),
+                   "mrcm_copy_factor")
+        return out
+
+    def interface_dims(self):
+        n = c_int32()
+        w = c_int32()
+        _lib.check(self.lib.mrcm_interface_dims(self._iface, byref(n), byref(w)), "mrcm_interface_dims")
+        return n.value, w.value
+
+    def copy_interface(self):
+        n, _ = self.interface_dims()
+        A = np.empty((n, n))
+        b = np.empty(n)
+        _lib.check(self.lib.mrcm_copy_interface(self._iface, A.ctypes.data_as(c_void_p),
+                                                b.ctypes.data_as(c_void_p)), "mrcm_copy_interface")
+        return A, b
+
+    def close(self):
+        if self._iface:
+            self.lib.mrcm_interface_destroy(self._iface)
+            self._iface = c_void_p()
+        if self._mbfs:
+            self.lib.mrcm_mbfs_destroy(self._mbfs)
+            self._mbfs = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# Function-style aliases with the C names.
+def build_mbfs(model: MRCM, kx, ky, kz, q, stream=None):
+    return model.build_mbfs(kx, ky, kz, q, stream)
+
+
+def assemble_interface(model: MRCM, stream=None):
+    return model.assemble_interface(stream)
+
+
+def solve_interface(model: MRCM, refine=1, stream=None):
+    return model.solve_interface(refine=refine, stream=stream)
+
+
+def reconstruct(model: MRCM, X, stream=None):
+    return model.reconstruct(X, stream=stream)

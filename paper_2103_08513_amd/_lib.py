@@ -1,0 +1,107 @@
+"""ctypes declarations of the C ABI in include/mrcm.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_uint32, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrcm.so")
+
+STATUS = {0: "MRCM_OK", -1: "MRCM_EINVAL", -2: "MRCM_ENOMEM", -3: "MRCM_ENOTSPD",
+          -4: "MRCM_ENOCONV", -5: "MRCM_ESINGULAR", -6: "MRCM_EHIP", -7: "MRCM_EUNSUPPORTED"}
+
+# Every entry point declared in include/mrcm.h.
+EXPORTS = [
+    "mrcm_build_mbfs", "mrcm_assemble_interface", "mrcm_solve_interface", "mrcm_reconstruct",
+    "mrcm_query", "mrcm_get_subdomain", "mrcm_copy_mbfs", "mrcm_copy_flux", "mrcm_copy_factor",
+    "mrcm_interface_dims", "mrcm_copy_interface", "mrcm_mbfs_destroy", "mrcm_interface_destroy",
+    "mrcm_status_string", "mrcm_last_error",
+]
+
+
+class CProblem(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32),
+                ("hx", c_double), ("hy", c_double), ("hz", c_double),
+                ("kx", c_void_p), ("ky", c_void_p), ("kz", c_void_p), ("q", c_void_p),
+                ("wall_type", c_int32 * 6), ("wall_value", c_void_p * 6),
+                ("pin_cell", c_int64)]
+
+
+class CPartition(ctypes.Structure):
+    _fields_ = [("ndx", c_int32), ("ndy", c_int32), ("ndz", c_int32),
+                ("cut_x", POINTER(c_int32)), ("cut_y", POINTER(c_int32)), ("cut_z", POINTER(c_int32))]
+
+
+class CIfaceSpace(ctypes.Structure):
+    _fields_ = [("uniform_split", (c_int32 * 2) * 3), ("split", POINTER(c_int32))]
+
+
+class COptions(ctypes.Structure):
+    _fields_ = [("alpha", c_double), ("precision", c_int32), ("ir_tol", c_double),
+                ("ir_max_iter", c_int32)]
+
+
+class CInfo(ctypes.Structure):
+    _fields_ = [("n_sub", c_int32), ("n_patch", c_int32), ("n_cells", c_int64),
+                ("n_mbfs", c_int64), ("n_rhs", c_int64), ("max_band", c_int32),
+                ("max_rhs", c_int32), ("precision", c_int32), ("ir_iters", c_int32),
+                ("ir_residual", c_double), ("factor_flops", c_double), ("solve_flops", c_double),
+                ("device_bytes", c_int64)]
+
+
+class CSubInfo(ctypes.Structure):
+    _fields_ = [("lo", c_int32 * 3), ("ext", c_int32 * 3), ("ax", c_int32 * 3),
+                ("n_cells", c_int32), ("band", c_int32), ("n_rhs", c_int32),
+                ("n_patch", c_int32), ("pin_local", c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmrcm.so and declare its signatures.  Raises if it is missing:
+    there is no other implementation to fall back to."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_2103_08513_amd.build.build() first")
+    lib = ctypes.CDLL(path)
+    P = POINTER
+    sigs = {
+        "mrcm_build_mbfs": ([P(CProblem), P(CPartition), P(CIfaceSpace), P(COptions), c_void_p,
+                             P(c_void_p)], c_int32),
+        "mrcm_assemble_interface": ([c_void_p, c_void_p, P(c_void_p)], c_int32),
+        "mrcm_solve_interface": ([c_void_p, c_int32, c_void_p, c_void_p, P(c_double)], c_int32),
+        "mrcm_reconstruct": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
+        "mrcm_query": ([c_void_p, P(CInfo)], c_int32),
+        "mrcm_get_subdomain": ([c_void_p, c_int32, P(CSubInfo)], c_int32),
+        "mrcm_copy_mbfs": ([c_void_p, c_int32, c_void_p], c_int32),
+        "mrcm_copy_flux": ([c_void_p, c_int32, c_void_p, c_void_p, c_void_p], c_int32),
+        "mrcm_copy_factor": ([c_void_p, c_int32, c_void_p], c_int32),
+        "mrcm_interface_dims": ([c_void_p, P(c_int32), P(c_int32)], c_int32),
+        "mrcm_copy_interface": ([c_void_p, c_void_p, c_void_p], c_int32),
+        "mrcm_mbfs_destroy": ([c_void_p], None),
+        "mrcm_interface_destroy": ([c_void_p], None),
+        "mrcm_status_string": ([c_int32], c_char_p),
+        "mrcm_last_error": ([], c_char_p),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+class MRCMError(RuntimeError):
+    def __init__(self, code, where, detail):
+        self.code = code
+        super().__init__(f"{where}: {STATUS.get(code, code)}: {detail}")
+
+
+def check(code, where):
+    if code != 0:
+        detail = _lib.mrcm_last_error().decode(errors="replace") if _lib else ""
+        raise MRCMError(code, where, detail)

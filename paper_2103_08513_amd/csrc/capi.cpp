@@ -1,0 +1,814 @@
+// C ABI of the MRCM library: argument validation, subdomain / interface
+// descriptors, reverse Cuthill-McKee ordering of the interface unknowns,
+// device memory plan, and the enqueueing of the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "../../include/mrcm.h"
+#include "internal.h"
+#include "launch.h"
+
+using namespace mrcm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mrcm_status fail(mrcm_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(MRCM_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));       \
+  } while (0)
+
+template <typename T>
+hipError_t dev_alloc(T **p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  return hipMalloc((void **)p, n * sizeof(T));
+}
+
+template <typename T>
+hipError_t upload(T **p, const std::vector<T> &v) {
+  hipError_t e = dev_alloc(p, v.size());
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+// Host description of the geometry: everything that does not depend on the
+// coefficient arrays.
+struct HostGeom {
+  int n[3];
+  double h[3];
+  double alpha;
+  int precision;
+  int wall_type[6];
+  int64_t pin;
+  std::vector<int> cuts[3];
+  std::vector<int> split;  // 2 per interface (resolved, never 0)
+  std::vector<SubDesc> subs;
+  std::vector<IfaceDesc> ifcs;
+  std::vector<int> patches;  // concatenated I^l
+  std::vector<int> order;    // launch order, most expensive first
+  std::vector<int> sub_of[3];
+  int n_patch = 0;
+  int bmax = 0, mmax = 0, max_cells = 0;
+  long long max_nm = 0;
+  int64_t totL = 0, totD = 0, totX = 0, totF = 0, totCells = 0;
+  int totCols = 0;
+  int64_t n_mbfs = 0, n_rhs = 0;
+  double factor_flops = 0.0, solve_flops = 0.0;
+};
+
+bool same_config(const HostGeom &a, const HostGeom &b) {
+  for (int d = 0; d < 3; ++d)
+    if (a.n[d] != b.n[d] || a.h[d] != b.h[d] || a.cuts[d] != b.cuts[d]) return false;
+  for (int f = 0; f < 6; ++f)
+    if (a.wall_type[f] != b.wall_type[f]) return false;
+  return a.alpha == b.alpha && a.precision == b.precision && a.pin == b.pin && a.split == b.split;
+}
+
+mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
+                            const mrcm_iface_space *ifs, const mrcm_options *opt, HostGeom &G) {
+  if (!pb || !part || !ifs || !opt) return fail(MRCM_EINVAL, "null argument");
+  G.n[0] = pb->nx;
+  G.n[1] = pb->ny;
+  G.n[2] = pb->nz;
+  G.h[0] = pb->hx;
+  G.h[1] = pb->hy;
+  G.h[2] = pb->hz;
+  for (int d = 0; d < 3; ++d) {
+    if (G.n[d] < 1) return fail(MRCM_EINVAL, "grid dimensions must be positive");
+    if (!(G.h[d] > 0.0) || !std::isfinite(G.h[d])) return fail(MRCM_EINVAL, "cell sizes must be positive");
+  }
+  if (!pb->kx || !pb->ky || !pb->kz || !pb->q) return fail(MRCM_EINVAL, "kx, ky, kz and q are required");
+  const int64_t N = (int64_t)G.n[0] * G.n[1] * G.n[2];
+  if (N > (int64_t)1 << 31) return fail(MRCM_EUNSUPPORTED, "more than 2^31 cells");
+  bool dirichlet = false;
+  for (int f = 0; f < 6; ++f) {
+    G.wall_type[f] = pb->wall_type[f];
+    if (G.wall_type[f] < 0 || G.wall_type[f] > 2) return fail(MRCM_EINVAL, "wall type must be 0, 1 or 2");
+    if (G.wall_type[f] == MRCM_WALL_DIRICHLET) dirichlet = true;
+  }
+  G.pin = pb->pin_cell;
+  if (G.pin < -1 || G.pin >= N) return fail(MRCM_EINVAL, "pin_cell out of range");
+  if (G.pin < 0 && !dirichlet)
+    return fail(MRCM_EINVAL, "a pinned cell or a Dirichlet wall is needed to fix the pressure");
+  G.alpha = opt->alpha;
+  if (!(G.alpha > 0.0) || !std::isfinite(G.alpha)) return fail(MRCM_EINVAL, "alpha must be positive");
+  G.precision = opt->precision;
+  if (G.precision != MRCM_FP64 && G.precision != MRCM_FP32_IR)
+    return fail(MRCM_EINVAL, "precision must be MRCM_FP64 or MRCM_FP32_IR");
+
+  const int nd[3] = {part->ndx, part->ndy, part->ndz};
+  const int32_t *cut_in[3] = {part->cut_x, part->cut_y, part->cut_z};
+  for (int d = 0; d < 3; ++d) {
+    if (nd[d] < 1 || nd[d] > G.n[d]) return fail(MRCM_EINVAL, "subdomain counts must be in [1, n]");
+    G.cuts[d].resize(nd[d] + 1);
+    for (int s = 0; s <= nd[d]; ++s)
+      G.cuts[d][s] = cut_in[d] ? cut_in[d][s] : (int)(((int64_t)s * G.n[d]) / nd[d]);
+    if (G.cuts[d][0] != 0 || G.cuts[d][nd[d]] != G.n[d])
+      return fail(MRCM_EINVAL, "cuts must start at 0 and end at n");
+    for (int s = 0; s < nd[d]; ++s)
+      if (G.cuts[d][s + 1] <= G.cuts[d][s]) return fail(MRCM_EINVAL, "cuts must increase strictly");
+    G.sub_of[d].resize(G.n[d]);
+    for (int s = 0; s < nd[d]; ++s)
+      for (int x = G.cuts[d][s]; x < G.cuts[d][s + 1]; ++x) G.sub_of[d][x] = s;
+  }
+  const int n_sub = nd[0] * nd[1] * nd[2];
+  G.subs.assign(n_sub, SubDesc{});
+  auto sid = [&](int sx, int sy, int sz) { return sx + nd[0] * (sy + nd[1] * sz); };
+  for (int sz = 0; sz < nd[2]; ++sz)
+    for (int sy = 0; sy < nd[1]; ++sy)
+      for (int sx = 0; sx < nd[0]; ++sx) {
+        SubDesc &S = G.subs[sid(sx, sy, sz)];
+        const int s[3] = {sx, sy, sz};
+        for (int d = 0; d < 3; ++d) {
+          S.lo[d] = G.cuts[d][s[d]];
+          S.ext[d] = G.cuts[d][s[d] + 1] - G.cuts[d][s[d]];
+        }
+        // shortest axis fastest, ties by lower axis id
+        int ax[3] = {0, 1, 2};
+        std::stable_sort(ax, ax + 3, [&](int a, int b) { return S.ext[a] < S.ext[b]; });
+        for (int k = 0; k < 3; ++k) S.ax[k] = ax[k];
+        S.n0 = S.ext[ax[0]];
+        S.n1 = S.ext[ax[1]];
+        S.n2 = S.ext[ax[2]];
+        S.N = S.n0 * S.n1 * S.n2;
+        S.b = S.n0 * S.n1;
+        for (int f = 0; f < 6; ++f) {
+          S.face_if[f] = -1;
+          S.face_p0[f] = 0;
+        }
+        S.pin_local = -1;
+      }
+  // interfaces: x-normal, then y, then z, each by increasing lower id
+  G.ifcs.clear();
+  int p0 = 0;
+  int t = 0;
+  int n_if = 0;
+  for (int d = 0; d < 3; ++d) {
+    int c = 1;
+    for (int e = 0; e < 3; ++e) c *= (e == d) ? nd[e] - 1 : nd[e];
+    n_if += c;
+  }
+  G.split.assign(2 * (size_t)n_if, 0);
+  for (int d = 0; d < 3; ++d) {
+    const int a = (d == 0) ? 1 : 0;
+    const int b = (d == 2) ? 1 : 2;
+    for (int l = 0; l < n_sub; ++l) {
+      const int s[3] = {l % nd[0], (l / nd[0]) % nd[1], l / (nd[0] * nd[1])};
+      if (s[d] + 1 >= nd[d]) continue;
+      int s2[3] = {s[0], s[1], s[2]};
+      s2[d] += 1;
+      const int l2 = sid(s2[0], s2[1], s2[2]);
+      IfaceDesc I;
+      I.d = d;
+      I.lo_sub = l;
+      I.hi_sub = l2;
+      I.a = a;
+      I.b = b;
+      I.la = G.subs[l].ext[a];
+      I.lb = G.subs[l].ext[b];
+      int na = ifs->split ? ifs->split[2 * t] : ifs->uniform_split[d][0];
+      int nb = ifs->split ? ifs->split[2 * t + 1] : ifs->uniform_split[d][1];
+      if (na == 0 && nb == 0) {
+        na = I.la;
+        nb = I.lb;
+      }
+      if (na < 1 || nb < 1 || na > I.la || nb > I.lb)
+        return fail(MRCM_EINVAL, "interface split " + std::to_string(t) + " does not fit its face");
+      I.na = na;
+      I.nb = nb;
+      I.p0 = p0;
+      G.split[2 * t] = na;
+      G.split[2 * t + 1] = nb;
+      p0 += na * nb;
+      G.ifcs.push_back(I);
+      G.subs[l].face_if[2 * d + 1] = t;
+      G.subs[l2].face_if[2 * d] = t;
+      ++t;
+    }
+  }
+  G.n_patch = p0;
+  // per-subdomain patch lists (faces -x..+z, i.e. increasing global id) and offsets
+  G.patches.clear();
+  G.bmax = G.mmax = G.max_cells = 0;
+  G.max_nm = 0;
+  G.totL = G.totD = G.totX = G.totF = G.totCells = 0;
+  G.totCols = 0;
+  G.n_mbfs = G.n_rhs = 0;
+  G.factor_flops = G.solve_flops = 0.0;
+  for (int l = 0; l < n_sub; ++l) {
+    SubDesc &S = G.subs[l];
+    S.patch_off = (int)G.patches.size();
+    int np = 0;
+    for (int f = 0; f < 6; ++f) {
+      if (S.face_if[f] < 0) continue;
+      const IfaceDesc &I = G.ifcs[S.face_if[f]];
+      S.face_p0[f] = np;
+      for (int k = 0; k < I.na * I.nb; ++k) G.patches.push_back(I.p0 + k);
+      np += I.na * I.nb;
+    }
+    S.npatch = np;
+    S.m = 2 * np + 1;
+    S.cell_off = G.totCells;
+    S.L_off = G.totL;
+    S.D_off = G.totD;
+    S.X_off = G.totX;
+    S.F_off = G.totF;
+    S.col_off = G.totCols;
+    G.totCells += S.N;
+    G.totL += (int64_t)S.N * (S.b + 1);
+    G.totD += (int64_t)((S.N + kNB - 1) / kNB) * kNB * kNB;
+    G.totX += (int64_t)S.N * S.m;
+    G.totF += (int64_t)S.npatch * S.m;
+    G.totCols += S.m;
+    G.bmax = std::max(G.bmax, S.b);
+    G.mmax = std::max(G.mmax, S.m);
+    G.max_cells = std::max(G.max_cells, S.N);
+    G.max_nm = std::max(G.max_nm, (long long)S.N * S.m);
+    G.n_mbfs += 2 * np;
+    G.n_rhs += S.m;
+    for (int k = 0; k < S.N; ++k) {
+      const double bk = std::min(S.b, S.N - 1 - k);
+      G.factor_flops += bk * bk + 2.0 * bk + 1.0;
+    }
+    G.solve_flops += 4.0 * S.N * (double)S.b * S.m;
+    if (G.pin >= 0) {
+      const int x[3] = {(int)(G.pin % G.n[0]), (int)((G.pin / G.n[0]) % G.n[1]),
+                        (int)(G.pin / ((int64_t)G.n[0] * G.n[1]))};
+      bool inside = true;
+      for (int d = 0; d < 3; ++d) inside = inside && x[d] >= S.lo[d] && x[d] < S.lo[d] + S.ext[d];
+      if (inside) {
+        const int t0 = x[S.ax[0]] - S.lo[S.ax[0]], t1 = x[S.ax[1]] - S.lo[S.ax[1]],
+                  t2 = x[S.ax[2]] - S.lo[S.ax[2]];
+        S.pin_local = t0 + S.n0 * (t1 + S.n1 * t2);
+      }
+    }
+  }
+  const int bcap = G.precision == MRCM_FP64 ? kMaxBand64 : kMaxBand32;
+  if (G.bmax > bcap)
+    return fail(MRCM_EUNSUPPORTED, "local bandwidth " + std::to_string(G.bmax) + " exceeds " +
+                                       std::to_string(bcap) + " for this precision");
+  if (G.mmax > kMaxRhs)
+    return fail(MRCM_EUNSUPPORTED, "a subdomain has " + std::to_string(G.mmax) +
+                                       " right-hand sides; the limit is " + std::to_string(kMaxRhs));
+  const int fp32 = G.precision == MRCM_FP32_IR;
+  if (solve_lds_bytes(fp32, G.bmax, G.mmax) > 160 * 1024)
+    return fail(MRCM_EUNSUPPORTED, "band and right-hand-side window exceed the 160 KiB LDS");
+  // launch order: most expensive subdomain first (N b^2 + N b m)
+  G.order.resize(n_sub);
+  for (int l = 0; l < n_sub; ++l) G.order[l] = l;
+  std::stable_sort(G.order.begin(), G.order.end(), [&](int a, int b) {
+    const SubDesc &A = G.subs[a], &B = G.subs[b];
+    const double ca = (double)A.N * A.b * (A.b + 4.0 * A.m);
+    const double cb = (double)B.N * B.b * (B.b + 4.0 * B.m);
+    return ca > cb;
+  });
+  return MRCM_OK;
+}
+
+// Reverse Cuthill-McKee ordering of the patch graph (patches adjacent when a
+// subdomain contains both); returns pos[patch] and the resulting bandwidth of
+// the interleaved (pi^p, pi^u) unknowns.
+void rcm_order(const HostGeom &G, std::vector<int> &pos, int &w) {
+  const int nv = G.n_patch;
+  std::vector<std::vector<int>> adj(nv);
+  for (const SubDesc &S : G.subs) {
+    for (int i = 0; i < S.npatch; ++i)
+      for (int j = 0; j < S.npatch; ++j)
+        if (i != j) adj[G.patches[S.patch_off + i]].push_back(G.patches[S.patch_off + j]);
+  }
+  for (auto &a : adj) {
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
+  }
+  std::vector<int> deg(nv);
+  for (int i = 0; i < nv; ++i) deg[i] = (int)adj[i].size();
+  std::vector<int> perm;
+  perm.reserve(nv);
+  std::vector<char> seen(nv, 0);
+  auto bfs = [&](int start, std::vector<int> &out, std::vector<int> &level) {
+    out.clear();
+    std::vector<int> lev(nv, -1);
+    std::deque<int> qu;
+    qu.push_back(start);
+    lev[start] = 0;
+    while (!qu.empty()) {
+      const int u = qu.front();
+      qu.pop_front();
+      out.push_back(u);
+      std::vector<int> nb;
+      for (int v : adj[u])
+        if (lev[v] < 0 && !seen[v]) nb.push_back(v);
+      std::sort(nb.begin(), nb.end(), [&](int a, int b) { return deg[a] < deg[b] || (deg[a] == deg[b] && a < b); });
+      for (int v : nb) {
+        lev[v] = lev[u] + 1;
+        qu.push_back(v);
+      }
+    }
+    level = lev;
+  };
+  for (int s0 = 0; s0 < nv; ++s0) {
+    if (seen[s0]) continue;
+    // pseudo-peripheral start: repeat BFS from the farthest, lowest-degree node
+    int start = s0;
+    std::vector<int> comp, lev;
+    int ecc = -1;
+    for (int it = 0; it < 4; ++it) {
+      bfs(start, comp, lev);
+      int far = start, best = -1;
+      for (int u : comp)
+        if (lev[u] > best || (lev[u] == best && deg[u] < deg[far])) {
+          best = lev[u];
+          far = u;
+        }
+      if (best <= ecc) break;
+      ecc = best;
+      start = far;
+    }
+    bfs(start, comp, lev);
+    for (int u : comp) {
+      seen[u] = 1;
+      perm.push_back(u);
+    }
+  }
+  std::reverse(perm.begin(), perm.end());
+  pos.assign(nv, 0);
+  for (int i = 0; i < nv; ++i) pos[perm[i]] = i;
+  int bw = 1;
+  for (int u = 0; u < nv; ++u)
+    for (int v : adj[u]) bw = std::max(bw, 2 * std::abs(pos[u] - pos[v]) + 1);
+  w = bw;
+}
+
+}  // namespace
+
+struct mrcm_mbfs {
+  HostGeom G;
+  Geom g{};
+  int n_sub = 0;
+  SubDesc *d_sub = nullptr;
+  IfaceDesc *d_ifc = nullptr;
+  int *d_order = nullptr;
+  int *d_patches = nullptr;
+  int *d_subof[3] = {nullptr, nullptr, nullptr};
+  double *coef = nullptr, *r0 = nullptr, *scal = nullptr;
+  void *L = nullptr, *Dinv = nullptr;
+  double *X = nullptr, *R = nullptr;
+  double *F = nullptr, *Fb = nullptr, *SAb = nullptr;
+  double *norms = nullptr, *scalar = nullptr;
+  DevStatus *st = nullptr;
+  hipStream_t stream = nullptr;
+  int ir_iters = 0;
+  double ir_res = 0.0;
+  double ir_tol = 1e-13;
+  int ir_max = 30;
+  int64_t bytes = 0;
+};
+
+struct mrcm_interface {
+  const mrcm_mbfs *mb = nullptr;
+  int nv = 0, n = 0, w = 0;
+  std::vector<int> pos;
+  int *d_pos = nullptr;
+  double *AB = nullptr, *AB0 = nullptr;
+  double *b = nullptr, *b0 = nullptr;
+  double *diag = nullptr, *r = nullptr, *scalar = nullptr;
+  DevStatus *st = nullptr;
+  hipStream_t stream = nullptr;
+  int64_t bytes = 0;
+};
+
+namespace {
+
+void free_mbfs(mrcm_mbfs *h) {
+  if (!h) return;
+  void *ptrs[] = {h->d_sub, h->d_ifc, h->d_order, h->d_patches, h->d_subof[0], h->d_subof[1],
+                  h->d_subof[2], h->coef, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, h->F, h->Fb, h->SAb,
+                  h->norms, h->scalar, h->st};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete h;
+}
+
+void free_iface(mrcm_interface *h) {
+  if (!h) return;
+  void *ptrs[] = {h->d_pos, h->AB, h->AB0, h->b, h->b0, h->diag, h->r, h->scalar, h->st};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete h;
+}
+
+mrcm_status alloc_mbfs(mrcm_mbfs *h) {
+  const HostGeom &G = h->G;
+  h->n_sub = (int)G.subs.size();
+  std::vector<int> subof[3] = {G.sub_of[0], G.sub_of[1], G.sub_of[2]};
+  const size_t es = G.precision == MRCM_FP32_IR ? sizeof(float) : sizeof(double);
+  int64_t bytes = 0;
+#define ALLOC(p, n, T)                                                                \
+  do {                                                                                \
+    if (dev_alloc(&p, (size_t)(n)) != hipSuccess)                                     \
+      return fail(MRCM_ENOMEM, "device allocation of " #p " failed");                 \
+    bytes += (int64_t)(n) * (int64_t)sizeof(T);                                       \
+  } while (0)
+  HIP_TRY(upload(&h->d_sub, G.subs));
+  HIP_TRY(upload(&h->d_ifc, G.ifcs));
+  HIP_TRY(upload(&h->d_order, G.order));
+  HIP_TRY(upload(&h->d_patches, G.patches));
+  for (int d = 0; d < 3; ++d) HIP_TRY(upload(&h->d_subof[d], subof[d]));
+  ALLOC(h->coef, 4 * G.totCells, double);
+  ALLOC(h->r0, G.totCells, double);
+  ALLOC(h->scal, G.totCells, double);
+  {
+    char *p = nullptr;
+    if (hipMalloc((void **)&p, (size_t)G.totL * es) != hipSuccess)
+      return fail(MRCM_ENOMEM, "device allocation of the band factors failed");
+    h->L = p;
+    bytes += G.totL * (int64_t)es;
+    if (hipMalloc((void **)&p, (size_t)G.totD * es) != hipSuccess)
+      return fail(MRCM_ENOMEM, "device allocation of the diagonal-block inverses failed");
+    h->Dinv = p;
+    bytes += G.totD * (int64_t)es;
+  }
+  ALLOC(h->X, G.totX, double);
+  if (G.precision == MRCM_FP32_IR) ALLOC(h->R, G.totX, double);
+  ALLOC(h->F, std::max<int64_t>(1, G.totF), double);
+  ALLOC(h->Fb, std::max<int64_t>(1, G.totF), double);
+  ALLOC(h->SAb, std::max<int64_t>(1, (int64_t)G.patches.size()), double);
+  ALLOC(h->norms, 2 * (int64_t)G.totCols, double);
+  ALLOC(h->scalar, 4, double);
+  {
+    DevStatus *p = nullptr;
+    HIP_TRY(hipMalloc((void **)&p, sizeof(DevStatus)));
+    h->st = p;
+  }
+#undef ALLOC
+  h->bytes = bytes;
+  Geom &g = h->g;
+  g.nx = G.n[0];
+  g.ny = G.n[1];
+  g.nz = G.n[2];
+  const double V = G.h[0] * G.h[1] * G.h[2];
+  for (int d = 0; d < 3; ++d) {
+    g.h[d] = G.h[d];
+    g.area[d] = V / G.h[d];
+    g.sub_of[d] = h->d_subof[d];
+    g.nd[d] = (int)G.cuts[d].size() - 1;
+  }
+  g.alpha = G.alpha;
+  for (int f = 0; f < 6; ++f) g.wall_type[f] = G.wall_type[f];
+  g.pin = G.pin;
+  g.sub = h->d_sub;
+  g.ifc = h->d_ifc;
+  return MRCM_OK;
+}
+
+mrcm_status read_status(DevStatus *st, hipStream_t s, const char *what) {
+  DevStatus hs;
+  HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hs.code == 0) return MRCM_OK;
+  char buf[256];
+  if (hs.code == MRCM_ENOTSPD)
+    snprintf(buf, sizeof buf, "%s: non-positive pivot %.6g in subdomain %d", what, hs.value, hs.where);
+  else if (hs.code == MRCM_EINVAL)
+    snprintf(buf, sizeof buf, "%s: permeability %.6g at cell %d is not positive and finite", what,
+             hs.value, hs.where);
+  else if (hs.code == MRCM_ESINGULAR)
+    snprintf(buf, sizeof buf, "%s: zero pivot %.6g at interface unknown %d", what, hs.value, hs.where);
+  else
+    snprintf(buf, sizeof buf, "%s: device status %d", what, hs.code);
+  return fail((mrcm_status)hs.code, buf);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mrcm_status_string(mrcm_status s) {
+  switch (s) {
+    case MRCM_OK: return "ok";
+    case MRCM_EINVAL: return "invalid argument";
+    case MRCM_ENOMEM: return "out of device memory";
+    case MRCM_ENOTSPD: return "local matrix not positive definite";
+    case MRCM_ENOCONV: return "iterative refinement did not converge";
+    case MRCM_ESINGULAR: return "interface matrix singular";
+    case MRCM_EHIP: return "HIP runtime error";
+    case MRCM_EUNSUPPORTED: return "unsupported by this build";
+  }
+  return "unknown status";
+}
+
+const char *mrcm_last_error(void) { return g_last_error.c_str(); }
+
+mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
+                            const mrcm_iface_space *ifs, const mrcm_options *opt, void *stream,
+                            mrcm_mbfs **out) {
+  if (!out) return fail(MRCM_EINVAL, "out is null");
+  HostGeom G;
+  mrcm_status st = build_host_geom(pb, part, ifs, opt, G);
+  if (st != MRCM_OK) return st;
+  mrcm_mbfs *h = *out;
+  bool created = false;
+  if (h && !same_config(h->G, G))
+    return fail(MRCM_EINVAL, "handle was built for a different configuration");
+  if (!h) {
+    h = new mrcm_mbfs();
+    h->G = std::move(G);
+    st = alloc_mbfs(h);
+    if (st != MRCM_OK) {
+      free_mbfs(h);
+      return st;
+    }
+    created = true;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  h->stream = s;
+  h->ir_tol = opt->ir_tol > 0.0 ? opt->ir_tol : 1e-13;
+  h->ir_max = opt->ir_max_iter > 0 ? opt->ir_max_iter : 30;
+  Geom &g = h->g;
+  g.k[0] = pb->kx;
+  g.k[1] = pb->ky;
+  g.k[2] = pb->kz;
+  g.q = pb->q;
+  for (int f = 0; f < 6; ++f) g.wall_value[f] = pb->wall_value[f];
+  const HostGeom &H = h->G;
+  const int fp32 = H.precision == MRCM_FP32_IR;
+  auto bail = [&](mrcm_status e) {
+    if (created) free_mbfs(h);
+    return e;
+  };
+#define ENQ(expr)                                                                   \
+  do {                                                                              \
+    hipError_t _e = (expr);                                                         \
+    if (_e != hipSuccess) return bail(fail(MRCM_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e))); \
+  } while (0)
+  const long long N = (long long)H.n[0] * H.n[1] * H.n[2];
+  ENQ(launch_reset_status(h->st, s));
+  ENQ(launch_check_perm(pb->kx, pb->ky, pb->kz, N, h->st, s));
+  st = read_status(h->st, s, "mrcm_build_mbfs");
+  if (st != MRCM_OK) return bail(st);
+  ENQ(launch_coef(g, h->n_sub, H.max_cells, h->coef, h->r0, h->scal, s));
+  ENQ(launch_factor(fp32, h->d_sub, h->d_order, h->n_sub, h->coef, h->scal, h->L, h->Dinv, h->st,
+                    H.bmax, s));
+  ENQ(launch_solve(fp32, g, h->d_order, h->n_sub, h->r0, h->scal, h->L, h->Dinv, h->X, nullptr, 0,
+                   H.bmax, H.mmax, s));
+  h->ir_iters = 0;
+  h->ir_res = 0.0;
+  if (fp32) {
+    for (int it = 0;; ++it) {
+      ENQ(launch_fill(h->norms, 2LL * H.totCols, 0.0, s));
+      ENQ(launch_residual(g, h->n_sub, H.max_nm, h->coef, h->r0, h->X, h->R, h->norms, s));
+      ENQ(launch_ir_check(h->norms, H.totCols, h->scalar, s));
+      double res = 0.0;
+      ENQ(hipMemcpyAsync(&res, h->scalar, sizeof(double), hipMemcpyDeviceToHost, s));
+      ENQ(hipStreamSynchronize(s));
+      h->ir_res = res;
+      h->ir_iters = it;
+      if (res <= h->ir_tol) break;
+      if (it >= h->ir_max || !std::isfinite(res)) {
+        st = read_status(h->st, s, "mrcm_build_mbfs");
+        if (st != MRCM_OK) return bail(st);
+        char buf[160];
+        snprintf(buf, sizeof buf, "refinement stopped at relative residual %.3g after %d sweeps", res, it);
+        return bail(fail(MRCM_ENOCONV, buf));
+      }
+      ENQ(launch_solve(fp32, g, h->d_order, h->n_sub, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, 1,
+                       H.bmax, H.mmax, s));
+    }
+  }
+  ENQ(launch_flux(g, h->n_sub, h->X, h->F, h->Fb, h->SAb, s));
+  st = read_status(h->st, s, "mrcm_build_mbfs");
+  if (st != MRCM_OK) return bail(st);
+#undef ENQ
+  *out = h;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_assemble_interface(const mrcm_mbfs *mb, void *stream, mrcm_interface **out) {
+  if (!mb || !out) return fail(MRCM_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  mrcm_interface *h = *out;
+  bool created = false;
+  if (h && h->mb != mb) return fail(MRCM_EINVAL, "interface handle belongs to another mbfs handle");
+  if (!h) {
+    h = new mrcm_interface();
+    created = true;
+    h->mb = mb;
+    h->nv = mb->G.n_patch;
+    h->n = 2 * h->nv;
+    rcm_order(mb->G, h->pos, h->w);
+    if (h->nv == 0) h->w = 0;
+    const int64_t band = (int64_t)h->n * (2 * h->w + 1);
+    bool ok = upload(&h->d_pos, h->pos) == hipSuccess && dev_alloc(&h->AB, band) == hipSuccess &&
+              dev_alloc(&h->AB0, band) == hipSuccess && dev_alloc(&h->b, h->n) == hipSuccess &&
+              dev_alloc(&h->b0, h->n) == hipSuccess && dev_alloc(&h->diag, 32 * 32) == hipSuccess &&
+              dev_alloc(&h->r, h->n) == hipSuccess && dev_alloc(&h->scalar, 4) == hipSuccess &&
+              hipMalloc((void **)&h->st, sizeof(DevStatus)) == hipSuccess;
+    if (!ok) {
+      free_iface(h);
+      return fail(MRCM_ENOMEM, "device allocation of the interface system failed");
+    }
+    h->bytes = 2 * band * 8 + 4 * (int64_t)h->n * 8;
+  }
+  h->stream = s;
+  const int64_t band = (int64_t)h->n * (2 * h->w + 1);
+  auto bail = [&](mrcm_status e) {
+    if (created) free_iface(h);
+    return e;
+  };
+  hipError_t e = launch_fill(h->AB, band, 0.0, s);
+  if (e == hipSuccess) e = launch_fill(h->b, h->n, 0.0, s);
+  if (e == hipSuccess && h->nv > 0)
+    e = launch_iface_scatter(mb->g, mb->n_sub, mb->d_patches, h->d_pos, mb->F, mb->Fb, mb->SAb, h->AB,
+                             h->w, h->b, s);
+  if (e == hipSuccess) e = launch_copy(h->AB, h->AB0, band, s);
+  if (e == hipSuccess) e = launch_copy(h->b, h->b0, h->n, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return bail(fail(MRCM_EHIP, std::string("interface assembly: ") + hipGetErrorString(e)));
+  *out = h;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_solve_interface(mrcm_interface *h, int32_t refine, void *stream, double *X,
+                                 double *rel_residual) {
+  if (!h) return fail(MRCM_EINVAL, "null interface handle");
+  if (h->n > 0 && !X) return fail(MRCM_EINVAL, "X is null");
+  if (refine < 0 || refine > 10) return fail(MRCM_EINVAL, "refine must be in [0, 10]");
+  hipStream_t s = (hipStream_t)stream;
+  h->stream = s;
+  if (h->n == 0) {
+    if (rel_residual) *rel_residual = 0.0;
+    return MRCM_OK;
+  }
+  const int64_t band = (int64_t)h->n * (2 * h->w + 1);
+  HIP_TRY(launch_reset_status(h->st, s));
+  // factor a fresh copy of the assembled system (the assembled one stays for refinement)
+  HIP_TRY(launch_copy(h->AB0, h->AB, band, s));
+  HIP_TRY(launch_copy(h->b0, h->b, h->n, s));
+  HIP_TRY(launch_band_lu(h->AB, h->n, h->w, h->diag, h->b, h->st, s));
+  HIP_TRY(launch_lu_sweep(h->AB, h->n, h->w, h->b, 1, s));
+  for (int it = 0; it < refine; ++it) {
+    HIP_TRY(launch_band_residual(h->AB0, h->n, h->w, h->b, h->b0, h->r, s));
+    HIP_TRY(launch_lu_sweep(h->AB, h->n, h->w, h->r, 0, s));
+    HIP_TRY(launch_lu_sweep(h->AB, h->n, h->w, h->r, 1, s));
+    HIP_TRY(launch_axpy(h->b, h->r, h->n, s));
+  }
+  HIP_TRY(launch_perm(h->b, h->d_pos, h->nv, X, 1, s));
+  mrcm_status st = read_status(h->st, s, "mrcm_solve_interface");
+  if (st != MRCM_OK) return st;
+  if (rel_residual) {
+    HIP_TRY(launch_band_residual(h->AB0, h->n, h->w, h->b, h->b0, h->r, s));
+    HIP_TRY(launch_norm2(h->r, h->n, h->scalar, s));
+    HIP_TRY(launch_norm2(h->b0, h->n, h->scalar + 1, s));
+    double v[2];
+    HIP_TRY(hipMemcpyAsync(v, h->scalar, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *rel_residual = v[1] > 0.0 ? std::sqrt(v[0] / v[1]) : std::sqrt(v[0]);
+  }
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_reconstruct(const mrcm_mbfs *mb, const double *X, void *stream, double *p,
+                             double *U) {
+  if (!mb || !p || !U) return fail(MRCM_EINVAL, "null argument");
+  if (mb->G.n_patch > 0 && !X) return fail(MRCM_EINVAL, "X is null");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_recon_p(mb->g, mb->n_sub, mb->d_patches, mb->X, X, mb->G.n_patch, p, s));
+  HIP_TRY(launch_recon_u(mb->g, p, X, mb->G.n_patch, U, s));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_query(const mrcm_mbfs *mb, mrcm_info *info) {
+  if (!mb || !info) return fail(MRCM_EINVAL, "null argument");
+  const HostGeom &G = mb->G;
+  info->n_sub = (int32_t)G.subs.size();
+  info->n_patch = G.n_patch;
+  info->n_cells = G.totCells;
+  info->n_mbfs = G.n_mbfs;
+  info->n_rhs = G.n_rhs;
+  info->max_band = G.bmax;
+  info->max_rhs = G.mmax;
+  info->precision = G.precision;
+  info->ir_iters = mb->ir_iters;
+  info->ir_residual = mb->ir_res;
+  info->factor_flops = G.factor_flops;
+  info->solve_flops = G.solve_flops;
+  info->device_bytes = mb->bytes;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_get_subdomain(const mrcm_mbfs *mb, int32_t l, mrcm_subdomain_info *info) {
+  if (!mb || !info) return fail(MRCM_EINVAL, "null argument");
+  if (l < 0 || l >= (int32_t)mb->G.subs.size()) return fail(MRCM_EINVAL, "subdomain out of range");
+  const SubDesc &S = mb->G.subs[l];
+  for (int d = 0; d < 3; ++d) {
+    info->lo[d] = S.lo[d];
+    info->ext[d] = S.ext[d];
+    info->ax[d] = S.ax[d];
+  }
+  info->n_cells = S.N;
+  info->band = S.b;
+  info->n_rhs = S.m;
+  info->n_patch = S.npatch;
+  info->pin_local = S.pin_local;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_copy_mbfs(const mrcm_mbfs *mb, int32_t l, double *X) {
+  if (!mb || !X) return fail(MRCM_EINVAL, "null argument");
+  if (l < 0 || l >= (int32_t)mb->G.subs.size()) return fail(MRCM_EINVAL, "subdomain out of range");
+  const SubDesc &S = mb->G.subs[l];
+  HIP_TRY(hipStreamSynchronize(mb->stream));
+  HIP_TRY(hipMemcpy(X, mb->X + S.X_off, (size_t)S.N * S.m * sizeof(double), hipMemcpyDeviceToHost));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_copy_flux(const mrcm_mbfs *mb, int32_t l, double *F, double *Fb, double *SAb) {
+  if (!mb || !F || !Fb || !SAb) return fail(MRCM_EINVAL, "null argument");
+  if (l < 0 || l >= (int32_t)mb->G.subs.size()) return fail(MRCM_EINVAL, "subdomain out of range");
+  const SubDesc &S = mb->G.subs[l];
+  HIP_TRY(hipStreamSynchronize(mb->stream));
+  const size_t nb = (size_t)S.npatch * S.m * sizeof(double);
+  HIP_TRY(hipMemcpy(F, mb->F + S.F_off, nb, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(Fb, mb->Fb + S.F_off, nb, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(SAb, mb->SAb + S.patch_off, (size_t)S.npatch * sizeof(double), hipMemcpyDeviceToHost));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_copy_factor(const mrcm_mbfs *mb, int32_t l, double *Lband) {
+  if (!mb || !Lband) return fail(MRCM_EINVAL, "null argument");
+  if (l < 0 || l >= (int32_t)mb->G.subs.size()) return fail(MRCM_EINVAL, "subdomain out of range");
+  const SubDesc &S = mb->G.subs[l];
+  const size_t cnt = (size_t)S.N * (S.b + 1);
+  HIP_TRY(hipStreamSynchronize(mb->stream));
+  if (mb->G.precision == MRCM_FP32_IR) {
+    std::vector<float> tmp(cnt);
+    HIP_TRY(hipMemcpy(tmp.data(), (const float *)mb->L + S.L_off, cnt * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < cnt; ++i) Lband[i] = tmp[i];
+  } else {
+    HIP_TRY(hipMemcpy(Lband, (const double *)mb->L + S.L_off, cnt * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_interface_dims(const mrcm_interface *h, int32_t *n, int32_t *bandwidth) {
+  if (!h || !n || !bandwidth) return fail(MRCM_EINVAL, "null argument");
+  *n = h->n;
+  *bandwidth = h->w;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_copy_interface(const mrcm_interface *h, double *A, double *b) {
+  if (!h || !A || !b) return fail(MRCM_EINVAL, "null argument");
+  const int n = h->n, w = h->w, nv = h->nv, ld = 2 * w + 1;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  std::vector<double> band((size_t)n * ld), bb(n);
+  if (n > 0) {
+    HIP_TRY(hipMemcpy(band.data(), h->AB0, band.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(bb.data(), h->b0, n * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  // band index of natural unknown u: P of patch p -> 2 pos[p]; U -> 2 pos[p] + 1
+  std::vector<int> bidx(n);
+  for (int p = 0; p < nv; ++p) {
+    bidx[p] = 2 * h->pos[p];
+    bidx[nv + p] = 2 * h->pos[p] + 1;
+  }
+  for (int i = 0; i < n; ++i) {
+    b[i] = bb[bidx[i]];
+    for (int j = 0; j < n; ++j) {
+      const int bi = bidx[i], bj = bidx[j];
+      A[(size_t)i * n + j] = (std::abs(bi - bj) <= w) ? band[(size_t)bj * ld + (w + bi - bj)] : 0.0;
+    }
+  }
+  return MRCM_OK;
+}
+
+void mrcm_mbfs_destroy(mrcm_mbfs *h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  free_mbfs(h);
+}
+
+void mrcm_interface_destroy(mrcm_interface *h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  free_iface(h);
+}
+
+}  // extern "C"

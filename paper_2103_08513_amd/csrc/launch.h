@@ -1,0 +1,50 @@
+// Host-side launchers of the gfx950 kernels (one per kernel family).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace mrcm {
+
+// Local problems (local_kernels.hip)
+hipError_t launch_reset_status(DevStatus *st, hipStream_t s);
+hipError_t launch_check_perm(const double *kx, const double *ky, const double *kz, long long n,
+                             DevStatus *st, hipStream_t s);
+hipError_t launch_coef(const Geom &g, int n_sub, int max_cells, double *coef, double *r0,
+                       double *scal, hipStream_t s);
+hipError_t launch_factor(int fp32, const SubDesc *subs, const int *order, int n_sub,
+                         const double *coef, const double *scal, void *L, void *Dg, DevStatus *st,
+                         int bmax, hipStream_t s);
+hipError_t launch_solve(int fp32, const Geom &g, const int *order, int n_sub, const double *r0,
+                        const double *scal, const void *L, const void *Dg, double *X, double *R,
+                        int mode, int bmax, int mmax, hipStream_t s);
+size_t factor_lds_bytes(int fp32, int bmax);
+size_t solve_lds_bytes(int fp32, int bmax, int mmax);
+hipError_t launch_residual(const Geom &g, int n_sub, long long max_nm, const double *coef,
+                           const double *r0, const double *X, double *R, double *norms,
+                           hipStream_t s);
+hipError_t launch_ir_check(const double *norms, int ncols, double *out, hipStream_t s);
+hipError_t launch_flux(const Geom &g, int n_sub, const double *X, double *F, double *Fb,
+                       double *SAb, hipStream_t s);
+
+// Interface system and reconstruction (iface_kernels.hip)
+hipError_t launch_fill(double *a, long long n, double v, hipStream_t s);
+hipError_t launch_copy(const double *a, double *b, long long n, hipStream_t s);
+hipError_t launch_iface_scatter(const Geom &g, int n_sub, const int *patches, const int *pos,
+                                const double *F, const double *Fb, const double *SAb, double *AB,
+                                int w, double *b, hipStream_t s);
+hipError_t launch_band_lu(double *AB, int n, int w, double *diag, double *b, DevStatus *st,
+                          hipStream_t s);
+hipError_t launch_lu_sweep(const double *AB, int n, int w, double *x, int upper, hipStream_t s);
+hipError_t launch_band_residual(const double *AB, int n, int w, const double *x, const double *b,
+                                double *r, hipStream_t s);
+hipError_t launch_perm(const double *src, const int *pos, int nv, double *dst, int to_natural,
+                       hipStream_t s);
+hipError_t launch_norm2(const double *v, int n, double *out, hipStream_t s);
+hipError_t launch_axpy(double *y, const double *x, int n, hipStream_t s);
+hipError_t launch_recon_p(const Geom &g, int n_sub, const int *patches, const double *X,
+                          const double *pi, int nv, double *p, hipStream_t s);
+hipError_t launch_recon_u(const Geom &g, const double *p, const double *pi, int nv, double *U,
+                          hipStream_t s);
+
+}  // namespace mrcm

@@ -1,0 +1,105 @@
+"""The C ABI: the library loads without a GPU, exports every entry point that
+include/mrcm.h declares, and the ctypes structures match the C layout."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mrcm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mrcm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_three_named_entry_points():
+    names = _declared_functions()
+    for n in ("mrcm_build_mbfs", "mrcm_assemble_interface", "mrcm_reconstruct"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2103_08513_amd import _lib
+    lib = _lib.load()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTS) == _declared_functions()
+
+
+def test_status_strings_without_gpu():
+    from paper_2103_08513_amd import _lib
+    lib = _lib.load()
+    assert lib.mrcm_status_string(0) == b"ok"
+    assert lib.mrcm_status_string(-7) == b"unsupported by this build"
+
+
+def test_host_validation_rejects_bad_arguments_before_any_gpu_work():
+    """Argument errors are caught on the host: no device is touched."""
+    import numpy as np
+    from paper_2103_08513_amd import _lib
+    from paper_2103_08513_amd._lib import CIfaceSpace, COptions, CPartition, CProblem
+    lib = _lib.load()
+    pb = CProblem()
+    pb.nx, pb.ny, pb.nz = 4, 4, 4
+    pb.hx = pb.hy = pb.hz = 1.0
+    pb.kx = pb.ky = pb.kz = pb.q = 8  # never dereferenced: validation fails first
+    pb.pin_cell = -1                  # no pin and no Dirichlet wall -> EINVAL
+    part = CPartition()
+    part.ndx = part.ndy = part.ndz = 1
+    ifs = CIfaceSpace()
+    opt = COptions()
+    opt.alpha = 1.0
+    out = ctypes.c_void_p()
+    code = lib.mrcm_build_mbfs(ctypes.byref(pb), ctypes.byref(part), ctypes.byref(ifs),
+                               ctypes.byref(opt), None, ctypes.byref(out))
+    assert code == -1
+    assert b"pin" in lib.mrcm_last_error()
+    pb.pin_cell = 0
+    opt.alpha = -1.0
+    code = lib.mrcm_build_mbfs(ctypes.byref(pb), ctypes.byref(part), ctypes.byref(ifs),
+                               ctypes.byref(opt), None, ctypes.byref(out))
+    assert code == -1 and b"alpha" in lib.mrcm_last_error()
+    opt.alpha = 1.0
+    cuts = np.array([0, 3, 3, 4], dtype=np.int32)
+    part.ndx = 3
+    part.cut_x = cuts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    code = lib.mrcm_build_mbfs(ctypes.byref(pb), ctypes.byref(part), ctypes.byref(ifs),
+                               ctypes.byref(opt), None, ctypes.byref(out))
+    assert code == -1 and b"cuts" in lib.mrcm_last_error()
+
+
+def test_ctypes_layout_matches_c(tmp_path):
+    """sizeof/offsetof of the ABI structs, from the C compiler, equal ctypes'."""
+    from paper_2103_08513_amd._lib import CInfo, CIfaceSpace, COptions, CPartition, CProblem, CSubInfo
+    src = tmp_path / "layout.c"
+    src.write_text(f'''
+#include <stdio.h>
+#include <stddef.h>
+#include "{HEADER}"
+int main(void) {{
+  printf("%zu %zu %zu %zu\\n", sizeof(mrcm_problem), offsetof(mrcm_problem, kx), offsetof(mrcm_problem, wall_type), offsetof(mrcm_problem, pin_cell));
+  printf("%zu %zu\\n", sizeof(mrcm_partition), offsetof(mrcm_partition, cut_x));
+  printf("%zu %zu\\n", sizeof(mrcm_iface_space), offsetof(mrcm_iface_space, split));
+  printf("%zu %zu %zu\\n", sizeof(mrcm_options), offsetof(mrcm_options, ir_tol), offsetof(mrcm_options, ir_max_iter));
+  printf("%zu %zu %zu\\n", sizeof(mrcm_info), offsetof(mrcm_info, ir_residual), offsetof(mrcm_info, device_bytes));
+  printf("%zu %zu\\n", sizeof(mrcm_subdomain_info), offsetof(mrcm_subdomain_info, pin_local));
+  return 0;
+}}
+''')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-o", str(exe), str(src)])
+    got = [list(map(int, ln.split())) for ln in subprocess.check_output([str(exe)]).decode().splitlines()]
+    want = [
+        [ctypes.sizeof(CProblem), CProblem.kx.offset, CProblem.wall_type.offset, CProblem.pin_cell.offset],
+        [ctypes.sizeof(CPartition), CPartition.cut_x.offset],
+        [ctypes.sizeof(CIfaceSpace), CIfaceSpace.split.offset],
+        [ctypes.sizeof(COptions), COptions.ir_tol.offset, COptions.ir_max_iter.offset],
+        [ctypes.sizeof(CInfo), CInfo.ir_residual.offset, CInfo.device_bytes.offset],
+        [ctypes.sizeof(CSubInfo), CSubInfo.pin_local.offset],
+    ]
+    assert got == want

@@ -1,0 +1,213 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element.
+
+Every test calls the library through its C ABI (via the ctypes binding) on
+seeded inputs and compares with the oracle on the same inputs.  Tolerances:
+  * local MBFs X_l, flux blocks, interface matrix (FP64 path): 1e-10 relative
+    to the largest entry of the compared block (rounding-order differences
+    only, amplified by the local condition number);
+  * end-to-end pressure and velocity: 1e-8 relative L2 (FP64 and FP32 with
+    FP64 refinement), the accuracy the method's FP64 solution is judged at.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from mrcm_inputs import config1, config2, small_case  # noqa: E402
+from oracle.banded import band_cholesky, to_band  # noqa: E402
+from oracle.geometry import Geometry  # noqa: E402
+from oracle.mrcm import build_mbfs as oracle_build, local_system, mrcm_solve  # noqa: E402
+from oracle.norms import rel_l2  # noqa: E402
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def _run(case, precision=0, refine=1):
+    import paper_2103_08513_amd as lib
+    pb = case.problem
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision)
+    p, U, X = m.solve(_dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q), refine=refine)
+    torch.cuda.synchronize()
+    return m, p.cpu().numpy(), U.cpu().numpy(), X.cpu().numpy()
+
+
+def _maxrel(a, b):
+    scale = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (scale if scale > 0 else 1.0))
+
+
+def _check_local_blocks(m, ref, tol=1e-10):
+    """X_l, F, Fb, SAb of every subdomain against the oracle."""
+    for l, ls in enumerate(ref.systems):
+        order = m.local_order(l)
+        Xg = m.copy_mbfs(l)
+        Xo = ref.X[l][order]
+        assert Xg.shape == Xo.shape
+        for c in range(Xo.shape[1]):
+            assert _maxrel(Xg[:, c], Xo[:, c]) < tol, (l, c, _maxrel(Xg[:, c], Xo[:, c]))
+        F, Fb, SAb = m.copy_flux(l)
+        assert _maxrel(F, ref.F[l]) < tol, (l, "F")
+        assert _maxrel(Fb, ref.Fb[l]) < tol, (l, "Fb")
+        assert _maxrel(SAb, ref.SAb[l]) < 1e-13, (l, "SAb")
+
+
+CASES = {
+    "2x2x2-onepatch": dict(dims=(8, 6, 4), nd=(2, 2, 2), seed=1),
+    "coarse-patches": dict(dims=(10, 8, 6), nd=(2, 2, 3), split=((2, 1), (1, 2), (2, 2)), seed=5, std=2.0),
+    "fine-trace": dict(dims=(9, 6, 4), nd=(3, 2, 1), split=((0, 0), (0, 0), (0, 0)), seed=3),
+    "ragged": dict(dims=(9, 7, 5), nd=(3, 2, 2), split=((2, 1), (1, 1), (2, 2)), seed=8,
+                   parts=([2, 4, 3], [3, 4], [2, 3])),
+    "thin-slabs": dict(dims=(5, 4, 3), nd=(2, 2, 1), seed=11, parts=([1, 4], [2, 2], [3])),
+    "tall-band": dict(dims=(24, 18, 6), nd=(2, 2, 1), split=((3, 2), (2, 2), (1, 1)), seed=12),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_local_blocks_and_solution_fp64(name):
+    case = small_case(**CASES[name])
+    ref = mrcm_solve(case)
+    m, p, U, X = _run(case)
+    _check_local_blocks(m, ref)
+    A, b = m.copy_interface()
+    Ao = ref.A_int.toarray()
+    assert _maxrel(A, Ao) < 1e-10
+    assert _maxrel(b, ref.b_int) < 1e-10
+    assert rel_l2(X, ref.pi) < 1e-9
+    assert rel_l2(p, ref.p) < 1e-9
+    assert rel_l2(U, ref.U) < 1e-9
+    m.close()
+
+
+def test_band_factor_matches_textbook_cholesky():
+    """The stored band factor is the Cholesky factor of A^H_l in the library's
+    row order (unique for an SPD matrix), compared with the textbook band
+    Cholesky of the oracle's local matrix permuted to that order."""
+    case = small_case((24, 18, 6), (2, 2, 1), split=((3, 2), (2, 2), (1, 1)), seed=12)
+    m, *_ = _run(case)
+    geo = Geometry(case.problem.dims, case.partition, case.iface)
+    for l in range(geo.n_sub):
+        ls = local_system(case.problem, geo, l, case.alpha)
+        order = m.local_order(l)
+        M = ls.M.toarray()[np.ix_(order, order)]
+        b = m.subdomain(l).band
+        Lo = band_cholesky(to_band(M, b))
+        Lg = m.copy_factor(l)
+        assert _maxrel(Lg, Lo) < 1e-12, l
+    m.close()
+
+
+def test_single_subdomain_no_interface():
+    case = small_case((7, 5, 4), (1, 1, 1), seed=0)
+    ref = mrcm_solve(case)
+    m, p, U, X = _run(case)
+    assert X.size == 0
+    assert rel_l2(p, ref.p) < 1e-10
+    assert rel_l2(U, ref.U) < 1e-10
+    m.close()
+
+
+def test_dirichlet_neumann_walls_no_pin():
+    case = small_case((8, 6, 4), (2, 2, 2), split=((1, 2), (2, 1), (2, 2)), seed=4, pin=-1)
+    pb = case.problem
+    rng = np.random.default_rng(9)
+    pb.wall_type = [1, 2, 0, 2, 1, 0]
+    pb.wall_value = [rng.standard_normal(6 * 4), 0.1 * rng.standard_normal(6 * 4), None,
+                     0.1 * rng.standard_normal(8 * 4), rng.standard_normal(8 * 6), None]
+    ref = mrcm_solve(case)
+    m, p, U, X = _run(case)
+    _check_local_blocks(m, ref)
+    assert rel_l2(p, ref.p) < 1e-9
+    assert rel_l2(U, ref.U) < 1e-9
+    m.close()
+
+
+def test_config1_fp64_end_to_end():
+    """40x40x20 cells, 64 subdomains of 10x10x5, one patch per interface."""
+    case = config1()
+    ref = mrcm_solve(case)
+    m, p, U, X = _run(case)
+    assert rel_l2(p, ref.p) < 1e-8
+    assert rel_l2(U, ref.U) < 1e-8
+    assert rel_l2(X, ref.pi) < 1e-8
+    info = m.info()
+    assert info.n_sub == 64 and info.n_patch == 144 and info.n_mbfs == 4 * 144
+    m.close()
+
+
+def test_config1_fp32_refined_end_to_end():
+    case = config1()
+    ref = mrcm_solve(case)
+    m, p, U, X = _run(case, precision=1)
+    info = m.info()
+    assert info.ir_residual <= 1e-13
+    assert rel_l2(p, ref.p) < 1e-8
+    assert rel_l2(U, ref.U) < 1e-8
+    m.close()
+
+
+def test_mass_conservation_on_gpu_output():
+    case = small_case((10, 8, 6), (2, 2, 3), split=((2, 1), (1, 2), (2, 2)), seed=5, std=2.0)
+    m, p, U, X = _run(case)
+    pb = case.problem
+    A = np.array([pb.hy * pb.hz, pb.hx * pb.hz, pb.hx * pb.hy])
+    Q = U * np.repeat(A, 2)[:, None]
+    net = Q.sum(axis=0) - pb.q
+    assert np.max(np.abs(net)) < 1e-12 * np.max(np.abs(Q).sum(axis=0))
+    m.close()
+
+
+def test_rebuild_in_place_is_deterministic():
+    """A second build into the same handle (no allocation) gives bitwise the same MBFs."""
+    import paper_2103_08513_amd as lib
+    case = small_case((10, 8, 6), (2, 2, 3), split=((2, 1), (1, 2), (2, 2)), seed=5)
+    pb = case.problem
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha)
+    args = (_dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q))
+    p1, U1, X1 = m.solve(*args)
+    a = [m.copy_mbfs(l) for l in range(12)]
+    A1, _ = m.copy_interface()
+    p1 = p1.cpu().numpy().copy()
+    p2, U2, X2 = m.solve(*args)
+    b = [m.copy_mbfs(l) for l in range(12)]
+    A2, _ = m.copy_interface()
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    assert np.array_equal(A1, A2)
+    assert np.array_equal(p1, p2.cpu().numpy())
+    m.close()
+
+
+def test_invalid_permeability_is_rejected():
+    import paper_2103_08513_amd as lib
+    case = small_case((6, 4, 4), (2, 1, 1), seed=0)
+    pb = case.problem
+    kx = pb.kx.copy()
+    kx[5] = -1.0
+    m = lib.MRCM(pb, case.partition, case.iface)
+    with pytest.raises(lib.MRCMError) as ei:
+        m.build_mbfs(_dev(kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q))
+    assert ei.value.code == -1
+
+
+def test_config2_sampled_subdomains():
+    """The 60x220x85 workload (561 subdomains of 20x20x5, b = 100, m up to 33):
+    MBFs of sampled interior, face, edge and corner subdomains vs the oracle."""
+    case = config2()
+    pb = case.problem
+    import paper_2103_08513_amd as lib
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha)
+    m.build_mbfs(_dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q))
+    torch.cuda.synchronize()
+    geo = Geometry(pb.dims, case.partition, case.iface)
+    sample = [0, 1, 4, 37, 280, 300, 560, geo.n_sub // 2]
+    systems, Xs, Fs, Fbs, SAbs = oracle_build(pb, geo, case.alpha, subdomains=sample)
+    for l, X, F in zip(sample, Xs, Fs):
+        Xg = m.copy_mbfs(l)[np.argsort(m.local_order(l))]
+        for c in range(X.shape[1]):
+            assert _maxrel(Xg[:, c], X[:, c]) < 1e-9, (l, c)
+        Fg, _, _ = m.copy_flux(l)
+        assert _maxrel(Fg, F) < 1e-9
+    m.close()
