@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""MRCM benchmark: one step = one whole MRCM solve (Algorithm 2) on the GPU.
+
+Workload: the 60x220x85 channelised reservoir block (cells of 20x10x2 ft),
+3x11x17 = 561 subdomains of 20x20x5 cells, patches 2x1 on x/y-normal and 2x2
+on z-normal interfaces (N_V = 3,880 patches, 15,520 MBFs), alpha = 1,
+quarter-five-spot wells, synthetic seeded field.  Inputs are resident in HBM
+before the timed region.
+
+Reported: MBFs per second of whole MRCM solve (value), cells per second, the
+build-only rate, stage times from HIP events, the roofline position of the
+dominant kernel, the error against the FP64 CPU oracle, and the oracle's own
+rate on this host (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_gpu(case, precision, steps, warmup, refine):
+    import torch
+    import paper_2103_08513_amd as lib
+    from paper_2103_08513_amd import _lib
+    pb = case.problem
+    dev = torch.device("cuda:0")
+    kx, ky, kz, q = (torch.as_tensor(a, dtype=torch.float64, device=dev) for a in (pb.kx, pb.ky, pb.kz, pb.q))
+    model = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision)
+    N = pb.n
+    X = None
+    p = torch.empty(N, dtype=torch.float64, device=dev)
+    U = torch.empty(6 * N, dtype=torch.float64, device=dev)
+
+    def step():
+        nonlocal X
+        model.build_mbfs(kx, ky, kz, q)
+        model.assemble_interface()
+        X = model.solve_interface(X, refine=refine)
+        model.reconstruct(X, p, U)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    L = _lib.load()
+    L.mrcm_profile_reset()
+    L.mrcm_profile_enable(0)
+    # timed region: K whole solves, synchronised on both sides
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    # stage times from HIP events, over the same number of steps
+    L.mrcm_profile_reset()
+    L.mrcm_profile_enable(1)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    prof = _lib.CProfile()
+    L.mrcm_profile_get(ctypes_byref(prof))
+    L.mrcm_profile_enable(0)
+    stages = {}
+    for i, name in enumerate(_lib.STAGES):
+        if prof.count[i]:
+            stages[name] = {"ms_total": prof.ms[i], "count": int(prof.count[i]),
+                            "ms_avg": prof.ms[i] / prof.count[i]}
+    info = model.info()
+    n_dims, w = model.interface_dims()
+    out = dict(ms_step=ms_step, stages=stages, info=info, interface_n=n_dims, interface_w=w,
+               p=p.cpu().numpy(), U=U.view(6, N).cpu().numpy(), X=X.cpu().numpy(),
+               interface_residual=model.interface_residual)
+    model.close()
+    return out
+
+
+def ctypes_byref(x):
+    import ctypes
+    return ctypes.byref(x)
+
+
+def cpu_baseline(case):
+    """The CPU oracle as it stands, one thread, whole MRCM solve of the workload."""
+    from threadpoolctl import threadpool_limits
+    from oracle.mrcm import mrcm_solve
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        r = mrcm_solve(case)
+        t = time.perf_counter() - t
+    return r, t
+
+
+def roofline_for(stage_name, res, info, precision):
+    st = res["stages"].get(stage_name)
+    if st is None:
+        return None
+    sec = st["ms_avg"] * 1e-3
+    es = 4 if precision == 1 else 8
+    if stage_name == "factor":
+        flops = info.factor_flops
+        peak = PEAK_FP32_TFLOPS if precision == 1 else PEAK_FP64_TFLOPS
+        ach = flops / sec / 1e12
+        return {"kernel": "k_factor", "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None, "ms_avg": st["ms_avg"],
+                "algorithmic_flops": flops}
+    if stage_name == "solve":
+        # forward + backward sweeps read the band factor twice and write X once
+        nbytes = 0.0
+        for l_n, l_b, l_m in res["sub_shapes"]:
+            nbytes += 2.0 * es * l_n * (l_b + 1) + 8.0 * l_n * l_m
+        ach = nbytes / sec / 1e9
+        return {"kernel": "k_solve", "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None, "ms_avg": st["ms_avg"],
+                "algorithmic_bytes": nbytes}
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64")
+    ap.add_argument("--refine", type=int, default=1, help="FP64 refinement steps of the interface solve")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the other precision")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+    from mrcm_inputs import config2
+    from oracle.norms import rel_l2
+    case = config2()
+    pb = case.problem
+    prec = 1 if args.precision == "fp32ir" else 0
+    log(f"workload 60x220x85, precision {args.precision}, steps {args.steps}, warmup {args.warmup}")
+    res = run_gpu(case, prec, args.steps, args.warmup, args.refine)
+    info = res["info"]
+    from oracle.geometry import Geometry
+    geo = Geometry(pb.dims, case.partition, case.iface)
+    shapes = []
+    for l in range(geo.n_sub):
+        ext = geo.sub_hi[l] - geo.sub_lo[l]
+        e = sorted(int(x) for x in ext)
+        shapes.append((e[0] * e[1] * e[2], e[0] * e[1], 2 * len(geo.sub_patches[l]) + 1))
+    res["sub_shapes"] = shapes
+    log(f"ms/step {res['ms_step']:.3f}; stages " +
+        ", ".join(f"{k} {v['ms_avg']:.3f}" for k, v in res["stages"].items()))
+    secondary = None
+    if not args.no_secondary:
+        other = 1 - prec
+        r2 = run_gpu(case, other, args.steps, args.warmup, args.refine)
+        r2["sub_shapes"] = shapes
+        secondary = r2
+        log(f"other precision ms/step {r2['ms_step']:.3f}")
+    cpu = None
+    err = {}
+    if not args.no_cpu_baseline:
+        log("oracle (CPU, FP64) whole solve ...")
+        ref, t_cpu = cpu_baseline(case)
+        cpu = {"value": info.n_mbfs / t_cpu, "unit": "MBFs/s", "cores": 1, "kind": "oracle",
+               "sample": "whole MRCM solve of the 60x220x85 workload (561 subdomains, 15,520 MBFs), "
+                         "single thread", "seconds": t_cpu, "mcells_per_s": pb.n / t_cpu / 1e6}
+        err = {"p": rel_l2(res["p"], ref.p), "U": rel_l2(res["U"], ref.U), "pi": rel_l2(res["X"], ref.pi)}
+        if secondary is not None:
+            secondary["err"] = {"p": rel_l2(secondary["p"], ref.p), "U": rel_l2(secondary["U"], ref.U)}
+    t_step = res["ms_step"] * 1e-3
+    build_ms = sum(res["stages"].get(k, {}).get("ms_avg", 0.0) *
+                   (res["stages"].get(k, {}).get("count", 0) / max(1, args.steps))
+                   for k in ("coef", "factor", "solve", "refine", "flux"))
+    # dominant hot-path kernel by time
+    cand = [k for k in ("factor", "solve") if k in res["stages"]]
+    dom = max(cand, key=lambda k: res["stages"][k]["ms_total"])
+    roof = roofline_for(dom, res, info, prec)
+    line = {
+        "metric": "MBFs/s & Mcells/s per MRCM solve: FP32+IR & surrogate vs FP64, at rel err 1e-8",
+        "value": info.n_mbfs / t_step,
+        "unit": "MBFs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "60x220x85 channelised block, 561 subdomains of 20x20x5, "
+                               "2x1/2x1/2x2 patches, alpha 1, MRCM whole solve",
+                   "cells": pb.n, "subdomains": info.n_sub, "patches": info.n_patch,
+                   "mbfs": int(info.n_mbfs), "precision": args.precision},
+        "mcells_per_s": pb.n / t_step / 1e6,
+        "build_mbfs_per_s": info.n_mbfs / (build_ms * 1e-3) if build_ms > 0 else None,
+        "build_ms": build_ms,
+        "stages_ms": {k: round(v["ms_avg"] * v["count"] / args.steps, 4) for k, v in res["stages"].items()},
+        "interface": {"unknowns": res["interface_n"], "bandwidth": res["interface_w"],
+                      "rel_residual": res["interface_residual"]},
+        "rel_err_vs_oracle": err,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if prec == 1 or secondary is not None:
+        ir_info = info if prec == 1 else secondary["info"]
+        line["ir"] = {"sweeps": int(ir_info.ir_iters), "residual": ir_info.ir_residual}
+    if secondary is not None:
+        sp = "fp32ir" if prec == 0 else "fp64"
+        line["other_precision"] = {
+            "precision": sp, "ms_per_step": secondary["ms_step"],
+            "value": info.n_mbfs / (secondary["ms_step"] * 1e-3),
+            "stages_ms": {k: round(v["ms_avg"] * v["count"] / args.steps, 4)
+                          for k, v in secondary["stages"].items()},
+            "rel_err_vs_oracle": secondary.get("err"),
+            "roofline": roofline_for(max([k for k in ("factor", "solve") if k in secondary["stages"]],
+                                         key=lambda k: secondary["stages"][k]["ms_total"]),
+                                     secondary, secondary["info"], 1 - prec),
+        }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -231,6 +231,28 @@ mrcm_status mrcm_copy_factor(const mrcm_mbfs *mbfs, int32_t l, double *Lband);
 mrcm_status mrcm_interface_dims(const mrcm_interface *iface, int32_t *n, int32_t *bandwidth);
 mrcm_status mrcm_copy_interface(const mrcm_interface *iface, double *A, double *b);
 
+/*
+ * Stage profiling with HIP events recorded on the caller's stream (tracing
+ * subsystem; off by default).  While enabled, every call records an event
+ * pair around each stage and accumulates the elapsed milliseconds and the
+ * number of occurrences in a process-wide table, resolved when the call has
+ * synchronised.  Stages: coefficients (one kernel), local factorisation (one
+ * kernel), local solves (one kernel per sweep set), refinement residuals and
+ * corrections, Gamma-flux reduction (one kernel), interface assembly,
+ * interface LU (two kernels per 32-column block), interface triangular
+ * sweeps, reconstruction.
+ */
+enum { MRCM_STAGE_COEF = 0, MRCM_STAGE_FACTOR, MRCM_STAGE_SOLVE, MRCM_STAGE_REFINE,
+       MRCM_STAGE_FLUX, MRCM_STAGE_ASSEMBLE, MRCM_STAGE_LU, MRCM_STAGE_SWEEP,
+       MRCM_STAGE_RECONSTRUCT, MRCM_STAGE_COUNT };
+typedef struct {
+  double ms[16];        /* accumulated milliseconds per stage */
+  int64_t count[16];    /* occurrences per stage */
+} mrcm_profile;
+void mrcm_profile_enable(int32_t on);
+void mrcm_profile_reset(void);
+mrcm_status mrcm_profile_get(mrcm_profile *out /* [host] */);
+
 void mrcm_mbfs_destroy(mrcm_mbfs *mbfs);
 void mrcm_interface_destroy(mrcm_interface *iface);
 const char *mrcm_status_string(mrcm_status status);

@@ -16,8 +16,11 @@ EXPORTS = [
     "mrcm_build_mbfs", "mrcm_assemble_interface", "mrcm_solve_interface", "mrcm_reconstruct",
     "mrcm_query", "mrcm_get_subdomain", "mrcm_copy_mbfs", "mrcm_copy_flux", "mrcm_copy_factor",
     "mrcm_interface_dims", "mrcm_copy_interface", "mrcm_mbfs_destroy", "mrcm_interface_destroy",
-    "mrcm_status_string", "mrcm_last_error",
+    "mrcm_status_string", "mrcm_last_error", "mrcm_profile_enable", "mrcm_profile_reset",
+    "mrcm_profile_get",
 ]
+
+STAGES = ["coef", "factor", "solve", "refine", "flux", "assemble", "lu", "sweep", "reconstruct"]
 
 
 class CProblem(ctypes.Structure):
@@ -48,6 +51,10 @@ class CInfo(ctypes.Structure):
                 ("max_rhs", c_int32), ("precision", c_int32), ("ir_iters", c_int32),
                 ("ir_residual", c_double), ("factor_flops", c_double), ("solve_flops", c_double),
                 ("device_bytes", c_int64)]
+
+
+class CProfile(ctypes.Structure):
+    _fields_ = [("ms", c_double * 16), ("count", c_int64 * 16)]
 
 
 class CSubInfo(ctypes.Structure):
@@ -86,6 +93,9 @@ def load(path: str = LIB_PATH):
         "mrcm_interface_destroy": ([c_void_p], None),
         "mrcm_status_string": ([c_int32], c_char_p),
         "mrcm_last_error": ([], c_char_p),
+        "mrcm_profile_enable": ([c_int32], None),
+        "mrcm_profile_reset": ([], None),
+        "mrcm_profile_get": ([P(CProfile)], c_int32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)

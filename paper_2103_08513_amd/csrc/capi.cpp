@@ -356,6 +356,52 @@ void rcm_order(const HostGeom &G, std::vector<int> &pos, int &w) {
   w = bw;
 }
 
+// Stage profiling: event pairs recorded on the caller's stream, resolved
+// after the call's own synchronisation.
+struct Profile {
+  bool on = false;
+  double ms[16] = {};
+  int64_t count[16] = {};
+  struct Pending {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+};
+Profile g_prof;
+
+struct Stage {
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  Stage(int st, hipStream_t str) : stage(st), s(str) {
+    if (!g_prof.on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      a = b = nullptr;
+      return;
+    }
+    (void)hipEventRecord(a, s);
+  }
+  ~Stage() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    g_prof.pending.push_back({stage, a, b});
+  }
+};
+
+void profile_flush() {
+  for (auto &p : g_prof.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      g_prof.ms[p.stage] += ms;
+      g_prof.count[p.stage] += 1;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  g_prof.pending.clear();
+}
+
 }  // namespace
 
 struct mrcm_mbfs {
@@ -563,18 +609,30 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   ENQ(launch_check_perm(pb->kx, pb->ky, pb->kz, N, h->st, s));
   st = read_status(h->st, s, "mrcm_build_mbfs");
   if (st != MRCM_OK) return bail(st);
-  ENQ(launch_coef(g, h->n_sub, H.max_cells, h->coef, h->r0, h->scal, s));
-  ENQ(launch_factor(fp32, h->d_sub, h->d_order, h->n_sub, h->coef, h->scal, h->L, h->Dinv, h->st,
-                    H.bmax, s));
-  ENQ(launch_solve(fp32, g, h->d_order, h->n_sub, h->r0, h->scal, h->L, h->Dinv, h->X, nullptr, 0,
-                   H.bmax, H.mmax, s));
+  {
+    Stage t(MRCM_STAGE_COEF, s);
+    ENQ(launch_coef(g, h->n_sub, H.max_cells, h->coef, h->r0, h->scal, s));
+  }
+  {
+    Stage t(MRCM_STAGE_FACTOR, s);
+    ENQ(launch_factor(fp32, h->d_sub, h->d_order, h->n_sub, h->coef, h->scal, h->L, h->Dinv, h->st,
+                      H.bmax, s));
+  }
+  {
+    Stage t(MRCM_STAGE_SOLVE, s);
+    ENQ(launch_solve(fp32, g, h->d_order, h->n_sub, h->r0, h->scal, h->L, h->Dinv, h->X, nullptr, 0,
+                     H.bmax, H.mmax, s));
+  }
   h->ir_iters = 0;
   h->ir_res = 0.0;
   if (fp32) {
     for (int it = 0;; ++it) {
-      ENQ(launch_fill(h->norms, 2LL * H.totCols, 0.0, s));
-      ENQ(launch_residual(g, h->n_sub, H.max_nm, h->coef, h->r0, h->X, h->R, h->norms, s));
-      ENQ(launch_ir_check(h->norms, H.totCols, h->scalar, s));
+      {
+        Stage t(MRCM_STAGE_REFINE, s);
+        ENQ(launch_fill(h->norms, 2LL * H.totCols, 0.0, s));
+        ENQ(launch_residual(g, h->n_sub, H.max_nm, h->coef, h->r0, h->X, h->R, h->norms, s));
+        ENQ(launch_ir_check(h->norms, H.totCols, h->scalar, s));
+      }
       double res = 0.0;
       ENQ(hipMemcpyAsync(&res, h->scalar, sizeof(double), hipMemcpyDeviceToHost, s));
       ENQ(hipStreamSynchronize(s));
@@ -588,12 +646,19 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
         snprintf(buf, sizeof buf, "refinement stopped at relative residual %.3g after %d sweeps", res, it);
         return bail(fail(MRCM_ENOCONV, buf));
       }
-      ENQ(launch_solve(fp32, g, h->d_order, h->n_sub, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, 1,
-                       H.bmax, H.mmax, s));
+      {
+        Stage t(MRCM_STAGE_REFINE, s);
+        ENQ(launch_solve(fp32, g, h->d_order, h->n_sub, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, 1,
+                         H.bmax, H.mmax, s));
+      }
     }
   }
-  ENQ(launch_flux(g, h->n_sub, h->X, h->F, h->Fb, h->SAb, s));
+  {
+    Stage t(MRCM_STAGE_FLUX, s);
+    ENQ(launch_flux(g, h->n_sub, h->X, h->F, h->Fb, h->SAb, s));
+  }
   st = read_status(h->st, s, "mrcm_build_mbfs");
+  profile_flush();
   if (st != MRCM_OK) return bail(st);
 #undef ENQ
   *out = h;
@@ -632,14 +697,17 @@ mrcm_status mrcm_assemble_interface(const mrcm_mbfs *mb, void *stream, mrcm_inte
     if (created) free_iface(h);
     return e;
   };
-  hipError_t e = launch_fill(h->AB, band, 0.0, s);
-  if (e == hipSuccess) e = launch_fill(h->b, h->n, 0.0, s);
-  if (e == hipSuccess && h->nv > 0)
-    e = launch_iface_scatter(mb->g, mb->n_sub, mb->d_patches, h->d_pos, mb->F, mb->Fb, mb->SAb, h->AB,
-                             h->w, h->b, s);
-  if (e == hipSuccess) e = launch_copy(h->AB, h->AB0, band, s);
-  if (e == hipSuccess) e = launch_copy(h->b, h->b0, h->n, s);
+  hipError_t e;
+  {
+    Stage t(MRCM_STAGE_ASSEMBLE, s);
+    e = launch_fill(h->AB0, band, 0.0, s);
+    if (e == hipSuccess) e = launch_fill(h->b0, h->n, 0.0, s);
+    if (e == hipSuccess && h->nv > 0)
+      e = launch_iface_scatter(mb->g, mb->n_sub, mb->d_patches, h->d_pos, mb->F, mb->Fb, mb->SAb,
+                               h->AB0, h->w, h->b0, s);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  profile_flush();
   if (e != hipSuccess) return bail(fail(MRCM_EHIP, std::string("interface assembly: ") + hipGetErrorString(e)));
   *out = h;
   return MRCM_OK;
@@ -658,19 +726,26 @@ mrcm_status mrcm_solve_interface(mrcm_interface *h, int32_t refine, void *stream
   }
   const int64_t band = (int64_t)h->n * (2 * h->w + 1);
   HIP_TRY(launch_reset_status(h->st, s));
-  // factor a fresh copy of the assembled system (the assembled one stays for refinement)
-  HIP_TRY(launch_copy(h->AB0, h->AB, band, s));
-  HIP_TRY(launch_copy(h->b0, h->b, h->n, s));
-  HIP_TRY(launch_band_lu(h->AB, h->n, h->w, h->diag, h->b, h->st, s));
-  HIP_TRY(launch_lu_sweep(h->AB, h->n, h->w, h->b, 1, s));
-  for (int it = 0; it < refine; ++it) {
-    HIP_TRY(launch_band_residual(h->AB0, h->n, h->w, h->b, h->b0, h->r, s));
-    HIP_TRY(launch_lu_sweep(h->AB, h->n, h->w, h->r, 0, s));
-    HIP_TRY(launch_lu_sweep(h->AB, h->n, h->w, h->r, 1, s));
-    HIP_TRY(launch_axpy(h->b, h->r, h->n, s));
+  {
+    // factor a fresh copy of the assembled system (the assembled one stays for refinement)
+    Stage t(MRCM_STAGE_LU, s);
+    HIP_TRY(launch_copy(h->AB0, h->AB, band, s));
+    HIP_TRY(launch_copy(h->b0, h->b, h->n, s));
+    HIP_TRY(launch_band_lu(h->AB, h->n, h->w, h->diag, h->b, h->st, s));
   }
-  HIP_TRY(launch_perm(h->b, h->d_pos, h->nv, X, 1, s));
+  {
+    Stage t(MRCM_STAGE_SWEEP, s);
+    HIP_TRY(launch_lu_sweep(h->AB, h->n, h->w, h->b, 1, s));
+    for (int it = 0; it < refine; ++it) {
+      HIP_TRY(launch_band_residual(h->AB0, h->n, h->w, h->b, h->b0, h->r, s));
+      HIP_TRY(launch_lu_sweep(h->AB, h->n, h->w, h->r, 0, s));
+      HIP_TRY(launch_lu_sweep(h->AB, h->n, h->w, h->r, 1, s));
+      HIP_TRY(launch_axpy(h->b, h->r, h->n, s));
+    }
+    HIP_TRY(launch_perm(h->b, h->d_pos, h->nv, X, 1, s));
+  }
   mrcm_status st = read_status(h->st, s, "mrcm_solve_interface");
+  profile_flush();
   if (st != MRCM_OK) return st;
   if (rel_residual) {
     HIP_TRY(launch_band_residual(h->AB0, h->n, h->w, h->b, h->b0, h->r, s));
@@ -689,8 +764,15 @@ mrcm_status mrcm_reconstruct(const mrcm_mbfs *mb, const double *X, void *stream,
   if (!mb || !p || !U) return fail(MRCM_EINVAL, "null argument");
   if (mb->G.n_patch > 0 && !X) return fail(MRCM_EINVAL, "X is null");
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(launch_recon_p(mb->g, mb->n_sub, mb->d_patches, mb->X, X, mb->G.n_patch, p, s));
-  HIP_TRY(launch_recon_u(mb->g, p, X, mb->G.n_patch, U, s));
+  {
+    Stage t(MRCM_STAGE_RECONSTRUCT, s);
+    HIP_TRY(launch_recon_p(mb->g, mb->n_sub, mb->d_patches, mb->X, X, mb->G.n_patch, p, s));
+    HIP_TRY(launch_recon_u(mb->g, p, X, mb->G.n_patch, U, s));
+  }
+  if (g_prof.on) {
+    HIP_TRY(hipStreamSynchronize(s));
+    profile_flush();
+  }
   return MRCM_OK;
 }
 
@@ -795,6 +877,29 @@ mrcm_status mrcm_copy_interface(const mrcm_interface *h, double *A, double *b) {
       const int bi = bidx[i], bj = bidx[j];
       A[(size_t)i * n + j] = (std::abs(bi - bj) <= w) ? band[(size_t)bj * ld + (w + bi - bj)] : 0.0;
     }
+  }
+  return MRCM_OK;
+}
+
+void mrcm_profile_enable(int32_t on) {
+  profile_flush();
+  g_prof.on = on != 0;
+}
+
+void mrcm_profile_reset(void) {
+  profile_flush();
+  for (int i = 0; i < 16; ++i) {
+    g_prof.ms[i] = 0.0;
+    g_prof.count[i] = 0;
+  }
+}
+
+mrcm_status mrcm_profile_get(mrcm_profile *out) {
+  if (!out) return fail(MRCM_EINVAL, "null argument");
+  profile_flush();
+  for (int i = 0; i < 16; ++i) {
+    out->ms[i] = g_prof.ms[i];
+    out->count[i] = g_prof.count[i];
   }
   return MRCM_OK;
 }
