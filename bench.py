@@ -34,14 +34,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(case, precision, steps, warmup, refine):
+def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1):
     import torch
     import paper_2103_08513_amd as lib
     from paper_2103_08513_amd import _lib
     pb = case.problem
     dev = torch.device("cuda:0")
     kx, ky, kz, q = (torch.as_tensor(a, dtype=torch.float64, device=dev) for a in (pb.kx, pb.ky, pb.kz, pb.q))
-    model = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision)
+    model = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision,
+                     fp64_refine=fp64_refine)
     N = pb.n
     X = None
     p = torch.empty(N, dtype=torch.float64, device=dev)
@@ -138,7 +139,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64")
-    ap.add_argument("--refine", type=int, default=1, help="FP64 refinement steps of the interface solve")
+    ap.add_argument("--refine", type=int, default=0, help="FP64 refinement steps of the interface solve")
+    ap.add_argument("--fp64-refine", type=int, default=1, help="FP64 refinement sweeps of the FP64 local solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other precision")
     args = ap.parse_args()
@@ -156,7 +158,7 @@ def main():
     pb = case.problem
     prec = 1 if args.precision == "fp32ir" else 0
     log(f"workload 60x220x85, precision {args.precision}, steps {args.steps}, warmup {args.warmup}")
-    res = run_gpu(case, prec, args.steps, args.warmup, args.refine)
+    res = run_gpu(case, prec, args.steps, args.warmup, args.refine, args.fp64_refine)
     info = res["info"]
     from oracle.geometry import Geometry
     geo = Geometry(pb.dims, case.partition, case.iface)
@@ -171,7 +173,7 @@ def main():
     secondary = None
     if not args.no_secondary:
         other = 1 - prec
-        r2 = run_gpu(case, other, args.steps, args.warmup, args.refine)
+        r2 = run_gpu(case, other, args.steps, args.warmup, args.refine, args.fp64_refine)
         r2["sub_shapes"] = shapes
         secondary = r2
         log(f"other precision ms/step {r2['ms_step']:.3f}")

@@ -52,7 +52,7 @@ enum { MRCM_WALL_NOFLOW = 0, MRCM_WALL_DIRICHLET = 1, MRCM_WALL_NEUMANN = 2 };
 
 /* Precision of the local factorisations. */
 enum { MRCM_FP64 = 0,          /* FP64 band Cholesky and solves */
-       MRCM_FP32_IR = 1 };     /* FP32 factor of the Jacobi-scaled matrix + FP64 refinement */
+       MRCM_FP32_IR = 1 };     /* FP32 factor and solves + FP64 refinement */
 
 /*
  * The Darcy problem (Sec. 2.1).  All arrays have N = nx*ny*nz entries.
@@ -113,12 +113,16 @@ typedef struct {
  * ir_tol       FP32_IR: stop when every column's relative FP64 residual
  *              ||R - M X|| / ||R|| is at most ir_tol (<= 0 selects 1e-13).
  * ir_max_iter  FP32_IR: refinement sweeps before MRCM_ENOCONV (<= 0: 30).
+ * fp64_refine  FP64: fixed number of FP64 refinement sweeps (residual
+ *              R - A X from the coefficients, correction with the same factor)
+ *              after the direct solves; 0 for none.
  */
 typedef struct {
   double alpha;
   int32_t precision;
   double ir_tol;
   int32_t ir_max_iter;
+  int32_t fp64_refine;
 } mrcm_options;
 
 typedef struct mrcm_mbfs mrcm_mbfs;           /* local factors, MBFs, Gamma-flux blocks */
@@ -216,8 +220,8 @@ mrcm_status mrcm_get_subdomain(const mrcm_mbfs *mbfs, int32_t l, mrcm_subdomain_
 /* Copies for tests and tools (synchronous; [host] outputs).
  *  mrcm_copy_mbfs:    X_l, row-major [n_cells][n_rhs] in the local row ordering.
  *  mrcm_copy_flux:    F and Fb [n_patch][n_rhs], SAb [n_patch] (sum A beta per patch).
- *  mrcm_copy_factor:  Cholesky factor L of A^H_l (of the Jacobi-scaled matrix
- *                     D^-1/2 A D^-1/2 for MRCM_FP32_IR) in the local row order,
+ *  mrcm_copy_factor:  Cholesky factor L of the Jacobi-scaled local matrix
+ *                     D^-1/2 A^H_l D^-1/2 (D its diagonal) in the local row order,
  *                     by column, [n_cells][band+1] with entry (j, t) = L[j+t][j],
  *                     converted to double.
  */

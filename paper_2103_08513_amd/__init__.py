@@ -50,7 +50,7 @@ class MRCM:
     ``mrcm_inputs`` (or any objects with the same attributes)."""
 
     def __init__(self, problem, partition, iface, alpha=1.0, precision=FP64, ir_tol=1e-13,
-                 ir_max_iter=30, device="cuda"):
+                 ir_max_iter=30, fp64_refine=1, device="cuda"):
         import torch
         self.lib = library()
         self.device = torch.device(device)
@@ -97,6 +97,7 @@ class MRCM:
         opt.precision = int(precision)
         opt.ir_tol = float(ir_tol)
         opt.ir_max_iter = int(ir_max_iter)
+        opt.fp64_refine = int(fp64_refine)
         self._opt = opt
 
     # -- the four steps of Algorithm 2 ------------------------------------
@@ -117,7 +118,7 @@ class MRCM:
         _lib.check(code, "mrcm_assemble_interface")
         return self
 
-    def solve_interface(self, X=None, refine=1, stream=None):
+    def solve_interface(self, X=None, refine=0, stream=None):
         import torch
         info = self.info()
         nv = info.n_patch
@@ -143,7 +144,7 @@ class MRCM:
         _lib.check(code, "mrcm_reconstruct")
         return p, U.view(6, N)
 
-    def solve(self, kx, ky, kz, q, refine=1, stream=None):
+    def solve(self, kx, ky, kz, q, refine=0, stream=None):
         """Whole MRCM: MBFs, interface assembly and solve, reconstruction."""
         self.build_mbfs(kx, ky, kz, q, stream)
         self.assemble_interface(stream)
@@ -235,7 +236,7 @@ def assemble_interface(model: MRCM, stream=None):
     return model.assemble_interface(stream)
 
 
-def solve_interface(model: MRCM, refine=1, stream=None):
+def solve_interface(model: MRCM, refine=0, stream=None):
     return model.solve_interface(refine=refine, stream=stream)
 
 

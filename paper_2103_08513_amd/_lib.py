@@ -42,7 +42,7 @@ class CIfaceSpace(ctypes.Structure):
 
 class COptions(ctypes.Structure):
     _fields_ = [("alpha", c_double), ("precision", c_int32), ("ir_tol", c_double),
-                ("ir_max_iter", c_int32)]
+                ("ir_max_iter", c_int32), ("fp64_refine", c_int32)]
 
 
 class CInfo(ctypes.Structure):

@@ -63,6 +63,7 @@ struct HostGeom {
   std::vector<IfaceDesc> ifcs;
   std::vector<int> patches;  // concatenated I^l
   std::vector<int> order;    // launch order, most expensive first
+  std::vector<int4> work;    // solve work items (subdomain, first column, end column)
   std::vector<int> sub_of[3];
   int n_patch = 0;
   int bmax = 0, mmax = 0, max_cells = 0;
@@ -268,7 +269,7 @@ mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
     return fail(MRCM_EUNSUPPORTED, "a subdomain has " + std::to_string(G.mmax) +
                                        " right-hand sides; the limit is " + std::to_string(kMaxRhs));
   const int fp32 = G.precision == MRCM_FP32_IR;
-  if (solve_lds_bytes(fp32, G.bmax, G.mmax) > 160 * 1024)
+  if (solve_lds_bytes(fp32, G.bmax, G.mmax) > 160 * 1024 || factor_lds_bytes(fp32, G.bmax) > 160 * 1024)
     return fail(MRCM_EUNSUPPORTED, "band and right-hand-side window exceed the 160 KiB LDS");
   // launch order: most expensive subdomain first (N b^2 + N b m)
   G.order.resize(n_sub);
@@ -279,6 +280,30 @@ mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
     const double cb = (double)B.N * B.b * (B.b + 4.0 * B.m);
     return ca > cb;
   });
+  // Solve work items: column chunks of whole 16-column tiles, at most
+  // solve_chunk_max() columns, balanced.  Chunks of one subdomain go to the
+  // same XCD (workgroup i runs on XCD i mod 8) so they share its L2 when they
+  // read the subdomain's factor; consecutive subdomains rotate over XCDs.
+  {
+    const int kXcd = 8;
+    std::vector<std::vector<int4>> per(kXcd);
+    const int maxt = solve_chunk_max() / 16;
+    for (int idx = 0; idx < n_sub; ++idx) {
+      const int l = G.order[idx];
+      const SubDesc &S = G.subs[l];
+      const int nt = (S.m + 15) / 16;
+      const int nch = (nt + maxt - 1) / maxt;
+      for (int ch = 0; ch < nch; ++ch) {
+        const int t0 = split_start(ch, nt, nch), t1 = split_start(ch + 1, nt, nch);
+        per[idx % kXcd].push_back(make_int4(l, 16 * t0, std::min(S.m, 16 * t1), 0));
+      }
+    }
+    size_t kmax = 0;
+    for (auto &v : per) kmax = std::max(kmax, v.size());
+    G.work.assign(kXcd * kmax, make_int4(-1, 0, 0, 0));
+    for (int x = 0; x < kXcd; ++x)
+      for (size_t k = 0; k < per[x].size(); ++k) G.work[kXcd * k + x] = per[x][k];
+  }
   return MRCM_OK;
 }
 
@@ -411,6 +436,7 @@ struct mrcm_mbfs {
   SubDesc *d_sub = nullptr;
   IfaceDesc *d_ifc = nullptr;
   int *d_order = nullptr;
+  int4 *d_work = nullptr;
   int *d_patches = nullptr;
   int *d_subof[3] = {nullptr, nullptr, nullptr};
   double *coef = nullptr, *r0 = nullptr, *scal = nullptr;
@@ -424,6 +450,7 @@ struct mrcm_mbfs {
   double ir_res = 0.0;
   double ir_tol = 1e-13;
   int ir_max = 30;
+  int refine64 = 0;
   int64_t bytes = 0;
 };
 
@@ -444,7 +471,7 @@ namespace {
 
 void free_mbfs(mrcm_mbfs *h) {
   if (!h) return;
-  void *ptrs[] = {h->d_sub, h->d_ifc, h->d_order, h->d_patches, h->d_subof[0], h->d_subof[1],
+  void *ptrs[] = {h->d_sub, h->d_ifc, h->d_order, h->d_work, h->d_patches, h->d_subof[0], h->d_subof[1],
                   h->d_subof[2], h->coef, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, h->F, h->Fb, h->SAb,
                   h->norms, h->scalar, h->st};
   for (void *p : ptrs)
@@ -475,6 +502,7 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
   HIP_TRY(upload(&h->d_sub, G.subs));
   HIP_TRY(upload(&h->d_ifc, G.ifcs));
   HIP_TRY(upload(&h->d_order, G.order));
+  HIP_TRY(upload(&h->d_work, G.work));
   HIP_TRY(upload(&h->d_patches, G.patches));
   for (int d = 0; d < 3; ++d) HIP_TRY(upload(&h->d_subof[d], subof[d]));
   ALLOC(h->coef, 4 * G.totCells, double);
@@ -587,6 +615,8 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   h->stream = s;
   h->ir_tol = opt->ir_tol > 0.0 ? opt->ir_tol : 1e-13;
   h->ir_max = opt->ir_max_iter > 0 ? opt->ir_max_iter : 30;
+  if (opt->fp64_refine < 0 || opt->fp64_refine > 10) return fail(MRCM_EINVAL, "fp64_refine must be in [0, 10]");
+  h->refine64 = opt->fp64_refine;
   Geom &g = h->g;
   g.k[0] = pb->kx;
   g.k[1] = pb->ky;
@@ -620,11 +650,27 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   }
   {
     Stage t(MRCM_STAGE_SOLVE, s);
-    ENQ(launch_solve(fp32, g, h->d_order, h->n_sub, h->r0, h->scal, h->L, h->Dinv, h->X, nullptr, 0,
-                     H.bmax, H.mmax, s));
+    ENQ(launch_rhs(g, h->n_sub, H.max_nm, h->r0, h->X, s));
+    ENQ(launch_solve(fp32, g, h->d_work, (int)H.work.size(), h->scal, h->L, h->Dinv, h->X, h->X, 0,
+                     H.bmax, s));
   }
   h->ir_iters = 0;
   h->ir_res = 0.0;
+  if (!fp32 && h->refine64 > 0) {
+    if (!h->R) {
+      if (dev_alloc(&h->R, (size_t)H.totX) != hipSuccess)
+        return bail(fail(MRCM_ENOMEM, "device allocation of the refinement buffer failed"));
+      h->bytes += H.totX * 8;
+    }
+    for (int it = 0; it < h->refine64; ++it) {
+      Stage t(MRCM_STAGE_REFINE, s);
+      ENQ(launch_fill(h->norms, 2LL * H.totCols, 0.0, s));
+      ENQ(launch_residual(g, h->n_sub, H.max_nm, h->coef, h->r0, h->X, h->R, h->norms, s));
+      ENQ(launch_solve(fp32, g, h->d_work, (int)H.work.size(), h->scal, h->L, h->Dinv, h->R, h->X,
+                       1, H.bmax, s));
+    }
+    h->ir_iters = h->refine64;
+  }
   if (fp32) {
     for (int it = 0;; ++it) {
       {
@@ -648,8 +694,8 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       }
       {
         Stage t(MRCM_STAGE_REFINE, s);
-        ENQ(launch_solve(fp32, g, h->d_order, h->n_sub, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, 1,
-                         H.bmax, H.mmax, s));
+        ENQ(launch_solve(fp32, g, h->d_work, (int)H.work.size(), h->scal, h->L, h->Dinv, h->R, h->X,
+                         1, H.bmax, s));
       }
     }
   }

@@ -50,27 +50,80 @@ __device__ __forceinline__ void set_status(DevStatus *st, int code, int where, d
 }
 
 // ---------------------------------------------------------------------------
-// Subdomain indexing.
+// Per-axis accessors.  Kernel arguments and small private arrays indexed with
+// a run-time axis would be spilled to scratch; selects keep them in registers.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void local_to_global(const SubDesc &S, int r, int x[3]) {
+struct I3 {
+  int v0, v1, v2;
+  __device__ __forceinline__ int operator[](int d) const { return d == 0 ? v0 : (d == 1 ? v1 : v2); }
+  __device__ __forceinline__ void set(int d, int x) {
+    v0 = (d == 0) ? x : v0;
+    v1 = (d == 1) ? x : v1;
+    v2 = (d == 2) ? x : v2;
+  }
+};
+
+__device__ __forceinline__ const double *kdir(const Geom &g, int d) {
+  return d == 0 ? g.k[0] : (d == 1 ? g.k[1] : g.k[2]);
+}
+__device__ __forceinline__ double hdir(const Geom &g, int d) {
+  return d == 0 ? g.h[0] : (d == 1 ? g.h[1] : g.h[2]);
+}
+__device__ __forceinline__ double adir(const Geom &g, int d) {
+  return d == 0 ? g.area[0] : (d == 1 ? g.area[1] : g.area[2]);
+}
+__device__ __forceinline__ int ndir(const Geom &g, int d) {
+  return d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
+}
+__device__ __forceinline__ int wall_type_of(const Geom &g, int f) {
+  int w = g.wall_type[0];
+  w = (f == 1) ? g.wall_type[1] : w;
+  w = (f == 2) ? g.wall_type[2] : w;
+  w = (f == 3) ? g.wall_type[3] : w;
+  w = (f == 4) ? g.wall_type[4] : w;
+  w = (f == 5) ? g.wall_type[5] : w;
+  return w;
+}
+__device__ __forceinline__ const double *wall_value_of(const Geom &g, int f) {
+  const double *w = g.wall_value[0];
+  w = (f == 1) ? g.wall_value[1] : w;
+  w = (f == 2) ? g.wall_value[2] : w;
+  w = (f == 3) ? g.wall_value[3] : w;
+  w = (f == 4) ? g.wall_value[4] : w;
+  w = (f == 5) ? g.wall_value[5] : w;
+  return w;
+}
+__device__ __forceinline__ const int *subof_dir(const Geom &g, int d) {
+  return d == 0 ? g.sub_of[0] : (d == 1 ? g.sub_of[1] : g.sub_of[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Subdomain indexing (descriptors are read through references to global
+// memory, never copied into private arrays).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ I3 local_to_global(const SubDesc &S, int r) {
   const int t0 = r % S.n0;
   const int rr = r / S.n0;
   const int t1 = rr % S.n1;
   const int t2 = rr / S.n1;
-  x[S.ax[0]] = S.lo[S.ax[0]] + t0;
-  x[S.ax[1]] = S.lo[S.ax[1]] + t1;
-  x[S.ax[2]] = S.lo[S.ax[2]] + t2;
+  const int a0 = S.ax[0], a1 = S.ax[1], a2 = S.ax[2];
+  I3 x{0, 0, 0};
+  x.set(a0, S.lo[a0] + t0);
+  x.set(a1, S.lo[a1] + t1);
+  x.set(a2, S.lo[a2] + t2);
+  return x;
 }
 
-__device__ __forceinline__ int local_row(const SubDesc &S, const int x[3]) {
-  const int t0 = x[S.ax[0]] - S.lo[S.ax[0]];
-  const int t1 = x[S.ax[1]] - S.lo[S.ax[1]];
-  const int t2 = x[S.ax[2]] - S.lo[S.ax[2]];
+__device__ __forceinline__ int local_row(const SubDesc &S, const I3 &x) {
+  const int a0 = S.ax[0], a1 = S.ax[1], a2 = S.ax[2];
+  const int t0 = x[a0] - S.lo[a0];
+  const int t1 = x[a1] - S.lo[a1];
+  const int t2 = x[a2] - S.lo[a2];
   return t0 + S.n0 * (t1 + S.n1 * t2);
 }
 
-__device__ __forceinline__ long long cell_index(const Geom &g, const int x[3]) {
-  return (long long)x[0] + (long long)g.nx * ((long long)x[1] + (long long)g.ny * x[2]);
+__device__ __forceinline__ long long cell_index(const Geom &g, const I3 &x) {
+  return (long long)x.v0 + (long long)g.nx * ((long long)x.v1 + (long long)g.ny * x.v2);
 }
 
 // Robin face rule.  Face f (-x..+z) of the cell at global coordinates x in
@@ -78,21 +131,22 @@ __device__ __forceinline__ long long cell_index(const Geom &g, const int x[3]) {
 // but inside the domain.  Then: local patch lp, Robin parameter
 // beta = alpha H_d / K_d(c), transmissibility T = A_d / (h_d / (2 K_d) + beta)
 // and sigma = +1 on a + face (lower side of the interface), -1 on a - face.
-__device__ __forceinline__ bool gamma_face(const Geom &g, const SubDesc &S, const int x[3], int f,
+__device__ __forceinline__ bool gamma_face(const Geom &g, const SubDesc &S, const I3 &x, int f,
                                            double kd, int &lp, double &T, double &beta) {
   const int d = f >> 1;
   const int side = (f & 1) ? 1 : -1;
   const int xn = x[d] + side;
-  if (xn >= S.lo[d] && xn < S.lo[d] + S.ext[d]) return false;
+  const int lo = S.lo[d], ext = S.ext[d];
+  if (xn >= lo && xn < lo + ext) return false;
   const int ifc = S.face_if[f];
   if (ifc < 0) return false;
-  const IfaceDesc I = g.ifc[ifc];
+  const IfaceDesc &I = g.ifc[ifc];
   const int ta = x[I.a] - S.lo[I.a];
   const int tb = x[I.b] - S.lo[I.b];
   lp = S.face_p0[f] + split_group(ta, I.la, I.na) + I.na * split_group(tb, I.lb, I.nb);
-  const double H = S.ext[d] * g.h[d];
-  beta = g.alpha * H / kd;
-  T = g.area[d] / (g.h[d] / (2.0 * kd) + beta);
+  const double hd = hdir(g, d);
+  beta = g.alpha * (ext * hd) / kd;
+  T = adir(g, d) / (hd / (2.0 * kd) + beta);
   return true;
 }
 

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_iface_scatter(Geom g, const int *__rest
                                                        const double *__restrict__ SAb,
                                                        double *__restrict__ AB, int w,
                                                        double *__restrict__ bint) {
-  const SubDesc S = g.sub[blockIdx.x];
+  const SubDesc &S = g.sub[blockIdx.x];
   const int n = S.npatch, m = S.m;
   const int ld = 2 * w + 1;
   const double *Fs = F + S.F_off;
@@ -48,8 +48,9 @@ __global__ __launch_bounds__(256) void k_iface_scatter(Geom g, const int *__rest
     const int li = e / n, lj = e % n;
     int fi = 0;
     for (int ff = 0; ff < 6; ++ff) {
-      if (S.face_if[ff] < 0) continue;
-      const IfaceDesc I = g.ifc[S.face_if[ff]];
+      const int ii = S.face_if[ff];
+      if (ii < 0) continue;
+      const IfaceDesc &I = g.ifc[ii];
       if (li >= S.face_p0[ff] && li < S.face_p0[ff] + I.na * I.nb) fi = ff;
     }
     const double sig = (fi & 1) ? 1.0 : -1.0;
@@ -81,6 +82,53 @@ __global__ __launch_bounds__(256) void k_iface_scatter(Geom g, const int *__rest
 // ---------------------------------------------------------------------------
 constexpr int kLU = 32;
 
+// Unrolled LU of the kLU x kLU diagonal block held one row per lane
+// (rows beyond kb and entries outside the band are zero).  Step P: the pivot
+// row P is broadcast from lane P and every lower row eliminates column P.
+template <int P>
+__device__ __forceinline__ void lu_rows_step(double (&row)[kLU], int lane, int kb, int k0,
+                                             DevStatus *st) {
+  if (P < kb) {
+    double piv = lane_bcast(row[P], P);
+    if (piv == 0.0 || !isfinite(piv)) {
+      if (lane == 0) set_status(st, -5, k0 + P, piv);
+      piv = 1.0;
+    }
+    const double l = row[P] / piv;
+    if (lane > P) row[P] = l;
+#pragma unroll
+    for (int c = P + 1; c < kLU; ++c) {
+      const double u = lane_bcast(row[c], P);
+      if (lane > P) row[c] -= l * u;
+    }
+  }
+  if constexpr (P + 1 < kLU) lu_rows_step<P + 1>(row, lane, kb, k0, st);
+}
+
+// l U11 = a for one row l (U11 upper, from LDS D).
+template <int C>
+__device__ __forceinline__ void trsm_row_upper(double (&l)[kLU], const double *D, int kb) {
+  if (C < kb) {
+    double s = l[C];
+#pragma unroll
+    for (int p = 0; p < C; ++p) s -= l[p] * D[p * (kLU + 1) + C];
+    l[C] = s / D[C * (kLU + 1) + C];
+  }
+  if constexpr (C + 1 < kLU) trsm_row_upper<C + 1>(l, D, kb);
+}
+
+// L11 u = a for one column u (L11 unit lower, from LDS D).
+template <int R>
+__device__ __forceinline__ void trsm_col_lower(double (&u)[kLU], const double *D, int kb) {
+  if (R < kb) {
+    double s = u[R];
+#pragma unroll
+    for (int p = 0; p < R; ++p) s -= D[R * (kLU + 1) + p] * u[p];
+    u[R] = s;
+  }
+  if constexpr (R + 1 < kLU) trsm_col_lower<R + 1>(u, D, kb);
+}
+
 __device__ __forceinline__ void lu_diag_block(const double *AB, int ld, int w, int k0, int kb,
                                               double *D /* [kLU][kLU+1] */, DevStatus *st) {
   const int tid = threadIdx.x;
@@ -91,23 +139,7 @@ __device__ __forceinline__ void lu_diag_block(const double *AB, int ld, int w, i
     for (int c = 0; c < kLU; ++c)
       row[c] = (lane < kb && c < kb && abs(lane - c) <= w) ? AB[(size_t)(k0 + c) * ld + (w + lane - c)]
                                                             : 0.0;
-#pragma unroll
-    for (int p = 0; p < kLU; ++p) {
-      if (p < kb) {
-        double piv = lane_bcast(row[p], p);
-        if (piv == 0.0 || !isfinite(piv)) {
-          if (lane == 0) set_status(st, -5, k0 + p, piv);
-          piv = 1.0;
-        }
-        const double l = row[p] / piv;
-        if (lane > p) row[p] = l;
-#pragma unroll
-        for (int c = p + 1; c < kLU; ++c) {
-          const double upc = lane_bcast(row[c], p);
-          if (lane > p) row[c] -= l * upc;
-        }
-      }
-    }
+    lu_rows_step<0>(row, lane, kb, k0, st);
     if (lane < kLU) {
 #pragma unroll
       for (int c = 0; c < kLU; ++c) D[lane * (kLU + 1) + c] = row[c];
@@ -116,18 +148,41 @@ __device__ __forceinline__ void lu_diag_block(const double *AB, int ld, int w, i
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_lu_panel(double *__restrict__ AB, int n, int w, int k0,
-                                                  double *__restrict__ diag,
-                                                  double *__restrict__ bint, DevStatus *st) {
-  __shared__ double D[kLU * (kLU + 1)];
+// One unit of the panel step at column k0 (role 0: diagonal block and
+// right-hand side; roles 1..nchunk: 256 rows of L21; the rest: 256 columns of
+// U12).  Every unit factors the diagonal block itself, from the unmodified
+// band, so units need no ordering among themselves.
+__device__ void lu_panel_unit(double *__restrict__ AB, int n, int w, int k0, int role,
+                              double *__restrict__ diag, double *__restrict__ bint, DevStatus *st,
+                              double *D) {
   const int ld = 2 * w + 1;
   const int kb = min(kLU, n - k0);
   const int r0 = k0 + kb;
   const int nr = max(0, min(n, k0 + kb + w) - r0);  // rows of L21 / columns of U12
   const int nchunk = (nr + 255) / 256;
-  lu_diag_block(AB, ld, w, k0, kb, D, st);
   const int tid = threadIdx.x;
-  const int role = blockIdx.x;
+  // Each workgroup loads its row / column of the panel before factoring the
+  // diagonal block, so the loads overlap the factorisation.
+  double v[kLU];
+  int idx = -1;
+  if (role >= 1 && role <= nchunk) {
+    const int i = r0 + (role - 1) * 256 + tid;
+    if (i < r0 + nr) idx = i;
+#pragma unroll
+    for (int c = 0; c < kLU; ++c) {
+      const int j = k0 + c;
+      v[c] = (idx >= 0 && c < kb && idx - j <= w) ? AB[(size_t)j * ld + (w + idx - j)] : 0.0;
+    }
+  } else if (role > nchunk) {
+    const int j = r0 + (role - 1 - nchunk) * 256 + tid;
+    if (j < r0 + nr) idx = j;
+#pragma unroll
+    for (int r = 0; r < kLU; ++r) {
+      const int i = k0 + r;
+      v[r] = (idx >= 0 && r < kb && idx - i <= w) ? AB[(size_t)idx * ld + (w + i - idx)] : 0.0;
+    }
+  }
+  lu_diag_block(AB, ld, w, k0, kb, D, st);
   if (role == 0) {
     for (int e = tid; e < kb * kb; e += blockDim.x) {
       const int r = e / kb, c = e % kb;
@@ -136,82 +191,54 @@ __global__ __launch_bounds__(256) void k_lu_panel(double *__restrict__ AB, int n
     if (tid == 0) {
       // y1 = L11^{-1} b1 (unit lower)
       for (int r = 0; r < kb; ++r) {
-        double s = bint[k0 + r];
-        for (int p = 0; p < r; ++p) s -= D[r * (kLU + 1) + p] * bint[k0 + p];
-        bint[k0 + r] = s;
+        double sum = bint[k0 + r];
+        for (int p = 0; p < r; ++p) sum -= D[r * (kLU + 1) + p] * bint[k0 + p];
+        bint[k0 + r] = sum;
       }
     }
     return;
   }
+  if (idx < 0) return;
   if (role <= nchunk) {
-    // L21 rows: l U11 = a, for row i = r0 + chunk*256 + tid
-    const int i = r0 + (role - 1) * 256 + tid;
-    if (i >= r0 + nr) return;
-    double l[kLU];
+    trsm_row_upper<0>(v, D, kb);
 #pragma unroll
     for (int c = 0; c < kLU; ++c) {
       const int j = k0 + c;
-      l[c] = (c < kb && i - j <= w) ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
+      if (c < kb && idx - j <= w) AB[(size_t)j * ld + (w + idx - j)] = v[c];
     }
-#pragma unroll
-    for (int c = 0; c < kLU; ++c) {
-      if (c < kb) {
-        double s = l[c];
-#pragma unroll
-        for (int p = 0; p < c; ++p) s -= l[p] * D[p * (kLU + 1) + c];
-        l[c] = s / D[c * (kLU + 1) + c];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < kLU; ++c) {
-      const int j = k0 + c;
-      if (c < kb && i - j <= w) AB[(size_t)j * ld + (w + i - j)] = l[c];
-    }
-    return;
-  }
-  {
-    // U12 columns: L11 u = a (unit lower), for column j = r0 + chunk*256 + tid
-    const int j = r0 + (role - 1 - nchunk) * 256 + tid;
-    if (j >= r0 + nr) return;
-    double u[kLU];
+  } else {
+    trsm_col_lower<0>(v, D, kb);
 #pragma unroll
     for (int r = 0; r < kLU; ++r) {
       const int i = k0 + r;
-      u[r] = (r < kb && j - i <= w) ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < kLU; ++r) {
-      if (r < kb) {
-        double s = u[r];
-#pragma unroll
-        for (int p = 0; p < r; ++p) s -= D[r * (kLU + 1) + p] * u[p];
-        u[r] = s;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < kLU; ++r) {
-      const int i = k0 + r;
-      if (r < kb && j - i <= w) AB[(size_t)j * ld + (w + i - j)] = u[r];
+      if (r < kb && idx - i <= w) AB[(size_t)idx * ld + (w + i - idx)] = v[r];
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_lu_panel(double *__restrict__ AB, int n, int w, int k0,
+                                                  double *__restrict__ diag,
+                                                  double *__restrict__ bint, DevStatus *st) {
+  __shared__ double D[kLU * (kLU + 1)];
+  lu_panel_unit(AB, n, w, k0, blockIdx.x, diag, bint, st, D);
 }
 
 // A22 -= L21 U12 in 64x64 tiles (four waves, each 16 rows x 64 columns).
 // Extra workgroups: one copies the factored diagonal block, the last ones
 // update the right-hand side.
-__global__ __launch_bounds__(256) void k_lu_update(double *__restrict__ AB, int n, int w, int k0,
-                                                   const double *__restrict__ diag,
-                                                   double *__restrict__ bint) {
+// One unit of the update step at column k0: units 0..nt*nt-1 are 64x64 tiles
+// of A22 -= L21 U12; unit nt*nt copies the factored diagonal block into the
+// band; the last units update the right-hand side, b2 -= L21 y1.
+__device__ void lu_update_unit(double *__restrict__ AB, int n, int w, int k0, int bid,
+                               const double *__restrict__ diag, double *__restrict__ bint,
+                               double *Ls, double *Us) {
   using M = Mma<double>;
-  __shared__ double Ls[64 * (kLU + 1)];
-  __shared__ double Us[kLU * (64 + 1)];
   const int ld = 2 * w + 1;
   const int kb = min(kLU, n - k0);
   const int r0 = k0 + kb;
   const int nr = max(0, min(n, k0 + kb + w) - r0);
   const int nt = (nr + 63) / 64;
   const int tid = threadIdx.x;
-  const int bid = blockIdx.x;
   if (bid == nt * nt) {
     for (int e = tid; e < kb * kb; e += blockDim.x) {
       const int r = e / kb, c = e % kb;
@@ -233,6 +260,19 @@ __global__ __launch_bounds__(256) void k_lu_update(double *__restrict__ AB, int 
   }
   const int ti = bid / nt, tj = bid % nt;
   const int i0 = r0 + ti * 64, j0 = r0 + tj * 64;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  // the C tile is fetched first so its latency overlaps the staging below
+  typename M::v4 cacc[4];
+#pragma unroll
+  for (int tc = 0; tc < 4; ++tc) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + wave * 16 + M::crow(v, lane), j = j0 + tc * 16 + lr;
+      const bool ok = i < r0 + nr && j < r0 + nr && (i - j <= w) && (j - i <= w);
+      cacc[tc][v] = ok ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
+    }
+  }
   // stage L21 tile (64 x kb) and U12 tile (kb x 64)
   for (int e = tid; e < 64 * kLU; e += 256) {
     const int r = e % 64, c = e / 64;
@@ -245,17 +285,9 @@ __global__ __launch_bounds__(256) void k_lu_update(double *__restrict__ AB, int 
     Us[r * 65 + c] = (r < kb && j < r0 + nr && j - i <= w) ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
   }
   __syncthreads();
-  const int lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int tc = 0; tc < 4; ++tc) {
-    typename M::v4 c;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + wave * 16 + M::crow(v, lane), j = j0 + tc * 16 + lr;
-      const bool ok = i < r0 + nr && j < r0 + nr && (i - j <= w) && (j - i <= w);
-      c[v] = ok ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
-    }
+    typename M::v4 c = cacc[tc];
 #pragma unroll
     for (int s = 0; s < kLU / 4; ++s) {
       const int kk = 4 * s + lk;
@@ -272,63 +304,163 @@ __global__ __launch_bounds__(256) void k_lu_update(double *__restrict__ AB, int 
   }
 }
 
+__global__ __launch_bounds__(256) void k_lu_update(double *__restrict__ AB, int n, int w, int k0,
+                                                   const double *__restrict__ diag,
+                                                   double *__restrict__ bint) {
+  __shared__ double Ls[64 * (kLU + 1)];
+  __shared__ double Us[kLU * (64 + 1)];
+  lu_update_unit(AB, n, w, k0, blockIdx.x, diag, bint, Ls, Us);
+}
+
 // Triangular sweeps with the band factors, one workgroup of 1024 lanes.
 // lower: L y = b (unit lower), forward.  upper: U x = y, backward.  In place.
-__global__ __launch_bounds__(1024) void k_lu_sweep(const double *__restrict__ AB, int n, int w,
-                                                   double *__restrict__ x, int upper) {
-  __shared__ double xb[kLU];
+// Per block of kSW unknowns, wave 0 solves the diagonal block (one row per
+// lane, broadcasts between lanes) while the other waves apply the block to
+// the rows it couples to (one row per lane; beyond 960 rows a slower loop).
+// The active part of x lives in an LDS ring of RW >= w + 2 kSW entries; the
+// band entries of the next block and the x entries that enter the ring next
+// are fetched one block ahead, so no global access sits on the critical path.
+constexpr int kSW = 16;
+
+template <int C>
+__device__ __forceinline__ void sweep_upper_step(const double (&u)[kSW], double &xv, int lane, int kb) {
+  constexpr int c = kSW - 1 - C;
+  if (c < kb) {
+    const double dc = lane_bcast(u[c], c);
+    const double xc = lane_bcast(xv, c) / dc;
+    if (lane == c) xv = xc;
+    if (lane < c) xv -= u[c] * xc;
+  }
+  if constexpr (C + 1 < kSW) sweep_upper_step<C + 1>(u, xv, lane, kb);
+}
+
+template <int C>
+__device__ __forceinline__ void sweep_lower_step(const double (&u)[kSW], double &xv, int lane, int kb) {
+  if (C < kb) {
+    const double xc = lane_bcast(xv, C);
+    if (lane > C) xv -= u[C] * xc;
+  }
+  if constexpr (C + 1 < kSW) sweep_lower_step<C + 1>(u, xv, lane, kb);
+}
+
+constexpr int kSweepThreads = 1024;
+
+__global__ __launch_bounds__(kSweepThreads) void k_lu_sweep(const double *__restrict__ AB, int n,
+                                                            int w, double *__restrict__ x, int upper,
+                                                            int RW) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *xr = reinterpret_cast<double *>(smem_raw);  // ring, entry i at i % RW
+  __shared__ double xb[kSW];
   const int ld = 2 * w + 1;
   const int tid = threadIdx.x;
-  const int nblk = (n + kLU - 1) / kLU;
-  for (int s = 0; s < nblk; ++s) {
+  const int nblk = (n + kSW - 1) / kSW;
+  const int nprop = kSweepThreads - 64;
+  double cur[kSW], nxt[kSW];
+  double xin_cur = 0.0, xin_nxt = 0.0;  // entering x value (threads 64..64+kSW-1)
+  // rows the block at k0 updates: [lo, hi)
+  auto prop_lo = [&](int k0, int kb) { return upper ? max(0, k0 - w) : k0 + kb; };
+  auto prop_hi = [&](int k0, int kb) { return upper ? k0 : min(n, k0 + kb + w); };
+  auto fetch = [&](int blk, double (&dst)[kSW]) {
+    const int k0 = blk * kSW;
+    const int kb = min(kSW, n - k0);
+    if (tid < 64) {
+#pragma unroll
+      for (int c = 0; c < kSW; ++c)
+        dst[c] = (tid < kb && c < kb && abs(tid - c) <= w) ? AB[(size_t)(k0 + c) * ld + (w + tid - c)] : 0.0;
+    } else {
+      const int i = prop_lo(k0, kb) + (tid - 64);
+      const bool ok = i < prop_hi(k0, kb);
+#pragma unroll
+      for (int c = 0; c < kSW; ++c) {
+        const int j = k0 + c;
+        const bool in = ok && c < kb && (upper ? (j - i <= w) : (i - j <= w));
+        dst[c] = in ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
+      }
+    }
+  };
+  // x entries that enter the ring when block blk becomes current: for the
+  // upper sweep the rows [lo(blk), lo(blk+1)), for the lower sweep the rows
+  // [hi(blk-1), hi(blk)) -- at most kSW of them.
+  auto enter_range = [&](int blk, int &a, int &b) {
+    const int k0 = blk * kSW, kb = min(kSW, n - k0);
+    if (upper) {
+      a = prop_lo(k0, kb);
+      const int k1 = (blk + 1) * kSW;
+      b = (blk + 1 < nblk) ? prop_lo(k1, min(kSW, n - k1)) : a;
+    } else {
+      const int kp = (blk - 1) * kSW;
+      a = (blk > 0) ? prop_hi(kp, kSW) : b;
+      b = prop_hi(k0, kb);
+      if (blk == 0) a = b;
+    }
+  };
+  auto fetch_x = [&](int blk) {
+    int a, b;
+    enter_range(blk, a, b);
+    const int i = a + (tid - 64);
+    return (tid >= 64 && tid < 64 + kSW && i < b) ? x[i] : 0.0;
+  };
+  auto store_x = [&](int blk, double v) {
+    int a, b;
+    enter_range(blk, a, b);
+    const int i = a + (tid - 64);
+    if (tid >= 64 && tid < 64 + kSW && i < b) xr[i % RW] = v;
+  };
+  // initial ring: the first block's own rows and the rows it updates
+  {
+    const int blk = upper ? nblk - 1 : 0;
+    const int k0 = blk * kSW, kb = min(kSW, n - k0);
+    const int a = upper ? prop_lo(k0, kb) : k0;
+    const int b = upper ? n : prop_hi(k0, kb);
+    for (int i = a + tid; i < b; i += kSweepThreads) xr[i % RW] = x[i];
+  }
+  fetch(upper ? nblk - 1 : 0, cur);
+  if (nblk > 1) xin_nxt = fetch_x(upper ? nblk - 2 : 1);
+  __syncthreads();
+  auto body = [&](int s, double (&cu)[kSW], double (&nx)[kSW]) {
     const int blk = upper ? (nblk - 1 - s) : s;
-    const int k0 = blk * kLU;
-    const int kb = min(kLU, n - k0);
+    const int k0 = blk * kSW;
+    const int kb = min(kSW, n - k0);
+    const int nb = upper ? blk - 1 : blk + 1;
+    xin_cur = xin_nxt;
+    if (s + 1 < nblk) fetch(nb, nx);
+    if (s + 2 < nblk) xin_nxt = fetch_x(upper ? blk - 2 : blk + 2);
     if (tid < 64) {
       const int lane = tid;
-      double xv = (lane < kb) ? x[k0 + lane] : 0.0;
-      if (upper) {
-        for (int c = kb - 1; c >= 0; --c) {
-          const double dc = AB[(size_t)(k0 + c) * ld + w];
-          double xc = lane_bcast(xv, c) / dc;
-          if (lane == c) xv = xc;
-          if (lane < c && c - lane <= w) xv -= AB[(size_t)(k0 + c) * ld + (w + lane - c)] * xc;
-        }
-      } else {
-        for (int c = 0; c < kb; ++c) {
-          const double xc = lane_bcast(xv, c);
-          if (lane > c && lane < kb && lane - c <= w) xv -= AB[(size_t)(k0 + c) * ld + (w + lane - c)] * xc;
-        }
-      }
+      double xv = (lane < kb) ? xr[(k0 + lane) % RW] : 0.0;
+      if (upper) sweep_upper_step<0>(cu, xv, lane, kb);
+      else sweep_lower_step<0>(cu, xv, lane, kb);
       if (lane < kb) {
         xb[lane] = xv;
         x[k0 + lane] = xv;
       }
     }
     __syncthreads();
-    // propagate the block to the rows it couples to
-    if (upper) {
-      const int ilo = max(0, k0 - w);
-      for (int i = ilo + tid; i < k0; i += blockDim.x) {
+    if (tid >= 64) {
+      const int ilo = prop_lo(k0, kb), ihi = prop_hi(k0, kb);
+      const int i0 = ilo + (tid - 64);
+      if (i0 < ihi) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < kSW; ++c) acc += cu[c] * xb[c];
+        xr[i0 % RW] -= acc;
+      }
+      for (int i = i0 + nprop; i < ihi; i += nprop) {
         double acc = 0.0;
         for (int c = 0; c < kb; ++c) {
           const int j = k0 + c;
-          if (j - i <= w) acc += AB[(size_t)j * ld + (w + i - j)] * xb[c];
+          if (upper ? (j - i <= w) : (i - j <= w)) acc += AB[(size_t)j * ld + (w + i - j)] * xb[c];
         }
-        x[i] -= acc;
+        xr[i % RW] -= acc;
       }
-    } else {
-      const int ihi = min(n, k0 + kb + w);
-      for (int i = k0 + kb + tid; i < ihi; i += blockDim.x) {
-        double acc = 0.0;
-        for (int c = 0; c < kb; ++c) {
-          const int j = k0 + c;
-          if (i - j <= w) acc += AB[(size_t)j * ld + (w + i - j)] * xb[c];
-        }
-        x[i] -= acc;
-      }
+      // rows that the next block needs and no earlier block touched
+      if (s + 1 < nblk) store_x(nb, xin_cur);
     }
     __syncthreads();
+  };
+  for (int s = 0; s < nblk; s += 2) {
+    body(s, cur, nxt);
+    if (s + 1 < nblk) body(s + 1, nxt, cur);
   }
 }
 
@@ -390,7 +522,7 @@ __global__ __launch_bounds__(256) void k_recon_p(Geom g, const int *__restrict__
                                                  const double *__restrict__ pi, int nv,
                                                  double *__restrict__ p) {
   __shared__ double cw[kMaxRhs];
-  const SubDesc S = g.sub[blockIdx.x];
+  const SubDesc &S = g.sub[blockIdx.x];
   const int m = S.m, n = S.npatch;
   for (int c = threadIdx.x; c < m; c += blockDim.x) {
     double v = 1.0;
@@ -404,9 +536,7 @@ __global__ __launch_bounds__(256) void k_recon_p(Geom g, const int *__restrict__
     const double *row = X + (size_t)r * m;
     double s = 0.0;
     for (int c = 0; c < m; ++c) s += row[c] * cw[c];
-    int x[3];
-    local_to_global(S, r, x);
-    p[cell_index(g, x)] = s;
+    p[cell_index(g, local_to_global(S, r))] = s;
   }
 }
 
@@ -418,41 +548,43 @@ __global__ void k_recon_u(Geom g, const double *__restrict__ p, const double *__
   const long long N = (long long)g.nx * g.ny * g.nz;
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
-  int x[3];
-  x[0] = (int)(c % g.nx);
-  x[1] = (int)((c / g.nx) % g.ny);
-  x[2] = (int)(c / ((long long)g.nx * g.ny));
-  const int s[3] = {g.sub_of[0][x[0]], g.sub_of[1][x[1]], g.sub_of[2][x[2]]};
-  const int l = s[0] + g.nd[0] * (s[1] + g.nd[1] * s[2]);
-  const SubDesc S = g.sub[l];
-  const int n[3] = {g.nx, g.ny, g.nz};
+  I3 x;
+  x.v0 = (int)(c % g.nx);
+  x.v1 = (int)((c / g.nx) % g.ny);
+  x.v2 = (int)(c / ((long long)g.nx * g.ny));
+  const int l = g.sub_of[0][x.v0] + g.nd[0] * (g.sub_of[1][x.v1] + g.nd[1] * g.sub_of[2][x.v2]);
+  const SubDesc &S = g.sub[l];
   const double pc = p[c];
+#pragma unroll
   for (int f = 0; f < 6; ++f) {
     const int d = f >> 1;
     const int side = (f & 1) ? 1 : -1;
-    const double kd = g.k[d][c];
+    const double *karr = kdir(g, d);
+    const double kd = karr[c];
+    const double hd = hdir(g, d);
     const int xn = x[d] + side;
     double u = 0.0;
     if (xn >= S.lo[d] && xn < S.lo[d] + S.ext[d]) {
-      int y[3] = {x[0], x[1], x[2]};
-      y[d] = xn;
+      I3 y = x;
+      y.set(d, xn);
       const long long cn = cell_index(g, y);
-      const double kn = g.k[d][cn];
-      u = (2.0 * kd * kn / (kd + kn)) * (pc - p[cn]) / g.h[d];
-    } else if (xn >= 0 && xn < n[d]) {
+      const double kn = karr[cn];
+      u = (2.0 * kd * kn / (kd + kn)) * (pc - p[cn]) / hd;
+    } else if (xn >= 0 && xn < ndir(g, d)) {
       int lp;
       double T, beta;
       gamma_face(g, S, x, f, kd, lp, T, beta);
       const int patch = g.ifc[S.face_if[f]].p0 + (lp - S.face_p0[f]);
       const double G = pi[patch] - side * beta * pi[nv + patch];
-      u = T * (pc - G) / g.area[d];
+      u = T * (pc - G) / adir(g, d);
     } else {
-      const int wt = g.wall_type[f];
+      const int wt = wall_type_of(g, f);
       if (wt != 0) {
         const int a = (d == 0) ? 1 : 0;
         const int b = (d == 2) ? 1 : 2;
-        const double gv = g.wall_value[f] ? g.wall_value[f][x[a] + (long long)n[a] * x[b]] : 0.0;
-        u = (wt == 1) ? 2.0 * kd / g.h[d] * (pc - gv) : gv;
+        const double *wv = wall_value_of(g, f);
+        const double gv = wv ? wv[x[a] + (long long)ndir(g, a) * x[b]] : 0.0;
+        u = (wt == 1) ? 2.0 * kd / hd * (pc - gv) : gv;
       }
     }
     U[(long long)f * N + c] = u;
@@ -494,11 +626,11 @@ hipError_t launch_iface_scatter(const Geom &g, int n_sub, const int *patches, co
 hipError_t launch_band_lu(double *AB, int n, int w, double *diag, double *b, DevStatus *st,
                           hipStream_t s) {
   for (int k0 = 0; k0 < n; k0 += kLU) {
-    const int kb = (n - k0 < kLU) ? n - k0 : kLU;
+    const int kb = std::min(kLU, n - k0);
     const int nr = std::max(0, std::min(n, k0 + kb + w) - (k0 + kb));
     const int nchunk = (nr + 255) / 256;
-    hipLaunchKernelGGL(k_lu_panel, dim3(1 + 2 * nchunk), dim3(256), 0, s, AB, n, w, k0, diag, b, st);
     const int nt = (nr + 63) / 64;
+    hipLaunchKernelGGL(k_lu_panel, dim3(1 + 2 * nchunk), dim3(256), 0, s, AB, n, w, k0, diag, b, st);
     hipLaunchKernelGGL(k_lu_update, dim3(nt * nt + 1 + nchunk), dim3(256), 0, s, AB, n, w, k0, diag,
                        b);
   }
@@ -506,7 +638,13 @@ hipError_t launch_band_lu(double *AB, int n, int w, double *diag, double *b, Dev
 }
 
 hipError_t launch_lu_sweep(const double *AB, int n, int w, double *x, int upper, hipStream_t s) {
-  hipLaunchKernelGGL(k_lu_sweep, dim3(1), dim3(1024), 0, s, AB, n, w, x, upper);
+  const int RW = w + 2 * kSW + 1;
+  const size_t lds = (size_t)RW * sizeof(double);
+  if (lds > 150 * 1024) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void *)k_lu_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lu_sweep, dim3(1), dim3(kSweepThreads), lds, s, AB, n, w, x, upper, RW);
   return hipGetLastError();
 }
 

@@ -13,8 +13,8 @@ namespace mrcm {
 // Panel width of the local band Cholesky and of the band solves.
 constexpr int kNB = 16;
 // Largest local bandwidth the factor kernels accept, per precision: the LDS
-// window of the factor holds (b + kNB) columns of (b + 1) entries.
-constexpr int kMaxBand64 = 128;
+// window of the factor holds (b + kNB) columns of 16*ceil(b/16) + 17 entries.
+constexpr int kMaxBand64 = 112;
 constexpr int kMaxBand32 = 176;
 // Largest number of right-hand sides of one subdomain (2|I^l| + 1).
 constexpr int kMaxRhs = 128;

@@ -35,83 +35,138 @@ __global__ void k_check_perm(const double *kx, const double *ky, const double *k
 // ---------------------------------------------------------------------------
 __global__ void k_coef(Geom g, double *__restrict__ coef, double *__restrict__ r0,
                        double *__restrict__ scal) {
-  const SubDesc S = g.sub[blockIdx.y];
+  const SubDesc &S = g.sub[blockIdx.y];
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= S.N) return;
-  int x[3];
-  local_to_global(S, r, x);
+  const I3 x = local_to_global(S, r);
   const long long c = cell_index(g, x);
-  const double kc[3] = {g.k[0][c], g.k[1][c], g.k[2][c]};
-  int pos[3];
-  pos[S.ax[0]] = 0;
-  pos[S.ax[1]] = 1;
-  pos[S.ax[2]] = 2;
-  const int n[3] = {g.nx, g.ny, g.nz};
+  const double kc0 = g.k[0][c], kc1 = g.k[1][c], kc2 = g.k[2][c];
+  const int a0 = S.ax[0], a1 = S.ax[1];
   double diag = 0.0, rhs = g.q[c];
-  double toff[3] = {0.0, 0.0, 0.0};
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll
   for (int f = 0; f < 6; ++f) {
     const int d = f >> 1;
     const int side = (f & 1) ? 1 : -1;
+    const double kd = d == 0 ? kc0 : (d == 1 ? kc1 : kc2);
     const int xn = x[d] + side;
-    if (xn >= S.lo[d] && xn < S.lo[d] + S.ext[d]) {
-      int y[3] = {x[0], x[1], x[2]};
-      y[d] = xn;
+    const int lo = S.lo[d], ext = S.ext[d];
+    const double hd = hdir(g, d), ad = adir(g, d);
+    if (xn >= lo && xn < lo + ext) {
+      I3 y = x;
+      y.set(d, xn);
       const long long cn = cell_index(g, y);
-      const double kn = g.k[d][cn];
-      const double T = g.area[d] * (2.0 * kc[d] * kn / (kc[d] + kn)) / g.h[d];
+      const double kn = kdir(g, d)[cn];
+      const double T = ad * (2.0 * kd * kn / (kd + kn)) / hd;
       diag += T;
-      if (side > 0) toff[pos[d]] = (cn == g.pin) ? 0.0 : T;
-    } else if (xn >= 0 && xn < n[d]) {
-      const double beta = g.alpha * (S.ext[d] * g.h[d]) / kc[d];
-      diag += g.area[d] / (g.h[d] / (2.0 * kc[d]) + beta);
+      if (side > 0) {
+        const double tv = (cn == g.pin) ? 0.0 : T;
+        const int p = (d == a0) ? 0 : ((d == a1) ? 1 : 2);
+        t0 = (p == 0) ? tv : t0;
+        t1 = (p == 1) ? tv : t1;
+        t2 = (p == 2) ? tv : t2;
+      }
+    } else if (xn >= 0 && xn < ndir(g, d)) {
+      const double beta = g.alpha * (ext * hd) / kd;
+      diag += ad / (hd / (2.0 * kd) + beta);
     } else {
-      const int wt = g.wall_type[f];
+      const int wt = wall_type_of(g, f);
       if (wt != 0) {
         const int a = (d == 0) ? 1 : 0;
         const int b = (d == 2) ? 1 : 2;
-        const double gv = g.wall_value[f] ? g.wall_value[f][x[a] + (long long)n[a] * x[b]] : 0.0;
+        const double *wv = wall_value_of(g, f);
+        const double gv = wv ? wv[x[a] + (long long)ndir(g, a) * x[b]] : 0.0;
         if (wt == 1) {
-          const double T = g.area[d] * 2.0 * kc[d] / g.h[d];
+          const double T = ad * 2.0 * kd / hd;
           diag += T;
           rhs += T * gv;
         } else {
-          rhs -= g.area[d] * gv;
+          rhs -= ad * gv;
         }
       }
     }
   }
   if (c == g.pin) {
     diag = 1.0;
-    toff[0] = toff[1] = toff[2] = 0.0;
+    t0 = t1 = t2 = 0.0;
     rhs = 0.0;
   }
   const long long o = S.cell_off + r;
   coef[4 * o + 0] = diag;
-  coef[4 * o + 1] = toff[0];
-  coef[4 * o + 2] = toff[1];
-  coef[4 * o + 3] = toff[2];
+  coef[4 * o + 1] = t0;
+  coef[4 * o + 2] = t1;
+  coef[4 * o + 3] = t2;
   r0[o] = rhs;
   scal[o] = 1.0 / sqrt(diag);
+}
+
+// ---------------------------------------------------------------------------
+// Right-hand sides of one local row: column 0 the particular problem, column
+// 1+j the P-type MBF of local patch j (G = 1 on the patch), column 1+n+j the
+// U-type MBF (G = -sigma beta_f); entry = T_f G_f per Robin face.  Calls
+// emit(col, value) for each Robin entry of the row; the pinned row is zero.
+// ---------------------------------------------------------------------------
+template <typename F>
+__device__ __forceinline__ void rhs_row_faces(const Geom &g, const SubDesc &S, int r, F emit) {
+  if (r == S.pin_local) return;
+  const I3 x = local_to_global(S, r);
+  const long long c = cell_index(g, x);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1;
+    const int sigma = (f & 1) ? 1 : -1;
+    const int xn = x[d] + sigma;
+    if (xn >= S.lo[d] && xn < S.lo[d] + S.ext[d]) continue;
+    int lp;
+    double T, beta;
+    if (gamma_face(g, S, x, f, kdir(g, d)[c], lp, T, beta)) {
+      emit(1 + lp, T);
+      emit(1 + S.npatch + lp, -sigma * beta * T);
+    }
+  }
+}
+
+// Dense right-hand sides R (row-major, N_l x m_l) of every subdomain, one
+// thread per entry.
+__global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ r0,
+                                             double *__restrict__ B) {
+  const SubDesc &S = g.sub[blockIdx.y];
+  const int m = S.m;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)S.N * m) return;
+  const int r = (int)(e / m), c = (int)(e % m);
+  double v = 0.0;
+  if (c == 0) {
+    v = r0[S.cell_off + r];
+  } else {
+    rhs_row_faces(g, S, r, [&](int col, double val) {
+      if (col == c) v = val;
+    });
+  }
+  B[S.X_off + e] = v;
 }
 
 // ---------------------------------------------------------------------------
 // Band Cholesky.  The active part of the band -- the current panel of kNB
 // columns and the b columns it updates -- lives in LDS as a ring of
 // W = b + kNB column slots, each holding the b+1 entries L[j..j+b][j].
-// Columns are assembled straight from the coefficients when they enter the
-// ring, so A^H_l never exists in global memory.
-//   panel:    wave 0 keeps the panel's rows in registers (row k+lane+64q in
-//             lane `lane`), factors it with lane broadcasts instead of
-//             workgroup barriers, and forms the inverse of the 16x16
-//             diagonal block.
-//   update:   all four waves subtract L21 L21^T from the b x b lower
-//             triangle that follows the panel, in 16x16 MFMA tiles.
+// Columns are assembled from the coefficients when they enter the ring, so
+// A^H_l never exists in global memory.  Per panel k (already factored):
+//   A  all waves update the next panel's 16 columns (tiles with tp = 0);
+//      threads 0..63 fetch the coefficients of the columns that enter next;
+//   B  wave 0 factors the next panel -- rows in registers, lane broadcasts
+//      instead of barriers, plus the inverse of its 16x16 diagonal block --
+//      while waves 1..3 finish the b x b trailing update (MFMA tiles);
+//   C  the incoming columns replace the retired panel in the ring.
 // The factor is written by column, (b+1) entries per column; the inverses of
 // its 16x16 diagonal blocks (what the solves use) go to a separate array.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrap(int s, int W) { return s >= W ? s - W : s; }
+
 template <typename T, int RPL>
 __device__ __forceinline__ void factor_panel(T *S, T *L, T *Dinv, int ldb, int k, int kb, int N, int b,
                                              int W, int lane, DevStatus *st, int sub) {
+  const int sk = k % W;
   T v[RPL][kNB];
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
@@ -119,7 +174,7 @@ __device__ __forceinline__ void factor_panel(T *S, T *L, T *Dinv, int ldb, int k
 #pragma unroll
     for (int jj = 0; jj < kNB; ++jj) {
       const int t = ri - jj;
-      v[q][jj] = (jj < kb && t >= 0 && t <= b && k + ri < N) ? S[((k + jj) % W) * ldb + t] : T(0);
+      v[q][jj] = (jj < kb && t >= 0 && t <= b && k + ri < N) ? S[wrap(sk + jj, W) * ldb + t] : T(0);
     }
   }
 #pragma unroll
@@ -184,45 +239,45 @@ __device__ __forceinline__ void factor_panel(T *S, T *L, T *Dinv, int ldb, int k
       if (jj < kb && t >= 0 && t <= b) {
         const T val = (k + ri < N) ? v[q][jj] : T(0);
         L[(size_t)(k + jj) * (b + 1) + t] = val;
-        if (ri >= kb) S[((k + jj) % W) * ldb + t] = val;
+        if (ri >= kb) S[wrap(sk + jj, W) * ldb + t] = val;
       }
     }
   }
 }
 
+// One 16x16 tile (ti, tp) of the trailing update C -= L21 L21^T after panel k
+// (rows / columns counted from k + kNB).  Each ring column is padded with
+// zeros beyond offset b up to 16*(nT+1), so operand reads outside the band or
+// below the matrix need no test; colA[s] is the slot offset of panel column
+// k + 4s + lane/16.  Only the strictly upper half of diagonal tiles and tile
+// columns past the band are masked.
 template <typename T>
-__device__ __forceinline__ void factor_update(T *S, int ldb, int k, int kb, int N, int b, int W,
-                                              int lane, int wave) {
+__device__ __forceinline__ void factor_tile(T *S, int ldb, int b, int W, int sk, int lane, int ti,
+                                            int tp, const int (&colA)[4]) {
   using M = Mma<T>;
-  const int nT = (b + 15) >> 4;
   const int lr = lane & 15, lk = lane >> 4;
-  const int base = k + kb;
-  int tile = 0;
-  for (int ti = 0; ti < nT; ++ti) {
-    for (int tp = 0; tp <= ti; ++tp, ++tile) {
-      if ((tile & 3) != wave) continue;
-      typename M::v4 c;
+  const int pp = tp * 16 + lr;
+  const int cs = wrap(sk + kNB + pp, W) * ldb - pp;
+  const bool colok = pp < b;
+  const bool diag = ti == tp;
+  typename M::v4 c;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int ii = ti * 16 + M::crow(v, lane), pp = tp * 16 + lr;
-        const bool ok = ii >= pp && ii < b && base + ii < N;
-        c[v] = ok ? S[((base + pp) % W) * ldb + (ii - pp)] : T(0);
-      }
+  for (int v = 0; v < 4; ++v) {
+    const int ii = ti * 16 + M::crow(v, lane);
+    c[v] = (colok && (!diag || ii >= pp)) ? S[cs + ii] : T(0);
+  }
+  const int ia = kNB + ti * 16 + lr, ib = kNB + pp;
 #pragma unroll
-      for (int s = 0; s < kNB / 4; ++s) {
-        const int jj = 4 * s + lk;
-        const int ia = ti * 16 + lr, ib = tp * 16 + lr;
-        const int ta = kb + ia - jj, tb = kb + ib - jj;
-        const T a = (jj < kb && ta <= b && base + ia < N) ? S[((k + jj) % W) * ldb + ta] : T(0);
-        const T bb = (jj < kb && tb <= b && base + ib < N) ? S[((k + jj) % W) * ldb + tb] : T(0);
-        c = M::mma(-a, bb, c);
-      }
+  for (int s = 0; s < kNB / 4; ++s) {
+    const int jj = 4 * s + lk;
+    const T a = S[colA[s] + ia - jj];
+    const T bb = S[colA[s] + ib - jj];
+    c = M::mma(-a, bb, c);
+  }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int ii = ti * 16 + M::crow(v, lane), pp = tp * 16 + lr;
-        if (ii >= pp && ii < b && base + ii < N) S[((base + pp) % W) * ldb + (ii - pp)] = c[v];
-      }
-    }
+  for (int v = 0; v < 4; ++v) {
+    const int ii = ti * 16 + M::crow(v, lane);
+    if (colok && (!diag || ii >= pp)) S[cs + ii] = c[v];
   }
 }
 
@@ -236,18 +291,25 @@ __global__ __launch_bounds__(256) void k_factor(const SubDesc *__restrict__ subs
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *S = reinterpret_cast<T *>(smem_raw);
   const int sub = order[blockIdx.x];
-  const SubDesc D = subs[sub];
+  const SubDesc &D = subs[sub];
   const int N = D.N, b = D.b, n0 = D.n0, W = b + kNB, bp1 = b + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double *cf = coef + 4 * D.cell_off;
   const double *sc = scal + D.cell_off;
   T *L = Lg + D.L_off;
   T *Dinv = Dg + D.D_off;
+  const int nT = (b + 15) >> 4;
+  // band offsets of the four coefficient kinds: diagonal, +ax0, +ax1, +ax2
+  const int pos[4] = {0, 1, n0, b};
 
-  auto load_cols = [&](int j0, int j1) {
-    const int cnt = (j1 - j0) * bp1;
-    for (int e = tid; e < cnt; e += 256) {
-      const int j = j0 + e / bp1, t = e % bp1;
+  // the whole window starts at zero: padding beyond offset b stays zero
+  for (int e = tid; e < W * ldb; e += 256) S[e] = T(0);
+  __syncthreads();
+  // prologue: the first W columns
+  {
+    const int ncol = min(N, W);
+    for (int e = tid; e < ncol * bp1; e += 256) {
+      const int j = e / bp1, t = e % bp1;
       double v = 0.0;
       if (j + t < N) {
         if (t == 0) v += cf[4 * j];
@@ -256,160 +318,222 @@ __global__ __launch_bounds__(256) void k_factor(const SubDesc *__restrict__ subs
         if (t == b) v -= cf[4 * j + 3];
         if (scaled && v != 0.0) v *= sc[j] * sc[j + t];
       }
-      S[(j % W) * ldb + t] = T(v);
+      S[j * ldb + t] = T(v);
     }
-  };
-
-  load_cols(0, min(N, W));
+  }
   __syncthreads();
+  if (wave == 0) factor_panel<T, RPL>(S, L, Dinv, ldb, 0, min(kNB, N), N, b, W, lane, st, sub);
+  __syncthreads();
+
   for (int k = 0; k < N; k += kNB) {
-    const int kb = min(kNB, N - k);
-    if (wave == 0) factor_panel<T, RPL>(S, L, Dinv, ldb, k, kb, N, b, W, lane, st, sub);
-    __syncthreads();
-    if (k + kb < N) factor_update<T>(S, ldb, k, kb, N, b, W, lane, wave);
-    __syncthreads();
-    const int j0 = k + W;
-    if (j0 < N) load_cols(j0, min(N, j0 + kb));
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Right-hand sides of one local row (mode 0): column 0 the particular problem,
-// column 1+j the P-type MBF of local patch j (G = 1 on the patch), column
-// 1+n+j the U-type MBF (G = -sigma beta_f); entry = T_f G_f per Robin face.
-// Calls emit(col, value) for each nonzero of the row; the pinned row is zero.
-// ---------------------------------------------------------------------------
-template <typename F>
-__device__ __forceinline__ void rhs_row_faces(const Geom &g, const SubDesc &S, int r, F emit) {
-  if (r == S.pin_local) return;
-  int x[3];
-  local_to_global(S, r, x);
-  const long long c = cell_index(g, x);
-  for (int f = 0; f < 6; ++f) {
-    const int d = f >> 1;
-    const int sigma = (f & 1) ? 1 : -1;
-    int lp;
-    double T, beta;
-    if (gamma_face(g, S, x, f, g.k[d][c], lp, T, beta)) {
-      emit(1 + lp, T);
-      emit(1 + S.npatch + lp, -sigma * beta * T);
+    const bool more = k + kNB < N;
+    // -- A: next panel's columns, and fetch the entering columns' coefficients
+    double cval = 0.0;
+    int cslot = -1;
+    if (tid < 64) {
+      const int jj = tid >> 2, kind = tid & 3;
+      const int j = k + W + jj;
+      const int t = pos[kind];
+      bool first = true;
+      for (int q = 0; q < kind; ++q) first = first && (pos[q] != t);
+      if (j < N && j + t < N && first) {
+        double v = 0.0;
+        if (t == 0) v += cf[4 * j];
+        if (t == 1) v -= cf[4 * j + 1];
+        if (t == n0) v -= cf[4 * j + 2];
+        if (t == b) v -= cf[4 * j + 3];
+        if (scaled && v != 0.0) v *= sc[j] * sc[j + t];
+        cval = v;
+        cslot = t;
+      }
     }
+    const int sk = k % W;
+    int colA[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) colA[q] = wrap(sk + 4 * q + (lane >> 4), W) * ldb;
+    if (more) {
+      for (int ti = wave; ti < nT; ti += 4) factor_tile<T>(S, ldb, b, W, sk, lane, ti, 0, colA);
+    }
+    __syncthreads();
+    // -- C: the entering columns take the retired panel's slots.  With a
+    // single tile column (b <= 16) the whole update happened in A, and the
+    // next panel reaches past the ring, so C comes before B.
+    auto enter = [&]() {
+      const int j0 = k + W;
+      if (j0 < N) {
+        const int ncol = min(kNB, N - j0);
+        for (int e = tid; e < ncol * bp1; e += 256) {
+          const int jj = e / bp1, t = e % bp1;
+          if (t != 0 && t != 1 && t != n0 && t != b) S[wrap(sk + jj, W) * ldb + t] = T(0);
+        }
+        if (cslot >= 0) S[wrap(sk + (tid >> 2), W) * ldb + cslot] = T(cval);
+        // entries beyond the matrix (j + t >= N) at the special offsets
+        if (tid < 64) {
+          const int jj = tid >> 2, kind = tid & 3, t = pos[kind];
+          if (jj < ncol && j0 + jj + t >= N) S[wrap(sk + jj, W) * ldb + t] = T(0);
+        }
+      }
+      __syncthreads();
+    };
+    const bool early = nT == 1;
+    if (early) enter();
+    // -- B: factor the next panel on wave 0, finish the trailing update on waves 1..3
+    if (wave == 0) {
+      if (more) factor_panel<T, RPL>(S, L, Dinv, ldb, k + kNB, min(kNB, N - k - kNB), N, b, W, lane, st, sub);
+    } else if (more) {
+      int tile = 0;
+      for (int ti = 1; ti < nT; ++ti) {
+        for (int tp = 1; tp <= ti; ++tp, ++tile) {
+          if (tile % 3 == wave - 1) factor_tile<T>(S, ldb, b, W, sk, lane, ti, tp, colA);
+        }
+      }
+    }
+    __syncthreads();
+    if (!early) enter();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Multi-right-hand-side band solve with the stored factor.
-//   mode 0: right-hand sides built on the fly; X = s.(L L^T)^{-1}(s.R).
-//   mode 1: right-hand sides read from Rbuf (an FP64 residual);
-//           X += s.(L L^T)^{-1}(s.Rbuf).  Rbuf is overwritten.
-// s is 1/sqrt(diag) when `scaled` (the FP32 factor is of the Jacobi-scaled
-// matrix) and 1 otherwise.  Forward sweep: a ring of W = b + kNB rows of the
-// m (padded to MP) columns in LDS; per panel Y1 = inv(L11) R1 and
-// R2 -= L21 Y1 as MFMA tiles.  Backward sweep: X1 = inv(L11)^T (Y1 - L21^T X2).
+// Multi-right-hand-side band solve with the stored factor, for one column
+// chunk [c0, c1) of one subdomain per workgroup.
+//   mode 0: B holds R; on exit B holds X = s.(L L^T)^{-1}(s.R)     (in place)
+//   mode 1: B holds a residual; Xout += s.(L L^T)^{-1}(s.B), B is clobbered.
+// s is 1/sqrt(diag) when `scaled` (the factor is of the Jacobi-scaled matrix
+// D^-1/2 A D^-1/2, which keeps the 16x16 diagonal blocks -- applied through
+// their explicit inverses -- well scaled under strong permeability contrast)
+// and 1 otherwise.  Forward sweep per panel: Y1 = inv(L11) R1 and
+// R2 -= L21 Y1 over a ring of W = b + kNB rows in LDS; backward sweep:
+// X1 = inv(L11)^T (Y1 - L21^T X2).  The next panel of L, its inverse diagonal
+// block and the next rows of B are fetched into registers while the current
+// panel computes, so each panel costs two workgroup barriers.
 // ---------------------------------------------------------------------------
+constexpr int kLReg = 12;   // L entries per thread and panel: 16*(b+1) <= 256*kLReg
+constexpr int kMaxChunk = 48;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_solve(Geom g, const int *__restrict__ order,
-                                               const double *__restrict__ r0,
+__global__ __launch_bounds__(256) void k_solve(Geom g, const int4 *__restrict__ work,
                                                const double *__restrict__ scal,
                                                const T *__restrict__ Lg, const T *__restrict__ Dg,
-                                               double *__restrict__ Xg,
-                                               double *__restrict__ Rbuf, int mode, int scaled,
-                                               int ldb, int wmax, int mpmax) {
+                                               double *Bg, double *Xg,
+                                               int mode, int scaled, int ldb, int wmax) {
   using M = Mma<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const SubDesc D = g.sub[order[blockIdx.x]];
+  const int4 item = work[blockIdx.x];
+  if (item.x < 0) return;
+  const SubDesc &D = g.sub[item.x];
+  const int c0 = item.y, cw = item.z - item.y;
   const int N = D.N, b = D.b, m = D.m, W = b + kNB, bp1 = b + 1;
-  const int MP = (m + 15) & ~15;
-  const int nct = MP >> 4;
+  const int CP = (cw + 15) & ~15;
+  const int nct = CP >> 4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  T *Lp = reinterpret_cast<T *>(smem_raw);  // [kNB][ldb]
-  T *Dp = Lp + kNB * ldb;                    // [kNB][kNB] inverse of the diagonal block
-  T *Y = Dp + kNB * kNB;                     // [wmax][mpmax] ring (stride MP)
-  T *Zs = Y + (size_t)wmax * mpmax;          // [16][mpmax]
+  T *Lp = reinterpret_cast<T *>(smem_raw);     // [2][kNB][ldb], zero beyond offset b
+  T *Dp = Lp + 2 * kNB * ldb;                   // [2][kNB*kNB]
+  T *Y = Dp + 2 * kNB * kNB;                    // ring [wmax][kMaxChunk] (stride CP)
+  T *Zs = Y + (size_t)wmax * kMaxChunk;         // [16][kMaxChunk]
   const T *L = Lg + D.L_off;
   const T *Dinv = Dg + D.D_off;
-  double *X = Xg + D.X_off;
-  double *Rb = Rbuf ? Rbuf + D.X_off : nullptr;
-  double *Ybuf = (mode == 0) ? X : Rb;
+  double *B = Bg + D.X_off;
+  double *Xo = Xg + D.X_off;
   const double *sc = scal + D.cell_off;
+  const int nP = (N + kNB - 1) / kNB;
+  const int lcnt = kNB * bp1;
 
-  auto slot = [&](int r) { return (r % W) * MP; };
-
-  auto build_rows = [&](int ra, int rb) {
-    const int cnt = (rb - ra) * MP;
-    for (int e = tid; e < cnt; e += 256) Y[slot(ra + e / MP) + e % MP] = T(0);
-    __syncthreads();
-    if (mode == 0) {
-      for (int e = tid; e < (rb - ra) * 2; e += 256) {
-        const int r = ra + (e >> 1);
-        if (r >= N) continue;
-        const double s = scaled ? sc[r] : 1.0;
-        T *row = Y + slot(r);
-        if ((e & 1) == 0) {
-          row[0] = T(s * r0[D.cell_off + r]);
-        } else {
-          rhs_row_faces(g, D, r, [&](int col, double v) { row[col] = T(s * v); });
-        }
-      }
-    } else {
-      const int cnt2 = (rb - ra) * m;
-      for (int e = tid; e < cnt2; e += 256) {
-        const int r = ra + e / m, c = e % m;
-        if (r >= N) continue;
-        const double s = scaled ? sc[r] : 1.0;
-        Y[slot(r) + c] = T(s * Rb[(size_t)r * m + c]);
-      }
+  T lreg[kLReg];
+  T dreg;
+  auto fetch_panel = [&](int p) {
+    const size_t base = (size_t)p * kNB * bp1;
+    const int ncol = min(kNB, N - p * kNB);
+#pragma unroll
+    for (int i = 0; i < kLReg; ++i) {
+      const int e = tid + 256 * i;
+      lreg[i] = (e < lcnt && e / bp1 < ncol) ? L[base + e] : T(0);
     }
-    __syncthreads();
+    dreg = Dinv[(size_t)p * kNB * kNB + tid];
+  };
+  auto store_panel = [&](int buf) {
+    T *lp = Lp + buf * kNB * ldb;
+#pragma unroll
+    for (int i = 0; i < kLReg; ++i) {
+      const int e = tid + 256 * i;
+      if (e < lcnt) lp[(e / bp1) * ldb + e % bp1] = lreg[i];
+    }
+    Dp[buf * kNB * kNB + tid] = dreg;
+  };
+  // rows of B (scaled) for the forward sweep: 16 rows x CP columns, 3 per thread
+  constexpr int kRReg = (kNB * kMaxChunk) / 256;
+  T rreg[kRReg];
+  auto fetch_rows = [&](int r0) {
+#pragma unroll
+    for (int i = 0; i < kRReg; ++i) {
+      const int e = tid + 256 * i;
+      const int rr = r0 + e / CP, c = e % CP;
+      T v = T(0);
+      if (e < kNB * CP && rr < N && c < cw) {
+        const double s = scaled ? sc[rr] : 1.0;
+        v = T(s * B[(size_t)rr * m + c0 + c]);
+      }
+      rreg[i] = v;
+    }
+  };
+  auto store_rows = [&](int r0, int sk0) {
+#pragma unroll
+    for (int i = 0; i < kRReg; ++i) {
+      const int e = tid + 256 * i;
+      if (e < kNB * CP) Y[wrap(sk0 + e / CP, W) * CP + e % CP] = rreg[i];
+    }
   };
 
-  auto load_panel = [&](int k, int kb) {
-    for (int e = tid; e < kNB * bp1; e += 256) {
-      const int jj = e / bp1, t = e % bp1;
-      Lp[jj * ldb + t] = (jj < kb) ? L[(size_t)(k + jj) * bp1 + t] : T(0);
-    }
-    Dp[tid] = Dinv[(size_t)(k / kNB) * (kNB * kNB) + tid];
-  };
-
+  // panel buffers start at zero: their padding beyond offset b stays zero
+  for (int e = tid; e < 2 * kNB * ldb; e += 256) Lp[e] = T(0);
+  __syncthreads();
   // ------------------------------ forward ------------------------------
-  build_rows(0, min(N, W));
-  for (int k = 0; k < N; k += kNB) {
+  {
+    const int nrow = min(N, W);
+    for (int e = tid; e < W * CP; e += 256) {
+      const int rr = e / CP, c = e % CP;
+      T v = T(0);
+      if (rr < nrow && c < cw) {
+        const double s = scaled ? sc[rr] : 1.0;
+        v = T(s * B[(size_t)rr * m + c0 + c]);
+      }
+      Y[e] = v;
+    }
+    fetch_panel(0);
+    store_panel(0);
+  }
+  __syncthreads();
+  for (int p = 0; p < nP; ++p) {
+    const int k = p * kNB;
     const int kb = min(kNB, N - k);
-    load_panel(k, kb);
-    __syncthreads();
-    typename M::v4 acc[2];
+    const int cur = p & 1;
+    const int sk = k % W;
+    const T *lp = Lp + cur * kNB * ldb;
+    const T *dp = Dp + cur * kNB * kNB;
+    const bool has_next = p + 1 < nP;
+    if (has_next) {
+      fetch_panel(p + 1);
+      fetch_rows(k + W);
+    }
+    // Y1 = inv(L11) R1
+    typename M::v4 acc = {0, 0, 0, 0};
+    if (wave < nct) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int ct = wave + 4 * i;
-      acc[i] = typename M::v4{0, 0, 0, 0};
-      if (ct < nct) {
+      for (int s = 0; s < 4; ++s) {
+        const int jj = 4 * s + lk;
+        const T a = dp[lr * kNB + jj];
+        const T bb = Y[wrap(sk + jj, W) * CP + wave * 16 + lr];
+        acc = M::mma(a, bb, acc);
+      }
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int jj = 4 * s + lk;
-          const T a = Dp[lr * kNB + jj];
-          const T bb = (jj < kb) ? Y[slot(k + jj) + ct * 16 + lr] : T(0);
-          acc[i] = M::mma(a, bb, acc[i]);
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int row = M::crow(v, lane), col = wave * 16 + lr;
+        Zs[row * CP + col] = acc[v];
+        if (row < kb && col < cw) B[(size_t)(k + row) * m + c0 + col] = (double)acc[v];
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int ct = wave + 4 * i;
-      if (ct < nct) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = M::crow(v, lane), col = ct * 16 + lr;
-          if (row < kb) {
-            Y[slot(k + row) + col] = acc[i][v];
-            if (col < m) Ybuf[(size_t)(k + row) * m + col] = (double)acc[i][v];
-          }
-        }
-      }
-    }
-    __syncthreads();
+    // R2 -= L21 Y1
     if (k + kb < N) {
       const int nrt = (b + 15) >> 4;
       for (int tile = wave; tile < nrt * nct; tile += 4) {
@@ -418,91 +542,98 @@ __global__ __launch_bounds__(256) void k_solve(Geom g, const int *__restrict__ o
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int ii = ti * 16 + M::crow(v, lane);
-          const bool ok = ii < b && k + kb + ii < N;
-          c[v] = ok ? Y[slot(k + kb + ii) + ct * 16 + lr] : T(0);
+          c[v] = (ii < b) ? Y[wrap(sk + kNB + ii, W) * CP + ct * 16 + lr] : T(0);
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int jj = 4 * s + lk;
-          const int ia = ti * 16 + lr;
-          const int ta = kb + ia - jj;
-          const T a = (jj < kb && ta <= b && k + kb + ia < N) ? Lp[jj * ldb + ta] : T(0);
-          const T bb = (jj < kb) ? Y[slot(k + jj) + ct * 16 + lr] : T(0);
+          const int ta = kNB + ti * 16 + lr - jj;
+          const T a = lp[jj * ldb + ta];
+          const T bb = Zs[jj * CP + ct * 16 + lr];
           c = M::mma(-a, bb, c);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int ii = ti * 16 + M::crow(v, lane);
-          if (ii < b && k + kb + ii < N) Y[slot(k + kb + ii) + ct * 16 + lr] = c[v];
+          if (ii < b) Y[wrap(sk + kNB + ii, W) * CP + ct * 16 + lr] = c[v];
         }
       }
     }
+    if (has_next) {
+      store_rows(k + W, sk);
+      store_panel(cur ^ 1);
+    }
     __syncthreads();
-    if (k + W < N) build_rows(k + W, min(N, k + W + kb));
   }
 
   // ------------------------------ backward ------------------------------
-  for (int e = tid; e < W * MP; e += 256) Y[e] = T(0);
-  __syncthreads();
-  const int klast = ((N - 1) / kNB) * kNB;
-  for (int k = klast; k >= 0; k -= kNB) {
-    const int kb = min(kNB, N - k);
-    load_panel(k, kb);
-    __syncthreads();
+  for (int e = tid; e < W * CP; e += 256) Y[e] = T(0);
+  typename M::v4 yreg = {0, 0, 0, 0};
+  auto fetch_y = [&](int p) {
+    const int k = p * kNB;
+    if (wave < nct) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int ct = wave + 4 * i;
-      if (ct < nct) {
-        typename M::v4 c;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = M::crow(v, lane), col = ct * 16 + lr;
-          c[v] = (row < kb && col < m) ? T(Ybuf[(size_t)(k + row) * m + col]) : T(0);
-        }
-        const int ks = (b + 3) >> 2;
-        for (int s = 0; s < ks; ++s) {
-          const int t = 4 * s + lk;
-          const int ta = kb + t - lr;
-          const T a = (lr < kb && t < b && ta <= b && k + kb + t < N) ? Lp[lr * ldb + ta] : T(0);
-          const T bb = (t < b) ? Y[slot(k + kb + t) + ct * 16 + lr] : T(0);
-          c = M::mma(-a, bb, c);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = M::crow(v, lane), col = ct * 16 + lr;
-          Zs[row * MP + col] = c[v];
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int row = M::crow(v, lane), col = wave * 16 + lr;
+        yreg[v] = (k + row < N && col < cw) ? T(B[(size_t)(k + row) * m + c0 + col]) : T(0);
       }
     }
+  };
+  fetch_panel(nP - 1);
+  store_panel(0);
+  fetch_y(nP - 1);
+  __syncthreads();
+  for (int p = nP - 1, it = 0; p >= 0; --p, ++it) {
+    const int k = p * kNB;
+    const int kb = min(kNB, N - k);
+    const int cur = it & 1;
+    const int sk = k % W;
+    const T *lp = Lp + cur * kNB * ldb;
+    const T *dp = Dp + cur * kNB * kNB;
+    typename M::v4 c = yreg;
+    if (p > 0) {
+      fetch_panel(p - 1);
+      fetch_y(p - 1);
+    }
+    // Z = Y1 - L21^T X2
+    if (wave < nct) {
+      const int ks = (b + 3) >> 2;
+      for (int s = 0; s < ks; ++s) {
+        const int t = 4 * s + lk;
+        const T a = lp[lr * ldb + (kNB + t - lr)];
+        const T bb = (t < b) ? Y[wrap(sk + kNB + t, W) * CP + wave * 16 + lr] : T(0);
+        c = M::mma(-a, bb, c);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Zs[M::crow(v, lane) * CP + wave * 16 + lr] = c[v];
+    }
     __syncthreads();
+    // X1 = inv(L11)^T Z
+    if (wave < nct) {
+      typename M::v4 acc = {0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int ct = wave + 4 * i;
-      if (ct < nct) {
-        typename M::v4 acc = {0, 0, 0, 0};
+      for (int s = 0; s < 4; ++s) {
+        const int jj = 4 * s + lk;
+        const T a = dp[jj * kNB + lr];
+        const T bb = Zs[jj * CP + wave * 16 + lr];
+        acc = M::mma(a, bb, acc);
+      }
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int jj = 4 * s + lk;
-          const T a = Dp[jj * kNB + lr];
-          const T bb = Zs[jj * MP + ct * 16 + lr];
-          acc = M::mma(a, bb, acc);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = M::crow(v, lane), col = ct * 16 + lr;
-          if (row < kb) {
-            Y[slot(k + row) + col] = acc[v];
-            if (col < m) {
-              const double s = scaled ? sc[k + row] : 1.0;
-              const double xv = s * (double)acc[v];
-              double *dst = X + (size_t)(k + row) * m + col;
-              if (mode == 0) *dst = xv;
-              else *dst += xv;
-            }
+      for (int v = 0; v < 4; ++v) {
+        const int row = M::crow(v, lane), col = wave * 16 + lr;
+        if (row < kb) {
+          Y[wrap(sk + row, W) * CP + col] = acc[v];
+          if (col < cw) {
+            const double s = scaled ? sc[k + row] : 1.0;
+            const double xv = s * (double)acc[v];
+            double *dst = Xo + (size_t)(k + row) * m + c0 + col;
+            if (mode == 0) *dst = xv;
+            else *dst += xv;
           }
         }
       }
     }
+    if (p > 0) store_panel(cur ^ 1);
     __syncthreads();
   }
 }
@@ -517,7 +648,7 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, const double *__restri
                                                   double *__restrict__ Rbuf,
                                                   double *__restrict__ norms) {
   __shared__ double red[2 * kMaxRhs];
-  const SubDesc S = g.sub[blockIdx.y];
+  const SubDesc &S = g.sub[blockIdx.y];
   const int m = S.m, N = S.N;
   for (int i = threadIdx.x; i < 2 * m; i += blockDim.x) red[i] = 0.0;
   __syncthreads();
@@ -583,33 +714,37 @@ __global__ __launch_bounds__(256) void k_ir_check(const double *__restrict__ nor
 __global__ __launch_bounds__(256) void k_flux(Geom g, const double *__restrict__ Xg,
                                               double *__restrict__ F, double *__restrict__ Fb,
                                               double *__restrict__ SAb) {
-  const SubDesc S = g.sub[blockIdx.x];
+  const SubDesc &S = g.sub[blockIdx.x];
   const int n = S.npatch, m = S.m;
   const double *X = Xg + S.X_off;
   for (int e = threadIdx.x; e < n * m; e += blockDim.x) {
     const int lp = e / m, c = e % m;
     int f = 0;
     for (int ff = 0; ff < 6; ++ff) {
-      if (S.face_if[ff] < 0) continue;
-      const IfaceDesc I = g.ifc[S.face_if[ff]];
+      const int fi = S.face_if[ff];
+      if (fi < 0) continue;
+      const IfaceDesc &I = g.ifc[fi];
       if (lp >= S.face_p0[ff] && lp < S.face_p0[ff] + I.na * I.nb) f = ff;
     }
-    const IfaceDesc I = g.ifc[S.face_if[f]];
+    const IfaceDesc &I = g.ifc[S.face_if[f]];
     const int w = lp - S.face_p0[f];
     const int pa = w % I.na, pb = w / I.na;
     const int a0 = split_start(pa, I.la, I.na), a1 = split_start(pa + 1, I.la, I.na);
     const int b0 = split_start(pb, I.lb, I.nb), b1 = split_start(pb + 1, I.lb, I.nb);
     const int d = f >> 1;
     const int sigma = (f & 1) ? 1 : -1;
-    const double H = S.ext[d] * g.h[d], A = g.area[d], hd = g.h[d];
+    const double hd = hdir(g, d), A = adir(g, d);
+    const double H = S.ext[d] * hd;
+    const double *kd_arr = kdir(g, d);
+    const int xd = sigma < 0 ? S.lo[d] : S.lo[d] + S.ext[d] - 1;
     double sf = 0.0, sb = 0.0, sab = 0.0;
     for (int tb = b0; tb < b1; ++tb) {
       for (int ta = a0; ta < a1; ++ta) {
-        int x[3];
-        x[I.a] = S.lo[I.a] + ta;
-        x[I.b] = S.lo[I.b] + tb;
-        x[d] = sigma < 0 ? S.lo[d] : S.lo[d] + S.ext[d] - 1;
-        const double kd = g.k[d][cell_index(g, x)];
+        I3 x{0, 0, 0};
+        x.set(I.a, S.lo[I.a] + ta);
+        x.set(I.b, S.lo[I.b] + tb);
+        x.set(d, xd);
+        const double kd = kd_arr[cell_index(g, x)];
         const double beta = g.alpha * H / kd;
         const double T = A / (hd / (2.0 * kd) + beta);
         const double G = (c == 1 + lp) ? 1.0 : ((c == 1 + n + lp) ? -sigma * beta : 0.0);
@@ -659,16 +794,26 @@ hipError_t launch_coef(const Geom &g, int n_sub, int max_cells, double *coef, do
   return hipGetLastError();
 }
 
+// Column stride of the factor's LDS ring: room for offsets up to 16*(nT+1)
+// (nT = ceil(b/16) tiles), odd to spread LDS banks.
+int factor_ldb(int bmax) { return 16 * ((bmax + 15) / 16) + 17; }
+
 size_t factor_lds_bytes(int fp32, int bmax) {
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
-  return (size_t)(bmax + kNB) * (bmax + 1) * es;
+  return (size_t)(bmax + kNB) * factor_ldb(bmax) * es;
 }
 
+// Column stride of the solve's panel buffers: operand offsets reach b + 31.
+int solve_ldb(int bmax) { return bmax + 33; }
+
 size_t solve_lds_bytes(int fp32, int bmax, int mmax) {
+  (void)mmax;
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
-  const size_t mp = (size_t)((mmax + 15) & ~15);
-  return ((size_t)kNB * (bmax + 1) + kNB * kNB + (size_t)(bmax + kNB) * mp + 16 * mp) * es;
+  return ((size_t)2 * kNB * solve_ldb(bmax) + 2 * kNB * kNB + (size_t)(bmax + kNB) * kMaxChunk +
+          (size_t)kNB * kMaxChunk) * es;
 }
+
+int solve_chunk_max() { return kMaxChunk; }
 
 template <typename T, int RPL>
 static hipError_t launch_factor_t(const SubDesc *subs, const int *order, int n_sub,
@@ -679,7 +824,7 @@ static hipError_t launch_factor_t(const SubDesc *subs, const int *order, int n_s
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_factor<T, RPL>), dim3(n_sub), dim3(256), lds, s, subs, order, coef, scal, L,
-                     Dg, st, bmax + 1, scaled);
+                     Dg, st, factor_ldb(bmax), scaled);
   return hipGetLastError();
 }
 
@@ -696,33 +841,39 @@ hipError_t launch_factor(int fp32, const SubDesc *subs, const int *order, int n_
   }
   if (W <= 128)
     return launch_factor_t<double, 2>(subs, order, n_sub, coef, scal, (double *)L, (double *)Dg, st,
-                                      bmax, 0, s);
+                                      bmax, 1, s);
   return launch_factor_t<double, 3>(subs, order, n_sub, coef, scal, (double *)L, (double *)Dg, st,
-                                    bmax, 0, s);
+                                    bmax, 1, s);
 }
 
 template <typename T>
-static hipError_t launch_solve_t(const Geom &g, const int *order, int n_sub, const double *r0,
-                                 const double *scal, const T *L, const T *Dg, double *X, double *R,
-                                 int mode, int bmax, int mmax, int scaled, hipStream_t s) {
-  const size_t lds = solve_lds_bytes(sizeof(T) == 4, bmax, mmax);
+static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, const double *scal,
+                                 const T *L, const T *Dg, double *B, double *X, int mode, int bmax,
+                                 int scaled, hipStream_t s) {
+  const size_t lds = solve_lds_bytes(sizeof(T) == 4, bmax, 0);
   hipError_t e = hipFuncSetAttribute((const void *)k_solve<T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int mpmax = (mmax + 15) & ~15;
-  hipLaunchKernelGGL(k_solve<T>, dim3(n_sub), dim3(256), lds, s, g, order, r0, scal, L, Dg, X, R,
-                     mode, scaled, bmax + 1, bmax + kNB, mpmax);
+  hipLaunchKernelGGL(k_solve<T>, dim3(n_work), dim3(256), lds, s, g, work, scal, L, Dg, B, X, mode,
+                     scaled, solve_ldb(bmax), bmax + kNB);
   return hipGetLastError();
 }
 
-hipError_t launch_solve(int fp32, const Geom &g, const int *order, int n_sub, const double *r0,
-                        const double *scal, const void *L, const void *Dg, double *X, double *R,
-                        int mode, int bmax, int mmax, hipStream_t s) {
+hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, const double *scal,
+                        const void *L, const void *Dg, double *B, double *X, int mode, int bmax,
+                        hipStream_t s) {
   if (fp32)
-    return launch_solve_t<float>(g, order, n_sub, r0, scal, (const float *)L, (const float *)Dg, X,
-                                 R, mode, bmax, mmax, 1, s);
-  return launch_solve_t<double>(g, order, n_sub, r0, scal, (const double *)L, (const double *)Dg, X,
-                                R, mode, bmax, mmax, 0, s);
+    return launch_solve_t<float>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X,
+                                 mode, bmax, 1, s);
+  return launch_solve_t<double>(g, work, n_work, scal, (const double *)L, (const double *)Dg, B, X,
+                                mode, bmax, 1, s);
+}
+
+hipError_t launch_rhs(const Geom &g, int n_sub, long long max_nm, const double *r0, double *B,
+                      hipStream_t s) {
+  dim3 grid((unsigned)((max_nm + 255) / 256), n_sub);
+  hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, g, r0, B);
+  return hipGetLastError();
 }
 
 hipError_t launch_residual(const Geom &g, int n_sub, long long max_nm, const double *coef,

@@ -85,7 +85,7 @@ int main(void) {{
   printf("%zu %zu %zu %zu\\n", sizeof(mrcm_problem), offsetof(mrcm_problem, kx), offsetof(mrcm_problem, wall_type), offsetof(mrcm_problem, pin_cell));
   printf("%zu %zu\\n", sizeof(mrcm_partition), offsetof(mrcm_partition, cut_x));
   printf("%zu %zu\\n", sizeof(mrcm_iface_space), offsetof(mrcm_iface_space, split));
-  printf("%zu %zu %zu\\n", sizeof(mrcm_options), offsetof(mrcm_options, ir_tol), offsetof(mrcm_options, ir_max_iter));
+  printf("%zu %zu %zu %zu\\n", sizeof(mrcm_options), offsetof(mrcm_options, ir_tol), offsetof(mrcm_options, ir_max_iter), offsetof(mrcm_options, fp64_refine));
   printf("%zu %zu %zu\\n", sizeof(mrcm_info), offsetof(mrcm_info, ir_residual), offsetof(mrcm_info, device_bytes));
   printf("%zu %zu\\n", sizeof(mrcm_subdomain_info), offsetof(mrcm_subdomain_info, pin_local));
   return 0;
@@ -98,7 +98,8 @@ int main(void) {{
         [ctypes.sizeof(CProblem), CProblem.kx.offset, CProblem.wall_type.offset, CProblem.pin_cell.offset],
         [ctypes.sizeof(CPartition), CPartition.cut_x.offset],
         [ctypes.sizeof(CIfaceSpace), CIfaceSpace.split.offset],
-        [ctypes.sizeof(COptions), COptions.ir_tol.offset, COptions.ir_max_iter.offset],
+        [ctypes.sizeof(COptions), COptions.ir_tol.offset, COptions.ir_max_iter.offset,
+         COptions.fp64_refine.offset],
         [ctypes.sizeof(CInfo), CInfo.ir_residual.offset, CInfo.device_bytes.offset],
         [ctypes.sizeof(CSubInfo), CSubInfo.pin_local.offset],
     ]

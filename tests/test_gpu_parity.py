@@ -83,9 +83,10 @@ def test_local_blocks_and_solution_fp64(name):
 
 
 def test_band_factor_matches_textbook_cholesky():
-    """The stored band factor is the Cholesky factor of A^H_l in the library's
-    row order (unique for an SPD matrix), compared with the textbook band
-    Cholesky of the oracle's local matrix permuted to that order."""
+    """The stored band factor is the Cholesky factor of the Jacobi-scaled
+    local matrix D^-1/2 A^H_l D^-1/2 in the library's row order (unique for an
+    SPD matrix), compared with the textbook band Cholesky of the oracle's local
+    matrix scaled and permuted the same way."""
     case = small_case((24, 18, 6), (2, 2, 1), split=((3, 2), (2, 2), (1, 1)), seed=12)
     m, *_ = _run(case)
     geo = Geometry(case.problem.dims, case.partition, case.iface)
@@ -93,6 +94,8 @@ def test_band_factor_matches_textbook_cholesky():
         ls = local_system(case.problem, geo, l, case.alpha)
         order = m.local_order(l)
         M = ls.M.toarray()[np.ix_(order, order)]
+        d = 1.0 / np.sqrt(np.diag(M))
+        M = d[:, None] * M * d[None, :]
         b = m.subdomain(l).band
         Lo = band_cholesky(to_band(M, b))
         Lg = m.copy_factor(l)
