@@ -42,6 +42,33 @@ __device__ __forceinline__ float lane_bcast(float v, int lane) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
 
+// Value of lane n of each row of 16 lanes, for every lane of that row (DPP
+// row_newbcast: a VGPR-to-VGPR move, no scalar registers involved; FP64 moves
+// in one instruction).  n must fold to a constant after unrolling.
+template <int n, typename T> __device__ __forceinline__ T row_bcast_c(T x) {
+  return __builtin_amdgcn_mov_dpp(x, 0x150 + n, 0xf, 0xf, true);
+}
+template <typename T> __device__ __forceinline__ T row_bcast(T x, int n) {
+  switch (n) {
+    case 0: return row_bcast_c<0>(x);
+    case 1: return row_bcast_c<1>(x);
+    case 2: return row_bcast_c<2>(x);
+    case 3: return row_bcast_c<3>(x);
+    case 4: return row_bcast_c<4>(x);
+    case 5: return row_bcast_c<5>(x);
+    case 6: return row_bcast_c<6>(x);
+    case 7: return row_bcast_c<7>(x);
+    case 8: return row_bcast_c<8>(x);
+    case 9: return row_bcast_c<9>(x);
+    case 10: return row_bcast_c<10>(x);
+    case 11: return row_bcast_c<11>(x);
+    case 12: return row_bcast_c<12>(x);
+    case 13: return row_bcast_c<13>(x);
+    case 14: return row_bcast_c<14>(x);
+    default: return row_bcast_c<15>(x);
+  }
+}
+
 __device__ __forceinline__ void set_status(DevStatus *st, int code, int where, double value) {
   if (atomicCAS(&st->code, 0, code) == 0) {
     st->where = where;

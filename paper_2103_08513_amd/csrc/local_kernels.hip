@@ -8,6 +8,8 @@
 // b = n0*n1 and the factor of a 20x20x5 block has b = 100.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_common.h"
 #include "launch.h"
 
@@ -148,151 +150,283 @@ __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ 
 
 // ---------------------------------------------------------------------------
 // Band Cholesky.  The active part of the band -- the current panel of kNB
-// columns and the b columns it updates -- lives in LDS as a ring of
-// W = b + kNB column slots, each holding the b+1 entries L[j..j+b][j].
-// Columns are assembled from the coefficients when they enter the ring, so
-// A^H_l never exists in global memory.  Per panel k (already factored):
-//   A  all waves update the next panel's 16 columns (tiles with tp = 0);
-//      threads 0..63 fetch the coefficients of the columns that enter next;
-//   B  wave 0 factors the next panel -- rows in registers, lane broadcasts
-//      instead of barriers, plus the inverse of its 16x16 diagonal block --
-//      while waves 1..3 finish the b x b trailing update (MFMA tiles);
-//   C  the incoming columns replace the retired panel in the ring.
+// columns and the columns it updates -- lives in LDS as a ring of
+// W = max(b, kNB) + kNB column slots, each holding the b+1 entries
+// L[j..j+b][j] and zero padding beyond offset b.  Columns are assembled from
+// the coefficients when they enter the ring, so A^H_l never exists in global
+// memory.  Iteration k (panel k fully factored) has two phases separated by
+// workgroup barriers:
+//   P1  wave 0 applies panel k to the next panel's 16x16 diagonal block and
+//       factors it in registers (lane broadcasts, reciprocal square roots),
+//       inverting it on the way; the other waves -- and wave 0 once done --
+//       take the rest of panel k's trailing update (MFMA tiles) and the
+//       copies of panel k to global memory from a shared counter;
+//   P2  all waves form the next panel's sub-diagonal rows
+//       L21 = A21 L11^{-T} on MFMA, and the columns k+W .. k+W+15 (their
+//       coefficients fetched one iteration earlier) take panel k's slots.
 // The factor is written by column, (b+1) entries per column; the inverses of
-// its 16x16 diagonal blocks (what the solves use) go to a separate array.
+// the 16x16 diagonal blocks (what the solves use) go to a separate array.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wrap(int s, int W) { return s >= W ? s - W : s; }
 
-template <typename T, int RPL>
-__device__ __forceinline__ void factor_panel(T *S, T *L, T *Dinv, int ldb, int k, int kb, int N, int b,
-                                             int W, int lane, DevStatus *st, int sub) {
+// 1/sqrt(x) for x > 0: the hardware estimate refined by Newton's iteration
+// y <- y + (y/2)(1 - x y^2), two steps in FP64 and one in FP32.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ float rsqrt_nr(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  const float e = fmaf(-x * y, y, 1.0f);
+  return fmaf(0.5f * y, e, y);
+}
+
+// 1/x: the hardware estimate refined by Newton's iteration y <- y + y(1 - x y),
+// two steps in FP64 and one in FP32.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+  const float y = __builtin_amdgcn_rcpf(x);
+  return fmaf(y, fmaf(-x, y, 1.0f), y);
+}
+
+// Diagonal block of panel k (kb <= 16 columns) on one wave: Cholesky factor
+// L11, written back into the ring, and X = L11^{-1} into Xs (row-major
+// 16x16; rows and columns past the matrix hold the identity).  Each row of
+// 16 lanes holds the whole block (lane r: row r), so every broadcast stays
+// within a row.  The elimination runs in the square-root-free form: with
+// pivot D and column a (entries a_i = A'[i][jj]), the Schur update is
+// A'[i][p] -= a_i a_p / D, so the chain from one pivot to the next needs only
+// 1/D; the Cholesky column a / sqrt(D) and the step of the inverse are formed
+// beside it.  The inverse rides along: lane c solves L11 x = e_c column by
+// column, x_i -= L[i][jj] x_jj = a_i (x_jj / D) with x_jj taken before its
+// own scaling by 1/sqrt(D).  Returns nonzero when a pivot was not positive.
+template <typename T>
+__device__ __forceinline__ int factor_diag(T *S, T *Xs, int ldb, int k, int kb, int b, int W, int lane) {
   const int sk = k % W;
-  T v[RPL][kNB];
-#pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    const int ri = lane + 64 * q;
-#pragma unroll
-    for (int jj = 0; jj < kNB; ++jj) {
-      const int t = ri - jj;
-      v[q][jj] = (jj < kb && t >= 0 && t <= b && k + ri < N) ? S[wrap(sk + jj, W) * ldb + t] : T(0);
-    }
-  }
+  int r = lane & 15;
+  // opaque to the optimiser: values derived from the lane index (identity
+  // entries, addresses) are recomputed per call instead of being hoisted out
+  // of the panel loop and held in registers across it
+  asm volatile("" : "+v"(r));
+  T v[kNB], x[kNB];
 #pragma unroll
   for (int jj = 0; jj < kNB; ++jj) {
-    if (jj < kb) {
-      T d2 = lane_bcast(v[0][jj], jj);
-      if (!(d2 > T(0))) {
-        if (lane == 0) set_status(st, -3, sub, (double)d2);
-        d2 = T(1);
-      }
-      const T d = sqrt(d2);
-      const T inv = T(1) / d;
+    T a = (r == jj) ? T(1) : T(0);
+    if (jj < kb && r < kb && jj <= r) a = S[wrap(sk + jj, W) * ldb + r - jj];
+    v[jj] = a;
+    x[jj] = (r == jj) ? T(1) : T(0);
+  }
+  T ok = T(1);
+  T d = row_bcast(v[0], 0);
 #pragma unroll
-      for (int q = 0; q < RPL; ++q) {
-        const int ri = lane + 64 * q;
-        if (ri > jj) v[q][jj] *= inv;
-        else if (ri == jj) v[q][jj] = d;
-      }
+  for (int jj = 0; jj < kNB; ++jj) {
+    ok = (d > T(0)) ? ok : T(0);
+    const T q = rcp_nr(d);
+    const T y = rsqrt_nr(d);
+    const T w = v[jj] * q;
+    const T xq = x[jj] * q;
+    if (jj + 1 < kNB) {
+      // column jj+1 first: it carries the next pivot
+      const T a = row_bcast(v[jj], jj + 1);
+      v[jj + 1] -= w * a;
+      x[jj + 1] -= a * xq;
+      d = row_bcast(v[jj + 1], jj + 1);
+    }
+    // entries above the diagonal of v collect garbage that is never read
 #pragma unroll
-      for (int pp = jj + 1; pp < kNB; ++pp) {
-        if (pp < kb) {
-          const T lpj = lane_bcast(v[0][jj], pp);
+    for (int i = jj + 2; i < kNB; ++i) {
+      const T a = row_bcast(v[jj], i);
+      v[i] -= w * a;
+      x[i] -= a * xq;
+    }
+    // lane jj holds the pivot itself, so the same product gives it sqrt(D)
+    v[jj] *= y;
+    x[jj] *= y;
+    // keep the pivots in order: without this the scheduler may defer whole
+    // chains of updates and hold their broadcast values in registers
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // every row of 16 lanes stores (the rows hold identical values): a store
+  // under a lane test would let the optimiser sink the whole computation of x
+  // into it and hold all broadcast values in registers until then
 #pragma unroll
-          for (int q = 0; q < RPL; ++q) {
-            const int ri = lane + 64 * q;
-            if (ri >= pp) v[q][pp] -= v[q][jj] * lpj;
-          }
-        }
-      }
+  for (int jj = 0; jj < kNB; ++jj) Xs[jj * kNB + r] = x[jj];
+#pragma unroll
+  for (int jj = 0; jj < kNB; ++jj) {
+    if (jj < kb && jj <= r && r - jj <= b) S[wrap(sk + jj, W) * ldb + r - jj] = v[jj];
+  }
+  return ok == T(1) ? 0 : 1;
+}
+
+// Tiles ti = ti0 + dt*t, t < NB (all >= 1; rows 16ti..16ti+15 of panel k) of
+// L21 = A21 X^T, X = L11^{-1} from Xs, written back into the ring; slots
+// t >= cnt repeat tile ti0 and store nothing.  Rows past the matrix or the
+// band come out zero because the corresponding entries of A21 are zero.
+// The MFMA chains of the tiles are interleaved without branches.
+template <typename T, int NB>
+__device__ __forceinline__ void panel_l21_tiles(T *S, const T *Xs, int ldb, int k, int kb, int b, int W,
+                                                int lane, int ti0, int dt, int cnt) {
+  using M = Mma<T>;
+  const int sk = k % W;
+  const int r = lane & 15, lk = lane >> 4;
+  T bx[4];
+  int colk[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int kk = 4 * s + lk;
+    bx[s] = Xs[r * kNB + kk];
+    colk[s] = wrap(sk + kk, W) * ldb - kk + r;
+  }
+  int ti[NB];
+  T a[NB][4];
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    ti[t] = t < cnt ? ti0 + dt * t : ti0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[t][s] = S[colk[s] + 16 * ti[t]];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  typename M::v4 acc[NB];
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    acc[t] = typename M::v4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[t][s] = (4 * s + lk < kb) ? a[t][s] : T(0);
+  }
+  if constexpr (NB == 1) {
+    // a lone tile: four independent MFMAs summed
+    typename M::v4 p1 = M::mma(a[0][1], bx[1], acc[0]);
+    typename M::v4 p2 = M::mma(a[0][2], bx[2], acc[0]);
+    typename M::v4 p3 = M::mma(a[0][3], bx[3], acc[0]);
+    acc[0] = M::mma(a[0][0], bx[0], acc[0]);
+    acc[0] = (acc[0] + p1) + (p2 + p3);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+      for (int t = 0; t < NB; ++t) acc[t] = M::mma(a[t][s], bx[s], acc[t]);
     }
   }
-  // Inverse of the diagonal block: lane r < kb ends with row r of L11^{-1}.
-  T xi[kNB];
+  T *col = S + wrap(sk + r, W) * ldb - r;
 #pragma unroll
-  for (int c = 0; c < kNB; ++c) xi[c] = (c == lane) ? T(1) : T(0);
+  for (int t = 0; t < NB; ++t) {
 #pragma unroll
-  for (int p = 0; p < kNB; ++p) {
-    if (p < kb) {
-      if (lane == p) {
-        const T dinv = T(1) / v[0][p];
-#pragma unroll
-        for (int c = 0; c <= p; ++c) xi[c] *= dinv;
-      }
-#pragma unroll
-      for (int c = 0; c <= p; ++c) {
-        const T xpc = lane_bcast(xi[c], p);
-        if (lane > p) xi[c] -= v[0][p] * xpc;
-      }
-    }
-  }
-  if (lane < kNB) {
-    T *dst = Dinv + (size_t)(k / kNB) * (kNB * kNB) + lane * kNB;
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) dst[c] = (lane < kb && c < kb) ? xi[c] : T(0);
-  }
-#pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    const int ri = lane + 64 * q;
-#pragma unroll
-    for (int jj = 0; jj < kNB; ++jj) {
-      const int t = ri - jj;
-      if (jj < kb && t >= 0 && t <= b) {
-        const T val = (k + ri < N) ? v[q][jj] : T(0);
-        L[(size_t)(k + jj) * (b + 1) + t] = val;
-        if (ri >= kb) S[wrap(sk + jj, W) * ldb + t] = val;
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * ti[t] + M::crow(q, lane);
+      if (t < cnt && r < kb && i - r <= b) col[i] = acc[t][q];
     }
   }
 }
 
-// One 16x16 tile (ti, tp) of the trailing update C -= L21 L21^T after panel k
-// (rows / columns counted from k + kNB).  Each ring column is padded with
-// zeros beyond offset b up to 16*(nT+1), so operand reads outside the band or
-// below the matrix need no test; colA[s] is the slot offset of panel column
-// k + 4s + lane/16.  Only the strictly upper half of diagonal tiles and tile
-// columns past the band are masked.
-template <typename T>
-__device__ __forceinline__ void factor_tile(T *S, int ldb, int b, int W, int sk, int lane, int ti,
-                                            int tp, const int (&colA)[4]) {
+// NB tiles (ti[t], tp[t]) of the trailing update C -= L21 L21^T after panel k
+// (rows and columns counted from k + kNB); slots t >= cnt repeat a valid tile
+// and store nothing.  All operands are loaded first and the MFMA chains of
+// the tiles are interleaved without branches: a single chain would wait out
+// the full MFMA latency at every step.  Each ring column is padded with zeros
+// beyond offset b up to 16*(nT+1), so operand reads outside the band or below
+// the matrix need no test; colA[s] is the slot offset of panel column
+// k + 4s + lane/16.  Accumulator loads clamp the offset so that the strictly
+// upper half of diagonal tiles and columns past the band need no branch; only
+// their stores are masked.
+template <typename T, int NB>
+__device__ __forceinline__ void factor_tiles(T *S, int ldb, int b, int W, int sk, int lane, const int (&ti)[NB],
+                                             const int (&tp)[NB], int cnt, const int (&colA)[4]) {
   using M = Mma<T>;
   const int lr = lane & 15, lk = lane >> 4;
-  const int pp = tp * 16 + lr;
-  const int cs = wrap(sk + kNB + pp, W) * ldb - pp;
-  const bool colok = pp < b;
-  const bool diag = ti == tp;
-  typename M::v4 c;
+  typename M::v4 c[NB];
+  T a[NB][4], bb[NB][4];
+  int cs[NB];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int ii = ti * 16 + M::crow(v, lane);
-    c[v] = (colok && (!diag || ii >= pp)) ? S[cs + ii] : T(0);
+  for (int t = 0; t < NB; ++t) {
+    const int pp = tp[t] * 16 + lr;
+    cs[t] = wrap(sk + kNB + pp, W) * ldb;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[t][v] = S[cs[t] + max(ti[t] * 16 + M::crow(v, lane) - pp, 0)];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      a[t][s] = S[colA[s] + kNB + ti[t] * 16 + lr - (4 * s + lk)];
+      bb[t][s] = S[colA[s] + kNB + pp - (4 * s + lk)];
+    }
   }
-  const int ia = kNB + ti * 16 + lr, ib = kNB + pp;
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (NB == 1) {
+    // a lone tile: four independent MFMAs summed, instead of one dependent
+    // chain of four
+    typename M::v4 p1 = M::mma(-a[0][1], bb[0][1], typename M::v4{T(0), T(0), T(0), T(0)});
+    typename M::v4 p2 = M::mma(-a[0][2], bb[0][2], typename M::v4{T(0), T(0), T(0), T(0)});
+    typename M::v4 p3 = M::mma(-a[0][3], bb[0][3], typename M::v4{T(0), T(0), T(0), T(0)});
+    c[0] = M::mma(-a[0][0], bb[0][0], c[0]);
+    c[0] = (c[0] + p1) + (p2 + p3);
+  } else {
 #pragma unroll
-  for (int s = 0; s < kNB / 4; ++s) {
-    const int jj = 4 * s + lk;
-    const T a = S[colA[s] + ia - jj];
-    const T bb = S[colA[s] + ib - jj];
-    c = M::mma(-a, bb, c);
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+      for (int t = 0; t < NB; ++t) c[t] = M::mma(-a[t][s], bb[t][s], c[t]);
+    }
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int ii = ti * 16 + M::crow(v, lane);
-    if (colok && (!diag || ii >= pp)) S[cs + ii] = c[v];
+  for (int t = 0; t < NB; ++t) {
+    const int pp = tp[t] * 16 + lr;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int off = ti[t] * 16 + M::crow(v, lane) - pp;
+      // the loaded accumulator of a masked entry is never stored, so it need
+      // not be zero
+      if (t < cnt && pp < b && (ti[t] != tp[t] || off >= 0)) S[cs[t] + off] = c[t][v];
+    }
   }
 }
 
-template <typename T, int RPL>
-__global__ __launch_bounds__(256) void k_factor(const SubDesc *__restrict__ subs,
-                                                const int *__restrict__ order,
-                                                const double *__restrict__ coef,
-                                                const double *__restrict__ scal,
-                                                T *__restrict__ Lg, T *__restrict__ Dg,
-                                                DevStatus *st, int ldb, int scaled) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *S = reinterpret_cast<T *>(smem_raw);
+// Coefficient of the entering column j at band offset t (kind = which of the
+// offsets 0, 1, n0, b; duplicates of an earlier kind load nothing).  The
+// loads are issued one iteration ahead; the value is formed when the column
+// enters.
+struct ColFetch {
+  double c0, c1, c2, c3, s1, s2;
+  int slot;
+};
+
+__device__ __forceinline__ ColFetch fetch_column_entry(const double *cf, const double *sc, int j, int t,
+                                                       bool first, int N, int n0, int b) {
+  ColFetch f{0.0, 0.0, 0.0, 0.0, 1.0, 1.0, -1};
+  if (j < N && j + t < N && first) {
+    if (t == 0) f.c0 = cf[4 * j];
+    if (t == 1) f.c1 = cf[4 * j + 1];
+    if (t == n0) f.c2 = cf[4 * j + 2];
+    if (t == b) f.c3 = cf[4 * j + 3];
+    f.s1 = sc[j];
+    f.s2 = sc[j + t];
+    f.slot = t;
+  }
+  return f;
+}
+
+template <typename T, int kMaxT, int NW>
+__device__ __forceinline__ void factor_body(const SubDesc *__restrict__ subs, const int *__restrict__ order,
+                                            const double *__restrict__ coef, const double *__restrict__ scal,
+                                            T *__restrict__ Lg, T *__restrict__ Dg, DevStatus *st, int ldb,
+                                            unsigned char *smem_raw, int &tile_ctr) {
   const int sub = order[blockIdx.x];
   const SubDesc &D = subs[sub];
-  const int N = D.N, b = D.b, n0 = D.n0, W = b + kNB, bp1 = b + 1;
+  const int N = D.N, b = D.b, n0 = D.n0, bp1 = b + 1;
+  const int W = max(b, kNB) + kNB;
+  T *S = reinterpret_cast<T *>(smem_raw);
+  // X = L11^{-1} of the current and of the next panel (alternating buffers)
+  T *Xbuf = S + (size_t)W * ldb;
+  // NW waves; tiles per wave in the L21 phase, and per batch of the
+  // trailing update
+  constexpr int NTH = 64 * NW;
+  constexpr int kNBA = (kMaxT + NW) / NW;
+  constexpr int kNB1 = 3;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double *cf = coef + 4 * D.cell_off;
   const double *sc = scal + D.cell_off;
@@ -301,14 +435,20 @@ __global__ __launch_bounds__(256) void k_factor(const SubDesc *__restrict__ subs
   const int nT = (b + 15) >> 4;
   // band offsets of the four coefficient kinds: diagonal, +ax0, +ax1, +ax2
   const int pos[4] = {0, 1, n0, b};
+  // entering-column work of threads 0..63: column jj = tid/4, kind tid%4
+  const int ejj = (tid >> 2) & 15, ekind = tid & 3, et = pos[ekind];
+  bool efirst = true;
+  for (int q = 0; q < ekind; ++q) efirst = efirst && (pos[q] != et);
+  int bad = 0;
 
   // the whole window starts at zero: padding beyond offset b stays zero
-  for (int e = tid; e < W * ldb; e += 256) S[e] = T(0);
+  for (int e = tid; e < W * ldb; e += NTH) S[e] = T(0);
+  if (tid == 0) tile_ctr = 0;
   __syncthreads();
-  // prologue: the first W columns
+  // prologue: the first W columns, then panel 0
   {
     const int ncol = min(N, W);
-    for (int e = tid; e < ncol * bp1; e += 256) {
+    for (int e = tid; e < ncol * bp1; e += NTH) {
       const int j = e / bp1, t = e % bp1;
       double v = 0.0;
       if (j + t < N) {
@@ -316,81 +456,152 @@ __global__ __launch_bounds__(256) void k_factor(const SubDesc *__restrict__ subs
         if (t == 1) v -= cf[4 * j + 1];
         if (t == n0) v -= cf[4 * j + 2];
         if (t == b) v -= cf[4 * j + 3];
-        if (scaled && v != 0.0) v *= sc[j] * sc[j + t];
+        if (v != 0.0) v *= sc[j] * sc[j + t];
       }
       S[j * ldb + t] = T(v);
     }
   }
+  ColFetch cur{0.0, 0.0, 0.0, 0.0, 1.0, 1.0, -1};
+  if (tid < 64) cur = fetch_column_entry(cf, sc, W + ejj, et, efirst, N, n0, b);
   __syncthreads();
-  if (wave == 0) factor_panel<T, RPL>(S, L, Dinv, ldb, 0, min(kNB, N), N, b, W, lane, st, sub);
+  if (wave == 0) bad |= factor_diag<T>(S, Xbuf, ldb, 0, min(kNB, N), b, W, lane);
+  __syncthreads();
+  if (wave < nT)
+    panel_l21_tiles<T, kNBA>(S, Xbuf, ldb, 0, min(kNB, N), b, W, lane, 1 + wave, NW, (nT - wave + NW - 1) / NW);
   __syncthreads();
 
   for (int k = 0; k < N; k += kNB) {
     const bool more = k + kNB < N;
-    // -- A: next panel's columns, and fetch the entering columns' coefficients
-    double cval = 0.0;
-    int cslot = -1;
-    if (tid < 64) {
-      const int jj = tid >> 2, kind = tid & 3;
-      const int j = k + W + jj;
-      const int t = pos[kind];
-      bool first = true;
-      for (int q = 0; q < kind; ++q) first = first && (pos[q] != t);
-      if (j < N && j + t < N && first) {
-        double v = 0.0;
-        if (t == 0) v += cf[4 * j];
-        if (t == 1) v -= cf[4 * j + 1];
-        if (t == n0) v -= cf[4 * j + 2];
-        if (t == b) v -= cf[4 * j + 3];
-        if (scaled && v != 0.0) v *= sc[j] * sc[j + t];
-        cval = v;
-        cslot = t;
-      }
-    }
     const int sk = k % W;
+    const int kb = min(kNB, N - k);
+    const int kb1 = min(kNB, N - k - kNB);
+    const T *Xc = Xbuf + ((k / kNB) & 1) * (kNB * kNB);
+    T *Xn = Xbuf + (((k / kNB) + 1) & 1) * (kNB * kNB);
+    // coefficients of the columns entering at the end of the next iteration
+    ColFetch nxt{0.0, 0.0, 0.0, 0.0, 1.0, 1.0, -1};
+    if (tid < 64) nxt = fetch_column_entry(cf, sc, k + kNB + W + ejj, et, efirst, N, n0, b);
     int colA[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) colA[q] = wrap(sk + 4 * q + (lane >> 4), W) * ldb;
-    if (more) {
-      for (int ti = wave; ti < nT; ti += 4) factor_tile<T>(S, ldb, b, W, sk, lane, ti, 0, colA);
+    // -- P1: wave 0 applies panel k to the next panel's diagonal block (tile
+    // (0, 0)) and factors it; the other waves -- and wave 0 once done -- take
+    // the remaining tiles of the update and the copies of panel k to global
+    // memory from a shared counter
+    if (wave == 0 && more) {
+      const int z[1] = {0};
+      factor_tiles<T, 1>(S, ldb, b, W, sk, lane, z, z, 1, colA);
+      bad |= factor_diag<T>(S, Xn, ldb, k + kNB, kb1, b, W, lane);
+    }
+    if (wave == NW - 1) {
+      // inverse diagonal block of panel k
+      T *dst = Dinv + (size_t)(k / kNB) * (kNB * kNB);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = lane + 64 * q;
+        dst[e] = ((e >> 4) < kb && (e & 15) < kb) ? Xc[e] : T(0);
+      }
+    }
+    {
+      // tiles by column: tp = 0 holds ti = 1 .. nT-1, tp >= 1 holds
+      // ti = tp .. nT-1
+      const int n_tiles = more ? (nT - 1) + nT * (nT - 1) / 2 : 0;
+      const int n_batch = (n_tiles + kNB1 - 1) / kNB1;
+      const int n_items = n_batch + kb;
+      for (;;) {
+        int idx = 0;
+        if (lane == 0) idx = atomicAdd(&tile_ctr, 1);
+        idx = __builtin_amdgcn_readfirstlane(idx);
+        if (idx >= n_items) break;
+        if (idx < n_batch) {
+          const int f0 = idx * kNB1;
+          int cp = 0, ci = f0;
+          while (ci >= nT - max(cp, 1)) {
+            ci -= nT - max(cp, 1);
+            ++cp;
+          }
+          ci += max(cp, 1);
+          const int ti0 = ci, tp0 = cp;
+          int ti[kNB1], tp[kNB1];
+#pragma unroll
+          for (int t = 0; t < kNB1; ++t) {
+            const bool valid = f0 + t < n_tiles;
+            ti[t] = valid ? ci : ti0;
+            tp[t] = valid ? cp : tp0;
+            if (++ci >= nT) {
+              ++cp;
+              ci = cp;
+            }
+          }
+          factor_tiles<T, kNB1>(S, ldb, b, W, sk, lane, ti, tp, min(kNB1, n_tiles - f0), colA);
+        } else {
+          // column k + jj of the factor to global memory
+          const int jj = idx - n_batch;
+          const T *col = S + wrap(sk + jj, W) * ldb;
+          T *dst = L + (size_t)(k + jj) * bp1;
+          for (int t = lane; t <= b; t += 64) dst[t] = col[t];
+        }
+      }
     }
     __syncthreads();
-    // -- C: the entering columns take the retired panel's slots.  With a
-    // single tile column (b <= 16) the whole update happened in A, and the
-    // next panel reaches past the ring, so C comes before B.
-    auto enter = [&]() {
+    // -- P2: the next panel's L21 on all waves; columns k+W .. k+W+15 take
+    // the slots of panel k
+    if (more && wave < nT)
+      panel_l21_tiles<T, kNBA>(S, Xn, ldb, k + kNB, kb1, b, W, lane, 1 + wave, NW, (nT - wave + NW - 1) / NW);
+    {
       const int j0 = k + W;
       if (j0 < N) {
         const int ncol = min(kNB, N - j0);
-        for (int e = tid; e < ncol * bp1; e += 256) {
-          const int jj = e / bp1, t = e % bp1;
-          if (t != 0 && t != 1 && t != n0 && t != b) S[wrap(sk + jj, W) * ldb + t] = T(0);
+        constexpr int TPC = NTH / kNB;  // threads per entering column
+        const int jj = tid / TPC;
+        if (jj < ncol) {
+          T *col = S + wrap(sk + jj, W) * ldb;
+          for (int t = tid % TPC; t <= b; t += TPC) {
+            if (t != 0 && t != 1 && t != n0 && t != b) col[t] = T(0);
+          }
         }
-        if (cslot >= 0) S[wrap(sk + (tid >> 2), W) * ldb + cslot] = T(cval);
-        // entries beyond the matrix (j + t >= N) at the special offsets
-        if (tid < 64) {
-          const int jj = tid >> 2, kind = tid & 3, t = pos[kind];
-          if (jj < ncol && j0 + jj + t >= N) S[wrap(sk + jj, W) * ldb + t] = T(0);
-        }
-      }
-      __syncthreads();
-    };
-    const bool early = nT == 1;
-    if (early) enter();
-    // -- B: factor the next panel on wave 0, finish the trailing update on waves 1..3
-    if (wave == 0) {
-      if (more) factor_panel<T, RPL>(S, L, Dinv, ldb, k + kNB, min(kNB, N - k - kNB), N, b, W, lane, st, sub);
-    } else if (more) {
-      int tile = 0;
-      for (int ti = 1; ti < nT; ++ti) {
-        for (int tp = 1; tp <= ti; ++tp, ++tile) {
-          if (tile % 3 == wave - 1) factor_tile<T>(S, ldb, b, W, sk, lane, ti, tp, colA);
+        if (tid < 64 && ejj < ncol) {
+          T *col = S + wrap(sk + ejj, W) * ldb;
+          if (cur.slot >= 0) {
+            col[cur.slot] = T((cur.c0 - cur.c1 - cur.c2 - cur.c3) * (cur.s1 * cur.s2));
+          } else if (j0 + ejj + et >= N) {
+            col[et] = T(0);  // entries beyond the matrix at the special offsets
+          }
         }
       }
     }
+    if (tid == 0) tile_ctr = 0;
     __syncthreads();
-    if (!early) enter();
+    cur = nxt;
   }
+  if (bad && tid == 0) set_status(st, -3, sub, 0.0);
+}
+
+// One workgroup per subdomain.  The FP64 ring fills most of the LDS (one
+// workgroup per CU), so the FP64 kernel runs eight waves: wave 0's diagonal
+// block (VALU) shares its SIMD with a wave issuing MFMA tiles.  The FP32
+// kernel runs four waves, held to two waves per SIMD so that two workgroups
+// share a CU.
+template <int kMaxT>
+__global__ __launch_bounds__(512, 1) void k_factor64(const SubDesc *__restrict__ subs,
+                                                     const int *__restrict__ order,
+                                                     const double *__restrict__ coef,
+                                                     const double *__restrict__ scal,
+                                                     double *__restrict__ Lg, double *__restrict__ Dg,
+                                                     DevStatus *st, int ldb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int tile_ctr;
+  factor_body<double, kMaxT, 8>(subs, order, coef, scal, Lg, Dg, st, ldb, smem_raw, tile_ctr);
+}
+template <int kMaxT>
+__global__ __launch_bounds__(256, 2) void k_factor32(const SubDesc *__restrict__ subs,
+                                                     const int *__restrict__ order,
+                                                     const double *__restrict__ coef,
+                                                     const double *__restrict__ scal,
+                                                     float *__restrict__ Lg, float *__restrict__ Dg,
+                                                     DevStatus *st, int ldb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int tile_ctr;
+  factor_body<float, kMaxT, 4>(subs, order, coef, scal, Lg, Dg, st, ldb, smem_raw, tile_ctr);
 }
 
 // ---------------------------------------------------------------------------
@@ -796,11 +1007,14 @@ hipError_t launch_coef(const Geom &g, int n_sub, int max_cells, double *coef, do
 
 // Column stride of the factor's LDS ring: room for offsets up to 16*(nT+1)
 // (nT = ceil(b/16) tiles), odd to spread LDS banks.
-int factor_ldb(int bmax) { return 16 * ((bmax + 15) / 16) + 17; }
+// Ring column stride: at least 16*(nT+1) entries, and chosen so that the
+// MFMA operand and accumulator accesses of a trailing-update tile spread over
+// the LDS banks (the offsets were picked by counting bank collisions).
+int factor_ldb(int fp32, int bmax) { return 16 * ((bmax + 15) / 16) + (fp32 ? 26 : 19); }
 
 size_t factor_lds_bytes(int fp32, int bmax) {
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
-  return (size_t)(bmax + kNB) * factor_ldb(bmax) * es;
+  return ((size_t)(std::max(bmax, kNB) + kNB) * factor_ldb(fp32, bmax) + 2 * kNB * kNB) * es;
 }
 
 // Column stride of the solve's panel buffers: operand offsets reach b + 31.
@@ -815,35 +1029,33 @@ size_t solve_lds_bytes(int fp32, int bmax, int mmax) {
 
 int solve_chunk_max() { return kMaxChunk; }
 
-template <typename T, int RPL>
-static hipError_t launch_factor_t(const SubDesc *subs, const int *order, int n_sub,
+// kMaxT: most tiles in one tile column of the trailing update, nT - 1
+template <typename T, typename K>
+static hipError_t launch_factor_t(K kern, int threads, const SubDesc *subs, const int *order, int n_sub,
                                   const double *coef, const double *scal, T *L, T *Dg,
-                                  DevStatus *st, int bmax, int scaled, hipStream_t s) {
-  const size_t lds = factor_lds_bytes(sizeof(T) == 4, bmax);
-  hipError_t e = hipFuncSetAttribute((const void *)k_factor<T, RPL>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                                  DevStatus *st, int bmax, hipStream_t s) {
+  const int fp32 = sizeof(T) == 4;
+  const size_t lds = factor_lds_bytes(fp32, bmax);
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_factor<T, RPL>), dim3(n_sub), dim3(256), lds, s, subs, order, coef, scal, L,
-                     Dg, st, factor_ldb(bmax), scaled);
+  hipLaunchKernelGGL(kern, dim3(n_sub), dim3(threads), lds, s, subs, order, coef, scal, L, Dg, st,
+                     factor_ldb(fp32, bmax));
   return hipGetLastError();
 }
 
 hipError_t launch_factor(int fp32, const SubDesc *subs, const int *order, int n_sub,
                          const double *coef, const double *scal, void *L, void *Dg, DevStatus *st,
                          int bmax, hipStream_t s) {
-  const int W = bmax + kNB;
+  const int nT = (bmax + 15) / 16;
   if (fp32) {
-    if (W <= 128)
-      return launch_factor_t<float, 2>(subs, order, n_sub, coef, scal, (float *)L, (float *)Dg, st,
-                                       bmax, 1, s);
-    return launch_factor_t<float, 3>(subs, order, n_sub, coef, scal, (float *)L, (float *)Dg, st,
-                                     bmax, 1, s);
+    if (nT <= 7)
+      return launch_factor_t(k_factor32<6>, 256, subs, order, n_sub, coef, scal, (float *)L, (float *)Dg, st,
+                             bmax, s);
+    return launch_factor_t(k_factor32<(kMaxBand32 + 15) / 16 - 1>, 256, subs, order, n_sub, coef, scal,
+                           (float *)L, (float *)Dg, st, bmax, s);
   }
-  if (W <= 128)
-    return launch_factor_t<double, 2>(subs, order, n_sub, coef, scal, (double *)L, (double *)Dg, st,
-                                      bmax, 1, s);
-  return launch_factor_t<double, 3>(subs, order, n_sub, coef, scal, (double *)L, (double *)Dg, st,
-                                    bmax, 1, s);
+  return launch_factor_t(k_factor64<(kMaxBand64 + 15) / 16 - 1>, 512, subs, order, n_sub, coef, scal,
+                         (double *)L, (double *)Dg, st, bmax, s);
 }
 
 template <typename T>
