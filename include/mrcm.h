@@ -240,15 +240,17 @@ mrcm_status mrcm_copy_interface(const mrcm_interface *iface, double *A, double *
  * subsystem; off by default).  While enabled, every call records an event
  * pair around each stage and accumulates the elapsed milliseconds and the
  * number of occurrences in a process-wide table, resolved when the call has
- * synchronised.  Stages: coefficients (one kernel), local factorisation (one
- * kernel), local solves (one kernel per sweep set), refinement residuals and
- * corrections, Gamma-flux reduction (one kernel), interface assembly,
- * interface LU (two kernels per 32-column block), interface triangular
- * sweeps, reconstruction.
+ * synchronised.  Stages, each one kernel launch unless noted: coefficients,
+ * local factorisation, right-hand sides of (2.25)/(2.26), the local band
+ * solves, the FP64 residuals of refinement (a fill, the residual and, in
+ * FP32, the convergence check), the correction solves of refinement,
+ * Gamma-flux reduction, interface assembly (several kernels), interface LU
+ * (two kernels per 32-column block), interface triangular sweeps (several
+ * kernels), reconstruction (two kernels).
  */
-enum { MRCM_STAGE_COEF = 0, MRCM_STAGE_FACTOR, MRCM_STAGE_SOLVE, MRCM_STAGE_REFINE,
-       MRCM_STAGE_FLUX, MRCM_STAGE_ASSEMBLE, MRCM_STAGE_LU, MRCM_STAGE_SWEEP,
-       MRCM_STAGE_RECONSTRUCT, MRCM_STAGE_COUNT };
+enum { MRCM_STAGE_COEF = 0, MRCM_STAGE_FACTOR, MRCM_STAGE_RHS, MRCM_STAGE_SOLVE,
+       MRCM_STAGE_RESIDUAL, MRCM_STAGE_REFINE, MRCM_STAGE_FLUX, MRCM_STAGE_ASSEMBLE,
+       MRCM_STAGE_LU, MRCM_STAGE_SWEEP, MRCM_STAGE_RECONSTRUCT, MRCM_STAGE_COUNT };
 typedef struct {
   double ms[16];        /* accumulated milliseconds per stage */
   int64_t count[16];    /* occurrences per stage */

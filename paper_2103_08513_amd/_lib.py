@@ -20,7 +20,8 @@ EXPORTS = [
     "mrcm_profile_get",
 ]
 
-STAGES = ["coef", "factor", "solve", "refine", "flux", "assemble", "lu", "sweep", "reconstruct"]
+STAGES = ["coef", "factor", "rhs", "solve", "residual", "refine", "flux", "assemble", "lu", "sweep",
+          "reconstruct"]
 
 
 class CProblem(ctypes.Structure):

@@ -650,8 +650,11 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
                       H.bmax, s));
   }
   {
-    Stage t(MRCM_STAGE_SOLVE, s);
+    Stage t(MRCM_STAGE_RHS, s);
     ENQ(launch_rhs(g, h->n_sub, H.max_nm, h->r0, h->X, s));
+  }
+  {
+    Stage t(MRCM_STAGE_SOLVE, s);
     ENQ(launch_solve(fp32, g, h->d_work, (int)H.work.size(), h->scal, h->L, h->Dinv, h->X, h->X, 0,
                      H.bmax, s));
   }
@@ -664,9 +667,12 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       h->bytes += H.totX * 8;
     }
     for (int it = 0; it < h->refine64; ++it) {
+      {
+        Stage t(MRCM_STAGE_RESIDUAL, s);
+        ENQ(launch_fill(h->norms, 2LL * H.totCols, 0.0, s));
+        ENQ(launch_residual(g, h->n_sub, H.max_nm, h->coef, h->r0, h->X, h->R, h->norms, s));
+      }
       Stage t(MRCM_STAGE_REFINE, s);
-      ENQ(launch_fill(h->norms, 2LL * H.totCols, 0.0, s));
-      ENQ(launch_residual(g, h->n_sub, H.max_nm, h->coef, h->r0, h->X, h->R, h->norms, s));
       ENQ(launch_solve(fp32, g, h->d_work, (int)H.work.size(), h->scal, h->L, h->Dinv, h->R, h->X,
                        1, H.bmax, s));
     }
@@ -675,7 +681,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   if (fp32) {
     for (int it = 0;; ++it) {
       {
-        Stage t(MRCM_STAGE_REFINE, s);
+        Stage t(MRCM_STAGE_RESIDUAL, s);
         ENQ(launch_fill(h->norms, 2LL * H.totCols, 0.0, s));
         ENQ(launch_residual(g, h->n_sub, H.max_nm, h->coef, h->r0, h->X, h->R, h->norms, s));
         ENQ(launch_ir_check(h->norms, H.totCols, h->scalar, s));

@@ -621,12 +621,11 @@ __global__ __launch_bounds__(256, 2) void k_factor32(const SubDesc *__restrict__
 constexpr int kLReg = 12;   // L entries per thread and panel: 16*(b+1) <= 256*kLReg
 constexpr int kMaxChunk = 48;
 
-template <typename T>
+template <typename T, int mode>
 __global__ __launch_bounds__(256) void k_solve(Geom g, const int4 *__restrict__ work,
                                                const double *__restrict__ scal,
                                                const T *__restrict__ Lg, const T *__restrict__ Dg,
-                                               double *Bg, double *Xg,
-                                               int mode, int scaled, int ldb, int wmax) {
+                                               double *Bg, double *Xg, int scaled, int ldb, int wmax) {
   using M = Mma<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int4 item = work[blockIdx.x];
@@ -1058,15 +1057,15 @@ hipError_t launch_factor(int fp32, const SubDesc *subs, const int *order, int n_
                          (double *)L, (double *)Dg, st, bmax, s);
 }
 
-template <typename T>
+template <typename T, int mode>
 static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, const double *scal,
-                                 const T *L, const T *Dg, double *B, double *X, int mode, int bmax,
-                                 int scaled, hipStream_t s) {
+                                 const T *L, const T *Dg, double *B, double *X, int bmax, int scaled,
+                                 hipStream_t s) {
   const size_t lds = solve_lds_bytes(sizeof(T) == 4, bmax, 0);
-  hipError_t e = hipFuncSetAttribute((const void *)k_solve<T>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_solve<T, mode>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_solve<T>, dim3(n_work), dim3(256), lds, s, g, work, scal, L, Dg, B, X, mode,
+  hipLaunchKernelGGL((k_solve<T, mode>), dim3(n_work), dim3(256), lds, s, g, work, scal, L, Dg, B, X,
                      scaled, solve_ldb(bmax), bmax + kNB);
   return hipGetLastError();
 }
@@ -1074,11 +1073,20 @@ static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, co
 hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, const double *scal,
                         const void *L, const void *Dg, double *B, double *X, int mode, int bmax,
                         hipStream_t s) {
-  if (fp32)
-    return launch_solve_t<float>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X,
-                                 mode, bmax, 1, s);
-  return launch_solve_t<double>(g, work, n_work, scal, (const double *)L, (const double *)Dg, B, X,
-                                mode, bmax, 1, s);
+  // separate instantiations per mode, so that profiles tell the first solve
+  // from the refinement corrections
+  if (fp32) {
+    if (mode == 0)
+      return launch_solve_t<float, 0>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax,
+                                      1, s);
+    return launch_solve_t<float, 1>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax, 1,
+                                    s);
+  }
+  if (mode == 0)
+    return launch_solve_t<double, 0>(g, work, n_work, scal, (const double *)L, (const double *)Dg, B, X, bmax,
+                                     1, s);
+  return launch_solve_t<double, 1>(g, work, n_work, scal, (const double *)L, (const double *)Dg, B, X, bmax,
+                                   1, s);
 }
 
 hipError_t launch_rhs(const Geom &g, int n_sub, long long max_nm, const double *r0, double *B,
