@@ -83,6 +83,9 @@ def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1):
         if prof.count[i]:
             stages[name] = {"ms_total": prof.ms[i], "count": int(prof.count[i]),
                             "ms_avg": prof.ms[i] / prof.count[i]}
+    # the interface residual once, outside the timed and profiled loops
+    model.solve_interface(X, refine=refine, residual=True)
+    torch.cuda.synchronize()
     info = model.info()
     n_dims, w = model.interface_dims()
     out = dict(ms_step=ms_step, stages=stages, info=info, interface_n=n_dims, interface_w=w,

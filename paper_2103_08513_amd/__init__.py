@@ -118,7 +118,10 @@ class MRCM:
         _lib.check(code, "mrcm_assemble_interface")
         return self
 
-    def solve_interface(self, X=None, refine=0, stream=None):
+    def solve_interface(self, X=None, refine=0, stream=None, residual=False):
+        """Interface solve; with residual=True the relative residual of the
+        unfactored system is also computed (one more band product and a
+        stream synchronisation) and kept in ``interface_residual``."""
         import torch
         info = self.info()
         nv = info.n_patch
@@ -126,9 +129,10 @@ class MRCM:
             X = torch.empty(2 * nv, dtype=torch.float64, device=self.device)
         res = c_double(0.0)
         code = self.lib.mrcm_solve_interface(self._iface, int(refine), _stream_ptr(stream),
-                                             _dev_ptr(X, "X") if nv > 0 else None, byref(res))
+                                             _dev_ptr(X, "X") if nv > 0 else None,
+                                             byref(res) if residual else None)
         _lib.check(code, "mrcm_solve_interface")
-        self.interface_residual = res.value
+        self.interface_residual = res.value if residual else None
         return X
 
     def reconstruct(self, X, p=None, U=None, stream=None):

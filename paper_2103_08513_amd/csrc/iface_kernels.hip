@@ -72,280 +72,265 @@ __global__ __launch_bounds__(256) void k_iface_scatter(Geom g, const int *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Band LU without pivoting, right-looking, blocks of kLU columns.
-// Step k0 = panel kernel (every workgroup factors the kLU x kLU diagonal block
-// in wave 0's registers; workgroup 0 stores it to `diag` and applies L11^{-1}
-// to the right-hand side, the others compute a chunk of L21 = A21 U11^{-1} or
-// U12 = L11^{-1} A12) followed by the update kernel A22 -= L21 U12 (MFMA
-// FP64), which also copies the factored diagonal block into the band and
-// updates the right-hand side, b2 -= L21 y1.
+// Band LDL^T of the interface system.  With s = -1 on the pressure rows (even
+// unknowns) and +1 on the velocity rows, M = diag(s) A^int is symmetric:
+// A^UP = -(A^PU)^T, A^PP and A^UU symmetric (eqs. (2.19)-(2.22)), with
+// -A^PP >= 0 and A^UU < 0, i.e. quasi-definite, which admits an LDL^T
+// factorisation in any symmetric order without pivoting.  The factors are
+// stored LU-fashion in the band -- L below the diagonal, D on it, U = D L^T
+// above -- so the two triangular sweeps solve M x = diag(s) b.
+//
+// Column blocks of kLB = 16.  Block k is factored by one wave (each row of 16
+// lanes holds the whole 16x16 block, so broadcasts are DPP row moves), which
+// also forms L11^{-1} and 1/D into `inv` (272 entries per block: L11^{-1}
+// row-major, then 1/D).  One kernel per block then applies it to the trailing
+// band: every lower 64x64 tile (ti >= tj) forms W = A21 L11^{-T} for its
+// row and column blocks on MFMA (L21 = W D^{-1}, U12 = W^T) and updates
+// C -= L21 W^T; the tile holding the next diagonal block factors it at once.
 // ---------------------------------------------------------------------------
-constexpr int kLU = 32;
+constexpr int kLB = 16;
+constexpr int kInvStride = kLB * kLB + kLB;
 
-// Unrolled LU of the kLU x kLU diagonal block held one row per lane
-// (rows beyond kb and entries outside the band are zero).  Step P: the pivot
-// row P is broadcast from lane P and every lower row eliminates column P.
-template <int P>
-__device__ __forceinline__ void lu_rows_step(double (&row)[kLU], int lane, int kb, int k0,
-                                             DevStatus *st) {
-  if (P < kb) {
-    double piv = lane_bcast(row[P], P);
-    if (piv == 0.0 || !isfinite(piv)) {
-      if (lane == 0) set_status(st, -5, k0 + P, piv);
-      piv = 1.0;
+__global__ void k_flip_copy(const double *__restrict__ AB0, double *__restrict__ AB,
+                            const double *__restrict__ b0, double *__restrict__ b, int n, int w) {
+  const int ld = 2 * w + 1;
+  const long long total = (long long)n * ld;
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (; e < total; e += stride) {
+    const int j = (int)(e / ld);
+    const int i = j + (int)(e % ld) - w;
+    AB[e] = (i & 1) ? AB0[e] : -AB0[e];
+    if (e < n) b[e] = (e & 1) ? b0[e] : -b0[e];
+  }
+}
+
+// 16x16 LDL^T of the block at rows and columns k0 .. k0+kb-1 of M, whose lower
+// triangle is given row-major in blk (stride 17); rows and columns past kb act
+// as the identity.  Runs on one wave; writes L, D and U = D L^T into the band
+// and L11^{-1}, 1/D into inv.  Returns nonzero on a zero or non-finite pivot.
+__device__ int ldl_diag16(const double *blk, int kb, int lane, double *__restrict__ AB, int w, int k0,
+                          double *__restrict__ inv) {
+  const int ld = 2 * w + 1;
+  int r = lane & 15;
+  // opaque to the optimiser, as in the local factor: lane-derived constants
+  // are recomputed rather than held across the caller's loop
+  asm volatile("" : "+v"(r));
+  double v[kLB], x[kLB];
+#pragma unroll
+  for (int c = 0; c < kLB; ++c) {
+    double a = (r == c) ? 1.0 : 0.0;
+    if (c < kb && r < kb && c <= r) a = blk[r * (kLB + 1) + c];
+    v[c] = a;
+    x[c] = (r == c) ? 1.0 : 0.0;
+  }
+  double ok = 1.0;
+  double qs[kLB];
+  double d = row_bcast(v[0], 0);
+#pragma unroll
+  for (int jj = 0; jj < kLB; ++jj) {
+    ok = (d != 0.0 && isfinite(d)) ? ok : 0.0;
+    double dd = (d != 0.0 && isfinite(d)) ? d : 1.0;
+    double q = __builtin_amdgcn_rcp(dd);
+    double e = fma(-dd, q, 1.0);
+    q = fma(q, e, q);
+    e = fma(-dd, q, 1.0);
+    q = fma(q, e, q);
+    qs[jj] = q;
+    const double wv = v[jj] * q;
+    const double xq = x[jj] * q;
+    if (jj + 1 < kLB) {
+      const double a = row_bcast(v[jj], jj + 1);
+      v[jj + 1] -= wv * a;
+      x[jj + 1] -= a * xq;
+      d = row_bcast(v[jj + 1], jj + 1);
     }
-    const double l = row[P] / piv;
-    if (lane > P) row[P] = l;
 #pragma unroll
-    for (int c = P + 1; c < kLU; ++c) {
-      const double u = lane_bcast(row[c], P);
-      if (lane > P) row[c] -= l * u;
+    for (int i = jj + 2; i < kLB; ++i) {
+      const double a = row_bcast(v[jj], i);
+      v[i] -= wv * a;
+      x[i] -= a * xq;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // every row of 16 lanes stores (identical values), so no computation is
+  // sunk into a lane-conditional block
+#pragma unroll
+  for (int i = 0; i < kLB; ++i) inv[i * kLB + r] = x[i];
+  if (r == 0) {
+#pragma unroll
+    for (int c = 0; c < kLB; ++c) inv[kLB * kLB + c] = qs[c];
+  }
+#pragma unroll
+  for (int c = 0; c < kLB; ++c) {
+    if (c < kb && r < kb && c <= r && r - c <= w) {
+      // lower: L[r][c] = a / D_c; diagonal: D_r; upper: U[c][r] = D_c L[r][c] = a
+      AB[(size_t)(k0 + c) * ld + (w + r - c)] = (r == c) ? v[c] : v[c] * qs[c];
+      if (r != c) AB[(size_t)(k0 + r) * ld + (w + c - r)] = v[c];
     }
   }
-  if constexpr (P + 1 < kLU) lu_rows_step<P + 1>(row, lane, kb, k0, st);
+  return ok == 1.0 ? 0 : 1;
 }
 
-// l U11 = a for one row l (U11 upper, from LDS D).
-template <int C>
-__device__ __forceinline__ void trsm_row_upper(double (&l)[kLU], const double *D, int kb) {
-  if (C < kb) {
-    double s = l[C];
-#pragma unroll
-    for (int p = 0; p < C; ++p) s -= l[p] * D[p * (kLU + 1) + C];
-    l[C] = s / D[C * (kLU + 1) + C];
+__global__ __launch_bounds__(64) void k_ldl_first(double *__restrict__ AB, int n, int w,
+                                                  double *__restrict__ inv, DevStatus *st) {
+  __shared__ double blk[kLB * (kLB + 1)];
+  const int ld = 2 * w + 1;
+  const int lane = threadIdx.x;
+  const int kb = min(kLB, n);
+  for (int e = lane; e < kLB * kLB; e += 64) {
+    const int r = e / kLB, c = e % kLB;
+    blk[r * (kLB + 1) + c] = (r < kb && c <= r && r - c <= w) ? AB[(size_t)c * ld + (w + r - c)] : 0.0;
   }
-  if constexpr (C + 1 < kLU) trsm_row_upper<C + 1>(l, D, kb);
+  __syncthreads();
+  if (ldl_diag16(blk, kb, lane, AB, w, 0, inv) && lane == 0) set_status(st, -5, 0, 0.0);
 }
 
-// L11 u = a for one column u (L11 unit lower, from LDS D).
-template <int R>
-__device__ __forceinline__ void trsm_col_lower(double (&u)[kLU], const double *D, int kb) {
-  if (R < kb) {
-    double s = u[R];
-#pragma unroll
-    for (int p = 0; p < R; ++p) s -= D[R * (kLU + 1) + p] * u[p];
-    u[R] = s;
+// Step for block k0 (factored; its L11^{-1}, 1/D in inv_k): the trailing rows
+// and columns r0 = k0 + 16 .. r0 + nr - 1 in lower 64x64 tiles, one
+// workgroup (four waves, 16 rows each) per tile.
+__global__ __launch_bounds__(256) void k_ldl_step(double *__restrict__ AB, int n, int w, int k0,
+                                                  const double *__restrict__ inv_k,
+                                                  double *__restrict__ inv_next, DevStatus *st) {
+  using M = Mma<double>;
+  __shared__ double Li[kLB * (kLB + 1)];
+  __shared__ double Dq[kLB];
+  __shared__ double Wi[64 * (kLB + 1)];
+  __shared__ double Wj[64 * (kLB + 1)];
+  __shared__ double Dn[kLB * (kLB + 1)];
+  const int ld = 2 * w + 1;
+  const int r0 = k0 + kLB;
+  const int nr = min(n, k0 + kLB + w) - r0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  // lower tile (ti, tj) of this workgroup
+  int ti = 0, tj = blockIdx.x;
+  while (tj > ti) {
+    tj -= ti + 1;
+    ++ti;
   }
-  if constexpr (R + 1 < kLU) trsm_col_lower<R + 1>(u, D, kb);
-}
-
-__device__ __forceinline__ void lu_diag_block(const double *AB, int ld, int w, int k0, int kb,
-                                              double *D /* [kLU][kLU+1] */, DevStatus *st) {
-  const int tid = threadIdx.x;
-  if (tid < 64) {
-    const int lane = tid;
-    double row[kLU];
+  const int i0 = r0 + 64 * ti, j0 = r0 + 64 * tj;
+  for (int e = tid; e < kLB * kLB; e += 256) Li[(e / kLB) * (kLB + 1) + (e % kLB)] = inv_k[e];
+  if (tid < kLB) Dq[tid] = inv_k[kLB * kLB + tid];
+  // A21 rows of this wave for the row block (and the column block)
+  auto a21 = [&](int i, int c) -> double {
+    const int j = k0 + c;
+    return (i < r0 + nr && i - j <= w) ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
+  };
+  double ai[4], aj[4];
 #pragma unroll
-    for (int c = 0; c < kLU; ++c)
-      row[c] = (lane < kb && c < kb && abs(lane - c) <= w) ? AB[(size_t)(k0 + c) * ld + (w + lane - c)]
-                                                            : 0.0;
-    lu_rows_step<0>(row, lane, kb, k0, st);
-    if (lane < kLU) {
+  for (int s = 0; s < 4; ++s) {
+    ai[s] = a21(i0 + 16 * wave + lr, 4 * s + lk);
+    aj[s] = a21(j0 + 16 * wave + lr, 4 * s + lk);
+  }
+  // the C tile of this wave: rows i0 + 16 wave + .., columns j0 + 16 tc + ..
+  typename M::v4 c[4];
 #pragma unroll
-      for (int c = 0; c < kLU; ++c) D[lane * (kLU + 1) + c] = row[c];
+  for (int tc = 0; tc < 4; ++tc) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + 16 * wave + M::crow(v, lane), j = j0 + 16 * tc + lr;
+      const bool ok = i < r0 + nr && j < r0 + nr && i >= j && i - j <= w;
+      c[tc][v] = ok ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
     }
   }
   __syncthreads();
-}
-
-// One unit of the panel step at column k0 (role 0: diagonal block and
-// right-hand side; roles 1..nchunk: 256 rows of L21; the rest: 256 columns of
-// U12).  Every unit factors the diagonal block itself, from the unmodified
-// band, so units need no ordering among themselves.
-__device__ void lu_panel_unit(double *__restrict__ AB, int n, int w, int k0, int role,
-                              double *__restrict__ diag, double *__restrict__ bint, DevStatus *st,
-                              double *D) {
-  const int ld = 2 * w + 1;
-  const int kb = min(kLU, n - k0);
-  const int r0 = k0 + kb;
-  const int nr = max(0, min(n, k0 + kb + w) - r0);  // rows of L21 / columns of U12
-  const int nchunk = (nr + 255) / 256;
-  const int tid = threadIdx.x;
-  // Each workgroup loads its row / column of the panel before factoring the
-  // diagonal block, so the loads overlap the factorisation.
-  double v[kLU];
-  int idx = -1;
-  if (role >= 1 && role <= nchunk) {
-    const int i = r0 + (role - 1) * 256 + tid;
-    if (i < r0 + nr) idx = i;
+  // W = A21 L11^{-T}: lane supplies A[l%16][k] and B[k][l%16] = L11^{-1}[l%16][k]
+  {
+    double bl[4];
 #pragma unroll
-    for (int c = 0; c < kLU; ++c) {
-      const int j = k0 + c;
-      v[c] = (idx >= 0 && c < kb && idx - j <= w) ? AB[(size_t)j * ld + (w + idx - j)] : 0.0;
+    for (int s = 0; s < 4; ++s) bl[s] = Li[lr * (kLB + 1) + 4 * s + lk];
+    typename M::v4 wi = {0.0, 0.0, 0.0, 0.0}, wj = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      wi = M::mma(ai[s], bl[s], wi);
+      wj = M::mma(aj[s], bl[s], wj);
     }
-  } else if (role > nchunk) {
-    const int j = r0 + (role - 1 - nchunk) * 256 + tid;
-    if (j < r0 + nr) idx = j;
 #pragma unroll
-    for (int r = 0; r < kLU; ++r) {
-      const int i = k0 + r;
-      v[r] = (idx >= 0 && r < kb && idx - i <= w) ? AB[(size_t)idx * ld + (w + i - idx)] : 0.0;
+    for (int v = 0; v < 4; ++v) {
+      Wi[(16 * wave + M::crow(v, lane)) * (kLB + 1) + lr] = wi[v];
+      Wj[(16 * wave + M::crow(v, lane)) * (kLB + 1) + lr] = wj[v];
     }
   }
-  lu_diag_block(AB, ld, w, k0, kb, D, st);
-  if (role == 0) {
-    for (int e = tid; e < kb * kb; e += blockDim.x) {
-      const int r = e / kb, c = e % kb;
-      diag[r * kLU + c] = D[r * (kLU + 1) + c];
-    }
-    if (tid == 0) {
-      // y1 = L11^{-1} b1 (unit lower)
-      for (int r = 0; r < kb; ++r) {
-        double sum = bint[k0 + r];
-        for (int p = 0; p < r; ++p) sum -= D[r * (kLU + 1) + p] * bint[k0 + p];
-        bint[k0 + r] = sum;
+  __syncthreads();
+  // C -= (W_i D^{-1}) W_j^T.  In the tile holding the next diagonal block,
+  // wave 0 finishes that block's columns first and factors it before the
+  // rest of its row: it is the critical path from one step to the next.
+  const bool has_next = ti == 0 && tj == 0;
+  double a[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = 4 * s + lk;
+    a[s] = Wi[(16 * wave + lr) * (kLB + 1) + k] * Dq[k];
+  }
+  auto update_store = [&](int tc) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c[tc] = M::mma(-a[s], Wj[(16 * tc + lr) * (kLB + 1) + 4 * s + lk], c[tc]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + 16 * wave + M::crow(v, lane), j = j0 + 16 * tc + lr;
+      const bool ok = i < r0 + nr && j < r0 + nr && i >= j && i - j <= w;
+      if (has_next && wave == 0 && tc == 0) {
+        // the next diagonal block goes to LDS for its factorisation
+        Dn[(i - r0) * (kLB + 1) + (j - r0)] = ok ? c[tc][v] : 0.0;
+      } else if (ok) {
+        AB[(size_t)j * ld + (w + i - j)] = c[tc][v];
       }
     }
-    return;
-  }
-  if (idx < 0) return;
-  if (role <= nchunk) {
-    trsm_row_upper<0>(v, D, kb);
-#pragma unroll
-    for (int c = 0; c < kLU; ++c) {
-      const int j = k0 + c;
-      if (c < kb && idx - j <= w) AB[(size_t)j * ld + (w + idx - j)] = v[c];
-    }
+  };
+  if (has_next && wave == 0) {
+    update_store(0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int kb = min(kLB, n - r0);
+    if (ldl_diag16(Dn, kb, lane, AB, w, r0, inv_next) && lane == 0) set_status(st, -5, r0, 0.0);
+    update_store(1);
+    update_store(2);
+    update_store(3);
   } else {
-    trsm_col_lower<0>(v, D, kb);
 #pragma unroll
-    for (int r = 0; r < kLU; ++r) {
-      const int i = k0 + r;
-      if (r < kb && idx - i <= w) AB[(size_t)idx * ld + (w + i - idx)] = v[r];
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_lu_panel(double *__restrict__ AB, int n, int w, int k0,
-                                                  double *__restrict__ diag,
-                                                  double *__restrict__ bint, DevStatus *st) {
-  __shared__ double D[kLU * (kLU + 1)];
-  lu_panel_unit(AB, n, w, k0, blockIdx.x, diag, bint, st, D);
-}
-
-// A22 -= L21 U12 in 64x64 tiles (four waves, each 16 rows x 64 columns).
-// Extra workgroups: one copies the factored diagonal block, the last ones
-// update the right-hand side.
-// One unit of the update step at column k0: units 0..nt*nt-1 are 64x64 tiles
-// of A22 -= L21 U12; unit nt*nt copies the factored diagonal block into the
-// band; the last units update the right-hand side, b2 -= L21 y1.
-__device__ void lu_update_unit(double *__restrict__ AB, int n, int w, int k0, int bid,
-                               const double *__restrict__ diag, double *__restrict__ bint,
-                               double *Ls, double *Us) {
-  using M = Mma<double>;
-  const int ld = 2 * w + 1;
-  const int kb = min(kLU, n - k0);
-  const int r0 = k0 + kb;
-  const int nr = max(0, min(n, k0 + kb + w) - r0);
-  const int nt = (nr + 63) / 64;
-  const int tid = threadIdx.x;
-  if (bid == nt * nt) {
-    for (int e = tid; e < kb * kb; e += blockDim.x) {
-      const int r = e / kb, c = e % kb;
-      if (abs(r - c) <= w) AB[(size_t)(k0 + c) * ld + (w + r - c)] = diag[r * kLU + c];
-    }
-    return;
-  }
-  if (bid > nt * nt) {
-    // b2 -= L21 y1 for rows r0 + chunk*256 + tid
-    const int i = r0 + (bid - nt * nt - 1) * 256 + tid;
-    if (i >= r0 + nr) return;
-    double s = 0.0;
-    for (int c = 0; c < kb; ++c) {
-      const int j = k0 + c;
-      if (i - j <= w) s += AB[(size_t)j * ld + (w + i - j)] * bint[j];
-    }
-    bint[i] -= s;
-    return;
-  }
-  const int ti = bid / nt, tj = bid % nt;
-  const int i0 = r0 + ti * 64, j0 = r0 + tj * 64;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-  // the C tile is fetched first so its latency overlaps the staging below
-  typename M::v4 cacc[4];
+    for (int s = 0; s < 4; ++s) {
 #pragma unroll
-  for (int tc = 0; tc < 4; ++tc) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + wave * 16 + M::crow(v, lane), j = j0 + tc * 16 + lr;
-      const bool ok = i < r0 + nr && j < r0 + nr && (i - j <= w) && (j - i <= w);
-      cacc[tc][v] = ok ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
-    }
-  }
-  // stage L21 tile (64 x kb) and U12 tile (kb x 64)
-  for (int e = tid; e < 64 * kLU; e += 256) {
-    const int r = e % 64, c = e / 64;
-    const int i = i0 + r, j = k0 + c;
-    Ls[r * (kLU + 1) + c] = (c < kb && i < r0 + nr && i - j <= w) ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
-  }
-  for (int e = tid; e < 64 * kLU; e += 256) {
-    const int r = e % kLU, c = e / kLU;
-    const int i = k0 + r, j = j0 + c;
-    Us[r * 65 + c] = (r < kb && j < r0 + nr && j - i <= w) ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int tc = 0; tc < 4; ++tc) {
-    typename M::v4 c = cacc[tc];
-#pragma unroll
-    for (int s = 0; s < kLU / 4; ++s) {
-      const int kk = 4 * s + lk;
-      const double a = Ls[(wave * 16 + lr) * (kLU + 1) + kk];
-      const double b = Us[kk * 65 + tc * 16 + lr];
-      c = M::mma(-a, b, c);
+      for (int tc = 0; tc < 4; ++tc) c[tc] = M::mma(-a[s], Wj[(16 * tc + lr) * (kLB + 1) + 4 * s + lk], c[tc]);
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + wave * 16 + M::crow(v, lane), j = j0 + tc * 16 + lr;
-      const bool ok = i < r0 + nr && j < r0 + nr && (i - j <= w) && (j - i <= w);
-      if (ok) AB[(size_t)j * ld + (w + i - j)] = c[v];
+    for (int tc = 0; tc < 4; ++tc) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 16 * wave + M::crow(v, lane), j = j0 + 16 * tc + lr;
+        const bool ok = i < r0 + nr && j < r0 + nr && i >= j && i - j <= w;
+        if (ok) AB[(size_t)j * ld + (w + i - j)] = c[tc][v];
+      }
     }
   }
-}
-
-__global__ __launch_bounds__(256) void k_lu_update(double *__restrict__ AB, int n, int w, int k0,
-                                                   const double *__restrict__ diag,
-                                                   double *__restrict__ bint) {
-  __shared__ double Ls[64 * (kLU + 1)];
-  __shared__ double Us[kLU * (64 + 1)];
-  lu_update_unit(AB, n, w, k0, blockIdx.x, diag, bint, Ls, Us);
+  // the diagonal tile of each row block stores L21 = W D^{-1} and U12 = W^T
+  if (ti == tj) {
+    for (int e = tid; e < 64 * kLB; e += 256) {
+      const int rr = e / kLB, cc = e % kLB;
+      const int i = i0 + rr, j = k0 + cc;
+      if (i < r0 + nr && i - j <= w) {
+        const double wv = Wi[rr * (kLB + 1) + cc];
+        AB[(size_t)j * ld + (w + i - j)] = wv * Dq[cc];
+        AB[(size_t)i * ld + (w + j - i)] = wv;
+      }
+    }
+  }
 }
 
 // Triangular sweeps with the band factors, one workgroup of 1024 lanes.
 // lower: L y = b (unit lower), forward.  upper: U x = y, backward.  In place.
-// Per block of kSW unknowns, wave 0 solves the diagonal block (one row per
-// lane, broadcasts between lanes) while the other waves apply the block to
-// the rows it couples to (one row per lane; beyond 960 rows a slower loop).
-// The active part of x lives in an LDS ring of RW >= w + 2 kSW entries; the
-// band entries of the next block and the x entries that enter the ring next
-// are fetched one block ahead, so no global access sits on the critical path.
-constexpr int kSW = 16;
-
-template <int C>
-__device__ __forceinline__ void sweep_upper_step(const double (&u)[kSW], double &xv, int lane, int kb) {
-  constexpr int c = kSW - 1 - C;
-  if (c < kb) {
-    const double dc = lane_bcast(u[c], c);
-    const double xc = lane_bcast(xv, c) / dc;
-    if (lane == c) xv = xc;
-    if (lane < c) xv -= u[c] * xc;
-  }
-  if constexpr (C + 1 < kSW) sweep_upper_step<C + 1>(u, xv, lane, kb);
-}
-
-template <int C>
-__device__ __forceinline__ void sweep_lower_step(const double (&u)[kSW], double &xv, int lane, int kb) {
-  if (C < kb) {
-    const double xc = lane_bcast(xv, C);
-    if (lane > C) xv -= u[C] * xc;
-  }
-  if constexpr (C + 1 < kSW) sweep_lower_step<C + 1>(u, xv, lane, kb);
-}
+// Per block of kSW = 16 unknowns, wave 0 solves the diagonal block as a
+// product with its stored inverse -- L11^{-1} forward, U11^{-1} = L11^{-T} D^{-1}
+// backward -- while the other waves apply the block to the rows it couples
+// to (one row per lane; beyond 960 rows a slower loop).  The active part of x
+// lives in an LDS ring of RW >= w + 2 kSW entries; the band entries and
+// inverse of the next block and the x entries that enter the ring next are
+// fetched one block ahead, so no global access sits on the critical path.
+constexpr int kSW = kLB;
 
 constexpr int kSweepThreads = 1024;
 
-__global__ __launch_bounds__(kSweepThreads) void k_lu_sweep(const double *__restrict__ AB, int n,
+__global__ __launch_bounds__(kSweepThreads) void k_lu_sweep(const double *__restrict__ AB,
+                                                            const double *__restrict__ inv, int n,
                                                             int w, double *__restrict__ x, int upper,
                                                             int RW) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -355,18 +340,30 @@ __global__ __launch_bounds__(kSweepThreads) void k_lu_sweep(const double *__rest
   const int tid = threadIdx.x;
   const int nblk = (n + kSW - 1) / kSW;
   const int nprop = kSweepThreads - 64;
-  double cur[kSW], nxt[kSW];
+  // band entries of one block (diagonal-block inverse for wave 0; entry kSW
+  // carries wave 0's 1/D_r)
+  double cur[kSW + 1], nxt[kSW + 1];
   double xin_cur = 0.0, xin_nxt = 0.0;  // entering x value (threads 64..64+kSW-1)
   // rows the block at k0 updates: [lo, hi)
   auto prop_lo = [&](int k0, int kb) { return upper ? max(0, k0 - w) : k0 + kb; };
   auto prop_hi = [&](int k0, int kb) { return upper ? k0 : min(n, k0 + kb + w); };
-  auto fetch = [&](int blk, double (&dst)[kSW]) {
+  auto fetch = [&](int blk, double (&dst)[kSW + 1]) {
+    dst[kSW] = 0.0;
     const int k0 = blk * kSW;
     const int kb = min(kSW, n - k0);
     if (tid < 64) {
+      // row tid of the diagonal block's inverse: lower L11^{-1}, upper
+      // L11^{-T} (applied to D^{-1} times the block, with 1/D_r in dst[kSW]);
+      // rows and columns past the matrix are zero.  Nothing is computed on
+      // the loaded values here, so the loads stay in flight.
+      const double *iv = inv + (size_t)blk * kInvStride;
+      const int r = tid & 15;
 #pragma unroll
-      for (int c = 0; c < kSW; ++c)
-        dst[c] = (tid < kb && c < kb && abs(tid - c) <= w) ? AB[(size_t)(k0 + c) * ld + (w + tid - c)] : 0.0;
+      for (int c = 0; c < kSW; ++c) {
+        const bool in = r < kb && c < kb;
+        dst[c] = !in ? 0.0 : (upper ? iv[c * kLB + r] : iv[r * kLB + c]);
+      }
+      dst[kSW] = (upper && r < kb) ? iv[kLB * kLB + r] : 0.0;
     } else {
       const int i = prop_lo(k0, kb) + (tid - 64);
       const bool ok = i < prop_hi(k0, kb);
@@ -417,7 +414,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_lu_sweep(const double *__rest
   fetch(upper ? nblk - 1 : 0, cur);
   if (nblk > 1) xin_nxt = fetch_x(upper ? nblk - 2 : 1);
   __syncthreads();
-  auto body = [&](int s, double (&cu)[kSW], double (&nx)[kSW]) {
+  auto body = [&](int s, double (&cu)[kSW + 1], double (&nx)[kSW + 1]) {
     const int blk = upper ? (nblk - 1 - s) : s;
     const int k0 = blk * kSW;
     const int kb = min(kSW, n - k0);
@@ -427,9 +424,15 @@ __global__ __launch_bounds__(kSweepThreads) void k_lu_sweep(const double *__rest
     if (s + 2 < nblk) xin_nxt = fetch_x(upper ? blk - 2 : blk + 2);
     if (tid < 64) {
       const int lane = tid;
-      double xv = (lane < kb) ? xr[(k0 + lane) % RW] : 0.0;
-      if (upper) sweep_upper_step<0>(cu, xv, lane, kb);
-      else sweep_lower_step<0>(cu, xv, lane, kb);
+      double xo = (lane < kb) ? xr[(k0 + lane) % RW] : 0.0;
+      if (upper) xo *= cu[kSW];
+      double xv = 0.0, xw = 0.0;
+#pragma unroll
+      for (int c = 0; c < kSW; c += 2) {
+        xv += cu[c] * row_bcast(xo, c);
+        xw += cu[c + 1] * row_bcast(xo, c + 1);
+      }
+      xv += xw;
       if (lane < kb) {
         xb[lane] = xv;
         x[k0 + lane] = xv;
@@ -464,17 +467,119 @@ __global__ __launch_bounds__(kSweepThreads) void k_lu_sweep(const double *__rest
   }
 }
 
+// Sweeps for systems whose right-hand side fits in LDS (n <= kSweepLdsMax):
+// the whole vector stays in LDS, so no ring bookkeeping sits in the loop.
+// Band loads are unconditional at clamped addresses with a validity mask
+// applied at use, so nothing stops them from staying in flight while the
+// previous block computes (a load under a branch makes the compiler wait for
+// every outstanding load before the loop goes on).
+constexpr int kSweepLdsMax = 14336;
+
+template <int UPPER>
+__global__ __launch_bounds__(kSweepThreads) void k_band_sweep(const double *__restrict__ AB,
+                                                              const double *__restrict__ inv, int n,
+                                                              int w, double *__restrict__ x) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *xs = reinterpret_cast<double *>(smem_raw);
+  const int ld = 2 * w + 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nblk = (n + kSW - 1) / kSW;
+  const int q = tid - 64;  // propagation row offset of threads 64..
+  for (int i = tid; i < n; i += kSweepThreads) xs[i] = x[i];
+  // rows a block updates: lower [k0+kb, k0+kb+w), upper [k0-w, k0)
+  auto fetch = [&](int blk, double (&dst)[kSW + 1], unsigned &mask) {
+    const int k0 = blk * kSW;
+    const int kb = min(kSW, n - k0);
+    mask = 0u;
+    if (tid < 64) {
+      // diagonal-block inverse, row r (identity past the matrix): lower
+      // L11^{-1}, upper L11^{-T} with 1/D_r in dst[kSW]
+      const double *iv = inv + (size_t)blk * kInvStride;
+      const int r = tid & 15;
+#pragma unroll
+      for (int c = 0; c < kSW; ++c) dst[c] = UPPER ? iv[c * kLB + r] : iv[r * kLB + c];
+      dst[kSW] = iv[kLB * kLB + r];
+    } else {
+      const int i = UPPER ? k0 - w + q : k0 + kb + q;
+      const bool row_ok = UPPER ? (i >= 0 && i < k0) : (i < min(n, k0 + kb + w));
+#pragma unroll
+      for (int c = 0; c < kSW; ++c) {
+        const int j = k0 + c;
+        const int off = UPPER ? (j - i) : (i - j);
+        const bool in = row_ok && c < kb && off <= w;
+        const long long e = in ? (long long)j * ld + (w + i - j) : 0;
+        dst[c] = AB[e];
+        mask |= in ? (1u << c) : 0u;
+      }
+      dst[kSW] = 0.0;
+    }
+  };
+  double cu[kSW + 1], nx[kSW + 1];
+  unsigned mcu = 0u, mnx = 0u;
+  fetch(UPPER ? nblk - 1 : 0, cu, mcu);
+  __syncthreads();
+  auto body = [&](int s, double (&c0)[kSW + 1], unsigned m0, double (&c1)[kSW + 1], unsigned &m1) {
+    const int blk = UPPER ? (nblk - 1 - s) : s;
+    const int k0 = blk * kSW;
+    const int kb = min(kSW, n - k0);
+    if (s + 1 < nblk) fetch(UPPER ? blk - 1 : blk + 1, c1, m1);
+    if (tid < 64) {
+      double xo = (lane < kb) ? xs[k0 + lane] : 0.0;
+      if (UPPER) xo *= c0[kSW];
+      double xv = 0.0, xw = 0.0;
+#pragma unroll
+      for (int c = 0; c < kSW; c += 2) {
+        xv += c0[c] * row_bcast(xo, c);
+        xw += c0[c + 1] * row_bcast(xo, c + 1);
+      }
+      if (lane < kb) xs[k0 + lane] = xv + xw;
+    }
+    __syncthreads();
+    if (tid >= 64) {
+      const int i = UPPER ? k0 - w + q : k0 + kb + q;
+      if (m0) {
+        double acc = 0.0, acd = 0.0;
+#pragma unroll
+        for (int c = 0; c < kSW; c += 2) {
+          acc += ((m0 >> c) & 1u ? c0[c] : 0.0) * xs[k0 + c];
+          acd += ((m0 >> (c + 1)) & 1u ? c0[c + 1] : 0.0) * xs[k0 + c + 1];
+        }
+        xs[i] -= acc + acd;
+      }
+      // rows beyond the threads' reach (w > kSweepThreads - 64)
+      const int lo = UPPER ? max(0, k0 - w) : k0 + kb;
+      const int hi = UPPER ? k0 : min(n, k0 + kb + w);
+      for (int i2 = (UPPER ? k0 - w : k0 + kb) + q + (kSweepThreads - 64); i2 < hi; i2 += kSweepThreads - 64) {
+        if (i2 < lo) continue;
+        double acc = 0.0;
+        for (int c = 0; c < kb; ++c) {
+          const int j = k0 + c;
+          if (UPPER ? (j - i2 <= w) : (i2 - j <= w)) acc += AB[(size_t)j * ld + (w + i2 - j)] * xs[j];
+        }
+        xs[i2] -= acc;
+      }
+    }
+    __syncthreads();
+  };
+  for (int s = 0; s < nblk; s += 2) {
+    body(s, cu, mcu, nx, mnx);
+    if (s + 1 < nblk) body(s + 1, nx, mnx, cu, mcu);
+  }
+  for (int i = tid; i < n; i += kSweepThreads) x[i] = xs[i];
+}
+
 // r = b - A x with the unfactored band (one thread per row).
 __global__ void k_band_residual(const double *__restrict__ AB, int n, int w,
                                 const double *__restrict__ x, const double *__restrict__ b,
-                                double *__restrict__ r) {
+                                double *__restrict__ r, int flip) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int ld = 2 * w + 1;
   double acc = 0.0;
   const int jlo = max(0, i - w), jhi = min(n - 1, i + w);
   for (int j = jlo; j <= jhi; ++j) acc += AB[(size_t)j * ld + (w + i - j)] * x[j];
-  r[i] = b[i] - acc;
+  // flip: the residual of the symmetric form, diag(s) (b - A x)
+  r[i] = (flip && !(i & 1)) ? acc - b[i] : b[i] - acc;
 }
 
 // Permutation between the natural order (pi^p then pi^u) and the band order.
@@ -623,34 +728,47 @@ hipError_t launch_iface_scatter(const Geom &g, int n_sub, const int *patches, co
   return hipGetLastError();
 }
 
-hipError_t launch_band_lu(double *AB, int n, int w, double *diag, double *b, DevStatus *st,
-                          hipStream_t s) {
-  for (int k0 = 0; k0 < n; k0 += kLU) {
-    const int kb = std::min(kLU, n - k0);
-    const int nr = std::max(0, std::min(n, k0 + kb + w) - (k0 + kb));
-    const int nchunk = (nr + 255) / 256;
+size_t ldl_inv_size(int n) { return (size_t)((n + kLB - 1) / kLB) * kInvStride; }
+
+hipError_t launch_band_ldl(const double *AB0, double *AB, const double *b0, double *b, int n, int w,
+                           double *inv, DevStatus *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_flip_copy, dim3(1024), dim3(256), 0, s, AB0, AB, b0, b, n, w);
+  hipLaunchKernelGGL(k_ldl_first, dim3(1), dim3(64), 0, s, AB, n, w, inv, st);
+  for (int k0 = 0; k0 + kLB < n; k0 += kLB) {
+    const int nr = std::min(n, k0 + kLB + w) - (k0 + kLB);
     const int nt = (nr + 63) / 64;
-    hipLaunchKernelGGL(k_lu_panel, dim3(1 + 2 * nchunk), dim3(256), 0, s, AB, n, w, k0, diag, b, st);
-    hipLaunchKernelGGL(k_lu_update, dim3(nt * nt + 1 + nchunk), dim3(256), 0, s, AB, n, w, k0, diag,
-                       b);
+    hipLaunchKernelGGL(k_ldl_step, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, AB, n, w, k0,
+                       inv + (size_t)(k0 / kLB) * kInvStride, inv + (size_t)(k0 / kLB + 1) * kInvStride, st);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_lu_sweep(const double *AB, int n, int w, double *x, int upper, hipStream_t s) {
+hipError_t launch_lu_sweep(const double *AB, const double *inv, int n, int w, double *x, int upper,
+                           hipStream_t s) {
+  if (n <= kSweepLdsMax) {
+    const size_t lds = (size_t)n * sizeof(double);
+    const void *k = upper ? (const void *)k_band_sweep<1> : (const void *)k_band_sweep<0>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (upper)
+      hipLaunchKernelGGL(k_band_sweep<1>, dim3(1), dim3(kSweepThreads), lds, s, AB, inv, n, w, x);
+    else
+      hipLaunchKernelGGL(k_band_sweep<0>, dim3(1), dim3(kSweepThreads), lds, s, AB, inv, n, w, x);
+    return hipGetLastError();
+  }
   const int RW = w + 2 * kSW + 1;
   const size_t lds = (size_t)RW * sizeof(double);
   if (lds > 150 * 1024) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute((const void *)k_lu_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lu_sweep, dim3(1), dim3(kSweepThreads), lds, s, AB, n, w, x, upper, RW);
+  hipLaunchKernelGGL(k_lu_sweep, dim3(1), dim3(kSweepThreads), lds, s, AB, inv, n, w, x, upper, RW);
   return hipGetLastError();
 }
 
 hipError_t launch_band_residual(const double *AB, int n, int w, const double *x, const double *b,
-                                double *r, hipStream_t s) {
-  hipLaunchKernelGGL(k_band_residual, dim3(grid_for(n)), dim3(256), 0, s, AB, n, w, x, b, r);
+                                double *r, int flip, hipStream_t s) {
+  hipLaunchKernelGGL(k_band_residual, dim3(grid_for(n)), dim3(256), 0, s, AB, n, w, x, b, r, flip);
   return hipGetLastError();
 }
 

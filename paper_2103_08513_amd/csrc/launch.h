@@ -36,11 +36,13 @@ hipError_t launch_copy(const double *a, double *b, long long n, hipStream_t s);
 hipError_t launch_iface_scatter(const Geom &g, int n_sub, const int *patches, const int *pos,
                                 const double *F, const double *Fb, const double *SAb, double *AB,
                                 int w, double *b, hipStream_t s);
-hipError_t launch_band_lu(double *AB, int n, int w, double *diag, double *b, DevStatus *st,
-                          hipStream_t s);
-hipError_t launch_lu_sweep(const double *AB, int n, int w, double *x, int upper, hipStream_t s);
+size_t ldl_inv_size(int n);
+hipError_t launch_band_ldl(const double *AB0, double *AB, const double *b0, double *b, int n, int w,
+                           double *inv, DevStatus *st, hipStream_t s);
+hipError_t launch_lu_sweep(const double *AB, const double *inv, int n, int w, double *x, int upper,
+                           hipStream_t s);
 hipError_t launch_band_residual(const double *AB, int n, int w, const double *x, const double *b,
-                                double *r, hipStream_t s);
+                                double *r, int flip, hipStream_t s);
 hipError_t launch_perm(const double *src, const int *pos, int nv, double *dst, int to_natural,
                        hipStream_t s);
 hipError_t launch_norm2(const double *v, int n, double *out, hipStream_t s);

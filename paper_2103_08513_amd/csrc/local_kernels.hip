@@ -621,8 +621,24 @@ __global__ __launch_bounds__(256, 2) void k_factor32(const SubDesc *__restrict__
 constexpr int kLReg = 12;   // L entries per thread and panel: 16*(b+1) <= 256*kLReg
 constexpr int kMaxChunk = 48;
 
-template <typename T, int mode>
-__global__ __launch_bounds__(256) void k_solve(Geom g, const int4 *__restrict__ work,
+// Four independent 16x16x4 MFMAs summed: a 16x16x16 product without a
+// dependent chain (a[s], b[s] are the operands of k-step s).
+template <typename T>
+__device__ __forceinline__ typename Mma<T>::v4 mma16_split(const T (&a)[4], const T (&b)[4],
+                                                          typename Mma<T>::v4 c) {
+  using M = Mma<T>;
+  const typename M::v4 z = {T(0), T(0), T(0), T(0)};
+  typename M::v4 p1 = M::mma(a[1], b[1], z);
+  typename M::v4 p2 = M::mma(a[2], b[2], z);
+  typename M::v4 p3 = M::mma(a[3], b[3], z);
+  c = M::mma(a[0], b[0], c);
+  return (c + p1) + (p2 + p3);
+}
+
+// NBT: most R2-update tiles per wave; KS: k-steps of the backward L21^T
+// product (4*KS >= the largest band).
+template <typename T, int mode, int NBT, int KS>
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_solve(Geom g, const int4 *__restrict__ work,
                                                const double *__restrict__ scal,
                                                const T *__restrict__ Lg, const T *__restrict__ Dg,
                                                double *Bg, double *Xg, int scaled, int ldb, int wmax) {
@@ -649,15 +665,22 @@ __global__ __launch_bounds__(256) void k_solve(Geom g, const int4 *__restrict__ 
   const int nP = (N + kNB - 1) / kNB;
   const int lcnt = kNB * bp1;
 
+  // the next panel of L and its diagonal-block inverse, loaded without any
+  // arithmetic or branch on the loaded values (a validity mask is applied
+  // when they are stored) so that the loads stay in flight
   T lreg[kLReg];
   T dreg;
+  unsigned lok = 0u;
   auto fetch_panel = [&](int p) {
     const size_t base = (size_t)p * kNB * bp1;
     const int ncol = min(kNB, N - p * kNB);
+    lok = 0u;
 #pragma unroll
     for (int i = 0; i < kLReg; ++i) {
       const int e = tid + 256 * i;
-      lreg[i] = (e < lcnt && e / bp1 < ncol) ? L[base + e] : T(0);
+      const bool ok = e < lcnt && e / bp1 < ncol;
+      lreg[i] = L[base + (ok ? e : 0)];
+      lok |= ok ? (1u << i) : 0u;
     }
     dreg = Dinv[(size_t)p * kNB * kNB + tid];
   };
@@ -666,31 +689,35 @@ __global__ __launch_bounds__(256) void k_solve(Geom g, const int4 *__restrict__ 
 #pragma unroll
     for (int i = 0; i < kLReg; ++i) {
       const int e = tid + 256 * i;
-      if (e < lcnt) lp[(e / bp1) * ldb + e % bp1] = lreg[i];
+      if (e < lcnt) lp[(e / bp1) * ldb + e % bp1] = ((lok >> i) & 1u) ? lreg[i] : T(0);
     }
     Dp[buf * kNB * kNB + tid] = dreg;
   };
-  // rows of B (scaled) for the forward sweep: 16 rows x CP columns, 3 per thread
+  // rows of B for the forward sweep: 16 rows x CP columns, 3 per thread.
+  // The raw values and their scale factors are held as loaded (any
+  // arithmetic on them here would wait for the loads); they are combined
+  // when stored, one panel later.
   constexpr int kRReg = (kNB * kMaxChunk) / 256;
-  T rreg[kRReg];
+  double rraw[kRReg], rsc[kRReg];
+  unsigned rok = 0u;
   auto fetch_rows = [&](int r0) {
+    rok = 0u;
 #pragma unroll
     for (int i = 0; i < kRReg; ++i) {
       const int e = tid + 256 * i;
       const int rr = r0 + e / CP, c = e % CP;
-      T v = T(0);
-      if (e < kNB * CP && rr < N && c < cw) {
-        const double s = scaled ? sc[rr] : 1.0;
-        v = T(s * B[(size_t)rr * m + c0 + c]);
-      }
-      rreg[i] = v;
+      const bool ok = e < kNB * CP && rr < N && c < cw;
+      const int rrc = ok ? rr : 0;
+      rraw[i] = B[(size_t)rrc * m + (ok ? c0 + c : 0)];
+      rsc[i] = scaled ? sc[rrc] : 1.0;
+      rok |= ok ? (1u << i) : 0u;
     }
   };
   auto store_rows = [&](int r0, int sk0) {
 #pragma unroll
     for (int i = 0; i < kRReg; ++i) {
       const int e = tid + 256 * i;
-      if (e < kNB * CP) Y[wrap(sk0 + e / CP, W) * CP + e % CP] = rreg[i];
+      if (e < kNB * CP) Y[wrap(sk0 + e / CP, W) * CP + e % CP] = ((rok >> i) & 1u) ? T(rsc[i] * rraw[i]) : T(0);
     }
   };
 
@@ -728,13 +755,14 @@ __global__ __launch_bounds__(256) void k_solve(Geom g, const int4 *__restrict__ 
     // Y1 = inv(L11) R1
     typename M::v4 acc = {0, 0, 0, 0};
     if (wave < nct) {
+      T a[4], bb[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int jj = 4 * s + lk;
-        const T a = dp[lr * kNB + jj];
-        const T bb = Y[wrap(sk + jj, W) * CP + wave * 16 + lr];
-        acc = M::mma(a, bb, acc);
+        a[s] = dp[lr * kNB + jj];
+        bb[s] = Y[wrap(sk + jj, W) * CP + wave * 16 + lr];
       }
+      acc = mma16_split<T>(a, bb, acc);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = M::crow(v, lane), col = wave * 16 + lr;
@@ -743,29 +771,47 @@ __global__ __launch_bounds__(256) void k_solve(Geom g, const int4 *__restrict__ 
       }
     }
     __syncthreads();
-    // R2 -= L21 Y1
+    // R2 -= L21 Y1: this wave's tiles (wave, wave+4, ...) with their MFMA
+    // chains interleaved and all operands loaded first
     if (k + kb < N) {
       const int nrt = (b + 15) >> 4;
-      for (int tile = wave; tile < nrt * nct; tile += 4) {
-        const int ti = tile / nct, ct = tile % nct;
-        typename M::v4 c;
+      const int ntile = nrt * nct;
+      const int cnt_all = (ntile - wave + 3) >> 2;
+      for (int t0 = 0; t0 < cnt_all; t0 += NBT) {
+        const int cnt = min(NBT, cnt_all - t0);
+        int ti[NBT], ct[NBT];
+        typename M::v4 c[NBT];
+        T a[NBT][4], bb[NBT][4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int ii = ti * 16 + M::crow(v, lane);
-          c[v] = (ii < b) ? Y[wrap(sk + kNB + ii, W) * CP + ct * 16 + lr] : T(0);
+        for (int t = 0; t < NBT; ++t) {
+          const int tile = wave + 4 * (t0 + (t < cnt ? t : 0));
+          ti[t] = tile / nct;
+          ct[t] = tile % nct;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ii = ti[t] * 16 + M::crow(v, lane);
+            c[t][v] = Y[wrap(sk + kNB + min(ii, b - 1), W) * CP + ct[t] * 16 + lr];
+          }
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2) {
+            const int jj = 4 * s2 + lk;
+            a[t][s2] = lp[jj * ldb + (kNB + ti[t] * 16 + lr - jj)];
+            bb[t][s2] = Zs[jj * CP + ct[t] * 16 + lr];
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+#pragma unroll
+          for (int t = 0; t < NBT; ++t) c[t] = M::mma(-a[t][s2], bb[t][s2], c[t]);
         }
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int jj = 4 * s + lk;
-          const int ta = kNB + ti * 16 + lr - jj;
-          const T a = lp[jj * ldb + ta];
-          const T bb = Zs[jj * CP + ct * 16 + lr];
-          c = M::mma(-a, bb, c);
-        }
+        for (int t = 0; t < NBT; ++t) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int ii = ti * 16 + M::crow(v, lane);
-          if (ii < b) Y[wrap(sk + kNB + ii, W) * CP + ct * 16 + lr] = c[v];
+          for (int v = 0; v < 4; ++v) {
+            const int ii = ti[t] * 16 + M::crow(v, lane);
+            if (t < cnt && ii < b) Y[wrap(sk + kNB + ii, W) * CP + ct[t] * 16 + lr] = c[t][v];
+          }
         }
       }
     }
@@ -778,14 +824,20 @@ __global__ __launch_bounds__(256) void k_solve(Geom g, const int4 *__restrict__ 
 
   // ------------------------------ backward ------------------------------
   for (int e = tid; e < W * CP; e += 256) Y[e] = T(0);
-  typename M::v4 yreg = {0, 0, 0, 0};
+  // B rows of the next panel for the backward sweep, as loaded (FP64) with a
+  // validity mask applied at use
+  double yraw[4] = {0.0, 0.0, 0.0, 0.0};
+  unsigned yok = 0u;
   auto fetch_y = [&](int p) {
     const int k = p * kNB;
+    yok = 0u;
     if (wave < nct) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = M::crow(v, lane), col = wave * 16 + lr;
-        yreg[v] = (k + row < N && col < cw) ? T(B[(size_t)(k + row) * m + c0 + col]) : T(0);
+        const bool ok = k + row < N && col < cw;
+        yraw[v] = B[(size_t)(ok ? k + row : 0) * m + (ok ? c0 + col : 0)];
+        yok |= ok ? (1u << v) : 0u;
       }
     }
   };
@@ -800,20 +852,35 @@ __global__ __launch_bounds__(256) void k_solve(Geom g, const int4 *__restrict__ 
     const int sk = k % W;
     const T *lp = Lp + cur * kNB * ldb;
     const T *dp = Dp + cur * kNB * kNB;
-    typename M::v4 c = yreg;
+    typename M::v4 c;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[v] = ((yok >> v) & 1u) ? T(yraw[v]) : T(0);
     if (p > 0) {
       fetch_panel(p - 1);
       fetch_y(p - 1);
     }
-    // Z = Y1 - L21^T X2
+    // Z = Y1 - L21^T X2 over K = b, as four independent MFMA chains
     if (wave < nct) {
-      const int ks = (b + 3) >> 2;
-      for (int s = 0; s < ks; ++s) {
-        const int t = 4 * s + lk;
-        const T a = lp[lr * ldb + (kNB + t - lr)];
-        const T bb = (t < b) ? Y[wrap(sk + kNB + t, W) * CP + wave * 16 + lr] : T(0);
-        c = M::mma(-a, bb, c);
+      T a[KS], bb[KS];
+#pragma unroll
+      for (int s2 = 0; s2 < KS; ++s2) {
+        const int t = 4 * s2 + lk;
+        // offsets clamped into the panel row; entries past the band meet a
+        // zero operand
+        a[s2] = lp[lr * ldb + (kNB + min(t, b - 1) - lr)];
+        bb[s2] = (t < b) ? Y[wrap(sk + kNB + min(t, b - 1), W) * CP + wave * 16 + lr] : T(0);
       }
+      __builtin_amdgcn_sched_barrier(0);
+      const typename M::v4 z = {T(0), T(0), T(0), T(0)};
+      typename M::v4 p1 = z, p2 = z, p3 = z;
+#pragma unroll
+      for (int s2 = 0; s2 < KS; s2 += 4) {
+        c = M::mma(-a[s2], bb[s2], c);
+        if (s2 + 1 < KS) p1 = M::mma(-a[s2 + 1], bb[s2 + 1], p1);
+        if (s2 + 2 < KS) p2 = M::mma(-a[s2 + 2], bb[s2 + 2], p2);
+        if (s2 + 3 < KS) p3 = M::mma(-a[s2 + 3], bb[s2 + 3], p3);
+      }
+      c = (c + p1) + (p2 + p3);
 #pragma unroll
       for (int v = 0; v < 4; ++v) Zs[M::crow(v, lane) * CP + wave * 16 + lr] = c[v];
     }
@@ -821,13 +888,14 @@ __global__ __launch_bounds__(256) void k_solve(Geom g, const int4 *__restrict__ 
     // X1 = inv(L11)^T Z
     if (wave < nct) {
       typename M::v4 acc = {0, 0, 0, 0};
+      T a[4], bb[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int jj = 4 * s + lk;
-        const T a = dp[jj * kNB + lr];
-        const T bb = Zs[jj * CP + wave * 16 + lr];
-        acc = M::mma(a, bb, acc);
+        a[s] = dp[jj * kNB + lr];
+        bb[s] = Zs[jj * CP + wave * 16 + lr];
       }
+      acc = mma16_split<T>(a, bb, acc);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = M::crow(v, lane), col = wave * 16 + lr;
@@ -1057,17 +1125,35 @@ hipError_t launch_factor(int fp32, const SubDesc *subs, const int *order, int n_
                          (double *)L, (double *)Dg, st, bmax, s);
 }
 
-template <typename T, int mode>
+template <typename T, int mode, int NBT, int KS>
 static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, const double *scal,
                                  const T *L, const T *Dg, double *B, double *X, int bmax, int scaled,
                                  hipStream_t s) {
   const size_t lds = solve_lds_bytes(sizeof(T) == 4, bmax, 0);
-  hipError_t e = hipFuncSetAttribute((const void *)k_solve<T, mode>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_solve<T, mode, NBT, KS>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_solve<T, mode>), dim3(n_work), dim3(256), lds, s, g, work, scal, L, Dg, B, X,
-                     scaled, solve_ldb(bmax), bmax + kNB);
+  hipLaunchKernelGGL((k_solve<T, mode, NBT, KS>), dim3(n_work), dim3(256), lds, s, g, work, scal, L, Dg, B,
+                     X, scaled, solve_ldb(bmax), bmax + kNB);
   return hipGetLastError();
+}
+
+// NBT: tiles per MFMA batch -- all of a wave's tiles in FP64 (one workgroup
+// per CU: registers are plentiful), three in FP32 (two workgroups per CU);
+// KS = ceil(b/4) for the largest band of the precision.
+template <typename T, int mode>
+static hipError_t launch_solve_m(const Geom &g, const int4 *work, int n_work, const double *scal,
+                                 const T *L, const T *Dg, double *B, double *X, int bmax, hipStream_t s) {
+  constexpr int nct = kMaxChunk / 16;
+  constexpr bool f32 = sizeof(T) == 4;
+  if (bmax <= 112) {
+    constexpr int nrt = 7;
+    constexpr int nbt = f32 ? 3 : (nrt * nct + 3) / 4;
+    return launch_solve_t<T, mode, nbt, 28>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s);
+  }
+  constexpr int nrt = (kMaxBand32 + 15) / 16;
+  constexpr int nbt = f32 ? 3 : (nrt * nct + 3) / 4;
+  return launch_solve_t<T, mode, nbt, (kMaxBand32 + 3) / 4>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s);
 }
 
 hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, const double *scal,
@@ -1077,16 +1163,12 @@ hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, c
   // from the refinement corrections
   if (fp32) {
     if (mode == 0)
-      return launch_solve_t<float, 0>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax,
-                                      1, s);
-    return launch_solve_t<float, 1>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax, 1,
-                                    s);
+      return launch_solve_m<float, 0>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax, s);
+    return launch_solve_m<float, 1>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax, s);
   }
   if (mode == 0)
-    return launch_solve_t<double, 0>(g, work, n_work, scal, (const double *)L, (const double *)Dg, B, X, bmax,
-                                     1, s);
-  return launch_solve_t<double, 1>(g, work, n_work, scal, (const double *)L, (const double *)Dg, B, X, bmax,
-                                   1, s);
+    return launch_solve_m<double, 0>(g, work, n_work, scal, (const double *)L, (const double *)Dg, B, X, bmax, s);
+  return launch_solve_m<double, 1>(g, work, n_work, scal, (const double *)L, (const double *)Dg, B, X, bmax, s);
 }
 
 hipError_t launch_rhs(const Geom &g, int n_sub, long long max_nm, const double *r0, double *B,
