@@ -462,7 +462,7 @@ struct mrcm_interface {
   int *d_pos = nullptr;
   double *AB = nullptr, *AB0 = nullptr;
   double *b = nullptr, *b0 = nullptr;
-  double *inv = nullptr, *r = nullptr, *scalar = nullptr;
+  double *inv = nullptr, *r = nullptr, *y = nullptr, *scalar = nullptr;
   DevStatus *st = nullptr;
   hipStream_t stream = nullptr;
   int64_t bytes = 0;
@@ -482,7 +482,7 @@ void free_mbfs(mrcm_mbfs *h) {
 
 void free_iface(mrcm_interface *h) {
   if (!h) return;
-  void *ptrs[] = {h->d_pos, h->AB, h->AB0, h->b, h->b0, h->inv, h->r, h->scalar, h->st};
+  void *ptrs[] = {h->d_pos, h->AB, h->AB0, h->b, h->b0, h->inv, h->r, h->y, h->scalar, h->st};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -736,13 +736,14 @@ mrcm_status mrcm_assemble_interface(const mrcm_mbfs *mb, void *stream, mrcm_inte
     bool ok = upload(&h->d_pos, h->pos) == hipSuccess && dev_alloc(&h->AB, band) == hipSuccess &&
               dev_alloc(&h->AB0, band) == hipSuccess && dev_alloc(&h->b, h->n) == hipSuccess &&
               dev_alloc(&h->b0, h->n) == hipSuccess && dev_alloc(&h->inv, (int64_t)ldl_inv_size(h->n)) == hipSuccess &&
+              dev_alloc(&h->y, h->n) == hipSuccess &&
               dev_alloc(&h->r, h->n) == hipSuccess && dev_alloc(&h->scalar, 4) == hipSuccess &&
               hipMalloc((void **)&h->st, sizeof(DevStatus)) == hipSuccess;
     if (!ok) {
       free_iface(h);
       return fail(MRCM_ENOMEM, "device allocation of the interface system failed");
     }
-    h->bytes = 2 * band * 8 + 4 * (int64_t)h->n * 8;
+    h->bytes = 2 * band * 8 + 5 * (int64_t)h->n * 8 + (int64_t)ldl_inv_size(h->n) * 8;
   }
   h->stream = s;
   const int64_t band = (int64_t)h->n * (2 * h->w + 1);
@@ -782,25 +783,25 @@ mrcm_status mrcm_solve_interface(mrcm_interface *h, int32_t refine, void *stream
     // factor a sign-flipped copy of the assembled system (the assembled one
     // stays for refinement and the residual)
     Stage t(MRCM_STAGE_LU, s);
-    HIP_TRY(launch_band_ldl(h->AB0, h->AB, h->b0, h->b, h->n, h->w, h->inv, h->st, s));
+    // the factorisation also carries out the forward substitution into y
+    HIP_TRY(launch_band_ldl(h->AB0, h->AB, h->b0, h->b, h->y, h->n, h->w, h->inv, h->st, s));
   }
   {
     Stage t(MRCM_STAGE_SWEEP, s);
-    HIP_TRY(launch_lu_sweep(h->AB, h->inv, h->n, h->w, h->b, 0, s));
-    HIP_TRY(launch_lu_sweep(h->AB, h->inv, h->n, h->w, h->b, 1, s));
+    HIP_TRY(launch_lu_sweep(h->AB, h->inv, h->n, h->w, h->y, 1, s));
     for (int it = 0; it < refine; ++it) {
-      HIP_TRY(launch_band_residual(h->AB0, h->n, h->w, h->b, h->b0, h->r, 1, s));
+      HIP_TRY(launch_band_residual(h->AB0, h->n, h->w, h->y, h->b0, h->r, 1, s));
       HIP_TRY(launch_lu_sweep(h->AB, h->inv, h->n, h->w, h->r, 0, s));
       HIP_TRY(launch_lu_sweep(h->AB, h->inv, h->n, h->w, h->r, 1, s));
-      HIP_TRY(launch_axpy(h->b, h->r, h->n, s));
+      HIP_TRY(launch_axpy(h->y, h->r, h->n, s));
     }
-    HIP_TRY(launch_perm(h->b, h->d_pos, h->nv, X, 1, s));
+    HIP_TRY(launch_perm(h->y, h->d_pos, h->nv, X, 1, s));
   }
   mrcm_status st = read_status(h->st, s, "mrcm_solve_interface");
   profile_flush();
   if (st != MRCM_OK) return st;
   if (rel_residual) {
-    HIP_TRY(launch_band_residual(h->AB0, h->n, h->w, h->b, h->b0, h->r, 0, s));
+    HIP_TRY(launch_band_residual(h->AB0, h->n, h->w, h->y, h->b0, h->r, 0, s));
     HIP_TRY(launch_norm2(h->r, h->n, h->scalar, s));
     HIP_TRY(launch_norm2(h->b0, h->n, h->scalar + 1, s));
     double v[2];

@@ -186,18 +186,35 @@ __global__ __launch_bounds__(64) void k_ldl_first(double *__restrict__ AB, int n
   if (ldl_diag16(blk, kb, lane, AB, w, 0, inv) && lane == 0) set_status(st, -5, 0, 0.0);
 }
 
+// y of the last block, y = L11^{-1} b (its rows of b are final after the
+// last step).
+__global__ __launch_bounds__(64) void k_ldl_tail_y(const double *__restrict__ inv_last, const double *__restrict__ b,
+                                                   double *__restrict__ y, int n, int k0) {
+  const int r = threadIdx.x;
+  if (r >= kLB || k0 + r >= n) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < kLB; ++c) acc += inv_last[r * kLB + c] * (k0 + c < n ? b[k0 + c] : 0.0);
+  y[k0 + r] = acc;
+}
+
 // Step for block k0 (factored; its L11^{-1}, 1/D in inv_k): the trailing rows
 // and columns r0 = k0 + 16 .. r0 + nr - 1 in lower 64x64 tiles, one
-// workgroup (four waves, 16 rows each) per tile.
+// workgroup (four waves, 16 rows each) per tile.  The forward substitution
+// L y = b rides along: block k's y_k = L11^{-1} b_k (b_k is final once the
+// previous steps have run) goes to y, and each diagonal tile applies
+// b -= L21 y_k to its 64 rows.
 __global__ __launch_bounds__(256) void k_ldl_step(double *__restrict__ AB, int n, int w, int k0,
                                                   const double *__restrict__ inv_k,
-                                                  double *__restrict__ inv_next, DevStatus *st) {
+                                                  double *__restrict__ inv_next, double *__restrict__ b,
+                                                  double *__restrict__ y, DevStatus *st) {
   using M = Mma<double>;
   __shared__ double Li[kLB * (kLB + 1)];
   __shared__ double Dq[kLB];
   __shared__ double Wi[64 * (kLB + 1)];
   __shared__ double Wj[64 * (kLB + 1)];
   __shared__ double Dn[kLB * (kLB + 1)];
+  __shared__ double yk[kLB];
   const int ld = 2 * w + 1;
   const int r0 = k0 + kLB;
   const int nr = min(n, k0 + kLB + w) - r0;
@@ -252,7 +269,26 @@ __global__ __launch_bounds__(256) void k_ldl_step(double *__restrict__ AB, int n
       Wj[(16 * wave + M::crow(v, lane)) * (kLB + 1) + lr] = wj[v];
     }
   }
+  // forward substitution of block k: y_k = L11^{-1} b_k (diagonal tiles)
+  if (ti == tj && tid >= 64 && tid < 64 + kLB) {
+    const int r = tid - 64;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < kLB; ++c) acc += Li[r * (kLB + 1) + c] * (k0 + c < n ? b[k0 + c] : 0.0);
+    yk[r] = acc;
+    if (ti == 0 && k0 + r < n) y[k0 + r] = acc;
+  }
   __syncthreads();
+  // and b -= L21 y_k on this tile's rows, by wave 1 (off wave 0's path)
+  if (ti == tj && wave == 1) {
+    const int i = i0 + lane;
+    if (i < r0 + nr) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < kLB; ++c) acc += Wi[lane * (kLB + 1) + c] * Dq[c] * yk[c];
+      b[i] -= acc;
+    }
+  }
   // C -= (W_i D^{-1}) W_j^T.  In the tile holding the next diagonal block,
   // wave 0 finishes that block's columns first and factors it before the
   // rest of its row: it is the critical path from one step to the next.
@@ -730,16 +766,18 @@ hipError_t launch_iface_scatter(const Geom &g, int n_sub, const int *patches, co
 
 size_t ldl_inv_size(int n) { return (size_t)((n + kLB - 1) / kLB) * kInvStride; }
 
-hipError_t launch_band_ldl(const double *AB0, double *AB, const double *b0, double *b, int n, int w,
+hipError_t launch_band_ldl(const double *AB0, double *AB, const double *b0, double *b, double *y, int n, int w,
                            double *inv, DevStatus *st, hipStream_t s) {
   hipLaunchKernelGGL(k_flip_copy, dim3(1024), dim3(256), 0, s, AB0, AB, b0, b, n, w);
   hipLaunchKernelGGL(k_ldl_first, dim3(1), dim3(64), 0, s, AB, n, w, inv, st);
-  for (int k0 = 0; k0 + kLB < n; k0 += kLB) {
+  int k0 = 0;
+  for (; k0 + kLB < n; k0 += kLB) {
     const int nr = std::min(n, k0 + kLB + w) - (k0 + kLB);
     const int nt = (nr + 63) / 64;
     hipLaunchKernelGGL(k_ldl_step, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, AB, n, w, k0,
-                       inv + (size_t)(k0 / kLB) * kInvStride, inv + (size_t)(k0 / kLB + 1) * kInvStride, st);
+                       inv + (size_t)(k0 / kLB) * kInvStride, inv + (size_t)(k0 / kLB + 1) * kInvStride, b, y, st);
   }
+  hipLaunchKernelGGL(k_ldl_tail_y, dim3(1), dim3(64), 0, s, inv + (size_t)(k0 / kLB) * kInvStride, b, y, n, k0);
   return hipGetLastError();
 }
 

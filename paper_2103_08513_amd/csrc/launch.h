@@ -37,7 +37,7 @@ hipError_t launch_iface_scatter(const Geom &g, int n_sub, const int *patches, co
                                 const double *F, const double *Fb, const double *SAb, double *AB,
                                 int w, double *b, hipStream_t s);
 size_t ldl_inv_size(int n);
-hipError_t launch_band_ldl(const double *AB0, double *AB, const double *b0, double *b, int n, int w,
+hipError_t launch_band_ldl(const double *AB0, double *AB, const double *b0, double *b, double *y, int n, int w,
                            double *inv, DevStatus *st, hipStream_t s);
 hipError_t launch_lu_sweep(const double *AB, const double *inv, int n, int w, double *x, int upper,
                            hipStream_t s);
