@@ -638,7 +638,8 @@ __device__ __forceinline__ typename Mma<T>::v4 mma16_split(const T (&a)[4], cons
 // NBT: most R2-update tiles per wave; KS: k-steps of the backward L21^T
 // product (4*KS >= the largest band).
 template <typename T, int mode, int NBT, int KS>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_solve(Geom g, const int4 *__restrict__ work,
+// two workgroups per CU where the band fits (FP64 with b <= 112, all FP32)
+__global__ __launch_bounds__(256, (sizeof(T) == 8 && KS > 28) ? 1 : 2) void k_solve(Geom g, const int4 *__restrict__ work,
                                                const double *__restrict__ scal,
                                                const T *__restrict__ Lg, const T *__restrict__ Dg,
                                                double *Bg, double *Xg, int scaled, int ldb, int wmax) {
@@ -653,9 +654,11 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_solve(Geom g, c
   const int nct = CP >> 4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  T *Lp = reinterpret_cast<T *>(smem_raw);     // [2][kNB][ldb], zero beyond offset b
-  T *Dp = Lp + 2 * kNB * ldb;                   // [2][kNB*kNB]
-  T *Y = Dp + 2 * kNB * kNB;                    // ring [wmax][kMaxChunk] (stride CP)
+  // one panel buffer: the next panel waits in registers and is stored after
+  // the end-of-panel barrier, which keeps two workgroups within one CU's LDS
+  T *Lp = reinterpret_cast<T *>(smem_raw);     // [kNB][ldb], zero beyond offset b
+  T *Dp = Lp + kNB * ldb;                       // [kNB*kNB]
+  T *Y = Dp + kNB * kNB;                        // ring [wmax][kMaxChunk] (stride CP)
   T *Zs = Y + (size_t)wmax * kMaxChunk;         // [16][kMaxChunk]
   const T *L = Lg + D.L_off;
   const T *Dinv = Dg + D.D_off;
@@ -684,14 +687,14 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_solve(Geom g, c
     }
     dreg = Dinv[(size_t)p * kNB * kNB + tid];
   };
-  auto store_panel = [&](int buf) {
-    T *lp = Lp + buf * kNB * ldb;
+  auto store_panel = [&]() {
+    T *lp = Lp;
 #pragma unroll
     for (int i = 0; i < kLReg; ++i) {
       const int e = tid + 256 * i;
       if (e < lcnt) lp[(e / bp1) * ldb + e % bp1] = ((lok >> i) & 1u) ? lreg[i] : T(0);
     }
-    Dp[buf * kNB * kNB + tid] = dreg;
+    Dp[tid] = dreg;
   };
   // rows of B for the forward sweep: 16 rows x CP columns, 3 per thread.
   // The raw values and their scale factors are held as loaded (any
@@ -722,7 +725,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_solve(Geom g, c
   };
 
   // panel buffers start at zero: their padding beyond offset b stays zero
-  for (int e = tid; e < 2 * kNB * ldb; e += 256) Lp[e] = T(0);
+  for (int e = tid; e < kNB * ldb; e += 256) Lp[e] = T(0);
   __syncthreads();
   // ------------------------------ forward ------------------------------
   {
@@ -737,17 +740,20 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_solve(Geom g, c
       Y[e] = v;
     }
     fetch_panel(0);
-    store_panel(0);
+    store_panel();
   }
   __syncthreads();
+  const T *lp = Lp;
+  const T *dp = Dp;
   for (int p = 0; p < nP; ++p) {
     const int k = p * kNB;
     const int kb = min(kNB, N - k);
-    const int cur = p & 1;
     const int sk = k % W;
-    const T *lp = Lp + cur * kNB * ldb;
-    const T *dp = Dp + cur * kNB * kNB;
     const bool has_next = p + 1 < nP;
+    if (p > 0) {
+      store_panel();
+      __syncthreads();
+    }
     if (has_next) {
       fetch_panel(p + 1);
       fetch_rows(k + W);
@@ -815,10 +821,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_solve(Geom g, c
         }
       }
     }
-    if (has_next) {
-      store_rows(k + W, sk);
-      store_panel(cur ^ 1);
-    }
+    if (has_next) store_rows(k + W, sk);
     __syncthreads();
   }
 
@@ -842,16 +845,17 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_solve(Geom g, c
     }
   };
   fetch_panel(nP - 1);
-  store_panel(0);
+  store_panel();
   fetch_y(nP - 1);
   __syncthreads();
-  for (int p = nP - 1, it = 0; p >= 0; --p, ++it) {
+  for (int p = nP - 1; p >= 0; --p) {
     const int k = p * kNB;
     const int kb = min(kNB, N - k);
-    const int cur = it & 1;
     const int sk = k % W;
-    const T *lp = Lp + cur * kNB * ldb;
-    const T *dp = Dp + cur * kNB * kNB;
+    if (p < nP - 1) {
+      store_panel();
+      __syncthreads();
+    }
     typename M::v4 c;
 #pragma unroll
     for (int v = 0; v < 4; ++v) c[v] = ((yok >> v) & 1u) ? T(yraw[v]) : T(0);
@@ -859,26 +863,32 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_solve(Geom g, c
       fetch_panel(p - 1);
       fetch_y(p - 1);
     }
-    // Z = Y1 - L21^T X2 over K = b, as four independent MFMA chains
+    // Z = Y1 - L21^T X2 over K = b, as four independent MFMA chains, the
+    // operands loaded in two halves
     if (wave < nct) {
-      T a[KS], bb[KS];
-#pragma unroll
-      for (int s2 = 0; s2 < KS; ++s2) {
-        const int t = 4 * s2 + lk;
-        // offsets clamped into the panel row; entries past the band meet a
-        // zero operand
-        a[s2] = lp[lr * ldb + (kNB + min(t, b - 1) - lr)];
-        bb[s2] = (t < b) ? Y[wrap(sk + kNB + min(t, b - 1), W) * CP + wave * 16 + lr] : T(0);
-      }
-      __builtin_amdgcn_sched_barrier(0);
+      constexpr int KH = (KS + 1) / 2;
       const typename M::v4 z = {T(0), T(0), T(0), T(0)};
       typename M::v4 p1 = z, p2 = z, p3 = z;
 #pragma unroll
-      for (int s2 = 0; s2 < KS; s2 += 4) {
-        c = M::mma(-a[s2], bb[s2], c);
-        if (s2 + 1 < KS) p1 = M::mma(-a[s2 + 1], bb[s2 + 1], p1);
-        if (s2 + 2 < KS) p2 = M::mma(-a[s2 + 2], bb[s2 + 2], p2);
-        if (s2 + 3 < KS) p3 = M::mma(-a[s2 + 3], bb[s2 + 3], p3);
+      for (int h = 0; h < 2; ++h) {
+        T a[KH], bb[KH];
+#pragma unroll
+        for (int s3 = 0; s3 < KH; ++s3) {
+          const int s2 = h * KH + s3;
+          const int t = 4 * s2 + lk;
+          // offsets clamped into the panel row; entries past the band meet a
+          // zero operand
+          a[s3] = lp[lr * ldb + (kNB + min(t, b - 1) - lr)];
+          bb[s3] = (t < b) ? Y[wrap(sk + kNB + min(t, b - 1), W) * CP + wave * 16 + lr] : T(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s3 = 0; s3 < KH; s3 += 4) {
+          c = M::mma(-a[s3], bb[s3], c);
+          if (s3 + 1 < KH) p1 = M::mma(-a[s3 + 1], bb[s3 + 1], p1);
+          if (s3 + 2 < KH) p2 = M::mma(-a[s3 + 2], bb[s3 + 2], p2);
+          if (s3 + 3 < KH) p3 = M::mma(-a[s3 + 3], bb[s3 + 3], p3);
+        }
       }
       c = (c + p1) + (p2 + p3);
 #pragma unroll
@@ -911,7 +921,6 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_solve(Geom g, c
         }
       }
     }
-    if (p > 0) store_panel(cur ^ 1);
     __syncthreads();
   }
 }
@@ -1090,7 +1099,7 @@ int solve_ldb(int bmax) { return bmax + 33; }
 size_t solve_lds_bytes(int fp32, int bmax, int mmax) {
   (void)mmax;
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
-  return ((size_t)2 * kNB * solve_ldb(bmax) + 2 * kNB * kNB + (size_t)(bmax + kNB) * kMaxChunk +
+  return ((size_t)kNB * solve_ldb(bmax) + kNB * kNB + (size_t)(bmax + kNB) * kMaxChunk +
           (size_t)kNB * kMaxChunk) * es;
 }
 
@@ -1138,22 +1147,14 @@ static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, co
   return hipGetLastError();
 }
 
-// NBT: tiles per MFMA batch -- all of a wave's tiles in FP64 (one workgroup
-// per CU: registers are plentiful), three in FP32 (two workgroups per CU);
-// KS = ceil(b/4) for the largest band of the precision.
+// NBT: tiles per MFMA batch, three, which keeps the registers within two
+// workgroups per CU; KS = ceil(b/4) for the largest band the instantiation
+// serves.
 template <typename T, int mode>
 static hipError_t launch_solve_m(const Geom &g, const int4 *work, int n_work, const double *scal,
                                  const T *L, const T *Dg, double *B, double *X, int bmax, hipStream_t s) {
-  constexpr int nct = kMaxChunk / 16;
-  constexpr bool f32 = sizeof(T) == 4;
-  if (bmax <= 112) {
-    constexpr int nrt = 7;
-    constexpr int nbt = f32 ? 3 : (nrt * nct + 3) / 4;
-    return launch_solve_t<T, mode, nbt, 28>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s);
-  }
-  constexpr int nrt = (kMaxBand32 + 15) / 16;
-  constexpr int nbt = f32 ? 3 : (nrt * nct + 3) / 4;
-  return launch_solve_t<T, mode, nbt, (kMaxBand32 + 3) / 4>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s);
+  if (bmax <= 112) return launch_solve_t<T, mode, 3, 28>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s);
+  return launch_solve_t<T, mode, 3, (kMaxBand32 + 3) / 4>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s);
 }
 
 hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, const double *scal,
