@@ -109,7 +109,7 @@ __global__ void k_flip_copy(const double *__restrict__ AB0, double *__restrict__
 // triangle is given row-major in blk (stride 17); rows and columns past kb act
 // as the identity.  Runs on one wave; writes L, D and U = D L^T into the band
 // and L11^{-1}, 1/D into inv.  Returns nonzero on a zero or non-finite pivot.
-__device__ int ldl_diag16(const double *blk, int kb, int lane, double *__restrict__ AB, int w, int k0,
+__device__ __attribute__((always_inline)) int ldl_diag16(const double *blk, int kb, int lane, double *__restrict__ AB, int w, int k0,
                           double *__restrict__ inv) {
   const int ld = 2 * w + 1;
   int r = lane & 15;
@@ -126,30 +126,60 @@ __device__ int ldl_diag16(const double *blk, int kb, int lane, double *__restric
   }
   double ok = 1.0;
   double qs[kLB];
-  double d = row_bcast(v[0], 0);
+  // 1/d by the hardware estimate and two Newton steps; a zero or non-finite
+  // pivot is flagged beside the chain, not on it
+  auto recip = [&](double d) -> double {
+    ok = (d != 0.0 && isfinite(d)) ? ok : 0.0;
+    double q = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, q, 1.0);
+    q = fma(q, e, q);
+    e = fma(-d, q, 1.0);
+    return fma(q, e, q);
+  };
+  // Software-pipelined: pivot jj finishes row jj + 1 first and starts the
+  // reciprocal of the next pivot; the updates of the remaining rows are
+  // issued between the dependent steps of that reciprocal, whose latency they
+  // cover (the scheduling barriers keep this interleaving, which the
+  // compiler would otherwise undo by grouping the dependent chain).
+  double q = recip(row_bcast(v[0], 0));
 #pragma unroll
   for (int jj = 0; jj < kLB; ++jj) {
-    ok = (d != 0.0 && isfinite(d)) ? ok : 0.0;
-    double dd = (d != 0.0 && isfinite(d)) ? d : 1.0;
-    double q = __builtin_amdgcn_rcp(dd);
-    double e = fma(-dd, q, 1.0);
-    q = fma(q, e, q);
-    e = fma(-dd, q, 1.0);
-    q = fma(q, e, q);
     qs[jj] = q;
     const double wv = v[jj] * q;
     const double xq = x[jj] * q;
+    auto upd = [&](int i) {
+      if (i < kLB) {
+        const double a = row_bcast(v[jj], i);
+        v[i] -= wv * a;
+        x[i] -= a * xq;
+      }
+    };
     if (jj + 1 < kLB) {
       const double a = row_bcast(v[jj], jj + 1);
       v[jj + 1] -= wv * a;
       x[jj + 1] -= a * xq;
-      d = row_bcast(v[jj + 1], jj + 1);
-    }
+      const double d = row_bcast(v[jj + 1], jj + 1);
+      ok = (d != 0.0 && isfinite(d)) ? ok : 0.0;
+      double qn = __builtin_amdgcn_rcp(d);
+      upd(jj + 2);
+      upd(jj + 3);
+      __builtin_amdgcn_sched_barrier(0);
+      double e = fma(-d, qn, 1.0);
+      upd(jj + 4);
+      upd(jj + 5);
+      __builtin_amdgcn_sched_barrier(0);
+      qn = fma(qn, e, qn);
+      upd(jj + 6);
+      upd(jj + 7);
+      __builtin_amdgcn_sched_barrier(0);
+      e = fma(-d, qn, 1.0);
+      upd(jj + 8);
+      upd(jj + 9);
+      __builtin_amdgcn_sched_barrier(0);
+      qn = fma(qn, e, qn);
 #pragma unroll
-    for (int i = jj + 2; i < kLB; ++i) {
-      const double a = row_bcast(v[jj], i);
-      v[i] -= wv * a;
-      x[i] -= a * xq;
+      for (int i = jj + 10; i < kLB; ++i) upd(i);
+      q = qn;
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -200,11 +230,15 @@ __global__ __launch_bounds__(64) void k_ldl_tail_y(const double *__restrict__ in
 
 // Step for block k0 (factored; its L11^{-1}, 1/D in inv_k): the trailing rows
 // and columns r0 = k0 + 16 .. r0 + nr - 1 in lower 64x64 tiles, one
-// workgroup (four waves, 16 rows each) per tile.  The forward substitution
+// workgroup (four waves, 16 rows each) per tile, plus a fifth wave that, in
+// the tile holding the next diagonal block, factors that block while the
+// other waves finish the tile.  The forward substitution
 // L y = b rides along: block k's y_k = L11^{-1} b_k (b_k is final once the
 // previous steps have run) goes to y, and each diagonal tile applies
 // b -= L21 y_k to its 64 rows.
-__global__ __launch_bounds__(256) void k_ldl_step(double *__restrict__ AB, int n, int w, int k0,
+constexpr int kStepThreads = 320;
+
+__global__ __launch_bounds__(kStepThreads) void k_ldl_step(double *__restrict__ AB, int n, int w, int k0,
                                                   const double *__restrict__ inv_k,
                                                   double *__restrict__ inv_next, double *__restrict__ b,
                                                   double *__restrict__ y, DevStatus *st) {
@@ -234,26 +268,30 @@ __global__ __launch_bounds__(256) void k_ldl_step(double *__restrict__ AB, int n
     const int j = k0 + c;
     return (i < r0 + nr && i - j <= w) ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
   };
-  double ai[4], aj[4];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    ai[s] = a21(i0 + 16 * wave + lr, 4 * s + lk);
-    aj[s] = a21(j0 + 16 * wave + lr, 4 * s + lk);
-  }
-  // the C tile of this wave: rows i0 + 16 wave + .., columns j0 + 16 tc + ..
+  // waves 0..3 own 16 rows of the tile each; wave 4 owns none
+  const bool rows = wave < 4;
+  double ai[4] = {0.0, 0.0, 0.0, 0.0}, aj[4] = {0.0, 0.0, 0.0, 0.0};
   typename M::v4 c[4];
+  if (rows) {
 #pragma unroll
-  for (int tc = 0; tc < 4; ++tc) {
+    for (int s = 0; s < 4; ++s) {
+      ai[s] = a21(i0 + 16 * wave + lr, 4 * s + lk);
+      aj[s] = a21(j0 + 16 * wave + lr, 4 * s + lk);
+    }
+    // the C tile of this wave: rows i0 + 16 wave + .., columns j0 + 16 tc + ..
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + 16 * wave + M::crow(v, lane), j = j0 + 16 * tc + lr;
-      const bool ok = i < r0 + nr && j < r0 + nr && i >= j && i - j <= w;
-      c[tc][v] = ok ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
+    for (int tc = 0; tc < 4; ++tc) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 16 * wave + M::crow(v, lane), j = j0 + 16 * tc + lr;
+        const bool ok = i < r0 + nr && j < r0 + nr && i >= j && i - j <= w;
+        c[tc][v] = ok ? AB[(size_t)j * ld + (w + i - j)] : 0.0;
+      }
     }
   }
   __syncthreads();
   // W = A21 L11^{-T}: lane supplies A[l%16][k] and B[k][l%16] = L11^{-1}[l%16][k]
-  {
+  if (rows) {
     double bl[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) bl[s] = Li[lr * (kLB + 1) + 4 * s + lk];
@@ -290,14 +328,17 @@ __global__ __launch_bounds__(256) void k_ldl_step(double *__restrict__ AB, int n
     }
   }
   // C -= (W_i D^{-1}) W_j^T.  In the tile holding the next diagonal block,
-  // wave 0 finishes that block's columns first and factors it before the
-  // rest of its row: it is the critical path from one step to the next.
+  // wave 0 finishes that block's columns first and hands them to wave 4,
+  // which factors the block -- the critical path from one step to the next --
+  // while the row waves finish the tile.
   const bool has_next = ti == 0 && tj == 0;
-  double a[4];
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  if (rows) {
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int k = 4 * s + lk;
-    a[s] = Wi[(16 * wave + lr) * (kLB + 1) + k] * Dq[k];
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + lk;
+      a[s] = Wi[(16 * wave + lr) * (kLB + 1) + k] * Dq[k];
+    }
   }
   auto update_store = [&](int tc) {
 #pragma unroll
@@ -314,15 +355,19 @@ __global__ __launch_bounds__(256) void k_ldl_step(double *__restrict__ AB, int n
       }
     }
   };
-  if (has_next && wave == 0) {
-    update_store(0);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  if (has_next) {
+    // (workgroup-uniform branch: only this workgroup takes the extra barrier)
+    if (wave == 0) update_store(0);
+    __syncthreads();
+  }
+  if (has_next && wave == 4) {
     const int kb = min(kLB, n - r0);
     if (ldl_diag16(Dn, kb, lane, AB, w, r0, inv_next) && lane == 0) set_status(st, -5, r0, 0.0);
+  } else if (has_next && wave == 0) {
     update_store(1);
     update_store(2);
     update_store(3);
-  } else {
+  } else if (rows) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
 #pragma unroll
@@ -339,7 +384,7 @@ __global__ __launch_bounds__(256) void k_ldl_step(double *__restrict__ AB, int n
     }
   }
   // the diagonal tile of each row block stores L21 = W D^{-1} and U12 = W^T
-  if (ti == tj) {
+  if (ti == tj && rows) {
     for (int e = tid; e < 64 * kLB; e += 256) {
       const int rr = e / kLB, cc = e % kLB;
       const int i = i0 + rr, j = k0 + cc;
@@ -774,7 +819,7 @@ hipError_t launch_band_ldl(const double *AB0, double *AB, const double *b0, doub
   for (; k0 + kLB < n; k0 += kLB) {
     const int nr = std::min(n, k0 + kLB + w) - (k0 + kLB);
     const int nt = (nr + 63) / 64;
-    hipLaunchKernelGGL(k_ldl_step, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, AB, n, w, k0,
+    hipLaunchKernelGGL(k_ldl_step, dim3(nt * (nt + 1) / 2), dim3(kStepThreads), 0, s, AB, n, w, k0,
                        inv + (size_t)(k0 / kLB) * kInvStride, inv + (size_t)(k0 / kLB + 1) * kInvStride, b, y, st);
   }
   hipLaunchKernelGGL(k_ldl_tail_y, dim3(1), dim3(64), 0, s, inv + (size_t)(k0 / kLB) * kInvStride, b, y, n, k0);
