@@ -106,11 +106,16 @@ __global__ void k_flip_copy(const double *__restrict__ AB0, double *__restrict__
 }
 
 // 16x16 LDL^T of the block at rows and columns k0 .. k0+kb-1 of M, whose lower
-// triangle is given row-major in blk (stride 17); rows and columns past kb act
-// as the identity.  Runs on one wave; writes L, D and U = D L^T into the band
-// and L11^{-1}, 1/D into inv.  Returns nonzero on a zero or non-finite pivot.
-__device__ __attribute__((always_inline)) int ldl_diag16(const double *blk, int kb, int lane, double *__restrict__ AB, int w, int k0,
-                          double *__restrict__ inv) {
+// triangle is given row-major in blk (stride 17, the upper part zero); rows
+// and columns past kb act as the identity.  Runs on one wave; writes L, D and
+// U = D L^T into the band and L11^{-1} (row-major), 1/D into inv, both staged
+// through the LDS buffers S (544 doubles, may start at blk: blk is read
+// first) and T (272 doubles), so that the global stores are contiguous runs.
+// The wave's LDS accesses complete in order, so its reads see its writes.  Returns nonzero on a zero or
+// non-finite pivot.
+__device__ __attribute__((always_inline)) int ldl_diag16(const double *blk, int kb, int lane,
+                                                         double *__restrict__ AB, int w, int k0,
+                                                         double *__restrict__ inv, double *S, double *T) {
   const int ld = 2 * w + 1;
   int r = lane & 15;
   // opaque to the optimiser, as in the local factor: lane-derived constants
@@ -119,13 +124,11 @@ __device__ __attribute__((always_inline)) int ldl_diag16(const double *blk, int 
   double v[kLB], x[kLB];
 #pragma unroll
   for (int c = 0; c < kLB; ++c) {
-    double a = (r == c) ? 1.0 : 0.0;
-    if (c < kb && r < kb && c <= r) a = blk[r * (kLB + 1) + c];
-    v[c] = a;
+    const double a = blk[r * (kLB + 1) + c];
+    v[c] = (c < kb && r < kb) ? a : ((r == c) ? 1.0 : 0.0);
     x[c] = (r == c) ? 1.0 : 0.0;
   }
   double ok = 1.0;
-  double qs[kLB];
   // 1/d by the hardware estimate and two Newton steps; a zero or non-finite
   // pivot is flagged beside the chain, not on it
   auto recip = [&](double d) -> double {
@@ -144,9 +147,19 @@ __device__ __attribute__((always_inline)) int ldl_diag16(const double *blk, int 
   double q = recip(row_bcast(v[0], 0));
 #pragma unroll
   for (int jj = 0; jj < kLB; ++jj) {
-    qs[jj] = q;
     const double wv = v[jj] * q;
     const double xq = x[jj] * q;
+    // Results of pivot jj, final from here on, go to LDS off the chain, at
+    // lane-based addresses with constant offsets.  S[t * 17 + i] = entry
+    // (i, t) of the factored block: lane r > jj holds L[r][jj] = wv (written
+    // to the lower half of S) and U[jj][r] = v[jj] (the upper half of S + 272),
+    // lane jj holds D_jj = v[jj].  Lanes r < jj write to the other half of
+    // each, which is never read.  Lane r's x is column r of L11^{-1}, whose
+    // entry jj is final too.
+    S[jj * (kLB + 1) + r] = (r == jj) ? v[jj] : wv;
+    S[kLB * (kLB + 1) + r * (kLB + 1) + jj] = v[jj];
+    T[jj * kLB + r] = x[jj];
+    T[kLB * kLB + jj] = q;
     auto upd = [&](int i) {
       if (i < kLB) {
         const double a = row_bcast(v[jj], i);
@@ -183,28 +196,22 @@ __device__ __attribute__((always_inline)) int ldl_diag16(const double *blk, int 
     }
     __builtin_amdgcn_sched_barrier(0);
   }
-  // every row of 16 lanes stores (identical values), so no computation is
-  // sunk into a lane-conditional block
+  // band columns k0 + t, rows k0 .. k0 + 15: sixteen contiguous entries each
 #pragma unroll
-  for (int i = 0; i < kLB; ++i) inv[i * kLB + r] = x[i];
-  if (r == 0) {
-#pragma unroll
-    for (int c = 0; c < kLB; ++c) inv[kLB * kLB + c] = qs[c];
+  for (int e = lane; e < kLB * kLB; e += 64) {
+    const int t = e >> 4, i = e & 15;
+    const double val = S[(i < t ? kLB * (kLB + 1) : 0) + t * (kLB + 1) + i];
+    if (t < kb && i < kb && abs(i - t) <= w) AB[(size_t)(k0 + t) * ld + (w + i - t)] = val;
   }
 #pragma unroll
-  for (int c = 0; c < kLB; ++c) {
-    if (c < kb && r < kb && c <= r && r - c <= w) {
-      // lower: L[r][c] = a / D_c; diagonal: D_r; upper: U[c][r] = D_c L[r][c] = a
-      AB[(size_t)(k0 + c) * ld + (w + r - c)] = (r == c) ? v[c] : v[c] * qs[c];
-      if (r != c) AB[(size_t)(k0 + r) * ld + (w + c - r)] = v[c];
-    }
-  }
+  for (int e = lane; e < kInvStride; e += 64) inv[e] = T[e];
   return ok == 1.0 ? 0 : 1;
 }
 
 __global__ __launch_bounds__(64) void k_ldl_first(double *__restrict__ AB, int n, int w,
                                                   double *__restrict__ inv, DevStatus *st) {
-  __shared__ double blk[kLB * (kLB + 1)];
+  __shared__ double blk[2 * kLB * (kLB + 1)];
+  __shared__ double T[kInvStride];
   const int ld = 2 * w + 1;
   const int lane = threadIdx.x;
   const int kb = min(kLB, n);
@@ -213,7 +220,7 @@ __global__ __launch_bounds__(64) void k_ldl_first(double *__restrict__ AB, int n
     blk[r * (kLB + 1) + c] = (r < kb && c <= r && r - c <= w) ? AB[(size_t)c * ld + (w + r - c)] : 0.0;
   }
   __syncthreads();
-  if (ldl_diag16(blk, kb, lane, AB, w, 0, inv) && lane == 0) set_status(st, -5, 0, 0.0);
+  if (ldl_diag16(blk, kb, lane, AB, w, 0, inv, blk, T) && lane == 0) set_status(st, -5, 0, 0.0);
 }
 
 // y of the last block, y = L11^{-1} b (its rows of b are final after the
@@ -247,8 +254,9 @@ __global__ __launch_bounds__(kStepThreads) void k_ldl_step(double *__restrict__ 
   __shared__ double Dq[kLB];
   __shared__ double Wi[64 * (kLB + 1)];
   __shared__ double Wj[64 * (kLB + 1)];
-  __shared__ double Dn[kLB * (kLB + 1)];
+  __shared__ double Dn[2 * kLB * (kLB + 1)];
   __shared__ double yk[kLB];
+  __shared__ double bk[kLB];
   const int ld = 2 * w + 1;
   const int r0 = k0 + kLB;
   const int nr = min(n, k0 + kLB + w) - r0;
@@ -263,6 +271,7 @@ __global__ __launch_bounds__(kStepThreads) void k_ldl_step(double *__restrict__ 
   const int i0 = r0 + 64 * ti, j0 = r0 + 64 * tj;
   for (int e = tid; e < kLB * kLB; e += 256) Li[(e / kLB) * (kLB + 1) + (e % kLB)] = inv_k[e];
   if (tid < kLB) Dq[tid] = inv_k[kLB * kLB + tid];
+  if (tid >= 64 && tid < 64 + kLB) bk[tid - 64] = (k0 + tid - 64 < n) ? b[k0 + tid - 64] : 0.0;
   // A21 rows of this wave for the row block (and the column block)
   auto a21 = [&](int i, int c) -> double {
     const int j = k0 + c;
@@ -307,12 +316,36 @@ __global__ __launch_bounds__(kStepThreads) void k_ldl_step(double *__restrict__ 
       Wj[(16 * wave + M::crow(v, lane)) * (kLB + 1) + lr] = wj[v];
     }
   }
+  // C -= (W_i D^{-1}) W_j^T.  a = W_i D^{-1} comes from this wave's own rows
+  // of Wi (no barrier needed).  In the tile holding the next diagonal block,
+  // wave 0 updates that block right away -- its only columns on or below the
+  // diagonal -- and hands it to wave 4, which factors it (the critical path
+  // from one step to the next) while the row waves finish the tile.
+  const bool has_next = ti == 0 && tj == 0;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  if (rows) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + lk;
+      a[s] = Wi[(16 * wave + lr) * (kLB + 1) + k] * Dq[k];
+    }
+  }
+  if (has_next && wave == 0) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c[0] = M::mma(-a[s], Wj[lr * (kLB + 1) + 4 * s + lk], c[0]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + M::crow(v, lane), j = j0 + lr;
+      const bool ok = i < r0 + nr && j < r0 + nr && i >= j && i - j <= w;
+      Dn[(i - r0) * (kLB + 1) + (j - r0)] = ok ? c[0][v] : 0.0;
+    }
+  }
   // forward substitution of block k: y_k = L11^{-1} b_k (diagonal tiles)
   if (ti == tj && tid >= 64 && tid < 64 + kLB) {
     const int r = tid - 64;
     double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < kLB; ++c) acc += Li[r * (kLB + 1) + c] * (k0 + c < n ? b[k0 + c] : 0.0);
+    for (int c = 0; c < kLB; ++c) acc += Li[r * (kLB + 1) + c] * bk[c];
     yk[r] = acc;
     if (ti == 0 && k0 + r < n) y[k0 + r] = acc;
   }
@@ -327,61 +360,41 @@ __global__ __launch_bounds__(kStepThreads) void k_ldl_step(double *__restrict__ 
       b[i] -= acc;
     }
   }
-  // C -= (W_i D^{-1}) W_j^T.  In the tile holding the next diagonal block,
-  // wave 0 finishes that block's columns first and hands them to wave 4,
-  // which factors the block -- the critical path from one step to the next --
-  // while the row waves finish the tile.
-  const bool has_next = ti == 0 && tj == 0;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  if (rows) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int k = 4 * s + lk;
-      a[s] = Wi[(16 * wave + lr) * (kLB + 1) + k] * Dq[k];
-    }
-  }
-  auto update_store = [&](int tc) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) c[tc] = M::mma(-a[s], Wj[(16 * tc + lr) * (kLB + 1) + 4 * s + lk], c[tc]);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + 16 * wave + M::crow(v, lane), j = j0 + 16 * tc + lr;
-      const bool ok = i < r0 + nr && j < r0 + nr && i >= j && i - j <= w;
-      if (has_next && wave == 0 && tc == 0) {
-        // the next diagonal block goes to LDS for its factorisation
-        Dn[(i - r0) * (kLB + 1) + (j - r0)] = ok ? c[tc][v] : 0.0;
-      } else if (ok) {
-        AB[(size_t)j * ld + (w + i - j)] = c[tc][v];
-      }
-    }
-  };
-  if (has_next) {
-    // (workgroup-uniform branch: only this workgroup takes the extra barrier)
-    if (wave == 0) update_store(0);
-    __syncthreads();
-  }
   if (has_next && wave == 4) {
     const int kb = min(kLB, n - r0);
-    if (ldl_diag16(Dn, kb, lane, AB, w, r0, inv_next) && lane == 0) set_status(st, -5, r0, 0.0);
-  } else if (has_next && wave == 0) {
-    update_store(1);
-    update_store(2);
-    update_store(3);
-  } else if (rows) {
+    // Li is free after the barrier: it stages the inverse
+    if (ldl_diag16(Dn, kb, lane, AB, w, r0, inv_next, Dn, Li) && lane == 0) set_status(st, -5, r0, 0.0);
+  } else if (rows && !(has_next && wave == 0)) {
+    // the first ntc tile columns of this wave's rows; in a diagonal tile the
+    // columns past the wave's own 16 rows lie above the diagonal (and in the
+    // tile of the next diagonal block wave 0 is already done)
+    auto update_cols = [&](auto ntc_c) {
+      constexpr int NTC = decltype(ntc_c)::value;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < 4; ++s) {
 #pragma unroll
-      for (int tc = 0; tc < 4; ++tc) c[tc] = M::mma(-a[s], Wj[(16 * tc + lr) * (kLB + 1) + 4 * s + lk], c[tc]);
-    }
-#pragma unroll
-    for (int tc = 0; tc < 4; ++tc) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + 16 * wave + M::crow(v, lane), j = j0 + 16 * tc + lr;
-        const bool ok = i < r0 + nr && j < r0 + nr && i >= j && i - j <= w;
-        if (ok) AB[(size_t)j * ld + (w + i - j)] = c[tc][v];
+        for (int tc = 0; tc < NTC; ++tc)
+          c[tc] = M::mma(-a[s], Wj[(16 * tc + lr) * (kLB + 1) + 4 * s + lk], c[tc]);
       }
-    }
+#pragma unroll
+      for (int tc = 0; tc < NTC; ++tc) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + 16 * wave + M::crow(v, lane), j = j0 + 16 * tc + lr;
+          const bool ok = i < r0 + nr && j < r0 + nr && i >= j && i - j <= w;
+          if (ok) AB[(size_t)j * ld + (w + i - j)] = c[tc][v];
+        }
+      }
+    };
+    const int ntc = (ti == tj) ? wave + 1 : 4;
+    if (ntc == 4)
+      update_cols(std::integral_constant<int, 4>{});
+    else if (ntc == 3)
+      update_cols(std::integral_constant<int, 3>{});
+    else if (ntc == 2)
+      update_cols(std::integral_constant<int, 2>{});
+    else
+      update_cols(std::integral_constant<int, 1>{});
   }
   // the diagonal tile of each row block stores L21 = W D^{-1} and U12 = W^T
   if (ti == tj && rows) {
