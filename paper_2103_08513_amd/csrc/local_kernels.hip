@@ -169,33 +169,31 @@ __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wrap(int s, int W) { return s >= W ? s - W : s; }
 
-// 1/sqrt(x) for x > 0: the hardware estimate refined by Newton's iteration
-// y <- y + (y/2)(1 - x y^2), two steps in FP64 and one in FP32.
-__device__ __forceinline__ double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double e = fma(-x * y, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  e = fma(-x * y, y, 1.0);
-  return fma(0.5 * y, e, y);
+// Reciprocal and reciprocal square root from the hardware estimates (relative
+// error near 2^-24 in FP64, about an ulp in FP32).  FP64 refines with one
+// third-order step: with e = 1 - x y, 1/x = y (1 + e + e^2 + ...), so
+// y (1 + e + e^2) leaves an error of order e^3; with e = 1 - x y^2,
+// 1/sqrt(x) = y (1 + e/2 + 3e^2/8 + ...).  FP32 takes one Newton step.
+// The estimate and the refinement are separate calls so that a caller can
+// place independent work between them.
+__device__ __forceinline__ double rcp_est(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ float rcp_est(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rsq_est(double x) { return __builtin_amdgcn_rsq(x); }
+__device__ __forceinline__ float rsq_est(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmat(float a, float b, float c) { return fmaf(a, b, c); }
+// the correction factors: 1/x = y (1 + rcp_t(e)), 1/sqrt(x) = y (1 + rsq_t(e))
+__device__ __forceinline__ double rcp_t(double e) { return fma(e, e, e); }
+__device__ __forceinline__ float rcp_t(float e) { return e; }
+__device__ __forceinline__ double rsq_t(double e) { return e * fma(0.375, e, 0.5); }
+__device__ __forceinline__ float rsq_t(float e) { return 0.5f * e; }
+template <typename T>
+__device__ __forceinline__ T rcp_refine(T x, T y) {
+  return fmat(y, rcp_t(fmat(-x, y, T(1))), y);
 }
-__device__ __forceinline__ float rsqrt_nr(float x) {
-  const float y = __builtin_amdgcn_rsqf(x);
-  const float e = fmaf(-x * y, y, 1.0f);
-  return fmaf(0.5f * y, e, y);
-}
-
-// 1/x: the hardware estimate refined by Newton's iteration y <- y + y(1 - x y),
-// two steps in FP64 and one in FP32.
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-x, y, 1.0);
-  return fma(y, e, y);
-}
-__device__ __forceinline__ float rcp_nr(float x) {
-  const float y = __builtin_amdgcn_rcpf(x);
-  return fmaf(y, fmaf(-x, y, 1.0f), y);
+template <typename T>
+__device__ __forceinline__ T rsq_refine(T x, T y) {
+  return fmat(y, rsq_t(fmat(-x * y, y, T(1))), y);
 }
 
 // Diagonal block of panel k (kb <= 16 columns) on one wave: Cholesky factor
@@ -208,9 +206,13 @@ __device__ __forceinline__ float rcp_nr(float x) {
 // 1/D; the Cholesky column a / sqrt(D) and the step of the inverse are formed
 // beside it.  The inverse rides along: lane c solves L11 x = e_c column by
 // column, x_i -= L[i][jj] x_jj = a_i (x_jj / D) with x_jj taken before its
-// own scaling by 1/sqrt(D).  Returns nonzero when a pivot was not positive.
+// own scaling by 1/sqrt(D).  The results of each pivot are written as soon as
+// they are final, beside the chain; lanes with nothing to write put it into
+// `junk` (kNB spare LDS entries).  Returns nonzero when a pivot was not
+// positive.
 template <typename T>
-__device__ __forceinline__ int factor_diag(T *S, T *Xs, int ldb, int k, int kb, int b, int W, int lane) {
+__device__ __forceinline__ int factor_diag(T *S, T *Xs, T *junk, int ldb, int k, int kb, int b, int W,
+                                           int lane) {
   const int sk = k % W;
   int r = lane & 15;
   // opaque to the optimiser: values derived from the lane index (identity
@@ -220,49 +222,85 @@ __device__ __forceinline__ int factor_diag(T *S, T *Xs, int ldb, int k, int kb, 
   T v[kNB], x[kNB];
 #pragma unroll
   for (int jj = 0; jj < kNB; ++jj) {
-    T a = (r == jj) ? T(1) : T(0);
-    if (jj < kb && r < kb && jj <= r) a = S[wrap(sk + jj, W) * ldb + r - jj];
-    v[jj] = a;
+    // all sixteen loads in flight at once: the offset is clamped into the
+    // column and the entry selected afterwards
+    const T a = S[wrap(sk + jj, W) * ldb + max(r - jj, 0)];
+    v[jj] = (jj < kb && r < kb && jj <= r) ? a : ((r == jj) ? T(1) : T(0));
     x[jj] = (r == jj) ? T(1) : T(0);
   }
   T ok = T(1);
-  T d = row_bcast(v[0], 0);
+  T q, y;
+  {
+    const T d = row_bcast(v[0], 0);
+    ok = (d > T(0)) ? ok : T(0);
+    q = rcp_refine(d, rcp_est(d));
+    y = rsq_refine(d, rsq_est(d));
+  }
+  // Software-pipelined: pivot jj finishes column jj + 1 first and starts the
+  // reciprocals of the next pivot, whose latency the updates of the remaining
+  // columns cover; the scheduling barriers keep this interleaving (and the
+  // pivots in order: without them the scheduler may defer whole chains of
+  // updates and hold their broadcast values in registers).
 #pragma unroll
   for (int jj = 0; jj < kNB; ++jj) {
-    ok = (d > T(0)) ? ok : T(0);
-    const T q = rcp_nr(d);
-    const T y = rsqrt_nr(d);
     const T w = v[jj] * q;
     const T xq = x[jj] * q;
+    // entries above the diagonal of v collect garbage that is never read
+    auto upd = [&](int i) {
+      if (i < kNB) {
+        const T a = row_bcast(v[jj], i);
+        v[i] -= w * a;
+        x[i] -= a * xq;
+      }
+    };
+    T qn = T(0), yn = T(0);
     if (jj + 1 < kNB) {
       // column jj+1 first: it carries the next pivot
       const T a = row_bcast(v[jj], jj + 1);
       v[jj + 1] -= w * a;
       x[jj + 1] -= a * xq;
-      d = row_bcast(v[jj + 1], jj + 1);
-    }
-    // entries above the diagonal of v collect garbage that is never read
+      const T d = row_bcast(v[jj + 1], jj + 1);
+      ok = (d > T(0)) ? ok : T(0);
+      // the refinements step by step, two column updates between dependent
+      // steps (the compiler would otherwise issue the chain back to back)
+      const T q0 = rcp_est(d);
+      const T y0 = rsq_est(d);
+      upd(jj + 2);
+      upd(jj + 3);
+      __builtin_amdgcn_sched_barrier(0);
+      const T e = fmat(-d, q0, T(1));
+      const T xy = d * y0;
+      upd(jj + 4);
+      upd(jj + 5);
+      __builtin_amdgcn_sched_barrier(0);
+      const T t = rcp_t(e);
+      const T ey = fmat(-xy, y0, T(1));
+      upd(jj + 6);
+      upd(jj + 7);
+      __builtin_amdgcn_sched_barrier(0);
+      qn = fmat(q0, t, q0);
+      const T ty = rsq_t(ey);
+      upd(jj + 8);
+      upd(jj + 9);
+      __builtin_amdgcn_sched_barrier(0);
+      yn = fmat(y0, ty, y0);
 #pragma unroll
-    for (int i = jj + 2; i < kNB; ++i) {
-      const T a = row_bcast(v[jj], i);
-      v[i] -= w * a;
-      x[i] -= a * xq;
+      for (int i = jj + 10; i < kNB; ++i) upd(i);
     }
     // lane jj holds the pivot itself, so the same product gives it sqrt(D)
     v[jj] *= y;
     x[jj] *= y;
-    // keep the pivots in order: without this the scheduler may defer whole
-    // chains of updates and hold their broadcast values in registers
+    // column jj of the factor and entry jj of lane r's column of the inverse
+    // are final
+    Xs[jj * kNB + r] = x[jj];
+    {
+      const bool mine = jj < kb && jj <= r && r - jj <= b;
+      T *dst = mine ? S + (wrap(sk + jj, W) * ldb + r - jj) : junk + r;
+      *dst = v[jj];
+    }
     __builtin_amdgcn_sched_barrier(0);
-  }
-  // every row of 16 lanes stores (the rows hold identical values): a store
-  // under a lane test would let the optimiser sink the whole computation of x
-  // into it and hold all broadcast values in registers until then
-#pragma unroll
-  for (int jj = 0; jj < kNB; ++jj) Xs[jj * kNB + r] = x[jj];
-#pragma unroll
-  for (int jj = 0; jj < kNB; ++jj) {
-    if (jj < kb && jj <= r && r - jj <= b) S[wrap(sk + jj, W) * ldb + r - jj] = v[jj];
+    q = qn;
+    y = yn;
   }
   return ok == T(1) ? 0 : 1;
 }
@@ -422,6 +460,8 @@ __device__ __forceinline__ void factor_body(const SubDesc *__restrict__ subs, co
   T *S = reinterpret_cast<T *>(smem_raw);
   // X = L11^{-1} of the current and of the next panel (alternating buffers)
   T *Xbuf = S + (size_t)W * ldb;
+  // spare entries for the diagonal factorisation's masked-out writes
+  T *junk = Xbuf + 2 * kNB * kNB;
   // NW waves; tiles per wave in the L21 phase, and per batch of the
   // trailing update
   constexpr int NTH = 64 * NW;
@@ -464,7 +504,7 @@ __device__ __forceinline__ void factor_body(const SubDesc *__restrict__ subs, co
   ColFetch cur{0.0, 0.0, 0.0, 0.0, 1.0, 1.0, -1};
   if (tid < 64) cur = fetch_column_entry(cf, sc, W + ejj, et, efirst, N, n0, b);
   __syncthreads();
-  if (wave == 0) bad |= factor_diag<T>(S, Xbuf, ldb, 0, min(kNB, N), b, W, lane);
+  if (wave == 0) bad |= factor_diag<T>(S, Xbuf, junk, ldb, 0, min(kNB, N), b, W, lane);
   __syncthreads();
   if (wave < nT)
     panel_l21_tiles<T, kNBA>(S, Xbuf, ldb, 0, min(kNB, N), b, W, lane, 1 + wave, NW, (nT - wave + NW - 1) / NW);
@@ -488,11 +528,20 @@ __device__ __forceinline__ void factor_body(const SubDesc *__restrict__ subs, co
     // the remaining tiles of the update and the copies of panel k to global
     // memory from a shared counter
     if (wave == 0 && more) {
+      // the critical path: wave 0 takes issue priority over the tile waves
+      // that share its SIMD and the LDS while it runs
+      __builtin_amdgcn_s_setprio(3);
       const int z[1] = {0};
       factor_tiles<T, 1>(S, ldb, b, W, sk, lane, z, z, 1, colA);
-      bad |= factor_diag<T>(S, Xn, ldb, k + kNB, kb1, b, W, lane);
+      bad |= factor_diag<T>(S, Xn, junk, ldb, k + kNB, kb1, b, W, lane);
+      __builtin_amdgcn_s_setprio(0);
     }
-    if (wave == NW - 1) {
+    // With eight waves, wave 4 shares wave 0's SIMD: it takes no MFMA work in
+    // this phase (the tile waves' MFMAs would hold up wave 0's chain) but the
+    // copies to global memory.  With four waves the copies go round the
+    // shared counter with the tiles.
+    constexpr int kCopyWave = NW == 8 ? 4 : -1;
+    if (wave == (kCopyWave >= 0 ? kCopyWave : NW - 1)) {
       // inverse diagonal block of panel k
       T *dst = Dinv + (size_t)(k / kNB) * (kNB * kNB);
 #pragma unroll
@@ -506,8 +555,16 @@ __device__ __forceinline__ void factor_body(const SubDesc *__restrict__ subs, co
       // ti = tp .. nT-1
       const int n_tiles = more ? (nT - 1) + nT * (nT - 1) / 2 : 0;
       const int n_batch = (n_tiles + kNB1 - 1) / kNB1;
-      const int n_items = n_batch + kb;
-      for (;;) {
+      const int n_items = n_batch + (kCopyWave >= 0 ? 0 : kb);
+      if (wave == kCopyWave) {
+        // columns k .. k + kb - 1 of the factor to global memory
+        for (int jj = 0; jj < kb; ++jj) {
+          const T *col = S + wrap(sk + jj, W) * ldb;
+          T *dst = L + (size_t)(k + jj) * bp1;
+          for (int t = lane; t <= b; t += 64) dst[t] = col[t];
+        }
+      }
+      for (; wave != kCopyWave;) {
         int idx = 0;
         if (lane == 0) idx = atomicAdd(&tile_ctr, 1);
         idx = __builtin_amdgcn_readfirstlane(idx);
@@ -1090,7 +1147,7 @@ int factor_ldb(int fp32, int bmax) { return 16 * ((bmax + 15) / 16) + (fp32 ? 26
 
 size_t factor_lds_bytes(int fp32, int bmax) {
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
-  return ((size_t)(std::max(bmax, kNB) + kNB) * factor_ldb(fp32, bmax) + 2 * kNB * kNB) * es;
+  return ((size_t)(std::max(bmax, kNB) + kNB) * factor_ldb(fp32, bmax) + 2 * kNB * kNB + kNB) * es;
 }
 
 // Column stride of the solve's panel buffers: operand offsets reach b + 31.
