@@ -657,6 +657,118 @@ __global__ __launch_bounds__(kSweepThreads) void k_band_sweep(const double *__re
   for (int i = tid; i < n; i += kSweepThreads) x[i] = xs[i];
 }
 
+// Backward sweep U x = y by chunks of kChunk = 128 unknowns, last chunk
+// first, two launches per chunk.  k_usweep_chunk (one workgroup) solves the
+// chunk's own triangle: its rows already hold y minus the contributions of
+// every later chunk.  Wave 0 solves each 16-block with the stored inverse,
+// U_bb^{-1} = L11^{-T} D^{-1}, while waves 1 and 2 (one row each) subtract the
+// block from the rows above it in the chunk; all their band entries are
+// loaded at the start.  k_usweep_update then subtracts the solved chunk from
+// the up to w rows above it, spread over workgroups of 64 rows, which is
+// where nearly all of the band is read -- in parallel rather than through a
+// single compute unit.
+constexpr int kChunk = 128;
+constexpr int kChunkBlocks = kChunk / kSW;
+
+__global__ __launch_bounds__(192) void k_usweep_chunk(const double *__restrict__ AB,
+                                                      const double *__restrict__ inv, int n, int w,
+                                                      double *__restrict__ x, int c0) {
+  __shared__ double xs[kChunk];
+  __shared__ double lt[kChunkBlocks * kInvStride];
+  const int ld = 2 * w + 1;
+  const int m = min(kChunk, n - c0);
+  const int nbk = (m + kSW - 1) / kSW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int t = tid; t < kChunk; t += 192) xs[t] = t < m ? x[c0 + t] : 0.0;
+  const double *iv = inv + (size_t)(c0 / kSW) * kInvStride;
+  for (int e = tid; e < nbk * kInvStride; e += 192) lt[e] = iv[e];
+  // waves 1, 2: row t of the chunk; u[bb-1][c] = U(c0 + t, c0 + 16 bb + c)
+  // for blocks bb above the row's own block, loaded unconditionally at a
+  // clamped address, with the validity in a bit mask
+  const int t = tid - 64;
+  double u[kChunkBlocks - 1][kSW];
+  unsigned msk[kChunkBlocks - 1];
+  if (wave > 0) {
+    const int i = c0 + t;
+#pragma unroll
+    for (int bb = 1; bb < kChunkBlocks; ++bb) {
+      msk[bb - 1] = 0u;
+#pragma unroll
+      for (int c = 0; c < kSW; ++c) {
+        const int j = c0 + kSW * bb + c;
+        const bool ok = t < kSW * bb && j < c0 + m && j - i <= w;
+        u[bb - 1][c] = AB[ok ? (size_t)j * ld + (w + i - j) : 0];
+        msk[bb - 1] |= ok ? (1u << c) : 0u;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int bb = kChunkBlocks - 1; bb >= 0; --bb) {
+    if (bb < nbk) {
+      const int b0 = kSW * bb;
+      const int kb = min(kSW, m - b0);
+      if (wave == 0) {
+        const int r = lane & 15;
+        const double *l = lt + bb * kInvStride;
+        const double xo = (r < kb) ? xs[b0 + r] * l[kLB * kLB + r] : 0.0;
+        double xv = 0.0, xw = 0.0;
+#pragma unroll
+        for (int c = 0; c < kSW; c += 2) {
+          xv += l[c * kLB + r] * row_bcast(xo, c);
+          xw += l[(c + 1) * kLB + r] * row_bcast(xo, c + 1);
+        }
+        if (lane < kb) xs[b0 + lane] = xv + xw;
+      }
+      __syncthreads();
+      if (bb > 0 && wave > 0 && t < b0) {
+        double acc = 0.0, acd = 0.0;
+#pragma unroll
+        for (int c = 0; c < kSW; c += 2) {
+          acc += ((msk[bb - 1] >> c) & 1u ? u[bb - 1][c] : 0.0) * xs[b0 + c];
+          acd += ((msk[bb - 1] >> (c + 1)) & 1u ? u[bb - 1][c + 1] : 0.0) * xs[b0 + c + 1];
+        }
+        xs[t] -= acc + acd;
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = tid; e < m; e += 192) x[c0 + e] = xs[e];
+}
+
+// Rows [max(0, c0 - w), c0) minus U(rows, chunk) x_chunk.  Workgroup g takes
+// 64 rows (one per lane); wave q the chunk columns 32q .. 32q + 31.
+__global__ __launch_bounds__(256) void k_usweep_update(const double *__restrict__ AB, int n, int w,
+                                                       double *__restrict__ x, int c0) {
+  __shared__ double xc[kChunk];
+  __shared__ double part[4][64];
+  const int ld = 2 * w + 1;
+  const int m = min(kChunk, n - c0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lo = max(0, c0 - w);
+  const int i = lo + 64 * blockIdx.x + lane;
+  for (int e = tid; e < kChunk; e += 256) xc[e] = e < m ? x[c0 + e] : 0.0;
+  double a[32];
+  unsigned msk = 0u;
+#pragma unroll
+  for (int c = 0; c < 32; ++c) {
+    const int j = c0 + 32 * wave + c;
+    const bool ok = i < c0 && j < c0 + m && j - i <= w;
+    a[c] = AB[ok ? (size_t)j * ld + (w + i - j) : 0];
+    msk |= ok ? (1u << c) : 0u;
+  }
+  __syncthreads();
+  double acc = 0.0, acd = 0.0;
+#pragma unroll
+  for (int c = 0; c < 32; c += 2) {
+    acc += ((msk >> c) & 1u ? a[c] : 0.0) * xc[32 * wave + c];
+    acd += ((msk >> (c + 1)) & 1u ? a[c + 1] : 0.0) * xc[32 * wave + c + 1];
+  }
+  part[wave][lane] = acc + acd;
+  __syncthreads();
+  if (wave == 0 && i < c0) x[i] -= (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
 // r = b - A x with the unfactored band (one thread per row).
 __global__ void k_band_residual(const double *__restrict__ AB, int n, int w,
                                 const double *__restrict__ x, const double *__restrict__ b,
@@ -836,6 +948,14 @@ hipError_t launch_band_ldl(const double *AB0, double *AB, const double *b0, doub
 
 hipError_t launch_lu_sweep(const double *AB, const double *inv, int n, int w, double *x, int upper,
                            hipStream_t s) {
+  if (upper) {
+    for (int c0 = ((n - 1) / kChunk) * kChunk; c0 >= 0; c0 -= kChunk) {
+      hipLaunchKernelGGL(k_usweep_chunk, dim3(1), dim3(192), 0, s, AB, inv, n, w, x, c0);
+      const int rows = c0 - std::max(0, c0 - w);
+      if (rows > 0) hipLaunchKernelGGL(k_usweep_update, dim3((rows + 63) / 64), dim3(256), 0, s, AB, n, w, x, c0);
+    }
+    return hipGetLastError();
+  }
   if (n <= kSweepLdsMax) {
     const size_t lds = (size_t)n * sizeof(double);
     const void *k = upper ? (const void *)k_band_sweep<1> : (const void *)k_band_sweep<0>;
