@@ -651,7 +651,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   }
   {
     Stage t(MRCM_STAGE_RHS, s);
-    ENQ(launch_rhs(g, h->n_sub, H.max_nm, h->r0, h->X, s));
+    ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, h->X, s));
   }
   {
     Stage t(MRCM_STAGE_SOLVE, s);
@@ -669,8 +669,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     for (int it = 0; it < h->refine64; ++it) {
       {
         Stage t(MRCM_STAGE_RESIDUAL, s);
-        ENQ(launch_fill(h->norms, 2LL * H.totCols, 0.0, s));
-        ENQ(launch_residual(g, h->n_sub, H.max_nm, h->coef, h->r0, h->X, h->R, h->norms, s));
+        ENQ(launch_residual(g, h->n_sub, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s));
       }
       Stage t(MRCM_STAGE_REFINE, s);
       ENQ(launch_solve(fp32, g, h->d_work, (int)H.work.size(), h->scal, h->L, h->Dinv, h->R, h->X,
@@ -683,7 +682,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       {
         Stage t(MRCM_STAGE_RESIDUAL, s);
         ENQ(launch_fill(h->norms, 2LL * H.totCols, 0.0, s));
-        ENQ(launch_residual(g, h->n_sub, H.max_nm, h->coef, h->r0, h->X, h->R, h->norms, s));
+        ENQ(launch_residual(g, h->n_sub, H.max_cells, h->coef, h->r0, h->X, h->R, h->norms, s));
         ENQ(launch_ir_check(h->norms, H.totCols, h->scalar, s));
       }
       double res = 0.0;

@@ -679,9 +679,20 @@ __global__ __launch_bounds__(192) void k_usweep_chunk(const double *__restrict__
   const int m = min(kChunk, n - c0);
   const int nbk = (m + kSW - 1) / kSW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int t = tid; t < kChunk; t += 192) xs[t] = t < m ? x[c0 + t] : 0.0;
+  // the chunk's right-hand side and block inverses: every load issued before
+  // the first LDS store (a loop of load-then-store would wait out the memory
+  // latency once per trip)
+  constexpr int kLtPer = (kChunkBlocks * kInvStride + 191) / 192;
   const double *iv = inv + (size_t)(c0 / kSW) * kInvStride;
-  for (int e = tid; e < nbk * kInvStride; e += 192) lt[e] = iv[e];
+  const int nlt = nbk * kInvStride;
+  double ltv[kLtPer];
+#pragma unroll
+  for (int q = 0; q < kLtPer; ++q) ltv[q] = iv[min(tid + 192 * q, nlt - 1)];
+  const double xv0 = x[c0 + min(tid, m - 1)];
+  if (tid < kChunk) xs[tid] = tid < m ? xv0 : 0.0;
+#pragma unroll
+  for (int q = 0; q < kLtPer; ++q)
+    if (tid + 192 * q < nlt) lt[tid + 192 * q] = ltv[q];
   // waves 1, 2: row t of the chunk; u[bb-1][c] = U(c0 + t, c0 + 16 bb + c)
   // for blocks bb above the row's own block, loaded unconditionally at a
   // clamped address, with the validity in a bit mask

@@ -18,12 +18,12 @@ hipError_t launch_factor(int fp32, const SubDesc *subs, const int *order, int n_
 hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, const double *scal,
                         const void *L, const void *Dg, double *B, double *X, int mode, int bmax,
                         hipStream_t s);
-hipError_t launch_rhs(const Geom &g, int n_sub, long long max_nm, const double *r0, double *B,
+hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, const double *r0, double *B,
                       hipStream_t s);
 int solve_chunk_max();
 size_t factor_lds_bytes(int fp32, int bmax);
 size_t solve_lds_bytes(int fp32, int bmax, int mmax);
-hipError_t launch_residual(const Geom &g, int n_sub, long long max_nm, const double *coef,
+hipError_t launch_residual(const Geom &g, int n_sub, int max_cells, const double *coef,
                            const double *r0, const double *X, double *R, double *norms,
                            hipStream_t s);
 hipError_t launch_ir_check(const double *norms, int ncols, double *out, hipStream_t s);

@@ -128,24 +128,37 @@ __device__ __forceinline__ void rhs_row_faces(const Geom &g, const SubDesc &S, i
   }
 }
 
-// Dense right-hand sides R (row-major, N_l x m_l) of every subdomain, one
-// thread per entry.
+// Right-hand sides of rows rbase .. rbase + kRowsPB - 1 of subdomain S into
+// the LDS tile (row-major, stride m): one thread per row finds the row's
+// Robin entries once, the rest of the tile is zero.  Ends with a barrier.
+constexpr int kRowsPB = 32;
+
+__device__ __forceinline__ void rhs_tile(const Geom &g, const SubDesc &S, const double *__restrict__ r0,
+                                         int rbase, double *tile) {
+  const int m = S.m, tid = threadIdx.x;
+  for (int e = tid; e < kRowsPB * m; e += blockDim.x) tile[e] = 0.0;
+  __syncthreads();
+  if (tid < kRowsPB && rbase + tid < S.N) {
+    const int r = rbase + tid;
+    double *row = tile + tid * m;
+    row[0] = r0[S.cell_off + r];
+    rhs_row_faces(g, S, r, [&](int col, double v) { row[col] = v; });
+  }
+  __syncthreads();
+}
+
+// Dense right-hand sides R (row-major, N_l x m_l) of every subdomain,
+// kRowsPB rows per workgroup, written out as one contiguous run.
 __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ r0,
                                              double *__restrict__ B) {
+  __shared__ double tile[kRowsPB * kMaxRhs];
   const SubDesc &S = g.sub[blockIdx.y];
-  const int m = S.m;
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)S.N * m) return;
-  const int r = (int)(e / m), c = (int)(e % m);
-  double v = 0.0;
-  if (c == 0) {
-    v = r0[S.cell_off + r];
-  } else {
-    rhs_row_faces(g, S, r, [&](int col, double val) {
-      if (col == c) v = val;
-    });
-  }
-  B[S.X_off + e] = v;
+  const int rbase = blockIdx.x * kRowsPB;
+  if (rbase >= S.N) return;
+  rhs_tile(g, S, r0, rbase, tile);
+  const int ne = min(kRowsPB, S.N - rbase) * S.m;
+  double *dst = B + S.X_off + (size_t)rbase * S.m;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) dst[e] = tile[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -488,17 +501,40 @@ __device__ __forceinline__ void factor_body(const SubDesc *__restrict__ subs, co
   // prologue: the first W columns, then panel 0
   {
     const int ncol = min(N, W);
-    for (int e = tid; e < ncol * bp1; e += NTH) {
-      const int j = e / bp1, t = e % bp1;
-      double v = 0.0;
-      if (j + t < N) {
-        if (t == 0) v += cf[4 * j];
-        if (t == 1) v -= cf[4 * j + 1];
-        if (t == n0) v -= cf[4 * j + 2];
-        if (t == b) v -= cf[4 * j + 3];
-        if (v != 0.0) v *= sc[j] * sc[j + t];
+    const int ne = ncol * bp1;
+    // eight entries per thread at a time, their loads all issued (at clamped
+    // addresses) before any is used, so the memory latency is paid once per
+    // batch rather than once per entry
+    constexpr int kPB = 8;
+    for (int e0 = tid; e0 < ne; e0 += kPB * NTH) {
+      double c[kPB][4], s1[kPB], s2[kPB];
+#pragma unroll
+      for (int q = 0; q < kPB; ++q) {
+        const int e = e0 + q * NTH;
+        const int j = e / bp1, t = e % bp1;
+        const bool ok = e < ne && j + t < N;
+        const int jj = ok ? j : 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[q][u] = cf[4 * jj + u];
+        s1[q] = sc[jj];
+        s2[q] = sc[ok ? j + t : 0];
       }
-      S[j * ldb + t] = T(v);
+#pragma unroll
+      for (int q = 0; q < kPB; ++q) {
+        const int e = e0 + q * NTH;
+        if (e < ne) {
+          const int j = e / bp1, t = e % bp1;
+          double v = 0.0;
+          if (j + t < N) {
+            if (t == 0) v += c[q][0];
+            if (t == 1) v -= c[q][1];
+            if (t == n0) v -= c[q][2];
+            if (t == b) v -= c[q][3];
+            if (v != 0.0) v *= s1[q] * s2[q];
+          }
+          S[j * ldb + t] = T(v);
+        }
+      }
     }
   }
   ColFetch cur{0.0, 0.0, 0.0, 0.0, 1.0, 1.0, -1};
@@ -787,14 +823,28 @@ __global__ __launch_bounds__(256, (sizeof(T) == 8 && KS > 28) ? 1 : 2) void k_so
   // ------------------------------ forward ------------------------------
   {
     const int nrow = min(N, W);
-    for (int e = tid; e < W * CP; e += 256) {
-      const int rr = e / CP, c = e % CP;
-      T v = T(0);
-      if (rr < nrow && c < cw) {
-        const double s = scaled ? sc[rr] : 1.0;
-        v = T(s * B[(size_t)rr * m + c0 + c]);
+    // loads batched as in the factor's prologue
+    constexpr int kPB = 8;
+    for (int e0 = tid; e0 < W * CP; e0 += kPB * 256) {
+      double bv[kPB], sv[kPB];
+#pragma unroll
+      for (int q = 0; q < kPB; ++q) {
+        const int e = e0 + q * 256;
+        const int rr = e / CP, c = e % CP;
+        const bool ok = e < W * CP && rr < nrow && c < cw;
+        bv[q] = B[ok ? (size_t)rr * m + c0 + c : 0];
+        sv[q] = scaled ? sc[ok ? rr : 0] : 1.0;
       }
-      Y[e] = v;
+#pragma unroll
+      for (int q = 0; q < kPB; ++q) {
+        const int e = e0 + q * 256;
+        const int rr = e / CP, c = e % CP;
+        if (e < W * CP) {
+          T v = T(0);
+          if (rr < nrow && c < cw) v = T((scaled ? sv[q] : 1.0) * bv[q]);
+          Y[e] = v;
+        }
+      }
     }
     fetch_panel(0);
     store_panel();
@@ -984,24 +1034,30 @@ __global__ __launch_bounds__(256, (sizeof(T) == 8 && KS > 28) ? 1 : 2) void k_so
 
 // ---------------------------------------------------------------------------
 // FP64 residual of all right-hand sides, Rb = R - A^H_l X, matrix-free from
-// the coefficients; accumulates per-column ||Rb||^2 and ||R||^2.
+// the coefficients; accumulates per-column ||Rb||^2 and ||R||^2 into norms
+// unless norms is null (a fixed number of refinement sweeps needs none).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_residual(Geom g, const double *__restrict__ coef,
                                                   const double *__restrict__ r0,
                                                   const double *__restrict__ Xg,
                                                   double *__restrict__ Rbuf,
                                                   double *__restrict__ norms) {
+  __shared__ double tile[kRowsPB * kMaxRhs];
   __shared__ double red[2 * kMaxRhs];
   const SubDesc &S = g.sub[blockIdx.y];
   const int m = S.m, N = S.N;
-  for (int i = threadIdx.x; i < 2 * m; i += blockDim.x) red[i] = 0.0;
-  __syncthreads();
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < (long long)N * m) {
-    const int r = (int)(e / m), c = (int)(e % m);
-    const double *cf = coef + 4 * S.cell_off;
-    const double *X = Xg + S.X_off;
-    const int n0 = S.n0, b = S.b;
+  const int rbase = blockIdx.x * kRowsPB;
+  if (rbase >= N) return;
+  const bool acc_norms = norms != nullptr;
+  if (acc_norms)
+    for (int i = threadIdx.x; i < 2 * m; i += blockDim.x) red[i] = 0.0;
+  rhs_tile(g, S, r0, rbase, tile);
+  const double *cf = coef + 4 * S.cell_off;
+  const double *X = Xg + S.X_off;
+  const int n0 = S.n0, b = S.b;
+  const int ne = min(kRowsPB, N - rbase) * m;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const int r = rbase + e / m, c = e % m;
     double ax = cf[4 * r] * X[(size_t)r * m + c];
     if (r + 1 < N) ax -= cf[4 * r + 1] * X[(size_t)(r + 1) * m + c];
     if (r >= 1) ax -= cf[4 * (r - 1) + 1] * X[(size_t)(r - 1) * m + c];
@@ -1009,19 +1065,15 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, const double *__restri
     if (r >= n0) ax -= cf[4 * (r - n0) + 2] * X[(size_t)(r - n0) * m + c];
     if (r + b < N) ax -= cf[4 * r + 3] * X[(size_t)(r + b) * m + c];
     if (r >= b) ax -= cf[4 * (r - b) + 3] * X[(size_t)(r - b) * m + c];
-    double rhs = 0.0;
-    if (c == 0) {
-      rhs = r0[S.cell_off + r];
-    } else {
-      rhs_row_faces(g, S, r, [&](int col, double v) {
-        if (col == c) rhs = v;
-      });
-    }
+    const double rhs = tile[e];
     const double res = rhs - ax;
     Rbuf[S.X_off + (size_t)r * m + c] = res;
-    atomicAdd(&red[2 * c], res * res);
-    atomicAdd(&red[2 * c + 1], rhs * rhs);
+    if (acc_norms) {
+      atomicAdd(&red[2 * c], res * res);
+      atomicAdd(&red[2 * c + 1], rhs * rhs);
+    }
   }
+  if (!acc_norms) return;
   __syncthreads();
   for (int i = threadIdx.x; i < 2 * m; i += blockDim.x) {
     if (red[i] != 0.0) atomicAdd(&norms[2 * (long long)S.col_off + i], red[i]);
@@ -1229,17 +1281,17 @@ hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, c
   return launch_solve_m<double, 1>(g, work, n_work, scal, (const double *)L, (const double *)Dg, B, X, bmax, s);
 }
 
-hipError_t launch_rhs(const Geom &g, int n_sub, long long max_nm, const double *r0, double *B,
+hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, const double *r0, double *B,
                       hipStream_t s) {
-  dim3 grid((unsigned)((max_nm + 255) / 256), n_sub);
+  dim3 grid((unsigned)((max_cells + kRowsPB - 1) / kRowsPB), n_sub);
   hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, g, r0, B);
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const Geom &g, int n_sub, long long max_nm, const double *coef,
+hipError_t launch_residual(const Geom &g, int n_sub, int max_cells, const double *coef,
                            const double *r0, const double *X, double *R, double *norms,
                            hipStream_t s) {
-  dim3 grid((unsigned)((max_nm + 255) / 256), n_sub);
+  dim3 grid((unsigned)((max_cells + kRowsPB - 1) / kRowsPB), n_sub);
   hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, s, g, coef, r0, X, R, norms);
   return hipGetLastError();
 }
