@@ -1041,12 +1041,18 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, const double *__restri
                                                   const double *__restrict__ r0,
                                                   const double *__restrict__ Xg,
                                                   double *__restrict__ Rbuf,
-                                                  double *__restrict__ norms) {
+                                                  double *__restrict__ norms, int ntile, int n_sub) {
   __shared__ double tile[kRowsPB * kMaxRhs];
   __shared__ double red[2 * kMaxRhs];
-  const SubDesc &S = g.sub[blockIdx.y];
+  // XCD-aware order: workgroups go round-robin to the eight XCDs, so XCD x
+  // gets subdomains x, x + 8, ... with all their row tiles in sequence, and
+  // the stencil's neighbour rows come from that XCD's L2
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int sub = xcd + 8 * (slot / ntile);
+  if (sub >= n_sub) return;
+  const SubDesc &S = g.sub[sub];
   const int m = S.m, N = S.N;
-  const int rbase = blockIdx.x * kRowsPB;
+  const int rbase = (slot % ntile) * kRowsPB;
   if (rbase >= N) return;
   const bool acc_norms = norms != nullptr;
   if (acc_norms)
@@ -1291,8 +1297,9 @@ hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, const double *r0,
 hipError_t launch_residual(const Geom &g, int n_sub, int max_cells, const double *coef,
                            const double *r0, const double *X, double *R, double *norms,
                            hipStream_t s) {
-  dim3 grid((unsigned)((max_cells + kRowsPB - 1) / kRowsPB), n_sub);
-  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, s, g, coef, r0, X, R, norms);
+  const int ntile = (max_cells + kRowsPB - 1) / kRowsPB;
+  const long long nblk = 8LL * ntile * ((n_sub + 7) / 8);
+  hipLaunchKernelGGL(k_residual, dim3((unsigned)nblk), dim3(256), 0, s, g, coef, r0, X, R, norms, ntile, n_sub);
   return hipGetLastError();
 }
 
