@@ -87,10 +87,15 @@ def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1):
     model.solve_interface(X, refine=refine, residual=True)
     torch.cuda.synchronize()
     info = model.info()
+    # per-subdomain shapes from the library: (N_l, b_l, m_l, solve group)
+    shapes = []
+    for l in range(info.n_sub):
+        si = model.subdomain(l)
+        shapes.append((si.n_cells, si.band, si.n_rhs, si.solve_group))
     n_dims, w = model.interface_dims()
     out = dict(ms_step=ms_step, stages=stages, info=info, interface_n=n_dims, interface_w=w,
                p=p.cpu().numpy(), U=U.view(6, N).cpu().numpy(), X=X.cpu().numpy(),
-               interface_residual=model.interface_residual)
+               interface_residual=model.interface_residual, sub_shapes=shapes)
     model.close()
     return out
 
@@ -111,12 +116,16 @@ def cpu_baseline(case):
     return r, t
 
 
-def solve_algorithmic_bytes(shapes, es):
+def solve_algorithmic_bytes(shapes, es, group=None):
     """Bytes one k_solve launch must move: the band factor and the inverses of
     its 16x16 diagonal blocks read once per sweep (forward and backward), the
-    right-hand sides read once and the solutions written once (FP64)."""
+    right-hand sides read once and the solutions written once (FP64).  With
+    `group`, only the subdomains of that solve group (the launch timed as the
+    'solve' stage when the first solve is split)."""
     nbytes = 0.0
-    for l_n, l_b, l_m in shapes:
+    for l_n, l_b, l_m, l_g in shapes:
+        if group is not None and l_g != group:
+            continue
         panels = (l_n + 15) // 16
         nbytes += 2.0 * es * (l_n * (l_b + 1) + 256 * panels) + 2.0 * 8.0 * l_n * l_m
     return nbytes
@@ -160,7 +169,10 @@ def roofline_for(stage_name, res, info, precision):
                 "frac": ach / peak, "traffic": None, "ms_avg": st["ms_avg"],
                 "algorithmic_flops": flops}
     if stage_name == "solve":
-        nbytes = solve_algorithmic_bytes(res["sub_shapes"], es)
+        # the 'solve' stage is one launch: group 0 when the solve is split
+        # (some subdomain in group 1), otherwise all subdomains
+        split = any(sh[3] == 1 for sh in res["sub_shapes"])
+        nbytes = solve_algorithmic_bytes(res["sub_shapes"], es, 0 if split else None)
         ach = nbytes / sec / 1e9
         traffic = measured_traffic("k_solve", "60x220x85") if precision == 0 else None
         return {"kernel": "k_solve", "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -207,34 +219,25 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     from mrcm_inputs import config2
-    from oracle.norms import rel_l2
     case = config2()
     pb = case.problem
     prec = 1 if args.precision == "fp32ir" else 0
     log(f"workload 60x220x85, precision {args.precision}, steps {args.steps}, warmup {args.warmup}")
     res = run_gpu(case, prec, args.steps, args.warmup, args.refine, args.fp64_refine)
     info = res["info"]
-    from oracle.geometry import Geometry
-    geo = Geometry(pb.dims, case.partition, case.iface)
-    shapes = []
-    for l in range(geo.n_sub):
-        ext = geo.sub_hi[l] - geo.sub_lo[l]
-        e = sorted(int(x) for x in ext)
-        shapes.append((e[0] * e[1] * e[2], e[0] * e[1], 2 * len(geo.sub_patches[l]) + 1))
-    res["sub_shapes"] = shapes
     log(f"ms/step {res['ms_step']:.3f}; stages " +
         ", ".join(f"{k} {v['ms_avg']:.3f}" for k, v in res["stages"].items()))
     secondary = None
     if not args.no_secondary:
         other = 1 - prec
         r2 = run_gpu(case, other, args.steps, args.warmup, args.refine, args.fp64_refine)
-        r2["sub_shapes"] = shapes
         secondary = r2
         log(f"other precision ms/step {r2['ms_step']:.3f}")
     cpu = None
     err = {}
     if not args.no_cpu_baseline:
         log("oracle (CPU, FP64) whole solve ...")
+        from oracle.norms import rel_l2
         ref, t_cpu = cpu_baseline(case)
         cpu = {"value": info.n_mbfs / t_cpu, "unit": "MBFs/s", "cores": 1, "kind": "oracle",
                "sample": "whole MRCM solve of the 60x220x85 workload (561 subdomains, 15,520 MBFs), "

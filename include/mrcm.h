@@ -153,6 +153,8 @@ typedef struct {
   int32_t ax[3];
   int32_t n_cells, band, n_rhs, n_patch;
   int32_t pin_local;      /* local row of the pinned cell, or -1 */
+  int32_t solve_group;    /* FP64 path: 0 if the subdomain's first solve is in the 'solve'
+                             stage's launch, 1 if it runs in the 'refine' stage (see below) */
 } mrcm_subdomain_info;
 
 /*
@@ -244,9 +246,15 @@ mrcm_status mrcm_copy_interface(const mrcm_interface *iface, double *A, double *
  * local factorisation, right-hand sides of (2.25)/(2.26), the local band
  * solves, the FP64 residuals of refinement (a fill, the residual and, in
  * FP32, the convergence check), the correction solves of refinement,
- * Gamma-flux reduction, interface assembly (several kernels), interface LU
- * (two kernels per 32-column block), interface triangular sweeps (several
- * kernels), reconstruction (two kernels).
+ * Gamma-flux reduction, interface assembly (several kernels), interface
+ * LDL^T factorisation with the forward substitution (one step kernel per
+ * 16-column block), interface backward sweeps (two kernels per 128 unknowns)
+ * and refinement, reconstruction (two kernels).
+ * FP64 path with refinement, when the solve work exceeds one round of
+ * resident workgroups: 'solve' is the first solve of group 0 (the first
+ * round's subdomains); 'refine' covers the rest -- group 1's first solve and
+ * both groups' residuals and corrections, group 0's on a second stream that
+ * joins the caller's stream at the end -- and 'residual' stays empty.
  */
 enum { MRCM_STAGE_COEF = 0, MRCM_STAGE_FACTOR, MRCM_STAGE_RHS, MRCM_STAGE_SOLVE,
        MRCM_STAGE_RESIDUAL, MRCM_STAGE_REFINE, MRCM_STAGE_FLUX, MRCM_STAGE_ASSEMBLE,

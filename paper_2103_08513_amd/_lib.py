@@ -61,7 +61,7 @@ class CProfile(ctypes.Structure):
 class CSubInfo(ctypes.Structure):
     _fields_ = [("lo", c_int32 * 3), ("ext", c_int32 * 3), ("ax", c_int32 * 3),
                 ("n_cells", c_int32), ("band", c_int32), ("n_rhs", c_int32),
-                ("n_patch", c_int32), ("pin_local", c_int32)]
+                ("n_patch", c_int32), ("pin_local", c_int32), ("solve_group", c_int32)]
 
 
 _lib = None

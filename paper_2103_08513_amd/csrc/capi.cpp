@@ -438,6 +438,16 @@ struct mrcm_mbfs {
   IfaceDesc *d_ifc = nullptr;
   int *d_order = nullptr;
   int4 *d_work = nullptr;
+  // FP64 path: when the solve work exceeds one round of resident workgroups,
+  // the first n_first items form group 0 and the rest group 1 (whole
+  // subdomains each); group 0's refinement overlaps group 1's first solve on
+  // a second stream
+  int n_first = 0;
+  std::vector<int> solve_group;  // per subdomain
+  int *d_grp_subs[2] = {nullptr, nullptr};
+  int n_grp_subs[2] = {0, 0};
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int *d_patches = nullptr;
   int *d_subof[3] = {nullptr, nullptr, nullptr};
   double *coef = nullptr, *r0 = nullptr, *scal = nullptr;
@@ -474,9 +484,12 @@ void free_mbfs(mrcm_mbfs *h) {
   if (!h) return;
   void *ptrs[] = {h->d_sub, h->d_ifc, h->d_order, h->d_work, h->d_patches, h->d_subof[0], h->d_subof[1],
                   h->d_subof[2], h->coef, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, h->F, h->Fb, h->SAb,
-                  h->norms, h->scalar, h->st};
+                  h->norms, h->scalar, h->st, h->d_grp_subs[0], h->d_grp_subs[1]};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->s2) (void)hipStreamDestroy(h->s2);
   delete h;
 }
 
@@ -533,6 +546,42 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
     h->st = p;
   }
 #undef ALLOC
+  // the split of the solve work into resident rounds (FP64 path)
+  h->solve_group.assign(G.subs.size(), 0);
+  if (G.precision != MRCM_FP32_IR) {
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    // a multiple of 8 keeps every item on its XCD (workgroup i on XCD i mod 8)
+    const size_t slots = ((size_t)ncu * solve_blocks_per_cu(0, G.bmax) / 8) * 8;
+    if (slots > 0 && slots < G.work.size()) {
+      std::vector<int> grp(G.subs.size(), -1);
+      bool whole = true;
+      for (size_t i = 0; i < G.work.size(); ++i) {
+        const int l = G.work[i].x;
+        if (l < 0) continue;
+        const int gi = i < slots ? 0 : 1;
+        if (grp[l] >= 0 && grp[l] != gi) whole = false;
+        grp[l] = gi;
+      }
+      if (whole) {
+        std::vector<int> lists[2];
+        for (size_t i = 0; i < G.work.size(); ++i) {
+          const int l = G.work[i].x;
+          if (l >= 0 && (lists[grp[l]].empty() || lists[grp[l]].back() != l)) lists[grp[l]].push_back(l);
+        }
+        for (int gi = 0; gi < 2; ++gi) {
+          HIP_TRY(upload(&h->d_grp_subs[gi], lists[gi]));
+          h->n_grp_subs[gi] = (int)lists[gi].size();
+        }
+        for (size_t l = 0; l < grp.size(); ++l) h->solve_group[l] = std::max(0, grp[l]);
+        HIP_TRY(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+        h->n_first = (int)slots;
+      }
+    }
+  }
   h->bytes = bytes;
   Geom &g = h->g;
   g.nx = G.n[0];
@@ -653,19 +702,46 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     Stage t(MRCM_STAGE_RHS, s);
     ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, h->X, s));
   }
+  const bool split = !fp32 && h->refine64 > 0 && h->n_first > 0;
+  const int n_work = (int)H.work.size();
   {
     Stage t(MRCM_STAGE_SOLVE, s);
-    ENQ(launch_solve(fp32, g, h->d_work, (int)H.work.size(), h->scal, h->L, h->Dinv, h->X, h->X, 0,
+    ENQ(launch_solve(fp32, g, h->d_work, split ? h->n_first : n_work, h->scal, h->L, h->Dinv, h->X, h->X, 0,
                      H.bmax, s));
   }
   h->ir_iters = 0;
   h->ir_res = 0.0;
-  if (!fp32 && h->refine64 > 0) {
-    if (!h->R) {
-      if (dev_alloc(&h->R, (size_t)H.totX) != hipSuccess)
-        return bail(fail(MRCM_ENOMEM, "device allocation of the refinement buffer failed"));
-      h->bytes += H.totX * 8;
+  if (!fp32 && h->refine64 > 0 && !h->R) {
+    if (dev_alloc(&h->R, (size_t)H.totX) != hipSuccess)
+      return bail(fail(MRCM_ENOMEM, "device allocation of the refinement buffer failed"));
+    h->bytes += H.totX * 8;
+  }
+  if (split) {
+    // Group 0 (one full round of resident workgroups) is solved; its
+    // residuals and corrections run on the second stream while the caller's
+    // stream solves group 1 and refines it; the streams join before the
+    // fluxes.  The groups hold disjoint subdomains, so they touch disjoint
+    // parts of X and R.
+    Stage t(MRCM_STAGE_REFINE, s);
+    const int4 *w1 = h->d_work + h->n_first;
+    const int n1 = n_work - h->n_first;
+    ENQ(hipEventRecord(h->ev_fork, s));
+    ENQ(hipStreamWaitEvent(h->s2, h->ev_fork, 0));
+    for (int it = 0; it < h->refine64; ++it) {
+      ENQ(launch_residual(g, h->n_grp_subs[0], H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, h->s2,
+                          h->d_grp_subs[0]));
+      ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->R, h->X, 1, H.bmax, h->s2));
     }
+    ENQ(hipEventRecord(h->ev_join, h->s2));
+    ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->X, h->X, 2, H.bmax, s));
+    for (int it = 0; it < h->refine64; ++it) {
+      ENQ(launch_residual(g, h->n_grp_subs[1], H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s,
+                          h->d_grp_subs[1]));
+      ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->R, h->X, 3, H.bmax, s));
+    }
+    ENQ(hipStreamWaitEvent(s, h->ev_join, 0));
+    h->ir_iters = h->refine64;
+  } else if (!fp32 && h->refine64 > 0) {
     for (int it = 0; it < h->refine64; ++it) {
       {
         Stage t(MRCM_STAGE_RESIDUAL, s);
@@ -861,6 +937,7 @@ mrcm_status mrcm_get_subdomain(const mrcm_mbfs *mb, int32_t l, mrcm_subdomain_in
   info->n_rhs = S.m;
   info->n_patch = S.npatch;
   info->pin_local = S.pin_local;
+  info->solve_group = mb->solve_group.empty() ? 0 : mb->solve_group[l];
   return MRCM_OK;
 }
 

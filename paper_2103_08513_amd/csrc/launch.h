@@ -23,9 +23,11 @@ hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, const double *r0,
 int solve_chunk_max();
 size_t factor_lds_bytes(int fp32, int bmax);
 size_t solve_lds_bytes(int fp32, int bmax, int mmax);
+// subs: the subdomains to take (n_sub of them), or null for 0 .. n_sub-1
 hipError_t launch_residual(const Geom &g, int n_sub, int max_cells, const double *coef,
                            const double *r0, const double *X, double *R, double *norms,
-                           hipStream_t s);
+                           hipStream_t s, const int *subs = nullptr);
+int solve_blocks_per_cu(int fp32, int bmax);
 hipError_t launch_ir_check(const double *norms, int ncols, double *out, hipStream_t s);
 hipError_t launch_flux(const Geom &g, int n_sub, const double *X, double *F, double *Fb,
                        double *SAb, hipStream_t s);

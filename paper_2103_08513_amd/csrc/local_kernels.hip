@@ -1022,7 +1022,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 8 && KS > 28) ? 1 : 2) void k_so
             const double s = scaled ? sc[k + row] : 1.0;
             const double xv = s * (double)acc[v];
             double *dst = Xo + (size_t)(k + row) * m + c0 + col;
-            if (mode == 0) *dst = xv;
+            if ((mode & 1) == 0) *dst = xv;
             else *dst += xv;
           }
         }
@@ -1041,16 +1041,17 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, const double *__restri
                                                   const double *__restrict__ r0,
                                                   const double *__restrict__ Xg,
                                                   double *__restrict__ Rbuf,
-                                                  double *__restrict__ norms, int ntile, int n_sub) {
+                                                  double *__restrict__ norms, int ntile, int n_sub,
+                                                  const int *__restrict__ subs) {
   __shared__ double tile[kRowsPB * kMaxRhs];
   __shared__ double red[2 * kMaxRhs];
   // XCD-aware order: workgroups go round-robin to the eight XCDs, so XCD x
   // gets subdomains x, x + 8, ... with all their row tiles in sequence, and
   // the stencil's neighbour rows come from that XCD's L2
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-  const int sub = xcd + 8 * (slot / ntile);
-  if (sub >= n_sub) return;
-  const SubDesc &S = g.sub[sub];
+  const int isub = xcd + 8 * (slot / ntile);
+  if (isub >= n_sub) return;
+  const SubDesc &S = g.sub[subs ? subs[isub] : isub];
   const int m = S.m, N = S.N;
   const int rbase = (slot % ntile) * kRowsPB;
   if (rbase >= N) return;
@@ -1275,16 +1276,34 @@ static hipError_t launch_solve_m(const Geom &g, const int4 *work, int n_work, co
 hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, const double *scal,
                         const void *L, const void *Dg, double *B, double *X, int mode, int bmax,
                         hipStream_t s) {
-  // separate instantiations per mode, so that profiles tell the first solve
-  // from the refinement corrections
+  // Separate instantiations per mode, so that profiles tell them apart: bit 0
+  // set for a correction (X += ...), bit 1 set for the second group of work
+  // items when the first solve is split (FP64 path only).
   if (fp32) {
     if (mode == 0)
       return launch_solve_m<float, 0>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax, s);
     return launch_solve_m<float, 1>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax, s);
   }
-  if (mode == 0)
-    return launch_solve_m<double, 0>(g, work, n_work, scal, (const double *)L, (const double *)Dg, B, X, bmax, s);
-  return launch_solve_m<double, 1>(g, work, n_work, scal, (const double *)L, (const double *)Dg, B, X, bmax, s);
+  const double *Ld = (const double *)L, *Dd = (const double *)Dg;
+  switch (mode) {
+    case 0: return launch_solve_m<double, 0>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s);
+    case 1: return launch_solve_m<double, 1>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s);
+    case 2: return launch_solve_m<double, 2>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s);
+    default: return launch_solve_m<double, 3>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s);
+  }
+}
+
+// Workgroups of the solve that one CU holds at once.
+int solve_blocks_per_cu(int fp32, int bmax) {
+  const size_t lds = solve_lds_bytes(fp32, bmax, 0);
+  const void *k = fp32 ? (bmax <= 112 ? (const void *)k_solve<float, 0, 3, 28>
+                                      : (const void *)k_solve<float, 0, 3, (kMaxBand32 + 3) / 4>)
+                       : (bmax <= 112 ? (const void *)k_solve<double, 0, 3, 28>
+                                      : (const void *)k_solve<double, 0, 3, (kMaxBand32 + 3) / 4>);
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, lds) != hipSuccess) return 0;
+  return nb;
 }
 
 hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, const double *r0, double *B,
@@ -1296,10 +1315,10 @@ hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, const double *r0,
 
 hipError_t launch_residual(const Geom &g, int n_sub, int max_cells, const double *coef,
                            const double *r0, const double *X, double *R, double *norms,
-                           hipStream_t s) {
+                           hipStream_t s, const int *subs) {
   const int ntile = (max_cells + kRowsPB - 1) / kRowsPB;
   const long long nblk = 8LL * ntile * ((n_sub + 7) / 8);
-  hipLaunchKernelGGL(k_residual, dim3((unsigned)nblk), dim3(256), 0, s, g, coef, r0, X, R, norms, ntile, n_sub);
+  hipLaunchKernelGGL(k_residual, dim3((unsigned)nblk), dim3(256), 0, s, g, coef, r0, X, R, norms, ntile, n_sub, subs);
   return hipGetLastError();
 }
 

@@ -205,7 +205,13 @@ def test_config2_sampled_subdomains():
     m.build_mbfs(_dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q))
     torch.cuda.synchronize()
     geo = Geometry(pb.dims, case.partition, case.iface)
-    sample = [0, 1, 4, 37, 280, 300, 560, geo.n_sub // 2]
+    # the FP64 first solve is split into resident rounds when the work exceeds
+    # one (group 1 is solved and refined beside group 0's refinement): take
+    # subdomains of both groups
+    groups = [m.subdomain(l).solve_group for l in range(geo.n_sub)]
+    late = [l for l in range(geo.n_sub) if groups[l] == 1]
+    sample = sorted(set([0, 1, 4, 37, 280, 300, 560, geo.n_sub // 2] + late[:2] + late[-1:]))
+    print(f"cfg2: {len(late)} subdomains in the second solve group; sample {sample}", flush=True)
     systems, Xs, Fs, Fbs, SAbs = oracle_build(pb, geo, case.alpha, subdomains=sample)
     for l, X, F in zip(sample, Xs, Fs):
         Xg = m.copy_mbfs(l)[np.argsort(m.local_order(l))]
