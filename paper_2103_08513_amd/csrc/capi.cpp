@@ -445,6 +445,8 @@ struct mrcm_mbfs {
   int n_first = 0;
   std::vector<int> solve_group;  // per subdomain
   int *d_grp_subs[2] = {nullptr, nullptr};
+  int *d_order_split = nullptr;  // group 0's subdomains, then group 1's
+  int n_fac_main = 0;            // subdomains factored before the fork (whole factor rounds)
   int n_grp_subs[2] = {0, 0};
   hipStream_t s2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -484,7 +486,7 @@ void free_mbfs(mrcm_mbfs *h) {
   if (!h) return;
   void *ptrs[] = {h->d_sub, h->d_ifc, h->d_order, h->d_work, h->d_patches, h->d_subof[0], h->d_subof[1],
                   h->d_subof[2], h->coef, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, h->F, h->Fb, h->SAb,
-                  h->norms, h->scalar, h->st, h->d_grp_subs[0], h->d_grp_subs[1]};
+                  h->norms, h->scalar, h->st, h->d_grp_subs[0], h->d_grp_subs[1], h->d_order_split};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
@@ -552,9 +554,24 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    // a multiple of 8 keeps every item on its XCD (workgroup i on XCD i mod 8)
-    const size_t slots = ((size_t)ncu * solve_blocks_per_cu(0, G.bmax) / 8) * 8;
-    if (slots > 0 && slots < G.work.size()) {
+    // The factorisation runs whole rounds of resident workgroups and a last,
+    // partial round (the tail).  Group 0 is what the solve can hold beside
+    // the tail: its first solve starts when the whole rounds are factored,
+    // on the CUs the tail leaves free.  A multiple of 8 keeps every item on
+    // its XCD (workgroup i runs on XCD i mod 8).
+    const int fpc = std::max(1, factor64_blocks_per_cu(G.bmax));
+    const int spc = solve_blocks_per_cu(0, G.bmax);
+    const int n_sub_all = (int)G.subs.size();
+    const int tail = n_sub_all % (ncu * fpc);
+    const int tail_cus = (tail + fpc - 1) / fpc;
+    size_t slots = (size_t)std::max(0, ncu - tail_cus) * spc;
+    slots = std::min(slots, (size_t)(n_sub_all - tail));
+    slots = (slots / 8) * 8;
+    // the factor's whole rounds must cover group 0: true when every work
+    // item is one whole subdomain taken in factor order, checked below
+    bool in_order = G.work.size() >= (size_t)n_sub_all;
+    for (size_t i = 0; in_order && i < (size_t)n_sub_all; ++i) in_order = G.work[i].x == G.order[i];
+    if (in_order && slots > 0 && slots < G.work.size()) {
       std::vector<int> grp(G.subs.size(), -1);
       bool whole = true;
       for (size_t i = 0; i < G.work.size(); ++i) {
@@ -574,6 +591,10 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
           HIP_TRY(upload(&h->d_grp_subs[gi], lists[gi]));
           h->n_grp_subs[gi] = (int)lists[gi].size();
         }
+        std::vector<int> ord(lists[0]);
+        ord.insert(ord.end(), lists[1].begin(), lists[1].end());
+        HIP_TRY(upload(&h->d_order_split, ord));
+        h->n_fac_main = n_sub_all - tail;
         for (size_t l = 0; l < grp.size(); ++l) h->solve_group[l] = std::max(0, grp[l]);
         HIP_TRY(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
@@ -694,21 +715,11 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     ENQ(launch_coef(g, h->n_sub, H.max_cells, h->coef, h->r0, h->scal, s));
   }
   {
-    Stage t(MRCM_STAGE_FACTOR, s);
-    ENQ(launch_factor(fp32, h->d_sub, h->d_order, h->n_sub, h->coef, h->scal, h->L, h->Dinv, h->st,
-                      H.bmax, s));
-  }
-  {
     Stage t(MRCM_STAGE_RHS, s);
     ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, h->X, s));
   }
   const bool split = !fp32 && h->refine64 > 0 && h->n_first > 0;
   const int n_work = (int)H.work.size();
-  {
-    Stage t(MRCM_STAGE_SOLVE, s);
-    ENQ(launch_solve(fp32, g, h->d_work, split ? h->n_first : n_work, h->scal, h->L, h->Dinv, h->X, h->X, 0,
-                     H.bmax, s));
-  }
   h->ir_iters = 0;
   h->ir_res = 0.0;
   if (!fp32 && h->refine64 > 0 && !h->R) {
@@ -717,30 +728,57 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     h->bytes += H.totX * 8;
   }
   if (split) {
-    // Group 0 (one full round of resident workgroups) is solved; its
-    // residuals and corrections run on the second stream while the caller's
-    // stream solves group 1 and refines it; the streams join before the
-    // fluxes.  The groups hold disjoint subdomains, so they touch disjoint
-    // parts of X and R.
-    Stage t(MRCM_STAGE_REFINE, s);
-    const int4 *w1 = h->d_work + h->n_first;
-    const int n1 = n_work - h->n_first;
-    ENQ(hipEventRecord(h->ev_fork, s));
+    // Per-subdomain pipeline over two streams.  The whole rounds of the
+    // factorisation go first; group 0's first solve, residuals and
+    // corrections then run on the second stream while the caller's stream
+    // factors the last, partial round and solves and refines group 1 (the
+    // rest of the subdomains).  The streams join before the fluxes.  The
+    // groups hold disjoint subdomains, so they touch disjoint parts of L,
+    // Dinv, X and R; group 0 lies inside the whole rounds.
+    const int n0 = h->n_grp_subs[0], n1s = h->n_grp_subs[1];
+    {
+      Stage t(MRCM_STAGE_FACTOR, s);
+      const int nm = h->n_fac_main;
+      ENQ(launch_factor(fp32, h->d_sub, h->d_order_split, nm, h->coef, h->scal, h->L, h->Dinv, h->st,
+                        H.bmax, s));
+      ENQ(hipEventRecord(h->ev_fork, s));
+      if (h->n_sub > nm)
+        ENQ(launch_factor(fp32, h->d_sub, h->d_order_split + nm, h->n_sub - nm, h->coef, h->scal, h->L, h->Dinv,
+                          h->st, H.bmax, s));
+    }
     ENQ(hipStreamWaitEvent(h->s2, h->ev_fork, 0));
+    {
+      Stage t(MRCM_STAGE_SOLVE, h->s2);
+      ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->X, h->X, 0, H.bmax, h->s2));
+    }
     for (int it = 0; it < h->refine64; ++it) {
-      ENQ(launch_residual(g, h->n_grp_subs[0], H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, h->s2,
-                          h->d_grp_subs[0]));
+      ENQ(launch_residual(g, n0, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, h->s2, h->d_grp_subs[0]));
       ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->R, h->X, 1, H.bmax, h->s2));
     }
     ENQ(hipEventRecord(h->ev_join, h->s2));
+    Stage t(MRCM_STAGE_REFINE, s);
+    const int4 *w1 = h->d_work + h->n_first;
+    const int n1 = n_work - h->n_first;
     ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->X, h->X, 2, H.bmax, s));
     for (int it = 0; it < h->refine64; ++it) {
-      ENQ(launch_residual(g, h->n_grp_subs[1], H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s,
-                          h->d_grp_subs[1]));
+      ENQ(launch_residual(g, n1s, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s, h->d_grp_subs[1]));
       ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->R, h->X, 3, H.bmax, s));
     }
     ENQ(hipStreamWaitEvent(s, h->ev_join, 0));
     h->ir_iters = h->refine64;
+  } else {
+    {
+      Stage t(MRCM_STAGE_FACTOR, s);
+      ENQ(launch_factor(fp32, h->d_sub, h->d_order, h->n_sub, h->coef, h->scal, h->L, h->Dinv, h->st,
+                        H.bmax, s));
+    }
+    {
+      Stage t(MRCM_STAGE_SOLVE, s);
+      ENQ(launch_solve(fp32, g, h->d_work, n_work, h->scal, h->L, h->Dinv, h->X, h->X, 0, H.bmax, s));
+    }
+  }
+  if (split) {
+    // refinement done in the pipeline above
   } else if (!fp32 && h->refine64 > 0) {
     for (int it = 0; it < h->refine64; ++it) {
       {

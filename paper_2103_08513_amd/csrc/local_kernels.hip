@@ -1293,6 +1293,16 @@ hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, c
   }
 }
 
+// Workgroups of the FP64 factorisation that one CU holds at once.
+int factor64_blocks_per_cu(int bmax) {
+  const size_t lds = factor_lds_bytes(0, bmax);
+  const void *k = (const void *)k_factor64<(kMaxBand64 + 15) / 16 - 1>;
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 512, lds) != hipSuccess) return 0;
+  return nb;
+}
+
 // Workgroups of the solve that one CU holds at once.
 int solve_blocks_per_cu(int fp32, int bmax) {
   const size_t lds = solve_lds_bytes(fp32, bmax, 0);
