@@ -658,61 +658,145 @@ __global__ __launch_bounds__(kSweepThreads) void k_band_sweep(const double *__re
 }
 
 // Backward sweep U x = y by chunks of kChunk = 128 unknowns, last chunk
-// first, two launches per chunk.  k_usweep_chunk (one workgroup) solves the
-// chunk's own triangle: its rows already hold y minus the contributions of
-// every later chunk.  Wave 0 solves each 16-block with the stored inverse,
-// U_bb^{-1} = L11^{-T} D^{-1}, while waves 1 and 2 (one row each) subtract the
-// block from the rows above it in the chunk; all their band entries are
-// loaded at the start.  k_usweep_update then subtracts the solved chunk from
-// the up to w rows above it, spread over workgroups of 64 rows, which is
-// where nearly all of the band is read -- in parallel rather than through a
-// single compute unit.
+// first, one launch per chunk.  The launch for the chunk at c0 also applies
+// the chunk solved by the previous launch (at cn = c0 + 128):
+//   workgroup 0 subtracts it from the chunk's own rows and then solves the
+//     chunk's triangle: wave 0 solves each 16-block with the stored inverse,
+//     U_bb^{-1} = L11^{-T} D^{-1}, while waves 1-4 subtract it from the rows
+//     above it in the chunk;
+//   workgroups 1.. subtract it from the rows above the chunk (up to w rows
+//     above cn), 64 rows each -- nearly all of the band is read there, in
+//     parallel rather than through a single compute unit.
+// The two parts write disjoint rows and read only the finished chunk at cn.
 constexpr int kChunk = 128;
 constexpr int kChunkBlocks = kChunk / kSW;
+constexpr int kStepT = 512;
 
-__global__ __launch_bounds__(192) void k_usweep_chunk(const double *__restrict__ AB,
-                                                      const double *__restrict__ inv, int n, int w,
-                                                      double *__restrict__ x, int c0) {
+// Rows [lo, hi) minus U(rows, cn .. cn+mn-1) x(cn ..): 64 rows from row0,
+// one per lane, wave q taking columns 16q .. 16q+15 (eight waves).
+__device__ __forceinline__ void usweep_far(const double *__restrict__ AB, int w, double *__restrict__ x,
+                                           int cn, int mn, int row0, int hi, double *xc, double *part) {
+  const int ld = 2 * w + 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = row0 + lane;
+  if (tid < kChunk) xc[tid] = tid < mn ? x[cn + tid] : 0.0;
+  double a[kSW];
+  unsigned msk = 0u;
+#pragma unroll
+  for (int c = 0; c < kSW; ++c) {
+    const int j = cn + kSW * wave + c;
+    const bool ok = i < hi && j < cn + mn && j - i <= w;
+    a[c] = AB[ok ? (size_t)j * ld + (w + i - j) : 0];
+    msk |= ok ? (1u << c) : 0u;
+  }
+  __syncthreads();
+  double acc = 0.0, acd = 0.0;
+#pragma unroll
+  for (int c = 0; c < kSW; c += 2) {
+    acc += ((msk >> c) & 1u ? a[c] : 0.0) * xc[kSW * wave + c];
+    acd += ((msk >> (c + 1)) & 1u ? a[c + 1] : 0.0) * xc[kSW * wave + c + 1];
+  }
+  part[wave * 64 + lane] = acc + acd;
+  __syncthreads();
+  if (wave == 0 && i < hi) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kStepT / 64; ++q) t += part[q * 64 + lane];
+    x[i] -= t;
+  }
+}
+
+__global__ __launch_bounds__(kStepT) void k_usweep_step(const double *__restrict__ AB,
+                                                        const double *__restrict__ inv, int n, int w,
+                                                        double *__restrict__ x, int c0, int has_next) {
   __shared__ double xs[kChunk];
   __shared__ double lt[kChunkBlocks * kInvStride];
+  __shared__ double part[kStepT];  // far: per-wave sums; near: 4 x 128 partial sums
+  __shared__ double xcn[kChunk];   // near: the x of the chunk at cn
   const int ld = 2 * w + 1;
   const int m = min(kChunk, n - c0);
+  const int cn = c0 + kChunk;
+  const int mn = has_next ? min(kChunk, n - cn) : 0;
+  if (blockIdx.x > 0) {
+    const int lo = max(0, cn - w);
+    usweep_far(AB, w, x, cn, mn, lo + 64 * (blockIdx.x - 1), c0, xs, part);
+    return;
+  }
   const int nbk = (m + kSW - 1) / kSW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // the chunk's right-hand side and block inverses: every load issued before
-  // the first LDS store (a loop of load-then-store would wait out the memory
-  // latency once per trip)
-  constexpr int kLtPer = (kChunkBlocks * kInvStride + 191) / 192;
+  // First the near update on all waves: row tid & 127 of the chunk against
+  // columns 32 q .. 32 q + 31 of the chunk at cn, q = tid >> 7.  Then the
+  // chunk's triangle on waves 1-4 (t = tid - 64): waves 1-2 hold row t & 127's
+  // entries in blocks 1..4 of the chunk, waves 3-4 in blocks 5..7 (only
+  // blocks above the row's own block are used).  The two phases' operands
+  // are never live together.
+  const bool rw = wave >= 1 && wave <= 4;
+  const int t = tid - 64, row = t & 127, half = t >> 7;
+  // global loads first: the block inverses, the chunk's right-hand side and
+  // the x of the chunk at cn, the near band block
+  constexpr int kLtPer = (kChunkBlocks * kInvStride + kStepT - 1) / kStepT;
   const double *iv = inv + (size_t)(c0 / kSW) * kInvStride;
   const int nlt = nbk * kInvStride;
   double ltv[kLtPer];
 #pragma unroll
-  for (int q = 0; q < kLtPer; ++q) ltv[q] = iv[min(tid + 192 * q, nlt - 1)];
+  for (int q = 0; q < kLtPer; ++q) ltv[q] = iv[min(tid + kStepT * q, nlt - 1)];
   const double xv0 = x[c0 + min(tid, m - 1)];
-  if (tid < kChunk) xs[tid] = tid < m ? xv0 : 0.0;
+  const double xn0 = mn > 0 ? x[cn + min(tid, mn - 1)] : 0.0;
+  const int nrow = tid & 127, nq = tid >> 7;
+  double nb[32];
+  unsigned nmsk = 0u;
+  if (mn > 0) {
+    const int i = c0 + nrow;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+      const int j = cn + 32 * nq + c;
+      const bool ok = nrow < m && j < cn + mn && j - i <= w;
+      nb[c] = AB[ok ? (size_t)j * ld + (w + i - j) : 0];
+      nmsk |= ok ? (1u << c) : 0u;
+    }
+  }
+  if (tid < kChunk) {
+    xs[tid] = tid < m ? xv0 : 0.0;
+    xcn[tid] = tid < mn ? xn0 : 0.0;
+  }
 #pragma unroll
   for (int q = 0; q < kLtPer; ++q)
-    if (tid + 192 * q < nlt) lt[tid + 192 * q] = ltv[q];
-  // waves 1, 2: row t of the chunk; u[bb-1][c] = U(c0 + t, c0 + 16 bb + c)
-  // for blocks bb above the row's own block, loaded unconditionally at a
-  // clamped address, with the validity in a bit mask
-  const int t = tid - 64;
-  double u[kChunkBlocks - 1][kSW];
-  unsigned msk[kChunkBlocks - 1];
-  if (wave > 0) {
-    const int i = c0 + t;
+    if (tid + kStepT * q < nlt) lt[tid + kStepT * q] = ltv[q];
+  __syncthreads();
+  {
+    double acc = 0.0, acd = 0.0;
+    if (mn > 0) {
+      const double *xc = xcn + 32 * nq;
 #pragma unroll
-    for (int bb = 1; bb < kChunkBlocks; ++bb) {
-      msk[bb - 1] = 0u;
+      for (int c = 0; c < 32; c += 2) {
+        acc += ((nmsk >> c) & 1u ? nb[c] : 0.0) * xc[c];
+        acd += ((nmsk >> (c + 1)) & 1u ? nb[c + 1] : 0.0) * xc[c + 1];
+      }
+    }
+    part[nq * kChunk + nrow] = acc + acd;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // the triangle's band entries: u[k][c] = U(c0 + row, c0 + 16 bb + c) with
+  // bb = 1 + k (waves 1-2) or 5 + k (waves 3-4)
+  double u[4][kSW];
+  unsigned msk[4];
+  if (rw) {
+    const int i = c0 + row;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int bb = (half ? 5 : 1) + k;
+      msk[k] = 0u;
 #pragma unroll
       for (int c = 0; c < kSW; ++c) {
         const int j = c0 + kSW * bb + c;
-        const bool ok = t < kSW * bb && j < c0 + m && j - i <= w;
-        u[bb - 1][c] = AB[ok ? (size_t)j * ld + (w + i - j) : 0];
-        msk[bb - 1] |= ok ? (1u << c) : 0u;
+        const bool ok = bb < kChunkBlocks && row < kSW * bb && j < c0 + m && j - i <= w;
+        u[k][c] = AB[ok ? (size_t)j * ld + (w + i - j) : 0];
+        msk[k] |= ok ? (1u << c) : 0u;
       }
     }
   }
+  __syncthreads();
+  if (tid < m) xs[tid] -= (part[tid] + part[kChunk + tid]) + (part[2 * kChunk + tid] + part[3 * kChunk + tid]);
   __syncthreads();
 #pragma unroll
   for (int bb = kChunkBlocks - 1; bb >= 0; --bb) {
@@ -732,52 +816,21 @@ __global__ __launch_bounds__(192) void k_usweep_chunk(const double *__restrict__
         if (lane < kb) xs[b0 + lane] = xv + xw;
       }
       __syncthreads();
-      if (bb > 0 && wave > 0 && t < b0) {
+      // block bb's owners: waves 1-2 for bb = 1..4, waves 3-4 for bb = 5..7
+      if (bb > 0 && rw && half == (bb >= 5 ? 1 : 0) && row < b0) {
+        const int k = bb - (bb >= 5 ? 5 : 1);
         double acc = 0.0, acd = 0.0;
 #pragma unroll
         for (int c = 0; c < kSW; c += 2) {
-          acc += ((msk[bb - 1] >> c) & 1u ? u[bb - 1][c] : 0.0) * xs[b0 + c];
-          acd += ((msk[bb - 1] >> (c + 1)) & 1u ? u[bb - 1][c + 1] : 0.0) * xs[b0 + c + 1];
+          acc += ((msk[k] >> c) & 1u ? u[k][c] : 0.0) * xs[b0 + c];
+          acd += ((msk[k] >> (c + 1)) & 1u ? u[k][c + 1] : 0.0) * xs[b0 + c + 1];
         }
-        xs[t] -= acc + acd;
+        xs[row] -= acc + acd;
       }
       __syncthreads();
     }
   }
-  for (int e = tid; e < m; e += 192) x[c0 + e] = xs[e];
-}
-
-// Rows [max(0, c0 - w), c0) minus U(rows, chunk) x_chunk.  Workgroup g takes
-// 64 rows (one per lane); wave q the chunk columns 32q .. 32q + 31.
-__global__ __launch_bounds__(256) void k_usweep_update(const double *__restrict__ AB, int n, int w,
-                                                       double *__restrict__ x, int c0) {
-  __shared__ double xc[kChunk];
-  __shared__ double part[4][64];
-  const int ld = 2 * w + 1;
-  const int m = min(kChunk, n - c0);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lo = max(0, c0 - w);
-  const int i = lo + 64 * blockIdx.x + lane;
-  for (int e = tid; e < kChunk; e += 256) xc[e] = e < m ? x[c0 + e] : 0.0;
-  double a[32];
-  unsigned msk = 0u;
-#pragma unroll
-  for (int c = 0; c < 32; ++c) {
-    const int j = c0 + 32 * wave + c;
-    const bool ok = i < c0 && j < c0 + m && j - i <= w;
-    a[c] = AB[ok ? (size_t)j * ld + (w + i - j) : 0];
-    msk |= ok ? (1u << c) : 0u;
-  }
-  __syncthreads();
-  double acc = 0.0, acd = 0.0;
-#pragma unroll
-  for (int c = 0; c < 32; c += 2) {
-    acc += ((msk >> c) & 1u ? a[c] : 0.0) * xc[32 * wave + c];
-    acd += ((msk >> (c + 1)) & 1u ? a[c + 1] : 0.0) * xc[32 * wave + c + 1];
-  }
-  part[wave][lane] = acc + acd;
-  __syncthreads();
-  if (wave == 0 && i < c0) x[i] -= (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+  if (tid < m) x[c0 + tid] = xs[tid];
 }
 
 // r = b - A x with the unfactored band (one thread per row).
@@ -960,11 +1013,16 @@ hipError_t launch_band_ldl(const double *AB0, double *AB, const double *b0, doub
 hipError_t launch_lu_sweep(const double *AB, const double *inv, int n, int w, double *x, int upper,
                            hipStream_t s) {
   if (upper) {
-    for (int c0 = ((n - 1) / kChunk) * kChunk; c0 >= 0; c0 -= kChunk) {
-      hipLaunchKernelGGL(k_usweep_chunk, dim3(1), dim3(192), 0, s, AB, inv, n, w, x, c0);
-      const int rows = c0 - std::max(0, c0 - w);
-      if (rows > 0) hipLaunchKernelGGL(k_usweep_update, dim3((rows + 63) / 64), dim3(256), 0, s, AB, n, w, x, c0);
+    const int last = ((n - 1) / kChunk) * kChunk;
+    for (int c0 = last; c0 >= 0; c0 -= kChunk) {
+      const int has_next = c0 < last;
+      // rows above this chunk that the chunk at c0 + kChunk still reaches
+      const int far = has_next ? c0 - std::max(0, c0 + kChunk - w) : 0;
+      hipLaunchKernelGGL(k_usweep_step, dim3(1 + (far > 0 ? (far + 63) / 64 : 0)), dim3(kStepT), 0, s, AB, inv, n,
+                         w, x, c0, has_next);
     }
+    // the first chunk's contribution to rows above it: there are none
+
     return hipGetLastError();
   }
   if (n <= kSweepLdsMax) {
