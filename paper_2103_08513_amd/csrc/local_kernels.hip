@@ -753,6 +753,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 8 && KS > 28) ? 1 : 2) void k_so
   T *Dp = Lp + kNB * ldb;                       // [kNB*kNB]
   T *Y = Dp + kNB * kNB;                        // ring [wmax][kMaxChunk] (stride CP)
   T *Zs = Y + (size_t)wmax * kMaxChunk;         // [16][kMaxChunk]
+  T *Zp = Zs + (size_t)kNB * kMaxChunk;         // [16][kMaxChunk]: second part of the backward K split
   const T *L = Lg + D.L_off;
   const T *Dinv = Dg + D.D_off;
   double *B = Bg + D.X_off;
@@ -970,36 +971,78 @@ __global__ __launch_bounds__(256, (sizeof(T) == 8 && KS > 28) ? 1 : 2) void k_so
       fetch_panel(p - 1);
       fetch_y(p - 1);
     }
-    // Z = Y1 - L21^T X2 over K = b, as four independent MFMA chains, the
-    // operands loaded in two halves
-    if (wave < nct) {
-      constexpr int KH = (KS + 1) / 2;
-      const typename M::v4 z = {T(0), T(0), T(0), T(0)};
-      typename M::v4 p1 = z, p2 = z, p3 = z;
+    // Z = Y1 - L21^T X2 over K = b (the offsets t = 4 s2 + lk, s2 < KS), split
+    // so that all four waves take part: with up to two column tiles, wave w
+    // takes tile w & 1 over half w >> 1 of K; with three, waves 0-2 take
+    // tile w over the first three quarters of K and wave 3 the last quarter
+    // of all three tiles.  The first part (with Y1) goes to Zs, the second
+    // to Zp; X1 adds them.  Each part runs as independent MFMA chains with
+    // all its operands loaded first.
+    {
+      // one K range [s0, s0 + NS) of the sum for column tile ct, into acc, in
+      // batches of at most 14 steps (operands of a batch loaded first)
+      auto zpart = [&](auto ns_c, int s0, int ct, typename M::v4 &acc) {
+        constexpr int NS = decltype(ns_c)::value;
+        constexpr int KB = 14;
+        // lane-derived offsets recomputed per panel: hoisted out of the
+        // panel loop they would hold dozens of registers across it
+        int lkk = lk, lrr = lr;
+        asm volatile("" : "+v"(lkk), "+v"(lrr));
+        const typename M::v4 z = {T(0), T(0), T(0), T(0)};
+        typename M::v4 p1 = z, p2 = z, p3 = z;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        T a[KH], bb[KH];
+        for (int q = 0; q < (NS + KB - 1) / KB; ++q) {
+          T a[KB], bb[KB];
 #pragma unroll
-        for (int s3 = 0; s3 < KH; ++s3) {
-          const int s2 = h * KH + s3;
-          const int t = 4 * s2 + lk;
-          // offsets clamped into the panel row; entries past the band meet a
-          // zero operand
-          a[s3] = lp[lr * ldb + (kNB + min(t, b - 1) - lr)];
-          bb[s3] = (t < b) ? Y[wrap(sk + kNB + min(t, b - 1), W) * CP + wave * 16 + lr] : T(0);
+          for (int s3 = 0; s3 < KB; ++s3) {
+            if (q * KB + s3 < NS) {
+              const int t = 4 * (s0 + q * KB + s3) + lkk;
+              // offsets clamped into the panel row; entries past the band
+              // meet a zero operand
+              a[s3] = lp[lrr * ldb + (kNB + min(t, b - 1) - lrr)];
+              bb[s3] = (t < b) ? Y[wrap(sk + kNB + min(t, b - 1), W) * CP + ct * 16 + lrr] : T(0);
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int s3 = 0; s3 < KB; s3 += 4) {
+            if (q * KB + s3 < NS) acc = M::mma(-a[s3], bb[s3], acc);
+            if (q * KB + s3 + 1 < NS && s3 + 1 < KB) p1 = M::mma(-a[s3 + 1], bb[s3 + 1], p1);
+            if (q * KB + s3 + 2 < NS && s3 + 2 < KB) p2 = M::mma(-a[s3 + 2], bb[s3 + 2], p2);
+            if (q * KB + s3 + 3 < NS && s3 + 3 < KB) p3 = M::mma(-a[s3 + 3], bb[s3 + 3], p3);
+          }
         }
+        acc = (acc + p1) + (p2 + p3);
         __builtin_amdgcn_sched_barrier(0);
+      };
+      auto zstore = [&](T *dst, int ct, const typename M::v4 &acc) {
 #pragma unroll
-        for (int s3 = 0; s3 < KH; s3 += 4) {
-          c = M::mma(-a[s3], bb[s3], c);
-          if (s3 + 1 < KH) p1 = M::mma(-a[s3 + 1], bb[s3 + 1], p1);
-          if (s3 + 2 < KH) p2 = M::mma(-a[s3 + 2], bb[s3 + 2], p2);
-          if (s3 + 3 < KH) p3 = M::mma(-a[s3 + 3], bb[s3 + 3], p3);
+        for (int v = 0; v < 4; ++v) dst[M::crow(v, lane) * CP + ct * 16 + lr] = acc[v];
+      };
+      const typename M::v4 z = {T(0), T(0), T(0), T(0)};
+      if (nct <= 2) {
+        constexpr int KH = (KS + 1) / 2;
+        const int ct = wave & 1, h = wave >> 1;
+        if (ct < nct) {
+          typename M::v4 acc = h ? z : c;
+          zpart(std::integral_constant<int, KH>{}, h * KH, ct, acc);
+          zstore(h ? Zp : Zs, ct, acc);
+        }
+      } else {
+        constexpr int K1 = (3 * KS + 3) / 4, K2 = KS - K1;
+        if (wave < 3) {
+          typename M::v4 acc = c;
+          zpart(std::integral_constant<int, K1>{}, 0, wave, acc);
+          zstore(Zs, wave, acc);
+        } else {
+#pragma unroll
+          for (int ct = 0; ct < 3; ++ct) {
+            typename M::v4 acc = z;
+            zpart(std::integral_constant<int, K2>{}, K1, ct, acc);
+            zstore(Zp, ct, acc);
+          }
         }
       }
-      c = (c + p1) + (p2 + p3);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Zs[M::crow(v, lane) * CP + wave * 16 + lr] = c[v];
     }
     __syncthreads();
     // X1 = inv(L11)^T Z
@@ -1010,7 +1053,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 8 && KS > 28) ? 1 : 2) void k_so
       for (int s = 0; s < 4; ++s) {
         const int jj = 4 * s + lk;
         a[s] = dp[jj * kNB + lr];
-        bb[s] = Zs[jj * CP + wave * 16 + lr];
+        bb[s] = Zs[jj * CP + wave * 16 + lr] + Zp[jj * CP + wave * 16 + lr];
       }
       acc = mma16_split<T>(a, bb, acc);
 #pragma unroll
@@ -1216,7 +1259,7 @@ size_t solve_lds_bytes(int fp32, int bmax, int mmax) {
   (void)mmax;
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
   return ((size_t)kNB * solve_ldb(bmax) + kNB * kNB + (size_t)(bmax + kNB) * kMaxChunk +
-          (size_t)kNB * kMaxChunk) * es;
+          (size_t)2 * kNB * kMaxChunk) * es;
 }
 
 int solve_chunk_max() { return kMaxChunk; }
