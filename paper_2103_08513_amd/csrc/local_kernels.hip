@@ -731,8 +731,8 @@ __device__ __forceinline__ typename Mma<T>::v4 mma16_split(const T (&a)[4], cons
 // NBT: most R2-update tiles per wave; KS: k-steps of the backward L21^T
 // product (4*KS >= the largest band).
 template <typename T, int mode, int NBT, int KS>
-// two workgroups per CU where the band fits (FP64 with b <= 112, all FP32)
-__global__ __launch_bounds__(256, (sizeof(T) == 8 && KS > 28) ? 1 : 2) void k_solve(Geom g, const int4 *__restrict__ work,
+// workgroups per CU: FP32 three (b <= 112) or two, FP64 two (b <= 112) or one
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 ? 1 : 2)) void k_solve(Geom g, const int4 *__restrict__ work,
                                                const double *__restrict__ scal,
                                                const T *__restrict__ Lg, const T *__restrict__ Dg,
                                                double *Bg, double *Xg, int scaled, int ldb, int wmax) {
@@ -1312,7 +1312,7 @@ static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, co
 template <typename T, int mode>
 static hipError_t launch_solve_m(const Geom &g, const int4 *work, int n_work, const double *scal,
                                  const T *L, const T *Dg, double *B, double *X, int bmax, hipStream_t s) {
-  if (bmax <= 112) return launch_solve_t<T, mode, 3, 28>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s);
+  if (bmax <= 112) return launch_solve_t<T, mode, sizeof(T) == 8 ? 4 : 3, 28>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s);
   return launch_solve_t<T, mode, 3, (kMaxBand32 + 3) / 4>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s);
 }
 
@@ -1351,7 +1351,7 @@ int solve_blocks_per_cu(int fp32, int bmax) {
   const size_t lds = solve_lds_bytes(fp32, bmax, 0);
   const void *k = fp32 ? (bmax <= 112 ? (const void *)k_solve<float, 0, 3, 28>
                                       : (const void *)k_solve<float, 0, 3, (kMaxBand32 + 3) / 4>)
-                       : (bmax <= 112 ? (const void *)k_solve<double, 0, 3, 28>
+                       : (bmax <= 112 ? (const void *)k_solve<double, 0, 4, 28>
                                       : (const void *)k_solve<double, 0, 3, (kMaxBand32 + 3) / 4>);
   if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
   int nb = 0;
