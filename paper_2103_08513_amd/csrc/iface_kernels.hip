@@ -144,20 +144,22 @@ __device__ __attribute__((always_inline)) int ldl_diag16(const double *blk, int 
   // issued between the dependent steps of that reciprocal, whose latency they
   // cover (the scheduling barriers keep this interleaving, which the
   // compiler would otherwise undo by grouping the dependent chain).
-  double q = recip(row_bcast(v[0], 0));
+  double dcur = row_bcast(v[0], 0);
+  double q = recip(dcur);
 #pragma unroll
   for (int jj = 0; jj < kLB; ++jj) {
+    double dn = 0.0;
     const double wv = v[jj] * q;
     const double xq = x[jj] * q;
     // Results of pivot jj, final from here on, go to LDS off the chain, at
     // lane-based addresses with constant offsets.  S[t * 17 + i] = entry
     // (i, t) of the factored block: lane r > jj holds L[r][jj] = wv (written
-    // to the lower half of S) and U[jj][r] = v[jj] (the upper half of S + 272),
-    // lane jj holds D_jj = v[jj].  Lanes r < jj write to the other half of
+    // to the lower half of S) and U[jj][r] = v[jj] (the upper half of S + 272);
+    // D_jj is the pivot dcur.  Lanes r < jj write to the other half of
     // each, which is never read.  Lane r's x is column r of L11^{-1}, whose
     // entry jj is final too.
-    S[jj * (kLB + 1) + r] = (r == jj) ? v[jj] : wv;
-    S[kLB * (kLB + 1) + r * (kLB + 1) + jj] = v[jj];
+    S[jj * (kLB + 1) + r] = (r == jj) ? dcur : wv;
+    S[kLB * (kLB + 1) + r * (kLB + 1) + jj] = (r == jj) ? dcur : v[jj];
     T[jj * kLB + r] = x[jj];
     T[kLB * kLB + jj] = q;
     auto upd = [&](int i) {
@@ -168,10 +170,16 @@ __device__ __attribute__((always_inline)) int ldl_diag16(const double *blk, int 
       }
     };
     if (jj + 1 < kLB) {
+      // The next pivot, d = A'[jj+1][jj+1] - a^2 / D with a = A'[jj+1][jj],
+      // formed in every lane from values final before this pivot, so that
+      // only one FMA after 1/D sits on the chain; it is also the D stored for
+      // that pivot (lane jj+1's own update of v[jj+1] agrees up to rounding).
       const double a = row_bcast(v[jj], jj + 1);
+      const double vd = row_bcast(v[jj + 1], jj + 1);
+      const double d = fma(-q, a * a, vd);
+      dn = d;
       v[jj + 1] -= wv * a;
       x[jj + 1] -= a * xq;
-      const double d = row_bcast(v[jj + 1], jj + 1);
       ok = (d != 0.0 && isfinite(d)) ? ok : 0.0;
       const double q0 = __builtin_amdgcn_rcp(d);
       upd(jj + 2);
@@ -189,6 +197,7 @@ __device__ __attribute__((always_inline)) int ldl_diag16(const double *blk, int 
 #pragma unroll
       for (int i = jj + 8; i < kLB; ++i) upd(i);
     }
+    dcur = dn;
     __builtin_amdgcn_sched_barrier(0);
   }
   // band columns k0 + t, rows k0 .. k0 + 15: sixteen contiguous entries each

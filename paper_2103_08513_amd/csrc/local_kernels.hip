@@ -269,10 +269,15 @@ __device__ __forceinline__ int factor_diag(T *S, T *Xs, T *junk, int ldb, int k,
     T qn = T(0), yn = T(0);
     if (jj + 1 < kNB) {
       // column jj+1 first: it carries the next pivot
+      // The next pivot, d = A'[jj+1][jj+1] - a^2 / D with a = A'[jj+1][jj],
+      // formed in every lane from values final before this pivot, so that
+      // only one FMA after 1/D sits on the chain (lane jj+1's own update of
+      // v[jj+1] gives the same value up to rounding).
       const T a = row_bcast(v[jj], jj + 1);
+      const T vd = row_bcast(v[jj + 1], jj + 1);
+      const T d = fmat(-q, a * a, vd);
       v[jj + 1] -= w * a;
       x[jj + 1] -= a * xq;
-      const T d = row_bcast(v[jj + 1], jj + 1);
       ok = (d > T(0)) ? ok : T(0);
       // the refinements step by step, two column updates between dependent
       // steps (the compiler would otherwise issue the chain back to back)
