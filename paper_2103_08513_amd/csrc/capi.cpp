@@ -714,10 +714,6 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     Stage t(MRCM_STAGE_COEF, s);
     ENQ(launch_coef(g, h->n_sub, H.max_cells, h->coef, h->r0, h->scal, s));
   }
-  {
-    Stage t(MRCM_STAGE_RHS, s);
-    ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, h->X, s));
-  }
   const bool split = !fp32 && h->refine64 > 0 && h->n_first > 0;
   const int n_work = (int)H.work.size();
   h->ir_iters = 0;
@@ -726,6 +722,13 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     if (dev_alloc(&h->R, (size_t)H.totX) != hipSuccess)
       return bail(fail(MRCM_ENOMEM, "device allocation of the refinement buffer failed"));
     h->bytes += H.totX * 8;
+  }
+  // one pipelined FP64 sweep: R takes a copy of the right-hand sides and each
+  // correction workgroup forms its own residual from it
+  const bool own_res = split && h->refine64 == 1;
+  {
+    Stage t(MRCM_STAGE_RHS, s);
+    ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, h->X, s, own_res ? h->R : nullptr));
   }
   if (split) {
     // Per-subdomain pipeline over two streams.  The whole rounds of the
@@ -752,8 +755,10 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->X, h->X, 0, H.bmax, h->s2));
     }
     for (int it = 0; it < h->refine64; ++it) {
-      ENQ(launch_residual(g, n0, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, h->s2, h->d_grp_subs[0]));
-      ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->R, h->X, 1, H.bmax, h->s2));
+      if (!own_res)
+        ENQ(launch_residual(g, n0, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, h->s2, h->d_grp_subs[0]));
+      ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->R, h->X, 1, H.bmax, h->s2,
+                       own_res ? h->coef : nullptr));
     }
     ENQ(hipEventRecord(h->ev_join, h->s2));
     Stage t(MRCM_STAGE_REFINE, s);
@@ -761,8 +766,10 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     const int n1 = n_work - h->n_first;
     ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->X, h->X, 2, H.bmax, s));
     for (int it = 0; it < h->refine64; ++it) {
-      ENQ(launch_residual(g, n1s, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s, h->d_grp_subs[1]));
-      ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->R, h->X, 3, H.bmax, s));
+      if (!own_res)
+        ENQ(launch_residual(g, n1s, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s, h->d_grp_subs[1]));
+      ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->R, h->X, 3, H.bmax, s,
+                       own_res ? h->coef : nullptr));
     }
     ENQ(hipStreamWaitEvent(s, h->ev_join, 0));
     h->ir_iters = h->refine64;

@@ -15,11 +15,14 @@ hipError_t launch_coef(const Geom &g, int n_sub, int max_cells, double *coef, do
 hipError_t launch_factor(int fp32, const SubDesc *subs, const int *order, int n_sub,
                          const double *coef, const double *scal, void *L, void *Dg, DevStatus *st,
                          int bmax, hipStream_t s);
+// coef non-null with a correction mode: each workgroup forms its item's
+// residual into B (which holds the right-hand sides) before solving
 hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, const double *scal,
                         const void *L, const void *Dg, double *B, double *X, int mode, int bmax,
-                        hipStream_t s);
+                        hipStream_t s, const double *coef = nullptr);
+// B2: a second copy of the right-hand sides, or null
 hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, const double *r0, double *B,
-                      hipStream_t s);
+                      hipStream_t s, double *B2 = nullptr);
 int solve_chunk_max();
 size_t factor_lds_bytes(int fp32, int bmax);
 size_t solve_lds_bytes(int fp32, int bmax, int mmax);

@@ -150,7 +150,7 @@ __device__ __forceinline__ void rhs_tile(const Geom &g, const SubDesc &S, const 
 // Dense right-hand sides R (row-major, N_l x m_l) of every subdomain,
 // kRowsPB rows per workgroup, written out as one contiguous run.
 __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ r0,
-                                             double *__restrict__ B) {
+                                             double *__restrict__ B, double *__restrict__ B2) {
   __shared__ double tile[kRowsPB * kMaxRhs];
   const SubDesc &S = g.sub[blockIdx.y];
   const int rbase = blockIdx.x * kRowsPB;
@@ -159,6 +159,10 @@ __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ 
   const int ne = min(kRowsPB, S.N - rbase) * S.m;
   double *dst = B + S.X_off + (size_t)rbase * S.m;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) dst[e] = tile[e];
+  if (B2) {
+    double *dst2 = B2 + S.X_off + (size_t)rbase * S.m;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) dst2[e] = tile[e];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -733,18 +737,76 @@ __device__ __forceinline__ typename Mma<T>::v4 mma16_split(const T (&a)[4], cons
   return (c + p1) + (p2 + p3);
 }
 
+// R(:, c0..c1) = R - A^H_l X(:, c0..c1) for one work item, R holding the
+// right-hand sides on entry: the FP64 residual of a refinement sweep, formed
+// by the workgroup that then solves for the correction.  Matrix-free from the
+// coefficients, eight entries per thread at a time with all their loads
+// issued first.
+__device__ __forceinline__ void item_residual(const Geom &g, const int4 item, const double *__restrict__ coef,
+                                              const double *Xg, double *Rg) {
+  const SubDesc &S = g.sub[item.x];
+  const int c0 = item.y, cw = item.z - item.y;
+  const int N = S.N, m = S.m, n0 = S.n0, b = S.b;
+  const double *cf = coef + 4 * S.cell_off;
+  const double *X = Xg + S.X_off;
+  double *R = Rg + S.X_off;
+  const int ne = N * cw;
+  constexpr int kPB = 8;
+  for (int e0 = threadIdx.x; e0 < ne; e0 += kPB * 256) {
+    double ax[kPB], rv[kPB];
+#pragma unroll
+    for (int q = 0; q < kPB; ++q) {
+      const int e = min(e0 + q * 256, ne - 1);
+      const int r = e / cw, c = c0 + e % cw;
+      const size_t o = (size_t)r * m + c;
+      const int rp1 = min(r + 1, N - 1), rm1 = max(r - 1, 0);
+      const int rpn = min(r + n0, N - 1), rmn = max(r - n0, 0);
+      const int rpb = min(r + b, N - 1), rmb = max(r - b, 0);
+      double a = cf[4 * r] * X[o];
+      const double t1 = cf[4 * r + 1] * X[(size_t)rp1 * m + c];
+      const double t2 = cf[4 * rm1 + 1] * X[(size_t)rm1 * m + c];
+      const double t3 = cf[4 * r + 2] * X[(size_t)rpn * m + c];
+      const double t4 = cf[4 * rmn + 2] * X[(size_t)rmn * m + c];
+      const double t5 = cf[4 * r + 3] * X[(size_t)rpb * m + c];
+      const double t6 = cf[4 * rmb + 3] * X[(size_t)rmb * m + c];
+      if (r + 1 < N) a -= t1;
+      if (r >= 1) a -= t2;
+      if (r + n0 < N) a -= t3;
+      if (r >= n0) a -= t4;
+      if (r + b < N) a -= t5;
+      if (r >= b) a -= t6;
+      ax[q] = a;
+      rv[q] = R[o];
+    }
+#pragma unroll
+    for (int q = 0; q < kPB; ++q) {
+      const int e = e0 + q * 256;
+      if (e < ne) R[(size_t)(e / cw) * m + c0 + e % cw] = rv[q] - ax[q];
+    }
+  }
+}
+
 // NBT: most R2-update tiles per wave; KS: k-steps of the backward L21^T
-// product (4*KS >= the largest band).
+// product (4*KS >= the largest band).  coef non-null (FP64 corrections
+// only): form the item's residual into Bg first (Bg holding the right-hand
+// sides).
 template <typename T, int mode, int NBT, int KS>
 // workgroups per CU: FP32 three (b <= 112) or two, FP64 two (b <= 112) or one
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 ? 1 : 2)) void k_solve(Geom g, const int4 *__restrict__ work,
                                                const double *__restrict__ scal,
                                                const T *__restrict__ Lg, const T *__restrict__ Dg,
-                                               double *Bg, double *Xg, int scaled, int ldb, int wmax) {
+                                               double *Bg, double *Xg, int scaled, int ldb, int wmax,
+                                               const double *__restrict__ coef) {
   using M = Mma<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int4 item = work[blockIdx.x];
   if (item.x < 0) return;
+  if constexpr (sizeof(T) == 8 && (mode & 1) != 0) {
+    if (coef) {
+      item_residual(g, item, coef, Xg, Bg);
+      __syncthreads();
+    }
+  }
   const SubDesc &D = g.sub[item.x];
   const int c0 = item.y, cw = item.z - item.y;
   const int N = D.N, b = D.b, m = D.m, W = b + kNB, bp1 = b + 1;
@@ -1301,13 +1363,13 @@ hipError_t launch_factor(int fp32, const SubDesc *subs, const int *order, int n_
 template <typename T, int mode, int NBT, int KS>
 static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, const double *scal,
                                  const T *L, const T *Dg, double *B, double *X, int bmax, int scaled,
-                                 hipStream_t s) {
+                                 hipStream_t s, const double *coef) {
   const size_t lds = solve_lds_bytes(sizeof(T) == 4, bmax, 0);
   hipError_t e = hipFuncSetAttribute((const void *)k_solve<T, mode, NBT, KS>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_solve<T, mode, NBT, KS>), dim3(n_work), dim3(256), lds, s, g, work, scal, L, Dg, B,
-                     X, scaled, solve_ldb(bmax), bmax + kNB);
+                     X, scaled, solve_ldb(bmax), bmax + kNB, coef);
   return hipGetLastError();
 }
 
@@ -1316,28 +1378,30 @@ static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, co
 // serves.
 template <typename T, int mode>
 static hipError_t launch_solve_m(const Geom &g, const int4 *work, int n_work, const double *scal,
-                                 const T *L, const T *Dg, double *B, double *X, int bmax, hipStream_t s) {
-  if (bmax <= 112) return launch_solve_t<T, mode, sizeof(T) == 8 ? 4 : 3, 28>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s);
-  return launch_solve_t<T, mode, 3, (kMaxBand32 + 3) / 4>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s);
+                                 const T *L, const T *Dg, double *B, double *X, int bmax, hipStream_t s,
+                                 const double *coef) {
+  if (bmax <= 112)
+    return launch_solve_t<T, mode, sizeof(T) == 8 ? 4 : 3, 28>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef);
+  return launch_solve_t<T, mode, 3, (kMaxBand32 + 3) / 4>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef);
 }
 
 hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, const double *scal,
                         const void *L, const void *Dg, double *B, double *X, int mode, int bmax,
-                        hipStream_t s) {
+                        hipStream_t s, const double *coef) {
   // Separate instantiations per mode, so that profiles tell them apart: bit 0
   // set for a correction (X += ...), bit 1 set for the second group of work
   // items when the first solve is split (FP64 path only).
   if (fp32) {
     if (mode == 0)
-      return launch_solve_m<float, 0>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax, s);
-    return launch_solve_m<float, 1>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax, s);
+      return launch_solve_m<float, 0>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax, s, coef);
+    return launch_solve_m<float, 1>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax, s, coef);
   }
   const double *Ld = (const double *)L, *Dd = (const double *)Dg;
   switch (mode) {
-    case 0: return launch_solve_m<double, 0>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s);
-    case 1: return launch_solve_m<double, 1>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s);
-    case 2: return launch_solve_m<double, 2>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s);
-    default: return launch_solve_m<double, 3>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s);
+    case 0: return launch_solve_m<double, 0>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef);
+    case 1: return launch_solve_m<double, 1>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef);
+    case 2: return launch_solve_m<double, 2>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef);
+    default: return launch_solve_m<double, 3>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef);
   }
 }
 
@@ -1365,9 +1429,9 @@ int solve_blocks_per_cu(int fp32, int bmax) {
 }
 
 hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, const double *r0, double *B,
-                      hipStream_t s) {
+                      hipStream_t s, double *B2) {
   dim3 grid((unsigned)((max_cells + kRowsPB - 1) / kRowsPB), n_sub);
-  hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, g, r0, B);
+  hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, g, r0, B, B2);
   return hipGetLastError();
 }
 
