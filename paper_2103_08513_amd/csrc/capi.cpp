@@ -74,6 +74,59 @@ struct HostGeom {
   double factor_flops = 0.0, solve_flops = 0.0;
 };
 
+// The raw inputs that determine a handle's geometry, compared before any
+// rebuild so that a rebuild in place skips the host-side geometry work.
+struct ConfigKey {
+  int32_t n[3] = {0, 0, 0};
+  double h[3] = {0.0, 0.0, 0.0};
+  int32_t wall_type[6] = {0, 0, 0, 0, 0, 0};
+  int64_t pin = 0;
+  double alpha = 0.0;
+  int32_t precision = 0;
+  std::vector<int32_t> cuts[3];
+  int32_t us[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  std::vector<int32_t> split;
+  bool operator==(const ConfigKey &o) const {
+    for (int d = 0; d < 3; ++d)
+      if (n[d] != o.n[d] || h[d] != o.h[d] || cuts[d] != o.cuts[d] || us[d][0] != o.us[d][0] ||
+          us[d][1] != o.us[d][1])
+        return false;
+    for (int f = 0; f < 6; ++f)
+      if (wall_type[f] != o.wall_type[f]) return false;
+    return pin == o.pin && alpha == o.alpha && precision == o.precision && split == o.split;
+  }
+};
+
+// false when an input is missing or malformed: the full check then reports it
+bool make_key(const mrcm_problem *pb, const mrcm_partition *part, const mrcm_iface_space *ifs,
+              const mrcm_options *opt, ConfigKey &k) {
+  if (!pb || !part || !ifs || !opt) return false;
+  k.n[0] = pb->nx;
+  k.n[1] = pb->ny;
+  k.n[2] = pb->nz;
+  k.h[0] = pb->hx;
+  k.h[1] = pb->hy;
+  k.h[2] = pb->hz;
+  for (int f = 0; f < 6; ++f) k.wall_type[f] = pb->wall_type[f];
+  k.pin = pb->pin_cell;
+  k.alpha = opt->alpha;
+  k.precision = opt->precision;
+  const int nd[3] = {part->ndx, part->ndy, part->ndz};
+  const int32_t *cut_in[3] = {part->cut_x, part->cut_y, part->cut_z};
+  for (int d = 0; d < 3; ++d) {
+    if (nd[d] < 1 || nd[d] > (1 << 20) || !cut_in[d]) return false;
+    k.cuts[d].assign(cut_in[d], cut_in[d] + nd[d] + 1);
+    k.us[d][0] = ifs->uniform_split[d][0];
+    k.us[d][1] = ifs->uniform_split[d][1];
+  }
+  if (ifs->split) {
+    const int64_t ni = (int64_t)(nd[0] - 1) * nd[1] * nd[2] + (int64_t)nd[0] * (nd[1] - 1) * nd[2] +
+                       (int64_t)nd[0] * nd[1] * (nd[2] - 1);
+    k.split.assign(ifs->split, ifs->split + 2 * ni);
+  }
+  return true;
+}
+
 bool same_config(const HostGeom &a, const HostGeom &b) {
   for (int d = 0; d < 3; ++d)
     if (a.n[d] != b.n[d] || a.h[d] != b.h[d] || a.cuts[d] != b.cuts[d]) return false;
@@ -431,6 +484,7 @@ void profile_flush() {
 }  // namespace
 
 struct mrcm_mbfs {
+  ConfigKey key;  // raw configuration inputs of the build that created the handle
   HostGeom G;
   Geom g{};
   int n_sub = 0;
@@ -665,15 +719,23 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
                             const mrcm_iface_space *ifs, const mrcm_options *opt, void *stream,
                             mrcm_mbfs **out) {
   if (!out) return fail(MRCM_EINVAL, "out is null");
-  HostGeom G;
-  mrcm_status st = build_host_geom(pb, part, ifs, opt, G);
-  if (st != MRCM_OK) return st;
   mrcm_mbfs *h = *out;
+  mrcm_status st = MRCM_OK;
+  ConfigKey key;
+  const bool have_key = make_key(pb, part, ifs, opt, key);
+  // a rebuild in place with the same configuration skips the host geometry
+  const bool same = h && have_key && key == h->key && pb->kx && pb->ky && pb->kz && pb->q;
+  HostGeom G;
+  if (!same) {
+    st = build_host_geom(pb, part, ifs, opt, G);
+    if (st != MRCM_OK) return st;
+  }
   bool created = false;
-  if (h && !same_config(h->G, G))
+  if (h && !same && !same_config(h->G, G))
     return fail(MRCM_EINVAL, "handle was built for a different configuration");
   if (!h) {
     h = new mrcm_mbfs();
+    h->key = key;
     h->G = std::move(G);
     st = alloc_mbfs(h);
     if (st != MRCM_OK) {
@@ -707,9 +769,9 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   } while (0)
   const long long N = (long long)H.n[0] * H.n[1] * H.n[2];
   ENQ(launch_reset_status(h->st, s));
+  // an invalid permeability is reported by the status read at the end of the
+  // call (the first status set wins), not by a synchronisation here
   ENQ(launch_check_perm(pb->kx, pb->ky, pb->kz, N, h->st, s));
-  st = read_status(h->st, s, "mrcm_build_mbfs");
-  if (st != MRCM_OK) return bail(st);
   {
     Stage t(MRCM_STAGE_COEF, s);
     ENQ(launch_coef(g, h->n_sub, H.max_cells, h->coef, h->r0, h->scal, s));
