@@ -261,6 +261,7 @@ __global__ __launch_bounds__(kStepThreads) void k_ldl_step(double *__restrict__ 
   __shared__ double Dn[2 * kLB * (kLB + 1)];
   __shared__ double yk[kLB];
   __shared__ double bk[kLB];
+  __shared__ double Ts[kInvStride];  // staging of the next block's inverse
   const int ld = 2 * w + 1;
   const int r0 = k0 + kLB;
   const int nr = min(n, k0 + kLB + w) - r0;
@@ -284,12 +285,17 @@ __global__ __launch_bounds__(kStepThreads) void k_ldl_step(double *__restrict__ 
   // waves 0..3 own 16 rows of the tile each; wave 4 owns none
   const bool rows = wave < 4;
   double ai[4] = {0.0, 0.0, 0.0, 0.0}, aj[4] = {0.0, 0.0, 0.0, 0.0};
+  // this lane's operands of L11^{-1} and 1/D, straight from global memory so
+  // that W and the next diagonal block need no barrier
+  double bl[4] = {0.0, 0.0, 0.0, 0.0}, dq[4] = {0.0, 0.0, 0.0, 0.0};
   typename M::v4 c[4];
   if (rows) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       ai[s] = a21(i0 + 16 * wave + lr, 4 * s + lk);
       aj[s] = a21(j0 + 16 * wave + lr, 4 * s + lk);
+      bl[s] = inv_k[lr * kLB + 4 * s + lk];
+      dq[s] = inv_k[kLB * kLB + 4 * s + lk];
     }
     // the C tile of this wave: rows i0 + 16 wave + .., columns j0 + 16 tc + ..
 #pragma unroll
@@ -302,12 +308,8 @@ __global__ __launch_bounds__(kStepThreads) void k_ldl_step(double *__restrict__ 
       }
     }
   }
-  __syncthreads();
   // W = A21 L11^{-T}: lane supplies A[l%16][k] and B[k][l%16] = L11^{-1}[l%16][k]
   if (rows) {
-    double bl[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) bl[s] = Li[lr * (kLB + 1) + 4 * s + lk];
     typename M::v4 wi = {0.0, 0.0, 0.0, 0.0}, wj = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -323,16 +325,14 @@ __global__ __launch_bounds__(kStepThreads) void k_ldl_step(double *__restrict__ 
   // C -= (W_i D^{-1}) W_j^T.  a = W_i D^{-1} comes from this wave's own rows
   // of Wi (no barrier needed).  In the tile holding the next diagonal block,
   // wave 0 updates that block right away -- its only columns on or below the
-  // diagonal -- and hands it to wave 4, which factors it (the critical path
-  // from one step to the next) while the row waves finish the tile.
+  // diagonal -- and hands it to wave 4 across the one barrier; wave 4 factors
+  // it (the critical path from one step to the next) while the row waves
+  // finish the tile.
   const bool has_next = ti == 0 && tj == 0;
   double a[4] = {0.0, 0.0, 0.0, 0.0};
   if (rows) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int k = 4 * s + lk;
-      a[s] = Wi[(16 * wave + lr) * (kLB + 1) + k] * Dq[k];
-    }
+    for (int s = 0; s < 4; ++s) a[s] = Wi[(16 * wave + lr) * (kLB + 1) + 4 * s + lk] * dq[s];
   }
   if (has_next && wave == 0) {
 #pragma unroll
@@ -344,18 +344,18 @@ __global__ __launch_bounds__(kStepThreads) void k_ldl_step(double *__restrict__ 
       Dn[(i - r0) * (kLB + 1) + (j - r0)] = ok ? c[0][v] : 0.0;
     }
   }
-  // forward substitution of block k: y_k = L11^{-1} b_k (diagonal tiles)
-  if (ti == tj && tid >= 64 && tid < 64 + kLB) {
-    const int r = tid - 64;
-    double acc = 0.0;
-#pragma unroll
-    for (int c = 0; c < kLB; ++c) acc += Li[r * (kLB + 1) + c] * bk[c];
-    yk[r] = acc;
-    if (ti == 0 && k0 + r < n) y[k0 + r] = acc;
-  }
   __syncthreads();
-  // and b -= L21 y_k on this tile's rows, by wave 1 (off wave 0's path)
+  // forward substitution of block k in the diagonal tiles, by wave 1 (off
+  // wave 0's path): y_k = L11^{-1} b_k on lanes 0..15, then b -= L21 y_k on
+  // the tile's rows (the wave's LDS accesses complete in order)
   if (ti == tj && wave == 1) {
+    if (lane < kLB) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < kLB; ++c) acc += Li[lane * (kLB + 1) + c] * bk[c];
+      yk[lane] = acc;
+      if (ti == 0 && k0 + lane < n) y[k0 + lane] = acc;
+    }
     const int i = i0 + lane;
     if (i < r0 + nr) {
       double acc = 0.0;
@@ -366,8 +366,7 @@ __global__ __launch_bounds__(kStepThreads) void k_ldl_step(double *__restrict__ 
   }
   if (has_next && wave == 4) {
     const int kb = min(kLB, n - r0);
-    // Li is free after the barrier: it stages the inverse
-    if (ldl_diag16(Dn, kb, lane, AB, w, r0, inv_next, Dn, Li) && lane == 0) set_status(st, -5, r0, 0.0);
+    if (ldl_diag16(Dn, kb, lane, AB, w, r0, inv_next, Dn, Ts) && lane == 0) set_status(st, -5, r0, 0.0);
   } else if (rows && !(has_next && wave == 0)) {
     // the first ntc tile columns of this wave's rows; in a diagonal tile the
     // columns past the wave's own 16 rows lie above the diagonal (and in the
