@@ -52,7 +52,10 @@ enum { MRCM_WALL_NOFLOW = 0, MRCM_WALL_DIRICHLET = 1, MRCM_WALL_NEUMANN = 2 };
 
 /* Precision of the local factorisations. */
 enum { MRCM_FP64 = 0,          /* FP64 band Cholesky and solves */
-       MRCM_FP32_IR = 1 };     /* FP32 factor and solves + FP64 refinement */
+       MRCM_FP32_IR = 1,       /* FP32 factor and solves + FP64 refinement */
+       MRCM_PCG = 2 };         /* per-column Jacobi-preconditioned CG (FP32
+                                  inner iterations, FP64 residual), FP64 band
+                                  Cholesky for the subdomains it leaves */
 
 /*
  * The Darcy problem (Sec. 2.1).  All arrays have N = nx*ny*nz entries.
@@ -116,6 +119,24 @@ typedef struct {
  * fp64_refine  FP64: fixed number of FP64 refinement sweeps (residual
  *              R - A X from the coefficients, correction with the same factor)
  *              after the direct solves; 0 for none.
+ * PCG (iterative local solves; the paper's "LocalSolver" paragraph of the
+ * implementation section (`sec:code_overview`) compares a direct LDL^T with preconditioned
+ * GMRES for the multi-right-hand-side local problems and keeps the direct one
+ * at these sizes, table `tab:comp_local_mumps_hypre`):
+ *              every right-hand-side column is solved by conjugate gradients on
+ *              the Jacobi-scaled local matrix, with FP32 inner iterations
+ *              restarted from the FP64 residual R - A X, until
+ *              ||R - A X|| / ||R|| <= ir_tol (<= 0 selects 1e-10, which keeps
+ *              the end-to-end pressure within 1e-6 of the direct solution on
+ *              the 40x40x20 and 60x220x85 workloads; 1e-8 leaves ~1e-5).  A subdomain
+ *              with any column not converged within pcg_max_iter inner
+ *              iterations (<= 0: 50) is factorised by the FP64 band Cholesky
+ *              and all its columns are solved directly instead.
+ * pcg_max_iter PCG: inner-iteration budget per column.
+ * pcg_x0       PCG: [dev] starting guess in the layout of the MBFs (per
+ *              subdomain l in id order, n_cells x n_rhs, row-major in the
+ *              local row ordering, the same layout as mrcm_copy_mbfs), or NULL
+ *              for zero.  Read during the call only.
  */
 typedef struct {
   double alpha;
@@ -123,6 +144,8 @@ typedef struct {
   double ir_tol;
   int32_t ir_max_iter;
   int32_t fp64_refine;
+  int32_t pcg_max_iter;
+  const double *pcg_x0;
 } mrcm_options;
 
 typedef struct mrcm_mbfs mrcm_mbfs;           /* local factors, MBFs, Gamma-flux blocks */
@@ -142,6 +165,8 @@ typedef struct {
   double factor_flops;    /* sum_l sum_k (b_k^2 + 2 b_k + 1), the band Cholesky count */
   double solve_flops;     /* sum_l 4 N_l b_l m_l (forward + backward band solves) */
   int64_t device_bytes;   /* device memory held by the handle */
+  int32_t pcg_fallback;   /* PCG: subdomains solved by the band Cholesky in the last build */
+  int64_t pcg_iters;      /* PCG: inner iterations of the last build, summed over columns */
 } mrcm_info;
 
 /* Per-subdomain layout, for tests and tools.  The local row ordering puts the
@@ -255,10 +280,14 @@ mrcm_status mrcm_copy_interface(const mrcm_interface *iface, double *A, double *
  * round's subdomains); 'refine' covers the rest -- group 1's first solve and
  * both groups' residuals and corrections, group 0's on a second stream that
  * joins the caller's stream at the end -- and 'residual' stays empty.
+ * PCG: 'pcg' is the conjugate-gradient kernel and the read-back of its
+ * convergence flags; 'fallback' the band Cholesky and direct solves of the
+ * subdomains it left (factor and solve stages stay empty).
  */
 enum { MRCM_STAGE_COEF = 0, MRCM_STAGE_FACTOR, MRCM_STAGE_RHS, MRCM_STAGE_SOLVE,
        MRCM_STAGE_RESIDUAL, MRCM_STAGE_REFINE, MRCM_STAGE_FLUX, MRCM_STAGE_ASSEMBLE,
-       MRCM_STAGE_LU, MRCM_STAGE_SWEEP, MRCM_STAGE_RECONSTRUCT, MRCM_STAGE_COUNT };
+       MRCM_STAGE_LU, MRCM_STAGE_SWEEP, MRCM_STAGE_RECONSTRUCT, MRCM_STAGE_PCG,
+       MRCM_STAGE_FALLBACK, MRCM_STAGE_COUNT };
 typedef struct {
   double ms[16];        /* accumulated milliseconds per stage */
   int64_t count[16];    /* occurrences per stage */

@@ -18,8 +18,9 @@ from ._lib import CInfo, CIfaceSpace, COptions, CPartition, CProblem, CSubInfo, 
 
 FP64 = 0
 FP32_IR = 1
+PCG = 2
 
-__all__ = ["MRCM", "MRCMError", "FP64", "FP32_IR", "build_mbfs", "assemble_interface",
+__all__ = ["MRCM", "MRCMError", "FP64", "FP32_IR", "PCG", "build_mbfs", "assemble_interface",
            "solve_interface", "reconstruct", "library"]
 
 
@@ -50,7 +51,7 @@ class MRCM:
     ``mrcm_inputs`` (or any objects with the same attributes)."""
 
     def __init__(self, problem, partition, iface, alpha=1.0, precision=FP64, ir_tol=1e-13,
-                 ir_max_iter=30, fp64_refine=1, device="cuda"):
+                 ir_max_iter=30, fp64_refine=1, pcg_max_iter=50, device="cuda"):
         import torch
         self.lib = library()
         self.device = torch.device(device)
@@ -98,11 +99,24 @@ class MRCM:
         opt.ir_tol = float(ir_tol)
         opt.ir_max_iter = int(ir_max_iter)
         opt.fp64_refine = int(fp64_refine)
+        opt.pcg_max_iter = int(pcg_max_iter)
+        opt.pcg_x0 = None
         self._opt = opt
 
     # -- the four steps of Algorithm 2 ------------------------------------
-    def build_mbfs(self, kx, ky, kz, q, stream=None):
+    def build_mbfs(self, kx, ky, kz, q, stream=None, x0=None):
+        """x0 (PCG only): starting guess, a float64 device tensor in the layout
+        of the MBFs (all subdomains' local blocks concatenated, see
+        ``mbf_layout``), or None.  A warm start needs the handle of an earlier
+        build, whose layout fixes the tensor's length."""
         cp = self._cp
+        if x0 is not None:
+            if not self._mbfs.value:
+                raise ValueError("a starting guess needs a handle from an earlier build_mbfs")
+            total = self.mbf_layout()[-1]
+            if x0.numel() != total:
+                raise ValueError(f"x0 has {x0.numel()} entries; the MBF layout has {total}")
+        self._opt.pcg_x0 = None if x0 is None else _dev_ptr(x0, "x0").value
         cp.kx = _dev_ptr(kx, "kx").value
         cp.ky = _dev_ptr(ky, "ky").value
         cp.kz = _dev_ptr(kz, "kz").value
@@ -160,6 +174,15 @@ class MRCM:
         inf = CInfo()
         _lib.check(self.lib.mrcm_query(self._mbfs, byref(inf)), "mrcm_query")
         return inf
+
+    def mbf_layout(self):
+        """Offsets of each subdomain's block (n_cells x n_rhs, row-major) in the
+        concatenated MBF layout, with the total length last."""
+        offs = [0]
+        for l in range(self.info().n_sub):
+            si = self.subdomain(l)
+            offs.append(offs[-1] + si.n_cells * si.n_rhs)
+        return offs
 
     def subdomain(self, l):
         si = CSubInfo()

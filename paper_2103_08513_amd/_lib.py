@@ -21,7 +21,7 @@ EXPORTS = [
 ]
 
 STAGES = ["coef", "factor", "rhs", "solve", "residual", "refine", "flux", "assemble", "lu", "sweep",
-          "reconstruct"]
+          "reconstruct", "pcg", "fallback"]
 
 
 class CProblem(ctypes.Structure):
@@ -43,7 +43,8 @@ class CIfaceSpace(ctypes.Structure):
 
 class COptions(ctypes.Structure):
     _fields_ = [("alpha", c_double), ("precision", c_int32), ("ir_tol", c_double),
-                ("ir_max_iter", c_int32), ("fp64_refine", c_int32)]
+                ("ir_max_iter", c_int32), ("fp64_refine", c_int32), ("pcg_max_iter", c_int32),
+                ("pcg_x0", ctypes.c_void_p)]
 
 
 class CInfo(ctypes.Structure):
@@ -51,7 +52,7 @@ class CInfo(ctypes.Structure):
                 ("n_mbfs", c_int64), ("n_rhs", c_int64), ("max_band", c_int32),
                 ("max_rhs", c_int32), ("precision", c_int32), ("ir_iters", c_int32),
                 ("ir_residual", c_double), ("factor_flops", c_double), ("solve_flops", c_double),
-                ("device_bytes", c_int64)]
+                ("device_bytes", c_int64), ("pcg_fallback", c_int32), ("pcg_iters", c_int64)]
 
 
 class CProfile(ctypes.Structure):

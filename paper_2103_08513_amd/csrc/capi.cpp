@@ -64,6 +64,7 @@ struct HostGeom {
   std::vector<int> patches;  // concatenated I^l
   std::vector<int> order;    // launch order, most expensive first
   std::vector<int4> work;    // solve work items (subdomain, first column, end column)
+  std::vector<int> col_sub;  // per right-hand-side column: its subdomain
   std::vector<int> sub_of[3];
   int n_patch = 0;
   int bmax = 0, mmax = 0, max_cells = 0;
@@ -164,8 +165,8 @@ mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
   G.alpha = opt->alpha;
   if (!(G.alpha > 0.0) || !std::isfinite(G.alpha)) return fail(MRCM_EINVAL, "alpha must be positive");
   G.precision = opt->precision;
-  if (G.precision != MRCM_FP64 && G.precision != MRCM_FP32_IR)
-    return fail(MRCM_EINVAL, "precision must be MRCM_FP64 or MRCM_FP32_IR");
+  if (G.precision != MRCM_FP64 && G.precision != MRCM_FP32_IR && G.precision != MRCM_PCG)
+    return fail(MRCM_EINVAL, "precision must be MRCM_FP64, MRCM_FP32_IR or MRCM_PCG");
 
   const int nd[3] = {part->ndx, part->ndy, part->ndz};
   const int32_t *cut_in[3] = {part->cut_x, part->cut_y, part->cut_z};
@@ -314,13 +315,20 @@ mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
       }
     }
   }
-  const int bcap = G.precision == MRCM_FP64 ? kMaxBand64 : kMaxBand32;
+  const int bcap = G.precision == MRCM_FP32_IR ? kMaxBand32 : kMaxBand64;
   if (G.bmax > bcap)
     return fail(MRCM_EUNSUPPORTED, "local bandwidth " + std::to_string(G.bmax) + " exceeds " +
                                        std::to_string(bcap) + " for this precision");
   if (G.mmax > kMaxRhs)
     return fail(MRCM_EUNSUPPORTED, "a subdomain has " + std::to_string(G.mmax) +
                                        " right-hand sides; the limit is " + std::to_string(kMaxRhs));
+  if (G.precision == MRCM_PCG && G.max_cells > pcg_max_cells())
+    return fail(MRCM_EUNSUPPORTED, "a subdomain has " + std::to_string(G.max_cells) +
+                                       " cells; the conjugate-gradient kernel holds at most " +
+                                       std::to_string(pcg_max_cells()));
+  G.col_sub.resize(G.totCols);
+  for (int l = 0; l < n_sub; ++l)
+    for (int c = 0; c < G.subs[l].m; ++c) G.col_sub[G.subs[l].col_off + c] = l;
   const int fp32 = G.precision == MRCM_FP32_IR;
   // the factor kernel also holds a few bytes of static LDS
   if (solve_lds_bytes(fp32, G.bmax, G.mmax) > 160 * 1024 || factor_lds_bytes(fp32, G.bmax) > 160 * 1024 - 64)
@@ -504,6 +512,17 @@ struct mrcm_mbfs {
   int n_grp_subs[2] = {0, 0};
   hipStream_t s2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // PCG form: column -> subdomain, per-column iteration counts and
+  // convergence flags, and the fallback's factor order and solve items
+  int *d_colsub = nullptr, *d_iters = nullptr, *d_conv = nullptr;
+  int *d_fb_order = nullptr;
+  int4 *d_fb_work = nullptr;
+  int pcg_max = 50;
+  const double *pcg_x0 = nullptr;
+  int pcg_fallback = 0;
+  int64_t pcg_iters = 0;
+  std::vector<int> fb_order;   // host copies kept until the next build
+  std::vector<int4> fb_work;
   int *d_patches = nullptr;
   int *d_subof[3] = {nullptr, nullptr, nullptr};
   double *coef = nullptr, *r0 = nullptr, *scal = nullptr;
@@ -540,7 +559,8 @@ void free_mbfs(mrcm_mbfs *h) {
   if (!h) return;
   void *ptrs[] = {h->d_sub, h->d_ifc, h->d_order, h->d_work, h->d_patches, h->d_subof[0], h->d_subof[1],
                   h->d_subof[2], h->coef, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, h->F, h->Fb, h->SAb,
-                  h->norms, h->scalar, h->st, h->d_grp_subs[0], h->d_grp_subs[1], h->d_order_split};
+                  h->norms, h->scalar, h->st, h->d_grp_subs[0], h->d_grp_subs[1], h->d_order_split,
+                  h->d_colsub, h->d_iters, h->d_conv, h->d_fb_order, h->d_fb_work};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
@@ -590,7 +610,14 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
     bytes += G.totD * (int64_t)es;
   }
   ALLOC(h->X, G.totX, double);
-  if (G.precision == MRCM_FP32_IR) ALLOC(h->R, G.totX, double);
+  if (G.precision != MRCM_FP64) ALLOC(h->R, G.totX, double);
+  if (G.precision == MRCM_PCG) {
+    HIP_TRY(upload(&h->d_colsub, G.col_sub));
+    ALLOC(h->d_iters, G.totCols, int);
+    ALLOC(h->d_conv, G.totCols, int);
+    ALLOC(h->d_fb_order, G.subs.size(), int);
+    ALLOC(h->d_fb_work, G.work.size(), int4);
+  }
   ALLOC(h->F, std::max<int64_t>(1, G.totF), double);
   ALLOC(h->Fb, std::max<int64_t>(1, G.totF), double);
   ALLOC(h->SAb, std::max<int64_t>(1, (int64_t)G.patches.size()), double);
@@ -604,7 +631,7 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
 #undef ALLOC
   // the split of the solve work into resident rounds (FP64 path)
   h->solve_group.assign(G.subs.size(), 0);
-  if (G.precision != MRCM_FP32_IR) {
+  if (G.precision == MRCM_FP64) {
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -746,7 +773,9 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   }
   hipStream_t s = (hipStream_t)stream;
   h->stream = s;
-  h->ir_tol = opt->ir_tol > 0.0 ? opt->ir_tol : 1e-13;
+  h->ir_tol = opt->ir_tol > 0.0 ? opt->ir_tol : (opt->precision == MRCM_PCG ? 1e-10 : 1e-13);
+  h->pcg_max = opt->pcg_max_iter > 0 ? opt->pcg_max_iter : 50;
+  h->pcg_x0 = opt->pcg_x0;
   h->ir_max = opt->ir_max_iter > 0 ? opt->ir_max_iter : 30;
   if (opt->fp64_refine < 0 || opt->fp64_refine > 10) return fail(MRCM_EINVAL, "fp64_refine must be in [0, 10]");
   h->refine64 = opt->fp64_refine;
@@ -776,11 +805,14 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     Stage t(MRCM_STAGE_COEF, s);
     ENQ(launch_coef(g, h->n_sub, H.max_cells, h->coef, h->r0, h->scal, s));
   }
-  const bool split = !fp32 && h->refine64 > 0 && h->n_first > 0;
+  const bool pcg = H.precision == MRCM_PCG;
+  const bool split = !fp32 && !pcg && h->refine64 > 0 && h->n_first > 0;
   const int n_work = (int)H.work.size();
   h->ir_iters = 0;
   h->ir_res = 0.0;
-  if (!fp32 && h->refine64 > 0 && !h->R) {
+  h->pcg_fallback = 0;
+  h->pcg_iters = 0;
+  if (!fp32 && !pcg && h->refine64 > 0 && !h->R) {
     if (dev_alloc(&h->R, (size_t)H.totX) != hipSuccess)
       return bail(fail(MRCM_ENOMEM, "device allocation of the refinement buffer failed"));
     h->bytes += H.totX * 8;
@@ -790,9 +822,45 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   const bool own_res = split && h->refine64 == 1;
   {
     Stage t(MRCM_STAGE_RHS, s);
-    ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, h->X, s, own_res ? h->R : nullptr));
+    ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, pcg ? h->R : h->X, s, own_res ? h->R : nullptr));
   }
-  if (split) {
+  if (pcg) {
+    // Conjugate gradients for every column (right-hand sides in R), then the
+    // band Cholesky and direct solves for every subdomain with a column that
+    // did not converge, which overwrite all of that subdomain's columns.
+    std::vector<int> conv(H.totCols), its(H.totCols);
+    {
+      Stage t(MRCM_STAGE_PCG, s);
+      ENQ(launch_pcg(g, h->d_colsub, H.totCols, H.max_cells, h->coef, h->scal, h->R, h->pcg_x0, h->X, h->pcg_max,
+                     h->ir_tol, h->d_iters, h->d_conv, s));
+      ENQ(hipMemcpyAsync(conv.data(), h->d_conv, conv.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+      ENQ(hipMemcpyAsync(its.data(), h->d_iters, its.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+      ENQ(hipStreamSynchronize(s));
+    }
+    std::vector<char> bad(h->n_sub, 0);
+    for (int c = 0; c < H.totCols; ++c) {
+      h->pcg_iters += its[c];
+      if (!conv[c]) bad[H.col_sub[c]] = 1;
+    }
+    h->fb_order.clear();
+    h->fb_work.clear();
+    for (int l : H.order)
+      if (bad[l]) h->fb_order.push_back(l);
+    for (const int4 &w : H.work)
+      if (w.x >= 0 && bad[w.x]) h->fb_work.push_back(w);
+    h->pcg_fallback = (int)h->fb_order.size();
+    if (!h->fb_order.empty()) {
+      Stage t(MRCM_STAGE_FALLBACK, s);
+      ENQ(hipMemcpyAsync(h->d_fb_order, h->fb_order.data(), h->fb_order.size() * sizeof(int),
+                         hipMemcpyHostToDevice, s));
+      ENQ(hipMemcpyAsync(h->d_fb_work, h->fb_work.data(), h->fb_work.size() * sizeof(int4), hipMemcpyHostToDevice,
+                         s));
+      ENQ(launch_factor(0, h->d_sub, h->d_fb_order, h->pcg_fallback, h->coef, h->scal, h->L, h->Dinv, h->st,
+                        H.bmax, s));
+      ENQ(launch_solve(0, g, h->d_fb_work, (int)h->fb_work.size(), h->scal, h->L, h->Dinv, h->R, h->X, 0, H.bmax,
+                       s));
+    }
+  } else if (split) {
     // Per-subdomain pipeline over two streams.  The whole rounds of the
     // factorisation go first; group 0's first solve, residuals and
     // corrections then run on the second stream while the caller's stream
@@ -846,8 +914,8 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       ENQ(launch_solve(fp32, g, h->d_work, n_work, h->scal, h->L, h->Dinv, h->X, h->X, 0, H.bmax, s));
     }
   }
-  if (split) {
-    // refinement done in the pipeline above
+  if (split || pcg) {
+    // refinement done in the pipeline above, or none (PCG)
   } else if (!fp32 && h->refine64 > 0) {
     for (int it = 0; it < h->refine64; ++it) {
       {
@@ -1027,6 +1095,8 @@ mrcm_status mrcm_query(const mrcm_mbfs *mb, mrcm_info *info) {
   info->factor_flops = G.factor_flops;
   info->solve_flops = G.solve_flops;
   info->device_bytes = mb->bytes;
+  info->pcg_fallback = mb->pcg_fallback;
+  info->pcg_iters = mb->pcg_iters;
   return MRCM_OK;
 }
 

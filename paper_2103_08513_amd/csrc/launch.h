@@ -36,6 +36,13 @@ hipError_t launch_ir_check(const double *norms, int ncols, double *out, hipStrea
 hipError_t launch_flux(const Geom &g, int n_sub, const double *X, double *F, double *Fb,
                        double *SAb, hipStream_t s);
 
+// Conjugate-gradient form of the local solves (pcg_kernels.hip).  One
+// workgroup per column (subdomain by col_sub); X0 null for a zero start.
+int pcg_max_cells();
+hipError_t launch_pcg(const Geom &g, const int *col_sub, int ncols, int max_cells, const double *coef,
+                      const double *scal, const double *B, const double *X0, double *X, int max_iter, double tol,
+                      int *iters, int *conv, hipStream_t s);
+
 // Interface system and reconstruction (iface_kernels.hip)
 hipError_t launch_fill(double *a, long long n, double v, hipStream_t s);
 hipError_t launch_copy(const double *a, double *b, long long n, hipStream_t s);
