@@ -34,7 +34,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1):
+def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=50):
     import torch
     import paper_2103_08513_amd as lib
     from paper_2103_08513_amd import _lib
@@ -42,7 +42,7 @@ def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1):
     dev = torch.device("cuda:0")
     kx, ky, kz, q = (torch.as_tensor(a, dtype=torch.float64, device=dev) for a in (pb.kx, pb.ky, pb.kz, pb.q))
     model = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision,
-                     fp64_refine=fp64_refine)
+                     fp64_refine=fp64_refine, pcg_max_iter=pcg_max_iter)
     N = pb.n
     X = None
     p = torch.empty(N, dtype=torch.float64, device=dev)
@@ -178,6 +178,17 @@ def roofline_for(stage_name, res, info, precision):
         return {"kernel": "k_solve", "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "ms_avg": st["ms_avg"],
                 "algorithmic_bytes": nbytes}
+    if stage_name == "pcg":
+        # FP32 inner iterations: 22 flops per row (7-point product 12, two
+        # dot products 4, three vector updates 6); the FP64 residuals of the
+        # restarts are left out.  All subdomains of the workload have the same
+        # number of cells.
+        rows = info.n_cells / info.n_sub
+        flops = 22.0 * rows * info.pcg_iters
+        ach = flops / sec / 1e12
+        return {"kernel": "k_pcg", "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "traffic": None, "ms_avg": st["ms_avg"],
+                "algorithmic_flops": flops}
     return None
 
 
@@ -204,6 +215,7 @@ def main():
     ap.add_argument("--fp64-refine", type=int, default=1, help="FP64 refinement sweeps of the FP64 local solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other precision")
+    ap.add_argument("--no-pcg", action="store_true", help="skip the conjugate-gradient form")
     ap.add_argument("--copy-calibration", type=float, default=None, metavar="MB",
                     help="only run a device copy of this many MB (counter calibration) and exit")
     args = ap.parse_args()
@@ -233,6 +245,17 @@ def main():
         r2 = run_gpu(case, other, args.steps, args.warmup, args.refine, args.fp64_refine)
         secondary = r2
         log(f"other precision ms/step {r2['ms_step']:.3f}")
+    pcg_runs = []
+    if not args.no_pcg:
+        # the conjugate-gradient form at the default budget (50 inner
+        # iterations per column, band-Cholesky fallback) and with a budget
+        # that lets every column converge
+        for budget in (50, 1000):
+            r = run_gpu(case, 2, min(args.steps, 3), 1, args.refine, pcg_max_iter=budget)
+            r["budget"] = budget
+            pcg_runs.append(r)
+            log(f"pcg budget {budget}: ms/step {r['ms_step']:.3f}, fallback {r['info'].pcg_fallback}, "
+                f"iterations {r['info'].pcg_iters}")
     cpu = None
     err = {}
     if not args.no_cpu_baseline:
@@ -245,6 +268,8 @@ def main():
         err = {"p": rel_l2(res["p"], ref.p), "U": rel_l2(res["U"], ref.U), "pi": rel_l2(res["X"], ref.pi)}
         if secondary is not None:
             secondary["err"] = {"p": rel_l2(secondary["p"], ref.p), "U": rel_l2(secondary["U"], ref.U)}
+        for r in pcg_runs:
+            r["err"] = {"p": rel_l2(r["p"], ref.p), "U": rel_l2(r["U"], ref.U)}
     t_step = res["ms_step"] * 1e-3
     build_ms = sum(res["stages"].get(k, {}).get("ms_avg", 0.0) *
                    (res["stages"].get(k, {}).get("count", 0) / max(1, args.steps))
@@ -295,6 +320,18 @@ def main():
             "roofline": roofline_for("solve", secondary, secondary["info"], 1 - prec),
             "roofline_factor": roofline_for("factor", secondary, secondary["info"], 1 - prec),
         }
+    if pcg_runs:
+        line["pcg"] = [{
+            "budget": r["budget"], "ms_per_step": r["ms_step"],
+            "value": info.n_mbfs / (r["ms_step"] * 1e-3),
+            "fallback_subdomains": int(r["info"].pcg_fallback),
+            "inner_iterations": int(r["info"].pcg_iters),
+            "columns": int(r["info"].n_rhs),
+            "stages_ms": {k: round(v["ms_avg"] * v["count"] / min(args.steps, 3), 4)
+                          for k, v in r["stages"].items()},
+            "rel_err_vs_oracle": r.get("err"),
+            "roofline": roofline_for("pcg", r, r["info"], 2),
+        } for r in pcg_runs]
     print(json.dumps(line), flush=True)
 
 

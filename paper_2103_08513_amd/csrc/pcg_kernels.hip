@@ -23,7 +23,7 @@
 namespace mrcm {
 namespace {
 
-constexpr float kInnerTol = 1e-4f;
+constexpr float kInnerTol = 1e-3f;
 // zero rows on both sides of the LDS vectors: every neighbour offset of a
 // row (+-1, +-n0, +-b with b <= kMaxBand64) stays inside the array
 constexpr int kPad = 128;
@@ -33,6 +33,25 @@ __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// FP32 sum over a wave by DPP moves (no LDS traffic): prefix sums within
+// rows of 16 lanes (row_shr 1, 2, 4, 8), then the row totals carried into
+// rows 1 and 3 (row_bcast 15) and 2 and 3 (row_bcast 31); lane 63 ends with
+// the total, which every lane reads.
+template <int ctrl, int row_mask>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int x = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, row_mask, 0xf, false);
+  return v + __builtin_bit_cast(float, x);
+}
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v = dpp_add<0x111, 0xf>(v);
+  v = dpp_add<0x112, 0xf>(v);
+  v = dpp_add<0x114, 0xf>(v);
+  v = dpp_add<0x118, 0xf>(v);
+  v = dpp_add<0x142, 0xa>(v);
+  v = dpp_add<0x143, 0xc>(v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
 // Sum over the workgroup's NW waves; every lane returns the same bits.  A
@@ -63,9 +82,9 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
                                             int *__restrict__ iters, int *__restrict__ conv) {
   constexpr int NW = NT / 64;
   constexpr int LEN = NT * CPT + 2 * kPad;
-  __shared__ float ps[LEN];
+  __shared__ float ps[2][LEN];
   __shared__ double xs[LEN];
-  __shared__ float redf[2][NW];
+  __shared__ float redf[2][2][NW];
   __shared__ double redd[2][NW];
   // columns in contiguous ranges per XCD (workgroup i runs on XCD i mod 8),
   // so that the columns of one subdomain share that XCD's L2
@@ -81,10 +100,12 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
   double *X = Xg + S.X_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int k = tid; k < LEN; k += NT) {
-    ps[k] = 0.0f;
+    ps[0][k] = 0.0f;
+    ps[1][k] = 0.0f;
     xs[k] = 0.0;
   }
-  float *pr = ps + kPad + tid;   // row tid + NT i at pr[NT i]
+  float *pr = ps[0] + kPad + tid;   // row tid + NT i at pr[NT i]
+  float *pr1 = ps[1] + kPad + tid;
   double *xr = xs + kPad + tid;
 
   // Scaled off-diagonal weights s_r t s_n (the matrix entries are their
@@ -175,56 +196,81 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
     if (it >= max_iter || !isfinite(rn2)) break;
     const double sn2 = block_sum<NW>(nsq, redd[0], wave, lane);
     const double sn = sqrt(sn2), inv_sn = 1.0 / sn;
-    // inner CG on (D^-1/2 A D^-1/2) y = D^-1/2 r / ||D^-1/2 r||
-    float y[CPT], rr[CPT], p[CPT];
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-      rr[i] = (float)(res[i] * inv_sn);
-      p[i] = rr[i];
-      y[i] = 0.0f;
-    }
-    float rho = 1.0f;
-    const float eta2 = kInnerTol * kInnerTol;
-    for (;;) {
-#pragma unroll
-      for (int i = 0; i < CPT; ++i)
-        if (tid + NT * i < N) pr[NT * i] = p[i];
-      __syncthreads();
-      float qv[CPT];
-      float pq = 0.0f;
+    // Inner solve of (D^-1/2 A D^-1/2) y = D^-1/2 r / ||D^-1/2 r|| by the
+    // pipelined conjugate-gradient recurrences of Ghysels and Vanroose (2014):
+    // the two dot products of an iteration and the exchange of the vector
+    // the next product needs share one barrier.  Vectors: r residual, w = A r,
+    // s = A p, z = A s, p direction; the exchange buffers alternate.
+    const auto matvec = [&](const float *base, const float(&v)[CPT], float(&out)[CPT]) {
 #pragma unroll
       for (int i = 0; i < CPT; ++i) {
-        const float *q = pr + NT * i;
-        float a = p[i];
+        const float *q = base + NT * i;
+        float a = v[i];
         a = fmaf(-w[0][i], q[1], a);
         a = fmaf(-w[1][i], q[-1], a);
         a = fmaf(-w[2][i], q[n0], a);
         a = fmaf(-w[3][i], q[-n0], a);
         a = fmaf(-w[4][i], q[b], a);
         a = fmaf(-w[5][i], q[-b], a);
-        qv[i] = a;
-        pq = fmaf(p[i], a, pq);
+        out[i] = a;
       }
-      pq = block_sum<NW>(pq, redf[0], wave, lane);
-      if (!(pq > 0.0f)) {  // breakdown: leave the column to the fallback
-        it = max_iter;
-        break;
-      }
-      const float alpha = rho / pq;
-      float rs = 0.0f;
+    };
+    float y[CPT], rv[CPT], wv[CPT], z[CPT], sv[CPT], p[CPT];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      rv[i] = (float)(res[i] * inv_sn);
+      y[i] = z[i] = sv[i] = p[i] = 0.0f;
+      if (tid + NT * i < N) pr[NT * i] = rv[i];
+    }
+    __syncthreads();
+    matvec(pr, rv, wv);
+    ++it;
+    const float eta2 = kInnerTol * kInnerTol;
+    float gam_prev = 1.0f, alpha_prev = 1.0f;
+    for (int k = 0;; ++k) {
+      float *buf = (k & 1) ? pr : pr1;
+      float(*red)[NW] = redf[k & 1];
+      float gp = 0.0f, dp = 0.0f;
 #pragma unroll
       for (int i = 0; i < CPT; ++i) {
-        y[i] = fmaf(alpha, p[i], y[i]);
-        rr[i] = fmaf(-alpha, qv[i], rr[i]);
-        rs = fmaf(rr[i], rr[i], rs);
+        if (tid + NT * i < N) buf[NT * i] = wv[i];
+        gp = fmaf(rv[i], rv[i], gp);
+        dp = fmaf(wv[i], rv[i], dp);
       }
-      const float rho_new = block_sum<NW>(rs, redf[1], wave, lane);
-      ++it;
-      if (rho_new <= eta2 || it >= max_iter) break;
-      const float beta = rho_new / rho;
-      rho = rho_new;
+      gp = wave_sum_dpp(gp);
+      dp = wave_sum_dpp(dp);
+      if (lane == 0) {
+        red[0][wave] = gp;
+        red[1][wave] = dp;
+      }
+      __syncthreads();
+      float gam = red[0][0], del = red[1][0];
 #pragma unroll
-      for (int i = 0; i < CPT; ++i) p[i] = fmaf(beta, p[i], rr[i]);
+      for (int j = 1; j < NW; ++j) {
+        gam += red[0][j];
+        del += red[1][j];
+      }
+      if (gam <= eta2 || it >= max_iter) break;
+      float q[CPT];
+      matvec(buf, wv, q);
+      ++it;
+      const float beta = k == 0 ? 0.0f : gam / gam_prev;
+      const float den = k == 0 ? del : del - beta * gam / alpha_prev;
+      const float alpha = gam / den;
+      // a non-positive or non-finite step (rounding in the pipelined
+      // recurrences): keep y and restart from the true residual
+      if (!(alpha > 0.0f) || !isfinite(alpha)) break;
+#pragma unroll
+      for (int i = 0; i < CPT; ++i) {
+        z[i] = fmaf(beta, z[i], q[i]);
+        sv[i] = fmaf(beta, sv[i], wv[i]);
+        p[i] = fmaf(beta, p[i], rv[i]);
+        y[i] = fmaf(alpha, p[i], y[i]);
+        rv[i] = fmaf(-alpha, sv[i], rv[i]);
+        wv[i] = fmaf(-alpha, z[i], wv[i]);
+      }
+      gam_prev = gam;
+      alpha_prev = alpha;
     }
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
