@@ -82,9 +82,9 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
                                             int *__restrict__ iters, int *__restrict__ conv) {
   constexpr int NW = NT / 64;
   constexpr int LEN = NT * CPT + 2 * kPad;
-  __shared__ float ps[2][LEN];
+  __shared__ float ps[LEN];
   __shared__ double xs[LEN];
-  __shared__ float redf[2][2][NW];
+  __shared__ float redf[2][NW];
   __shared__ double redd[2][NW];
   // columns in contiguous ranges per XCD (workgroup i runs on XCD i mod 8),
   // so that the columns of one subdomain share that XCD's L2
@@ -100,12 +100,10 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
   double *X = Xg + S.X_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int k = tid; k < LEN; k += NT) {
-    ps[0][k] = 0.0f;
-    ps[1][k] = 0.0f;
+    ps[k] = 0.0f;
     xs[k] = 0.0;
   }
-  float *pr = ps[0] + kPad + tid;   // row tid + NT i at pr[NT i]
-  float *pr1 = ps[1] + kPad + tid;
+  float *pr = ps + kPad + tid;   // row tid + NT i at pr[NT i]
   double *xr = xs + kPad + tid;
 
   // Scaled off-diagonal weights s_r t s_n (the matrix entries are their
@@ -197,77 +195,67 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
     const double sn2 = block_sum<NW>(nsq, redd[0], wave, lane);
     const double sn = sqrt(sn2), inv_sn = 1.0 / sn;
     // Inner solve of (D^-1/2 A D^-1/2) y = D^-1/2 r / ||D^-1/2 r|| by the
-    // pipelined conjugate-gradient recurrences of Ghysels and Vanroose (2014):
-    // the two dot products of an iteration and the exchange of the vector
-    // the next product needs share one barrier.  Vectors: r residual, w = A r,
-    // s = A p, z = A s, p direction; the exchange buffers alternate.
-    const auto matvec = [&](const float *base, const float(&v)[CPT], float(&out)[CPT]) {
+    // conjugate-gradient recurrences of Chronopoulos and Gear (1989): both
+    // dot products of an iteration, (r, r) and (A r, r), are reduced
+    // together, so an iteration takes two barriers (the exchange of r for
+    // the product, the reduction).  Vectors: r residual, w = A r, p
+    // direction, s = A p.
+    float y[CPT], rv[CPT], wv[CPT], sv[CPT], p[CPT];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      rv[i] = (float)(res[i] * inv_sn);
+      y[i] = sv[i] = p[i] = 0.0f;
+    }
+    const float eta2 = kInnerTol * kInnerTol;
+    float gam_prev = 1.0f, alpha_prev = 1.0f;
+    for (int k = 0;; ++k) {
+#pragma unroll
+      for (int i = 0; i < CPT; ++i)
+        if (tid + NT * i < N) pr[NT * i] = rv[i];
+      __syncthreads();
+      float gp = 0.0f, dp = 0.0f;
 #pragma unroll
       for (int i = 0; i < CPT; ++i) {
-        const float *q = base + NT * i;
-        float a = v[i];
+        const float *q = pr + NT * i;
+        float a = rv[i];
         a = fmaf(-w[0][i], q[1], a);
         a = fmaf(-w[1][i], q[-1], a);
         a = fmaf(-w[2][i], q[n0], a);
         a = fmaf(-w[3][i], q[-n0], a);
         a = fmaf(-w[4][i], q[b], a);
         a = fmaf(-w[5][i], q[-b], a);
-        out[i] = a;
-      }
-    };
-    float y[CPT], rv[CPT], wv[CPT], z[CPT], sv[CPT], p[CPT];
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-      rv[i] = (float)(res[i] * inv_sn);
-      y[i] = z[i] = sv[i] = p[i] = 0.0f;
-      if (tid + NT * i < N) pr[NT * i] = rv[i];
-    }
-    __syncthreads();
-    matvec(pr, rv, wv);
-    ++it;
-    const float eta2 = kInnerTol * kInnerTol;
-    float gam_prev = 1.0f, alpha_prev = 1.0f;
-    for (int k = 0;; ++k) {
-      float *buf = (k & 1) ? pr : pr1;
-      float(*red)[NW] = redf[k & 1];
-      float gp = 0.0f, dp = 0.0f;
-#pragma unroll
-      for (int i = 0; i < CPT; ++i) {
-        if (tid + NT * i < N) buf[NT * i] = wv[i];
+        wv[i] = a;
         gp = fmaf(rv[i], rv[i], gp);
-        dp = fmaf(wv[i], rv[i], dp);
+        dp = fmaf(a, rv[i], dp);
       }
       gp = wave_sum_dpp(gp);
       dp = wave_sum_dpp(dp);
       if (lane == 0) {
-        red[0][wave] = gp;
-        red[1][wave] = dp;
+        redf[0][wave] = gp;
+        redf[1][wave] = dp;
       }
       __syncthreads();
-      float gam = red[0][0], del = red[1][0];
+      float gam = redf[0][0], del = redf[1][0];
 #pragma unroll
       for (int j = 1; j < NW; ++j) {
-        gam += red[0][j];
-        del += red[1][j];
+        gam += redf[0][j];
+        del += redf[1][j];
       }
+      // the product above is counted once the step is taken
       if (gam <= eta2 || it >= max_iter) break;
-      float q[CPT];
-      matvec(buf, wv, q);
       ++it;
       const float beta = k == 0 ? 0.0f : gam / gam_prev;
       const float den = k == 0 ? del : del - beta * gam / alpha_prev;
       const float alpha = gam / den;
-      // a non-positive or non-finite step (rounding in the pipelined
-      // recurrences): keep y and restart from the true residual
+      // a non-positive or non-finite step (rounding): keep y and restart
+      // from the true residual
       if (!(alpha > 0.0f) || !isfinite(alpha)) break;
 #pragma unroll
       for (int i = 0; i < CPT; ++i) {
-        z[i] = fmaf(beta, z[i], q[i]);
-        sv[i] = fmaf(beta, sv[i], wv[i]);
         p[i] = fmaf(beta, p[i], rv[i]);
+        sv[i] = fmaf(beta, sv[i], wv[i]);
         y[i] = fmaf(alpha, p[i], y[i]);
         rv[i] = fmaf(-alpha, sv[i], rv[i]);
-        wv[i] = fmaf(-alpha, z[i], wv[i]);
       }
       gam_prev = gam;
       alpha_prev = alpha;
