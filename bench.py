@@ -34,11 +34,14 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=50, warm=None):
+def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=50, warm=None, net=None):
     """warm (PCG only): relative size of a mobility change.  The MBFs of the
     unchanged field start the conjugate gradients of every timed build on the
     field multiplied cell by cell by exp(warm * g), g standard normal (seed 7),
-    as when a two-phase run rebuilds its MBFs between pressure solves."""
+    as when a two-phase run rebuilds its MBFs between pressure solves.
+    net (PCG only): a trained WarmStartNet; every timed build first gathers
+    the network's inputs from the previous build, runs the network and uses
+    its Galerkin-scaled output as the starting guess."""
     import torch
     import paper_2103_08513_amd as lib
     from paper_2103_08513_amd import _lib
@@ -60,9 +63,18 @@ def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=
     p = torch.empty(N, dtype=torch.float64, device=dev)
     U = torch.empty(6 * N, dtype=torch.float64, device=dev)
 
+    nn_subs = None
+    if net is not None:
+        from paper_2103_08513_amd.surrogate import net_subdomains, warm_start
+        model.build_mbfs(kx, ky, kz, q)
+        nn_subs, nn_dims = net_subdomains(model)
+        x0 = torch.zeros(model.mbf_layout()[-1], dtype=torch.float64, device=dev)
+
     def step():
         nonlocal X
-        model.build_mbfs(kx, ky, kz, q, x0=x0)
+        if nn_subs is not None:
+            warm_start(model, net, nn_subs, nn_dims, x0)
+        model.build_mbfs(kx, ky, kz, q, x0=x0, x0_scale=nn_subs is not None)
         model.assemble_interface()
         X = model.solve_interface(X, refine=refine)
         model.reconstruct(X, p, U)
@@ -110,6 +122,37 @@ def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=
                interface_residual=model.interface_residual, sub_shapes=shapes)
     model.close()
     return out
+
+
+def train_surrogate(seeds=(1, 2), epochs=3):
+    """The warm-start network trained (outside any timed region) on the MBFs of
+    the FP64 path for channelised fields of other seeds than the workload's."""
+    import torch
+    import paper_2103_08513_amd as lib
+    from mrcm_inputs import config2
+    from paper_2103_08513_amd.surrogate import WarmStartNet, features, net_subdomains
+    net = WarmStartNet(seed=0)
+    inps, tgts = [], []
+    t0 = time.perf_counter()
+    for seed in seeds:
+        c = config2(seed=seed)
+        pb = c.problem
+        m = lib.MRCM(pb, c.partition, c.iface, alpha=c.alpha, precision=lib.FP64)
+        m.build_mbfs(*(torch.as_tensor(a, dtype=torch.float64, device="cuda") for a in (pb.kx, pb.ky, pb.kz, pb.q)))
+        subs, dims = net_subdomains(m)
+        i, t = features(m, subs, dims)
+        inps.append(i)
+        tgts.append(t)
+        m.close()
+    inp, tgt = torch.cat(inps), torch.cat(tgts)
+    hist = net.train(inp, tgt, dims, epochs=epochs, batch=256, lr=3e-3, seed=0)
+    torch.cuda.synchronize()
+    info = {"params": net.n_params(), "channels": list(net.channels), "dilations": list(net.dilations),
+            "train_fields": [f"channelised 60x220x85, seed {s}" for s in seeds], "samples": int(inp.shape[0]),
+            "epochs": epochs, "loss_by_epoch": hist, "train_seconds": time.perf_counter() - t0}
+    log(f"network trained: {info['params']} parameters, loss {[round(h, 3) for h in hist]}")
+    del inp, tgt, inps, tgts
+    return net, info
 
 
 def ctypes_byref(x):
@@ -228,6 +271,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other precision")
     ap.add_argument("--no-pcg", action="store_true", help="skip the conjugate-gradient form")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the network-started conjugate gradients")
     ap.add_argument("--copy-calibration", type=float, default=None, metavar="MB",
                     help="only run a device copy of this many MB (counter calibration) and exit")
     args = ap.parse_args()
@@ -266,9 +310,18 @@ def main():
             r = run_gpu(case, 2, min(args.steps, 3), 1, args.refine, pcg_max_iter=budget, warm=warm)
             r["budget"] = budget
             r["warm"] = warm
+            r["surrogate"] = None
             pcg_runs.append(r)
             log(f"pcg budget {budget}, warm start {warm}: ms/step {r['ms_step']:.3f}, fallback {r['info'].pcg_fallback}, "
                 f"iterations {r['info'].pcg_iters}")
+        if not args.no_surrogate:
+            net, train_info = train_surrogate()
+            r = run_gpu(case, 2, min(args.steps, 3), 1, args.refine, pcg_max_iter=1000, net=net)
+            r["budget"] = 1000
+            r["warm"] = None
+            r["surrogate"] = train_info
+            pcg_runs.append(r)
+            log(f"pcg with the network's start: ms/step {r['ms_step']:.3f}, iterations {r['info'].pcg_iters}")
     cpu = None
     err = {}
     if not args.no_cpu_baseline:
@@ -340,6 +393,7 @@ def main():
             "warm_start": (None if r["warm"] is None else
                            f"MBFs of the unchanged field; timed builds on k * exp({r['warm']} g), "
                            "g standard normal per cell"),
+            "surrogate": r["surrogate"],
             "value": info.n_mbfs / (r["ms_step"] * 1e-3),
             "fallback_subdomains": int(r["info"].pcg_fallback),
             "inner_iterations": int(r["info"].pcg_iters),

@@ -137,6 +137,10 @@ typedef struct {
  *              subdomain l in id order, n_cells x n_rhs, row-major in the
  *              local row ordering, the same layout as mrcm_copy_mbfs), or NULL
  *              for zero.  Read during the call only.
+ * pcg_x0_scale PCG: nonzero to replace each column's starting guess v by
+ *              c v with c = (v, b) / (v, A v), the multiple of v closest to the
+ *              solution in the A-norm (for a guess known only up to scale,
+ *              such as the network output of mrcm_nn.h).
  */
 typedef struct {
   double alpha;
@@ -146,6 +150,7 @@ typedef struct {
   int32_t fp64_refine;
   int32_t pcg_max_iter;
   const double *pcg_x0;
+  int32_t pcg_x0_scale;
 } mrcm_options;
 
 typedef struct mrcm_mbfs mrcm_mbfs;           /* local factors, MBFs, Gamma-flux blocks */

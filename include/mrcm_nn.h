@@ -1,0 +1,101 @@
+/*
+ * Learned warm start for the conjugate-gradient local solves (MRCM_PCG in
+ * mrcm.h).  A small 3D convolutional network maps, per right-hand-side column
+ * of a subdomain, two channels on the subdomain's cell grid -- the centred
+ * log-permeability and the right-hand side scaled to a largest magnitude of
+ * one -- to the column's solution up to a scale (the MBFs of (2.25), the
+ * particular solution of (2.26)).  Its output, written into the MBF layout by
+ * mrcm_nn_scatter, is the starting guess mrcm_options.pcg_x0, scaled in the
+ * solver by pcg_x0_scale.  The paper has no learned component; this is an
+ * addition on top of its local problems.
+ *
+ * These calls are the network's kernels and the exchange of data with an
+ * MBF handle; the network's parameters, activations and optimiser state are
+ * the caller's device buffers.  Tensors are FP32 (loss FP64), layout
+ * [batch][channel][d][h][w] with w fastest.  For a subdomain the grid is its
+ * local row order viewed as [n2][n1][n0] (mrcm_subdomain_info: the extents
+ * along ax[2], ax[1], ax[0]), so one column of the MBFs is one [d][h][w]
+ * sample.  Every call is asynchronous on the given HIP stream.
+ * Errors: MRCM_EINVAL (null pointer, non-positive size, channels above 16),
+ * MRCM_EUNSUPPORTED, MRCM_ENOMEM, MRCM_EHIP.
+ */
+#ifndef MRCM_NN_H
+#define MRCM_NN_H
+
+#include "mrcm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Largest channel count of one convolution (input or output). */
+int32_t mrcm_conv3d_max_channels(void);
+
+/*
+ * y = conv(x, w) + bias: 3x3x3 cross-correlation with dilation (taps at
+ * offsets -dilation, 0, +dilation along each axis) and zero padding, output
+ * of the input's size.  x [batch][cin][d][h][w], weights [cout][cin][3][3][3]
+ * (taps kd, kh, kw), bias [cout] or NULL, y [batch][cout][d][h][w].
+ * relu != 0: y = max(y, 0).  mask (optional, shaped like y): y = 0 where
+ * mask <= 0.
+ */
+mrcm_status mrcm_conv3d_forward(const float *x, const float *weights, const float *bias, float *y,
+                                const float *mask, int32_t batch, int32_t cin, int32_t cout, int32_t d,
+                                int32_t h, int32_t w, int32_t dilation, int32_t relu, void *stream);
+
+/*
+ * Gradients of y = conv(x, w) + bias (same dilation) for a given dL/dy:
+ *  dw [cout][cin][27], db [cout] (or NULL): sums over the batch and the grid;
+ *  dx [batch][cin][d][h][w] (or NULL to skip): the transposed convolution of
+ *    dy, zeroed where dx_mask <= 0 when dx_mask (shaped like x) is given --
+ *    with dx_mask = x this applies the derivative of the ReLU that produced x.
+ * wt: workspace of cout*cin*27 floats for the transposed weights (needed when
+ * dx is requested).  Sums are taken in a fixed order (reproducible).
+ */
+mrcm_status mrcm_conv3d_backward(const float *x, const float *weights, const float *dy, float *dx, float *dw,
+                                 float *db, float *wt, const float *dx_mask, int32_t batch, int32_t cin,
+                                 int32_t cout, int32_t d, int32_t h, int32_t w, int32_t dilation, void *stream);
+
+/*
+ * Mean squared error over n entries: *loss = sum (y - t)^2 / n (one FP64
+ * value in device memory), dy = 2 (y - t) / n.  workspace: 1024 doubles.
+ */
+mrcm_status mrcm_mse(const float *y, const float *t, float *dy, double *loss, double *workspace, int64_t n,
+                     void *stream);
+
+/*
+ * One Adam step (Kingma and Ba, 2015) on n parameters at step t >= 1:
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ */
+mrcm_status mrcm_adam_step(float *p, const float *g, float *m, float *v, int32_t n, int32_t t, float lr,
+                           float b1, float b2, float eps, void *stream);
+
+/*
+ * Network samples of the listed subdomains (host array subs, n_subs entries,
+ * all with the same grid): sample s = (position of l in subs, column c) in
+ * that order, i.e. the columns of subs[0] first.  From the handle's current
+ * build:
+ *  inp [samples][2][d][h][w]: log kx minus its mean over the subdomain, and
+ *       the column's right-hand side divided by its largest magnitude;
+ *  tgt [samples][1][d][h][w] (or NULL): the column's solution X divided by
+ *       its root mean square (zero columns stay zero).
+ * The right-hand sides are formed again into the handle's refinement buffer
+ * (allocated on first use).
+ */
+mrcm_status mrcm_nn_features(mrcm_mbfs *mbfs, const int32_t *subs, int32_t n_subs, float *inp, float *tgt,
+                             void *stream);
+
+/*
+ * x0 (MBF layout, as mrcm_options.pcg_x0) for the listed subdomains from the
+ * network's outputs out [samples][d][h][w] in the order of
+ * mrcm_nn_features; entries of other subdomains are left as they are.
+ */
+mrcm_status mrcm_nn_scatter(mrcm_mbfs *mbfs, const int32_t *subs, int32_t n_subs, const float *out, double *x0,
+                            void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRCM_NN_H */

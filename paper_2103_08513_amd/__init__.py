@@ -104,11 +104,12 @@ class MRCM:
         self._opt = opt
 
     # -- the four steps of Algorithm 2 ------------------------------------
-    def build_mbfs(self, kx, ky, kz, q, stream=None, x0=None):
+    def build_mbfs(self, kx, ky, kz, q, stream=None, x0=None, x0_scale=False):
         """x0 (PCG only): starting guess, a float64 device tensor in the layout
         of the MBFs (all subdomains' local blocks concatenated, see
         ``mbf_layout``), or None.  A warm start needs the handle of an earlier
-        build, whose layout fixes the tensor's length."""
+        build, whose layout fixes the tensor's length.  x0_scale: replace each
+        column's guess v by its Galerkin multiple (v, b) / (v, A v) v."""
         cp = self._cp
         if x0 is not None:
             if not self._mbfs.value:
@@ -117,6 +118,7 @@ class MRCM:
             if x0.numel() != total:
                 raise ValueError(f"x0 has {x0.numel()} entries; the MBF layout has {total}")
         self._opt.pcg_x0 = None if x0 is None else _dev_ptr(x0, "x0").value
+        self._opt.pcg_x0_scale = 1 if x0_scale else 0
         cp.kx = _dev_ptr(kx, "kx").value
         cp.ky = _dev_ptr(ky, "ky").value
         cp.kz = _dev_ptr(kz, "kz").value

@@ -3,7 +3,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_uint32, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_uint32, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmrcm.so")
@@ -18,6 +18,9 @@ EXPORTS = [
     "mrcm_interface_dims", "mrcm_copy_interface", "mrcm_mbfs_destroy", "mrcm_interface_destroy",
     "mrcm_status_string", "mrcm_last_error", "mrcm_profile_enable", "mrcm_profile_reset",
     "mrcm_profile_get",
+    # mrcm_nn.h
+    "mrcm_conv3d_max_channels", "mrcm_conv3d_forward", "mrcm_conv3d_backward", "mrcm_mse", "mrcm_adam_step",
+    "mrcm_nn_features", "mrcm_nn_scatter",
 ]
 
 STAGES = ["coef", "factor", "rhs", "solve", "residual", "refine", "flux", "assemble", "lu", "sweep",
@@ -44,7 +47,7 @@ class CIfaceSpace(ctypes.Structure):
 class COptions(ctypes.Structure):
     _fields_ = [("alpha", c_double), ("precision", c_int32), ("ir_tol", c_double),
                 ("ir_max_iter", c_int32), ("fp64_refine", c_int32), ("pcg_max_iter", c_int32),
-                ("pcg_x0", ctypes.c_void_p)]
+                ("pcg_x0", ctypes.c_void_p), ("pcg_x0_scale", c_int32)]
 
 
 class CInfo(ctypes.Structure):
@@ -98,6 +101,14 @@ def load(path: str = LIB_PATH):
         "mrcm_profile_enable": ([c_int32], None),
         "mrcm_profile_reset": ([], None),
         "mrcm_profile_get": ([P(CProfile)], c_int32),
+        "mrcm_conv3d_max_channels": ([], c_int32),
+        "mrcm_conv3d_forward": ([c_void_p] * 5 + [c_int32] * 8 + [c_void_p], c_int32),
+        "mrcm_conv3d_backward": ([c_void_p] * 8 + [c_int32] * 7 + [c_void_p], c_int32),
+        "mrcm_mse": ([c_void_p] * 5 + [c_int64, c_void_p], c_int32),
+        "mrcm_adam_step": ([c_void_p] * 4 + [c_int32, c_int32, c_float, c_float, c_float, c_float, c_void_p],
+                           c_int32),
+        "mrcm_nn_features": ([c_void_p, P(c_int32), c_int32, c_void_p, c_void_p, c_void_p], c_int32),
+        "mrcm_nn_scatter": ([c_void_p, P(c_int32), c_int32, c_void_p, c_void_p, c_void_p], c_int32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)

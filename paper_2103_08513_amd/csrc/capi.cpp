@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/mrcm.h"
+#include "../../include/mrcm_nn.h"
 #include "internal.h"
 #include "launch.h"
 
@@ -519,10 +520,14 @@ struct mrcm_mbfs {
   int4 *d_fb_work = nullptr;
   int pcg_max = 50;
   const double *pcg_x0 = nullptr;
+  int pcg_x0_scale = 0;
   int pcg_fallback = 0;
   int64_t pcg_iters = 0;
   std::vector<int> fb_order;   // host copies kept until the next build
   std::vector<int4> fb_work;
+  // network samples: selected subdomains and their first sample index
+  int *d_nn_sel = nullptr, *d_nn_s0 = nullptr;
+  std::vector<int> nn_sel, nn_s0;
   int *d_patches = nullptr;
   int *d_subof[3] = {nullptr, nullptr, nullptr};
   double *coef = nullptr, *r0 = nullptr, *scal = nullptr;
@@ -560,7 +565,7 @@ void free_mbfs(mrcm_mbfs *h) {
   void *ptrs[] = {h->d_sub, h->d_ifc, h->d_order, h->d_work, h->d_patches, h->d_subof[0], h->d_subof[1],
                   h->d_subof[2], h->coef, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, h->F, h->Fb, h->SAb,
                   h->norms, h->scalar, h->st, h->d_grp_subs[0], h->d_grp_subs[1], h->d_order_split,
-                  h->d_colsub, h->d_iters, h->d_conv, h->d_fb_order, h->d_fb_work};
+                  h->d_colsub, h->d_iters, h->d_conv, h->d_fb_order, h->d_fb_work, h->d_nn_sel, h->d_nn_s0};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
@@ -776,6 +781,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   h->ir_tol = opt->ir_tol > 0.0 ? opt->ir_tol : (opt->precision == MRCM_PCG ? 1e-10 : 1e-13);
   h->pcg_max = opt->pcg_max_iter > 0 ? opt->pcg_max_iter : 50;
   h->pcg_x0 = opt->pcg_x0;
+  h->pcg_x0_scale = opt->pcg_x0_scale;
   h->ir_max = opt->ir_max_iter > 0 ? opt->ir_max_iter : 30;
   if (opt->fp64_refine < 0 || opt->fp64_refine > 10) return fail(MRCM_EINVAL, "fp64_refine must be in [0, 10]");
   h->refine64 = opt->fp64_refine;
@@ -832,7 +838,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     {
       Stage t(MRCM_STAGE_PCG, s);
       ENQ(launch_pcg(g, h->d_colsub, H.totCols, H.max_cells, h->coef, h->scal, h->R, h->pcg_x0, h->X, h->pcg_max,
-                     h->ir_tol, h->d_iters, h->d_conv, s));
+                     h->ir_tol, h->pcg_x0_scale, h->d_iters, h->d_conv, s));
       ENQ(hipMemcpyAsync(conv.data(), h->d_conv, conv.size() * sizeof(int), hipMemcpyDeviceToHost, s));
       ENQ(hipMemcpyAsync(its.data(), h->d_iters, its.size() * sizeof(int), hipMemcpyDeviceToHost, s));
       ENQ(hipStreamSynchronize(s));
@@ -1207,6 +1213,131 @@ mrcm_status mrcm_profile_get(mrcm_profile *out) {
     out->ms[i] = g_prof.ms[i];
     out->count[i] = g_prof.count[i];
   }
+  return MRCM_OK;
+}
+
+int32_t mrcm_conv3d_max_channels(void) { return conv3d_max_channels(); }
+
+namespace {
+mrcm_status check_conv(const void *x, const void *w, const void *y, int32_t batch, int32_t cin, int32_t cout,
+                       int32_t d, int32_t h, int32_t wd) {
+  if (!x || !w || !y) return fail(MRCM_EINVAL, "null tensor");
+  if (batch <= 0 || cin <= 0 || cout <= 0 || d <= 0 || h <= 0 || wd <= 0)
+    return fail(MRCM_EINVAL, "sizes must be positive");
+  if (cin > conv3d_max_channels() || cout > conv3d_max_channels())
+    return fail(MRCM_EINVAL, "at most " + std::to_string(conv3d_max_channels()) + " channels");
+  if ((long long)batch * d * h * wd * std::max(cin, cout) >= (1LL << 40)) return fail(MRCM_EUNSUPPORTED, "tensor too large");
+  return MRCM_OK;
+}
+
+// Uploads the selection (subdomains with the same grid) and each one's first
+// sample; returns the sample size V and the largest column count.
+mrcm_status nn_select(mrcm_mbfs *h, const int32_t *subs, int32_t n, hipStream_t s, int &V, int &mmax) {
+  if (!h || !subs || n <= 0) return fail(MRCM_EINVAL, "null handle or empty subdomain list");
+  const HostGeom &G = h->G;
+  const int n_sub = (int)G.subs.size();
+  h->nn_sel.assign(subs, subs + n);
+  h->nn_s0.resize(n);
+  int s0 = 0;
+  mmax = 0;
+  V = -1;
+  int shape[3] = {0, 0, 0};
+  for (int k = 0; k < n; ++k) {
+    const int l = subs[k];
+    if (l < 0 || l >= n_sub) return fail(MRCM_EINVAL, "subdomain out of range");
+    const SubDesc &S = G.subs[l];
+    if (k == 0) {
+      shape[0] = S.n0;
+      shape[1] = S.n1;
+      shape[2] = S.n2;
+      V = S.N;
+    } else if (S.n0 != shape[0] || S.n1 != shape[1] || S.n2 != shape[2]) {
+      return fail(MRCM_EINVAL, "the listed subdomains must share one grid");
+    }
+    h->nn_s0[k] = s0;
+    s0 += S.m;
+    mmax = std::max(mmax, S.m);
+  }
+  if (!h->d_nn_sel) {
+    if (dev_alloc(&h->d_nn_sel, (size_t)n_sub) != hipSuccess || dev_alloc(&h->d_nn_s0, (size_t)n_sub) != hipSuccess)
+      return fail(MRCM_ENOMEM, "device allocation of the sample lists failed");
+  }
+  if (n > n_sub) return fail(MRCM_EINVAL, "more subdomains listed than the handle has");
+  HIP_TRY(hipMemcpyAsync(h->d_nn_sel, h->nn_sel.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->d_nn_s0, h->nn_s0.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+  return MRCM_OK;
+}
+}  // namespace
+
+mrcm_status mrcm_conv3d_forward(const float *x, const float *weights, const float *bias, float *y,
+                                const float *mask, int32_t batch, int32_t cin, int32_t cout, int32_t d,
+                                int32_t h, int32_t w, int32_t dilation, int32_t relu, void *stream) {
+  mrcm_status st = check_conv(x, weights, y, batch, cin, cout, d, h, w);
+  if (st != MRCM_OK) return st;
+  if (dilation < 1) return fail(MRCM_EINVAL, "dilation must be at least 1");
+  HIP_TRY(launch_conv3d(x, weights, bias, y, mask, batch, cin, cout, d, h, w, dilation, relu, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_conv3d_backward(const float *x, const float *weights, const float *dy, float *dx, float *dw,
+                                 float *db, float *wt, const float *dx_mask, int32_t batch, int32_t cin,
+                                 int32_t cout, int32_t d, int32_t h, int32_t w, int32_t dilation, void *stream) {
+  mrcm_status st = check_conv(x, weights, dy, batch, cin, cout, d, h, w);
+  if (st != MRCM_OK) return st;
+  if (dilation < 1) return fail(MRCM_EINVAL, "dilation must be at least 1");
+  if (!dw) return fail(MRCM_EINVAL, "dw is required");
+  if (dx && !wt) return fail(MRCM_EINVAL, "dx needs the workspace wt");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_conv3d_wgrad(x, dy, dw, db, batch, cin, cout, d, h, w, dilation, s));
+  if (dx) {
+    HIP_TRY(launch_conv3d_flip(weights, wt, cin, cout, s));
+    HIP_TRY(launch_conv3d(dy, wt, nullptr, dx, dx_mask, batch, cout, cin, d, h, w, dilation, 0, s));
+  }
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_mse(const float *y, const float *t, float *dy, double *loss, double *workspace, int64_t n,
+                     void *stream) {
+  if (!y || !t || !dy || !loss || !workspace) return fail(MRCM_EINVAL, "null argument");
+  if (n <= 0) return fail(MRCM_EINVAL, "n must be positive");
+  HIP_TRY(launch_mse(y, t, dy, workspace, loss, n, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_adam_step(float *p, const float *g, float *m, float *v, int32_t n, int32_t t, float lr,
+                           float b1, float b2, float eps, void *stream) {
+  if (!p || !g || !m || !v) return fail(MRCM_EINVAL, "null argument");
+  if (n <= 0 || t < 1) return fail(MRCM_EINVAL, "n must be positive and t at least 1");
+  HIP_TRY(launch_adam(p, g, m, v, n, t, lr, b1, b2, eps, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_nn_features(mrcm_mbfs *h, const int32_t *subs, int32_t n_subs, float *inp, float *tgt,
+                             void *stream) {
+  if (!inp) return fail(MRCM_EINVAL, "null input tensor");
+  hipStream_t s = (hipStream_t)stream;
+  int V = 0, mmax = 0;
+  mrcm_status st = nn_select(h, subs, n_subs, s, V, mmax);
+  if (st != MRCM_OK) return st;
+  const HostGeom &H = h->G;
+  if (!h->R) {
+    if (dev_alloc(&h->R, (size_t)H.totX) != hipSuccess)
+      return fail(MRCM_ENOMEM, "device allocation of the right-hand-side buffer failed");
+    h->bytes += H.totX * 8;
+  }
+  HIP_TRY(launch_rhs(h->g, h->n_sub, H.max_cells, h->r0, h->R, s));
+  HIP_TRY(launch_nn_features(h->g, h->d_nn_sel, h->d_nn_s0, n_subs, mmax, h->R, h->X, V, inp, tgt, s));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_nn_scatter(mrcm_mbfs *h, const int32_t *subs, int32_t n_subs, const float *out, double *x0,
+                            void *stream) {
+  if (!out || !x0) return fail(MRCM_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  int V = 0, mmax = 0;
+  mrcm_status st = nn_select(h, subs, n_subs, s, V, mmax);
+  if (st != MRCM_OK) return st;
+  HIP_TRY(launch_nn_scatter(h->g, h->d_nn_sel, h->d_nn_s0, n_subs, mmax, out, V, x0, s));
   return MRCM_OK;
 }
 

@@ -41,7 +41,24 @@ hipError_t launch_flux(const Geom &g, int n_sub, const double *X, double *F, dou
 int pcg_max_cells();
 hipError_t launch_pcg(const Geom &g, const int *col_sub, int ncols, int max_cells, const double *coef,
                       const double *scal, const double *B, const double *X0, double *X, int max_iter, double tol,
-                      int *iters, int *conv, hipStream_t s);
+                      int x0_scale, int *iters, int *conv, hipStream_t s);
+
+// Network of the learned warm start (nn_kernels.hip)
+int conv3d_max_channels();
+hipError_t launch_conv3d(const float *x, const float *w, const float *bias, float *y, const float *mask, int B,
+                         int Cin, int Cout, int D, int H, int W, int dil, int relu, hipStream_t s);
+hipError_t launch_conv3d_flip(const float *w, float *wt, int Cin, int Cout, hipStream_t s);
+hipError_t launch_conv3d_wgrad(const float *x, const float *dy, float *dw, float *db, int B, int Cin, int Cout,
+                               int D, int H, int W, int dil, hipStream_t s);
+int mse_partials(long long n);
+hipError_t launch_mse(const float *y, const float *t, float *dy, double *part, double *loss, long long n,
+                      hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, int t, float lr, float b1, float b2,
+                       float eps, hipStream_t s);
+hipError_t launch_nn_features(const Geom &g, const int *sel, const int *sample0, int n_sel, int mmax,
+                              const double *R, const double *X, int V, float *inp, float *tgt, hipStream_t s);
+hipError_t launch_nn_scatter(const Geom &g, const int *sel, const int *sample0, int n_sel, int mmax,
+                             const float *out, int V, double *x0, hipStream_t s);
 
 // Interface system and reconstruction (iface_kernels.hip)
 hipError_t launch_fill(double *a, long long n, double v, hipStream_t s);

@@ -160,6 +160,20 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
 #pragma unroll
     for (int i = 0; i < CPT; ++i) xr[NT * i] = 0.0;
   }
+  // (A x)_r in FP64 from the coefficients, x in xs (row rc, clamped);
+  // neighbours outside the box carry zero coefficients or read zero rows
+  const auto apply_a = [&](int rc) {
+    const int m1 = max(rc - 1, 0), mn = max(rc - n0, 0), mb = max(rc - b, 0);
+    const double *xc = xs + kPad + rc;
+    double a = cf[4 * rc] * xc[0];
+    a -= cf[4 * rc + 1] * xc[1];
+    a -= cf[4 * m1 + 1] * xc[-1];
+    a -= cf[4 * rc + 2] * xc[n0];
+    a -= cf[4 * mn + 2] * xc[-n0];
+    a -= cf[4 * rc + 3] * xc[b];
+    a -= cf[4 * mb + 3] * xc[-b];
+    return a;
+  };
   while (!ok) {
     // FP64 residual r = b - A x from the coefficients (x in xs)
     double res[CPT];
@@ -169,16 +183,7 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
     for (int i = 0; i < CPT; ++i) {
       const int r = t + NT * i;
       const int rc = min(r, N - 1);
-      const int m1 = max(rc - 1, 0), mn = max(rc - n0, 0), mb = max(rc - b, 0);
-      const double *xc = xs + kPad + rc;
-      // neighbours outside the box carry zero coefficients or read zero rows
-      double a = cf[4 * rc] * xc[0];
-      a -= cf[4 * rc + 1] * xc[1];
-      a -= cf[4 * m1 + 1] * xc[-1];
-      a -= cf[4 * rc + 2] * xc[n0];
-      a -= cf[4 * mn + 2] * xc[-n0];
-      a -= cf[4 * rc + 3] * xc[b];
-      a -= cf[4 * mb + 3] * xc[-b];
+      const double a = apply_a(rc);
       const double rv = r < N ? B[(size_t)rc * m + c] - a : 0.0;
       const double sv = sc[rc] * rv;
       res[i] = sv;
@@ -278,11 +283,73 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
   }
 }
 
+// Galerkin scaling of a starting guess, one workgroup per column as k_pcg:
+// X = c V with c = (V, b) / (V, A V), the multiple of V closest to the
+// solution in the A-norm (zero when V is zero).  X may alias V only if every
+// column is read before it is written, which holds per workgroup.
+template <int NT, int CPT>
+__global__ __launch_bounds__(NT) void k_pcg_scale(Geom g, const int *__restrict__ col_sub, int ncols,
+                                                  const double *__restrict__ coef, const double *__restrict__ Bg,
+                                                  const double *V0, double *Xg) {
+  constexpr int NW = NT / 64;
+  constexpr int LEN = NT * CPT + 2 * kPad;
+  __shared__ double xs[LEN];
+  __shared__ double redd[2][NW];
+  const int per = (ncols + 7) >> 3;
+  const int col = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (col >= ncols) return;
+  const SubDesc &S = g.sub[col_sub[col]];
+  const int N = S.N, m = S.m, n0 = S.n0, b = S.b;
+  const int c = col - S.col_off;
+  const double *cf = coef + 4 * S.cell_off;
+  const double *B = Bg + S.X_off;
+  const double *V = V0 + S.X_off;
+  double *X = Xg + S.X_off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k = tid; k < LEN; k += NT) xs[k] = 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    const int r = tid + NT * i;
+    if (r < N) xs[kPad + r] = V[(size_t)r * m + c];
+  }
+  __syncthreads();
+  double vb = 0.0, vav = 0.0;
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    const int r = tid + NT * i;
+    const int rc = min(r, N - 1);
+    const int m1 = max(rc - 1, 0), mn = max(rc - n0, 0), mb = max(rc - b, 0);
+    const double *xc = xs + kPad + rc;
+    double a = cf[4 * rc] * xc[0];
+    a -= cf[4 * rc + 1] * xc[1];
+    a -= cf[4 * m1 + 1] * xc[-1];
+    a -= cf[4 * rc + 2] * xc[n0];
+    a -= cf[4 * mn + 2] * xc[-n0];
+    a -= cf[4 * rc + 3] * xc[b];
+    a -= cf[4 * mb + 3] * xc[-b];
+    vb += r < N ? xc[0] * B[(size_t)rc * m + c] : 0.0;
+    vav += r < N ? xc[0] * a : 0.0;
+  }
+  const double sb = block_sum<NW>(vb, redd[0], wave, lane);
+  const double sa = block_sum<NW>(vav, redd[1], wave, lane);
+  const double cs = sa > 0.0 ? sb / sa : 0.0;
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    const int r = tid + NT * i;
+    if (r < N) X[(size_t)r * m + c] = cs * xs[kPad + r];
+  }
+}
+
 template <int NT, int CPT>
 hipError_t launch_pcg_t(const Geom &g, const int *col_sub, int ncols, const double *coef, const double *scal,
-                        const double *B, const double *X0, double *X, int max_iter, double tol, int *iters,
-                        int *conv, hipStream_t s) {
+                        const double *B, const double *X0, double *X, int max_iter, double tol, int x0_scale,
+                        int *iters, int *conv, hipStream_t s) {
   const int per = (ncols + 7) / 8;
+  if (X0 && x0_scale) {
+    hipLaunchKernelGGL((k_pcg_scale<NT, CPT>), dim3(8 * per), dim3(NT), 0, s, g, col_sub, ncols, coef, B, X0, X);
+    X0 = X;
+  }
   hipLaunchKernelGGL((k_pcg<NT, CPT>), dim3(8 * per), dim3(NT), 0, s, g, col_sub, ncols, coef, scal, B, X0, X,
                      max_iter, tol, iters, conv);
   return hipGetLastError();
@@ -294,14 +361,14 @@ int pcg_max_cells() { return 512 * 4; }
 
 hipError_t launch_pcg(const Geom &g, const int *col_sub, int ncols, int max_cells, const double *coef,
                       const double *scal, const double *B, const double *X0, double *X, int max_iter, double tol,
-                      int *iters, int *conv, hipStream_t s) {
+                      int x0_scale, int *iters, int *conv, hipStream_t s) {
   if (ncols <= 0) return hipSuccess;
   if (max_cells <= 512)
-    return launch_pcg_t<256, 2>(g, col_sub, ncols, coef, scal, B, X0, X, max_iter, tol, iters, conv, s);
+    return launch_pcg_t<256, 2>(g, col_sub, ncols, coef, scal, B, X0, X, max_iter, tol, x0_scale, iters, conv, s);
   if (max_cells <= 1024)
-    return launch_pcg_t<512, 2>(g, col_sub, ncols, coef, scal, B, X0, X, max_iter, tol, iters, conv, s);
+    return launch_pcg_t<512, 2>(g, col_sub, ncols, coef, scal, B, X0, X, max_iter, tol, x0_scale, iters, conv, s);
   if (max_cells <= 2048)
-    return launch_pcg_t<512, 4>(g, col_sub, ncols, coef, scal, B, X0, X, max_iter, tol, iters, conv, s);
+    return launch_pcg_t<512, 4>(g, col_sub, ncols, coef, scal, B, X0, X, max_iter, tol, x0_scale, iters, conv, s);
   return hipErrorInvalidValue;
 }
 

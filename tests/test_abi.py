@@ -1,5 +1,6 @@
 """The C ABI: the library loads without a GPU, exports every entry point that
-include/mrcm.h declares, and the ctypes structures match the C layout."""
+include/*.h declares, and the ctypes structures match the C layout."""
+import glob
 import ctypes
 import os
 import re
@@ -12,9 +13,11 @@ HEADER = os.path.join(ROOT, "include", "mrcm.h")
 
 
 def _declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mrcm_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(mrcm_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_three_named_entry_points():
