@@ -107,6 +107,25 @@ def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=
         if prof.count[i]:
             stages[name] = {"ms_total": prof.ms[i], "count": int(prof.count[i]),
                             "ms_avg": prof.ms[i] / prof.count[i]}
+    # the same step replayed from a recorded HIP graph (FP64 form only)
+    graph_ms = None
+    if precision == 0:
+        nv = model.info().n_patch
+        Xg = torch.empty(2 * nv, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        gs = torch.cuda.Stream()  # capture needs a stream other than the null stream
+        g = model.capture(kx, ky, kz, q, Xg, p, U, refine=refine, stream=gs)
+        for _ in range(warmup):
+            g.launch(stream=gs)
+        g.check(stream=gs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.launch(stream=gs)
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) * 1e3 / steps
+        g.check(stream=gs)
+        g.close()
     # the interface residual once, outside the timed and profiled loops
     model.solve_interface(X, refine=refine, residual=True)
     torch.cuda.synchronize()
@@ -117,7 +136,7 @@ def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=
         si = model.subdomain(l)
         shapes.append((si.n_cells, si.band, si.n_rhs, si.solve_group))
     n_dims, w = model.interface_dims()
-    out = dict(ms_step=ms_step, stages=stages, info=info, interface_n=n_dims, interface_w=w,
+    out = dict(ms_step=ms_step, graph_ms=graph_ms, stages=stages, info=info, interface_n=n_dims, interface_w=w,
                p=p.cpu().numpy(), U=U.view(6, N).cpu().numpy(), X=X.cpu().numpy(),
                interface_residual=model.interface_residual, sub_shapes=shapes)
     model.close()
@@ -293,6 +312,8 @@ def main():
     log(f"workload 60x220x85, precision {args.precision}, steps {args.steps}, warmup {args.warmup}")
     res = run_gpu(case, prec, args.steps, args.warmup, args.refine, args.fp64_refine)
     info = res["info"]
+    if res["graph_ms"] is not None:
+        log(f"graph replay ms/step {res['graph_ms']:.3f}")
     log(f"ms/step {res['ms_step']:.3f}; stages " +
         ", ".join(f"{k} {v['ms_avg']:.3f}" for k, v in res["stages"].items()))
     secondary = None
@@ -363,6 +384,9 @@ def main():
                    "cells": pb.n, "subdomains": info.n_sub, "patches": info.n_patch,
                    "mbfs": int(info.n_mbfs), "precision": args.precision},
         "mcells_per_s": pb.n / t_step / 1e6,
+        "graph": (None if res["graph_ms"] is None else
+                  {"ms_per_step": res["graph_ms"], "value": info.n_mbfs / (res["graph_ms"] * 1e-3),
+                   "what": "the same step recorded once by stream capture and replayed (mrcm_graph_launch)"}),
         "build_mbfs_per_s": info.n_mbfs / (build_ms * 1e-3) if build_ms > 0 else None,
         "build_ms": build_ms,
         "stages_ms": {k: round(v["ms_avg"] * v["count"] / args.steps, 4) for k, v in res["stages"].items()},

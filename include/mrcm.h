@@ -301,6 +301,32 @@ void mrcm_profile_enable(int32_t on);
 void mrcm_profile_reset(void);
 mrcm_status mrcm_profile_get(mrcm_profile *out /* [host] */);
 
+/*
+ * Orchestration (Algorithm 2 as one unit of work): the whole step
+ * mrcm_build_mbfs -> mrcm_assemble_interface -> mrcm_solve_interface ->
+ * mrcm_reconstruct recorded once into a HIP graph by stream capture, then
+ * replayed with one launch.
+ *  Requirements: precision MRCM_FP64 (the other forms take host decisions
+ *  between kernels); mbfs and iface already built for this configuration
+ *  (the capture rebuilds in place and allocates nothing); stream not the
+ *  null stream.  The graph keeps the addresses of the problem's arrays
+ *  (kx, ky, kz, q, wall values) and of X, p and U: a replay reads the
+ *  arrays' current contents, so a new field is copied into the same buffers.
+ *  mrcm_graph_launch enqueues one replay (asynchronous).  Errors the kernels
+ *  flag (invalid permeability, non-positive local pivot, zero interface
+ *  pivot) are read by mrcm_graph_check, which synchronises the stream.
+ *  The handles must outlive the graph; calls that overlap a replay on the
+ *  same handles race.
+ */
+typedef struct mrcm_graph mrcm_graph;
+mrcm_status mrcm_graph_capture(const mrcm_problem *problem, const mrcm_partition *partition,
+                               const mrcm_iface_space *iface_space, const mrcm_options *options,
+                               mrcm_mbfs *mbfs, mrcm_interface *iface, int32_t refine, double *X, double *p,
+                               double *U, void *stream, mrcm_graph **out);
+mrcm_status mrcm_graph_launch(mrcm_graph *graph, void *stream);
+mrcm_status mrcm_graph_check(mrcm_graph *graph, void *stream);
+void mrcm_graph_destroy(mrcm_graph *graph);
+
 void mrcm_mbfs_destroy(mrcm_mbfs *mbfs);
 void mrcm_interface_destroy(mrcm_interface *iface);
 const char *mrcm_status_string(mrcm_status status);

@@ -43,6 +43,33 @@ def _stream_ptr(stream=None):
     return c_void_p(s.cuda_stream)
 
 
+class Graph:
+    """A recorded MRCM step (mrcm_graph_capture): launch() replays it on a
+    stream, check() synchronises and raises on a status the kernels set."""
+
+    def __init__(self, model, handle, keep):
+        self.model = model
+        self.handle = handle
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _lib.check(self.model.lib.mrcm_graph_launch(self.handle, _stream_ptr(stream)), "mrcm_graph_launch")
+
+    def check(self, stream=None):
+        _lib.check(self.model.lib.mrcm_graph_check(self.handle, _stream_ptr(stream)), "mrcm_graph_check")
+
+    def close(self):
+        if self.handle:
+            self.model.lib.mrcm_graph_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class MRCM:
     """One MRCM configuration (grid, walls, pin, partition, interface space,
     Robin parameter, precision) and its device handles.
@@ -170,6 +197,27 @@ class MRCM:
         self.assemble_interface(stream)
         X = self.solve_interface(refine=refine, stream=stream)
         return self.reconstruct(X, stream=stream) + (X,)
+
+    def capture(self, kx, ky, kz, q, X, p, U, refine=0, stream=None):
+        """Record one whole MRCM step (build, assembly, interface solve,
+        reconstruction) as a HIP graph (FP64 form, handles already built).
+        The graph keeps the addresses of kx, ky, kz, q, X, p and U: a replay
+        reads their current contents.  Returns a Graph."""
+        cp = self._cp
+        cp.kx = _dev_ptr(kx, "kx").value
+        cp.ky = _dev_ptr(ky, "ky").value
+        cp.kz = _dev_ptr(kz, "kz").value
+        cp.q = _dev_ptr(q, "q").value
+        self._opt.pcg_x0 = None
+        self._opt.pcg_x0_scale = 0
+        g = c_void_p()
+        nv = self.info().n_patch
+        code = self.lib.mrcm_graph_capture(byref(cp), byref(self._part), byref(self._ifs), byref(self._opt),
+                                           self._mbfs, self._iface, int(refine),
+                                           _dev_ptr(X, "X") if nv > 0 else None, _dev_ptr(p, "p"),
+                                           _dev_ptr(U, "U"), _stream_ptr(stream), byref(g))
+        _lib.check(code, "mrcm_graph_capture")
+        return Graph(self, g, (kx, ky, kz, q, X, p, U))
 
     # -- introspection ------------------------------------------------------
     def info(self):

@@ -17,7 +17,7 @@ EXPORTS = [
     "mrcm_query", "mrcm_get_subdomain", "mrcm_copy_mbfs", "mrcm_copy_flux", "mrcm_copy_factor",
     "mrcm_interface_dims", "mrcm_copy_interface", "mrcm_mbfs_destroy", "mrcm_interface_destroy",
     "mrcm_status_string", "mrcm_last_error", "mrcm_profile_enable", "mrcm_profile_reset",
-    "mrcm_profile_get",
+    "mrcm_profile_get", "mrcm_graph_capture", "mrcm_graph_launch", "mrcm_graph_check", "mrcm_graph_destroy",
     # mrcm_nn.h
     "mrcm_conv3d_max_channels", "mrcm_conv3d_forward", "mrcm_conv3d_backward", "mrcm_mse", "mrcm_adam_step",
     "mrcm_nn_features", "mrcm_nn_scatter",
@@ -101,6 +101,11 @@ def load(path: str = LIB_PATH):
         "mrcm_profile_enable": ([c_int32], None),
         "mrcm_profile_reset": ([], None),
         "mrcm_profile_get": ([P(CProfile)], c_int32),
+        "mrcm_graph_capture": ([P(CProblem), P(CPartition), P(CIfaceSpace), P(COptions), c_void_p, c_void_p,
+                                c_int32, c_void_p, c_void_p, c_void_p, c_void_p, P(c_void_p)], c_int32),
+        "mrcm_graph_launch": ([c_void_p, c_void_p], c_int32),
+        "mrcm_graph_check": ([c_void_p, c_void_p], c_int32),
+        "mrcm_graph_destroy": ([c_void_p], None),
         "mrcm_conv3d_max_channels": ([], c_int32),
         "mrcm_conv3d_forward": ([c_void_p] * 5 + [c_int32] * 8 + [c_void_p], c_int32),
         "mrcm_conv3d_backward": ([c_void_p] * 8 + [c_int32] * 7 + [c_void_p], c_int32),

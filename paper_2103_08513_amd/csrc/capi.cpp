@@ -457,13 +457,16 @@ struct Profile {
   std::vector<Pending> pending;
 };
 Profile g_prof;
+// set while mrcm_graph_capture records a step: every call then only
+// enqueues work (no status reads, synchronisations or profiling events)
+thread_local bool g_capturing = false;
 
 struct Stage {
   int stage;
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
   Stage(int st, hipStream_t str) : stage(st), s(str) {
-    if (!g_prof.on) return;
+    if (!g_prof.on || g_capturing) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
       a = b = nullptr;
       return;
@@ -478,6 +481,7 @@ struct Stage {
 };
 
 void profile_flush() {
+  if (g_capturing) return;
   for (auto &p : g_prof.pending) {
     float ms = 0.f;
     if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
@@ -710,6 +714,7 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
 }
 
 mrcm_status read_status(DevStatus *st, hipStream_t s, const char *what) {
+  if (g_capturing) return MRCM_OK;  // read after a replay by mrcm_graph_check
   DevStatus hs;
   HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1016,7 +1021,7 @@ mrcm_status mrcm_assemble_interface(const mrcm_mbfs *mb, void *stream, mrcm_inte
       e = launch_iface_scatter(mb->g, mb->n_sub, mb->d_patches, h->d_pos, mb->F, mb->Fb, mb->SAb,
                                h->AB0, h->w, h->b0, s);
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && !g_capturing) e = hipStreamSynchronize(s);
   profile_flush();
   if (e != hipSuccess) return bail(fail(MRCM_EHIP, std::string("interface assembly: ") + hipGetErrorString(e)));
   *out = h;
@@ -1078,7 +1083,7 @@ mrcm_status mrcm_reconstruct(const mrcm_mbfs *mb, const double *X, void *stream,
     HIP_TRY(launch_recon_p(mb->g, mb->n_sub, mb->d_patches, mb->X, X, mb->G.n_patch, p, s));
     HIP_TRY(launch_recon_u(mb->g, p, X, mb->G.n_patch, U, s));
   }
-  if (g_prof.on) {
+  if (g_prof.on && !g_capturing) {
     HIP_TRY(hipStreamSynchronize(s));
     profile_flush();
   }
@@ -1214,6 +1219,78 @@ mrcm_status mrcm_profile_get(mrcm_profile *out) {
     out->count[i] = g_prof.count[i];
   }
   return MRCM_OK;
+}
+
+struct mrcm_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  mrcm_mbfs *mb = nullptr;
+  mrcm_interface *ifc = nullptr;
+};
+
+mrcm_status mrcm_graph_capture(const mrcm_problem *pb, const mrcm_partition *part, const mrcm_iface_space *ifs,
+                               const mrcm_options *opt, mrcm_mbfs *mb, mrcm_interface *ifc, int32_t refine,
+                               double *X, double *p, double *U, void *stream, mrcm_graph **out) {
+  if (!pb || !part || !ifs || !opt || !mb || !ifc || !p || !U || !out) return fail(MRCM_EINVAL, "null argument");
+  if (ifc->mb != mb) return fail(MRCM_EINVAL, "interface handle belongs to another mbfs handle");
+  if (opt->precision != MRCM_FP64 || mb->G.precision != MRCM_FP64)
+    return fail(MRCM_EUNSUPPORTED, "only the FP64 form can be captured");
+  if (!stream) return fail(MRCM_EINVAL, "capture needs a stream other than the null stream");
+  if (mb->G.n_patch > 0 && !X) return fail(MRCM_EINVAL, "X is null");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  g_capturing = true;
+  mrcm_mbfs *h = mb;
+  mrcm_interface *hi = ifc;
+  mrcm_status st = mrcm_build_mbfs(pb, part, ifs, opt, stream, &h);
+  if (st == MRCM_OK && h != mb) st = fail(MRCM_EINVAL, "the options or problem differ from the handle's");
+  if (st == MRCM_OK) st = mrcm_assemble_interface(mb, stream, &hi);
+  if (st == MRCM_OK) st = mrcm_solve_interface(ifc, refine, stream, X, nullptr);
+  if (st == MRCM_OK) st = mrcm_reconstruct(mb, X, stream, p, U);
+  g_capturing = false;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &graph);
+  if (st != MRCM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(MRCM_EHIP, std::string("stream capture: ") + hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(MRCM_EHIP, std::string("graph instantiation: ") + hipGetErrorString(e2));
+  }
+  mrcm_graph *gr = new mrcm_graph();
+  gr->graph = graph;
+  gr->exec = exec;
+  gr->mb = mb;
+  gr->ifc = ifc;
+  *out = gr;
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_graph_launch(mrcm_graph *gr, void *stream) {
+  if (!gr) return fail(MRCM_EINVAL, "null graph");
+  HIP_TRY(hipGraphLaunch(gr->exec, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_graph_check(mrcm_graph *gr, void *stream) {
+  if (!gr) return fail(MRCM_EINVAL, "null graph");
+  hipStream_t s = (hipStream_t)stream;
+  mrcm_status st = read_status(gr->mb->st, s, "mrcm_build_mbfs (graph)");
+  if (st != MRCM_OK) return st;
+  if (gr->ifc->n > 0) return read_status(gr->ifc->st, s, "mrcm_solve_interface (graph)");
+  return MRCM_OK;
+}
+
+void mrcm_graph_destroy(mrcm_graph *gr) {
+  if (!gr) return;
+  if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+  if (gr->graph) (void)hipGraphDestroy(gr->graph);
+  delete gr;
 }
 
 int32_t mrcm_conv3d_max_channels(void) { return conv3d_max_channels(); }
