@@ -34,7 +34,8 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=50, warm=None, net=None):
+def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=50, warm=None, net=None,
+            graph=True):
     """warm (PCG only): relative size of a mobility change.  The MBFs of the
     unchanged field start the conjugate gradients of every timed build on the
     field multiplied cell by cell by exp(warm * g), g standard normal (seed 7),
@@ -109,7 +110,7 @@ def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=
                             "ms_avg": prof.ms[i] / prof.count[i]}
     # the same step replayed from a recorded HIP graph (FP64 form only)
     graph_ms = None
-    if precision == 0:
+    if precision == 0 and graph:
         nv = model.info().n_patch
         Xg = torch.empty(2 * nv, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
@@ -291,6 +292,7 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the other precision")
     ap.add_argument("--no-pcg", action="store_true", help="skip the conjugate-gradient form")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the network-started conjugate gradients")
+    ap.add_argument("--no-graph", action="store_true", help="skip the replay of the recorded step")
     ap.add_argument("--copy-calibration", type=float, default=None, metavar="MB",
                     help="only run a device copy of this many MB (counter calibration) and exit")
     args = ap.parse_args()
@@ -310,7 +312,7 @@ def main():
     pb = case.problem
     prec = 1 if args.precision == "fp32ir" else 0
     log(f"workload 60x220x85, precision {args.precision}, steps {args.steps}, warmup {args.warmup}")
-    res = run_gpu(case, prec, args.steps, args.warmup, args.refine, args.fp64_refine)
+    res = run_gpu(case, prec, args.steps, args.warmup, args.refine, args.fp64_refine, graph=not args.no_graph)
     info = res["info"]
     if res["graph_ms"] is not None:
         log(f"graph replay ms/step {res['graph_ms']:.3f}")

@@ -131,7 +131,8 @@ typedef struct {
  *              the 40x40x20 and 60x220x85 workloads; 1e-8 leaves ~1e-5).  A subdomain
  *              with any column not converged within pcg_max_iter inner
  *              iterations (<= 0: 50) is factorised by the FP64 band Cholesky
- *              and all its columns are solved directly instead.
+ *              and all its columns are solved directly instead, followed by
+ *              fp64_refine refinement sweeps as in the FP64 form.
  * pcg_max_iter PCG: inner-iteration budget per column.
  * pcg_x0       PCG: [dev] starting guess in the layout of the MBFs (per
  *              subdomain l in id order, n_cells x n_rhs, row-major in the

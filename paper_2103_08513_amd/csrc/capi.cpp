@@ -870,6 +870,13 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
                         H.bmax, s));
       ENQ(launch_solve(0, g, h->d_fb_work, (int)h->fb_work.size(), h->scal, h->L, h->Dinv, h->R, h->X, 0, H.bmax,
                        s));
+      // the FP64 refinement sweeps of the direct form, on the same subdomains
+      for (int it = 0; it < h->refine64; ++it) {
+        ENQ(launch_residual(g, h->pcg_fallback, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s,
+                            h->d_fb_order));
+        ENQ(launch_solve(0, g, h->d_fb_work, (int)h->fb_work.size(), h->scal, h->L, h->Dinv, h->R, h->X, 1,
+                         H.bmax, s));
+      }
     }
   } else if (split) {
     // Per-subdomain pipeline over two streams.  The whole rounds of the

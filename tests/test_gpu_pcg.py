@@ -13,7 +13,7 @@ band Cholesky instead.  Checks, through the C ABI:
     of 1e-8 is not enough for that: the local condition numbers amplify it to
     about 1e-5 in the pressure of the 40x40x20 workload;
   * with a budget of one iteration every subdomain falls back and the MBFs are
-    bitwise those of the direct FP64 path;
+    bitwise those of the direct FP64 path with the same refinement sweeps;
   * a warm start with the exact MBFs takes no iteration and returns them.
 """
 import numpy as np
@@ -93,13 +93,14 @@ def test_pcg_residuals_and_solution(name):
     m.close()
 
 
-def test_pcg_budget_of_one_falls_back_to_direct_bitwise():
+@pytest.mark.parametrize("refine", [0, 1])
+def test_pcg_budget_of_one_falls_back_to_direct_bitwise(refine):
     case = config1()
     import paper_2103_08513_amd as lib
     args = _inputs(case)
-    d = _model(case, precision=lib.FP64, fp64_refine=0)
+    d = _model(case, precision=lib.FP64, fp64_refine=refine)
     d.build_mbfs(*args)
-    m = _model(case, precision=lib.PCG, pcg_max_iter=1)
+    m = _model(case, precision=lib.PCG, pcg_max_iter=1, fp64_refine=refine)
     m.build_mbfs(*args)
     torch.cuda.synchronize()
     info = m.info()
