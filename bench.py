@@ -35,7 +35,7 @@ def log(msg):
 
 
 def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=50, warm=None, net=None,
-            graph=True):
+            graph=True, tune=False):
     """warm (PCG only): relative size of a mobility change.  The MBFs of the
     unchanged field start the conjugate gradients of every timed build on the
     field multiplied cell by cell by exp(warm * g), g standard normal (seed 7),
@@ -54,6 +54,7 @@ def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=
     N = pb.n
     X = None
     x0 = None
+    tuned = model.autotune(kx, ky, kz, q) if tune else None
     if warm is not None:
         model.build_mbfs(kx, ky, kz, q)
         torch.cuda.synchronize()
@@ -137,7 +138,7 @@ def run_gpu(case, precision, steps, warmup, refine, fp64_refine=1, pcg_max_iter=
         si = model.subdomain(l)
         shapes.append((si.n_cells, si.band, si.n_rhs, si.solve_group))
     n_dims, w = model.interface_dims()
-    out = dict(ms_step=ms_step, graph_ms=graph_ms, stages=stages, info=info, interface_n=n_dims, interface_w=w,
+    out = dict(ms_step=ms_step, graph_ms=graph_ms, tuned=tuned, stages=stages, info=info, interface_n=n_dims, interface_w=w,
                p=p.cpu().numpy(), U=U.view(6, N).cpu().numpy(), X=X.cpu().numpy(),
                interface_residual=model.interface_residual, sub_shapes=shapes)
     model.close()
@@ -293,6 +294,7 @@ def main():
     ap.add_argument("--no-pcg", action="store_true", help="skip the conjugate-gradient form")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the network-started conjugate gradients")
     ap.add_argument("--no-graph", action="store_true", help="skip the replay of the recorded step")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default tunables)")
     ap.add_argument("--copy-calibration", type=float, default=None, metavar="MB",
                     help="only run a device copy of this many MB (counter calibration) and exit")
     args = ap.parse_args()
@@ -312,7 +314,8 @@ def main():
     pb = case.problem
     prec = 1 if args.precision == "fp32ir" else 0
     log(f"workload 60x220x85, precision {args.precision}, steps {args.steps}, warmup {args.warmup}")
-    res = run_gpu(case, prec, args.steps, args.warmup, args.refine, args.fp64_refine, graph=not args.no_graph)
+    res = run_gpu(case, prec, args.steps, args.warmup, args.refine, args.fp64_refine, graph=not args.no_graph,
+                  tune=not args.no_tune)
     info = res["info"]
     if res["graph_ms"] is not None:
         log(f"graph replay ms/step {res['graph_ms']:.3f}")
@@ -386,6 +389,7 @@ def main():
                    "cells": pb.n, "subdomains": info.n_sub, "patches": info.n_patch,
                    "mbfs": int(info.n_mbfs), "precision": args.precision},
         "mcells_per_s": pb.n / t_step / 1e6,
+        "autotune": res["tuned"],
         "graph": (None if res["graph_ms"] is None else
                   {"ms_per_step": res["graph_ms"], "value": info.n_mbfs / (res["graph_ms"] * 1e-3),
                    "what": "the same step recorded once by stream capture and replayed (mrcm_graph_launch)"}),

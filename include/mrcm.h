@@ -138,6 +138,13 @@ typedef struct {
  *              subdomain l in id order, n_cells x n_rhs, row-major in the
  *              local row ordering, the same layout as mrcm_copy_mbfs), or NULL
  *              for zero.  Read during the call only.
+ * solve_tiles  tiles of 16 right-hand-side columns per work item of the band
+ *              solves (0: the largest, 3): fewer give more, smaller items.
+ * solve_group  FP64 with refinement: subdomains whose first solve starts when
+ *              the factorisation's whole rounds are done (rounded down to a
+ *              multiple of 8); 0 derives it from the kernels' occupancy, -1
+ *              turns the two-stream pipeline off.  Both are set by
+ *              mrcm_autotune; a handle's geometry includes them.
  * pcg_x0_scale PCG: nonzero to replace each column's starting guess v by
  *              c v with c = (v, b) / (v, A v), the multiple of v closest to the
  *              solution in the A-norm (for a guess known only up to scale,
@@ -152,6 +159,8 @@ typedef struct {
   int32_t pcg_max_iter;
   const double *pcg_x0;
   int32_t pcg_x0_scale;
+  int32_t solve_tiles;
+  int32_t solve_group;
 } mrcm_options;
 
 typedef struct mrcm_mbfs mrcm_mbfs;           /* local factors, MBFs, Gamma-flux blocks */
@@ -319,6 +328,18 @@ mrcm_status mrcm_profile_get(mrcm_profile *out /* [host] */);
  *  The handles must outlive the graph; calls that overlap a replay on the
  *  same handles race.
  */
+/*
+ * Autotuner: times mrcm_build_mbfs on the given problem for candidate values
+ * of solve_tiles and solve_group (each candidate on a handle of its own:
+ * one untimed and three timed builds, synchronised, the fastest counted) and
+ * writes into *best a copy of *base with the fastest pair.  *best_ms and
+ * *rule_ms (either may be NULL): the fastest build and that of base's own
+ * pair.  Allocates and frees one handle per candidate.
+ */
+mrcm_status mrcm_autotune(const mrcm_problem *problem, const mrcm_partition *partition,
+                          const mrcm_iface_space *iface_space, const mrcm_options *base, void *stream,
+                          mrcm_options *best, double *best_ms, double *rule_ms);
+
 typedef struct mrcm_graph mrcm_graph;
 mrcm_status mrcm_graph_capture(const mrcm_problem *problem, const mrcm_partition *partition,
                                const mrcm_iface_space *iface_space, const mrcm_options *options,

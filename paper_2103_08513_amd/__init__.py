@@ -78,7 +78,7 @@ class MRCM:
     ``mrcm_inputs`` (or any objects with the same attributes)."""
 
     def __init__(self, problem, partition, iface, alpha=1.0, precision=FP64, ir_tol=1e-13,
-                 ir_max_iter=30, fp64_refine=1, pcg_max_iter=50, device="cuda"):
+                 ir_max_iter=30, fp64_refine=1, pcg_max_iter=50, solve_tiles=0, solve_group=0, device="cuda"):
         import torch
         self.lib = library()
         self.device = torch.device(device)
@@ -127,6 +127,8 @@ class MRCM:
         opt.ir_max_iter = int(ir_max_iter)
         opt.fp64_refine = int(fp64_refine)
         opt.pcg_max_iter = int(pcg_max_iter)
+        opt.solve_tiles = int(solve_tiles)
+        opt.solve_group = int(solve_group)
         opt.pcg_x0 = None
         self._opt = opt
 
@@ -197,6 +199,28 @@ class MRCM:
         self.assemble_interface(stream)
         X = self.solve_interface(refine=refine, stream=stream)
         return self.reconstruct(X, stream=stream) + (X,)
+
+    def autotune(self, kx, ky, kz, q, stream=None):
+        """Time the build for candidate solve_tiles / solve_group values on
+        these inputs (mrcm_autotune) and keep the fastest for the following
+        builds.  Existing handles are released (their geometry includes the
+        tunables).  Returns the chosen values and the build times."""
+        cp = self._cp
+        cp.kx = _dev_ptr(kx, "kx").value
+        cp.ky = _dev_ptr(ky, "ky").value
+        cp.kz = _dev_ptr(kz, "kz").value
+        cp.q = _dev_ptr(q, "q").value
+        self._opt.pcg_x0 = None
+        best = COptions()
+        t_best, t_rule = c_double(0.0), c_double(0.0)
+        code = self.lib.mrcm_autotune(byref(cp), byref(self._part), byref(self._ifs), byref(self._opt),
+                                      _stream_ptr(stream), byref(best), byref(t_best), byref(t_rule))
+        _lib.check(code, "mrcm_autotune")
+        self.close()
+        self._opt.solve_tiles = best.solve_tiles
+        self._opt.solve_group = best.solve_group
+        return {"solve_tiles": best.solve_tiles, "solve_group": best.solve_group,
+                "build_ms": t_best.value, "build_ms_default": t_rule.value}
 
     def capture(self, kx, ky, kz, q, X, p, U, refine=0, stream=None):
         """Record one whole MRCM step (build, assembly, interface solve,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -68,6 +69,8 @@ struct HostGeom {
   std::vector<int> col_sub;  // per right-hand-side column: its subdomain
   std::vector<int> sub_of[3];
   int n_patch = 0;
+  int solve_tiles = 0;   // 16-column tiles per solve work item (0: the largest chunk)
+  int solve_group = 0;   // FP64 pipeline: solve group 0's size (0: occupancy rule, -1: none)
   int bmax = 0, mmax = 0, max_cells = 0;
   long long max_nm = 0;
   int64_t totL = 0, totD = 0, totX = 0, totF = 0, totCells = 0;
@@ -85,6 +88,7 @@ struct ConfigKey {
   int64_t pin = 0;
   double alpha = 0.0;
   int32_t precision = 0;
+  int32_t solve_tiles = 0, solve_group = 0;
   std::vector<int32_t> cuts[3];
   int32_t us[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   std::vector<int32_t> split;
@@ -95,7 +99,8 @@ struct ConfigKey {
         return false;
     for (int f = 0; f < 6; ++f)
       if (wall_type[f] != o.wall_type[f]) return false;
-    return pin == o.pin && alpha == o.alpha && precision == o.precision && split == o.split;
+    return pin == o.pin && alpha == o.alpha && precision == o.precision && split == o.split &&
+           solve_tiles == o.solve_tiles && solve_group == o.solve_group;
   }
 };
 
@@ -113,6 +118,8 @@ bool make_key(const mrcm_problem *pb, const mrcm_partition *part, const mrcm_ifa
   k.pin = pb->pin_cell;
   k.alpha = opt->alpha;
   k.precision = opt->precision;
+  k.solve_tiles = opt->solve_tiles;
+  k.solve_group = opt->solve_group;
   const int nd[3] = {part->ndx, part->ndy, part->ndz};
   const int32_t *cut_in[3] = {part->cut_x, part->cut_y, part->cut_z};
   for (int d = 0; d < 3; ++d) {
@@ -134,7 +141,8 @@ bool same_config(const HostGeom &a, const HostGeom &b) {
     if (a.n[d] != b.n[d] || a.h[d] != b.h[d] || a.cuts[d] != b.cuts[d]) return false;
   for (int f = 0; f < 6; ++f)
     if (a.wall_type[f] != b.wall_type[f]) return false;
-  return a.alpha == b.alpha && a.precision == b.precision && a.pin == b.pin && a.split == b.split;
+  return a.alpha == b.alpha && a.precision == b.precision && a.pin == b.pin && a.split == b.split &&
+         a.solve_tiles == b.solve_tiles && a.solve_group == b.solve_group;
 }
 
 mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
@@ -166,6 +174,11 @@ mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
   G.alpha = opt->alpha;
   if (!(G.alpha > 0.0) || !std::isfinite(G.alpha)) return fail(MRCM_EINVAL, "alpha must be positive");
   G.precision = opt->precision;
+  if (opt->solve_tiles < 0 || opt->solve_tiles > solve_chunk_max() / 16)
+    return fail(MRCM_EINVAL, "solve_tiles must be in [0, " + std::to_string(solve_chunk_max() / 16) + "]");
+  if (opt->solve_group < -1) return fail(MRCM_EINVAL, "solve_group must be -1, 0 or a positive count");
+  G.solve_tiles = opt->solve_tiles;
+  G.solve_group = opt->solve_group;
   if (G.precision != MRCM_FP64 && G.precision != MRCM_FP32_IR && G.precision != MRCM_PCG)
     return fail(MRCM_EINVAL, "precision must be MRCM_FP64, MRCM_FP32_IR or MRCM_PCG");
 
@@ -350,7 +363,7 @@ mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
   {
     const int kXcd = 8;
     std::vector<std::vector<int4>> per(kXcd);
-    const int maxt = solve_chunk_max() / 16;
+    const int maxt = G.solve_tiles > 0 ? G.solve_tiles : solve_chunk_max() / 16;
     for (int idx = 0; idx < n_sub; ++idx) {
       const int l = G.order[idx];
       const SubDesc &S = G.subs[l];
@@ -656,6 +669,8 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
     const int tail_cus = (tail + fpc - 1) / fpc;
     size_t slots = (size_t)std::max(0, ncu - tail_cus) * spc;
     slots = std::min(slots, (size_t)(n_sub_all - tail));
+    if (G.solve_group > 0) slots = std::min((size_t)G.solve_group, (size_t)(n_sub_all - tail));
+    if (G.solve_group < 0) slots = 0;
     slots = (slots / 8) * 8;
     // the factor's whole rounds must cover group 0: true when every work
     // item is one whole subdomain taken in factor order, checked below
@@ -1225,6 +1240,63 @@ mrcm_status mrcm_profile_get(mrcm_profile *out) {
     out->ms[i] = g_prof.ms[i];
     out->count[i] = g_prof.count[i];
   }
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_autotune(const mrcm_problem *pb, const mrcm_partition *part, const mrcm_iface_space *ifs,
+                          const mrcm_options *base, void *stream, mrcm_options *best, double *best_ms,
+                          double *rule_ms) {
+  if (!pb || !part || !ifs || !base || !best) return fail(MRCM_EINVAL, "null argument");
+  // one handle per candidate: an untimed build, then the fastest of three
+  auto time_opts = [&](const mrcm_options &o, double &ms, int *n_first) -> mrcm_status {
+    mrcm_mbfs *h = nullptr;
+    mrcm_status st = mrcm_build_mbfs(pb, part, ifs, &o, stream, &h);
+    if (st != MRCM_OK) return st;
+    if (n_first) *n_first = h->n_first;
+    ms = 1e300;
+    for (int r = 0; r < 3 && st == MRCM_OK; ++r) {
+      const auto t0 = std::chrono::steady_clock::now();
+      st = mrcm_build_mbfs(pb, part, ifs, &o, stream, &h);  // returns after synchronising
+      const auto t1 = std::chrono::steady_clock::now();
+      ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+    }
+    mrcm_mbfs_destroy(h);
+    return st;
+  };
+  mrcm_options cur = *base;
+  double t_rule = 0.0;
+  int nf = 0;
+  mrcm_status st = time_opts(cur, t_rule, &nf);
+  if (st != MRCM_OK) return st;
+  mrcm_options win = cur;
+  double t_best = t_rule;
+  auto consider = [&](int tiles, int group) -> mrcm_status {
+    if (tiles == cur.solve_tiles && group == cur.solve_group) return MRCM_OK;
+    mrcm_options o = cur;
+    o.solve_tiles = tiles;
+    o.solve_group = group;
+    double t = 0.0;
+    mrcm_status e = time_opts(o, t, nullptr);
+    if (e != MRCM_OK) return e;
+    if (t < t_best) {
+      t_best = t;
+      win = o;
+    }
+    return MRCM_OK;
+  };
+  const int tmax = solve_chunk_max() / 16;
+  for (int tiles = 0; tiles <= tmax && st == MRCM_OK; ++tiles) {
+    st = consider(tiles, 0);
+    if (st == MRCM_OK && base->precision == MRCM_FP64) st = consider(tiles, -1);
+  }
+  // the size of the pipeline's first group around the occupancy rule's
+  if (st == MRCM_OK && nf > 0)
+    for (int dg : {-128, -64, 64, 128})
+      if (st == MRCM_OK && nf + dg > 0) st = consider(win.solve_tiles, nf + dg);
+  if (st != MRCM_OK) return st;
+  *best = win;
+  if (best_ms) *best_ms = t_best;
+  if (rule_ms) *rule_ms = t_rule;
   return MRCM_OK;
 }
 
