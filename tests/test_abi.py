@@ -89,8 +89,9 @@ int main(void) {{
   printf("%zu %zu\\n", sizeof(mrcm_partition), offsetof(mrcm_partition, cut_x));
   printf("%zu %zu\\n", sizeof(mrcm_iface_space), offsetof(mrcm_iface_space, split));
   printf("%zu %zu %zu %zu\\n", sizeof(mrcm_options), offsetof(mrcm_options, ir_tol), offsetof(mrcm_options, ir_max_iter), offsetof(mrcm_options, fp64_refine));
-  printf("%zu %zu %zu\\n", sizeof(mrcm_info), offsetof(mrcm_info, ir_residual), offsetof(mrcm_info, device_bytes));
-  printf("%zu %zu\\n", sizeof(mrcm_subdomain_info), offsetof(mrcm_subdomain_info, pin_local));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(mrcm_options, pcg_max_iter), offsetof(mrcm_options, pcg_x0), offsetof(mrcm_options, pcg_x0_scale), offsetof(mrcm_options, solve_tiles), offsetof(mrcm_options, solve_group));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(mrcm_info), offsetof(mrcm_info, ir_residual), offsetof(mrcm_info, device_bytes), offsetof(mrcm_info, pcg_fallback), offsetof(mrcm_info, pcg_iters));
+  printf("%zu %zu %zu\\n", sizeof(mrcm_subdomain_info), offsetof(mrcm_subdomain_info, pin_local), offsetof(mrcm_subdomain_info, solve_group));
   return 0;
 }}
 ''')
@@ -103,7 +104,56 @@ int main(void) {{
         [ctypes.sizeof(CIfaceSpace), CIfaceSpace.split.offset],
         [ctypes.sizeof(COptions), COptions.ir_tol.offset, COptions.ir_max_iter.offset,
          COptions.fp64_refine.offset],
-        [ctypes.sizeof(CInfo), CInfo.ir_residual.offset, CInfo.device_bytes.offset],
-        [ctypes.sizeof(CSubInfo), CSubInfo.pin_local.offset],
+        [COptions.pcg_max_iter.offset, COptions.pcg_x0.offset, COptions.pcg_x0_scale.offset,
+         COptions.solve_tiles.offset, COptions.solve_group.offset],
+        [ctypes.sizeof(CInfo), CInfo.ir_residual.offset, CInfo.device_bytes.offset, CInfo.pcg_fallback.offset,
+         CInfo.pcg_iters.offset],
+        [ctypes.sizeof(CSubInfo), CSubInfo.pin_local.offset, CSubInfo.solve_group.offset],
     ]
     assert got == want
+
+
+def test_host_validation_of_the_forms_and_tunables():
+    """Option, size and network-argument errors are caught on the host."""
+    from paper_2103_08513_amd import _lib
+    from paper_2103_08513_amd._lib import CIfaceSpace, COptions, CPartition, CProblem
+    lib = _lib.load()
+    pb = CProblem()
+    pb.nx, pb.ny, pb.nz = 2, 40, 30   # one 2400-cell block, bandwidth 60
+    pb.hx = pb.hy = pb.hz = 1.0
+    pb.kx = pb.ky = pb.kz = pb.q = 8  # never dereferenced
+    pb.pin_cell = 0
+    part = CPartition()
+    part.ndx = part.ndy = part.ndz = 1
+    ifs = CIfaceSpace()
+    opt = COptions()
+    opt.alpha = 1.0
+    out = ctypes.c_void_p()
+
+    def build():
+        return lib.mrcm_build_mbfs(ctypes.byref(pb), ctypes.byref(part), ctypes.byref(ifs),
+                                   ctypes.byref(opt), None, ctypes.byref(out))
+
+    opt.solve_tiles = 4
+    assert build() == -1 and b"solve_tiles" in lib.mrcm_last_error()
+    opt.solve_tiles = 0
+    opt.solve_group = -2
+    assert build() == -1 and b"solve_group" in lib.mrcm_last_error()
+    opt.solve_group = 0
+    opt.precision = 3
+    assert build() == -1 and b"precision" in lib.mrcm_last_error()
+    opt.precision = 2             # conjugate gradients: at most 2048 cells per block
+    assert build() == -7 and b"conjugate-gradient" in lib.mrcm_last_error()
+    # network kernels: channel limit and sizes
+    nul = ctypes.c_void_p(8)
+    assert lib.mrcm_conv3d_max_channels() == 16
+    assert lib.mrcm_conv3d_forward(nul, nul, None, nul, None, 1, 17, 1, 2, 2, 2, 1, 0, None) == -1
+    assert lib.mrcm_conv3d_forward(nul, nul, None, nul, None, 1, 2, 1, 0, 2, 2, 1, 0, None) == -1
+    assert lib.mrcm_conv3d_forward(nul, nul, None, nul, None, 1, 2, 1, 2, 2, 2, 0, 0, None) == -1
+    assert lib.mrcm_adam_step(nul, nul, nul, nul, 4, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    # graph capture and autotuning need handles and arguments
+    g = ctypes.c_void_p()
+    assert lib.mrcm_graph_capture(None, None, None, None, None, None, 0, None, None, None, None,
+                                  ctypes.byref(g)) == -1
+    assert lib.mrcm_graph_launch(None, None) == -1
+    assert lib.mrcm_autotune(None, None, None, None, None, None, None, None) == -1
