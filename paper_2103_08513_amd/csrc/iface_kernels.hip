@@ -399,17 +399,33 @@ __global__ __launch_bounds__(kStepThreads) void k_ldl_step(double *__restrict__ 
     else
       update_cols(std::integral_constant<int, 1>{});
   }
-  // the diagonal tile of each row block stores L21 = W D^{-1} and U12 = W^T
+  // the diagonal tile of each row block stores U12 = W^T above the diagonal.
+  // L21 = W D^{-1} is not stored here: the other tiles of this launch still
+  // read A21 from those entries, and a workgroup that starts after this one
+  // has finished would read L21 instead.  k_ldl_lower writes it once the
+  // whole factorisation is done.
   if (ti == tj && rows) {
     for (int e = tid; e < 64 * kLB; e += 256) {
       const int rr = e / kLB, cc = e % kLB;
       const int i = i0 + rr, j = k0 + cc;
-      if (i < r0 + nr && i - j <= w) {
-        const double wv = Wi[rr * (kLB + 1) + cc];
-        AB[(size_t)j * ld + (w + i - j)] = wv * Dq[cc];
-        AB[(size_t)i * ld + (w + j - i)] = wv;
-      }
+      if (i < r0 + nr && i - j <= w) AB[(size_t)i * ld + (w + j - i)] = Wi[rr * (kLB + 1) + cc];
     }
+  }
+}
+
+// L below the diagonal blocks from the stored U = D L^T: L(i, j) = U(j, i) / D_j
+// for j < i <= j + w outside j's own 16-block (whose L the block
+// factorisation wrote).  One thread per band entry below the diagonal.
+__global__ void k_ldl_lower(double *__restrict__ AB, const double *__restrict__ inv, int n, int w) {
+  const int ld = 2 * w + 1;
+  const long long total = (long long)n * w;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int j = (int)(e / w), t = 1 + (int)(e % w);
+    const int i = j + t;
+    if (i >= n || i / kLB == j / kLB) continue;
+    const double dinv = inv[(size_t)(j / kLB) * kInvStride + kLB * kLB + (j % kLB)];
+    AB[(size_t)j * ld + (w + t)] = AB[(size_t)i * ld + (w - t)] * dinv;
   }
 }
 
@@ -1015,6 +1031,7 @@ hipError_t launch_band_ldl(const double *AB0, double *AB, const double *b0, doub
                        inv + (size_t)(k0 / kLB) * kInvStride, inv + (size_t)(k0 / kLB + 1) * kInvStride, b, y, st);
   }
   hipLaunchKernelGGL(k_ldl_tail_y, dim3(1), dim3(64), 0, s, inv + (size_t)(k0 / kLB) * kInvStride, b, y, n, k0);
+  if (w > 0) hipLaunchKernelGGL(k_ldl_lower, dim3(grid_for((long long)n * w)), dim3(256), 0, s, AB, inv, n, w);
   return hipGetLastError();
 }
 
