@@ -332,7 +332,9 @@ mrcm_status mrcm_profile_get(mrcm_profile *out /* [host] */);
  * Autotuner: times mrcm_build_mbfs on the given problem for candidate values
  * of solve_tiles and solve_group (each candidate on a handle of its own:
  * one untimed and three timed builds, synchronised, the fastest counted) and
- * writes into *best a copy of *base with the fastest pair.  *best_ms and
+ * writes into *best a copy of *base with the fastest pair; a candidate
+ * replaces the current choice only when it is at least 2% faster, so that
+ * near-ties keep base's pair.  *best_ms and
  * *rule_ms (either may be NULL): the fastest build and that of base's own
  * pair.  Allocates and frees one handle per candidate.
  */

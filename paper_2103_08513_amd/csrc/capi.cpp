@@ -1278,7 +1278,9 @@ mrcm_status mrcm_autotune(const mrcm_problem *pb, const mrcm_partition *part, co
     double t = 0.0;
     mrcm_status e = time_opts(o, t, nullptr);
     if (e != MRCM_OK) return e;
-    if (t < t_best) {
+    // a candidate must beat the current choice by 2%, more than the
+    // run-to-run spread of the timings, so that near-ties keep the default
+    if (t < 0.98 * t_best) {
       t_best = t;
       win = o;
     }
