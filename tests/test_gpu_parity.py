@@ -6,7 +6,7 @@ seeded inputs and compares with the oracle on the same inputs.  Tolerances:
     to the largest entry of the compared block (rounding-order differences
     only, amplified by the local condition number);
   * end-to-end pressure and velocity: 1e-8 relative L2 (FP64 and FP32 with
-    FP64 refinement), the accuracy the method's FP64 solution is judged at.
+    FP64 refinement), the accuracy asked of the method's FP64 solution.
 """
 import numpy as np
 import pytest
