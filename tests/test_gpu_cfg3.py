@@ -3,7 +3,8 @@ shapes from 15x15x3 to 20x20x5, 2-8 patches per interface, 120,176 patches) on
 one GPU, end to end in FP64.  The oracle cannot solve it whole, so:
   * the MBFs and flux blocks of one subdomain of every shape (and a few more)
     are compared with the oracle's, column by column (1e-9 relative);
-  * the interface solve's relative residual on the assembled system is small;
+  * the interface solve's relative residual on the assembled system is small,
+    and one FP64 refinement step keeps it small;
   * the reconstructed velocity conserves mass in every cell: the net outflow
     equals the source to 1e-8 of the largest face flux in the domain (a
     property that holds at any size).  The balance is the local solves'
@@ -62,6 +63,16 @@ def test_cfg3_ragged_workload_end_to_end():
           f"assembly + solve + reconstruction {1e3 * t_rest:.0f} ms, interface residual "
           f"{m.interface_residual:.2e}", flush=True)
     assert m.interface_residual < 1e-9
+    # one FP64 refinement step of the interface solve: residual of the
+    # unfactored system, lower and upper sweeps with the stored factors (the
+    # ring-buffer lower sweep of systems beyond the LDS-resident size)
+    res0 = m.interface_residual
+    X1 = m.solve_interface(refine=1, residual=True)
+    torch.cuda.synchronize()
+    print(f"cfg3: interface residual after one refinement step {m.interface_residual:.2e} "
+          f"(before {res0:.2e})", flush=True)
+    assert m.interface_residual < max(1e-12, 2.0 * res0)
+    assert float(torch.linalg.norm(X1 - X) / torch.linalg.norm(X)) < 1e-6
     # sampled MBFs against the oracle: one subdomain of every shape, and more
     geo = Geometry(pb.dims, case.partition, case.iface)
     first = {}
