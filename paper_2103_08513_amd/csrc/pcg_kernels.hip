@@ -35,7 +35,7 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// FP32 sum over a wave by DPP moves (no LDS traffic): prefix sums within
+// FP32 sums over a wave by DPP moves (no LDS traffic): prefix sums within
 // rows of 16 lanes (row_shr 1, 2, 4, 8), then the row totals carried into
 // rows 1 and 3 (row_bcast 15) and 2 and 3 (row_bcast 31); lane 63 ends with
 // the total, which every lane reads.
@@ -44,14 +44,24 @@ __device__ __forceinline__ float dpp_add(float v) {
   const int x = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, row_mask, 0xf, false);
   return v + __builtin_bit_cast(float, x);
 }
-__device__ __forceinline__ float wave_sum_dpp(float v) {
-  v = dpp_add<0x111, 0xf>(v);
-  v = dpp_add<0x112, 0xf>(v);
-  v = dpp_add<0x114, 0xf>(v);
-  v = dpp_add<0x118, 0xf>(v);
-  v = dpp_add<0x142, 0xa>(v);
-  v = dpp_add<0x143, 0xc>(v);
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+
+// Two such sums at once: the steps of the two chains alternate, so that each
+// DPP move's wait states are filled by the other chain.
+__device__ __forceinline__ void wave_sum2_dpp(float &a, float &b) {
+  a = dpp_add<0x111, 0xf>(a);
+  b = dpp_add<0x111, 0xf>(b);
+  a = dpp_add<0x112, 0xf>(a);
+  b = dpp_add<0x112, 0xf>(b);
+  a = dpp_add<0x114, 0xf>(a);
+  b = dpp_add<0x114, 0xf>(b);
+  a = dpp_add<0x118, 0xf>(a);
+  b = dpp_add<0x118, 0xf>(b);
+  a = dpp_add<0x142, 0xa>(a);
+  b = dpp_add<0x142, 0xa>(b);
+  a = dpp_add<0x143, 0xc>(a);
+  b = dpp_add<0x143, 0xc>(b);
+  a = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, a), 63));
+  b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, b), 63));
 }
 
 // Sum over the workgroup's NW waves; every lane returns the same bits.  A
@@ -233,8 +243,7 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
         gp = fmaf(rv[i], rv[i], gp);
         dp = fmaf(a, rv[i], dp);
       }
-      gp = wave_sum_dpp(gp);
-      dp = wave_sum_dpp(dp);
+      wave_sum2_dpp(gp, dp);
       if (lane == 0) {
         redf[0][wave] = gp;
         redf[1][wave] = dp;
@@ -249,9 +258,11 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
       // the product above is counted once the step is taken
       if (gam <= eta2 || it >= max_iter) break;
       ++it;
-      const float beta = k == 0 ? 0.0f : gam / gam_prev;
-      const float den = k == 0 ? del : del - beta * gam / alpha_prev;
-      const float alpha = gam / den;
+      // the step lengths by hardware reciprocals: their relative error
+      // (about 1e-7) is that of the FP32 iteration itself
+      const float beta = k == 0 ? 0.0f : gam * __builtin_amdgcn_rcpf(gam_prev);
+      const float den = k == 0 ? del : del - beta * gam * __builtin_amdgcn_rcpf(alpha_prev);
+      const float alpha = gam * __builtin_amdgcn_rcpf(den);
       // a non-positive or non-finite step (rounding): keep y and restart
       // from the true residual
       if (!(alpha > 0.0f) || !isfinite(alpha)) break;
