@@ -86,6 +86,7 @@ class MRCM:
         self.nv = None
         self._mbfs = c_void_p()
         self._iface = c_void_p()
+        self._graphs = []
         self._keep = []
         nx, ny, nz = problem.nx, problem.ny, problem.nz
         cp = CProblem()
@@ -241,7 +242,9 @@ class MRCM:
                                            _dev_ptr(X, "X") if nv > 0 else None, _dev_ptr(p, "p"),
                                            _dev_ptr(U, "U"), _stream_ptr(stream), byref(g))
         _lib.check(code, "mrcm_graph_capture")
-        return Graph(self, g, (kx, ky, kz, q, X, p, U))
+        graph = Graph(self, g, (kx, ky, kz, q, X, p, U))
+        self._graphs.append(graph)
+        return graph
 
     # -- introspection ------------------------------------------------------
     def info(self):
@@ -314,6 +317,10 @@ class MRCM:
         return A, b
 
     def close(self):
+        # graphs hold the handles' device addresses: release them first
+        for graph in getattr(self, "_graphs", []):
+            graph.close()
+        self._graphs = []
         if self._iface:
             self.lib.mrcm_interface_destroy(self._iface)
             self._iface = c_void_p()
