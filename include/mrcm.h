@@ -115,7 +115,12 @@ typedef struct {
  * precision    MRCM_FP64 or MRCM_FP32_IR.
  * ir_tol       FP32_IR: stop when every column's relative FP64 residual
  *              ||R - M X|| / ||R|| is at most ir_tol (<= 0 selects 1e-13).
- * ir_max_iter  FP32_IR: refinement sweeps before MRCM_ENOCONV (<= 0: 30).
+ * ir_max_iter  FP32_IR: refinement sweeps (<= 0: 30).  If they stop short of
+ *              ir_tol, every column is polished once by the conjugate-gradient
+ *              kernel of MRCM_PCG (FP64 residual, FP32 inner iterations, up to
+ *              1000 of them, from the current X) when the blocks fit it
+ *              (bandwidth <= 112, at most 2048 cells); MRCM_ENOCONV if the
+ *              residual is still above ir_tol.
  * fp64_refine  FP64: fixed number of FP64 refinement sweeps (residual
  *              R - A X from the coefficients, correction with the same factor)
  *              after the direct solves; 0 for none.

@@ -962,6 +962,11 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     h->ir_iters = h->refine64;
   }
   if (fp32) {
+    // CG-IR fallback: when the sweeps stop short of the tolerance, the
+    // conjugate-gradient kernel (FP64 residual, FP32 inner iterations) polishes
+    // every column from the current X, once
+    const bool cg_ok = H.bmax <= kMaxBand64 && H.max_cells <= pcg_max_cells();
+    bool polished = false;
     for (int it = 0;; ++it) {
       {
         Stage t(MRCM_STAGE_RESIDUAL, s);
@@ -975,6 +980,26 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       h->ir_res = res;
       h->ir_iters = it;
       if (res <= h->ir_tol) break;
+      if ((it >= h->ir_max || !std::isfinite(res)) && !polished && cg_ok && std::isfinite(res)) {
+        polished = true;
+        if (!h->d_colsub) {
+          if (upload(&h->d_colsub, H.col_sub) != hipSuccess || dev_alloc(&h->d_iters, (size_t)H.totCols) != hipSuccess ||
+              dev_alloc(&h->d_conv, (size_t)H.totCols) != hipSuccess)
+            return bail(fail(MRCM_ENOMEM, "device allocation of the CG buffers failed"));
+        }
+        std::vector<int> its(H.totCols);
+        {
+          Stage t(MRCM_STAGE_PCG, s);
+          ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, h->R, s));
+          ENQ(launch_pcg(g, h->d_colsub, H.totCols, H.max_cells, h->coef, h->scal, h->R, h->X, h->X, 1000,
+                         h->ir_tol, 0, h->d_iters, h->d_conv, s));
+          ENQ(hipMemcpyAsync(its.data(), h->d_iters, its.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+          ENQ(hipStreamSynchronize(s));
+        }
+        h->pcg_iters = 0;
+        for (int v : its) h->pcg_iters += v;
+        continue;  // the residual check above decides
+      }
       if (it >= h->ir_max || !std::isfinite(res)) {
         st = read_status(h->st, s, "mrcm_build_mbfs");
         if (st != MRCM_OK) return bail(st);

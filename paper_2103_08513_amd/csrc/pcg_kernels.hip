@@ -12,7 +12,8 @@
 //    preconditioning), for the normalised scaled residual, until its own
 //    residual has dropped by kInnerTol; x += D^-1/2 y in FP64.
 // The budget max_iter counts inner iterations (matrix-vector products) over
-// all outer steps.  Thread t owns local rows t + 256 i, i < CPT; the search
+// all outer steps.  The starting guess X0 may be X itself: a workgroup reads
+// its column of X0 before it writes that column of X.  Thread t owns local rows t + 256 i, i < CPT; the search
 // direction is exchanged through LDS for the 7-point product, and every
 // branch depends only on workgroup sums that all lanes read alike.
 #include <hip/hip_runtime.h>
@@ -87,8 +88,8 @@ __device__ __forceinline__ int opaque(int v) {
 template <int NT, int CPT>
 __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_sub, int ncols,
                                             const double *__restrict__ coef, const double *__restrict__ scal,
-                                            const double *__restrict__ Bg, const double *__restrict__ X0g,
-                                            double *__restrict__ Xg, int max_iter, double tol,
+                                            const double *__restrict__ Bg, const double *X0g, double *Xg,
+                                            int max_iter, double tol,
                                             int *__restrict__ iters, int *__restrict__ conv) {
   constexpr int NW = NT / 64;
   constexpr int LEN = NT * CPT + 2 * kPad;

@@ -152,6 +152,26 @@ def test_config1_fp32_refined_end_to_end():
     m.close()
 
 
+def test_config1_fp32_refinement_short_of_tolerance_falls_back_to_cg():
+    """With a single refinement sweep the FP32 form stops short of its 1e-13
+    tolerance; the conjugate-gradient polish (CG-IR) finishes every column."""
+    import paper_2103_08513_amd as lib
+    case = config1()
+    ref = mrcm_solve(case)
+    pb = case.problem
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=lib.FP32_IR, ir_max_iter=1)
+    p, U, X = m.solve(_dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q))
+    torch.cuda.synchronize()
+    info = m.info()
+    print(f"FP32 with one sweep: CG polish {info.pcg_iters} inner iterations, residual {info.ir_residual:.2e}",
+          flush=True)
+    assert info.pcg_iters > 0
+    assert info.ir_residual <= 1e-13
+    assert rel_l2(p.cpu().numpy(), ref.p) < 1e-8
+    assert rel_l2(U.cpu().numpy(), ref.U) < 1e-8
+    m.close()
+
+
 def test_mass_conservation_on_gpu_output():
     case = small_case((10, 8, 6), (2, 2, 3), split=((2, 1), (1, 2), (2, 2)), seed=5, std=2.0)
     m, p, U, X = _run(case)
