@@ -198,8 +198,9 @@ typedef struct {
   int32_t ax[3];
   int32_t n_cells, band, n_rhs, n_patch;
   int32_t pin_local;      /* local row of the pinned cell, or -1 */
-  int32_t solve_group;    /* FP64 path: 0 if the subdomain's first solve is in the 'solve'
-                             stage's launch, 1 if it runs in the 'refine' stage (see below) */
+  int32_t solve_group;    /* FP64 (with refinement) and FP32 forms: 0 if the subdomain's first
+                             solve is in the 'solve' stage's launch, 1 if it runs in the
+                             'refine' stage (see below) */
 } mrcm_subdomain_info;
 
 /*
@@ -295,11 +296,13 @@ mrcm_status mrcm_copy_interface(const mrcm_interface *iface, double *A, double *
  * LDL^T factorisation with the forward substitution (one step kernel per
  * 16-column block), interface backward sweeps (two kernels per 128 unknowns)
  * and refinement, reconstruction (two kernels).
- * FP64 path with refinement, when the solve work exceeds one round of
- * resident workgroups: 'solve' is the first solve of group 0 (the first
- * round's subdomains); 'refine' covers the rest -- group 1's first solve and
- * both groups' residuals and corrections, group 0's on a second stream that
- * joins the caller's stream at the end -- and 'residual' stays empty.
+ * FP64 form with refinement and FP32 form, when the solve work exceeds one
+ * round of resident workgroups: 'solve' is the first solve of group 0 (the
+ * first round's subdomains); 'refine' covers the rest -- group 1's first
+ * solve and both groups' residuals and corrections (FP32: the first
+ * min(3, ir_max_iter) sweeps), group 0's on a second stream that joins the
+ * caller's stream at the end.  'residual' stays empty in the FP64 form; in
+ * the FP32 form it holds the convergence checks and any further sweeps.
  * PCG: 'pcg' is the conjugate-gradient kernel and the read-back of its
  * convergence flags; 'fallback' the band Cholesky and direct solves of the
  * subdomains it left (factor and solve stages stay empty).

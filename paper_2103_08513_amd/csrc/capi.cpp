@@ -653,7 +653,8 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
 #undef ALLOC
   // the split of the solve work into resident rounds (FP64 path)
   h->solve_group.assign(G.subs.size(), 0);
-  if (G.precision == MRCM_FP64) {
+  if (G.precision == MRCM_FP64 || G.precision == MRCM_FP32_IR) {
+    const int f32 = G.precision == MRCM_FP32_IR;
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -662,8 +663,8 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
     // the tail: its first solve starts when the whole rounds are factored,
     // on the CUs the tail leaves free.  A multiple of 8 keeps every item on
     // its XCD (workgroup i runs on XCD i mod 8).
-    const int fpc = std::max(1, factor64_blocks_per_cu(G.bmax));
-    const int spc = solve_blocks_per_cu(0, G.bmax);
+    const int fpc = std::max(1, f32 ? factor32_blocks_per_cu(G.bmax) : factor64_blocks_per_cu(G.bmax));
+    const int spc = solve_blocks_per_cu(f32, G.bmax);
     const int n_sub_all = (int)G.subs.size();
     const int tail = n_sub_all % (ncu * fpc);
     const int tail_cus = (tail + fpc - 1) / fpc;
@@ -832,7 +833,11 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     ENQ(launch_coef(g, h->n_sub, H.max_cells, h->coef, h->r0, h->scal, s));
   }
   const bool pcg = H.precision == MRCM_PCG;
-  const bool split = !fp32 && !pcg && h->refine64 > 0 && h->n_first > 0;
+  // the two-stream pipeline: the FP64 form with refinement, and the FP32
+  // form, whose first min(3, ir_max) sweeps run in it before the first
+  // convergence check (three reach 1e-13 on the channelised workloads)
+  const bool split = !pcg && h->n_first > 0 && (fp32 || h->refine64 > 0);
+  const int nsweep = fp32 ? std::min(3, h->ir_max) : h->refine64;
   const int n_work = (int)H.work.size();
   h->ir_iters = 0;
   h->ir_res = 0.0;
@@ -845,7 +850,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   }
   // one pipelined FP64 sweep: R takes a copy of the right-hand sides and each
   // correction workgroup forms its own residual from it
-  const bool own_res = split && h->refine64 == 1;
+  const bool own_res = split && !fp32 && h->refine64 == 1;
   {
     Stage t(MRCM_STAGE_RHS, s);
     ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, pcg ? h->R : h->X, s, own_res ? h->R : nullptr));
@@ -917,7 +922,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       Stage t(MRCM_STAGE_SOLVE, h->s2);
       ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->X, h->X, 0, H.bmax, h->s2));
     }
-    for (int it = 0; it < h->refine64; ++it) {
+    for (int it = 0; it < nsweep; ++it) {
       if (!own_res)
         ENQ(launch_residual(g, n0, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, h->s2, h->d_grp_subs[0]));
       ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->R, h->X, 1, H.bmax, h->s2,
@@ -928,14 +933,14 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     const int4 *w1 = h->d_work + h->n_first;
     const int n1 = n_work - h->n_first;
     ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->X, h->X, 2, H.bmax, s));
-    for (int it = 0; it < h->refine64; ++it) {
+    for (int it = 0; it < nsweep; ++it) {
       if (!own_res)
         ENQ(launch_residual(g, n1s, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s, h->d_grp_subs[1]));
       ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->R, h->X, 3, H.bmax, s,
                        own_res ? h->coef : nullptr));
     }
     ENQ(hipStreamWaitEvent(s, h->ev_join, 0));
-    h->ir_iters = h->refine64;
+    h->ir_iters = nsweep;
   } else {
     {
       Stage t(MRCM_STAGE_FACTOR, s);
@@ -967,7 +972,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     // every column from the current X, once
     const bool cg_ok = H.bmax <= kMaxBand64 && H.max_cells <= pcg_max_cells();
     bool polished = false;
-    for (int it = 0;; ++it) {
+    for (int it = split ? nsweep : 0;; ++it) {
       {
         Stage t(MRCM_STAGE_RESIDUAL, s);
         ENQ(launch_fill(h->norms, 2LL * H.totCols, 0.0, s));

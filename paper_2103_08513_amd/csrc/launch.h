@@ -32,6 +32,7 @@ hipError_t launch_residual(const Geom &g, int n_sub, int max_cells, const double
                            hipStream_t s, const int *subs = nullptr);
 int solve_blocks_per_cu(int fp32, int bmax);
 int factor64_blocks_per_cu(int bmax);
+int factor32_blocks_per_cu(int bmax);
 hipError_t launch_ir_check(const double *norms, int ncols, double *out, hipStream_t s);
 hipError_t launch_flux(const Geom &g, int n_sub, const double *X, double *F, double *Fb,
                        double *SAb, hipStream_t s);

@@ -1390,11 +1390,15 @@ hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, c
                         hipStream_t s, const double *coef) {
   // Separate instantiations per mode, so that profiles tell them apart: bit 0
   // set for a correction (X += ...), bit 1 set for the second group of work
-  // items when the first solve is split (FP64 path only).
+  // items when the first solve is split.
   if (fp32) {
-    if (mode == 0)
-      return launch_solve_m<float, 0>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax, s, coef);
-    return launch_solve_m<float, 1>(g, work, n_work, scal, (const float *)L, (const float *)Dg, B, X, bmax, s, coef);
+    const float *Lf = (const float *)L, *Df = (const float *)Dg;
+    switch (mode) {
+      case 0: return launch_solve_m<float, 0>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef);
+      case 1: return launch_solve_m<float, 1>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef);
+      case 2: return launch_solve_m<float, 2>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef);
+      default: return launch_solve_m<float, 3>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef);
+    }
   }
   const double *Ld = (const double *)L, *Dd = (const double *)Dg;
   switch (mode) {
@@ -1412,6 +1416,17 @@ int factor64_blocks_per_cu(int bmax) {
   if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 512, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+// Workgroups of the FP32 factorisation that one CU holds at once.
+int factor32_blocks_per_cu(int bmax) {
+  const size_t lds = factor_lds_bytes(1, bmax);
+  const void *k = ((bmax + 15) / 16 <= 7) ? (const void *)k_factor32<6>
+                                           : (const void *)k_factor32<(kMaxBand32 + 15) / 16 - 1>;
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, lds) != hipSuccess) return 0;
   return nb;
 }
 

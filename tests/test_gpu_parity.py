@@ -215,13 +215,16 @@ def test_invalid_permeability_is_rejected():
     assert ei.value.code == -1
 
 
-def test_config2_sampled_subdomains():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config2_sampled_subdomains(precision):
     """The 60x220x85 workload (561 subdomains of 20x20x5, b = 100, m up to 33):
-    MBFs of sampled interior, face, edge and corner subdomains vs the oracle."""
+    MBFs of sampled interior, face, edge and corner subdomains vs the oracle,
+    for the FP64 form and the FP32 form with refinement (both built through
+    the two-stream pipeline at this size)."""
     case = config2()
     pb = case.problem
     import paper_2103_08513_amd as lib
-    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha)
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision)
     m.build_mbfs(_dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q))
     torch.cuda.synchronize()
     geo = Geometry(pb.dims, case.partition, case.iface)
@@ -231,7 +234,12 @@ def test_config2_sampled_subdomains():
     groups = [m.subdomain(l).solve_group for l in range(geo.n_sub)]
     late = [l for l in range(geo.n_sub) if groups[l] == 1]
     sample = sorted(set([0, 1, 4, 37, 280, 300, 560, geo.n_sub // 2] + late[:2] + late[-1:]))
-    print(f"cfg2: {len(late)} subdomains in the second solve group; sample {sample}", flush=True)
+    info = m.info()
+    print(f"cfg2 precision {precision}: {len(late)} subdomains in the second solve group; sample {sample}; "
+          f"{info.ir_iters} refinement sweeps, residual {info.ir_residual:.2e}", flush=True)
+    assert len(late) > 0
+    if precision == 1:
+        assert info.ir_residual <= 1e-13
     systems, Xs, Fs, Fbs, SAbs = oracle_build(pb, geo, case.alpha, subdomains=sample)
     for l, X, F in zip(sample, Xs, Fs):
         Xg = m.copy_mbfs(l)[np.argsort(m.local_order(l))]
