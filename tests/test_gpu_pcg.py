@@ -152,3 +152,32 @@ def test_pcg_config2_sampled_subdomains():
         r = _column_residuals(m, ls, l)
         assert r.max() <= TOL * 1.01, (l, float(r.max()))
     m.close()
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_walls_without_pin_in_the_fp32_and_cg_forms(precision):
+    """Dirichlet and Neumann walls with wall data and no pinned cell: the FP32
+    form with refinement and the CG form against the oracle."""
+    import paper_2103_08513_amd as lib
+    case = small_case((8, 6, 4), (2, 2, 2), split=((1, 2), (2, 1), (2, 2)), seed=4, pin=-1)
+    pb = case.problem
+    rng = np.random.default_rng(9)
+    pb.wall_type = [1, 2, 0, 2, 1, 0]
+    pb.wall_value = [rng.standard_normal(6 * 4), 0.1 * rng.standard_normal(6 * 4), None,
+                     0.1 * rng.standard_normal(8 * 4), rng.standard_normal(8 * 6), None]
+    ref = mrcm_solve(case)
+    m = _model(case, precision=precision, pcg_max_iter=2000)
+    p, U, X = m.solve(*_inputs(case))
+    torch.cuda.synchronize()
+    info = m.info()
+    ep, eu = rel_l2(p.cpu().numpy(), ref.p), rel_l2(U.cpu().numpy(), ref.U)
+    print(f"walls, precision {precision}: p {ep:.2e}, U {eu:.2e}", flush=True)
+    tol = 1e-8 if precision == 1 else 1e-6
+    assert ep < tol and eu < tol
+    if precision == 2:
+        assert info.pcg_fallback == 0
+        geo = Geometry(pb.dims, case.partition, case.iface)
+        for l in range(geo.n_sub):
+            r = _column_residuals(m, local_system(pb, geo, l, case.alpha), l)
+            assert r.max() <= TOL * 1.01, (l, float(r.max()))
+    m.close()
