@@ -144,6 +144,15 @@ def test_host_validation_of_the_forms_and_tunables():
     assert build() == -1 and b"precision" in lib.mrcm_last_error()
     opt.precision = 2             # conjugate gradients: at most 2048 cells per block
     assert build() == -7 and b"conjugate-gradient" in lib.mrcm_last_error()
+    # the local bandwidth (product of the two shortest extents) above each
+    # form's largest: 112 in FP64, 176 in FP32
+    opt.precision = 0
+    pb.ny, pb.nz = 57, 60         # bandwidth 114
+    assert build() == -7 and b"local bandwidth 114 exceeds 112" in lib.mrcm_last_error()
+    opt.precision = 1
+    pb.ny, pb.nz = 89, 100        # bandwidth 178
+    assert build() == -7 and b"local bandwidth 178 exceeds 176" in lib.mrcm_last_error()
+    pb.ny, pb.nz = 40, 30
     # network kernels: channel limit and sizes
     nul = ctypes.c_void_p(8)
     assert lib.mrcm_conv3d_max_channels() == 16

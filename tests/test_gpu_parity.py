@@ -248,3 +248,42 @@ def test_config2_sampled_subdomains(precision):
         Fg, _, _ = m.copy_flux(l)
         assert _maxrel(Fg, F) < 1e-9
     m.close()
+
+
+@pytest.mark.parametrize("precision,dims", [(0, (14, 32, 20)), (1, (22, 32, 20)), (2, (14, 32, 18))],
+                         ids=["fp64-b112", "fp32-b176", "cg-b112"])
+def test_largest_local_bandwidth(precision, dims):
+    """Subdomains at the largest local bandwidth each form accepts: 7x16 cells
+    across the two shortest axes (b = 112) in FP64 and in the CG form (2,016
+    cells, inside its 2,048-cell limit), 11x16 (b = 176, the FP32 kernels'
+    wider instantiations) in FP32.  MBFs and flux blocks against the oracle,
+    then the solution."""
+    import paper_2103_08513_amd as lib
+    case = small_case(dims, (2, 2, 1), split=((2, 1), (1, 2), (1, 1)), seed=17)
+    pb = case.problem
+    kw = dict(pcg_max_iter=4000) if precision == 2 else {}
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision, **kw)
+    p, U, X = m.solve(_dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q))
+    torch.cuda.synchronize()
+    info = m.info()
+    assert info.max_band == (176 if precision == 1 else 112)
+    if precision == 1:
+        assert info.ir_residual <= 1e-13
+    if precision == 2:
+        assert info.pcg_fallback == 0
+    ref = mrcm_solve(case)
+    tol = 1e-10 if precision == 0 else 1e-8
+    worst = 0.0
+    for l, ls in enumerate(ref.systems):
+        Xg = m.copy_mbfs(l)
+        Xo = ref.X[l][m.local_order(l)]
+        for c in range(Xo.shape[1]):
+            worst = max(worst, _maxrel(Xg[:, c], Xo[:, c]))
+        F, _, _ = m.copy_flux(l)
+        assert _maxrel(F, ref.F[l]) < tol, l
+    ep, eu = rel_l2(p.cpu().numpy(), ref.p), rel_l2(U.cpu().numpy(), ref.U)
+    print(f"precision {precision}, b = {info.max_band}: worst MBF column {worst:.2e}, p {ep:.2e}, U {eu:.2e}",
+          flush=True)
+    assert worst < tol
+    assert ep < 1e-8 and eu < 1e-8
+    m.close()
