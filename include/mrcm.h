@@ -114,13 +114,18 @@ typedef struct {
  *              length) and K_d(c) the own cell's permeability; alpha > 0.
  * precision    MRCM_FP64 or MRCM_FP32_IR.
  * ir_tol       FP32_IR: stop when every column's relative FP64 residual
- *              ||R - M X|| / ||R|| is at most ir_tol (<= 0 selects 1e-13).
+ *              ||R - M X|| / ||R|| is at most ir_tol (<= 0 selects 1e-13), or
+ *              is within the rounding bound of its own evaluation,
+ *              ||R - M X|| <= 8u ||s|| with s_r = |R_r| + sum_j |M_rj X_j| and
+ *              u = 2^-53 (no sweep can improve such a column further; on
+ *              strongly heterogeneous or nearly Neumann local problems that
+ *              floor can lie above 1e-13).
  * ir_max_iter  FP32_IR: refinement sweeps (<= 0: 30).  If they stop short of
  *              ir_tol, every column is polished once by the conjugate-gradient
  *              kernel of MRCM_PCG (FP64 residual, FP32 inner iterations, up to
  *              1000 of them, from the current X) when the blocks fit it
- *              (bandwidth <= 112, at most 2048 cells); MRCM_ENOCONV if the
- *              residual is still above ir_tol.
+ *              (bandwidth <= 112, at most 2048 cells); MRCM_ENOCONV if a
+ *              column is still above both ir_tol and its rounding floor.
  * fp64_refine  FP64: fixed number of FP64 refinement sweeps (residual
  *              R - A X from the coefficients, correction with the same factor)
  *              after the direct solves; 0 for none.
@@ -181,7 +186,8 @@ typedef struct {
   int32_t max_rhs;        /* largest m_l */
   int32_t precision;
   int32_t ir_iters;       /* refinement sweeps of the last build (FP32_IR) */
-  double ir_residual;     /* largest relative column residual after the last build */
+  double ir_residual;     /* largest relative column residual after the last build
+                             (above ir_tol only for columns at their rounding floor) */
   double factor_flops;    /* sum_l sum_k (b_k^2 + 2 b_k + 1), the band Cholesky count */
   double solve_flops;     /* sum_l 4 N_l b_l m_l (forward + backward band solves) */
   int64_t device_bytes;   /* device memory held by the handle */

@@ -643,7 +643,7 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
   ALLOC(h->F, std::max<int64_t>(1, G.totF), double);
   ALLOC(h->Fb, std::max<int64_t>(1, G.totF), double);
   ALLOC(h->SAb, std::max<int64_t>(1, (int64_t)G.patches.size()), double);
-  ALLOC(h->norms, 2 * (int64_t)G.totCols, double);
+  ALLOC(h->norms, 3 * (int64_t)G.totCols, double);
   ALLOC(h->scalar, 4, double);
   {
     DevStatus *p = nullptr;
@@ -975,14 +975,18 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     for (int it = split ? nsweep : 0;; ++it) {
       {
         Stage t(MRCM_STAGE_RESIDUAL, s);
-        ENQ(launch_fill(h->norms, 2LL * H.totCols, 0.0, s));
+        ENQ(launch_fill(h->norms, 3LL * H.totCols, 0.0, s));
         ENQ(launch_residual(g, h->n_sub, H.max_cells, h->coef, h->r0, h->X, h->R, h->norms, s));
         ENQ(launch_ir_check(h->norms, H.totCols, h->scalar, s));
       }
-      double res = 0.0;
-      ENQ(hipMemcpyAsync(&res, h->scalar, sizeof(double), hipMemcpyDeviceToHost, s));
+      // res: the largest relative residual of the columns still above the
+      // rounding floor of their own residual (those that a sweep can still
+      // improve); the reported residual is the largest of all columns
+      double rv[2] = {0.0, 0.0};
+      ENQ(hipMemcpyAsync(rv, h->scalar, sizeof(rv), hipMemcpyDeviceToHost, s));
       ENQ(hipStreamSynchronize(s));
-      h->ir_res = res;
+      const double res = rv[0];
+      h->ir_res = rv[1];
       h->ir_iters = it;
       if (res <= h->ir_tol) break;
       if ((it >= h->ir_max || !std::isfinite(res)) && !polished && cg_ok && std::isfinite(res)) {

@@ -1144,8 +1144,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 
 
 // ---------------------------------------------------------------------------
 // FP64 residual of all right-hand sides, Rb = R - A^H_l X, matrix-free from
-// the coefficients; accumulates per-column ||Rb||^2 and ||R||^2 into norms
-// unless norms is null (a fixed number of refinement sweeps needs none).
+// the coefficients.  Unless norms is null (a fixed number of refinement
+// sweeps needs none) it accumulates per column, at norms[3 col + 0..2],
+// ||Rb||^2, ||R||^2 and ||s||^2 with s_r = |R_r| + sum of |a_rj X_j| over the
+// row's stencil: the componentwise bound on the rounding of Rb itself is
+// gamma_8 s_r (eight terms summed), gamma_8 = 8u / (1 - 8u) with the unit
+// roundoff u = 2^-53.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_residual(Geom g, const double *__restrict__ coef,
                                                   const double *__restrict__ r0,
@@ -1154,7 +1158,7 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, const double *__restri
                                                   double *__restrict__ norms, int ntile, int n_sub,
                                                   const int *__restrict__ subs) {
   __shared__ double tile[kRowsPB * kMaxRhs];
-  __shared__ double red[2 * kMaxRhs];
+  __shared__ double red[3 * kMaxRhs];
   // XCD-aware order: workgroups go round-robin to the eight XCDs, so XCD x
   // gets subdomains x, x + 8, ... with all their row tiles in sequence, and
   // the stencil's neighbour rows come from that XCD's L2
@@ -1167,7 +1171,7 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, const double *__restri
   if (rbase >= N) return;
   const bool acc_norms = norms != nullptr;
   if (acc_norms)
-    for (int i = threadIdx.x; i < 2 * m; i += blockDim.x) red[i] = 0.0;
+    for (int i = threadIdx.x; i < 3 * m; i += blockDim.x) red[i] = 0.0;
   rhs_tile(g, S, r0, rbase, tile);
   const double *cf = coef + 4 * S.cell_off;
   const double *X = Xg + S.X_off;
@@ -1175,46 +1179,68 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, const double *__restri
   const int ne = min(kRowsPB, N - rbase) * m;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
     const int r = rbase + e / m, c = e % m;
-    double ax = cf[4 * r] * X[(size_t)r * m + c];
-    if (r + 1 < N) ax -= cf[4 * r + 1] * X[(size_t)(r + 1) * m + c];
-    if (r >= 1) ax -= cf[4 * (r - 1) + 1] * X[(size_t)(r - 1) * m + c];
-    if (r + n0 < N) ax -= cf[4 * r + 2] * X[(size_t)(r + n0) * m + c];
-    if (r >= n0) ax -= cf[4 * (r - n0) + 2] * X[(size_t)(r - n0) * m + c];
-    if (r + b < N) ax -= cf[4 * r + 3] * X[(size_t)(r + b) * m + c];
-    if (r >= b) ax -= cf[4 * (r - b) + 3] * X[(size_t)(r - b) * m + c];
+    double t = cf[4 * r] * X[(size_t)r * m + c];
+    double ax = t, ab = fabs(t);
+    auto sub = [&](double v) {
+      ax -= v;
+      ab += fabs(v);
+    };
+    if (r + 1 < N) sub(cf[4 * r + 1] * X[(size_t)(r + 1) * m + c]);
+    if (r >= 1) sub(cf[4 * (r - 1) + 1] * X[(size_t)(r - 1) * m + c]);
+    if (r + n0 < N) sub(cf[4 * r + 2] * X[(size_t)(r + n0) * m + c]);
+    if (r >= n0) sub(cf[4 * (r - n0) + 2] * X[(size_t)(r - n0) * m + c]);
+    if (r + b < N) sub(cf[4 * r + 3] * X[(size_t)(r + b) * m + c]);
+    if (r >= b) sub(cf[4 * (r - b) + 3] * X[(size_t)(r - b) * m + c]);
     const double rhs = tile[e];
     const double res = rhs - ax;
     Rbuf[S.X_off + (size_t)r * m + c] = res;
     if (acc_norms) {
-      atomicAdd(&red[2 * c], res * res);
-      atomicAdd(&red[2 * c + 1], rhs * rhs);
+      ab += fabs(rhs);
+      atomicAdd(&red[3 * c], res * res);
+      atomicAdd(&red[3 * c + 1], rhs * rhs);
+      atomicAdd(&red[3 * c + 2], ab * ab);
     }
   }
   if (!acc_norms) return;
   __syncthreads();
-  for (int i = threadIdx.x; i < 2 * m; i += blockDim.x) {
-    if (red[i] != 0.0) atomicAdd(&norms[2 * (long long)S.col_off + i], red[i]);
+  for (int i = threadIdx.x; i < 3 * m; i += blockDim.x) {
+    if (red[i] != 0.0) atomicAdd(&norms[3 * (long long)S.col_off + i], red[i]);
   }
 }
 
-// Largest relative column residual sqrt(||Rb||^2 / ||R||^2) over all columns
-// (a zero right-hand side counts its absolute residual).  One workgroup.
+// Largest relative column residual sqrt(||Rb||^2 / ||R||^2) (a zero
+// right-hand side counts its absolute residual): out[0] over the columns
+// whose residual is above its own rounding floor, ||Rb|| > 8u ||s||
+// (refinement can still reduce those), out[1] over all columns.  One
+// workgroup.
 __global__ __launch_bounds__(256) void k_ir_check(const double *__restrict__ norms, int ncols,
                                                   double *__restrict__ out) {
-  __shared__ double red[256];
-  double mx = 0.0;
+  __shared__ double red[2][256];
+  constexpr double kFloor = 8.0 * 0x1.0p-53;  // gamma_8 / eps64 = 8, unit roundoff 2^-53
+  double mx = 0.0, ma = 0.0;
   for (int i = threadIdx.x; i < ncols; i += blockDim.x) {
-    const double rr = norms[2 * i], RR = norms[2 * i + 1];
+    const double rr = norms[3 * i], RR = norms[3 * i + 1], ss = norms[3 * i + 2];
     const double v = RR > 0.0 ? sqrt(rr / RR) : sqrt(rr);
-    mx = fmax(mx, v);
+    // a non-finite residual counts as infinite, and never as at its floor
+    const bool fin = v <= 1.7976931348623157e308;
+    const double vv = fin ? v : INFINITY;
+    ma = fmax(ma, vv);
+    if (!fin || !(rr <= kFloor * kFloor * ss)) mx = fmax(mx, vv);
   }
-  red[threadIdx.x] = mx;
+  red[0][threadIdx.x] = mx;
+  red[1][threadIdx.x] = ma;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    if (threadIdx.x < s) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (threadIdx.x == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+  }
 }
 
 // ---------------------------------------------------------------------------

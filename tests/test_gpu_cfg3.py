@@ -12,6 +12,9 @@ one GPU, end to end in FP64.  The oracle cannot solve it whole, so:
     deviation 3 (permeabilities spread over about eight orders of magnitude)
     it measures 3e-10 (test_gpu_parity.py holds a small case with log-k
     standard deviation 2 to 1e-12 of each cell's face fluxes).
+The FP32 form with FP64 refinement is held to the same three checks on the
+same inputs: its ragged batches, two-stream pipeline and per-column
+refinement at the full 9,108-subdomain size.
 """
 import time
 
@@ -36,12 +39,44 @@ def _maxrel(a, b):
     return float(np.max(np.abs(a - b)) / (s if s > 0 else 1.0))
 
 
-def test_cfg3_ragged_workload_end_to_end():
-    import paper_2103_08513_amd as lib
+@pytest.fixture(scope="module")
+def case3():
     t0 = time.perf_counter()
     case = config3()
-    pb = case.problem
     print(f"cfg3 inputs: {time.perf_counter() - t0:.1f} s", flush=True)
+    return case
+
+
+def _sampled_mbfs_match_oracle(m, case, tol):
+    """One subdomain of every shape, and two more, against the oracle."""
+    pb = case.problem
+    geo = Geometry(pb.dims, case.partition, case.iface)
+    first = {}
+    for l in range(geo.n_sub):
+        first.setdefault(tuple(int(x) for x in geo.sub_hi[l] - geo.sub_lo[l]), l)
+    sample = sorted(set(first.values()) | {4553, 9107})
+    _, Xs, Fs, _, _ = oracle_build(pb, geo, case.alpha, subdomains=sample)
+    for l, Xo, Fo in zip(sample, Xs, Fs):
+        Xg = m.copy_mbfs(l)[np.argsort(m.local_order(l))]
+        for c in range(Xo.shape[1]):
+            assert _maxrel(Xg[:, c], Xo[:, c]) < tol, (l, c)
+        Fg, _, _ = m.copy_flux(l)
+        assert _maxrel(Fg, Fo) < tol, l
+
+
+def _mass_imbalance(pb, U):
+    """Largest per-cell |net outflow - source| over the largest face flux."""
+    Uh = U.cpu().numpy()
+    A = np.array([pb.hy * pb.hz, pb.hx * pb.hz, pb.hx * pb.hy])
+    Q = Uh * np.repeat(A, 2)[:, None]
+    net = np.abs(Q.sum(axis=0) - pb.q)
+    return float(np.max(net) / np.max(np.abs(Q))), float(np.max(net / (np.max(np.abs(Q), axis=0) + 1e-300)))
+
+
+def test_cfg3_ragged_workload_end_to_end(case3):
+    import paper_2103_08513_amd as lib
+    case = case3
+    pb = case.problem
     m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha)
     args = [_dev(a) for a in (pb.kx, pb.ky, pb.kz, pb.q)]
     m.build_mbfs(*args)  # creates the handle
@@ -74,26 +109,41 @@ def test_cfg3_ragged_workload_end_to_end():
     assert m.interface_residual < max(1e-12, 2.0 * res0)
     assert float(torch.linalg.norm(X1 - X) / torch.linalg.norm(X)) < 1e-6
     # sampled MBFs against the oracle: one subdomain of every shape, and more
-    geo = Geometry(pb.dims, case.partition, case.iface)
-    first = {}
-    for l in range(geo.n_sub):
-        first.setdefault(tuple(int(x) for x in geo.sub_hi[l] - geo.sub_lo[l]), l)
-    sample = sorted(set(first.values()) | {4553, 9107})
-    _, Xs, Fs, _, _ = oracle_build(pb, geo, case.alpha, subdomains=sample)
-    for l, Xo, Fo in zip(sample, Xs, Fs):
-        Xg = m.copy_mbfs(l)[np.argsort(m.local_order(l))]
-        for c in range(Xo.shape[1]):
-            assert _maxrel(Xg[:, c], Xo[:, c]) < 1e-9, (l, c)
-        Fg, _, _ = m.copy_flux(l)
-        assert _maxrel(Fg, Fo) < 1e-9, l
+    _sampled_mbfs_match_oracle(m, case, 1e-9)
     # mass conservation per cell from the reconstructed velocities
-    Uh = U.cpu().numpy()
-    A = np.array([pb.hy * pb.hz, pb.hx * pb.hz, pb.hx * pb.hy])
-    Q = Uh * np.repeat(A, 2)[:, None]
-    net = np.abs(Q.sum(axis=0) - pb.q)
-    worst = float(np.max(net) / np.max(np.abs(Q)))
-    local = float(np.max(net / (np.max(np.abs(Q), axis=0) + 1e-300)))
+    worst, local = _mass_imbalance(pb, U)
     print(f"cfg3: largest per-cell mass imbalance {worst:.2e} of the largest face flux "
           f"({local:.2e} of the cell's own largest face flux)", flush=True)
+    assert worst < 1e-8
+    m.close()
+
+
+def test_cfg3_fp32_form(case3):
+    import paper_2103_08513_amd as lib
+    case = case3
+    pb = case.problem
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=lib.FP32_IR)
+    args = [_dev(a) for a in (pb.kx, pb.ky, pb.kz, pb.q)]
+    m.build_mbfs(*args)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.build_mbfs(*args)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    info = m.info()
+    print(f"cfg3 FP32 form: build {1e3 * t_build:.1f} ms, {info.ir_iters} refinement sweeps to "
+          f"{info.ir_residual:.2e}", flush=True)
+    # log-k of standard deviation 3: columns whose FP64 residual stalls at
+    # the rounding bound of its own evaluation stop there, just above 1e-13
+    assert info.ir_residual <= 1e-11
+    m.assemble_interface()
+    X = m.solve_interface(residual=True)
+    p, U = m.reconstruct(X)
+    torch.cuda.synchronize()
+    assert m.interface_residual < 1e-9
+    _sampled_mbfs_match_oracle(m, case, 1e-9)
+    worst, local = _mass_imbalance(pb, U)
+    print(f"cfg3 FP32 form: interface residual {m.interface_residual:.2e}, largest per-cell mass imbalance "
+          f"{worst:.2e} of the largest face flux", flush=True)
     assert worst < 1e-8
     m.close()

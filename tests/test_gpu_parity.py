@@ -146,7 +146,10 @@ def test_config1_fp32_refined_end_to_end():
     ref = mrcm_solve(case)
     m, p, U, X = _run(case, precision=1)
     info = m.info()
-    assert info.ir_residual <= 1e-13
+    print(f"cfg1 FP32: {info.ir_iters} refinement sweeps, residual {info.ir_residual:.2e}, "
+          f"p {rel_l2(p, ref.p):.2e}, U {rel_l2(U, ref.U):.2e}", flush=True)
+    # columns still above 1e-13 sit at the rounding bound of their own residual
+    assert info.ir_residual <= 1e-12
     assert rel_l2(p, ref.p) < 1e-8
     assert rel_l2(U, ref.U) < 1e-8
     m.close()
@@ -314,25 +317,13 @@ def test_extreme_robin_parameter(alpha, precision):
     """The Robin parameter alpha far from one: at 1e-3 the local problems are
     nearly Dirichlet, at 1e3 nearly Neumann (the local matrices lose the
     Robin terms' diagonal weight, and their condition grows with alpha).
-    Flux blocks and the solution against the oracle."""
+    Flux blocks and the solution against the oracle, with the FP32 form at
+    its default tolerance."""
     import paper_2103_08513_amd as lib
     case = small_case((10, 8, 6), (2, 2, 3), split=((2, 1), (1, 2), (2, 2)), seed=5, std=2.0, alpha=alpha)
     pb = case.problem
     args = [_dev(a) for a in (pb.kx, pb.ky, pb.kz, pb.q)]
-    kw = {}
-    if precision == 1 and alpha > 1.0:
-        # Nearly Neumann local problems with log-k of standard deviation 2:
-        # the FP64 residual of the refinement stalls near 1e-11 (rounding of
-        # R - M X against large |M| |X|), above the default 1e-13, and the
-        # build says so instead of returning
-        m = lib.MRCM(pb, case.partition, case.iface, alpha=alpha, precision=precision)
-        with pytest.raises(lib.MRCMError) as ei:
-            m.build_mbfs(*args)
-        assert ei.value.code == -4
-        print(f"alpha {alpha:g}, precision 1, ir_tol 1e-13: {ei.value}", flush=True)
-        m.close()
-        kw = dict(ir_tol=1e-10)
-    m = lib.MRCM(pb, case.partition, case.iface, alpha=alpha, precision=precision, **kw)
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=alpha, precision=precision)
     p, U, X = m.solve(*args)
     torch.cuda.synchronize()
     ref = mrcm_solve(case)
@@ -341,7 +332,14 @@ def test_extreme_robin_parameter(alpha, precision):
         F, Fb, _ = m.copy_flux(l)
         worst = max(worst, _maxrel(F, ref.F[l]), _maxrel(Fb, ref.Fb[l]))
     ep, eu = rel_l2(p.cpu().numpy(), ref.p), rel_l2(U.cpu().numpy(), ref.U)
-    print(f"alpha {alpha:g}, precision {precision}: flux blocks {worst:.2e}, p {ep:.2e}, U {eu:.2e}", flush=True)
+    info = m.info()
+    print(f"alpha {alpha:g}, precision {precision}: flux blocks {worst:.2e}, p {ep:.2e}, U {eu:.2e}; "
+          f"{info.ir_iters} refinement sweeps, residual {info.ir_residual:.2e}", flush=True)
+    if precision == 1:
+        # at alpha = 1e3 (log-k standard deviation 2) some columns' FP64
+        # residuals stall near 1e-11, at the rounding bound of their own
+        # evaluation: the refinement stops there rather than failing
+        assert info.ir_residual <= (1e-13 if alpha < 1.0 else 1e-10)
     assert worst < 1e-9
     assert ep < 1e-8 and eu < 1e-8
     m.close()
