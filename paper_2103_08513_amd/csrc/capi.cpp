@@ -550,6 +550,7 @@ struct mrcm_mbfs {
   double *coef = nullptr, *r0 = nullptr, *scal = nullptr;
   void *L = nullptr, *Dinv = nullptr;
   double *X = nullptr, *R = nullptr;
+  double *R0 = nullptr;  // FP32 pipeline: the right-hand sides, kept for every sweep's own residual
   double *F = nullptr, *Fb = nullptr, *SAb = nullptr;
   double *norms = nullptr, *scalar = nullptr;
   DevStatus *st = nullptr;
@@ -580,7 +581,7 @@ namespace {
 void free_mbfs(mrcm_mbfs *h) {
   if (!h) return;
   void *ptrs[] = {h->d_sub, h->d_ifc, h->d_order, h->d_work, h->d_patches, h->d_subof[0], h->d_subof[1],
-                  h->d_subof[2], h->coef, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, h->F, h->Fb, h->SAb,
+                  h->d_subof[2], h->coef, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, h->R0, h->F, h->Fb, h->SAb,
                   h->norms, h->scalar, h->st, h->d_grp_subs[0], h->d_grp_subs[1], h->d_order_split,
                   h->d_colsub, h->d_iters, h->d_conv, h->d_fb_order, h->d_fb_work, h->d_nn_sel, h->d_nn_s0};
   for (void *p : ptrs)
@@ -848,12 +849,20 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       return bail(fail(MRCM_ENOMEM, "device allocation of the refinement buffer failed"));
     h->bytes += H.totX * 8;
   }
-  // one pipelined FP64 sweep: R takes a copy of the right-hand sides and each
-  // correction workgroup forms its own residual from it
-  const bool own_res = split && !fp32 && h->refine64 == 1;
+  // Pipelined sweeps: each correction workgroup forms its own residual from
+  // a copy of the right-hand sides.  One FP64 sweep keeps the copy in R (the
+  // correction overwrites it); the FP32 form's several sweeps keep it in R0.
+  const bool own_res = split && (fp32 || h->refine64 == 1);
+  if (own_res && fp32 && !h->R0) {
+    if (dev_alloc(&h->R0, (size_t)H.totX) != hipSuccess)
+      return bail(fail(MRCM_ENOMEM, "device allocation of the right-hand-side copy failed"));
+    h->bytes += H.totX * 8;
+  }
+  const double *rhs0 = own_res && fp32 ? h->R0 : nullptr;
   {
     Stage t(MRCM_STAGE_RHS, s);
-    ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, pcg ? h->R : h->X, s, own_res ? h->R : nullptr));
+    ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, pcg ? h->R : h->X, s,
+                   own_res ? (fp32 ? h->R0 : h->R) : nullptr));
   }
   if (pcg) {
     // Conjugate gradients for every column (right-hand sides in R), then the
@@ -926,7 +935,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       if (!own_res)
         ENQ(launch_residual(g, n0, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, h->s2, h->d_grp_subs[0]));
       ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->R, h->X, 1, H.bmax, h->s2,
-                       own_res ? h->coef : nullptr));
+                       own_res ? h->coef : nullptr, rhs0));
     }
     ENQ(hipEventRecord(h->ev_join, h->s2));
     Stage t(MRCM_STAGE_REFINE, s);
@@ -937,7 +946,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       if (!own_res)
         ENQ(launch_residual(g, n1s, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s, h->d_grp_subs[1]));
       ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->R, h->X, 3, H.bmax, s,
-                       own_res ? h->coef : nullptr));
+                       own_res ? h->coef : nullptr, rhs0));
     }
     ENQ(hipStreamWaitEvent(s, h->ev_join, 0));
     h->ir_iters = nsweep;

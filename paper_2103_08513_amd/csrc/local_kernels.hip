@@ -737,21 +737,23 @@ __device__ __forceinline__ typename Mma<T>::v4 mma16_split(const T (&a)[4], cons
   return (c + p1) + (p2 + p3);
 }
 
-// R(:, c0..c1) = R - A^H_l X(:, c0..c1) for one work item, R holding the
-// right-hand sides on entry: the FP64 residual of a refinement sweep, formed
-// by the workgroup that then solves for the correction.  Matrix-free from the
-// coefficients, eight entries per thread at a time with all their loads
-// issued first.
+// R(:, c0..c1) = R0 - A^H_l X(:, c0..c1) for one work item, R0 holding the
+// right-hand sides (R0 may be R itself for a single sweep): the FP64 residual
+// of a refinement sweep, formed by the workgroup that then solves for the
+// correction.  Matrix-free from the coefficients, kPB entries per thread at
+// a time with all their loads issued first (kPB = 4 in the FP32 kernel,
+// whose register budget at three workgroups per CU does not hold eight).
+template <int kPB>
 __device__ __forceinline__ void item_residual(const Geom &g, const int4 item, const double *__restrict__ coef,
-                                              const double *Xg, double *Rg) {
+                                              const double *Xg, const double *R0g, double *Rg) {
   const SubDesc &S = g.sub[item.x];
   const int c0 = item.y, cw = item.z - item.y;
   const int N = S.N, m = S.m, n0 = S.n0, b = S.b;
   const double *cf = coef + 4 * S.cell_off;
   const double *X = Xg + S.X_off;
+  const double *R0 = R0g + S.X_off;
   double *R = Rg + S.X_off;
   const int ne = N * cw;
-  constexpr int kPB = 8;
   for (int e0 = threadIdx.x; e0 < ne; e0 += kPB * 256) {
     double ax[kPB], rv[kPB];
 #pragma unroll
@@ -776,7 +778,7 @@ __device__ __forceinline__ void item_residual(const Geom &g, const int4 item, co
       if (r + b < N) a -= t5;
       if (r >= b) a -= t6;
       ax[q] = a;
-      rv[q] = R[o];
+      rv[q] = R0[o];
     }
 #pragma unroll
     for (int q = 0; q < kPB; ++q) {
@@ -787,23 +789,23 @@ __device__ __forceinline__ void item_residual(const Geom &g, const int4 item, co
 }
 
 // NBT: most R2-update tiles per wave; KS: k-steps of the backward L21^T
-// product (4*KS >= the largest band).  coef non-null (FP64 corrections
-// only): form the item's residual into Bg first (Bg holding the right-hand
-// sides).
+// product (4*KS >= the largest band).  coef non-null (corrections only):
+// form the item's FP64 residual into Bg first, from the right-hand sides in
+// rhs0 (or in Bg itself when rhs0 is null).
 template <typename T, int mode, int NBT, int KS>
 // workgroups per CU: FP32 three (b <= 112) or two, FP64 two (b <= 112) or one
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 ? 1 : 2)) void k_solve(Geom g, const int4 *__restrict__ work,
                                                const double *__restrict__ scal,
                                                const T *__restrict__ Lg, const T *__restrict__ Dg,
                                                double *Bg, double *Xg, int scaled, int ldb, int wmax,
-                                               const double *__restrict__ coef) {
+                                               const double *__restrict__ coef, const double *rhs0) {
   using M = Mma<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int4 item = work[blockIdx.x];
   if (item.x < 0) return;
-  if constexpr (sizeof(T) == 8 && (mode & 1) != 0) {
+  if constexpr ((mode & 1) != 0) {
     if (coef) {
-      item_residual(g, item, coef, Xg, Bg);
+      item_residual<sizeof(T) == 8 ? 8 : 4>(g, item, coef, Xg, rhs0 ? rhs0 : Bg, Bg);
       __syncthreads();
     }
   }
@@ -1389,13 +1391,13 @@ hipError_t launch_factor(int fp32, const SubDesc *subs, const int *order, int n_
 template <typename T, int mode, int NBT, int KS>
 static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, const double *scal,
                                  const T *L, const T *Dg, double *B, double *X, int bmax, int scaled,
-                                 hipStream_t s, const double *coef) {
+                                 hipStream_t s, const double *coef, const double *rhs0) {
   const size_t lds = solve_lds_bytes(sizeof(T) == 4, bmax, 0);
   hipError_t e = hipFuncSetAttribute((const void *)k_solve<T, mode, NBT, KS>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_solve<T, mode, NBT, KS>), dim3(n_work), dim3(256), lds, s, g, work, scal, L, Dg, B,
-                     X, scaled, solve_ldb(bmax), bmax + kNB, coef);
+                     X, scaled, solve_ldb(bmax), bmax + kNB, coef, rhs0);
   return hipGetLastError();
 }
 
@@ -1405,33 +1407,33 @@ static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, co
 template <typename T, int mode>
 static hipError_t launch_solve_m(const Geom &g, const int4 *work, int n_work, const double *scal,
                                  const T *L, const T *Dg, double *B, double *X, int bmax, hipStream_t s,
-                                 const double *coef) {
+                                 const double *coef, const double *rhs0) {
   if (bmax <= 112)
-    return launch_solve_t<T, mode, sizeof(T) == 8 ? 4 : 3, 28>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef);
-  return launch_solve_t<T, mode, 3, (kMaxBand32 + 3) / 4>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef);
+    return launch_solve_t<T, mode, sizeof(T) == 8 ? 4 : 3, 28>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef, rhs0);
+  return launch_solve_t<T, mode, 3, (kMaxBand32 + 3) / 4>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef, rhs0);
 }
 
 hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, const double *scal,
                         const void *L, const void *Dg, double *B, double *X, int mode, int bmax,
-                        hipStream_t s, const double *coef) {
+                        hipStream_t s, const double *coef, const double *rhs0) {
   // Separate instantiations per mode, so that profiles tell them apart: bit 0
   // set for a correction (X += ...), bit 1 set for the second group of work
   // items when the first solve is split.
   if (fp32) {
     const float *Lf = (const float *)L, *Df = (const float *)Dg;
     switch (mode) {
-      case 0: return launch_solve_m<float, 0>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef);
-      case 1: return launch_solve_m<float, 1>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef);
-      case 2: return launch_solve_m<float, 2>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef);
-      default: return launch_solve_m<float, 3>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef);
+      case 0: return launch_solve_m<float, 0>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef, rhs0);
+      case 1: return launch_solve_m<float, 1>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef, rhs0);
+      case 2: return launch_solve_m<float, 2>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef, rhs0);
+      default: return launch_solve_m<float, 3>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef, rhs0);
     }
   }
   const double *Ld = (const double *)L, *Dd = (const double *)Dg;
   switch (mode) {
-    case 0: return launch_solve_m<double, 0>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef);
-    case 1: return launch_solve_m<double, 1>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef);
-    case 2: return launch_solve_m<double, 2>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef);
-    default: return launch_solve_m<double, 3>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef);
+    case 0: return launch_solve_m<double, 0>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef, rhs0);
+    case 1: return launch_solve_m<double, 1>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef, rhs0);
+    case 2: return launch_solve_m<double, 2>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef, rhs0);
+    default: return launch_solve_m<double, 3>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef, rhs0);
   }
 }
 
