@@ -327,3 +327,90 @@ def test_norms_reduce_to_plain_l2_for_unit_data():
     # unit K, unit cells: ||u||^2 = sum (1/2) u^2 over all 6 faces
     assert np.isclose(rel_kinv_velocity(Z, U, pb), 1.0)
     assert np.isclose(rel_l2_pressure(2 * U[0], U[0]), 1.0)
+
+
+# ------------------------------------------------------ T3 with walls -----
+def _wall_case(d, kind, dims=(8, 6, 5), nd=(2, 2, 1), split=((1, 1), (1, 1), (1, 1)), alpha=1.0):
+    """Constant K, no sources, flow along axis d driven by the two walls
+    normal to d; every other wall is no-flow and nothing is pinned.
+    kind 'dd': Dirichlet g0 on the - wall and g1 on the + wall.
+    kind 'nd': Neumann inflow s on the - wall (outward velocity -s),
+               Dirichlet g1 on the + wall.
+    kind 'dn': Dirichlet g0 on the - wall, Neumann outflow s on the + wall."""
+    nx, ny, nz = dims
+    N = nx * ny * nz
+    h = (2.0, 1.0, 0.5)
+    K = (2.5, 0.7, 0.3)   # anisotropic but constant: only K_d drives the flow
+    pb = Problem(nx, ny, nz, *h, np.full(N, K[0]), np.full(N, K[1]), np.full(N, K[2]), np.zeros(N), pin=-1)
+    n_wall = N // dims[d]
+    g0, g1, s = 1.3, -0.4, 0.25
+    wt = [0] * 6
+    wv = [None] * 6
+    if kind == "dd":
+        wt[2 * d], wv[2 * d] = 1, np.full(n_wall, g0)
+        wt[2 * d + 1], wv[2 * d + 1] = 1, np.full(n_wall, g1)
+    elif kind == "nd":
+        wt[2 * d], wv[2 * d] = 2, np.full(n_wall, -s)
+        wt[2 * d + 1], wv[2 * d + 1] = 1, np.full(n_wall, g1)
+    else:
+        wt[2 * d], wv[2 * d] = 1, np.full(n_wall, g0)
+        wt[2 * d + 1], wv[2 * d + 1] = 2, np.full(n_wall, s)
+    pb.wall_type, pb.wall_value = wt, wv
+    cuts = [np.linspace(0, n, k + 1).round().astype(np.int32) for n, k in zip(dims, nd)]
+    case = Case("walls", pb, Partition(*cuts), IfaceSpace(split), alpha)
+    # closed forms along axis d (i = cell coordinate, n cells of size hd)
+    n, hd, Kd = dims[d], h[d], K[d]
+    i = (np.arange(N) // (1, nx, nx * ny)[d]) % n
+    if kind == "dd":
+        # half-cell rule at both walls: the pressure drop g0 - g1 splits into
+        # n - 1 full cell spacings and two half cells, all of resistance h/K
+        exact = g0 + (g1 - g0) * (i + 0.5) / n
+        vel = -Kd * (g1 - g0) / (n * hd)       # velocity along +e_d
+    elif kind == "nd":
+        exact = g1 + s * hd * (n - i - 0.5) / Kd
+        vel = s
+    else:
+        exact = g0 - s * hd * (i + 0.5) / Kd
+        vel = s
+    return case, exact, vel
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+@pytest.mark.parametrize("kind", ["dd", "nd", "dn"])
+def test_wall_closed_forms_fine(d, kind):
+    """Eqs. (2.5), (2.6) with constant K: between a Dirichlet and a Dirichlet
+    or Neumann wall the TPFA pressure is linear in the cell coordinate, with a
+    half cell of resistance h/(2K) between the last cell centre and a
+    Dirichlet wall, and a Neumann wall passing exactly its data.  A full-cell
+    wall term, or the opposite sign of the Neumann datum, changes the answer."""
+    case, exact, vel = _wall_case(d, kind)
+    pb = case.problem
+    p, U = fine_solve(pb)
+    assert np.max(np.abs(p - exact)) < 1e-12 * max(1.0, np.max(np.abs(exact)))
+    # every face normal to d carries the same velocity along +e_d, walls included
+    assert np.allclose(U[2 * d + 1], vel, rtol=1e-12, atol=1e-13)
+    assert np.allclose(U[2 * d], -vel, rtol=1e-12, atol=1e-13)
+    for e in range(3):
+        if e != d:
+            assert np.max(np.abs(U[2 * e])) < 1e-12 and np.max(np.abs(U[2 * e + 1])) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["dd", "nd", "dn"])
+@pytest.mark.parametrize("alpha", [1e-2, 1.0, 1e2])
+def test_wall_closed_forms_mrcm(kind, alpha):
+    """The same closed forms through the MRCM's local problems (walls enter
+    only the particular problem (2.26)).  Cuts normal to the flow carry a
+    constant trace and flux, which the one-patch spaces contain, so the MRCM
+    is exact for every alpha; cuts parallel to the flow are exact with the
+    fine trace (Sec. 2.2)."""
+    for d, nd, split in ((0, (3, 1, 1), ((1, 1), (1, 1), (1, 1))),
+                         (1, (1, 2, 1), ((1, 1), (1, 1), (1, 1))),
+                         (2, (2, 2, 2), ((0, 0), (0, 0), (0, 0)))):
+        case, exact, vel = _wall_case(d, kind, nd=nd, split=split, alpha=alpha)
+        r = mrcm_solve(case)
+        assert np.max(np.abs(r.p - exact)) < 1e-10 * max(1.0, np.max(np.abs(exact))), (d, kind)
+        assert np.allclose(r.U[2 * d + 1], vel, rtol=1e-9, atol=1e-11)
+        assert np.allclose(r.U[2 * d], -vel, rtol=1e-9, atol=1e-11)
+        # the monolithic formulation, which assembles its walls separately
+        pm, _ = mrcm_monolithic(case)
+        assert np.max(np.abs(pm - exact)) < 1e-10 * max(1.0, np.max(np.abs(exact))), (d, kind)
