@@ -219,9 +219,36 @@ def robin_data(ls, col):
     return G
 
 
-def local_solve(ls):
+def refined_solve(M, R, extended=True, steps=2):
+    """Solve M X = R (sparse, one right-hand side per column): sparse LU in
+    FP64, then, when ``extended``, ``steps`` rounds of iterative refinement
+    X += M^-1 (R - M X) whose residual is formed in extended precision
+    (np.longdouble: a 64-bit significand on x86-64) and whose correction uses
+    the same FP64 factor.  While the condition number times the FP64 unit
+    roundoff stays below one, each round shrinks the error by that product,
+    so two rounds leave X correctly rounded to FP64 up to a few units in the
+    last place (classical mixed-precision refinement, Wilkinson; Moler 1967).
+
+    Plain FP64 is not enough for an end-to-end reference at the 1e-8 level:
+    the interface system amplifies the rounding errors of the local solves
+    (on the 60x220x85 channelised workload a relative change of 1e-15 in the
+    interface matrix moves the pressure by 1.7e-8)."""
+    lu = spla.splu(M.tocsc())
+    X = lu.solve(R)
+    if not extended:
+        return X
+    Ml = M.astype(np.longdouble)
+    Rl = np.asarray(R).astype(np.longdouble)
+    Xl = X.astype(np.longdouble)
+    for _ in range(steps):
+        r = Rl - Ml @ Xl
+        Xl = Xl + lu.solve(r.astype(np.float64)).astype(np.longdouble)
+    return Xl.astype(np.float64)
+
+
+def local_solve(ls, extended=True):
     """Loop 1 of Algorithm 2 for one subdomain: one factorisation, 2|I^l|+1 solves."""
-    return spla.splu(ls.M.tocsc()).solve(ls.R)
+    return refined_solve(ls.M, ls.R, extended)
 
 
 def gamma_flux_blocks(ls, X):
@@ -294,19 +321,52 @@ class MRCMResult:
     geo: Geometry
 
 
-def build_mbfs(pb, geo, alpha, subdomains=None):
-    """Loop 1 of Algorithm 2: local systems, MBFs and their Gamma-flux blocks."""
-    subs = range(geo.n_sub) if subdomains is None else subdomains
-    systems, Xs, Fs, Fbs, SAbs = [], [], [], [], []
-    for l in subs:
-        ls = local_system(pb, geo, l, alpha)
-        X = local_solve(ls)
-        F, Fb, SAb = gamma_flux_blocks(ls, X)
-        systems.append(ls)
-        Xs.append(X)
-        Fs.append(F)
-        Fbs.append(Fb)
-        SAbs.append(SAb)
+def _one_subdomain(pb, geo, l, alpha, extended):
+    ls = local_system(pb, geo, l, alpha)
+    X = local_solve(ls, extended)
+    F, Fb, SAb = gamma_flux_blocks(ls, X)
+    return ls, X, F, Fb, SAb
+
+
+_POOL_ARGS = None
+
+
+def _pool_task(l):
+    pb, geo, alpha, extended = _POOL_ARGS
+    return _one_subdomain(pb, geo, l, alpha, extended)
+
+
+def _pool_init():
+    # one BLAS thread per worker process: the parallelism is over subdomains
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(limits=1)
+    except ImportError:
+        pass
+
+
+def build_mbfs(pb, geo, alpha, subdomains=None, extended=True, processes=1):
+    """Loop 1 of Algorithm 2: local systems, MBFs and their Gamma-flux blocks.
+
+    The subdomains are independent; ``processes`` > 1 spreads them over a
+    pool of forked worker processes (same results, subdomain order kept)."""
+    global _POOL_ARGS
+    subs = list(range(geo.n_sub) if subdomains is None else subdomains)
+    if processes > 1 and len(subs) > 1:
+        import multiprocessing as mp
+        _POOL_ARGS = (pb, geo, alpha, extended)
+        try:
+            with mp.get_context("fork").Pool(processes, initializer=_pool_init) as pool:
+                out = pool.map(_pool_task, subs, chunksize=max(1, len(subs) // (8 * processes)))
+        finally:
+            _POOL_ARGS = None
+    else:
+        out = [_one_subdomain(pb, geo, l, alpha, extended) for l in subs]
+    systems = [o[0] for o in out]
+    Xs = [o[1] for o in out]
+    Fs = [o[2] for o in out]
+    Fbs = [o[3] for o in out]
+    SAbs = [o[4] for o in out]
     return systems, Xs, Fs, Fbs, SAbs
 
 
@@ -376,7 +436,7 @@ def _local_velocities(pb, geo, ls, pl, pi, U):
     U[:, cells] = Uloc
 
 
-def reconstruct_resolve(pb, geo, systems, pi):
+def reconstruct_resolve(pb, geo, systems, pi, extended=True):
     """The second option after (2.23): solve the local problems again with the
     Robin data G(pi) = P_H - sigma beta U_H and the particular data, instead of
     combining stored MBFs."""
@@ -389,24 +449,29 @@ def reconstruct_resolve(pb, geo, systems, pi):
         np.add.at(rhs, g.cell, g.T * G)
         if ls.pin_local >= 0:
             rhs[ls.pin_local] = 0.0
-        p[ls.cells] = spla.splu(ls.M.tocsc()).solve(rhs)
+        p[ls.cells] = refined_solve(ls.M, rhs, extended)
     return p
 
 
-def mrcm_solve(case_or_problem, partition=None, iface=None, alpha=None):
-    """Full MRCM (Algorithm 2) on the CPU.  Accepts a Case or its parts."""
+def mrcm_solve(case_or_problem, partition=None, iface=None, alpha=None, extended=True, processes=1):
+    """Full MRCM (Algorithm 2) on the CPU.  Accepts a Case or its parts.
+
+    ``extended``: refine every local solve and the interface solve with an
+    extended-precision residual (see ``refined_solve``); False gives the plain
+    FP64 algorithm.  ``processes``: worker processes for loop 1."""
     if partition is None:
         case = case_or_problem
         pb, partition, iface, alpha = case.problem, case.partition, case.iface, case.alpha
     else:
         pb = case_or_problem
     geo = Geometry(pb.dims, partition, iface)
-    systems, Xs, Fs, Fbs, SAbs = build_mbfs(pb, geo, alpha)
+    systems, Xs, Fs, Fbs, SAbs = build_mbfs(pb, geo, alpha, extended=extended, processes=processes)
     blocks = [(ls.patches, patch_sigma(ls), F, Fb, SAb)
               for ls, F, Fb, SAb in zip(systems, Fs, Fbs, SAbs)]
     if geo.n_patch > 0:
         A, b = assemble_interface(geo.n_patch, blocks)
-        pi = spla.splu(A.tocsc()).solve(b)
+        # InterfaceSolver: a sparse LU (the paper uses MUMPS LU), refined
+        pi = refined_solve(A, b, extended, steps=3)
     else:
         A, b = sp.csr_matrix((0, 0)), np.zeros(0)
         pi = np.zeros(0)
