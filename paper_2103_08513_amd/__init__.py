@@ -28,12 +28,21 @@ def library():
     return _lib.load()
 
 
-def _dev_ptr(t, name):
+def _dev_ptr(t, name, numel=None, device=None):
+    """Device address of a contiguous float64 tensor, after checking its
+    device and, when given, its number of entries: the library reads and
+    writes exactly that many, so a shorter tensor must never reach it."""
     import torch
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor on the HIP device")
     if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError(f"{name} must be a contiguous float64 tensor on the HIP device")
+    if device is not None:
+        want = device.index if device.index is not None else torch.cuda.current_device()
+        if t.device.index != want:
+            raise ValueError(f"{name} is on cuda:{t.device.index}; the model runs on cuda:{want}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} entries; {numel} are required")
     return c_void_p(t.data_ptr())
 
 
@@ -101,7 +110,12 @@ class MRCM:
         for f in range(6):
             v = problem.wall_value[f]
             if v is not None:
-                t = torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64), device=self.device)
+                d = f // 2
+                n_wall = (nx * ny * nz) // (nx, ny, nz)[d]
+                v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
+                if v.size != n_wall:
+                    raise ValueError(f"wall {f} has {v.size} values; its face has {n_wall} cells")
+                t = torch.as_tensor(v, device=self.device)
                 self._wall_tensors[f] = t
                 cp.wall_value[f] = t.data_ptr()
         cuts = [np.ascontiguousarray(c, dtype=np.int32) for c in partition.cuts]
@@ -133,6 +147,23 @@ class MRCM:
         opt.pcg_x0 = None
         self._opt = opt
 
+    @property
+    def n_cells(self):
+        return self.pb.nx * self.pb.ny * self.pb.nz
+
+    def _set_fields(self, kx, ky, kz, q):
+        N = self.n_cells
+        cp = self._cp
+        cp.kx = _dev_ptr(kx, "kx", N, self.device).value
+        cp.ky = _dev_ptr(ky, "ky", N, self.device).value
+        cp.kz = _dev_ptr(kz, "kz", N, self.device).value
+        cp.q = _dev_ptr(q, "q", N, self.device).value
+
+    def _n_unknowns(self):
+        if not self._mbfs.value:
+            raise ValueError("build_mbfs has not run on this model")
+        return 2 * self.info().n_patch
+
     # -- the four steps of Algorithm 2 ------------------------------------
     def build_mbfs(self, kx, ky, kz, q, stream=None, x0=None, x0_scale=False):
         """x0 (PCG only): starting guess, a float64 device tensor in the layout
@@ -147,12 +178,9 @@ class MRCM:
             total = self.mbf_layout()[-1]
             if x0.numel() != total:
                 raise ValueError(f"x0 has {x0.numel()} entries; the MBF layout has {total}")
-        self._opt.pcg_x0 = None if x0 is None else _dev_ptr(x0, "x0").value
+        self._opt.pcg_x0 = None if x0 is None else _dev_ptr(x0, "x0", device=self.device).value
         self._opt.pcg_x0_scale = 1 if x0_scale else 0
-        cp.kx = _dev_ptr(kx, "kx").value
-        cp.ky = _dev_ptr(ky, "ky").value
-        cp.kz = _dev_ptr(kz, "kz").value
-        cp.q = _dev_ptr(q, "q").value
+        self._set_fields(kx, ky, kz, q)
         self._inputs = (kx, ky, kz, q)
         code = self.lib.mrcm_build_mbfs(byref(cp), byref(self._part), byref(self._ifs),
                                         byref(self._opt), _stream_ptr(stream), byref(self._mbfs))
@@ -169,13 +197,14 @@ class MRCM:
         unfactored system is also computed (one more band product and a
         stream synchronisation) and kept in ``interface_residual``."""
         import torch
-        info = self.info()
-        nv = info.n_patch
+        n = self._n_unknowns()
+        if not self._iface.value:
+            raise ValueError("assemble_interface has not run on this model")
         if X is None:
-            X = torch.empty(2 * nv, dtype=torch.float64, device=self.device)
+            X = torch.empty(n, dtype=torch.float64, device=self.device)
         res = c_double(0.0)
         code = self.lib.mrcm_solve_interface(self._iface, int(refine), _stream_ptr(stream),
-                                             _dev_ptr(X, "X") if nv > 0 else None,
+                                             _dev_ptr(X, "X", n, self.device) if n > 0 else None,
                                              byref(res) if residual else None)
         _lib.check(code, "mrcm_solve_interface")
         self.interface_residual = res.value if residual else None
@@ -183,14 +212,17 @@ class MRCM:
 
     def reconstruct(self, X, p=None, U=None, stream=None):
         import torch
-        N = self.pb.nx * self.pb.ny * self.pb.nz
+        N = self.n_cells
+        n = self._n_unknowns()
         if p is None:
             p = torch.empty(N, dtype=torch.float64, device=self.device)
         if U is None:
             U = torch.empty(6 * N, dtype=torch.float64, device=self.device)
-        xp = _dev_ptr(X, "X") if X is not None and X.numel() > 0 else None
-        code = self.lib.mrcm_reconstruct(self._mbfs, xp, _stream_ptr(stream), _dev_ptr(p, "p"),
-                                         _dev_ptr(U, "U"))
+        if n > 0 and X is None:
+            raise ValueError("X is required: the model has interface unknowns")
+        xp = _dev_ptr(X, "X", n, self.device) if n > 0 else None
+        code = self.lib.mrcm_reconstruct(self._mbfs, xp, _stream_ptr(stream), _dev_ptr(p, "p", N, self.device),
+                                         _dev_ptr(U, "U", 6 * N, self.device))
         _lib.check(code, "mrcm_reconstruct")
         return p, U.view(6, N)
 
@@ -207,10 +239,7 @@ class MRCM:
         builds.  Existing handles are released (their geometry includes the
         tunables).  Returns the chosen values and the build times."""
         cp = self._cp
-        cp.kx = _dev_ptr(kx, "kx").value
-        cp.ky = _dev_ptr(ky, "ky").value
-        cp.kz = _dev_ptr(kz, "kz").value
-        cp.q = _dev_ptr(q, "q").value
+        self._set_fields(kx, ky, kz, q)
         self._opt.pcg_x0 = None
         best = COptions()
         t_best, t_rule = c_double(0.0), c_double(0.0)
@@ -229,18 +258,17 @@ class MRCM:
         The graph keeps the addresses of kx, ky, kz, q, X, p and U: a replay
         reads their current contents.  Returns a Graph."""
         cp = self._cp
-        cp.kx = _dev_ptr(kx, "kx").value
-        cp.ky = _dev_ptr(ky, "ky").value
-        cp.kz = _dev_ptr(kz, "kz").value
-        cp.q = _dev_ptr(q, "q").value
+        self._set_fields(kx, ky, kz, q)
         self._opt.pcg_x0 = None
         self._opt.pcg_x0_scale = 0
         g = c_void_p()
-        nv = self.info().n_patch
+        n = self._n_unknowns()
+        N = self.n_cells
         code = self.lib.mrcm_graph_capture(byref(cp), byref(self._part), byref(self._ifs), byref(self._opt),
                                            self._mbfs, self._iface, int(refine),
-                                           _dev_ptr(X, "X") if nv > 0 else None, _dev_ptr(p, "p"),
-                                           _dev_ptr(U, "U"), _stream_ptr(stream), byref(g))
+                                           _dev_ptr(X, "X", n, self.device) if n > 0 else None,
+                                           _dev_ptr(p, "p", N, self.device), _dev_ptr(U, "U", 6 * N, self.device),
+                                           _stream_ptr(stream), byref(g))
         _lib.check(code, "mrcm_graph_capture")
         graph = Graph(self, g, (kx, ky, kz, q, X, p, U))
         self._graphs.append(graph)

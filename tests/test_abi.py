@@ -166,3 +166,16 @@ def test_host_validation_of_the_forms_and_tunables():
                                   ctypes.byref(g)) == -1
     assert lib.mrcm_graph_launch(None, None) == -1
     assert lib.mrcm_autotune(None, None, None, None, None, None, None, None) == -1
+
+
+def test_binding_refuses_wall_data_of_the_wrong_length():
+    """Checked in the constructor, before any device memory is touched."""
+    import numpy as np
+    from mrcm_inputs import small_case
+    import paper_2103_08513_amd as lib
+    case = small_case((8, 6, 4), (2, 2, 2), seed=1, pin=-1)
+    pb = case.problem
+    pb.wall_type = [1, 0, 0, 0, 0, 0]
+    pb.wall_value = [np.zeros(6 * 4 - 1), None, None, None, None, None]
+    with pytest.raises(ValueError):
+        lib.MRCM(pb, case.partition, case.iface)
