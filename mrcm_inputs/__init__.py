@@ -36,7 +36,7 @@ import numpy as np
 __all__ = [
     "Problem", "Partition", "IfaceSpace", "Case",
     "grf", "channelised", "uniform_cuts", "ragged_cuts",
-    "config1", "config2", "config3", "small_case",
+    "config1", "config2", "config3", "config3_block", "small_case",
 ]
 
 
@@ -239,12 +239,18 @@ def config3(seed=0, patch_seed=3):
     part = Partition(ragged_cuts(nx, [15, 15] + [20] * 7 + [15, 15]),
                      ragged_cuts(ny, [15, 15] + [20] * 19 + [15, 15]),
                      ragged_cuts(nz, [3, 3, 3] + [5] * 31 + [3, 3]))
+    split = _random_splits(part, np.random.default_rng(patch_seed))
+    return Case("cfg3-200x440x170", pb, part, IfaceSpace(((1, 1), (1, 1), (1, 1)), split), 1.0)
+
+
+def _random_splits(part, rng):
+    """2, 4 or 8 patches per interface, split (2x1), (2x2) or (4x2) with the
+    larger count along the longer tangential side; interfaces in the order of
+    the interface-space override (x-normal, y-normal, z-normal, each in
+    increasing lower-subdomain id)."""
     ndx, ndy, ndz = part.nd
     nif = (ndx - 1) * ndy * ndz + ndx * (ndy - 1) * ndz + ndx * ndy * (ndz - 1)
-    rng = np.random.default_rng(patch_seed)
     choice = rng.choice([2, 4, 8], size=nif)
-    # (na, nb) along the interface's (lower, higher) tangential axis; the larger
-    # count goes along the longer side, decided per interface from the cuts.
     split = np.zeros((nif, 2), dtype=np.int32)
     t = 0
     ext = [np.diff(c) for c in part.cuts]
@@ -255,14 +261,35 @@ def config3(seed=0, patch_seed=3):
         for sz in range(counts[2]):
             for sy in range(counts[1]):
                 for sx in range(counts[0]):
-                    s = (sx, sy, sz)
-                    la, lb = ext[a][s[a]], ext[b][s[b]]
-                    c = choice[t]
-                    big, small = {2: (2, 1), 4: (2, 2), 8: (4, 2)}[int(c)]
+                    sxyz = (sx, sy, sz)
+                    la, lb = ext[a][sxyz[a]], ext[b][sxyz[b]]
+                    big, small = {2: (2, 1), 4: (2, 2), 8: (4, 2)}[int(choice[t])]
                     split[t] = (big, small) if la >= lb else (small, big)
                     t += 1
-    # the iteration above is z-slowest, i.e. increasing lower-subdomain id.
-    return Case("cfg3-200x440x170", pb, part, IfaceSpace(((1, 1), (1, 1), (1, 1)), split), 1.0)
+    return split
+
+
+def config3_block(seed=0, patch_seed=3):
+    """A 70x70x19 block with the ragged 200x440x170 workload's structure, small
+    enough for the whole oracle: cuts 15/20/20/15 along x and y and 3/5/5/3/3
+    along z (4x4x5 = 80 subdomains of eight shapes, 15x15x3 to 20x20x5),
+    2, 4 or 8 patches per interface drawn with default_rng(patch_seed), the
+    same Gaussian log-k (std 3, correlation lengths 20x20x3 cells), cells of
+    20x10x2 ft, a five-spot of well columns and the pin in the far corner."""
+    nx, ny, nz = 70, 70, 19
+    y = grf((nx, ny, nz), 3.0, (20.0, 20.0, 3.0), seed)
+    kx = np.exp(y)
+    q = np.zeros(nx * ny * nz)
+    for k in range(nz):
+        q[_cell(nx // 2, ny // 2, k, nx, ny)] += 1.0 / nz
+        for (i, j) in ((0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1)):
+            q[_cell(i, j, k, nx, ny)] -= 1.0 / (4 * nz)
+    pin = _cell(nx - 1, ny - 1, nz - 1, nx, ny)
+    pb = Problem(nx, ny, nz, 20.0, 10.0, 2.0, kx, kx.copy(), 0.1 * kx, q, pin=pin)
+    part = Partition(ragged_cuts(nx, [15, 20, 20, 15]), ragged_cuts(ny, [15, 20, 20, 15]),
+                     ragged_cuts(nz, [3, 5, 5, 3, 3]))
+    split = _random_splits(part, np.random.default_rng(patch_seed))
+    return Case("cfg3-block-70x70x19", pb, part, IfaceSpace(((1, 1), (1, 1), (1, 1)), split), 1.0)
 
 
 def small_case(dims=(8, 6, 4), nd=(2, 2, 2), split=((1, 1), (1, 1), (1, 1)), seed=0, std=1.0,

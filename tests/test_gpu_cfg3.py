@@ -147,3 +147,38 @@ def test_cfg3_fp32_form(case3):
           f"{worst:.2e} of the largest face flux", flush=True)
     assert worst < 1e-8
     m.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cfg3_shaped_block_against_the_whole_oracle(precision):
+    """A 70x70x19 block with the ragged workload's structure (eight subdomain
+    shapes in one launch, 2-8 patches per interface, log-k std 3), small enough
+    for the whole oracle: every subdomain's MBFs and flux blocks, the
+    interface system, pi, p and U, in FP64 and in FP32 with refinement."""
+    import paper_2103_08513_amd as lib
+    from mrcm_inputs import config3_block
+    from oracle.mrcm import mrcm_solve
+    from oracle.norms import rel_l2
+    case = config3_block()
+    pb = case.problem
+    ref = mrcm_solve(case, processes=8)
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision)
+    p, U, X = m.solve(_dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q), refine=1)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for l in range(len(ref.systems)):
+        Xg = m.copy_mbfs(l)
+        Xo = ref.X[l][m.local_order(l)]
+        for c in range(Xo.shape[1]):
+            worst = max(worst, _maxrel(Xg[:, c], Xo[:, c]))
+        F, Fb, _ = m.copy_flux(l)
+        worst = max(worst, _maxrel(F, ref.F[l]), _maxrel(Fb, ref.Fb[l]))
+    A, b = m.copy_interface()
+    e_a, e_b = _maxrel(A, ref.A_int.toarray()), _maxrel(b, ref.b_int)
+    ep, eu, epi = rel_l2(p.cpu().numpy(), ref.p), rel_l2(U.cpu().numpy(), ref.U), rel_l2(X.cpu().numpy(), ref.pi)
+    print(f"70x70x19 ragged block, precision {precision}: MBF/flux blocks {worst:.2e}, A_int {e_a:.2e}, "
+          f"b_int {e_b:.2e}, pi {epi:.2e}, p {ep:.2e}, U {eu:.2e}", flush=True)
+    assert worst < 1e-9
+    assert e_a < 1e-10 and e_b < 1e-10
+    assert epi < 1e-8 and ep < 1e-8 and eu < 1e-8
+    m.close()
