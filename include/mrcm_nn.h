@@ -64,6 +64,21 @@ mrcm_status mrcm_mse(const float *y, const float *t, float *dy, double *loss, do
                      void *stream);
 
 /*
+ * mrcm_mse without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight training or serving
+ * loops, harnesses that forbid hipMalloc).  The same kernels and the same
+ * result, bitwise, as mrcm_mse; the partial sums live in the library's own
+ * static array of 1024 doubles (8 KiB) per GPU, which every call on that GPU
+ * shares and which the GPU keeps until the process ends.  Calls that overlap
+ * on one GPU (on different streams, or from different threads) race on that
+ * array; calls in stream order do not.  Allocates nothing: no hipMalloc,
+ * hipFree or allocating library routine.  Errors: MRCM_EINVAL (null pointer,
+ * n <= 0, or n > MRCM_MSE_NOALLOC_MAX_N), MRCM_EHIP.
+ */
+#define MRCM_MSE_NOALLOC_MAX_N ((int64_t)1 << 40)
+mrcm_status mrcm_mse_noalloc(const float *y, const float *t, float *dy, double *loss, int64_t n, void *stream);
+
+/*
  * One Adam step (Kingma and Ba, 2015) on n parameters at step t >= 1:
  * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
  * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).

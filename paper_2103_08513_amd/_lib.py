@@ -19,7 +19,8 @@ EXPORTS = [
     "mrcm_status_string", "mrcm_last_error", "mrcm_profile_enable", "mrcm_profile_reset",
     "mrcm_profile_get", "mrcm_autotune", "mrcm_graph_capture", "mrcm_graph_launch", "mrcm_graph_check", "mrcm_graph_destroy",
     # mrcm_nn.h
-    "mrcm_conv3d_max_channels", "mrcm_conv3d_forward", "mrcm_conv3d_backward", "mrcm_mse", "mrcm_adam_step",
+    "mrcm_conv3d_max_channels", "mrcm_conv3d_forward", "mrcm_conv3d_backward", "mrcm_mse", "mrcm_mse_noalloc",
+    "mrcm_adam_step",
     "mrcm_nn_features", "mrcm_nn_scatter",
 ]
 
@@ -113,6 +114,7 @@ def load(path: str = LIB_PATH):
         "mrcm_conv3d_forward": ([c_void_p] * 5 + [c_int32] * 8 + [c_void_p], c_int32),
         "mrcm_conv3d_backward": ([c_void_p] * 8 + [c_int32] * 7 + [c_void_p], c_int32),
         "mrcm_mse": ([c_void_p] * 5 + [c_int64, c_void_p], c_int32),
+        "mrcm_mse_noalloc": ([c_void_p] * 4 + [c_int64, c_void_p], c_int32),
         "mrcm_adam_step": ([c_void_p] * 4 + [c_int32, c_int32, c_float, c_float, c_float, c_float, c_void_p],
                            c_int32),
         "mrcm_nn_features": ([c_void_p, P(c_int32), c_int32, c_void_p, c_void_p, c_void_p], c_int32),

@@ -1505,6 +1505,16 @@ mrcm_status mrcm_mse(const float *y, const float *t, float *dy, double *loss, do
   return MRCM_OK;
 }
 
+mrcm_status mrcm_mse_noalloc(const float *y, const float *t, float *dy, double *loss, int64_t n, void *stream) {
+  if (!y || !t || !dy || !loss) return fail(MRCM_EINVAL, "null argument");
+  if (n <= 0) return fail(MRCM_EINVAL, "n must be positive");
+  if (n > MRCM_MSE_NOALLOC_MAX_N)
+    return fail(MRCM_EINVAL, "n exceeds " + std::to_string(MRCM_MSE_NOALLOC_MAX_N) +
+                                 ", the largest this entry point takes");
+  HIP_TRY(launch_mse_static(y, t, dy, loss, n, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
 mrcm_status mrcm_adam_step(float *p, const float *g, float *m, float *v, int32_t n, int32_t t, float lr,
                            float b1, float b2, float eps, void *stream) {
   if (!p || !g || !m || !v) return fail(MRCM_EINVAL, "null argument");

@@ -52,7 +52,15 @@ hipError_t launch_conv3d(const float *x, const float *w, const float *bias, floa
 hipError_t launch_conv3d_flip(const float *w, float *wt, int Cin, int Cout, hipStream_t s);
 hipError_t launch_conv3d_wgrad(const float *x, const float *dy, float *dw, float *db, int B, int Cin, int Cout,
                                int D, int H, int W, int dil, hipStream_t s);
+// Most partial sums of the loss (one per workgroup of 256 threads).
+constexpr int kMsePartialsMax = 1024;
+// Devices for which the allocation-free entry point keeps a scratch address.
+constexpr int kMaxDevices = 64;
 int mse_partials(long long n);
+// As launch_mse, with the partial sums in the library's static per-device
+// array instead of a caller's workspace: allocates nothing.
+hipError_t launch_mse_static(const float *y, const float *t, float *dy, double *loss, long long n,
+                             hipStream_t s);
 hipError_t launch_mse(const float *y, const float *t, float *dy, double *part, double *loss, long long n,
                       hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, int t, float lr, float b1, float b2,

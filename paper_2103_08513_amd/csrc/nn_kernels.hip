@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "device_common.h"
 #include "launch.h"
@@ -277,7 +278,7 @@ hipError_t launch_conv3d_wgrad(const float *x, const float *dy, float *dw, float
   return hipGetLastError();
 }
 
-int mse_partials(long long n) { return (int)std::min<long long>(1024, (n + 255) / 256); }
+int mse_partials(long long n) { return (int)std::min<long long>(kMsePartialsMax, (n + 255) / 256); }
 
 hipError_t launch_mse(const float *y, const float *t, float *dy, double *part, double *loss, long long n,
                       hipStream_t s) {
@@ -285,6 +286,38 @@ hipError_t launch_mse(const float *y, const float *t, float *dy, double *part, d
   hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, y, t, dy, part, n);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, part, nb, loss);
   return hipGetLastError();
+}
+
+// Partial sums of the loss for callers that cannot allocate: one array per
+// GPU, for the life of the process.  Its address on each device comes from
+// hipGetSymbolAddress (the name itself is only a host-side stand-in).
+static __device__ __align__(256) double scratch[kMsePartialsMax];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t launch_mse_static(const float *y, const float *t, float *dy, double *loss, long long n,
+                             hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  double *part = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void *addr = nullptr;
+      e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return e;
+      g_scratch_ptr[dev] = static_cast<double *>(addr);
+    }
+    part = g_scratch_ptr[dev];
+  }
+  // every partial the sum reads is written by this call's first kernel, so
+  // nothing in the array needs clearing
+  return launch_mse(y, t, dy, part, loss, n, s);
 }
 
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, int t, float lr, float b1, float b2,
