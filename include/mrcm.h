@@ -240,22 +240,61 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *problem, const mrcm_partition *p
  *   U-row: sum_s sigma^s_i sum_j (Fb^s[i,P_j] pi^p_j + Fb^s[i,U_j] pi^u_j)
  *          - (sum_s sum_{f in i} A_f beta^s_f) pi^u_i = -sum_s sigma^s_i Fb^s[i,0]
  * Each entry receives at most two contributions, so the result is bitwise
- * reproducible.  The matrix is stored as a band after a reverse Cuthill-McKee
- * ordering of the patches.  *out: NULL to create, or a handle from an earlier
- * call on the same mbfs geometry (reused without allocation).
+ * reproducible.  The entries go straight into the frontal matrices of the
+ * multifrontal factorisation (nested dissection of the patch graph: planes
+ * of interfaces cut boxes of subdomains in two, recursively); the first call
+ * on a handle builds that plan and allocates the fronts.  *out: NULL to
+ * create, or a handle from an earlier call on the same mbfs handle (reused
+ * without allocation).  Errors: MRCM_EUNSUPPORTED (a front beyond the
+ * sweep kernels' shared memory), MRCM_ENOMEM, MRCM_EHIP.
  */
 mrcm_status mrcm_assemble_interface(const mrcm_mbfs *mbfs, void *stream, mrcm_interface **out);
 
+/* Interface solvers (InterfaceSolver of Algorithm 2; the paper factorises
+ * the interface system with a direct sparse LU). */
+enum { MRCM_IFACE_AUTO = 0,         /* the multifrontal form */
+       MRCM_IFACE_BAND = 1,         /* band LDL^T after a reverse Cuthill-McKee order (allocates its band,
+                                       2 n (2w+1) doubles, on first use; systems up to a few 10^5 unknowns) */
+       MRCM_IFACE_MULTIFRONTAL = 2  /* multifrontal LDL^T on the nested-dissection tree */ };
+
 /*
- * InterfaceSolver of Algorithm 2: solves A^int X = b^int in FP64 by band LU
- * without pivoting (the system is, up to the sign of its P-rows, symmetric
- * quasi-definite, so every ordering admits such a factorisation), followed by
- * `refine` steps of FP64 iterative refinement against the unfactored matrix.
- * X [dev] 2*N_V doubles, pi^p then pi^u.  rel_residual [host] or NULL:
- * ||b - A X|| / ||b|| after refinement.  Errors: MRCM_ESINGULAR.
+ * Solves A^int X = b^int in FP64.  With s = -1 on the pressure rows and +1 on
+ * the velocity rows, diag(s) A^int is symmetric quasi-definite, so it has an
+ * LDL^T factorisation in any symmetric order without pivoting; the factor
+ * then serves iterative refinement against the assembled (unfactored) system:
+ * X += (LDL^T)^-1 diag(s) (b - A X).
+ *  method      MRCM_IFACE_*.
+ *  rtol        > 0: refine until ||b - A X|| / ||b|| <= rtol or max_refine
+ *              steps (one stream synchronisation per step);
+ *              0: exactly max_refine steps, no synchronisation (capturable).
+ *  max_refine  0 .. 20.
+ *  X [dev]     2*N_V doubles, pi^p then pi^u.
+ *  iters [host] or NULL: refinement steps taken.
+ *  rel_residual [host] or NULL: ||b - A X|| / ||b|| of the returned X (one
+ *              more residual and a synchronisation).
+ * Errors: MRCM_EINVAL, MRCM_ESINGULAR (zero pivot), MRCM_ENOMEM (band form),
+ * MRCM_EHIP.
  */
-mrcm_status mrcm_solve_interface(mrcm_interface *iface, int32_t refine, void *stream,
-                                 double *X, double *rel_residual);
+mrcm_status mrcm_solve_interface(mrcm_interface *iface, int32_t method, double rtol, int32_t max_refine,
+                                 void *stream, double *X, int32_t *iters, double *rel_residual);
+
+/* Sizes of the interface system and its multifrontal factorisation, and the
+ * last solve's method, refinement steps and residual (-1 if not computed). */
+typedef struct {
+  int32_t n;               /* unknowns, 2 N_V */
+  int32_t nodes;           /* separators of the nested dissection */
+  int32_t levels;          /* tree height */
+  int32_t max_front;       /* largest frontal matrix */
+  int64_t front_bytes;     /* all fronts (FP64, f x f each) */
+  double factor_flops;     /* sum over separator pivots of (f - k - 1)^2 */
+  int32_t factor_launches; /* panel-step launches of the factorisation */
+  int32_t bandwidth;       /* band form: half bandwidth after the RCM order, or -1 if not built */
+  int64_t device_bytes;    /* device memory held by the handle */
+  int32_t method;          /* MRCM_IFACE_BAND or MRCM_IFACE_MULTIFRONTAL */
+  int32_t refine_iters;
+  double rel_residual;
+} mrcm_interface_info;
+mrcm_status mrcm_interface_query(const mrcm_interface *iface, mrcm_interface_info *info /* [host] */);
 
 /*
  * Loop 2 of Algorithm 2 by the combination (2.23): p^l = X_l [1, pi^p_{I^l}, pi^u_{I^l}].
@@ -283,9 +322,12 @@ mrcm_status mrcm_copy_mbfs(const mrcm_mbfs *mbfs, int32_t l, double *X);
 mrcm_status mrcm_copy_flux(const mrcm_mbfs *mbfs, int32_t l, double *F, double *Fb, double *SAb);
 mrcm_status mrcm_copy_factor(const mrcm_mbfs *mbfs, int32_t l, double *Lband);
 
-/* Interface system introspection: n = 2*N_V, bandwidth of the stored band.
- * mrcm_copy_interface: the assembled (unfactored) matrix as dense row-major
- * [n][n] in the natural unknown order (pi^p then pi^u), and b [n]. */
+/* Interface system introspection: n = 2*N_V and the band form's half
+ * bandwidth (-1 until the band form is used).  mrcm_copy_interface: the
+ * assembled (unfactored) matrix as dense row-major [n][n] in the natural
+ * unknown order (pi^p then pi^u), and b [n], formed on the device from the
+ * flux blocks exactly as the solvers see them (allocates n^2 doubles for the
+ * duration of the call). */
 mrcm_status mrcm_interface_dims(const mrcm_interface *iface, int32_t *n, int32_t *bandwidth);
 mrcm_status mrcm_copy_interface(const mrcm_interface *iface, double *A, double *b);
 

@@ -14,13 +14,19 @@ from ctypes import byref, c_double, c_int32, c_void_p
 import numpy as np
 
 from . import _lib
-from ._lib import CInfo, CIfaceSpace, COptions, CPartition, CProblem, CSubInfo, MRCMError
+from ._lib import CIfaceInfo, CInfo, CIfaceSpace, COptions, CPartition, CProblem, CSubInfo, MRCMError
 
 FP64 = 0
 FP32_IR = 1
 PCG = 2
 
-__all__ = ["MRCM", "MRCMError", "FP64", "FP32_IR", "PCG", "build_mbfs", "assemble_interface",
+# interface solvers (mrcm_solve_interface)
+IFACE_AUTO = 0
+IFACE_BAND = 1
+IFACE_MULTIFRONTAL = 2
+
+__all__ = ["MRCM", "MRCMError", "FP64", "FP32_IR", "PCG", "IFACE_AUTO", "IFACE_BAND", "IFACE_MULTIFRONTAL",
+           "build_mbfs", "assemble_interface",
            "solve_interface", "reconstruct", "library"]
 
 
@@ -192,10 +198,14 @@ class MRCM:
         _lib.check(code, "mrcm_assemble_interface")
         return self
 
-    def solve_interface(self, X=None, refine=0, stream=None, residual=False):
-        """Interface solve; with residual=True the relative residual of the
-        unfactored system is also computed (one more band product and a
-        stream synchronisation) and kept in ``interface_residual``."""
+    def solve_interface(self, X=None, refine=0, stream=None, residual=False, method=IFACE_AUTO, rtol=0.0):
+        """Interface solve (mrcm_solve_interface): ``method`` one of IFACE_*;
+        ``refine`` refinement steps at most (exactly that many when rtol is
+        0); ``rtol`` > 0 stops refining once the relative residual is below
+        it.  With residual=True the relative residual of the returned X is
+        also computed (one more residual and a stream synchronisation) and
+        kept in ``interface_residual``; ``interface_iters`` holds the
+        refinement steps taken."""
         import torch
         n = self._n_unknowns()
         if not self._iface.value:
@@ -203,12 +213,19 @@ class MRCM:
         if X is None:
             X = torch.empty(n, dtype=torch.float64, device=self.device)
         res = c_double(0.0)
-        code = self.lib.mrcm_solve_interface(self._iface, int(refine), _stream_ptr(stream),
-                                             _dev_ptr(X, "X", n, self.device) if n > 0 else None,
+        its = c_int32(0)
+        code = self.lib.mrcm_solve_interface(self._iface, int(method), float(rtol), int(refine), _stream_ptr(stream),
+                                             _dev_ptr(X, "X", n, self.device) if n > 0 else None, byref(its),
                                              byref(res) if residual else None)
         _lib.check(code, "mrcm_solve_interface")
         self.interface_residual = res.value if residual else None
+        self.interface_iters = its.value
         return X
+
+    def interface_info(self):
+        inf = CIfaceInfo()
+        _lib.check(self.lib.mrcm_interface_query(self._iface, byref(inf)), "mrcm_interface_query")
+        return inf
 
     def reconstruct(self, X, p=None, U=None, stream=None):
         import torch
@@ -226,11 +243,11 @@ class MRCM:
         _lib.check(code, "mrcm_reconstruct")
         return p, U.view(6, N)
 
-    def solve(self, kx, ky, kz, q, refine=0, stream=None):
+    def solve(self, kx, ky, kz, q, refine=0, stream=None, method=IFACE_AUTO):
         """Whole MRCM: MBFs, interface assembly and solve, reconstruction."""
         self.build_mbfs(kx, ky, kz, q, stream)
         self.assemble_interface(stream)
-        X = self.solve_interface(refine=refine, stream=stream)
+        X = self.solve_interface(refine=refine, stream=stream, method=method)
         return self.reconstruct(X, stream=stream) + (X,)
 
     def autotune(self, kx, ky, kz, q, stream=None):
@@ -372,8 +389,8 @@ def assemble_interface(model: MRCM, stream=None):
     return model.assemble_interface(stream)
 
 
-def solve_interface(model: MRCM, refine=0, stream=None):
-    return model.solve_interface(refine=refine, stream=stream)
+def solve_interface(model: MRCM, refine=0, stream=None, method=IFACE_AUTO, rtol=0.0):
+    return model.solve_interface(refine=refine, stream=stream, method=method, rtol=rtol)
 
 
 def reconstruct(model: MRCM, X, stream=None):

@@ -15,7 +15,7 @@ STATUS = {0: "MRCM_OK", -1: "MRCM_EINVAL", -2: "MRCM_ENOMEM", -3: "MRCM_ENOTSPD"
 EXPORTS = [
     "mrcm_build_mbfs", "mrcm_assemble_interface", "mrcm_solve_interface", "mrcm_reconstruct",
     "mrcm_query", "mrcm_get_subdomain", "mrcm_copy_mbfs", "mrcm_copy_flux", "mrcm_copy_factor",
-    "mrcm_interface_dims", "mrcm_copy_interface", "mrcm_mbfs_destroy", "mrcm_interface_destroy",
+    "mrcm_interface_dims", "mrcm_copy_interface", "mrcm_interface_query", "mrcm_mbfs_destroy", "mrcm_interface_destroy",
     "mrcm_status_string", "mrcm_last_error", "mrcm_profile_enable", "mrcm_profile_reset",
     "mrcm_profile_get", "mrcm_autotune", "mrcm_graph_capture", "mrcm_graph_launch", "mrcm_graph_check", "mrcm_graph_destroy",
     # mrcm_nn.h
@@ -50,6 +50,13 @@ class COptions(ctypes.Structure):
                 ("ir_max_iter", c_int32), ("fp64_refine", c_int32), ("pcg_max_iter", c_int32),
                 ("pcg_x0", ctypes.c_void_p), ("pcg_x0_scale", c_int32), ("solve_tiles", c_int32),
                 ("solve_group", c_int32)]
+
+
+class CIfaceInfo(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("nodes", c_int32), ("levels", c_int32), ("max_front", c_int32),
+                ("front_bytes", c_int64), ("factor_flops", c_double), ("factor_launches", c_int32),
+                ("bandwidth", c_int32), ("device_bytes", c_int64), ("method", c_int32),
+                ("refine_iters", c_int32), ("rel_residual", c_double)]
 
 
 class CInfo(ctypes.Structure):
@@ -87,7 +94,9 @@ def load(path: str = LIB_PATH):
         "mrcm_build_mbfs": ([P(CProblem), P(CPartition), P(CIfaceSpace), P(COptions), c_void_p,
                              P(c_void_p)], c_int32),
         "mrcm_assemble_interface": ([c_void_p, c_void_p, P(c_void_p)], c_int32),
-        "mrcm_solve_interface": ([c_void_p, c_int32, c_void_p, c_void_p, P(c_double)], c_int32),
+        "mrcm_solve_interface": ([c_void_p, c_int32, c_double, c_int32, c_void_p, c_void_p, P(c_int32),
+                                  P(c_double)], c_int32),
+        "mrcm_interface_query": ([c_void_p, P(CIfaceInfo)], c_int32),
         "mrcm_reconstruct": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
         "mrcm_query": ([c_void_p, P(CInfo)], c_int32),
         "mrcm_get_subdomain": ([c_void_p, c_int32, P(CSubInfo)], c_int32),

@@ -16,6 +16,7 @@
 #include "../../include/mrcm_nn.h"
 #include "internal.h"
 #include "launch.h"
+#include "nd_plan.h"
 
 using namespace mrcm;
 
@@ -565,15 +566,26 @@ struct mrcm_mbfs {
 
 struct mrcm_interface {
   const mrcm_mbfs *mb = nullptr;
-  int nv = 0, n = 0, w = 0;
+  int nv = 0, n = 0;
+  // multifrontal form (nested dissection of the patch graph), always built
+  NdPlan plan;
+  MfDevPlan dp;
+  double *fronts = nullptr, *minv = nullptr, *zbuf = nullptr;
+  double *xv = nullptr, *rv = nullptr, *bv = nullptr, *dv = nullptr;
+  bool fronts_fresh = false;  // fronts hold the assembled entries (not yet factored)
+  // band form, built on its first use
+  int w = -1;
   std::vector<int> pos;
   int *d_pos = nullptr;
   double *AB = nullptr, *AB0 = nullptr;
   double *b = nullptr, *b0 = nullptr;
-  double *inv = nullptr, *r = nullptr, *y = nullptr, *scalar = nullptr;
+  double *inv = nullptr, *r = nullptr, *y = nullptr;
+  double *scalar = nullptr;
   DevStatus *st = nullptr;
   hipStream_t stream = nullptr;
   int64_t bytes = 0;
+  int last_method = 0, last_iters = 0;
+  double last_residual = -1.0;
 };
 
 namespace {
@@ -594,10 +606,66 @@ void free_mbfs(mrcm_mbfs *h) {
 
 void free_iface(mrcm_interface *h) {
   if (!h) return;
-  void *ptrs[] = {h->d_pos, h->AB, h->AB0, h->b, h->b0, h->inv, h->r, h->y, h->scalar, h->st};
+  void *ptrs[] = {h->d_pos, h->AB, h->AB0, h->b, h->b0, h->inv, h->r, h->y, h->scalar, h->st,
+                  h->fronts, h->minv, h->zbuf, h->xv, h->rv, h->bv, h->dv,
+                  h->dp.nodes, h->dp.idx, h->dp.map, h->dp.level_nodes, h->dp.step_blocks, h->dp.pair_off,
+                  h->dp.sub_pair_off, h->dp.pair_ld, h->dp.pinfo};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
+}
+
+// The multifrontal plan of the handle's interface system, its device copy and
+// the fronts, factor and vector storage.
+mrcm_status init_mf(mrcm_interface *h) {
+  const mrcm_mbfs *mb = h->mb;
+  const HostGeom &G = mb->G;
+  const int nd[3] = {(int)G.cuts[0].size() - 1, (int)G.cuts[1].size() - 1, (int)G.cuts[2].size() - 1};
+  const std::string err = build_nd_plan(nd, G.subs, G.ifcs, G.patches, G.n_patch, h->plan);
+  if (!err.empty()) return fail(MRCM_EUNSUPPORTED, err);
+  const NdPlan &P = h->plan;
+  std::vector<int4> pinfo(G.n_patch);
+  for (const IfaceDesc &I : G.ifcs)
+    for (int k = 0; k < I.na * I.nb; ++k)
+      pinfo[I.p0 + k] = make_int4((int)(&I - G.ifcs.data()), G.subs[I.lo_sub].face_p0[2 * I.d + 1] + k,
+                                  G.subs[I.hi_sub].face_p0[2 * I.d] + k, 0);
+  HIP_TRY(mf_init_kernels());
+  MfDevPlan &dp = h->dp;
+  dp.n_nodes = (int)P.nodes.size();
+  dp.front_doubles = P.front_doubles;
+  HIP_TRY(upload(&dp.nodes, P.nodes));
+  HIP_TRY(upload(&dp.idx, P.idx));
+  HIP_TRY(upload(&dp.map, P.map));
+  HIP_TRY(upload(&dp.level_nodes, P.level_nodes));
+  HIP_TRY(upload(&dp.step_blocks, P.step_blocks));
+  HIP_TRY(upload(&dp.pair_off, P.pair_off));
+  HIP_TRY(upload(&dp.sub_pair_off, P.sub_pair_off));
+  HIP_TRY(upload(&dp.pair_ld, P.pair_ld));
+  HIP_TRY(upload(&dp.pinfo, pinfo));
+  const bool ok = dev_alloc(&h->fronts, (size_t)P.front_doubles) == hipSuccess &&
+                  dev_alloc(&h->minv, (size_t)P.inv_doubles) == hipSuccess &&
+                  dev_alloc(&h->zbuf, (size_t)P.z_doubles) == hipSuccess && dev_alloc(&h->xv, h->n) == hipSuccess &&
+                  dev_alloc(&h->rv, h->n) == hipSuccess && dev_alloc(&h->bv, h->n) == hipSuccess &&
+                  dev_alloc(&h->dv, h->n) == hipSuccess;
+  if (!ok) return fail(MRCM_ENOMEM, "device allocation of the interface fronts failed");
+  h->bytes += 8 * (P.front_doubles + P.inv_doubles + P.z_doubles + 4LL * h->n) +
+              (int64_t)sizeof(MfNode) * P.nodes.size() + 4LL * (P.idx.size() + P.map.size()) +
+              12LL * (int64_t)P.pair_off.size() + 8LL * (int64_t)P.step_blocks.size();
+  return MRCM_OK;
+}
+
+// The band form: reverse Cuthill-McKee order, band storage and work vectors.
+mrcm_status init_band(mrcm_interface *h) {
+  rcm_order(h->mb->G, h->pos, h->w);
+  const int64_t band = (int64_t)h->n * (2 * h->w + 1);
+  const bool ok = upload(&h->d_pos, h->pos) == hipSuccess && dev_alloc(&h->AB, band) == hipSuccess &&
+                  dev_alloc(&h->AB0, band) == hipSuccess && dev_alloc(&h->b, h->n) == hipSuccess &&
+                  dev_alloc(&h->b0, h->n) == hipSuccess &&
+                  dev_alloc(&h->inv, (int64_t)ldl_inv_size(h->n)) == hipSuccess &&
+                  dev_alloc(&h->y, h->n) == hipSuccess && dev_alloc(&h->r, h->n) == hipSuccess;
+  if (!ok) return fail(MRCM_ENOMEM, "device allocation of the interface band failed");
+  h->bytes += 2 * band * 8 + 4 * (int64_t)h->n * 8 + (int64_t)ldl_inv_size(h->n) * 8;
+  return MRCM_OK;
 }
 
 mrcm_status alloc_mbfs(mrcm_mbfs *h) {
@@ -743,7 +811,7 @@ mrcm_status read_status(DevStatus *st, hipStream_t s, const char *what) {
     snprintf(buf, sizeof buf, "%s: permeability %.6g at cell %d is not positive and finite", what,
              hs.value, hs.where);
   else if (hs.code == MRCM_ESINGULAR)
-    snprintf(buf, sizeof buf, "%s: zero pivot %.6g at interface unknown %d", what, hs.value, hs.where);
+    snprintf(buf, sizeof buf, "%s: zero pivot in the interface factorisation (block or node %d)", what, hs.where);
   else
     snprintf(buf, sizeof buf, "%s: device status %d", what, hs.code);
   return fail((mrcm_status)hs.code, buf);
@@ -1056,35 +1124,28 @@ mrcm_status mrcm_assemble_interface(const mrcm_mbfs *mb, void *stream, mrcm_inte
     h->mb = mb;
     h->nv = mb->G.n_patch;
     h->n = 2 * h->nv;
-    rcm_order(mb->G, h->pos, h->w);
-    if (h->nv == 0) h->w = 0;
-    const int64_t band = (int64_t)h->n * (2 * h->w + 1);
-    bool ok = upload(&h->d_pos, h->pos) == hipSuccess && dev_alloc(&h->AB, band) == hipSuccess &&
-              dev_alloc(&h->AB0, band) == hipSuccess && dev_alloc(&h->b, h->n) == hipSuccess &&
-              dev_alloc(&h->b0, h->n) == hipSuccess && dev_alloc(&h->inv, (int64_t)ldl_inv_size(h->n)) == hipSuccess &&
-              dev_alloc(&h->y, h->n) == hipSuccess &&
-              dev_alloc(&h->r, h->n) == hipSuccess && dev_alloc(&h->scalar, 4) == hipSuccess &&
-              hipMalloc((void **)&h->st, sizeof(DevStatus)) == hipSuccess;
-    if (!ok) {
+    mrcm_status st = MRCM_OK;
+    if (dev_alloc(&h->scalar, 4) != hipSuccess || hipMalloc((void **)&h->st, sizeof(DevStatus)) != hipSuccess)
+      st = fail(MRCM_ENOMEM, "device allocation of the interface status failed");
+    if (st == MRCM_OK && h->nv > 0) st = init_mf(h);
+    if (st != MRCM_OK) {
       free_iface(h);
-      return fail(MRCM_ENOMEM, "device allocation of the interface system failed");
+      return st;
     }
-    h->bytes = 2 * band * 8 + 5 * (int64_t)h->n * 8 + (int64_t)ldl_inv_size(h->n) * 8;
   }
   h->stream = s;
-  const int64_t band = (int64_t)h->n * (2 * h->w + 1);
   auto bail = [&](mrcm_status e) {
     if (created) free_iface(h);
     return e;
   };
-  hipError_t e;
-  {
+  hipError_t e = hipSuccess;
+  if (h->nv > 0) {
     Stage t(MRCM_STAGE_ASSEMBLE, s);
-    e = launch_fill(h->AB0, band, 0.0, s);
-    if (e == hipSuccess) e = launch_fill(h->b0, h->n, 0.0, s);
-    if (e == hipSuccess && h->nv > 0)
-      e = launch_iface_scatter(mb->g, mb->n_sub, mb->d_patches, h->d_pos, mb->F, mb->Fb, mb->SAb,
-                               h->AB0, h->w, h->b0, s);
+    e = launch_mf_assemble(mb->g, mb->n_sub, mb->d_patches, mb->F, mb->Fb, mb->SAb, h->dp, h->fronts, s);
+    if (e == hipSuccess)
+      e = launch_mf_residual(mb->g, mb->d_patches, mb->F, mb->Fb, mb->SAb, h->dp.pinfo, h->nv, nullptr, h->bv,
+                             nullptr, s);
+    h->fronts_fresh = true;
   }
   if (e == hipSuccess && !g_capturing) e = hipStreamSynchronize(s);
   profile_flush();
@@ -1093,30 +1154,97 @@ mrcm_status mrcm_assemble_interface(const mrcm_mbfs *mb, void *stream, mrcm_inte
   return MRCM_OK;
 }
 
-mrcm_status mrcm_solve_interface(mrcm_interface *h, int32_t refine, void *stream, double *X,
-                                 double *rel_residual) {
-  if (!h) return fail(MRCM_EINVAL, "null interface handle");
-  if (h->n > 0 && !X) return fail(MRCM_EINVAL, "X is null");
-  if (refine < 0 || refine > 10) return fail(MRCM_EINVAL, "refine must be in [0, 10]");
-  hipStream_t s = (hipStream_t)stream;
-  h->stream = s;
-  if (h->n == 0) {
-    if (rel_residual) *rel_residual = 0.0;
-    return MRCM_OK;
-  }
+namespace {
+
+// relative residual ||r|| / ||b|| from two device vectors (synchronises)
+mrcm_status rel_norm(mrcm_interface *h, const double *r, const double *b, hipStream_t s, double &out) {
+  HIP_TRY(launch_norm2(r, h->n, h->scalar, s));
+  HIP_TRY(launch_norm2(b, h->n, h->scalar + 1, s));
+  double v[2];
+  HIP_TRY(hipMemcpyAsync(v, h->scalar, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out = v[1] > 0.0 ? std::sqrt(v[0] / v[1]) : std::sqrt(v[0]);
+  return MRCM_OK;
+}
+
+mrcm_status solve_mf(mrcm_interface *h, double rtol, int max_refine, hipStream_t s, double *X, int &iters,
+                     double *rel_residual) {
+  const mrcm_mbfs *mb = h->mb;
   HIP_TRY(launch_reset_status(h->st, s));
   {
-    // factor a sign-flipped copy of the assembled system (the assembled one
-    // stays for refinement and the residual)
     Stage t(MRCM_STAGE_LU, s);
-    // the factorisation also carries out the forward substitution into y
+    // the fronts are consumed by the factorisation: a second solve of the
+    // same assembly scatters the entries again
+    if (!h->fronts_fresh)
+      HIP_TRY(launch_mf_assemble(mb->g, mb->n_sub, mb->d_patches, mb->F, mb->Fb, mb->SAb, h->dp, h->fronts, s));
+    HIP_TRY(launch_mf_factor(h->plan, h->dp, h->fronts, h->minv, h->st, s));
+    h->fronts_fresh = false;
+  }
+  iters = 0;
+  {
+    Stage t(MRCM_STAGE_SWEEP, s);
+    HIP_TRY(launch_mf_solve(h->plan, h->dp, h->fronts, h->minv, h->zbuf, h->bv, h->xv, s));
+    for (; iters < max_refine; ++iters) {
+      HIP_TRY(launch_mf_residual(mb->g, mb->d_patches, mb->F, mb->Fb, mb->SAb, h->dp.pinfo, h->nv, h->xv, h->rv,
+                                 nullptr, s));
+      if (rtol > 0.0 && !g_capturing) {
+        double rel = 0.0;
+        mrcm_status st = rel_norm(h, h->rv, h->bv, s, rel);
+        if (st != MRCM_OK) return st;
+        if (rel <= rtol) break;
+      }
+      HIP_TRY(launch_mf_solve(h->plan, h->dp, h->fronts, h->minv, h->zbuf, h->rv, h->dv, s));
+      HIP_TRY(launch_axpy(h->xv, h->dv, h->n, s));
+    }
+    HIP_TRY(launch_mf_deinterleave(h->xv, h->nv, X, s));
+  }
+  mrcm_status st = read_status(h->st, s, "mrcm_solve_interface");
+  profile_flush();
+  if (st != MRCM_OK) return st;
+  if (rel_residual) {
+    HIP_TRY(launch_mf_residual(mb->g, mb->d_patches, mb->F, mb->Fb, mb->SAb, h->dp.pinfo, h->nv, h->xv, h->rv,
+                               nullptr, s));
+    st = rel_norm(h, h->rv, h->bv, s, *rel_residual);
+  }
+  return st;
+}
+
+mrcm_status solve_band(mrcm_interface *h, double rtol, int max_refine, hipStream_t s, double *X, int &iters,
+                       double *rel_residual) {
+  const mrcm_mbfs *mb = h->mb;
+  if (h->w < 0) {
+    if (g_capturing) return fail(MRCM_EUNSUPPORTED, "the band form allocates on its first use: not under capture");
+    mrcm_status st = init_band(h);
+    if (st != MRCM_OK) return st;
+  }
+  const int64_t band = (int64_t)h->n * (2 * h->w + 1);
+  HIP_TRY(launch_reset_status(h->st, s));
+  {
+    Stage t(MRCM_STAGE_ASSEMBLE, s);
+    HIP_TRY(launch_fill(h->AB0, band, 0.0, s));
+    HIP_TRY(launch_fill(h->b0, h->n, 0.0, s));
+    HIP_TRY(launch_iface_scatter(mb->g, mb->n_sub, mb->d_patches, h->d_pos, mb->F, mb->Fb, mb->SAb, h->AB0, h->w,
+                                 h->b0, s));
+  }
+  {
+    // factor a sign-flipped copy of the assembled system (the assembled one
+    // stays for refinement and the residual); the factorisation also carries
+    // out the forward substitution into y
+    Stage t(MRCM_STAGE_LU, s);
     HIP_TRY(launch_band_ldl(h->AB0, h->AB, h->b0, h->b, h->y, h->n, h->w, h->inv, h->st, s));
   }
+  iters = 0;
   {
     Stage t(MRCM_STAGE_SWEEP, s);
     HIP_TRY(launch_lu_sweep(h->AB, h->inv, h->n, h->w, h->y, 1, s));
-    for (int it = 0; it < refine; ++it) {
+    for (; iters < max_refine; ++iters) {
       HIP_TRY(launch_band_residual(h->AB0, h->n, h->w, h->y, h->b0, h->r, 1, s));
+      if (rtol > 0.0 && !g_capturing) {
+        double rel = 0.0;
+        mrcm_status st = rel_norm(h, h->r, h->b0, s, rel);
+        if (st != MRCM_OK) return st;
+        if (rel <= rtol) break;
+      }
       HIP_TRY(launch_lu_sweep(h->AB, h->inv, h->n, h->w, h->r, 0, s));
       HIP_TRY(launch_lu_sweep(h->AB, h->inv, h->n, h->w, h->r, 1, s));
       HIP_TRY(launch_axpy(h->y, h->r, h->n, s));
@@ -1128,13 +1256,59 @@ mrcm_status mrcm_solve_interface(mrcm_interface *h, int32_t refine, void *stream
   if (st != MRCM_OK) return st;
   if (rel_residual) {
     HIP_TRY(launch_band_residual(h->AB0, h->n, h->w, h->y, h->b0, h->r, 0, s));
-    HIP_TRY(launch_norm2(h->r, h->n, h->scalar, s));
-    HIP_TRY(launch_norm2(h->b0, h->n, h->scalar + 1, s));
-    double v[2];
-    HIP_TRY(hipMemcpyAsync(v, h->scalar, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    *rel_residual = v[1] > 0.0 ? std::sqrt(v[0] / v[1]) : std::sqrt(v[0]);
+    st = rel_norm(h, h->r, h->b0, s, *rel_residual);
   }
+  return st;
+}
+
+}  // namespace
+
+mrcm_status mrcm_solve_interface(mrcm_interface *h, int32_t method, double rtol, int32_t max_refine, void *stream,
+                                 double *X, int32_t *iters, double *rel_residual) {
+  if (!h) return fail(MRCM_EINVAL, "null interface handle");
+  if (h->n > 0 && !X) return fail(MRCM_EINVAL, "X is null");
+  if (method < MRCM_IFACE_AUTO || method > MRCM_IFACE_MULTIFRONTAL)
+    return fail(MRCM_EINVAL, "method must be MRCM_IFACE_AUTO, MRCM_IFACE_BAND or MRCM_IFACE_MULTIFRONTAL");
+  if (!(rtol >= 0.0) || !std::isfinite(rtol)) return fail(MRCM_EINVAL, "rtol must be finite and non-negative");
+  if (max_refine < 0 || max_refine > 20) return fail(MRCM_EINVAL, "max_refine must be in [0, 20]");
+  hipStream_t s = (hipStream_t)stream;
+  h->stream = s;
+  const int m = method == MRCM_IFACE_AUTO ? MRCM_IFACE_MULTIFRONTAL : method;
+  int it = 0;
+  double res = -1.0;
+  mrcm_status st = MRCM_OK;
+  if (h->n > 0) {
+    st = (m == MRCM_IFACE_BAND) ? solve_band(h, rtol, max_refine, s, X, it, rel_residual ? &res : nullptr)
+                                : solve_mf(h, rtol, max_refine, s, X, it, rel_residual ? &res : nullptr);
+  } else {
+    res = 0.0;
+  }
+  if (st != MRCM_OK) return st;
+  h->last_method = m;
+  h->last_iters = it;
+  if (iters) *iters = it;
+  if (rel_residual) {
+    *rel_residual = res;
+    h->last_residual = res;
+  }
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_interface_query(const mrcm_interface *h, mrcm_interface_info *info) {
+  if (!h || !info) return fail(MRCM_EINVAL, "null argument");
+  const NdPlan &P = h->plan;
+  info->n = h->n;
+  info->nodes = (int32_t)P.nodes.size();
+  info->levels = P.level_off.empty() ? 0 : (int32_t)P.level_off.size() - 1;
+  info->max_front = P.max_f;
+  info->front_bytes = 8 * P.front_doubles;
+  info->factor_flops = P.flops;
+  info->factor_launches = (int32_t)P.steps.size();
+  info->bandwidth = h->w;
+  info->device_bytes = h->bytes;
+  info->method = h->last_method;
+  info->refine_iters = h->last_iters;
+  info->rel_residual = h->last_residual;
   return MRCM_OK;
 }
 
@@ -1240,26 +1414,22 @@ mrcm_status mrcm_interface_dims(const mrcm_interface *h, int32_t *n, int32_t *ba
 
 mrcm_status mrcm_copy_interface(const mrcm_interface *h, double *A, double *b) {
   if (!h || !A || !b) return fail(MRCM_EINVAL, "null argument");
-  const int n = h->n, w = h->w, nv = h->nv, ld = 2 * w + 1;
+  const int n = h->n, nv = h->nv;
   HIP_TRY(hipStreamSynchronize(h->stream));
-  std::vector<double> band((size_t)n * ld), bb(n);
-  if (n > 0) {
-    HIP_TRY(hipMemcpy(band.data(), h->AB0, band.size() * sizeof(double), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(bb.data(), h->b0, n * sizeof(double), hipMemcpyDeviceToHost));
+  if (n == 0) return MRCM_OK;
+  const mrcm_mbfs *mb = h->mb;
+  double *dA = nullptr, *db = nullptr;
+  if (dev_alloc(&dA, (size_t)n * n) != hipSuccess || dev_alloc(&db, (size_t)n) != hipSuccess) {
+    if (dA) (void)hipFree(dA);
+    return fail(MRCM_ENOMEM, "device allocation of the dense copy failed");
   }
-  // band index of natural unknown u: P of patch p -> 2 pos[p]; U -> 2 pos[p] + 1
-  std::vector<int> bidx(n);
-  for (int p = 0; p < nv; ++p) {
-    bidx[p] = 2 * h->pos[p];
-    bidx[nv + p] = 2 * h->pos[p] + 1;
-  }
-  for (int i = 0; i < n; ++i) {
-    b[i] = bb[bidx[i]];
-    for (int j = 0; j < n; ++j) {
-      const int bi = bidx[i], bj = bidx[j];
-      A[(size_t)i * n + j] = (std::abs(bi - bj) <= w) ? band[(size_t)bj * ld + (w + bi - bj)] : 0.0;
-    }
-  }
+  hipError_t e = launch_mf_dense(mb->g, mb->d_patches, mb->F, mb->Fb, mb->SAb, h->dp.pinfo, nv, dA, db, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = hipMemcpy(A, dA, (size_t)n * n * sizeof(double), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(b, db, (size_t)n * sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(dA);
+  (void)hipFree(db);
+  if (e != hipSuccess) return fail(MRCM_EHIP, std::string("mrcm_copy_interface: ") + hipGetErrorString(e));
   return MRCM_OK;
 }
 
@@ -1370,7 +1540,7 @@ mrcm_status mrcm_graph_capture(const mrcm_problem *pb, const mrcm_partition *par
   mrcm_status st = mrcm_build_mbfs(pb, part, ifs, opt, stream, &h);
   if (st == MRCM_OK && h != mb) st = fail(MRCM_EINVAL, "the options or problem differ from the handle's");
   if (st == MRCM_OK) st = mrcm_assemble_interface(mb, stream, &hi);
-  if (st == MRCM_OK) st = mrcm_solve_interface(ifc, refine, stream, X, nullptr);
+  if (st == MRCM_OK) st = mrcm_solve_interface(ifc, MRCM_IFACE_AUTO, 0.0, refine, stream, X, nullptr, nullptr);
   if (st == MRCM_OK) st = mrcm_reconstruct(mb, X, stream, p, U);
   g_capturing = false;
   hipGraph_t graph = nullptr;

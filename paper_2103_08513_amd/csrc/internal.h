@@ -65,6 +65,9 @@ struct Geom {
   int32_t nd[3];
 };
 
+// Status codes kernels write (values of mrcm_status).
+constexpr int kStatusSingular = -5;  // MRCM_ESINGULAR: zero pivot in the interface factorisation
+
 // Status word written by kernels (first error wins).
 struct DevStatus {
   int32_t code;     // 0 ok, else an mrcm_status value

@@ -1,0 +1,577 @@
+// Multifrontal LDL^T of the interface system on gfx950, over the nested-
+// dissection tree of nd_plan.cpp (InterfaceSolver of Algorithm 2).
+//
+// With s = -1 on the pressure rows and +1 on the velocity rows, M = diag(s) A
+// is symmetric quasi-definite (eqs. (2.19)-(2.22)); any symmetric order admits
+// LDL^T without pivoting.  Every tree node owns a dense f x f column-major
+// front: its separator's sp unknowns (the separator rounded up to a multiple
+// of 16 with identity pad rows), then its r boundary unknowns, which its
+// ancestors eliminate.  Its lower triangle receives the assembled entries of
+// the separator's rows and columns and the children's update matrices; the
+// partial factorisation of the separator columns then leaves
+//   the 16x16 diagonal blocks: L below, D on the diagonal, U = D L^T above,
+//     with L11^{-1} and 1/D per block in `inv` (272 doubles);
+//   W = A21 L11^{-T} of each block (the unscaled L21 = W D^{-1}) stored
+//     transposed above the diagonal: W[i][c] at column i, row k0 + c;
+//   the update matrix (Schur complement) in the trailing r x r block.
+// Levels are processed bottom-up, each as one extend-add per child slot, the
+// factorisation of every node's first block, and one launch per 16-column
+// step over all the level's nodes that still have a block there.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device_common.h"
+#include "launch.h"
+#include "ldl16.h"
+#include "nd_plan.h"
+
+namespace mrcm {
+
+// ---------------------------------------------------------------------------
+// One row pair of the assembled interface system (P-row and U-row of patch
+// a), as assemble_interface defines it: each entry is the sum over the (at
+// most two) subdomains holding both patches, of
+//   P-row: F^s[i, P_j], F^s[i, U_j];  U-row: sigma Fb^s[i, P_j],
+//   sigma Fb^s[i, U_j] - [i = j] SAb^s[i],
+// taken as fl(lower side + upper side), the order in which the front
+// scatter's two atomic additions onto zero round.  visit(b, cPP, cPU, cUP, cUU)
+// receives each column patch once; bP, bU the right-hand side.
+// ---------------------------------------------------------------------------
+template <typename Visit>
+__device__ __forceinline__ void iface_rows(const Geom &g, const int *__restrict__ patches, const double *__restrict__ F,
+                                           const double *__restrict__ Fb, const double *__restrict__ SAb, int a,
+                                           const int4 pinfo, double &bP, double &bU, Visit visit) {
+  const IfaceDesc &I = g.ifc[pinfo.x];
+  const SubDesc &S1 = g.sub[I.lo_sub];
+  const SubDesc &S2 = g.sub[I.hi_sub];
+  const int li1 = pinfo.y, li2 = pinfo.z;
+  const int n1 = S1.npatch, m1 = S1.m, n2 = S2.npatch, m2 = S2.m;
+  const double *f1 = F + S1.F_off + (size_t)li1 * m1;
+  const double *b1 = Fb + S1.F_off + (size_t)li1 * m1;
+  const double *f2 = F + S2.F_off + (size_t)li2 * m2;
+  const double *b2 = Fb + S2.F_off + (size_t)li2 * m2;
+  const int np = I.na * I.nb;
+  const int j2base = S2.face_p0[2 * I.d];
+  for (int j = 0; j < n1; ++j) {
+    const int bq = patches[S1.patch_off + j];
+    double cPP = f1[1 + j], cPU = f1[1 + n1 + j], cUP = b1[1 + j];
+    double cUU = b1[1 + n1 + j] - (j == li1 ? SAb[S1.patch_off + li1] : 0.0);
+    if (bq >= I.p0 && bq < I.p0 + np) {
+      // a patch of the shared interface: the upper side adds its part
+      const int j2 = j2base + (bq - I.p0);
+      cPP = cPP + f2[1 + j2];
+      cPU = cPU + f2[1 + n2 + j2];
+      cUP = cUP + (-b2[1 + j2]);
+      cUU = cUU + (-b2[1 + n2 + j2] - (j2 == li2 ? SAb[S2.patch_off + li2] : 0.0));
+    }
+    visit(bq, cPP, cPU, cUP, cUU);
+  }
+  for (int j = 0; j < n2; ++j) {
+    const int bq = patches[S2.patch_off + j];
+    if (bq >= I.p0 && bq < I.p0 + np) continue;
+    visit(bq, f2[1 + j], f2[1 + n2 + j], -b2[1 + j], -b2[1 + n2 + j]);
+  }
+  bP = (-f1[0]) + (-f2[0]);
+  bU = (-b1[0]) + b2[0];
+}
+
+// r = b - A x (unflipped, interleaved unknowns 2p, 2p+1), one thread per patch.
+__global__ __launch_bounds__(256) void k_mf_residual(Geom g, const int *__restrict__ patches,
+                                                     const double *__restrict__ F, const double *__restrict__ Fb,
+                                                     const double *__restrict__ SAb, const int4 *__restrict__ pinfo,
+                                                     int nv, const double *__restrict__ x, double *__restrict__ r,
+                                                     double *__restrict__ b) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nv) return;
+  double rP = 0.0, rU = 0.0, bP, bU;
+  iface_rows(g, patches, F, Fb, SAb, a, pinfo[a], bP, bU,
+             [&](int bq, double cPP, double cPU, double cUP, double cUU) {
+               if (!x) return;  // x = 0: r = b
+               const double xp = x[2 * bq], xu = x[2 * bq + 1];
+               rP = fma(cPP, xp, fma(cPU, xu, rP));
+               rU = fma(cUP, xp, fma(cUU, xu, rU));
+             });
+  r[2 * a] = bP - rP;
+  r[2 * a + 1] = bU - rU;
+  if (b) {
+    b[2 * a] = bP;
+    b[2 * a + 1] = bU;
+  }
+}
+
+// Dense rows of A (natural order: P-row of patch a at a, U-row at nv + a),
+// for inspection.  One thread per patch; the rows must be zero beforehand.
+__global__ __launch_bounds__(256) void k_mf_dense(Geom g, const int *__restrict__ patches,
+                                                  const double *__restrict__ F, const double *__restrict__ Fb,
+                                                  const double *__restrict__ SAb, const int4 *__restrict__ pinfo,
+                                                  int nv, double *__restrict__ A, double *__restrict__ b) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nv) return;
+  const size_t n = 2 * (size_t)nv;
+  double *rowP = A + (size_t)a * n, *rowU = A + (size_t)(nv + a) * n;
+  double bP, bU;
+  iface_rows(g, patches, F, Fb, SAb, a, pinfo[a], bP, bU,
+             [&](int bq, double cPP, double cPU, double cUP, double cUU) {
+               rowP[bq] = cPP;
+               rowP[nv + bq] = cPU;
+               rowU[bq] = cUP;
+               rowU[nv + bq] = cUU;
+             });
+  b[a] = bP;
+  b[nv + a] = bU;
+}
+
+// Scatter of the assembled entries into the fronts: one workgroup per
+// subdomain, one thread per (row patch, column patch) pair.  The sign flip
+// negates the pressure rows.  An entry receives one contribution per
+// subdomain holding both patches -- at most two -- so the atomic sums onto
+// zero do not depend on their order.  Pairs above the diagonal are skipped:
+// their transposes are below it.
+__global__ __launch_bounds__(256) void k_mf_scatter(Geom g, const int *__restrict__ patches,
+                                                    const double *__restrict__ F, const double *__restrict__ Fb,
+                                                    const double *__restrict__ SAb,
+                                                    const int64_t *__restrict__ sub_pair_off,
+                                                    const int64_t *__restrict__ pair_off,
+                                                    const int *__restrict__ pair_ld, double *__restrict__ fronts) {
+  const SubDesc &S = g.sub[blockIdx.x];
+  const int n = S.npatch, m = S.m;
+  const double *Fs = F + S.F_off;
+  const double *Fbs = Fb + S.F_off;
+  const int64_t e0 = sub_pair_off[blockIdx.x];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int64_t off = pair_off[e0 + e];
+    if (off < 0) continue;
+    const int ld = pair_ld[e0 + e];
+    const int li = e / n, lj = e % n;
+    int fi = 0;
+    for (int ff = 0; ff < 6; ++ff) {
+      const int ii = S.face_if[ff];
+      if (ii < 0) continue;
+      const IfaceDesc &I = g.ifc[ii];
+      if (li >= S.face_p0[ff] && li < S.face_p0[ff] + I.na * I.nb) fi = ff;
+    }
+    const double sig = (fi & 1) ? 1.0 : -1.0;
+    const double *fr = Fs + (size_t)li * m;
+    const double *br = Fbs + (size_t)li * m;
+    double uu = sig * br[1 + n + lj];
+    if (li == lj) uu -= SAb[S.patch_off + li];
+    atomicAdd(&fronts[off], -fr[1 + lj]);           // (P_a, P_b), flipped row
+    atomicAdd(&fronts[off + 1], sig * br[1 + lj]);  // (U_a, P_b)
+    if (li != lj) atomicAdd(&fronts[off + ld], -fr[1 + n + lj]);  // (P_a, U_b), flipped row
+    atomicAdd(&fronts[off + ld + 1], uu);           // (U_a, U_b)
+  }
+}
+
+// Identity on the pad rows of every separator.
+__global__ void k_mf_pad(const MfNode *__restrict__ nodes, int nn, double *__restrict__ fronts) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nn) return;
+  const MfNode nd = nodes[k];
+  for (int p = nd.s; p < nd.sp; ++p) fronts[nd.off + (int64_t)p * nd.f + p] = 1.0;
+}
+
+// Extend-add of one child slot: the update matrix of child `slot` of each of
+// the level's nodes into the node's front, through the child's map.
+// grid = (nodes of the level, groups of 16 child columns).
+__global__ __launch_bounds__(256) void k_mf_extend(const MfNode *__restrict__ nodes, const int *__restrict__ list,
+                                                   const int *__restrict__ map, int slot,
+                                                   double *__restrict__ fronts) {
+  const MfNode P = nodes[list[blockIdx.x]];
+  const int c = slot ? P.child1 : P.child0;
+  if (c < 0) return;
+  const MfNode C = nodes[c];
+  const int j0 = 16 * blockIdx.y;
+  if (j0 >= C.r) return;
+  const int *cm = map + C.map_off;
+  const double *src = fronts + C.off;
+  double *dst = fronts + P.off;
+  const int j1 = min(C.r, j0 + 16);
+  for (int j = j0; j < j1; ++j) {
+    const int pj = cm[j];
+    const double *col = src + (int64_t)(C.sp + j) * C.f + C.sp;
+    double *pcol = dst + (int64_t)pj * P.f;
+    for (int i = j + threadIdx.x; i < C.r; i += blockDim.x) pcol[cm[i]] += col[i];
+  }
+}
+
+// LDL^T of the first 16x16 block of every node of a level (one wave each).
+__global__ __launch_bounds__(64) void k_mf_first(const MfNode *__restrict__ nodes, const int *__restrict__ list,
+                                                 double *__restrict__ fronts, double *__restrict__ inv,
+                                                 DevStatus *st) {
+  __shared__ double blk[2 * kLB * (kLB + 1)];
+  __shared__ double T[kInvStride];
+  const int k = list[blockIdx.x];
+  const MfNode nd = nodes[k];
+  const int lane = threadIdx.x;
+  double *A = fronts + nd.off;
+  for (int e = lane; e < kLB * kLB; e += 64) {
+    const int r = e / kLB, c = e % kLB;
+    blk[r * (kLB + 1) + c] = (c <= r) ? A[(int64_t)c * nd.f + r] : 0.0;
+  }
+  __syncthreads();
+  const int f = nd.f;
+  auto store = [&](int t, int i, double v) { A[(int64_t)t * f + i] = v; };
+  if (ldl_diag16(blk, kLB, lane, store, inv + nd.inv_off, blk, T) && lane == 0)
+    set_status(st, kStatusSingular, k, 0.0);
+}
+
+// Step t of the partial factorisation, for every node of a level with a
+// block t: the trailing rows and columns r0 = 16 (t + 1) .. f - 1 of each
+// front in lower 64x64 tiles, one workgroup (four waves of 16 rows) per tile,
+// plus a fifth wave that, in the tile holding the node's next diagonal block
+// (when the separator has one), factors that block while the other waves
+// finish the tile.  W = A21 L11^{-T} and C -= W D^{-1} W^T are MFMA products.
+// Diagonal tiles store W^T above the diagonal for their 64 rows; the panel's
+// A21 entries below the diagonal are left as they are, so every tile of this
+// launch reads the same A21 whatever the order in which they run.
+constexpr int kMfStepThreads = 320;
+
+__global__ __launch_bounds__(kMfStepThreads) void k_mf_step(const MfNode *__restrict__ nodes,
+                                                            const int2 *__restrict__ blocks, int t,
+                                                            double *__restrict__ fronts, double *__restrict__ inv,
+                                                            DevStatus *st) {
+  using M = Mma<double>;
+  __shared__ double Wi[64 * (kLB + 1)];
+  __shared__ double Wj[64 * (kLB + 1)];
+  __shared__ double Dn[2 * kLB * (kLB + 1)];
+  __shared__ double Ts[kInvStride];
+  const int2 bt = blocks[blockIdx.x];
+  const MfNode nd = nodes[bt.x];
+  const int f = nd.f;
+  double *A = fronts + nd.off;
+  const double *inv_k = inv + nd.inv_off + (int64_t)t * kInvStride;
+  const int k0 = kLB * t;
+  const int r0 = k0 + kLB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  int ti = 0, tj = bt.y;
+  while (tj > ti) {
+    tj -= ti + 1;
+    ++ti;
+  }
+  const int i0 = r0 + 64 * ti, j0 = r0 + 64 * tj;
+  auto a21 = [&](int i, int c) -> double { return i < f ? A[(int64_t)(k0 + c) * f + i] : 0.0; };
+  const bool rows = wave < 4;
+  double ai[4] = {0.0, 0.0, 0.0, 0.0}, aj[4] = {0.0, 0.0, 0.0, 0.0};
+  double bl[4] = {0.0, 0.0, 0.0, 0.0}, dq[4] = {0.0, 0.0, 0.0, 0.0};
+  typename M::v4 c[4];
+  if (rows) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      ai[s] = a21(i0 + 16 * wave + lr, 4 * s + lk);
+      aj[s] = a21(j0 + 16 * wave + lr, 4 * s + lk);
+      bl[s] = inv_k[lr * kLB + 4 * s + lk];
+      dq[s] = inv_k[kLB * kLB + 4 * s + lk];
+    }
+#pragma unroll
+    for (int tc = 0; tc < 4; ++tc) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 16 * wave + M::crow(v, lane), j = j0 + 16 * tc + lr;
+        const bool ok = i < f && j < f && i >= j;
+        c[tc][v] = ok ? A[(int64_t)j * f + i] : 0.0;
+      }
+    }
+  }
+  if (rows) {
+    typename M::v4 wi = {0.0, 0.0, 0.0, 0.0}, wj = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      wi = M::mma(ai[s], bl[s], wi);
+      wj = M::mma(aj[s], bl[s], wj);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Wi[(16 * wave + M::crow(v, lane)) * (kLB + 1) + lr] = wi[v];
+      Wj[(16 * wave + M::crow(v, lane)) * (kLB + 1) + lr] = wj[v];
+    }
+  }
+  const bool has_next = ti == 0 && tj == 0 && r0 < nd.sp;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  if (rows) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[s] = Wi[(16 * wave + lr) * (kLB + 1) + 4 * s + lk] * dq[s];
+  }
+  if (has_next && wave == 0) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c[0] = M::mma(-a[s], Wj[lr * (kLB + 1) + 4 * s + lk], c[0]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + M::crow(v, lane), j = j0 + lr;
+      Dn[(i - r0) * (kLB + 1) + (j - r0)] = (i >= j) ? c[0][v] : 0.0;
+    }
+  }
+  __syncthreads();
+  if (has_next && wave == 4) {
+    auto store = [&](int tt, int i, double v) { A[(int64_t)(r0 + tt) * f + r0 + i] = v; };
+    if (ldl_diag16(Dn, kLB, lane, store, inv + nd.inv_off + (int64_t)(t + 1) * kInvStride, Dn, Ts) && lane == 0)
+      set_status(st, kStatusSingular, bt.x, 0.0);
+  } else if (rows && !(has_next && wave == 0)) {
+    auto update_cols = [&](auto ntc_c) {
+      constexpr int NTC = decltype(ntc_c)::value;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+#pragma unroll
+        for (int tc = 0; tc < NTC; ++tc)
+          c[tc] = M::mma(-a[s], Wj[(16 * tc + lr) * (kLB + 1) + 4 * s + lk], c[tc]);
+      }
+#pragma unroll
+      for (int tc = 0; tc < NTC; ++tc) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + 16 * wave + M::crow(v, lane), j = j0 + 16 * tc + lr;
+          if (i < f && j < f && i >= j) A[(int64_t)j * f + i] = c[tc][v];
+        }
+      }
+    };
+    const int ntc = (ti == tj) ? wave + 1 : 4;
+    if (ntc == 4)
+      update_cols(std::integral_constant<int, 4>{});
+    else if (ntc == 3)
+      update_cols(std::integral_constant<int, 3>{});
+    else if (ntc == 2)
+      update_cols(std::integral_constant<int, 2>{});
+    else
+      update_cols(std::integral_constant<int, 1>{});
+  }
+  if (ti == tj && rows) {
+    for (int e = tid; e < 64 * kLB; e += 256) {
+      const int rr = e / kLB, cc = e % kLB;
+      const int i = i0 + rr;
+      if (i < f) A[(int64_t)i * f + (k0 + cc)] = Wi[rr * (kLB + 1) + cc];
+    }
+  }
+}
+
+// Wave-wide sum (every lane receives it).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+constexpr int kMfSweepThreads = 1024;
+// the forward sweep gives one wave to each row of a 16-row block
+static_assert(kMfSweepThreads / 64 == kLB, "one wave per block row");
+
+// Forward sweep L z = diag(s) rhs of one level, one workgroup per node:
+// the node's right-hand side (its separator's entries of rhs, sign-flipped on
+// the pressure rows) plus its children's boundary parts; then block by block
+// y_k = L11^{-1} (z_k - sum_{j<k} W_kj D_j^{-1} y_j) with one wave per row of
+// the block, and the boundary rows z_b -= W_b D^{-1} y.  The node's vector
+// (y on the separator, z_b on the boundary) goes to zbuf.
+__global__ __launch_bounds__(kMfSweepThreads) void k_mf_fwd(const MfNode *__restrict__ nodes,
+                                                            const int *__restrict__ list, const int *__restrict__ idx,
+                                                            const int *__restrict__ map,
+                                                            const double *__restrict__ fronts,
+                                                            const double *__restrict__ inv,
+                                                            const double *__restrict__ rhs,
+                                                            double *__restrict__ zbuf) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double zk[kLB];
+  const int k = list[blockIdx.x];
+  const MfNode nd = nodes[k];
+  const int f = nd.f, sp = nd.sp;
+  double *z = reinterpret_cast<double *>(smem_raw);  // f entries
+  double *u = z + f;                                 // sp entries: D^{-1} y
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int *id = idx + nd.idx_off;
+  for (int p = tid; p < f; p += kMfSweepThreads) {
+    const int q = id[p];
+    double v = 0.0;
+    if (p < sp && q >= 0) v = (q & 1) ? rhs[q] : -rhs[q];
+    z[p] = v;
+  }
+  __syncthreads();
+  for (int slot = 0; slot < 2; ++slot) {
+    const int c = slot ? nd.child1 : nd.child0;
+    if (c < 0) continue;
+    const MfNode C = nodes[c];
+    const double *zc = zbuf + C.z_off + C.sp;
+    for (int i = tid; i < C.r; i += kMfSweepThreads) z[map[C.map_off + i]] += zc[i];
+    __syncthreads();
+  }
+  const double *A = fronts + nd.off;
+  const double *iv0 = inv + nd.inv_off;
+  for (int k0 = 0; k0 < sp; k0 += kLB) {
+    {
+      // wave w: row k0 + w of the block against the solved prefix
+      const double *row = A + (int64_t)(k0 + wave) * f;
+      double acc = 0.0;
+      for (int cidx = lane; cidx < k0; cidx += 64) acc = fma(row[cidx], u[cidx], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) zk[wave] = z[k0 + wave] - acc;
+    }
+    __syncthreads();
+    if (tid < kLB) {
+      const double *iv = iv0 + (int64_t)(k0 / kLB) * kInvStride;
+      double y = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < kLB; ++cc) y = fma(iv[tid * kLB + cc], zk[cc], y);
+      z[k0 + tid] = y;
+      u[k0 + tid] = y * iv[kLB * kLB + tid];
+    }
+    __syncthreads();
+  }
+  for (int i = sp + wave; i < f; i += kMfSweepThreads / 64) {
+    const double *row = A + (int64_t)i * f;
+    double acc = 0.0;
+    for (int cidx = lane; cidx < sp; cidx += 64) acc = fma(row[cidx], u[cidx], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) z[i] -= acc;
+  }
+  __syncthreads();
+  double *zo = zbuf + nd.z_off;
+  for (int p = tid; p < f; p += kMfSweepThreads) zo[p] = z[p];
+}
+
+// Backward sweep of one level (top-down), one workgroup per node: with the
+// boundary unknowns x_b solved by the ancestors, t = y - W_b^T x_b; then from
+// the last block down, x_k = L11^{-T} D_k^{-1} t_k and t_j -= W_kj^T x_k for
+// the earlier blocks.  The separator's unknowns go to x.
+__global__ __launch_bounds__(kMfSweepThreads) void k_mf_bwd(const MfNode *__restrict__ nodes,
+                                                            const int *__restrict__ list, const int *__restrict__ idx,
+                                                            const double *__restrict__ fronts,
+                                                            const double *__restrict__ inv,
+                                                            const double *__restrict__ zbuf, double *__restrict__ x) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int k = list[blockIdx.x];
+  const MfNode nd = nodes[k];
+  const int f = nd.f, sp = nd.sp;
+  double *xs = reinterpret_cast<double *>(smem_raw);  // f entries
+  double *tv = xs + f;                                // sp entries
+  const int tid = threadIdx.x;
+  const int *id = idx + nd.idx_off;
+  const double *A = fronts + nd.off;
+  const double *zo = zbuf + nd.z_off;
+  for (int p = sp + tid; p < f; p += kMfSweepThreads) xs[p] = x[id[p]];
+  __syncthreads();
+  for (int cidx = tid; cidx < sp; cidx += kMfSweepThreads) {
+    double acc = zo[cidx];
+    for (int i = sp; i < f; ++i) acc = fma(-A[(int64_t)i * f + cidx], xs[i], acc);
+    tv[cidx] = acc;
+  }
+  __syncthreads();
+  const double *iv0 = inv + nd.inv_off;
+  for (int k0 = sp - kLB; k0 >= 0; k0 -= kLB) {
+    if (tid < kLB) {
+      const double *iv = iv0 + (int64_t)(k0 / kLB) * kInvStride;
+      double v = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < kLB; ++cc) v = fma(iv[cc * kLB + tid], iv[kLB * kLB + cc] * tv[k0 + cc], v);
+      xs[k0 + tid] = v;
+    }
+    __syncthreads();
+    for (int cidx = tid; cidx < k0; cidx += kMfSweepThreads) {
+      double acc = tv[cidx];
+#pragma unroll
+      for (int r = 0; r < kLB; ++r) acc = fma(-A[(int64_t)(k0 + r) * f + cidx], xs[k0 + r], acc);
+      tv[cidx] = acc;
+    }
+    __syncthreads();
+  }
+  for (int p = tid; p < sp; p += kMfSweepThreads) {
+    const int q = id[p];
+    if (q >= 0) x[q] = xs[p];
+  }
+}
+
+__global__ void k_mf_deinterleave(const double *__restrict__ x, int nv, double *__restrict__ X) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nv) return;
+  X[p] = x[2 * p];
+  X[nv + p] = x[2 * p + 1];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_mf_assemble(const Geom &g, int n_sub, const int *patches, const double *F, const double *Fb,
+                              const double *SAb, const MfDevPlan &dp, double *fronts, hipStream_t s) {
+  hipError_t e = launch_fill(fronts, dp.front_doubles, 0.0, s);
+  if (e != hipSuccess) return e;
+  if (n_sub > 0)
+    hipLaunchKernelGGL(k_mf_scatter, dim3(n_sub), dim3(256), 0, s, g, patches, F, Fb, SAb, dp.sub_pair_off,
+                       dp.pair_off, dp.pair_ld, fronts);
+  if (dp.n_nodes > 0)
+    hipLaunchKernelGGL(k_mf_pad, dim3((dp.n_nodes + 255) / 256), dim3(256), 0, s, dp.nodes, dp.n_nodes, fronts);
+  return hipGetLastError();
+}
+
+hipError_t launch_mf_factor(const NdPlan &plan, const MfDevPlan &dp, double *fronts, double *inv, DevStatus *st,
+                            hipStream_t s) {
+  const int H = (int)plan.level_off.size() - 1;
+  size_t si = 0;
+  for (int h = 0; h < H; ++h) {
+    const int n0 = plan.level_off[h], nn = plan.level_off[h + 1] - n0;
+    if (nn <= 0) continue;
+    const int *list = dp.level_nodes + n0;
+    if (plan.level_child_rmax[h] > 0) {
+      const unsigned gy = (unsigned)((plan.level_child_rmax[h] + 15) / 16);
+      hipLaunchKernelGGL(k_mf_extend, dim3(nn, gy), dim3(256), 0, s, dp.nodes, list, dp.map, 0, fronts);
+      hipLaunchKernelGGL(k_mf_extend, dim3(nn, gy), dim3(256), 0, s, dp.nodes, list, dp.map, 1, fronts);
+    }
+    hipLaunchKernelGGL(k_mf_first, dim3(nn), dim3(64), 0, s, dp.nodes, list, fronts, inv, st);
+    for (; si < plan.steps.size() && plan.steps[si].level == h; ++si) {
+      const MfStepLaunch &L = plan.steps[si];
+      hipLaunchKernelGGL(k_mf_step, dim3(L.n_blocks), dim3(kMfStepThreads), 0, s, dp.nodes,
+                         dp.step_blocks + L.blk_off, L.t, fronts, inv, st);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mf_solve(const NdPlan &plan, const MfDevPlan &dp, const double *fronts, const double *inv,
+                           double *zbuf, const double *rhs, double *x, hipStream_t s) {
+  const int H = (int)plan.level_off.size() - 1;
+  // the plan keeps every level's (f + sp) within kMfSweepLdsMax, which
+  // mf_init_kernels has allowed
+  for (int h = 0; h < H; ++h) {
+    const int n0 = plan.level_off[h], nn = plan.level_off[h + 1] - n0;
+    const size_t lds = (size_t)plan.level_lds[h] * sizeof(double);
+    hipLaunchKernelGGL(k_mf_fwd, dim3(nn), dim3(kMfSweepThreads), lds, s, dp.nodes, dp.level_nodes + n0, dp.idx,
+                       dp.map, fronts, inv, rhs, zbuf);
+  }
+  for (int h = H - 1; h >= 0; --h) {
+    const int n0 = plan.level_off[h], nn = plan.level_off[h + 1] - n0;
+    const size_t lds = (size_t)plan.level_lds[h] * sizeof(double);
+    hipLaunchKernelGGL(k_mf_bwd, dim3(nn), dim3(kMfSweepThreads), lds, s, dp.nodes, dp.level_nodes + n0, dp.idx,
+                       fronts, inv, zbuf, x);
+  }
+  return hipGetLastError();
+}
+
+hipError_t mf_init_kernels() {
+  hipError_t e = hipFuncSetAttribute((const void *)k_mf_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kMfSweepLdsMax);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_mf_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMfSweepLdsMax);
+  return e;
+}
+
+hipError_t launch_mf_residual(const Geom &g, const int *patches, const double *F, const double *Fb,
+                              const double *SAb, const int4 *pinfo, int nv, const double *x, double *r, double *b,
+                              hipStream_t s) {
+  if (nv <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mf_residual, dim3((nv + 255) / 256), dim3(256), 0, s, g, patches, F, Fb, SAb, pinfo, nv, x, r,
+                     b);
+  return hipGetLastError();
+}
+
+hipError_t launch_mf_dense(const Geom &g, const int *patches, const double *F, const double *Fb, const double *SAb,
+                           const int4 *pinfo, int nv, double *A, double *b, hipStream_t s) {
+  if (nv <= 0) return hipSuccess;
+  hipError_t e = launch_fill(A, 4LL * nv * nv, 0.0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mf_dense, dim3((nv + 255) / 256), dim3(256), 0, s, g, patches, F, Fb, SAb, pinfo, nv, A, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_mf_deinterleave(const double *x, int nv, double *X, hipStream_t s) {
+  if (nv <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mf_deinterleave, dim3((nv + 255) / 256), dim3(256), 0, s, x, nv, X);
+  return hipGetLastError();
+}
+
+}  // namespace mrcm

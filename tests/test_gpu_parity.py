@@ -343,3 +343,40 @@ def test_extreme_robin_parameter(alpha, precision):
     assert worst < 1e-9
     assert ep < 1e-8 and eu < 1e-8
     m.close()
+
+
+@pytest.mark.parametrize("name", ["coarse-patches", "ragged", "tall-band", "fine-trace"])
+def test_interface_solvers_agree_with_the_oracle(name):
+    """Both interface solvers -- the band LDL^T and the multifrontal LDL^T on
+    the nested-dissection tree -- against the oracle's interface unknowns,
+    without and with refinement; the tolerance-driven refinement stops once
+    the relative residual is below its rtol."""
+    import paper_2103_08513_amd as lib
+    case = small_case(**CASES[name])
+    ref = mrcm_solve(case)
+    pb = case.problem
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha)
+    m.build_mbfs(_dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q))
+    m.assemble_interface()
+    sols = {}
+    for method in (lib.IFACE_BAND, lib.IFACE_MULTIFRONTAL):
+        for refine in (0, 2):
+            X = m.solve_interface(refine=refine, method=method, residual=True)
+            torch.cuda.synchronize()
+            e = rel_l2(X.cpu().numpy(), ref.pi)
+            print(f"{name}: method {method}, refine {refine}: pi {e:.2e}, residual {m.interface_residual:.2e}",
+                  flush=True)
+            assert e < 1e-10
+            assert m.interface_residual < 1e-13
+            assert m.interface_iters == refine
+            sols[(method, refine)] = X.cpu().numpy()
+    inf = m.interface_info()
+    assert inf.n == 2 * m.info().n_patch and inf.nodes >= 1 and inf.levels >= 1 and inf.bandwidth > 0
+    # rtol: refinement stops at the first residual below it
+    X = m.solve_interface(refine=10, rtol=1e-12, residual=True)
+    assert m.interface_iters <= 1 and m.interface_residual <= 1e-12
+    # a second solve of the same assembly scatters the entries again: same result
+    X2 = m.solve_interface(refine=2)
+    torch.cuda.synchronize()
+    assert np.array_equal(X2.cpu().numpy(), sols[(lib.IFACE_MULTIFRONTAL, 2)])
+    m.close()
