@@ -36,7 +36,8 @@ import numpy as np
 __all__ = [
     "Problem", "Partition", "IfaceSpace", "Case",
     "grf", "channelised", "uniform_cuts", "ragged_cuts",
-    "config1", "config2", "config3", "config3_block", "small_case",
+    "config1", "config2", "config3", "config3_block", "config5", "config5_block", "contrast_power",
+    "small_case",
 ]
 
 
@@ -145,7 +146,9 @@ def channelised(shape, seed, frac=0.3, mean_ch=7.0, mean_bg=0.0, std=1.0):
     yy = np.arange(ny)
     xx = np.arange(nx)
     guard = 0
-    while facies.mean() < frac and guard < 10000:
+    total = nx * ny * nz
+    count = 0  # channel cells so far (kept incrementally instead of re-counting the grid)
+    while count / total < frac and guard < 10000:
         guard += 1
         x0 = rng.uniform(0, nx)
         amp = rng.uniform(2, 12)
@@ -156,7 +159,9 @@ def channelised(shape, seed, frac=0.3, mean_ch=7.0, mean_bg=0.0, std=1.0):
         z0 = rng.integers(0, max(1, nz - thick + 1))
         xc = x0 + amp * np.sin(2 * np.pi * yy / lam + phi)
         band = np.abs(xx[None, :] - xc[:, None]) <= width / 2.0  # [ny, nx]
-        facies[z0:z0 + thick][:, band] = True
+        slab = facies[z0:z0 + thick]
+        count += int(np.count_nonzero(~slab[:, band]))
+        slab[:, band] = True
     noise = rng.standard_normal((nz, ny, nx))
     y = np.where(facies, mean_ch, mean_bg) + std * noise
     return y.reshape(-1)
@@ -219,6 +224,54 @@ def config2(seed=0, alpha=1.0):
     pb = Problem(nx, ny, nz, 20.0, 10.0, 2.0, kx, kx.copy(), 0.1 * kx, q, pin=pin)
     part = Partition(uniform_cuts(nx, 20), uniform_cuts(ny, 20), uniform_cuts(nz, 5))
     return Case(f"cfg2-60x220x85-a{alpha:g}", pb, part, IfaceSpace(((2, 1), (2, 1), (2, 2))), alpha)
+
+
+def contrast_power(k, contrast=1e8):
+    """K -> K^theta with theta = ln(contrast) / ln(K_max / K_min) of the given
+    field, so that the result spans exactly `contrast` (the paper raises its
+    permeability to a power to vary the contrast)."""
+    lk = np.log(k)
+    theta = np.log(contrast) / (lk.max() - lk.min())
+    return np.exp(theta * lk), float(theta)
+
+
+def config5(seed=0, alpha=1.0):
+    """600x2200x85 cells of 20x10x2 ft (112.2M), 30x110x17 = 56,100 subdomains
+    of 20x20x5, the channelised field of the 60x220x85 workload raised to the
+    power that makes its contrast 1e8, kz = 0.1 kx, patches 2x1 on x/y-normal
+    and 2x2 on z-normal faces (430,840 patches), quarter-five-spot well columns
+    at (0,0,.) and (599,2199,.), pin at (599,2199,84)."""
+    nx, ny, nz = 600, 2200, 85
+    kx, theta = contrast_power(np.exp(channelised((nx, ny, nz), seed)), 1e8)
+    q = np.zeros(nx * ny * nz)
+    for k in range(nz):
+        q[_cell(0, 0, k, nx, ny)] += 1.0 / nz
+        q[_cell(nx - 1, ny - 1, k, nx, ny)] -= 1.0 / nz
+    pin = _cell(nx - 1, ny - 1, nz - 1, nx, ny)
+    pb = Problem(nx, ny, nz, 20.0, 10.0, 2.0, kx, kx.copy(), 0.1 * kx, q, pin=pin)
+    part = Partition(uniform_cuts(nx, 20), uniform_cuts(ny, 20), uniform_cuts(nz, 5))
+    case = Case(f"cfg5-600x2200x85-a{alpha:g}", pb, part, IfaceSpace(((2, 1), (2, 1), (2, 2))), alpha)
+    case.theta = theta
+    return case
+
+
+def config5_block(big):
+    """The 60x220x85 block at the origin corner of a 600x2200x85 case (its
+    permeability exactly), laid out as the 60x220x85 workload: 3x11x17
+    subdomains of 20x20x5, the same patches, quarter-five-spot columns at the
+    block's corners (0,0,.) and (59,219,.), pin at (59,219,84)."""
+    nx, ny, nz = 60, 220, 85
+    B = big.problem
+    def win(a):
+        return np.ascontiguousarray(np.asarray(a).reshape(B.nz, B.ny, B.nx)[:nz, :ny, :nx]).reshape(-1)
+    q = np.zeros(nx * ny * nz)
+    for k in range(nz):
+        q[_cell(0, 0, k, nx, ny)] += 1.0 / nz
+        q[_cell(nx - 1, ny - 1, k, nx, ny)] -= 1.0 / nz
+    pin = _cell(nx - 1, ny - 1, nz - 1, nx, ny)
+    pb = Problem(nx, ny, nz, B.hx, B.hy, B.hz, win(B.kx), win(B.ky), win(B.kz), q, pin=pin)
+    part = Partition(uniform_cuts(nx, 20), uniform_cuts(ny, 20), uniform_cuts(nz, 5))
+    return Case("cfg5-block-60x220x85", pb, part, IfaceSpace(((2, 1), (2, 1), (2, 2))), big.alpha)
 
 
 def config3(seed=0, patch_seed=3):
