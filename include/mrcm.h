@@ -353,12 +353,15 @@ mrcm_status mrcm_copy_interface(const mrcm_interface *iface, double *A, double *
  * the FP32 form it holds the convergence checks and any further sweeps.
  * PCG: 'pcg' is the conjugate-gradient kernel and the read-back of its
  * convergence flags; 'fallback' the band Cholesky and direct solves of the
- * subdomains it left (factor and solve stages stay empty).
+ * subdomains it left (factor and solve stages stay empty).  'solve_rest' is
+ * the single launch of group 1's first solve, inside 'refine'.  Interface
+ * stages: 'assemble' the scatter into the fronts (band form: into the band),
+ * 'lu' the factorisation, 'sweep' the solves and refinement steps.
  */
 enum { MRCM_STAGE_COEF = 0, MRCM_STAGE_FACTOR, MRCM_STAGE_RHS, MRCM_STAGE_SOLVE,
        MRCM_STAGE_RESIDUAL, MRCM_STAGE_REFINE, MRCM_STAGE_FLUX, MRCM_STAGE_ASSEMBLE,
        MRCM_STAGE_LU, MRCM_STAGE_SWEEP, MRCM_STAGE_RECONSTRUCT, MRCM_STAGE_PCG,
-       MRCM_STAGE_FALLBACK, MRCM_STAGE_COUNT };
+       MRCM_STAGE_FALLBACK, MRCM_STAGE_SOLVE_REST, MRCM_STAGE_COUNT };
 typedef struct {
   double ms[16];        /* accumulated milliseconds per stage */
   int64_t count[16];    /* occurrences per stage */

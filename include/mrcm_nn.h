@@ -96,7 +96,8 @@ mrcm_status mrcm_adam_step(float *p, const float *g, float *m, float *v, int32_t
  *  tgt [samples][1][d][h][w] (or NULL): the column's solution X divided by
  *       its root mean square (zero columns stay zero).
  * The right-hand sides are formed again into the handle's refinement buffer
- * (allocated on first use).
+ * (allocated on first use), once per build: later calls on the same build
+ * reuse them, so a workload may be gathered a few subdomains at a time.
  */
 mrcm_status mrcm_nn_features(mrcm_mbfs *mbfs, const int32_t *subs, int32_t n_subs, float *inp, float *tgt,
                              void *stream);

@@ -25,7 +25,7 @@ EXPORTS = [
 ]
 
 STAGES = ["coef", "factor", "rhs", "solve", "residual", "refine", "flux", "assemble", "lu", "sweep",
-          "reconstruct", "pcg", "fallback"]
+          "reconstruct", "pcg", "fallback", "solve_rest"]
 
 
 class CProblem(ctypes.Structure):

@@ -545,6 +545,7 @@ struct mrcm_mbfs {
   std::vector<int4> fb_work;
   // network samples: selected subdomains and their first sample index
   int *d_nn_sel = nullptr, *d_nn_s0 = nullptr;
+  bool nn_rhs_ready = false;  // R holds the current build's right-hand sides
   std::vector<int> nn_sel, nn_s0;
   int *d_patches = nullptr;
   int *d_subof[3] = {nullptr, nullptr, nullptr};
@@ -868,6 +869,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   }
   hipStream_t s = (hipStream_t)stream;
   h->stream = s;
+  h->nn_rhs_ready = false;
   h->ir_tol = opt->ir_tol > 0.0 ? opt->ir_tol : (opt->precision == MRCM_PCG ? 1e-10 : 1e-13);
   h->pcg_max = opt->pcg_max_iter > 0 ? opt->pcg_max_iter : 50;
   h->pcg_x0 = opt->pcg_x0;
@@ -1009,7 +1011,10 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     Stage t(MRCM_STAGE_REFINE, s);
     const int4 *w1 = h->d_work + h->n_first;
     const int n1 = n_work - h->n_first;
-    ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->X, h->X, 2, H.bmax, s));
+    {
+      Stage t1(MRCM_STAGE_SOLVE_REST, s);
+      ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->X, h->X, 2, H.bmax, s));
+    }
     for (int it = 0; it < nsweep; ++it) {
       if (!own_res)
         ENQ(launch_residual(g, n1s, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s, h->d_grp_subs[1]));
@@ -1607,6 +1612,9 @@ mrcm_status nn_select(mrcm_mbfs *h, const int32_t *subs, int32_t n, hipStream_t 
   if (!h || !subs || n <= 0) return fail(MRCM_EINVAL, "null handle or empty subdomain list");
   const HostGeom &G = h->G;
   const int n_sub = (int)G.subs.size();
+  // the previous selection's upload may still be in flight from these host
+  // arrays: let the stream pass it before they change
+  if (h->d_nn_sel) HIP_TRY(hipStreamSynchronize(s));
   h->nn_sel.assign(subs, subs + n);
   h->nn_s0.resize(n);
   int s0 = 0;
@@ -1706,7 +1714,11 @@ mrcm_status mrcm_nn_features(mrcm_mbfs *h, const int32_t *subs, int32_t n_subs, 
       return fail(MRCM_ENOMEM, "device allocation of the right-hand-side buffer failed");
     h->bytes += H.totX * 8;
   }
-  HIP_TRY(launch_rhs(h->g, h->n_sub, H.max_cells, h->r0, h->R, s));
+  // the right-hand sides of the current build, formed once for all calls
+  if (!h->nn_rhs_ready) {
+    HIP_TRY(launch_rhs(h->g, h->n_sub, H.max_cells, h->r0, h->R, s));
+    h->nn_rhs_ready = true;
+  }
   HIP_TRY(launch_nn_features(h->g, h->d_nn_sel, h->d_nn_s0, n_subs, mmax, h->R, h->X, V, inp, tgt, s));
   return MRCM_OK;
 }

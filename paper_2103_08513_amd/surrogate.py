@@ -180,16 +180,20 @@ def features(model, subs, dims, targets=True):
     return inp, tgt
 
 
-def warm_start(model, net, subs, dims, x0=None):
+def warm_start(model, net, subs, dims, x0=None, chunk=4096):
     """Starting guess in the MBF layout from the network (zero for
-    subdomains not listed)."""
+    subdomains not listed), `chunk` subdomains at a time so that the
+    network's inputs and outputs stay a few GB at any workload size."""
     import torch
     lib = _lib.load()
-    inp, _ = features(model, subs, dims, targets=False)
-    out = net.predict(inp, dims)
     if x0 is None:
         x0 = torch.zeros(model.mbf_layout()[-1], dtype=torch.float64, device=model.device)
-    arr = (c_int32 * len(subs))(*subs)
-    code = lib.mrcm_nn_scatter(model._mbfs, arr, len(subs), _ptr(out), _ptr(x0), _stream())
-    _lib.check(code, "mrcm_nn_scatter")
+    for c0 in range(0, len(subs), chunk):
+        part = subs[c0:c0 + chunk]
+        inp, _ = features(model, part, dims, targets=False)
+        out = net.predict(inp, dims)
+        arr = (c_int32 * len(part))(*part)
+        code = lib.mrcm_nn_scatter(model._mbfs, arr, len(part), _ptr(out), _ptr(x0), _stream())
+        _lib.check(code, "mrcm_nn_scatter")
+        del inp, out
     return x0
