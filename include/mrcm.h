@@ -57,6 +57,21 @@ enum { MRCM_FP64 = 0,          /* FP64 band Cholesky and solves */
                                   inner iterations, FP64 residual), FP64 band
                                   Cholesky for the subdomains it leaves */
 
+/* Robin parameter on Gamma (mrcm_options.beta_mode); eq. (3.1) leaves open
+ * which K and H apply where the two sides of an interface differ. */
+enum { MRCM_BETA_PER_SIDE = 0,  /* each side its own: alpha H_own / K_d(own cell) */
+       MRCM_BETA_FACE = 1 };    /* one value per fine face, shared by both sides:
+                                   alpha H~ / K~ with H~ the harmonic mean of the two
+                                   subdomains' extents along the normal and K~ that of
+                                   the two cells' K_d across the face */
+
+/* What an MBF handle keeps after its build (mrcm_options.keep), deciding the
+ * reconstruction of Loop 2: by the combination (2.23) of the kept MBFs, or by
+ * solving the local problems again with the interface data, the second
+ * option the paper gives after (2.23). */
+enum { MRCM_KEEP_FACTORS = 1,   /* the local band factors */
+       MRCM_KEEP_MBFS = 2 };    /* the MBFs X_l (reconstruction by combination) */
+
 /*
  * The Darcy problem (Sec. 2.1).  All arrays have N = nx*ny*nz entries.
  *  kx, ky, kz  [dev] diagonal of K-hat per cell; must be positive and finite.
@@ -159,6 +174,15 @@ typedef struct {
  *              c v with c = (v, b) / (v, A v), the multiple of v closest to the
  *              solution in the A-norm (for a guess known only up to scale,
  *              such as the network output of mrcm_nn.h).
+ * beta_mode    MRCM_BETA_PER_SIDE (0, the default) or MRCM_BETA_FACE.
+ * keep         MRCM_KEEP_* bits; 0 selects MRCM_KEEP_FACTORS | MRCM_KEEP_MBFS.
+ *              Without MRCM_KEEP_MBFS, mrcm_reconstruct solves every local
+ *              problem again (particular data plus G(pi) on Gamma) with the
+ *              kept factors and the form's refinement sweeps (FP64: fp64_refine;
+ *              FP32: the build's, at least 3), and mrcm_copy_mbfs refuses.  The
+ *              build forms every MBF either way (the flux blocks reduce them),
+ *              so the handle's memory does not change.  The conjugate-gradient
+ *              form keeps no factors and needs MRCM_KEEP_MBFS.
  */
 typedef struct {
   double alpha;
@@ -171,6 +195,8 @@ typedef struct {
   int32_t pcg_x0_scale;
   int32_t solve_tiles;
   int32_t solve_group;
+  int32_t beta_mode;
+  uint32_t keep;
 } mrcm_options;
 
 typedef struct mrcm_mbfs mrcm_mbfs;           /* local factors, MBFs, Gamma-flux blocks */
@@ -307,6 +333,17 @@ mrcm_status mrcm_interface_query(const mrcm_interface *iface, mrcm_interface_inf
 mrcm_status mrcm_reconstruct(const mrcm_mbfs *mbfs, const double *X, void *stream,
                              double *p, double *U);
 
+/*
+ * Sizes and counts of a built handle.  n_patch counts the patches of the
+ * interface space (each carries two unknowns, so 2 n_patch is the interface
+ * system's size, the N_Gamma of eq. (2.24) for one patch per interface);
+ * n_mbfs = sum over subdomains of 2|I^l| and n_rhs = n_mbfs + n_sub: one
+ * P-type and one U-type MBF per patch of the subdomain, eq. (2.25), plus the
+ * particular problem, eq. (2.26), as counted in Sec. 2.2.3 (13 for an
+ * interior subdomain with one patch per face).  factor_flops and solve_flops
+ * are the band algorithms' own operation counts; ir_* and pcg_* describe the
+ * last build.
+ */
 mrcm_status mrcm_query(const mrcm_mbfs *mbfs, mrcm_info *info /* [host] */);
 mrcm_status mrcm_get_subdomain(const mrcm_mbfs *mbfs, int32_t l, mrcm_subdomain_info *info /* [host] */);
 

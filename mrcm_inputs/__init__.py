@@ -99,6 +99,9 @@ class Case:
     partition: Partition
     iface: IfaceSpace
     alpha: float = 1.0
+    # Robin parameter on Gamma: 0 per side (own subdomain extent and own cell's
+    # permeability), 1 one value per face shared by both sides
+    beta_mode: int = 0
 
 
 # ----------------------------------------------------------------------------

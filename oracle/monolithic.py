@@ -24,8 +24,8 @@ from .geometry import Geometry
 from .mrcm import local_system
 
 
-def _blocks(pb, geo, alpha):
-    return [local_system(pb, geo, l, alpha) for l in range(geo.n_sub)]
+def _blocks(pb, geo, alpha, beta_mode=0):
+    return [local_system(pb, geo, l, alpha, beta_mode) for l in range(geo.n_sub)]
 
 
 def mrcm_monolithic(case):
@@ -35,7 +35,7 @@ def mrcm_monolithic(case):
     N, NV = pb.n, geo.n_patch
     rows, cols, vals = [], [], []
     rhs = np.zeros(N + 2 * NV)
-    for ls in _blocks(pb, geo, alpha):
+    for ls in _blocks(pb, geo, alpha, getattr(case, "beta_mode", 0)):
         M = ls.M.tocoo()
         rows.append(ls.cells[M.row])
         cols.append(ls.cells[M.col])

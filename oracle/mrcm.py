@@ -75,13 +75,23 @@ def robin_beta(alpha, H, K):
     return alpha * H / K
 
 
+def harmonic_mean(a, b):
+    return 2.0 * a * b / (a + b)
+
+
 def robin_transmissibility(A, h, K, beta):
     """Q = T (p_c - G) for a Robin face: T = A / (h / (2K) + beta)."""
     return A / (h / (2.0 * K) + beta)
 
 
-def gamma_faces(pb, geo, l, alpha):
-    """Enumerate the Robin faces of subdomain l (faces of its box on Gamma)."""
+def gamma_faces(pb, geo, l, alpha, beta_mode=0):
+    """Enumerate the Robin faces of subdomain l (faces of its box on Gamma).
+
+    beta_mode 0: beta per side, eq. (3.1) with the own subdomain's extent H
+    along the normal and the own cell's K.  beta_mode 1: one beta per fine
+    face shared by both sides, eq. (3.1) with the harmonic means of the two
+    sides' H and of the two cells' K (the two-point face value of K, as in
+    (2.10))."""
     nx, ny, _ = pb.dims
     lo, hi = geo.sub_lo[l], geo.sub_hi[l]
     ext = hi - lo
@@ -100,6 +110,9 @@ def gamma_faces(pb, geo, l, alpha):
         ia = split_index(I["la"], I["na"])
         ib = split_index(I["lb"], I["nb"])
         H = ext[d] * pb.h[d]
+        other = I["hi_sub"] if sigma > 0 else I["lo_sub"]
+        H_other = (geo.sub_hi[other][d] - geo.sub_lo[other][d]) * pb.h[d]
+        stride = (1, nx, nx * pb.dims[1])[d]
         A = face_area(pb.h, d)
         for tb in range(I["lb"]):
             for ta in range(I["la"]):
@@ -110,7 +123,11 @@ def gamma_faces(pb, geo, l, alpha):
                 lc = x[0] + ext[0] * (x[1] + ext[1] * x[2])
                 gc = (lo[0] + x[0]) + nx * ((lo[1] + x[1]) + ny * (lo[2] + x[2]))
                 K = Ks[d][gc]
-                beta = robin_beta(alpha, H, K)
+                if beta_mode == 0:
+                    beta = robin_beta(alpha, H, K)
+                else:
+                    Kn = Ks[d][gc + (stride if sigma > 0 else -stride)]
+                    beta = robin_beta(alpha, harmonic_mean(H, H_other), harmonic_mean(K, Kn))
                 p = I["p0"] + ia[ta] + I["na"] * ib[tb]
                 out["cell"].append(lc)
                 out["gcell"].append(gc)
@@ -126,7 +143,7 @@ def gamma_faces(pb, geo, l, alpha):
                          for k, v in out.items()})
 
 
-def local_system(pb, geo, l, alpha):
+def local_system(pb, geo, l, alpha, beta_mode=0):
     """A^H_l and the right-hand sides of (2.25)/(2.26) for subdomain l."""
     lo, hi = geo.sub_lo[l], geo.sub_hi[l]
     ext = hi - lo
@@ -154,7 +171,7 @@ def local_system(pb, geo, l, alpha):
         cols += [n, c]
         vals += [-t, -t]
     # Robin faces on Gamma
-    g = gamma_faces(pb, geo, l, alpha)
+    g = gamma_faces(pb, geo, l, alpha, beta_mode)
     np.add.at(diag, g.cell, g.T)
     patches = geo.sub_patches[l]
     n = len(patches)
@@ -321,8 +338,8 @@ class MRCMResult:
     geo: Geometry
 
 
-def _one_subdomain(pb, geo, l, alpha, extended):
-    ls = local_system(pb, geo, l, alpha)
+def _one_subdomain(pb, geo, l, alpha, extended, beta_mode=0):
+    ls = local_system(pb, geo, l, alpha, beta_mode)
     X = local_solve(ls, extended)
     F, Fb, SAb = gamma_flux_blocks(ls, X)
     return ls, X, F, Fb, SAb
@@ -332,8 +349,8 @@ _POOL_ARGS = None
 
 
 def _pool_task(l):
-    pb, geo, alpha, extended = _POOL_ARGS
-    return _one_subdomain(pb, geo, l, alpha, extended)
+    pb, geo, alpha, extended, beta_mode = _POOL_ARGS
+    return _one_subdomain(pb, geo, l, alpha, extended, beta_mode)
 
 
 def _pool_init():
@@ -345,7 +362,7 @@ def _pool_init():
         pass
 
 
-def build_mbfs(pb, geo, alpha, subdomains=None, extended=True, processes=1):
+def build_mbfs(pb, geo, alpha, subdomains=None, extended=True, processes=1, beta_mode=0):
     """Loop 1 of Algorithm 2: local systems, MBFs and their Gamma-flux blocks.
 
     The subdomains are independent; ``processes`` > 1 spreads them over a
@@ -354,14 +371,14 @@ def build_mbfs(pb, geo, alpha, subdomains=None, extended=True, processes=1):
     subs = list(range(geo.n_sub) if subdomains is None else subdomains)
     if processes > 1 and len(subs) > 1:
         import multiprocessing as mp
-        _POOL_ARGS = (pb, geo, alpha, extended)
+        _POOL_ARGS = (pb, geo, alpha, extended, beta_mode)
         try:
             with mp.get_context("fork").Pool(processes, initializer=_pool_init) as pool:
                 out = pool.map(_pool_task, subs, chunksize=max(1, len(subs) // (8 * processes)))
         finally:
             _POOL_ARGS = None
     else:
-        out = [_one_subdomain(pb, geo, l, alpha, extended) for l in subs]
+        out = [_one_subdomain(pb, geo, l, alpha, extended, beta_mode) for l in subs]
     systems = [o[0] for o in out]
     Xs = [o[1] for o in out]
     Fs = [o[2] for o in out]
@@ -459,13 +476,16 @@ def mrcm_solve(case_or_problem, partition=None, iface=None, alpha=None, extended
     ``extended``: refine every local solve and the interface solve with an
     extended-precision residual (see ``refined_solve``); False gives the plain
     FP64 algorithm.  ``processes``: worker processes for loop 1."""
+    beta_mode = 0
     if partition is None:
         case = case_or_problem
         pb, partition, iface, alpha = case.problem, case.partition, case.iface, case.alpha
+        beta_mode = getattr(case, "beta_mode", 0)
     else:
         pb = case_or_problem
     geo = Geometry(pb.dims, partition, iface)
-    systems, Xs, Fs, Fbs, SAbs = build_mbfs(pb, geo, alpha, extended=extended, processes=processes)
+    systems, Xs, Fs, Fbs, SAbs = build_mbfs(pb, geo, alpha, extended=extended, processes=processes,
+                                            beta_mode=beta_mode)
     blocks = [(ls.patches, patch_sigma(ls), F, Fb, SAb)
               for ls, F, Fb, SAb in zip(systems, Fs, Fbs, SAbs)]
     if geo.n_patch > 0:

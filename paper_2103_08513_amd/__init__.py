@@ -20,12 +20,19 @@ FP64 = 0
 FP32_IR = 1
 PCG = 2
 
+# Robin parameter on Gamma and what a handle keeps (mrcm_options)
+BETA_PER_SIDE = 0
+BETA_FACE = 1
+KEEP_FACTORS = 1
+KEEP_MBFS = 2
+
 # interface solvers (mrcm_solve_interface)
 IFACE_AUTO = 0
 IFACE_BAND = 1
 IFACE_MULTIFRONTAL = 2
 
 __all__ = ["MRCM", "MRCMError", "FP64", "FP32_IR", "PCG", "IFACE_AUTO", "IFACE_BAND", "IFACE_MULTIFRONTAL",
+           "BETA_PER_SIDE", "BETA_FACE", "KEEP_FACTORS", "KEEP_MBFS",
            "build_mbfs", "assemble_interface",
            "solve_interface", "reconstruct", "library"]
 
@@ -93,7 +100,8 @@ class MRCM:
     ``mrcm_inputs`` (or any objects with the same attributes)."""
 
     def __init__(self, problem, partition, iface, alpha=1.0, precision=FP64, ir_tol=1e-13,
-                 ir_max_iter=30, fp64_refine=1, pcg_max_iter=50, solve_tiles=0, solve_group=0, device="cuda"):
+                 ir_max_iter=30, fp64_refine=1, pcg_max_iter=50, solve_tiles=0, solve_group=0, device="cuda",
+                 beta_mode=BETA_PER_SIDE, keep=KEEP_FACTORS | KEEP_MBFS):
         import torch
         self.lib = library()
         self.device = torch.device(device)
@@ -150,6 +158,8 @@ class MRCM:
         opt.pcg_max_iter = int(pcg_max_iter)
         opt.solve_tiles = int(solve_tiles)
         opt.solve_group = int(solve_group)
+        opt.beta_mode = int(beta_mode)
+        opt.keep = int(keep)
         opt.pcg_x0 = None
         self._opt = opt
 

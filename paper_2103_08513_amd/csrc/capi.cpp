@@ -57,6 +57,8 @@ struct HostGeom {
   int n[3];
   double h[3];
   double alpha;
+  int beta_mode = 0;
+  uint32_t keep = 0;
   int precision;
   int wall_type[6];
   int64_t pin;
@@ -88,6 +90,8 @@ struct ConfigKey {
   int32_t wall_type[6] = {0, 0, 0, 0, 0, 0};
   int64_t pin = 0;
   double alpha = 0.0;
+  int32_t beta_mode = 0;
+  uint32_t keep = 0;
   int32_t precision = 0;
   int32_t solve_tiles = 0, solve_group = 0;
   std::vector<int32_t> cuts[3];
@@ -100,8 +104,8 @@ struct ConfigKey {
         return false;
     for (int f = 0; f < 6; ++f)
       if (wall_type[f] != o.wall_type[f]) return false;
-    return pin == o.pin && alpha == o.alpha && precision == o.precision && split == o.split &&
-           solve_tiles == o.solve_tiles && solve_group == o.solve_group;
+    return pin == o.pin && alpha == o.alpha && beta_mode == o.beta_mode && keep == o.keep && precision == o.precision &&
+           split == o.split && solve_tiles == o.solve_tiles && solve_group == o.solve_group;
   }
 };
 
@@ -118,6 +122,8 @@ bool make_key(const mrcm_problem *pb, const mrcm_partition *part, const mrcm_ifa
   for (int f = 0; f < 6; ++f) k.wall_type[f] = pb->wall_type[f];
   k.pin = pb->pin_cell;
   k.alpha = opt->alpha;
+  k.beta_mode = opt->beta_mode;
+  k.keep = opt->keep;
   k.precision = opt->precision;
   k.solve_tiles = opt->solve_tiles;
   k.solve_group = opt->solve_group;
@@ -142,8 +148,9 @@ bool same_config(const HostGeom &a, const HostGeom &b) {
     if (a.n[d] != b.n[d] || a.h[d] != b.h[d] || a.cuts[d] != b.cuts[d]) return false;
   for (int f = 0; f < 6; ++f)
     if (a.wall_type[f] != b.wall_type[f]) return false;
-  return a.alpha == b.alpha && a.precision == b.precision && a.pin == b.pin && a.split == b.split &&
-         a.solve_tiles == b.solve_tiles && a.solve_group == b.solve_group;
+  return a.alpha == b.alpha && a.beta_mode == b.beta_mode && a.keep == b.keep && a.precision == b.precision &&
+         a.pin == b.pin &&
+         a.split == b.split && a.solve_tiles == b.solve_tiles && a.solve_group == b.solve_group;
 }
 
 mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
@@ -174,6 +181,9 @@ mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
     return fail(MRCM_EINVAL, "a pinned cell or a Dirichlet wall is needed to fix the pressure");
   G.alpha = opt->alpha;
   if (!(G.alpha > 0.0) || !std::isfinite(G.alpha)) return fail(MRCM_EINVAL, "alpha must be positive");
+  G.beta_mode = opt->beta_mode;
+  if (G.beta_mode != MRCM_BETA_PER_SIDE && G.beta_mode != MRCM_BETA_FACE)
+    return fail(MRCM_EINVAL, "beta_mode must be MRCM_BETA_PER_SIDE or MRCM_BETA_FACE");
   G.precision = opt->precision;
   if (opt->solve_tiles < 0 || opt->solve_tiles > solve_chunk_max() / 16)
     return fail(MRCM_EINVAL, "solve_tiles must be in [0, " + std::to_string(solve_chunk_max() / 16) + "]");
@@ -182,6 +192,12 @@ mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
   G.solve_group = opt->solve_group;
   if (G.precision != MRCM_FP64 && G.precision != MRCM_FP32_IR && G.precision != MRCM_PCG)
     return fail(MRCM_EINVAL, "precision must be MRCM_FP64, MRCM_FP32_IR or MRCM_PCG");
+  G.keep = opt->keep ? opt->keep : (MRCM_KEEP_FACTORS | MRCM_KEEP_MBFS);
+  if (G.keep & ~(uint32_t)(MRCM_KEEP_FACTORS | MRCM_KEEP_MBFS)) return fail(MRCM_EINVAL, "unknown keep bits");
+  if (!(G.keep & MRCM_KEEP_MBFS) && !(G.keep & MRCM_KEEP_FACTORS))
+    return fail(MRCM_EINVAL, "reconstruction needs the MBFs or the factors: keep one of them");
+  if (!(G.keep & MRCM_KEEP_MBFS) && G.precision == MRCM_PCG)
+    return fail(MRCM_EINVAL, "the conjugate-gradient form keeps no factors: reconstruction needs the MBFs");
 
   const int nd[3] = {part->ndx, part->ndy, part->ndz};
   const int32_t *cut_in[3] = {part->cut_x, part->cut_y, part->cut_z};
@@ -549,6 +565,12 @@ struct mrcm_mbfs {
   std::vector<int> nn_sel, nn_s0;
   int *d_patches = nullptr;
   int *d_subof[3] = {nullptr, nullptr, nullptr};
+  // reconstruction by re-solve (keep without MRCM_KEEP_MBFS): descriptors of
+  // one right-hand side per subdomain, its work list and vectors
+  uint32_t keep = MRCM_KEEP_FACTORS | MRCM_KEEP_MBFS;
+  SubDesc *d_sub_rs = nullptr;
+  int4 *d_work_rs = nullptr;
+  double *Brs = nullptr, *Xrs = nullptr, *Rrs = nullptr;
   double *coef = nullptr, *r0 = nullptr, *scal = nullptr;
   void *L = nullptr, *Dinv = nullptr;
   double *X = nullptr, *R = nullptr;
@@ -596,7 +618,8 @@ void free_mbfs(mrcm_mbfs *h) {
   void *ptrs[] = {h->d_sub, h->d_ifc, h->d_order, h->d_work, h->d_patches, h->d_subof[0], h->d_subof[1],
                   h->d_subof[2], h->coef, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, h->R0, h->F, h->Fb, h->SAb,
                   h->norms, h->scalar, h->st, h->d_grp_subs[0], h->d_grp_subs[1], h->d_order_split,
-                  h->d_colsub, h->d_iters, h->d_conv, h->d_fb_order, h->d_fb_work, h->d_nn_sel, h->d_nn_s0};
+                  h->d_colsub, h->d_iters, h->d_conv, h->d_fb_order, h->d_fb_work, h->d_nn_sel, h->d_nn_s0,
+                  h->d_sub_rs, h->d_work_rs, h->Brs, h->Xrs, h->Rrs};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
@@ -792,6 +815,7 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
     g.nd[d] = (int)G.cuts[d].size() - 1;
   }
   g.alpha = G.alpha;
+  g.beta_mode = G.beta_mode;
   for (int f = 0; f < 6; ++f) g.wall_type[f] = G.wall_type[f];
   g.pin = G.pin;
   g.sub = h->d_sub;
@@ -1317,6 +1341,50 @@ mrcm_status mrcm_interface_query(const mrcm_interface *h, mrcm_interface_info *i
   return MRCM_OK;
 }
 
+namespace {
+
+// The second reconstruction option: every local problem solved again with
+// the particular data and G(pi) on Gamma, by the kept band factors, then
+// the FP64 refinement sweeps of the build's form.
+mrcm_status reconstruct_resolve(const mrcm_mbfs *cmb, const double *X, hipStream_t s, double *p) {
+  mrcm_mbfs *mb = const_cast<mrcm_mbfs *>(cmb);  // lazily allocated re-solve buffers
+  const HostGeom &G = mb->G;
+  if (!mb->d_sub_rs) {
+    if (g_capturing) return fail(MRCM_EUNSUPPORTED, "the re-solve allocates on its first use: not under capture");
+    std::vector<SubDesc> rs(G.subs);
+    std::vector<int4> work;
+    for (SubDesc &S : rs) {
+      S.m = 1;
+      S.X_off = S.cell_off;
+    }
+    for (int l : G.order) work.push_back(make_int4(l, 0, 1, 0));
+    HIP_TRY(upload(&mb->d_sub_rs, rs));
+    HIP_TRY(upload(&mb->d_work_rs, work));
+    if (dev_alloc(&mb->Brs, (size_t)G.totCells) != hipSuccess || dev_alloc(&mb->Xrs, (size_t)G.totCells) != hipSuccess ||
+        dev_alloc(&mb->Rrs, (size_t)G.totCells) != hipSuccess)
+      return fail(MRCM_ENOMEM, "device allocation of the re-solve vectors failed");
+    mb->bytes += 24 * G.totCells;
+  }
+  Geom g1 = mb->g;
+  g1.sub = mb->d_sub_rs;
+  const int fp32 = G.precision == MRCM_FP32_IR;
+  const int n = mb->n_sub;
+  HIP_TRY(launch_resolve_rhs(g1, n, G.max_cells, mb->r0, X, G.n_patch, mb->Brs, s));
+  // the band solve overwrites its right-hand side with the forward sweep's
+  // result: solve a copy in place and keep Brs for the residuals
+  HIP_TRY(launch_copy(mb->Brs, mb->Xrs, G.totCells, s));
+  HIP_TRY(launch_solve(fp32, g1, mb->d_work_rs, n, mb->scal, mb->L, mb->Dinv, mb->Xrs, mb->Xrs, 0, G.bmax, s));
+  const int sweeps = fp32 ? std::max(3, mb->ir_iters) : mb->refine64;
+  for (int it = 0; it < sweeps; ++it) {
+    HIP_TRY(launch_resolve_residual(g1, n, G.max_cells, mb->coef, mb->Brs, mb->Xrs, mb->Rrs, s));
+    HIP_TRY(launch_solve(fp32, g1, mb->d_work_rs, n, mb->scal, mb->L, mb->Dinv, mb->Rrs, mb->Xrs, 1, G.bmax, s));
+  }
+  HIP_TRY(launch_resolve_scatter(g1, n, G.max_cells, mb->Xrs, p, s));
+  return MRCM_OK;
+}
+
+}  // namespace
+
 mrcm_status mrcm_reconstruct(const mrcm_mbfs *mb, const double *X, void *stream, double *p,
                              double *U) {
   if (!mb || !p || !U) return fail(MRCM_EINVAL, "null argument");
@@ -1324,7 +1392,12 @@ mrcm_status mrcm_reconstruct(const mrcm_mbfs *mb, const double *X, void *stream,
   hipStream_t s = (hipStream_t)stream;
   {
     Stage t(MRCM_STAGE_RECONSTRUCT, s);
-    HIP_TRY(launch_recon_p(mb->g, mb->n_sub, mb->d_patches, mb->X, X, mb->G.n_patch, p, s));
+    if (mb->G.keep & MRCM_KEEP_MBFS) {
+      HIP_TRY(launch_recon_p(mb->g, mb->n_sub, mb->d_patches, mb->X, X, mb->G.n_patch, p, s));
+    } else {
+      mrcm_status st = reconstruct_resolve(mb, X, s, p);
+      if (st != MRCM_OK) return st;
+    }
     HIP_TRY(launch_recon_u(mb->g, p, X, mb->G.n_patch, U, s));
   }
   if (g_prof.on && !g_capturing) {
@@ -1375,6 +1448,7 @@ mrcm_status mrcm_get_subdomain(const mrcm_mbfs *mb, int32_t l, mrcm_subdomain_in
 
 mrcm_status mrcm_copy_mbfs(const mrcm_mbfs *mb, int32_t l, double *X) {
   if (!mb || !X) return fail(MRCM_EINVAL, "null argument");
+  if (!(mb->G.keep & MRCM_KEEP_MBFS)) return fail(MRCM_EINVAL, "the handle does not keep its MBFs");
   if (l < 0 || l >= (int32_t)mb->G.subs.size()) return fail(MRCM_EINVAL, "subdomain out of range");
   const SubDesc &S = mb->G.subs[l];
   HIP_TRY(hipStreamSynchronize(mb->stream));

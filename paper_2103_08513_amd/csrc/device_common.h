@@ -153,10 +153,32 @@ __device__ __forceinline__ long long cell_index(const Geom &g, const I3 &x) {
   return (long long)x.v0 + (long long)g.nx * ((long long)x.v1 + (long long)g.ny * x.v2);
 }
 
+// Robin parameter, eq. (3.1), of face f (on Gamma) of the cell at global
+// coordinates x in subdomain S, whose permeability along the normal is kd:
+// beta_mode 0, per side, beta = alpha H_d / K_d(c) with H_d the subdomain's
+// extent along the normal; beta_mode 1, one value per face shared by both
+// sides, with the harmonic means of the two sides' H_d and of the two cells'
+// K_d across the face.
+__device__ __forceinline__ double robin_beta(const Geom &g, const SubDesc &S, const I3 &x, int f, double kd) {
+  const int d = f >> 1;
+  const double hd = hdir(g, d);
+  double H = S.ext[d] * hd, Kb = kd;
+  if (g.beta_mode) {
+    I3 y = x;
+    y.set(d, x[d] + ((f & 1) ? 1 : -1));
+    const double kn = kdir(g, d)[cell_index(g, y)];
+    const IfaceDesc &I = g.ifc[S.face_if[f]];
+    const double Ho = g.sub[(f & 1) ? I.hi_sub : I.lo_sub].ext[d] * hd;
+    H = 2.0 * H * Ho / (H + Ho);
+    Kb = 2.0 * kd * kn / (kd + kn);
+  }
+  return g.alpha * H / Kb;
+}
+
 // Robin face rule.  Face f (-x..+z) of the cell at global coordinates x in
 // subdomain S lies on Gamma when the neighbour across it is outside the box
-// but inside the domain.  Then: local patch lp, Robin parameter
-// beta = alpha H_d / K_d(c), transmissibility T = A_d / (h_d / (2 K_d) + beta)
+// but inside the domain.  Then: local patch lp, Robin parameter beta
+// (robin_beta), transmissibility T = A_d / (h_d / (2 K_d(c)) + beta)
 // and sigma = +1 on a + face (lower side of the interface), -1 on a - face.
 __device__ __forceinline__ bool gamma_face(const Geom &g, const SubDesc &S, const I3 &x, int f,
                                            double kd, int &lp, double &T, double &beta) {
@@ -172,7 +194,7 @@ __device__ __forceinline__ bool gamma_face(const Geom &g, const SubDesc &S, cons
   const int tb = x[I.b] - S.lo[I.b];
   lp = S.face_p0[f] + split_group(ta, I.la, I.na) + I.na * split_group(tb, I.lb, I.nb);
   const double hd = hdir(g, d);
-  beta = g.alpha * (ext * hd) / kd;
+  beta = robin_beta(g, S, x, f, kd);
   T = adir(g, d) / (hd / (2.0 * kd) + beta);
   return true;
 }

@@ -54,6 +54,7 @@ struct Geom {
   double h[3];
   double area[3];       // face areas V/h_d
   double alpha;
+  int32_t beta_mode;    // 0 per side, 1 one value per face shared by both sides
   int32_t wall_type[6];
   const double *wall_value[6];
   const double *k[3];   // kx, ky, kz

@@ -38,6 +38,16 @@ hipError_t launch_ir_check(const double *norms, int ncols, double *out, hipStrea
 hipError_t launch_flux(const Geom &g, int n_sub, const double *X, double *F, double *Fb,
                        double *SAb, hipStream_t s);
 
+// Reconstruction by re-solve: one right-hand side per subdomain (B, X, R at
+// each subdomain's cell offset), its residual from the coefficients, and the
+// scatter of the solution into the global pressure.
+hipError_t launch_resolve_rhs(const Geom &g, int n_sub, int max_cells, const double *r0, const double *pi, int nv,
+                              double *B, hipStream_t s);
+hipError_t launch_resolve_residual(const Geom &g, int n_sub, int max_cells, const double *coef, const double *B,
+                                   const double *X, double *R, hipStream_t s);
+hipError_t launch_resolve_scatter(const Geom &g, int n_sub, int max_cells, const double *X, double *p,
+                                  hipStream_t s);
+
 // Conjugate-gradient form of the local solves (pcg_kernels.hip).  One
 // workgroup per column (subdomain by col_sub); X0 null for a zero start.
 int pcg_max_cells();

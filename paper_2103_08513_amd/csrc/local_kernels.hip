@@ -69,7 +69,7 @@ __global__ void k_coef(Geom g, double *__restrict__ coef, double *__restrict__ r
         t2 = (p == 2) ? tv : t2;
       }
     } else if (xn >= 0 && xn < ndir(g, d)) {
-      const double beta = g.alpha * (ext * hd) / kd;
+      const double beta = robin_beta(g, S, x, f, kd);
       diag += ad / (hd / (2.0 * kd) + beta);
     } else {
       const int wt = wall_type_of(g, f);
@@ -1275,7 +1275,6 @@ __global__ __launch_bounds__(256) void k_flux(Geom g, const double *__restrict__
     const int d = f >> 1;
     const int sigma = (f & 1) ? 1 : -1;
     const double hd = hdir(g, d), A = adir(g, d);
-    const double H = S.ext[d] * hd;
     const double *kd_arr = kdir(g, d);
     const int xd = sigma < 0 ? S.lo[d] : S.lo[d] + S.ext[d] - 1;
     double sf = 0.0, sb = 0.0, sab = 0.0;
@@ -1286,7 +1285,7 @@ __global__ __launch_bounds__(256) void k_flux(Geom g, const double *__restrict__
         x.set(I.b, S.lo[I.b] + tb);
         x.set(d, xd);
         const double kd = kd_arr[cell_index(g, x)];
-        const double beta = g.alpha * H / kd;
+        const double beta = robin_beta(g, S, x, f, kd);
         const double T = A / (hd / (2.0 * kd) + beta);
         const double G = (c == 1 + lp) ? 1.0 : ((c == 1 + n + lp) ? -sigma * beta : 0.0);
         const double Q = T * (X[(size_t)local_row(S, x) * m + c] - G);
@@ -1299,6 +1298,68 @@ __global__ __launch_bounds__(256) void k_flux(Geom g, const double *__restrict__
     Fb[S.F_off + (size_t)lp * m + c] = sb;
     if (c == 0) SAb[S.patch_off + lp] = sab;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction by solving the local problems again (the second option the
+// paper gives after the combination (2.23)): one right-hand side per
+// subdomain, the particular data plus T_f G_f(pi) on every Robin face with
+// G_f = pi^p - sigma beta_f pi^u, solved with the kept band factors.  The
+// vectors are per subdomain, N_l rows at the subdomain's cell offset.
+// ---------------------------------------------------------------------------
+__global__ void k_resolve_rhs(Geom g, const double *__restrict__ r0, const double *__restrict__ pi, int nv,
+                              double *__restrict__ B) {
+  const SubDesc &S = g.sub[blockIdx.y];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= S.N) return;
+  double v = r0[S.cell_off + r];  // zero on the pinned row
+  if (r != S.pin_local) {
+    const I3 x = local_to_global(S, r);
+    const long long c = cell_index(g, x);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1;
+      const int sigma = (f & 1) ? 1 : -1;
+      const int xn = x[d] + sigma;
+      if (xn >= S.lo[d] && xn < S.lo[d] + S.ext[d]) continue;
+      int lp;
+      double T, beta;
+      if (gamma_face(g, S, x, f, kdir(g, d)[c], lp, T, beta)) {
+        const int patch = g.ifc[S.face_if[f]].p0 + (lp - S.face_p0[f]);
+        v += T * (pi[patch] - sigma * beta * pi[nv + patch]);
+      }
+    }
+  }
+  B[S.cell_off + r] = v;
+}
+
+// R = B - A X for one column per subdomain, A from the stored coefficients
+// (diagonal, and the transmissibilities to the +ax0, +ax1, +ax2 neighbours,
+// whose negatives are the off-diagonal entries on both sides).
+__global__ void k_resolve_residual(Geom g, const double *__restrict__ coef, const double *__restrict__ B,
+                                   const double *__restrict__ X, double *__restrict__ R) {
+  const SubDesc &S = g.sub[blockIdx.y];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = S.N;
+  if (r >= N) return;
+  const double *cf = coef + 4 * S.cell_off;
+  const double *x = X + S.cell_off;
+  const int st[3] = {1, S.n0, S.b};
+  double acc = cf[4 * r] * x[r];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (r + st[k] < N) acc -= cf[4 * r + 1 + k] * x[r + st[k]];
+    if (r - st[k] >= 0) acc -= cf[4 * (r - st[k]) + 1 + k] * x[r - st[k]];
+  }
+  R[S.cell_off + r] = B[S.cell_off + r] - acc;
+}
+
+// p at the global cells from the per-subdomain solution vectors.
+__global__ void k_resolve_scatter(Geom g, const double *__restrict__ X, double *__restrict__ p) {
+  const SubDesc &S = g.sub[blockIdx.y];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= S.N) return;
+  p[cell_index(g, local_to_global(S, r))] = X[S.cell_off + r];
 }
 
 }  // namespace mrcm
@@ -1495,6 +1556,27 @@ hipError_t launch_ir_check(const double *norms, int ncols, double *out, hipStrea
 hipError_t launch_flux(const Geom &g, int n_sub, const double *X, double *F, double *Fb,
                        double *SAb, hipStream_t s) {
   hipLaunchKernelGGL(k_flux, dim3(n_sub), dim3(256), 0, s, g, X, F, Fb, SAb);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve_rhs(const Geom &g, int n_sub, int max_cells, const double *r0, const double *pi, int nv,
+                              double *B, hipStream_t s) {
+  dim3 grid((max_cells + 255) / 256, n_sub);
+  hipLaunchKernelGGL(k_resolve_rhs, grid, dim3(256), 0, s, g, r0, pi, nv, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve_residual(const Geom &g, int n_sub, int max_cells, const double *coef, const double *B,
+                                   const double *X, double *R, hipStream_t s) {
+  dim3 grid((max_cells + 255) / 256, n_sub);
+  hipLaunchKernelGGL(k_resolve_residual, grid, dim3(256), 0, s, g, coef, B, X, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve_scatter(const Geom &g, int n_sub, int max_cells, const double *X, double *p,
+                                  hipStream_t s) {
+  dim3 grid((max_cells + 255) / 256, n_sub);
+  hipLaunchKernelGGL(k_resolve_scatter, grid, dim3(256), 0, s, g, X, p);
   return hipGetLastError();
 }
 

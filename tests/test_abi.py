@@ -78,7 +78,7 @@ def test_host_validation_rejects_bad_arguments_before_any_gpu_work():
 
 def test_ctypes_layout_matches_c(tmp_path):
     """sizeof/offsetof of the ABI structs, from the C compiler, equal ctypes'."""
-    from paper_2103_08513_amd._lib import CInfo, CIfaceSpace, COptions, CPartition, CProblem, CSubInfo
+    from paper_2103_08513_amd._lib import CIfaceInfo, CInfo, CIfaceSpace, COptions, CPartition, CProblem, CSubInfo
     src = tmp_path / "layout.c"
     src.write_text(f'''
 #include <stdio.h>
@@ -92,6 +92,8 @@ int main(void) {{
   printf("%zu %zu %zu %zu %zu\\n", offsetof(mrcm_options, pcg_max_iter), offsetof(mrcm_options, pcg_x0), offsetof(mrcm_options, pcg_x0_scale), offsetof(mrcm_options, solve_tiles), offsetof(mrcm_options, solve_group));
   printf("%zu %zu %zu %zu %zu\\n", sizeof(mrcm_info), offsetof(mrcm_info, ir_residual), offsetof(mrcm_info, device_bytes), offsetof(mrcm_info, pcg_fallback), offsetof(mrcm_info, pcg_iters));
   printf("%zu %zu %zu\\n", sizeof(mrcm_subdomain_info), offsetof(mrcm_subdomain_info, pin_local), offsetof(mrcm_subdomain_info, solve_group));
+  printf("%zu %zu\\n", offsetof(mrcm_options, beta_mode), offsetof(mrcm_options, keep));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(mrcm_interface_info), offsetof(mrcm_interface_info, front_bytes), offsetof(mrcm_interface_info, factor_flops), offsetof(mrcm_interface_info, device_bytes), offsetof(mrcm_interface_info, rel_residual));
   return 0;
 }}
 ''')
@@ -109,6 +111,9 @@ int main(void) {{
         [ctypes.sizeof(CInfo), CInfo.ir_residual.offset, CInfo.device_bytes.offset, CInfo.pcg_fallback.offset,
          CInfo.pcg_iters.offset],
         [ctypes.sizeof(CSubInfo), CSubInfo.pin_local.offset, CSubInfo.solve_group.offset],
+        [COptions.beta_mode.offset, COptions.keep.offset],
+        [ctypes.sizeof(CIfaceInfo), CIfaceInfo.front_bytes.offset, CIfaceInfo.factor_flops.offset,
+         CIfaceInfo.device_bytes.offset, CIfaceInfo.rel_residual.offset],
     ]
     assert got == want
 
@@ -140,6 +145,17 @@ def test_host_validation_of_the_forms_and_tunables():
     opt.solve_group = -2
     assert build() == -1 and b"solve_group" in lib.mrcm_last_error()
     opt.solve_group = 0
+    opt.beta_mode = 2
+    assert build() == -1 and b"beta_mode" in lib.mrcm_last_error()
+    opt.beta_mode = 1
+    opt.keep = 4
+    assert build() == -1 and b"keep" in lib.mrcm_last_error()
+    opt.keep = 2 | 1
+    opt.precision = 2
+    opt.keep = 1                  # re-solve without MBFs needs factors the CG form does not keep
+    assert build() == -1 and b"conjugate-gradient form keeps no factors" in lib.mrcm_last_error()
+    opt.keep = 0
+    opt.beta_mode = 0
     opt.precision = 3
     assert build() == -1 and b"precision" in lib.mrcm_last_error()
     opt.precision = 2             # conjugate gradients: at most 2048 cells per block
@@ -166,6 +182,9 @@ def test_host_validation_of_the_forms_and_tunables():
                                   ctypes.byref(g)) == -1
     assert lib.mrcm_graph_launch(None, None) == -1
     assert lib.mrcm_autotune(None, None, None, None, None, None, None, None) == -1
+    # interface solve arguments
+    assert lib.mrcm_solve_interface(None, 0, 0.0, 0, None, None, None, None) == -1
+    assert lib.mrcm_interface_query(None, None) == -1
 
 
 def test_binding_refuses_wall_data_of_the_wrong_length():

@@ -380,3 +380,59 @@ def test_interface_solvers_agree_with_the_oracle(name):
     torch.cuda.synchronize()
     assert np.array_equal(X2.cpu().numpy(), sols[(lib.IFACE_MULTIFRONTAL, 2)])
     m.close()
+
+
+@pytest.mark.parametrize("name", ["coarse-patches", "ragged", "thin-slabs"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_face_shared_beta_against_the_oracle(name, precision):
+    """beta_mode = MRCM_BETA_FACE: one Robin parameter per fine face, shared
+    by both sides (harmonic means of the sides' extents and of the two cells'
+    permeabilities), in every kernel that forms a Robin term; MBFs, flux blocks
+    and the solution against the oracle under the same reading."""
+    import paper_2103_08513_amd as lib
+    case = small_case(**CASES[name])
+    case.beta_mode = 1
+    ref = mrcm_solve(case)
+    pb = case.problem
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision, beta_mode=lib.BETA_FACE)
+    p, U, X = m.solve(_dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q), refine=2)
+    torch.cuda.synchronize()
+    _check_local_blocks(m, ref, tol=1e-10 if precision == 0 else 1e-9)
+    for a, b in ((X, ref.pi), (p, ref.p), (U, ref.U)):
+        assert rel_l2(a.cpu().numpy(), b) < 1e-9
+    # the per-side reading is a different (equally valid) answer
+    base = mrcm_solve(small_case(**CASES[name]))
+    assert rel_l2(base.p, ref.p) > 1e-6
+    m.close()
+
+
+@pytest.mark.parametrize("case_name", ["ragged", "config1"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_reconstruction_by_resolve_equals_the_combination(case_name, precision):
+    """T6 on the GPU: without MRCM_KEEP_MBFS the reconstruction solves every
+    local problem again with the particular data and G(pi) on Gamma (the
+    second option after (2.23)); its pressure and velocities equal those of
+    the combination and of the oracle's re-solve."""
+    import paper_2103_08513_amd as lib
+    from oracle.mrcm import reconstruct_resolve
+    case = small_case(**CASES[case_name]) if case_name in CASES else config1()
+    pb = case.problem
+    args = (_dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q))
+    mc = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision)
+    pc, Uc, Xc = mc.solve(*args, refine=2)
+    mr = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision, keep=lib.KEEP_FACTORS)
+    pr, Ur, Xr = mr.solve(*args, refine=2)
+    torch.cuda.synchronize()
+    assert torch.equal(Xc, Xr)  # same build and interface solve
+    ref = mrcm_solve(case)
+    p_os = reconstruct_resolve(pb, ref.geo, ref.systems, Xr.cpu().numpy())
+    e_c = rel_l2(pr.cpu().numpy(), pc.cpu().numpy())
+    e_o = rel_l2(pr.cpu().numpy(), p_os)
+    e_u = rel_l2(Ur.cpu().numpy(), Uc.cpu().numpy())
+    print(f"{case_name}, precision {precision}: re-solve vs combination p {e_c:.2e}, U {e_u:.2e}; "
+          f"vs the oracle's re-solve {e_o:.2e}", flush=True)
+    assert e_c < 1e-9 and e_u < 1e-9 and e_o < 1e-9
+    with pytest.raises(lib.MRCMError):
+        mr.copy_mbfs(0)
+    mc.close()
+    mr.close()

@@ -414,3 +414,59 @@ def test_wall_closed_forms_mrcm(kind, alpha):
         # the monolithic formulation, which assembles its walls separately
         pm, _ = mrcm_monolithic(case)
         assert np.max(np.abs(pm - exact)) < 1e-10 * max(1.0, np.max(np.abs(exact))), (d, kind)
+
+
+# ------------------------------------------------ shared (face) beta -----
+def test_face_beta_equals_per_side_beta_where_both_sides_agree():
+    """With K constant across every interface and equal subdomain extents,
+    the per-side and the face-shared Robin parameters coincide face by face,
+    so the two readings give the same MRCM solution (up to rounding)."""
+    c = small_case((8, 6, 4), (2, 2, 2), split=((2, 1), (1, 2), (2, 2)), seed=3)
+    pb = c.problem
+    pb.kx[:] = 2.0
+    pb.ky[:] = 0.5
+    pb.kz[:] = 0.3
+    r0 = mrcm_solve(c)
+    c.beta_mode = 1
+    r1 = mrcm_solve(c)
+    assert rel_l2(r1.p, r0.p) < 1e-12 and rel_l2(r1.pi, r0.pi) < 1e-12
+
+
+@pytest.mark.parametrize("alpha", [1e-3, 1.0, 1e3])
+def test_face_beta_keeps_the_fine_trace_exact_and_the_monolithic_form(alpha):
+    """Sec. 2.2: the fine-trace spaces reproduce the fine solution for any
+    positive Robin parameter on each side, the shared face value included;
+    and the MBF path equals the monolithic solve under it."""
+    c = small_case((9, 6, 4), (3, 2, 1), split=((0, 0), (0, 0), (0, 0)), seed=3, alpha=alpha, std=2.0)
+    c.beta_mode = 1
+    pf, Uf = fine_solve(c.problem)
+    r = mrcm_solve(c)
+    assert rel_l2(r.p, pf) < 1e-10 and rel_l2(r.U, Uf) < 1e-9
+    c2 = small_case((8, 6, 6), (2, 2, 3), split=((2, 2), (1, 2), (2, 1)), seed=7, std=1.5, alpha=alpha)
+    c2.beta_mode = 1
+    r2 = mrcm_solve(c2)
+    pm, _ = mrcm_monolithic(c2)
+    assert rel_l2(r2.p, pm) < 1e-11
+
+
+def test_face_beta_is_symmetric_across_each_interface():
+    """The shared value is the same seen from both sides: the two sides'
+    Robin faces of every fine face carry one beta."""
+    from oracle.mrcm import gamma_faces
+    c = small_case((9, 7, 5), (3, 2, 2), split=((2, 1), (1, 1), (2, 2)), seed=8, std=2.0,
+                   parts=([2, 4, 3], [3, 4], [2, 3]))
+    pb = c.problem
+    geo = Geometry(pb.dims, c.partition, c.iface)
+    seen = {}
+    for l in range(geo.n_sub):
+        g = gamma_faces(pb, geo, l, 0.7, beta_mode=1)
+        d = g.face // 2
+        stride = np.array([1, pb.nx, pb.nx * pb.ny])[d]
+        other = np.where(g.sigma > 0, g.gcell + stride, g.gcell - stride)
+        for a, b, beta in zip(g.gcell, other, g.beta):
+            key = (min(a, b), max(a, b))
+            if key in seen:
+                assert abs(seen[key] - beta) <= 1e-15 * beta
+            else:
+                seen[key] = beta
+    assert len(seen) > 0
