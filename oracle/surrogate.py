@@ -122,3 +122,123 @@ def features_and_targets(pb, ls, lo, ext, X=None):
             rms = np.sqrt(np.mean(x * x))
             tgt[c, 0] = (x / rms if rms > 0 else 0.0 * x).reshape(dhw)
     return inp, tgt
+
+
+# ---------------------------------------------------------------------------
+# The encoder-decoder of the learned warm start, with BF16 operands.
+#
+# Layers (a list of tuples): ("conv", cin, cout, relu) -- a zero-padded
+# 3x3x3 convolution with bias; ("pool",) -- the average of 2x2 cells over the
+# two leading grid axes (D, H); ("up",) -- nearest-neighbour upsampling by two
+# over the same axes.  Every convolution rounds its input and its weights to
+# bfloat16 (round to nearest, ties to even, from the float32 value) and sums
+# the products exactly here (float64); the result, the bias, the ReLU and
+# every other tensor stay unrounded.  The backward pass is the exact gradient
+# of that computation with the roundings passed straight through: for a
+# convolution y = conv(r(x), r(w)) + b with upstream gradient g (after the
+# ReLU mask),
+#   dL/dw = correlation of g with r(x),  dL/db = sum of g,
+#   dL/dx = transposed convolution of r(g) with r(w),
+# where r rounds to bfloat16.
+# ---------------------------------------------------------------------------
+
+def bf16(a):
+    """Round to bfloat16 (nearest, ties to even) via the float32 value,
+    returned as float64."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def f32(a):
+    """The float32 value of a (what the GPU stores between layers)."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def pool2(x):
+    """Average over 2x2 cells of the (D, H) axes of [B, C, D, H, W]."""
+    return F.avg_pool3d(torch.as_tensor(x, dtype=torch.float64), kernel_size=(2, 2, 1))
+
+
+def up2(x):
+    """Nearest-neighbour upsampling by two over (D, H) of [B, C, D, H, W]."""
+    return F.interpolate(torch.as_tensor(x, dtype=torch.float64), scale_factor=(2, 2, 1), mode="nearest")
+
+
+def unet_params(layers, seed):
+    """Seeded initial parameters (He-uniform weights, zero biases): one
+    (w [cout, cin, 3, 3, 3], b [cout]) per convolution, float32 values."""
+    rng = np.random.default_rng(seed)
+    ps = []
+    for L in layers:
+        if L[0] != "conv":
+            continue
+        _, ci, co, _ = L
+        bound = np.sqrt(6.0 / (27 * ci))
+        ps.append(f32(rng.uniform(-bound, bound, size=(co, ci, 3, 3, 3))))
+        ps.append(np.zeros(co))
+    return ps
+
+
+def unet_forward(layers, params, x, rounding=True):
+    """Network output and every layer's input (for the backward pass).
+    rounding=False drops the bfloat16 roundings (the exact float64 network)."""
+    r = bf16 if rounding else (lambda a: np.asarray(a, dtype=np.float64))
+    h = np.asarray(x, dtype=np.float64)
+    acts = []
+    k = 0
+    for L in layers:
+        acts.append(h)
+        if L[0] == "conv":
+            w, b = params[2 * k], params[2 * k + 1]
+            k += 1
+            h = conv3d(r(h), r(w), b).numpy()
+            if L[3]:
+                h = np.maximum(h, 0.0)
+        elif L[0] == "pool":
+            h = pool2(h).numpy()
+        else:
+            h = up2(h).numpy()
+    return h, acts
+
+
+def unet_loss_and_grads(layers, params, x, t, rounding=True):
+    """Mean squared error of the network on (x, t) and the gradients of
+    every parameter, by the backward pass stated above."""
+    r = bf16 if rounding else (lambda a: np.asarray(a, dtype=np.float64))
+    y, acts = unet_forward(layers, params, x, rounding)
+    t = np.asarray(t, dtype=np.float64)
+    loss = float(np.mean((y - t) ** 2))
+    g = 2.0 * (y - t) / y.size
+    grads = [None] * len(params)
+    k = sum(1 for L in layers if L[0] == "conv")
+    out = y
+    for i in reversed(range(len(layers))):
+        L, a = layers[i], acts[i]
+        if L[0] == "conv":
+            k -= 1
+            w = params[2 * k]
+            if L[3]:
+                g = g * (out > 0.0)
+            xr = torch.tensor(r(a), dtype=torch.float64, requires_grad=True)
+            wr = torch.tensor(r(w), dtype=torch.float64, requires_grad=True)
+            y_ = F.conv3d(xr, wr, None, padding=1)
+            y_.backward(torch.as_tensor(g, dtype=torch.float64))
+            grads[2 * k] = wr.grad.numpy()
+            grads[2 * k + 1] = g.sum(axis=(0, 2, 3, 4))
+            # dL/dx from the rounded upstream gradient and rounded weights
+            xs = torch.zeros(a.shape, dtype=torch.float64, requires_grad=True)
+            y2 = F.conv3d(xs, torch.as_tensor(r(w), dtype=torch.float64), None, padding=1)
+            y2.backward(torch.as_tensor(r(g), dtype=torch.float64))
+            g = xs.grad.numpy()
+        elif L[0] == "pool":
+            xs = torch.zeros(a.shape, dtype=torch.float64, requires_grad=True)
+            pool2(xs).backward(torch.as_tensor(g, dtype=torch.float64))
+            g = xs.grad.numpy()
+        else:
+            xs = torch.zeros(a.shape, dtype=torch.float64, requires_grad=True)
+            up2(xs).backward(torch.as_tensor(g, dtype=torch.float64))
+            g = xs.grad.numpy()
+        out = a
+    return loss, grads, y

@@ -127,3 +127,78 @@ def test_local_order_follows_the_stated_rule():
     assert tuple(coords[2]) == (11, 20, 30)   # then x
     assert tuple(coords[8]) == (10, 21, 30)   # then y
     assert len({tuple(c) for c in coords}) == 32
+
+
+# ------------------------------------------------- the encoder-decoder -----
+from oracle.surrogate import bf16, pool2, unet_forward, unet_loss_and_grads, unet_params, up2  # noqa: E402
+
+SMALL = [("conv", 2, 3, True), ("pool",), ("conv", 3, 4, True), ("conv", 4, 4, True), ("up",),
+         ("conv", 4, 3, True), ("conv", 3, 1, False)]
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    """Against the float32 -> bfloat16 conversion of torch (round to nearest,
+    ties to even), on random values and on exact ties."""
+    import torch
+    rng = np.random.default_rng(0)
+    x = (rng.standard_normal(5000) * 10.0 ** rng.integers(-6, 6, 5000)).astype(np.float32)
+    assert np.array_equal(bf16(x), torch.tensor(x).to(torch.bfloat16).to(torch.float64).numpy())
+    # 1 + 2^-8 lies halfway between 1 and 1 + 2^-7: ties go to the even significand (1)
+    assert bf16(np.float32(1.0 + 2.0 ** -8)) == 1.0
+    assert bf16(np.float32(1.0 + 3 * 2.0 ** -8)) == 1.0 + 2.0 ** -6
+
+
+def test_pool_and_upsampling_by_loops():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((2, 3, 4, 6, 5))
+    p = pool2(x).numpy()
+    for d in range(2):
+        for h in range(3):
+            want = 0.25 * (x[:, :, 2 * d, 2 * h] + x[:, :, 2 * d + 1, 2 * h] + x[:, :, 2 * d, 2 * h + 1]
+                           + x[:, :, 2 * d + 1, 2 * h + 1])
+            assert np.allclose(p[:, :, d, h], want, rtol=1e-14, atol=1e-14)
+    u = up2(p).numpy()
+    for d in range(4):
+        for h in range(6):
+            assert np.array_equal(u[:, :, d, h], p[:, :, d // 2, h // 2])
+
+
+def test_encoder_decoder_gradients_match_finite_differences():
+    """The backward pass of the encoder-decoder (convolutions, ReLUs, pooling,
+    upsampling) without the bfloat16 roundings, against central differences
+    of the loss."""
+    rng = np.random.default_rng(2)
+    ps = unet_params(SMALL, 3)
+    ps = [p + 0.05 * rng.standard_normal(p.shape) for p in ps]  # nonzero biases
+    x = rng.standard_normal((2, 2, 4, 4, 3))
+    t = rng.standard_normal((2, 1, 4, 4, 3))
+    _, g, _ = unet_loss_and_grads(SMALL, ps, x, t, rounding=False)
+    eps = 1e-6
+    for k in range(len(ps)):
+        for _ in range(3):
+            idx = tuple(int(rng.integers(0, s)) for s in ps[k].shape)
+            pp = [p.copy() for p in ps]
+            pp[k][idx] += eps
+            lp = unet_loss_and_grads(SMALL, pp, x, t, rounding=False)[0]
+            pp[k][idx] -= 2 * eps
+            lm = unet_loss_and_grads(SMALL, pp, x, t, rounding=False)[0]
+            fd = (lp - lm) / (2 * eps)
+            assert abs(fd - g[k][idx]) <= 1e-6 * max(1.0, abs(fd)), (k, idx, fd, g[k][idx])
+
+
+def test_roundings_change_nothing_on_bf16_values_of_one_layer():
+    """With inputs and weights already bfloat16 numbers, one convolution's
+    rounded forward pass and parameter gradients equal the exact ones (the
+    roundings pass straight through)."""
+    rng = np.random.default_rng(4)
+    layers = [("conv", 2, 3, False)]
+    w = bf16(0.3 * rng.standard_normal((3, 2, 3, 3, 3)))
+    b = rng.standard_normal(3)
+    x = bf16(rng.standard_normal((2, 2, 3, 4, 5)))
+    t = rng.standard_normal((2, 3, 3, 4, 5))
+    l0, g0, y0 = unet_loss_and_grads(layers, [w, b], x, t, rounding=False)
+    l1, g1, y1 = unet_loss_and_grads(layers, [w, b], x, t, rounding=True)
+    assert np.array_equal(y0, y1) and l0 == l1
+    assert all(np.array_equal(a, c) for a, c in zip(g0, g1))
+    y, _ = unet_forward(layers, [w, b], x)
+    assert np.allclose(y, conv3d(x, w, b).numpy(), rtol=1e-14, atol=1e-14)
