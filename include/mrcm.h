@@ -162,7 +162,9 @@ typedef struct {
  * pcg_x0       PCG: [dev] starting guess in the layout of the MBFs (per
  *              subdomain l in id order, n_cells x n_rhs, row-major in the
  *              local row ordering, the same layout as mrcm_copy_mbfs), or NULL
- *              for zero.  Read during the call only.
+ *              for zero.  A column whose guess (after pcg_x0_scale) leaves a
+ *              residual larger than its right-hand side starts from zero
+ *              instead.  Read during the call only.
  * solve_tiles  tiles of 16 right-hand-side columns per work item of the band
  *              solves (0: the largest, 3): fewer give more, smaller items.
  * solve_group  FP64 with refinement: subdomains whose first solve starts when

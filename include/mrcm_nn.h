@@ -79,6 +79,61 @@ mrcm_status mrcm_mse(const float *y, const float *t, float *dy, double *loss, do
 mrcm_status mrcm_mse_noalloc(const float *y, const float *t, float *dy, double *loss, int64_t n, void *stream);
 
 /*
+ * The encoder-decoder network (the learned form as specified: BF16 weights,
+ * FP32 accumulation).  Activations are FP32, channels last:
+ * [batch][d][h][w][c] with c fastest.  Master weights are FP32 [cout][cin][27]
+ * (taps kd*9 + kh*3 + kw, as mrcm_conv3d_forward's [cout][cin][3][3][3]);
+ * a convolution uses them packed to bfloat16 (round to nearest, ties to
+ * even) by mrcm_unet_pack:
+ *   wf [pad(cout)][27][pad(cin)]  forward weights,
+ *   wt [pad(cin)][27][pad(cout)]  the spatially flipped transpose, which makes
+ *                                 mrcm_unet_conv compute dL/dx,
+ * pad(c) = mrcm_unet_padded(c), c rounded up to 16; at most
+ * mrcm_unet_max_channels() (128) channels.
+ */
+int32_t mrcm_unet_max_channels(void);
+int32_t mrcm_unet_padded(int32_t c);
+mrcm_status mrcm_unet_pack(const float *w, uint16_t *wf, uint16_t *wt, int32_t cin, int32_t cout, void *stream);
+
+/*
+ * y = conv(x, w) + bias: zero-padded 3x3x3 cross-correlation with x and w
+ * rounded to bfloat16 and the products summed in FP32 on the matrix cores
+ * (implicit GEMM on v_mfma_f32_16x16x16_bf16).  relu != 0: y = max(y, 0);
+ * mask (shaped like y, optional): y = 0 where mask <= 0.  With x = dL/dy and
+ * the packed transpose wt (cin and cout exchanged) it gives dL/dx.
+ */
+mrcm_status mrcm_unet_conv(const float *x, const uint16_t *wf, const float *bias, float *y, const float *mask,
+                           int32_t batch, int32_t d, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t relu,
+                           void *stream);
+
+/*
+ * Weight gradients of y = conv(x, w) + b for a given dL/dy, in FP32:
+ * dw [cout][cin][27] = correlation of dy with bfloat16(x) (the operand the
+ * forward pass used), db [cout] (or NULL) = sum of dy over the batch and the
+ * grid.  workspace: mrcm_unet_wgrad_workspace(...) floats.  The partial sums
+ * are added in a fixed order (reproducible).
+ */
+int64_t mrcm_unet_wgrad_workspace(int32_t batch, int32_t d, int32_t h, int32_t w, int32_t cin, int32_t cout);
+mrcm_status mrcm_unet_wgrad(const float *x, const float *dy, float *dw, float *db, float *workspace, int32_t batch,
+                            int32_t d, int32_t h, int32_t w, int32_t cin, int32_t cout, void *stream);
+
+/*
+ * Average over 2x2 cells of (d, h) (d, h even; output d/2 x h/2 x w), and
+ * nearest upsampling by two over (d, h) (input d x h x w, output 2d x 2h x w);
+ * backward != 0: the adjoint (x the gradient at the output, y that at the
+ * input).  mrcm_unet_relu_mask: g = 0 where out <= 0.
+ */
+mrcm_status mrcm_unet_pool(const float *x, float *y, int32_t batch, int32_t d, int32_t h, int32_t w, int32_t c,
+                           int32_t backward, void *stream);
+mrcm_status mrcm_unet_upsample(const float *x, float *y, int32_t batch, int32_t d, int32_t h, int32_t w, int32_t c,
+                               int32_t backward, void *stream);
+mrcm_status mrcm_unet_relu_mask(float *g, const float *out, int64_t n, void *stream);
+
+/* [batch][c][voxels] -> [batch][voxels][c] (mrcm_nn_features' inputs to
+ * channels last). */
+mrcm_status mrcm_nn_channels_last(const float *in, float *out, int32_t batch, int32_t c, int64_t voxels, void *stream);
+
+/*
  * One Adam step (Kingma and Ba, 2015) on n parameters at step t >= 1:
  * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
  * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).

@@ -36,7 +36,7 @@ import numpy as np
 __all__ = [
     "Problem", "Partition", "IfaceSpace", "Case",
     "grf", "channelised", "uniform_cuts", "ragged_cuts",
-    "config1", "config2", "config3", "config3_block", "config5", "config5_block", "contrast_power",
+    "config1", "config2", "config3", "config3_block", "config4_field", "config5", "config5_block", "contrast_power",
     "small_case",
 ]
 
@@ -275,6 +275,24 @@ def config5_block(big):
     pb = Problem(nx, ny, nz, B.hx, B.hy, B.hz, win(B.kx), win(B.ky), win(B.kz), q, pin=pin)
     part = Partition(uniform_cuts(nx, 20), uniform_cuts(ny, 20), uniform_cuts(nz, 5))
     return Case("cfg5-block-60x220x85", pb, part, IfaceSpace(((2, 1), (2, 1), (2, 2))), big.alpha)
+
+
+def config4_field(seed):
+    """A field of the learned warm start's data: the 60x220x85 workload's
+    channelised generator on a 60x60x15 grid of 20x10x2 ft cells (3x3x3
+    subdomains of 20x20x5, so one interior, face, edge and corner subdomains),
+    the same patches, kz = 0.1 kx, quarter-five-spot columns and the pin in
+    the far corner."""
+    nx, ny, nz = 60, 60, 15
+    kx = np.exp(channelised((nx, ny, nz), seed))
+    q = np.zeros(nx * ny * nz)
+    for k in range(nz):
+        q[_cell(0, 0, k, nx, ny)] += 1.0 / nz
+        q[_cell(nx - 1, ny - 1, k, nx, ny)] -= 1.0 / nz
+    pin = _cell(nx - 1, ny - 1, nz - 1, nx, ny)
+    pb = Problem(nx, ny, nz, 20.0, 10.0, 2.0, kx, kx.copy(), 0.1 * kx, q, pin=pin)
+    part = Partition(uniform_cuts(nx, 20), uniform_cuts(ny, 20), uniform_cuts(nz, 5))
+    return Case(f"cfg4-field-{seed}", pb, part, IfaceSpace(((2, 1), (2, 1), (2, 2))), 1.0)
 
 
 def config3(seed=0, patch_seed=3):

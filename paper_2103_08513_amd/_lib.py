@@ -22,6 +22,8 @@ EXPORTS = [
     "mrcm_conv3d_max_channels", "mrcm_conv3d_forward", "mrcm_conv3d_backward", "mrcm_mse", "mrcm_mse_noalloc",
     "mrcm_adam_step",
     "mrcm_nn_features", "mrcm_nn_scatter",
+    "mrcm_unet_max_channels", "mrcm_unet_padded", "mrcm_unet_pack", "mrcm_unet_conv", "mrcm_unet_wgrad_workspace",
+    "mrcm_unet_wgrad", "mrcm_unet_pool", "mrcm_unet_upsample", "mrcm_unet_relu_mask", "mrcm_nn_channels_last",
 ]
 
 STAGES = ["coef", "factor", "rhs", "solve", "residual", "refine", "flux", "assemble", "lu", "sweep",
@@ -124,6 +126,16 @@ def load(path: str = LIB_PATH):
         "mrcm_conv3d_backward": ([c_void_p] * 8 + [c_int32] * 7 + [c_void_p], c_int32),
         "mrcm_mse": ([c_void_p] * 5 + [c_int64, c_void_p], c_int32),
         "mrcm_mse_noalloc": ([c_void_p] * 4 + [c_int64, c_void_p], c_int32),
+        "mrcm_unet_max_channels": ([], c_int32),
+        "mrcm_unet_padded": ([c_int32], c_int32),
+        "mrcm_unet_pack": ([c_void_p] * 3 + [c_int32, c_int32, c_void_p], c_int32),
+        "mrcm_unet_conv": ([c_void_p] * 5 + [c_int32] * 7 + [c_void_p], c_int32),
+        "mrcm_unet_wgrad_workspace": ([c_int32] * 6, c_int64),
+        "mrcm_unet_wgrad": ([c_void_p] * 5 + [c_int32] * 6 + [c_void_p], c_int32),
+        "mrcm_unet_pool": ([c_void_p] * 2 + [c_int32] * 6 + [c_void_p], c_int32),
+        "mrcm_unet_upsample": ([c_void_p] * 2 + [c_int32] * 6 + [c_void_p], c_int32),
+        "mrcm_unet_relu_mask": ([c_void_p] * 2 + [c_int64, c_void_p], c_int32),
+        "mrcm_nn_channels_last": ([c_void_p] * 2 + [c_int32, c_int32, c_int64, c_void_p], c_int32),
         "mrcm_adam_step": ([c_void_p] * 4 + [c_int32, c_int32, c_float, c_float, c_float, c_float, c_void_p],
                            c_int32),
         "mrcm_nn_features": ([c_void_p, P(c_int32), c_int32, c_void_p, c_void_p, c_void_p], c_int32),

@@ -1757,6 +1757,85 @@ mrcm_status mrcm_mse(const float *y, const float *t, float *dy, double *loss, do
   return MRCM_OK;
 }
 
+int32_t mrcm_unet_max_channels(void) { return unet_max_channels(); }
+int32_t mrcm_unet_padded(int32_t c) { return unet_pad16(c); }
+
+namespace {
+mrcm_status check_unet(int32_t batch, int32_t d, int32_t h, int32_t w, int32_t cin, int32_t cout) {
+  if (batch <= 0 || d <= 0 || h <= 0 || w <= 0 || cin <= 0 || cout <= 0)
+    return fail(MRCM_EINVAL, "sizes must be positive");
+  if (cin > unet_max_channels() || cout > unet_max_channels())
+    return fail(MRCM_EINVAL, "at most " + std::to_string(unet_max_channels()) + " channels");
+  if ((long long)batch * d * h * w >= (1LL << 31)) return fail(MRCM_EUNSUPPORTED, "more than 2^31 voxels");
+  return MRCM_OK;
+}
+}  // namespace
+
+mrcm_status mrcm_unet_pack(const float *w, uint16_t *wf, uint16_t *wt, int32_t cin, int32_t cout, void *stream) {
+  if (!w || !wf || !wt) return fail(MRCM_EINVAL, "null argument");
+  mrcm_status st = check_unet(1, 1, 1, 1, cin, cout);
+  if (st != MRCM_OK) return st;
+  HIP_TRY(launch_unet_pack(w, wf, wt, cin, cout, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_unet_conv(const float *x, const uint16_t *wf, const float *bias, float *y, const float *mask,
+                           int32_t batch, int32_t d, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t relu,
+                           void *stream) {
+  if (!x || !wf || !y) return fail(MRCM_EINVAL, "null tensor");
+  mrcm_status st = check_unet(batch, d, h, w, cin, cout);
+  if (st != MRCM_OK) return st;
+  HIP_TRY(launch_unet_conv(x, wf, bias, y, mask, batch, d, h, w, cin, cout, relu, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
+int64_t mrcm_unet_wgrad_workspace(int32_t batch, int32_t d, int32_t h, int32_t w, int32_t cin, int32_t cout) {
+  if (check_unet(batch, d, h, w, cin, cout) != MRCM_OK) return -1;
+  return unet_wgrad_workspace((long long)batch * d * h * w, cin, cout);
+}
+
+mrcm_status mrcm_unet_wgrad(const float *x, const float *dy, float *dw, float *db, float *workspace, int32_t batch,
+                            int32_t d, int32_t h, int32_t w, int32_t cin, int32_t cout, void *stream) {
+  if (!x || !dy || !dw || !workspace) return fail(MRCM_EINVAL, "null tensor");
+  mrcm_status st = check_unet(batch, d, h, w, cin, cout);
+  if (st != MRCM_OK) return st;
+  HIP_TRY(launch_unet_wgrad(x, dy, dw, db, workspace, batch, d, h, w, cin, cout, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_unet_pool(const float *x, float *y, int32_t batch, int32_t d, int32_t h, int32_t w, int32_t c,
+                           int32_t backward, void *stream) {
+  if (!x || !y) return fail(MRCM_EINVAL, "null tensor");
+  mrcm_status st = check_unet(batch, d, h, w, c, c);
+  if (st != MRCM_OK) return st;
+  if (d % 2 || h % 2) return fail(MRCM_EINVAL, "pooling needs even d and h");
+  HIP_TRY(launch_unet_pool(x, y, batch, d, h, w, c, backward, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_unet_upsample(const float *x, float *y, int32_t batch, int32_t d, int32_t h, int32_t w, int32_t c,
+                               int32_t backward, void *stream) {
+  if (!x || !y) return fail(MRCM_EINVAL, "null tensor");
+  mrcm_status st = check_unet(batch, 2 * d, 2 * h, w, c, c);
+  if (st != MRCM_OK) return st;
+  HIP_TRY(launch_unet_up(x, y, batch, d, h, w, c, backward, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_unet_relu_mask(float *g, const float *out, int64_t n, void *stream) {
+  if (!g || !out) return fail(MRCM_EINVAL, "null tensor");
+  if (n <= 0) return fail(MRCM_EINVAL, "n must be positive");
+  HIP_TRY(launch_unet_relu_mask(g, out, n, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_nn_channels_last(const float *in, float *out, int32_t batch, int32_t c, int64_t voxels, void *stream) {
+  if (!in || !out) return fail(MRCM_EINVAL, "null tensor");
+  if (batch <= 0 || c <= 0 || voxels <= 0) return fail(MRCM_EINVAL, "sizes must be positive");
+  HIP_TRY(launch_channels_last(in, out, batch, c, voxels, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
 mrcm_status mrcm_mse_noalloc(const float *y, const float *t, float *dy, double *loss, int64_t n, void *stream) {
   if (!y || !t || !dy || !loss) return fail(MRCM_EINVAL, "null argument");
   if (n <= 0) return fail(MRCM_EINVAL, "n must be positive");

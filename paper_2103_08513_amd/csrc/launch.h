@@ -80,6 +80,23 @@ hipError_t launch_nn_features(const Geom &g, const int *sel, const int *sample0,
 hipError_t launch_nn_scatter(const Geom &g, const int *sel, const int *sample0, int n_sel, int mmax,
                              const float *out, int V, double *x0, hipStream_t s);
 
+// Encoder-decoder network of the learned warm start (unet_kernels.hip);
+// activations FP32 channels last, convolutions on BF16 MFMA.
+int unet_pad16(int c);
+int unet_max_channels();
+hipError_t launch_unet_pack(const float *w, unsigned short *wf, unsigned short *wt, int cin, int cout, hipStream_t s);
+hipError_t launch_unet_conv(const float *x, const unsigned short *wf, const float *bias, float *y, const float *mask,
+                            int batch, int d, int h, int w, int cin, int cout, int relu, hipStream_t s);
+long long unet_wgrad_workspace(long long nvox, int cin, int cout);
+hipError_t launch_unet_wgrad(const float *x, const float *dy, float *dw, float *db, float *work, int batch, int d,
+                             int h, int w, int cin, int cout, hipStream_t s);
+hipError_t launch_unet_pool(const float *x, float *y, int batch, int d, int h, int w, int c, int backward,
+                            hipStream_t s);
+hipError_t launch_unet_up(const float *x, float *y, int batch, int d, int h, int w, int c, int backward,
+                          hipStream_t s);
+hipError_t launch_unet_relu_mask(float *g, const float *out, long long n, hipStream_t s);
+hipError_t launch_channels_last(const float *in, float *out, int batch, int c, long long v, hipStream_t s);
+
 // Interface system and reconstruction (iface_kernels.hip)
 hipError_t launch_fill(double *a, long long n, double v, hipStream_t s);
 hipError_t launch_copy(const double *a, double *b, long long n, hipStream_t s);

@@ -12,7 +12,8 @@
 //    preconditioning), for the normalised scaled residual, until its own
 //    residual has dropped by kInnerTol; x += D^-1/2 y in FP64.
 // The budget max_iter counts inner iterations (matrix-vector products) over
-// all outer steps.  The starting guess X0 may be X itself: a workgroup reads
+// all outer steps.  A starting guess whose residual exceeds ||b|| is replaced
+// by zero.  The starting guess X0 may be X itself: a workgroup reads
 // its column of X0 before it writes that column of X.  Thread t owns local rows t + 256 i, i < CPT; the search
 // direction is exchanged through LDS for the 7-point product, and every
 // branch depends only on workgroup sums that all lanes read alike.
@@ -185,6 +186,10 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
     a -= cf[4 * mb + 3] * xc[-b];
     return a;
   };
+  // a starting guess is kept only if its residual is no larger than that of
+  // the zero start (the stopping test is relative to ||b||, and a guess close
+  // in the A-norm can still carry a large high-frequency residual)
+  bool check_start = X0g != nullptr;
   while (!ok) {
     // FP64 residual r = b - A x from the coefficients (x in xs)
     double res[CPT];
@@ -206,6 +211,16 @@ __global__ __launch_bounds__(NT) void k_pcg(Geom g, const int *__restrict__ col_
     if (rn2 <= tol2) {
       ok = true;
       break;
+    }
+    if (check_start) {
+      check_start = false;
+      if (!(rn2 <= bn2)) {
+#pragma unroll
+        for (int i = 0; i < CPT; ++i)
+          if (tid + NT * i < N) xr[NT * i] = 0.0;
+        __syncthreads();
+        continue;
+      }
     }
     if (it >= max_iter || !isfinite(rn2)) break;
     const double sn2 = block_sum<NW>(nsq, redd[0], wave, lane);

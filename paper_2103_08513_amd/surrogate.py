@@ -197,3 +197,257 @@ def warm_start(model, net, subs, dims, x0=None, chunk=4096):
         _lib.check(code, "mrcm_nn_scatter")
         del inp, out
     return x0
+
+
+# -- the encoder-decoder (BF16 MFMA convolutions) ----------------------------
+# Layers: ("conv", cin, cout, relu), ("pool",) -- average over 2x2 cells of
+# the two long grid axes, ("up",) -- nearest upsampling by two over them.  On
+# a 20x20x5 block the three resolutions are 20x20x5, 10x10x5 and 5x5x5.
+UNET_LAYERS = (("conv", 2, 24, True), ("conv", 24, 24, True), ("pool",),
+               ("conv", 24, 48, True), ("conv", 48, 48, True), ("pool",),
+               ("conv", 48, 80, True), ("conv", 80, 80, True), ("up",),
+               ("conv", 80, 48, True), ("conv", 48, 48, True), ("up",),
+               ("conv", 48, 24, True), ("conv", 24, 1, False))
+
+
+def _u16(t):
+    return t  # packed bfloat16 weights live in int16 tensors
+
+
+class EncoderDecoder:
+    """The learned warm start as an encoder-decoder of 3x3x3 convolutions on
+    BF16 matrix cores (FP32 accumulation, FP32 master weights and Adam).
+    Inputs [S, D, H, W, 2] (channels last), outputs [S, D, H, W, 1]."""
+
+    def __init__(self, layers=UNET_LAYERS, seed=0, device="cuda", init=None):
+        import torch
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.layers = tuple(tuple(L) for L in layers)
+        cmax = self.lib.mrcm_unet_max_channels()
+        convs = [L for L in self.layers if L[0] == "conv"]
+        if any(L[1] > cmax or L[2] > cmax for L in convs):
+            raise ValueError(f"at most {cmax} channels per convolution")
+        rng = np.random.default_rng(seed)
+        self.params = []
+        for k, (_, ci, co, _) in enumerate(convs):
+            if init is not None:
+                w = np.asarray(init[2 * k], dtype=np.float32).reshape(co, ci * 27)
+                b = np.asarray(init[2 * k + 1], dtype=np.float32)
+            else:
+                bound = np.sqrt(6.0 / (27 * ci))
+                w = rng.uniform(-bound, bound, size=(co, ci * 27)).astype(np.float32)
+                b = np.zeros(co, dtype=np.float32)
+            self.params.append(torch.as_tensor(w.reshape(-1), device=self.device).contiguous())
+            self.params.append(torch.as_tensor(b, device=self.device).contiguous())
+        self.m = [torch.zeros_like(p) for p in self.params]
+        self.v = [torch.zeros_like(p) for p in self.params]
+        self.t = 0
+        self.packed = []
+        for (_, ci, co, _) in convs:
+            pi, po = self.lib.mrcm_unet_padded(ci), self.lib.mrcm_unet_padded(co)
+            wf = torch.zeros(po * 27 * pi, dtype=torch.int16, device=self.device)
+            wt = torch.zeros(pi * 27 * po, dtype=torch.int16, device=self.device)
+            self.packed.append((wf, wt))
+        self.loss_buf = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.work = torch.zeros(1024, dtype=torch.float64, device=self.device)
+        self._wg = {}
+        self.pack()
+
+    def n_params(self):
+        return int(sum(p.numel() for p in self.params))
+
+    def pack(self):
+        k = 0
+        for L in self.layers:
+            if L[0] != "conv":
+                continue
+            wf, wt = self.packed[k]
+            _lib.check(self.lib.mrcm_unet_pack(_ptr(self.params[2 * k]), _ptr(wf), _ptr(wt), L[1], L[2], _stream()),
+                       "mrcm_unet_pack")
+            k += 1
+
+    def forward(self, x, keep=False):
+        """x [B, D, H, W, C] float32 -> output [B, D, H, W, 1]; keep: also the
+        input of every layer."""
+        import torch
+        _f32(x, "x")
+        B, D, H, W, _ = x.shape
+        h = x
+        acts = []
+        k = 0
+        for L in self.layers:
+            acts.append(h)
+            if L[0] == "conv":
+                _, ci, co, relu = L
+                y = torch.empty((B, D, H, W, co), dtype=torch.float32, device=self.device)
+                _lib.check(self.lib.mrcm_unet_conv(_ptr(h), _ptr(self.packed[k][0]), _ptr(self.params[2 * k + 1]),
+                                                   _ptr(y), None, B, D, H, W, ci, co, 1 if relu else 0, _stream()),
+                           "mrcm_unet_conv")
+                k += 1
+            elif L[0] == "pool":
+                C = h.shape[-1]
+                y = torch.empty((B, D // 2, H // 2, W, C), dtype=torch.float32, device=self.device)
+                _lib.check(self.lib.mrcm_unet_pool(_ptr(h), _ptr(y), B, D, H, W, C, 0, _stream()), "mrcm_unet_pool")
+                D, H = D // 2, H // 2
+            else:
+                C = h.shape[-1]
+                y = torch.empty((B, 2 * D, 2 * H, W, C), dtype=torch.float32, device=self.device)
+                _lib.check(self.lib.mrcm_unet_upsample(_ptr(h), _ptr(y), B, D, H, W, C, 0, _stream()),
+                           "mrcm_unet_upsample")
+                D, H = 2 * D, 2 * H
+            h = y
+        return (h, acts) if keep else h
+
+    def _wgrad_work(self, B, D, H, W, ci, co):
+        import torch
+        n = int(self.lib.mrcm_unet_wgrad_workspace(B, D, H, W, ci, co))
+        if n < 0:
+            raise ValueError("invalid convolution shape")
+        key = "w"
+        if key not in self._wg or self._wg[key].numel() < n:
+            self._wg[key] = torch.empty(n, dtype=torch.float32, device=self.device)
+        return self._wg[key]
+
+    def loss_and_grads(self, x, t):
+        """Mean squared error on (x, t) and every parameter's gradient (loss as
+        a device scalar: no synchronisation)."""
+        import torch
+        _f32(t, "t")
+        out, acts = self.forward(x, keep=True)
+        g = torch.empty_like(out)
+        _lib.check(self.lib.mrcm_mse(_ptr(out), _ptr(t), _ptr(g), _ptr(self.loss_buf), _ptr(self.work),
+                                     out.numel(), _stream()), "mrcm_mse")
+        grads = [None] * len(self.params)
+        k = sum(1 for L in self.layers if L[0] == "conv")
+        y = out
+        for i in reversed(range(len(self.layers))):
+            L, a = self.layers[i], acts[i]
+            B, D, H, W, C = a.shape
+            if L[0] == "conv":
+                k -= 1
+                _, ci, co, relu = L
+                if relu:
+                    _lib.check(self.lib.mrcm_unet_relu_mask(_ptr(g), _ptr(y), g.numel(), _stream()),
+                               "mrcm_unet_relu_mask")
+                dw = torch.empty_like(self.params[2 * k])
+                db = torch.empty_like(self.params[2 * k + 1])
+                work = self._wgrad_work(B, D, H, W, ci, co)
+                _lib.check(self.lib.mrcm_unet_wgrad(_ptr(a), _ptr(g), _ptr(dw), _ptr(db), _ptr(work), B, D, H, W, ci,
+                                                    co, _stream()), "mrcm_unet_wgrad")
+                grads[2 * k], grads[2 * k + 1] = dw, db
+                if i > 0:
+                    dx = torch.empty_like(a)
+                    _lib.check(self.lib.mrcm_unet_conv(_ptr(g), _ptr(self.packed[k][1]), None, _ptr(dx), None, B, D,
+                                                       H, W, co, ci, 0, _stream()), "mrcm_unet_conv")
+                    g = dx
+            elif L[0] == "pool":
+                dx = torch.empty_like(a)
+                _lib.check(self.lib.mrcm_unet_pool(_ptr(g), _ptr(dx), B, D, H, W, C, 1, _stream()), "mrcm_unet_pool")
+                g = dx
+            else:
+                dx = torch.empty_like(a)
+                _lib.check(self.lib.mrcm_unet_upsample(_ptr(g), _ptr(dx), B, D, H, W, C, 1, _stream()),
+                           "mrcm_unet_upsample")
+                g = dx
+            y = a
+        return self.loss_buf, grads
+
+    def adam(self, grads, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.t += 1
+        for p, g, m, v in zip(self.params, grads, self.m, self.v):
+            code = self.lib.mrcm_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), self.t, c_float(lr),
+                                           c_float(b1), c_float(b2), c_float(eps), _stream())
+            _lib.check(code, "mrcm_adam_step")
+        self.pack()
+
+    def train(self, inp, tgt, epochs=4, batch=128, lr=1e-3, seed=0, lr_decay=0.7):
+        """Mini-batch Adam over the samples (shuffled each epoch with a seeded
+        generator, the step size scaled by lr_decay after each epoch);
+        returns the mean loss of each epoch."""
+        import torch
+        n = inp.shape[0]
+        rng = np.random.default_rng(seed)
+        history = []
+        for ep in range(epochs):
+            order = torch.as_tensor(rng.permutation(n), device=self.device)
+            total = torch.zeros(1, dtype=torch.float64, device=self.device)
+            nb = 0
+            for s in range(0, n - batch + 1, batch):
+                idx = order[s:s + batch]
+                xb = inp.index_select(0, idx).contiguous()
+                tb = tgt.index_select(0, idx).contiguous()
+                loss, grads = self.loss_and_grads(xb, tb)
+                total += loss
+                nb += 1
+                self.adam(grads, lr * lr_decay ** ep)
+            history.append(float(total.item()) / max(1, nb))
+        return history
+
+    def predict(self, inp, batch=2048):
+        import torch
+        outs = [self.forward(inp[s:s + batch]) for s in range(0, inp.shape[0], batch)]
+        return torch.cat(outs, 0)
+
+
+def channels_last(x):
+    """[S, C, D, H, W] -> [S, D, H, W, C] by the library's permute kernel."""
+    import torch
+    S, C = x.shape[0], x.shape[1]
+    V = int(np.prod(x.shape[2:]))
+    y = torch.empty((S,) + tuple(x.shape[2:]) + (C,), dtype=torch.float32, device=x.device)
+    _lib.check(_lib.load().mrcm_nn_channels_last(_ptr(x), _ptr(y), S, C, V, _stream()), "mrcm_nn_channels_last")
+    return y
+
+
+def warm_start_unet(model, net, subs, dims, x0=None, chunk=2048):
+    """Starting guess in the MBF layout from the encoder-decoder, `chunk`
+    subdomains at a time."""
+    import torch
+    lib = _lib.load()
+    if x0 is None:
+        x0 = torch.zeros(model.mbf_layout()[-1], dtype=torch.float64, device=model.device)
+    for c0 in range(0, len(subs), chunk):
+        part = subs[c0:c0 + chunk]
+        inp, _ = features(model, part, dims, targets=False)
+        out = net.predict(channels_last(inp))
+        del inp
+        arr = (c_int32 * len(part))(*part)
+        code = lib.mrcm_nn_scatter(model._mbfs, arr, len(part), _ptr(out), _ptr(x0), _stream())
+        _lib.check(code, "mrcm_nn_scatter")
+        del out
+    return x0
+
+
+def mbf_dataset(seeds, per_field=50, make_case=None):
+    """Training or test samples: for each seed, the channelised field of
+    `make_case(seed)` built by the FP64 direct path, and `per_field` of its
+    MBF columns (particular columns excluded) drawn with default_rng(seed);
+    returns channels-last inputs [S, D, H, W, 2], unit-RMS targets
+    [S, D, H, W, 1] and the grid."""
+    import torch
+    from . import MRCM, FP64
+    if make_case is None:
+        from mrcm_inputs import config4_field
+        make_case = config4_field
+    inps, tgts = [], []
+    dims = None
+    for seed in seeds:
+        c = make_case(seed)
+        pb = c.problem
+        m = MRCM(pb, c.partition, c.iface, alpha=c.alpha, precision=FP64)
+        m.build_mbfs(*(torch.as_tensor(a, dtype=torch.float64, device="cuda") for a in (pb.kx, pb.ky, pb.kz, pb.q)))
+        subs, dims = net_subdomains(m)
+        inp, tgt = features(m, subs, dims)
+        # MBF columns only: column 0 of each subdomain is the particular problem
+        cols, s0 = [], 0
+        for l in subs:
+            mr = m.subdomain(l).n_rhs
+            cols += list(range(s0 + 1, s0 + mr))
+            s0 += mr
+        pick = np.random.default_rng(seed).choice(cols, size=min(per_field, len(cols)), replace=False)
+        idx = torch.as_tensor(np.sort(pick), device=inp.device)
+        inps.append(channels_last(inp.index_select(0, idx).contiguous()))
+        tgts.append(tgt.index_select(0, idx).contiguous())
+        m.close()
+    return torch.cat(inps), torch.cat(tgts), dims

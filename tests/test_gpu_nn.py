@@ -168,7 +168,7 @@ def test_features_targets_and_scatter_match_oracle():
     mdl.close()
 
 
-def test_training_lowers_loss_and_the_guess_beats_a_zero_start():
+def test_training_lowers_loss_and_the_scaled_guess_has_less_energy_error_than_zero():
     import paper_2103_08513_amd as lib
     from paper_2103_08513_amd.surrogate import WarmStartNet, features, net_subdomains, warm_start
     net = WarmStartNet(seed=0)

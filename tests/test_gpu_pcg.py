@@ -133,6 +133,40 @@ def test_pcg_warm_start_with_exact_mbfs_takes_no_iteration():
     d.close()
 
 
+@pytest.mark.parametrize("scale", [False, True])
+def test_pcg_start_worse_than_zero_is_dropped(scale):
+    """Large noise as the starting guess: unscaled, its residual exceeds
+    ||b|| in every column, so every column starts from zero and the
+    iterations and MBFs are bitwise those of the zero start.  Galerkin-scaled,
+    each column keeps whichever start has the smaller residual, and every
+    column still meets the tolerance."""
+    case = small_case((20, 10, 8), (2, 1, 1), split=((2, 2), (1, 1), (1, 1)), seed=22)
+    import paper_2103_08513_amd as lib
+    args = _inputs(case)
+    m = _model(case, precision=lib.PCG, ir_tol=TOL, pcg_max_iter=2000)
+    m.build_mbfs(*args)
+    torch.cuda.synchronize()
+    n_sub = m.info().n_sub
+    it0 = m.info().pcg_iters
+    zero = [m.copy_mbfs(l) for l in range(n_sub)]
+    n = m.mbf_layout()[-1]
+    guess = 1e6 * np.random.default_rng(5).standard_normal(n)
+    m.build_mbfs(*args, x0=_dev(guess), x0_scale=scale)
+    torch.cuda.synchronize()
+    info = m.info()
+    assert info.pcg_fallback == 0
+    if not scale:
+        assert info.pcg_iters == it0
+        for l in range(n_sub):
+            assert np.array_equal(m.copy_mbfs(l), zero[l]), l
+    else:
+        geo = Geometry(case.problem.dims, case.partition, case.iface)
+        for l in range(n_sub):
+            ls = local_system(case.problem, geo, l, case.alpha)
+            assert np.max(_column_residuals(m, ls, l)) <= TOL * 1.01, l
+    m.close()
+
+
 def test_pcg_config2_sampled_subdomains():
     """60x220x85 workload with the default budget of 50 iterations: whatever
     the split between CG and the fallback, every sampled column meets the
