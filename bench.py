@@ -51,7 +51,8 @@ def _stages(L, _lib, steps):
     return out
 
 
-def run_gpu(case, precision, steps, warmup, refine, graph=False, tune=False, net=None, pcg_max_iter=1000):
+def run_gpu(case, precision, steps, warmup, refine, graph=False, tune=False, net=None, pcg_max_iter=1000,
+            profile=True):
     """K timed whole solves of `case` in the given form (0 FP64, 1 FP32 with
     FP64 refinement, 2 conjugate gradients started from the network `net`),
     then the same K steps with stage profiling, then (FP64) the step replayed
@@ -73,14 +74,15 @@ def run_gpu(case, precision, steps, warmup, refine, graph=False, tune=False, net
     if net is not None:
         from paper_2103_08513_amd.surrogate import net_subdomains
         model.build_mbfs(kx, ky, kz, q)
+        torch.cuda.synchronize()
         nn_subs, nn_dims = net_subdomains(model)
         x0 = torch.zeros(model.mbf_layout()[-1], dtype=torch.float64, device=dev)
 
     def step():
         nonlocal X
         if nn_subs is not None:
-            from paper_2103_08513_amd.surrogate import warm_start
-            warm_start(model, net, nn_subs, nn_dims, x0)
+            from paper_2103_08513_amd.surrogate import warm_start_unet
+            warm_start_unet(model, net, nn_subs, nn_dims, x0)
         model.build_mbfs(kx, ky, kz, q, x0=x0, x0_scale=nn_subs is not None)
         model.assemble_interface()
         X = model.solve_interface(X, refine=refine)
@@ -100,13 +102,15 @@ def run_gpu(case, precision, steps, warmup, refine, graph=False, tune=False, net
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) * 1e3 / steps
     # stage times from HIP events over the same number of steps
-    L.mrcm_profile_reset()
-    L.mrcm_profile_enable(1)
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    stages = _stages(L, _lib, steps)
-    L.mrcm_profile_enable(0)
+    stages = {}
+    if profile:
+        L.mrcm_profile_reset()
+        L.mrcm_profile_enable(1)
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        stages = _stages(L, _lib, steps)
+        L.mrcm_profile_enable(0)
     graph_ms = None
     if graph and precision == 0:
         Xg = torch.empty_like(X)
@@ -277,33 +281,48 @@ def roofline_interface(res):
             "ms_per_step": st["ms_per_step"], "algorithmic_flops": ii.factor_flops}
 
 
-def train_surrogate(seeds=(1, 2), epochs=3):
-    """The warm-start network trained (outside any timed region) on the MBFs of
-    the FP64 path for 60x220x85 channelised fields of other seeds."""
+def train_surrogate(train_seeds=range(1000), test_seeds=range(1000, 1100), per_field=50, epochs=4):
+    """The encoder-decoder warm start trained (outside any timed region) on
+    MBFs the FP64 path builds for channelised fields (seeds 0-999, 50 MBFs per
+    field), then its gain measured on unseen fields (seeds 1000-1099): the
+    conjugate-gradient form's inner iterations from zero and from the
+    network's Galerkin-scaled guess."""
     import torch
     import paper_2103_08513_amd as lib
-    from mrcm_inputs import config2
-    from paper_2103_08513_amd.surrogate import WarmStartNet, features, net_subdomains
-    net = WarmStartNet(seed=0)
-    inps, tgts = [], []
+    from mrcm_inputs import config4_field
+    from paper_2103_08513_amd.surrogate import EncoderDecoder, UNET_LAYERS, mbf_dataset, net_subdomains, warm_start_unet
     t0 = time.perf_counter()
-    for seed in seeds:
-        c = config2(seed=seed)
-        pb = c.problem
-        m = lib.MRCM(pb, c.partition, c.iface, alpha=c.alpha, precision=lib.FP64)
-        m.build_mbfs(*(torch.as_tensor(a, dtype=torch.float64, device="cuda") for a in (pb.kx, pb.ky, pb.kz, pb.q)))
-        subs, dims = net_subdomains(m)
-        i, t = features(m, subs, dims)
-        inps.append(i)
-        tgts.append(t)
-        m.close()
-    inp, tgt = torch.cat(inps), torch.cat(tgts)
-    hist = net.train(inp, tgt, dims, epochs=epochs, batch=256, lr=3e-3, seed=0)
+    inp, tgt, dims = mbf_dataset(train_seeds, per_field)
+    t_data = time.perf_counter() - t0
+    net = EncoderDecoder(UNET_LAYERS, seed=0)
+    t0 = time.perf_counter()
+    hist = net.train(inp, tgt, epochs=epochs, batch=128, lr=1e-3)
     torch.cuda.synchronize()
-    info = {"params": net.n_params(), "train_fields": [f"channelised 60x220x85, seed {s}" for s in seeds],
-            "samples": int(inp.shape[0]), "epochs": epochs, "loss_by_epoch": hist,
-            "train_seconds": time.perf_counter() - t0}
-    del inp, tgt, inps, tgts
+    t_train = time.perf_counter() - t0
+    n_samples = int(inp.shape[0])
+    del inp, tgt
+    it0 = itn = 0
+    for seed in test_seeds:
+        c = config4_field(seed)
+        pb = c.problem
+        args = [torch.as_tensor(a, dtype=torch.float64, device="cuda") for a in (pb.kx, pb.ky, pb.kz, pb.q)]
+        m = lib.MRCM(pb, c.partition, c.iface, alpha=c.alpha, precision=lib.PCG, pcg_max_iter=1000)
+        m.build_mbfs(*args)
+        it0 += m.info().pcg_iters
+        subs, d = net_subdomains(m)
+        x0 = warm_start_unet(m, net, subs, d)
+        m.build_mbfs(*args, x0=x0, x0_scale=True)
+        itn += m.info().pcg_iters
+        m.close()
+    info = {"params": net.n_params(), "layers": [list(L) for L in UNET_LAYERS],
+            "train": f"channelised 60x60x15 fields, seeds {train_seeds[0]}-{train_seeds[-1]}, {per_field} MBFs each",
+            "samples": n_samples, "epochs": epochs, "loss_by_epoch": hist, "data_seconds": t_data,
+            "train_seconds": t_train,
+            "test": f"seeds {test_seeds[0]}-{test_seeds[-1]}: CG inner iterations to 1e-10 from zero {it0}, "
+                    f"from the network {itn}",
+            "test_iterations_saved_frac": (it0 - itn) / it0}
+    log(f"network trained: {info['params']} parameters, loss {[round(h, 3) for h in hist]}; unseen fields: "
+        f"{100 * info['test_iterations_saved_frac']:.1f} % fewer CG iterations")
     return net, info
 
 
@@ -343,7 +362,7 @@ def main():
     ap.add_argument("--no-block", action="store_true", help="skip the oracle comparison on the corner block")
     ap.add_argument("--no-graph", action="store_true", help="skip the replay of the recorded step")
     ap.add_argument("--tune", action="store_true", help="run the autotuner first (a handle per candidate)")
-    ap.add_argument("--cpu-sample", type=int, default=640, help="subdomains in the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="subdomains in the oracle's timed sample")
     ap.add_argument("--copy-calibration", type=float, default=None, metavar="MB",
                     help="only run a device copy of this many MB (counter calibration) and exit")
     args = ap.parse_args()
@@ -376,7 +395,7 @@ def main():
     surrogate = None
     if not args.no_surrogate:
         net, train_info = train_surrogate()
-        surrogate = run_gpu(case, 2, 1, 1, args.refine, net=net)
+        surrogate = run_gpu(case, 2, 1, 0, args.refine, net=net, profile=False)
         surrogate["train"] = train_info
         log(f"network-started CG ms/step {surrogate['ms_step']:.1f}")
     errs, t_ref = ({}, None) if args.no_block else block_errors(case, [0, 1] + ([2] if False else []), procs)
