@@ -812,8 +812,14 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 
   const SubDesc &D = g.sub[item.x];
   const int c0 = item.y, cw = item.z - item.y;
   const int N = D.N, b = D.b, m = D.m, W = b + kNB, bp1 = b + 1;
-  const int CP = (cw + 15) & ~15;
-  const int nct = CP >> 4;
+  // 16 t + 1 columns (t > 0): the last one runs on the vector ALUs instead
+  // of being padded into a column tile of its own, which would cost a third
+  // more matrix-core work at t = 2 for one column.  That column is local
+  // column vc; nct counts the MFMA column tiles and CP is the LDS row stride.
+  const bool vcol = (cw & 15) == 1 && cw > 1;
+  const int nct = vcol ? (cw >> 4) : ((cw + 15) >> 4);
+  const int vc = 16 * nct;
+  const int CP = vcol ? vc + 1 : vc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   // one panel buffer: the next panel waits in registers and is stored after
@@ -823,6 +829,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 
   T *Y = Dp + kNB * kNB;                        // ring [wmax][kMaxChunk] (stride CP)
   T *Zs = Y + (size_t)wmax * kMaxChunk;         // [16][kMaxChunk]
   T *Zp = Zs + (size_t)kNB * kMaxChunk;         // [16][kMaxChunk]: second part of the backward K split
+  T *Vp = Zp + (size_t)kNB * kMaxChunk;         // [16 parts][16 rows]: the vector column's backward sums
   const T *L = Lg + D.L_off;
   const T *Dinv = Dg + D.D_off;
   double *B = Bg + D.X_off;
@@ -953,6 +960,15 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 
         if (row < kb && col < cw) B[(size_t)(k + row) * m + c0 + col] = (double)acc[v];
       }
     }
+    // the vector column: wave 3 (no column tile of its own: nct <= 2 here),
+    // one lane per row of the block
+    if (vcol && wave == 3 && lane < kNB) {
+      T y = T(0);
+#pragma unroll 4
+      for (int jj = 0; jj < kNB; ++jj) y += dp[lane * kNB + jj] * Y[wrap(sk + jj, W) * CP + vc];
+      Zs[lane * CP + vc] = y;
+      if (lane < kb) B[(size_t)(k + lane) * m + c0 + vc] = (double)y;
+    }
     __syncthreads();
     // R2 -= L21 Y1: this wave's tiles (wave, wave+4, ...) with their MFMA
     // chains interleaved and all operands loaded first
@@ -997,6 +1013,16 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 
           }
         }
       }
+      // the vector column: one row per thread of waves 2 and 3, which hold
+      // one tile fewer than waves 0 and 1 whenever the tile count is 2 mod 4
+      if (vcol && tid >= 128 && tid - 128 < b) {
+        const int ii = tid - 128;
+        T *yp = Y + wrap(sk + kNB + ii, W) * CP + vc;
+        T cv = *yp;
+#pragma unroll 4
+        for (int jj = 0; jj < kNB; ++jj) cv -= lp[jj * ldb + (kNB + ii - jj)] * Zs[jj * CP + vc];
+        *yp = cv;
+      }
     }
     if (has_next) store_rows(k + W, sk);
     __syncthreads();
@@ -1008,9 +1034,15 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 
   // validity mask applied at use
   double yraw[4] = {0.0, 0.0, 0.0, 0.0};
   unsigned yok = 0u;
+  double yvraw = 0.0;  // wave 3, lanes 0-15: the vector column's entries
+  bool yvok = false;
   auto fetch_y = [&](int p) {
     const int k = p * kNB;
     yok = 0u;
+    if (vcol && wave == 3) {
+      yvok = lane < kNB && k + lane < N;
+      yvraw = B[(size_t)(yvok ? k + lane : 0) * m + (yvok ? c0 + vc : 0)];
+    }
     if (wave < nct) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -1036,6 +1068,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 
     typename M::v4 c;
 #pragma unroll
     for (int v = 0; v < 4; ++v) c[v] = ((yok >> v) & 1u) ? T(yraw[v]) : T(0);
+    const T yv = yvok ? T(yvraw) : T(0);  // this panel's, before the next fetch
     if (p > 0) {
       fetch_panel(p - 1);
       fetch_y(p - 1);
@@ -1113,6 +1146,19 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 
         }
       }
     }
+    // the vector column's L21^T X2: row i = tid & 15 of the block, offsets
+    // t of part tid >> 4 (16 parts of kPer offsets cover 4 KS >= b)
+    if (vcol) {
+      constexpr int kPer = (4 * KS + 15) / 16;
+      const int i = tid & 15, part = tid >> 4;
+      T sv = T(0);
+#pragma unroll 4
+      for (int q = 0; q < kPer; ++q) {
+        const int t = part * kPer + q;
+        if (t < b) sv += lp[i * ldb + (kNB + t - i)] * Y[wrap(sk + kNB + t, W) * CP + vc];
+      }
+      Vp[part * kNB + i] = sv;
+    }
     __syncthreads();
     // X1 = inv(L11)^T Z
     if (wave < nct) {
@@ -1138,6 +1184,28 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 
             else *dst += xv;
           }
         }
+      }
+    }
+    // the vector column on wave 3: z = y1 - (sum of the parts), then
+    // x = inv(L11)^T z with z gathered across lanes 0-15
+    if (vcol && wave == 3) {
+      T zi = T(0);
+      if (lane < kNB) {
+        T sv = T(0);
+#pragma unroll 4
+        for (int part = 0; part < 16; ++part) sv += Vp[part * kNB + lane];
+        zi = yv - sv;
+      }
+      const int i = lane & 15;
+      T xv = T(0);
+#pragma unroll 4
+      for (int j = 0; j < kNB; ++j) xv += dp[j * kNB + i] * __shfl(zi, j, 64);
+      if (lane < kb) {
+        Y[wrap(sk + lane, W) * CP + vc] = xv;
+        const double s = scaled ? sc[k + lane] : 1.0;
+        double *dst = Xo + (size_t)(k + lane) * m + c0 + vc;
+        if ((mode & 1) == 0) *dst = s * (double)xv;
+        else *dst += s * (double)xv;
       }
     }
     __syncthreads();
@@ -1415,7 +1483,7 @@ size_t solve_lds_bytes(int fp32, int bmax, int mmax) {
   (void)mmax;
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
   return ((size_t)kNB * solve_ldb(bmax) + kNB * kNB + (size_t)(bmax + kNB) * kMaxChunk +
-          (size_t)2 * kNB * kMaxChunk) * es;
+          (size_t)2 * kNB * kMaxChunk + (size_t)kNB * kNB) * es;
 }
 
 int solve_chunk_max() { return kMaxChunk; }
