@@ -709,33 +709,37 @@ __global__ __launch_bounds__(256, 2) void k_factor32(const SubDesc *__restrict__
 // ---------------------------------------------------------------------------
 // Multi-right-hand-side band solve with the stored factor, for one column
 // chunk [c0, c1) of one subdomain per workgroup.
-//   mode 0: B holds R; on exit B holds X = s.(L L^T)^{-1}(s.R)     (in place)
-//   mode 1: B holds a residual; Xout += s.(L L^T)^{-1}(s.B), B is clobbered.
+//   mode 0: B holds R; on exit X = s.(L L^T)^{-1}(s.R), and B holds the
+//           forward-sweep values (X may be B itself);
+//   mode 1: B holds a residual; X += s.(L L^T)^{-1}(s.B), B is clobbered.
 // s is 1/sqrt(diag) when `scaled` (the factor is of the Jacobi-scaled matrix
 // D^-1/2 A D^-1/2, which keeps the 16x16 diagonal blocks -- applied through
 // their explicit inverses -- well scaled under strong permeability contrast)
-// and 1 otherwise.  Forward sweep per panel: Y1 = inv(L11) R1 and
-// R2 -= L21 Y1 over a ring of W = b + kNB rows in LDS; backward sweep:
-// X1 = inv(L11)^T (Y1 - L21^T X2).  The next panel of L, its inverse diagonal
-// block and the next rows of B are fetched into registers while the current
-// panel computes, so each panel costs two workgroup barriers.
+// and 1 otherwise.
+//
+// Column-split form.  A workgroup of three waves; wave w < nct owns the
+// 16-column tile w of the chunk and runs both sweeps on it alone, holding its
+// band window in MFMA accumulators from panel to panel.  An accumulator tile
+// is the B operand of the next product as it stands: at k-step s lane l
+// supplies register s, which holds row crow(s, l) of the tile, so the A
+// operand (read from LDS) is taken at that same k index and no lane exchange
+// is needed.  Per 16-row panel:
+//   forward:  Y1 = inv(L11) R1 from the window's first tile; R2 -= L21 Y1 on
+//             the NRT tiles below it; the window moves down one tile and the
+//             next rows of the right-hand sides (fetched a panel ahead)
+//             enter at its end;
+//   backward: Z = Y1 - L21^T X2 over the NRT solved tiles below the panel,
+//             X1 = inv(L11)^T Z, and X1 enters the window.
+// A chunk of 16t + 1 columns gives its last column to wave nct, which runs
+// the same sweeps for that column on the vector ALUs with its window spread
+// over the lanes.  The waves share only the panels of L and of the
+// diagonal-block inverses, fetched into registers a panel ahead and staged
+// through two LDS buffers: one barrier per panel.
 // ---------------------------------------------------------------------------
-constexpr int kLReg = 12;   // L entries per thread and panel: 16*(b+1) <= 256*kLReg
-constexpr int kMaxChunk = 48;
-
-// Four independent 16x16x4 MFMAs summed: a 16x16x16 product without a
-// dependent chain (a[s], b[s] are the operands of k-step s).
-template <typename T>
-__device__ __forceinline__ typename Mma<T>::v4 mma16_split(const T (&a)[4], const T (&b)[4],
-                                                          typename Mma<T>::v4 c) {
-  using M = Mma<T>;
-  const typename M::v4 z = {T(0), T(0), T(0), T(0)};
-  typename M::v4 p1 = M::mma(a[1], b[1], z);
-  typename M::v4 p2 = M::mma(a[2], b[2], z);
-  typename M::v4 p3 = M::mma(a[3], b[3], z);
-  c = M::mma(a[0], b[0], c);
-  return (c + p1) + (p2 + p3);
-}
+constexpr int kBsWaves = 3;
+constexpr int kBsThreads = 64 * kBsWaves;
+constexpr int kMaxChunk = 16 * kBsWaves;
+constexpr int kDStride = kNB + 1;  // LDS row stride of an inverse diagonal block (bank spread)
 
 // R(:, c0..c1) = R0 - A^H_l X(:, c0..c1) for one work item, R0 holding the
 // right-hand sides (R0 may be R itself for a single sweep): the FP64 residual
@@ -743,7 +747,7 @@ __device__ __forceinline__ typename Mma<T>::v4 mma16_split(const T (&a)[4], cons
 // correction.  Matrix-free from the coefficients, kPB entries per thread at
 // a time with all their loads issued first (kPB = 4 in the FP32 kernel,
 // whose register budget at three workgroups per CU does not hold eight).
-template <int kPB>
+template <int kPB, int NT>
 __device__ __forceinline__ void item_residual(const Geom &g, const int4 item, const double *__restrict__ coef,
                                               const double *Xg, const double *R0g, double *Rg) {
   const SubDesc &S = g.sub[item.x];
@@ -754,11 +758,11 @@ __device__ __forceinline__ void item_residual(const Geom &g, const int4 item, co
   const double *R0 = R0g + S.X_off;
   double *R = Rg + S.X_off;
   const int ne = N * cw;
-  for (int e0 = threadIdx.x; e0 < ne; e0 += kPB * 256) {
+  for (int e0 = threadIdx.x; e0 < ne; e0 += kPB * NT) {
     double ax[kPB], rv[kPB];
 #pragma unroll
     for (int q = 0; q < kPB; ++q) {
-      const int e = min(e0 + q * 256, ne - 1);
+      const int e = min(e0 + q * NT, ne - 1);
       const int r = e / cw, c = c0 + e % cw;
       const size_t o = (size_t)r * m + c;
       const int rp1 = min(r + 1, N - 1), rm1 = max(r - 1, 0);
@@ -782,433 +786,349 @@ __device__ __forceinline__ void item_residual(const Geom &g, const int4 item, co
     }
 #pragma unroll
     for (int q = 0; q < kPB; ++q) {
-      const int e = e0 + q * 256;
+      const int e = e0 + q * NT;
       if (e < ne) R[(size_t)(e / cw) * m + c0 + e % cw] = rv[q] - ax[q];
     }
   }
 }
 
-// NBT: most R2-update tiles per wave; KS: k-steps of the backward L21^T
-// product (4*KS >= the largest band).  coef non-null (corrections only):
-// form the item's FP64 residual into Bg first, from the right-hand sides in
-// rhs0 (or in Bg itself when rhs0 is null).
-template <typename T, int mode, int NBT, int KS>
-// workgroups per CU: FP32 three (b <= 112) or two, FP64 two (b <= 112) or one
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? (KS > 28 ? 2 : 3) : (KS > 28 ? 1 : 2)) void k_solve(Geom g, const int4 *__restrict__ work,
-                                               const double *__restrict__ scal,
-                                               const T *__restrict__ Lg, const T *__restrict__ Dg,
-                                               double *Bg, double *Xg, int scaled, int ldb, int wmax,
-                                               const double *__restrict__ coef, const double *rhs0) {
+// NRT: most 16-row tiles of the band below a panel (b <= 16 NRT).  coef
+// non-null (corrections only): form the item's FP64 residual into Bg first,
+// from the right-hand sides in rhs0 (or in Bg itself when rhs0 is null).
+// Three waves per SIMD (four workgroups per CU).
+template <typename T, int mode, int NRT>
+__global__ __launch_bounds__(kBsThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_solve(Geom g, const int4 *__restrict__ work,
+                                                         const double *__restrict__ scal,
+                                                         const T *__restrict__ Lg, const T *__restrict__ Dg,
+                                                         double *Bg, double *Xg, int scaled,
+                                                         const double *__restrict__ coef, const double *rhs0) {
   using M = Mma<T>;
+  using v4 = typename M::v4;
+  constexpr int kLPer = (kNB * (16 * NRT + 1) + kBsThreads - 1) / kBsThreads;  // L entries per thread
+  // LDS column length of a staged panel: every offset a product reads,
+  // 1 .. 16 NRT + 15, lies inside the column, and those past b hold zeros,
+  // so that the A operands are read without masks
+  constexpr int kLdl = 16 * (NRT + 1);
+  constexpr int kLBuf = kNB * kLdl;
+  constexpr int kWF = 16 * (NRT + 1) / 64;      // vector column: forward window rows per lane
+  constexpr int kWB = (16 * NRT + 63) / 64;     // backward window rows per lane
+  static_assert(16 * (NRT + 1) % 64 == 0, "the forward window spans whole waves");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int4 item = work[blockIdx.x];
   if (item.x < 0) return;
   if constexpr ((mode & 1) != 0) {
     if (coef) {
-      item_residual<sizeof(T) == 8 ? 8 : 4>(g, item, coef, Xg, rhs0 ? rhs0 : Bg, Bg);
+      item_residual<4, kBsThreads>(g, item, coef, Xg, rhs0 ? rhs0 : Bg, Bg);
       __syncthreads();
     }
   }
   const SubDesc &D = g.sub[item.x];
   const int c0 = item.y, cw = item.z - item.y;
-  const int N = D.N, b = D.b, m = D.m, W = b + kNB, bp1 = b + 1;
-  // 16 t + 1 columns (t > 0): the last one runs on the vector ALUs instead
-  // of being padded into a column tile of its own, which would cost a third
-  // more matrix-core work at t = 2 for one column.  That column is local
-  // column vc; nct counts the MFMA column tiles and CP is the LDS row stride.
-  const bool vcol = (cw & 15) == 1 && cw > 1;
+  const int N = D.N, b = D.b, m = D.m, bp1 = b + 1;
+  const bool vcol = (cw & 15) == 1;
   const int nct = vcol ? (cw >> 4) : ((cw + 15) >> 4);
-  const int vc = 16 * nct;
-  const int CP = vcol ? vc + 1 : vc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-  // one panel buffer: the next panel waits in registers and is stored after
-  // the end-of-panel barrier, which keeps two workgroups within one CU's LDS
-  T *Lp = reinterpret_cast<T *>(smem_raw);     // [kNB][ldb], zero beyond offset b
-  T *Dp = Lp + kNB * ldb;                       // [kNB*kNB]
-  T *Y = Dp + kNB * kNB;                        // ring [wmax][kMaxChunk] (stride CP)
-  T *Zs = Y + (size_t)wmax * kMaxChunk;         // [16][kMaxChunk]
-  T *Zp = Zs + (size_t)kNB * kMaxChunk;         // [16][kMaxChunk]: second part of the backward K split
-  T *Vp = Zp + (size_t)kNB * kMaxChunk;         // [16 parts][16 rows]: the vector column's backward sums
+  const int lr = lane & 15;
+  const bool mwave = wave < nct;            // an MFMA column tile
+  const bool vwave = vcol && wave == nct;   // the vector column
+  const int lcol = 16 * wave + lr;          // an MFMA lane's column in the chunk
+  const bool colok = mwave && lcol < cw;
+  const int lsz = kNB * bp1;                // entries of one panel of L
+  T *Lb = reinterpret_cast<T *>(smem_raw);  // [2][16][kLdl]: panels, column-major, zero past b
+  T *Db = Lb + 2 * kLBuf;                   // [2][16][kDStride]
   const T *L = Lg + D.L_off;
   const T *Dinv = Dg + D.D_off;
   double *B = Bg + D.X_off;
   double *Xo = Xg + D.X_off;
   const double *sc = scal + D.cell_off;
   const int nP = (N + kNB - 1) / kNB;
-  const int lcnt = kNB * bp1;
+  double *Bc = B + c0 + (colok ? lcol : 0);  // this lane's column (row stride m)
+  double *Bv = B + c0 + (vwave ? 16 * nct : 0);
+  double *Xc = Xo + c0 + (colok ? lcol : 0);
+  double *Xv = Xo + c0 + (vwave ? 16 * nct : 0);
 
-  // the next panel of L and its diagonal-block inverse, loaded without any
-  // arithmetic or branch on the loaded values (a validity mask is applied
-  // when they are stored) so that the loads stay in flight
-  T lreg[kLReg];
-  T dreg;
+  // the next panel of L and of the inverses, loaded without arithmetic or
+  // branches on the loaded values (masks are applied when they are stored)
+  T lreg[kLPer], dreg[2];
   unsigned lok = 0u;
+  // LDS position of this thread's entries e = tid + 192 j of a panel
+  int ldst[kLPer];
+#pragma unroll
+  for (int j = 0; j < kLPer; ++j) {
+    const int e = tid + kBsThreads * j, col = e / bp1;
+    ldst[j] = col * kLdl + (e - col * bp1);
+  }
+  for (int e = tid; e < 2 * kLBuf; e += kBsThreads) Lb[e] = T(0);
   auto fetch_panel = [&](int p) {
-    const size_t base = (size_t)p * kNB * bp1;
-    const int ncol = min(kNB, N - p * kNB);
+    const T *src = L + (size_t)p * lsz;
+    const int lim = min(kNB, N - p * kNB) * bp1;  // columns past the last row stay zero
     lok = 0u;
 #pragma unroll
-    for (int i = 0; i < kLReg; ++i) {
-      const int e = tid + 256 * i;
-      const bool ok = e < lcnt && e / bp1 < ncol;
-      lreg[i] = L[base + (ok ? e : 0)];
-      lok |= ok ? (1u << i) : 0u;
+    for (int j = 0; j < kLPer; ++j) {
+      const int e = tid + kBsThreads * j;
+      const bool ok = e < lim;
+      lreg[j] = src[ok ? e : 0];
+      lok |= ok ? (1u << j) : 0u;
     }
-    dreg = Dinv[(size_t)p * kNB * kNB + tid];
+    const T *dsrc = Dinv + (size_t)p * kNB * kNB;
+    dreg[0] = dsrc[tid];
+    dreg[1] = dsrc[min(tid + kBsThreads, kNB * kNB - 1)];
   };
-  auto store_panel = [&]() {
-    T *lp = Lp;
+  auto store_panel = [&](int buf) {
+    T *lp = Lb + buf * kLBuf;
 #pragma unroll
-    for (int i = 0; i < kLReg; ++i) {
-      const int e = tid + 256 * i;
-      if (e < lcnt) lp[(e / bp1) * ldb + e % bp1] = ((lok >> i) & 1u) ? lreg[i] : T(0);
+    for (int j = 0; j < kLPer; ++j) {
+      const int e = tid + kBsThreads * j;
+      if (e < lsz) lp[ldst[j]] = ((lok >> j) & 1u) ? lreg[j] : T(0);
     }
-    Dp[tid] = dreg;
-  };
-  // rows of B for the forward sweep: 16 rows x CP columns, 3 per thread.
-  // The raw values and their scale factors are held as loaded (any
-  // arithmetic on them here would wait for the loads); they are combined
-  // when stored, one panel later.
-  constexpr int kRReg = (kNB * kMaxChunk) / 256;
-  double rraw[kRReg], rsc[kRReg];
-  unsigned rok = 0u;
-  auto fetch_rows = [&](int r0) {
-    rok = 0u;
-#pragma unroll
-    for (int i = 0; i < kRReg; ++i) {
-      const int e = tid + 256 * i;
-      const int rr = r0 + e / CP, c = e % CP;
-      const bool ok = e < kNB * CP && rr < N && c < cw;
-      const int rrc = ok ? rr : 0;
-      rraw[i] = B[(size_t)rrc * m + (ok ? c0 + c : 0)];
-      rsc[i] = scaled ? sc[rrc] : 1.0;
-      rok |= ok ? (1u << i) : 0u;
-    }
-  };
-  auto store_rows = [&](int r0, int sk0) {
-#pragma unroll
-    for (int i = 0; i < kRReg; ++i) {
-      const int e = tid + 256 * i;
-      if (e < kNB * CP) Y[wrap(sk0 + e / CP, W) * CP + e % CP] = ((rok >> i) & 1u) ? T(rsc[i] * rraw[i]) : T(0);
-    }
+    T *dp = Db + buf * (kNB * kDStride);
+    dp[(tid >> 4) * kDStride + (tid & 15)] = dreg[0];
+    const int e1 = tid + kBsThreads;
+    if (e1 < kNB * kNB) dp[(e1 >> 4) * kDStride + (e1 & 15)] = dreg[1];
   };
 
-  // panel buffers start at zero: their padding beyond offset b stays zero
-  for (int e = tid; e < kNB * ldb; e += 256) Lp[e] = T(0);
-  __syncthreads();
   // ------------------------------ forward ------------------------------
-  {
-    const int nrow = min(N, W);
-    // loads batched as in the factor's prologue
-    constexpr int kPB = 8;
-    for (int e0 = tid; e0 < W * CP; e0 += kPB * 256) {
-      double bv[kPB], sv[kPB];
+  // MFMA waves: R[0] the panel's rows, R[1 + ti] the tiles below; rows
+  // 16 s + crow(v, lane) of the window in R[s][v]
+  v4 R[NRT + 1];
+  double nraw[4], nsc[4];
+  unsigned nok = 0u;
+  auto fetch_rows = [&](int r0) {
+    nok = 0u;
 #pragma unroll
-      for (int q = 0; q < kPB; ++q) {
-        const int e = e0 + q * 256;
-        const int rr = e / CP, c = e % CP;
-        const bool ok = e < W * CP && rr < nrow && c < cw;
-        bv[q] = B[ok ? (size_t)rr * m + c0 + c : 0];
-        sv[q] = scaled ? sc[ok ? rr : 0] : 1.0;
-      }
-#pragma unroll
-      for (int q = 0; q < kPB; ++q) {
-        const int e = e0 + q * 256;
-        const int rr = e / CP, c = e % CP;
-        if (e < W * CP) {
-          T v = T(0);
-          if (rr < nrow && c < cw) v = T((scaled ? sv[q] : 1.0) * bv[q]);
-          Y[e] = v;
-        }
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + M::crow(v, lane);
+      const bool ok = colok && r < N;
+      nraw[v] = Bc[(size_t)(ok ? r : 0) * m];
+      nsc[v] = sc[ok ? r : 0];
+      nok |= ok ? (1u << v) : 0u;
     }
-    fetch_panel(0);
-    store_panel();
+  };
+  auto rows_tile = [&]() {
+    v4 t;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] = ((nok >> v) & 1u) ? T((scaled ? nsc[v] : 1.0) * nraw[v]) : T(0);
+    return t;
+  };
+  // vector wave: window row lane + 64 j in vw[j]; vnew the next 16 rows
+  T vw[kWF > kWB ? kWF : kWB];
+  double vraw = 0.0, vscl = 1.0;
+  bool vok = false;
+  auto fetch_vrow = [&](int r) {  // lanes 0-15: row r + lane
+    vok = lane < kNB && r + lane < N;
+    vraw = Bv[(size_t)(vok ? r + lane : 0) * m];
+    vscl = sc[vok ? r + lane : 0];
+  };
+  if (mwave) {
+#pragma unroll
+    for (int s = 0; s <= NRT; ++s) {
+      fetch_rows(16 * s);
+      R[s] = rows_tile();
+    }
+    fetch_rows(16 * (NRT + 1));
   }
-  __syncthreads();
-  const T *lp = Lp;
-  const T *dp = Dp;
-  for (int p = 0; p < nP; ++p) {
-    const int k = p * kNB;
-    const int kb = min(kNB, N - k);
-    const int sk = k % W;
-    const bool has_next = p + 1 < nP;
-    if (p > 0) {
-      store_panel();
-      __syncthreads();
-    }
-    if (has_next) {
-      fetch_panel(p + 1);
-      fetch_rows(k + W);
-    }
-    // Y1 = inv(L11) R1
-    typename M::v4 acc = {0, 0, 0, 0};
-    if (wave < nct) {
-      T a[4], bb[4];
+  if (vwave) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int jj = 4 * s + lk;
-        a[s] = dp[lr * kNB + jj];
-        bb[s] = Y[wrap(sk + jj, W) * CP + wave * 16 + lr];
+    for (int j = 0; j < kWF; ++j) {
+      const int r = lane + 64 * j;
+      vw[j] = r < N ? T((scaled ? sc[r] : 1.0) * Bv[(size_t)r * m]) : T(0);
+    }
+    fetch_vrow(16 * (NRT + 1));
+  }
+  fetch_panel(0);
+  __syncthreads();  // zeroed buffers
+  store_panel(0);
+  for (int p = 0; p < nP; ++p) {
+    const int k = p * kNB, kb = min(kNB, N - k);
+    const T *lp = Lb + (p & 1) * kLBuf;
+    const T *dp = Db + (p & 1) * (kNB * kDStride);
+    const bool has_next = p + 1 < nP;
+    __syncthreads();  // panel p staged; panel p - 1's buffer free
+    if (has_next) fetch_panel(p + 1);
+    if (mwave) {
+      // Y1 = inv(L11) R1 (two chains)
+      v4 ya = {T(0), T(0), T(0), T(0)}, yb = ya;
+#pragma unroll
+      for (int s = 0; s < 4; s += 2) {
+        ya = M::mma(dp[lr * kDStride + M::crow(s, lane)], R[0][s], ya);
+        yb = M::mma(dp[lr * kDStride + M::crow(s + 1, lane)], R[0][s + 1], yb);
       }
-      acc = mma16_split<T>(a, bb, acc);
+      v4 y = ya + yb;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = M::crow(v, lane), col = wave * 16 + lr;
-        Zs[row * CP + col] = acc[v];
-        if (row < kb && col < cw) B[(size_t)(k + row) * m + c0 + col] = (double)acc[v];
+        const int row = M::crow(v, lane);
+        y[v] = row < kb ? y[v] : T(0);
+        if (colok && row < kb) Bc[(size_t)(k + row) * m] = (double)y[v];
       }
+      // R2 -= L21 Y1: tile ti, k-step s: A = L21[16 ti + lr][crow(s, lane)].
+      // Every tile of the window, without branches (tiles past the band and
+      // the last panel's update, which reaches only rows past N, add zeros or
+      // unused values): a branch per tile would copy the accumulator array.
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = M::crow(s, lane);
+        T a[NRT];
+#pragma unroll
+        for (int ti = 0; ti < NRT; ++ti) {
+          a[ti] = lp[kk * kLdl + 16 + 16 * ti + lr - kk];
+        }
+#pragma unroll
+        for (int ti = 0; ti < NRT; ++ti) R[ti + 1] = M::mma(-a[ti], y[s], R[ti + 1]);
+      }
+      // the window moves down one tile
+#pragma unroll
+      for (int i = 0; i < NRT; ++i) R[i] = R[i + 1];
+      R[NRT] = rows_tile();
+      if (has_next) fetch_rows(k + kNB + 16 * (NRT + 1));
     }
-    // the vector column: wave 3 (no column tile of its own: nct <= 2 here),
-    // one lane per row of the block
-    if (vcol && wave == 3 && lane < kNB) {
+    if (vwave) {
+      const int i = lane & 15;
       T y = T(0);
 #pragma unroll 4
-      for (int jj = 0; jj < kNB; ++jj) y += dp[lane * kNB + jj] * Y[wrap(sk + jj, W) * CP + vc];
-      Zs[lane * CP + vc] = y;
-      if (lane < kb) B[(size_t)(k + lane) * m + c0 + vc] = (double)y;
-    }
-    __syncthreads();
-    // R2 -= L21 Y1: this wave's tiles (wave, wave+4, ...) with their MFMA
-    // chains interleaved and all operands loaded first
-    if (k + kb < N) {
-      const int nrt = (b + 15) >> 4;
-      const int ntile = nrt * nct;
-      const int cnt_all = (ntile - wave + 3) >> 2;
-      for (int t0 = 0; t0 < cnt_all; t0 += NBT) {
-        const int cnt = min(NBT, cnt_all - t0);
-        int ti[NBT], ct[NBT];
-        typename M::v4 c[NBT];
-        T a[NBT][4], bb[NBT][4];
-#pragma unroll
-        for (int t = 0; t < NBT; ++t) {
-          const int tile = wave + 4 * (t0 + (t < cnt ? t : 0));
-          ti[t] = tile / nct;
-          ct[t] = tile % nct;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int ii = ti[t] * 16 + M::crow(v, lane);
-            c[t][v] = Y[wrap(sk + kNB + min(ii, b - 1), W) * CP + ct[t] * 16 + lr];
-          }
-#pragma unroll
-          for (int s2 = 0; s2 < 4; ++s2) {
-            const int jj = 4 * s2 + lk;
-            a[t][s2] = lp[jj * ldb + (kNB + ti[t] * 16 + lr - jj)];
-            bb[t][s2] = Zs[jj * CP + ct[t] * 16 + lr];
-          }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) {
-#pragma unroll
-          for (int t = 0; t < NBT; ++t) c[t] = M::mma(-a[t][s2], bb[t][s2], c[t]);
-        }
-#pragma unroll
-        for (int t = 0; t < NBT; ++t) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int ii = ti[t] * 16 + M::crow(v, lane);
-            if (t < cnt && ii < b) Y[wrap(sk + kNB + ii, W) * CP + ct[t] * 16 + lr] = c[t][v];
-          }
-        }
-      }
-      // the vector column: one row per thread of waves 2 and 3, which hold
-      // one tile fewer than waves 0 and 1 whenever the tile count is 2 mod 4
-      if (vcol && tid >= 128 && tid - 128 < b) {
-        const int ii = tid - 128;
-        T *yp = Y + wrap(sk + kNB + ii, W) * CP + vc;
-        T cv = *yp;
+      for (int j = 0; j < kNB; ++j) y += dp[i * kDStride + j] * __shfl(vw[0], j, 64);
+      if (i >= kb) y = T(0);
+      if (lane < kb) Bv[(size_t)(k + lane) * m] = (double)y;
 #pragma unroll 4
-        for (int jj = 0; jj < kNB; ++jj) cv -= lp[jj * ldb + (kNB + ii - jj)] * Zs[jj * CP + vc];
-        *yp = cv;
+      for (int jj = 0; jj < kNB; ++jj) {
+        const T yj = __shfl(y, jj, 64);
+#pragma unroll
+        for (int j = 0; j < kWF; ++j) {
+          const int ii = lane + 64 * j - 16;  // row below the panel
+          const int off = 16 + ii - jj;
+          const T a = ii >= 0 ? lp[jj * kLdl + max(off, 0)] : T(0);
+          vw[j] -= a * yj;
+        }
       }
+      // the window moves down 16 rows: row w takes row w + 16
+      const T vnew = vok ? T((scaled ? vscl : 1.0) * vraw) : T(0);
+      const int src = (lane + 16) & 63;
+      T sh[kWF];
+#pragma unroll
+      for (int j = 0; j < kWF; ++j) sh[j] = __shfl(vw[j], src, 64);
+      const T nv = __shfl(vnew, src, 64);
+#pragma unroll
+      for (int j = 0; j < kWF; ++j) vw[j] = lane < 48 ? sh[j] : (j + 1 < kWF ? sh[j + 1] : nv);
+      if (has_next) fetch_vrow(k + kNB + 16 * (NRT + 1));
     }
-    if (has_next) store_rows(k + W, sk);
-    __syncthreads();
+    if (has_next) store_panel((p + 1) & 1);
   }
 
   // ------------------------------ backward ------------------------------
-  for (int e = tid; e < W * CP; e += 256) Y[e] = T(0);
-  // B rows of the next panel for the backward sweep, as loaded (FP64) with a
-  // validity mask applied at use
-  double yraw[4] = {0.0, 0.0, 0.0, 0.0};
-  unsigned yok = 0u;
-  double yvraw = 0.0;  // wave 3, lanes 0-15: the vector column's entries
-  bool yvok = false;
-  auto fetch_y = [&](int p) {
-    const int k = p * kNB;
-    yok = 0u;
-    if (vcol && wave == 3) {
-      yvok = lane < kNB && k + lane < N;
-      yvraw = B[(size_t)(yvok ? k + lane : 0) * m + (yvok ? c0 + vc : 0)];
-    }
-    if (wave < nct) {
+  // The last panel is still staged in its buffer.  MFMA waves: X[ti] the
+  // solved tile ti below the panel (rows k + 16 + 16 ti + crow(v, lane)).
+  v4 X[NRT];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = M::crow(v, lane), col = wave * 16 + lr;
-        const bool ok = k + row < N && col < cw;
-        yraw[v] = B[(size_t)(ok ? k + row : 0) * m + (ok ? c0 + col : 0)];
-        yok |= ok ? (1u << v) : 0u;
-      }
+  for (int i = 0; i < NRT; ++i) X[i] = (v4){T(0), T(0), T(0), T(0)};
+  double yraw[4];
+  unsigned yok = 0u;
+  auto fetch_y = [&](int p) {
+    yok = 0u;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = p * kNB + M::crow(v, lane);
+      const bool ok = colok && r < N;
+      yraw[v] = Bc[(size_t)(ok ? r : 0) * m];
+      yok |= ok ? (1u << v) : 0u;
     }
   };
-  fetch_panel(nP - 1);
-  store_panel();
-  fetch_y(nP - 1);
-  __syncthreads();
+  // vector wave: window row (below the panel) lane + 64 j in vw[j]
+#pragma unroll
+  for (int j = 0; j < (kWF > kWB ? kWF : kWB); ++j) vw[j] = T(0);
+  double vyraw = 0.0;
+  bool vyok = false;
+  auto fetch_vy = [&](int p) {
+    vyok = lane < kNB && p * kNB + lane < N;
+    vyraw = Bv[(size_t)(vyok ? p * kNB + lane : 0) * m];
+  };
+  if (mwave) fetch_y(nP - 1);
+  if (vwave) fetch_vy(nP - 1);
   for (int p = nP - 1; p >= 0; --p) {
-    const int k = p * kNB;
-    const int kb = min(kNB, N - k);
-    const int sk = k % W;
-    if (p < nP - 1) {
-      store_panel();
-      __syncthreads();
-    }
-    typename M::v4 c;
+    const int k = p * kNB, kb = min(kNB, N - k);
+    const T *lp = Lb + (p & 1) * kLBuf;
+    const T *dp = Db + (p & 1) * (kNB * kDStride);
+    const bool has_prev = p > 0;
+    if (p < nP - 1) __syncthreads();  // panel p staged
+    if (has_prev) fetch_panel(p - 1);
+    if (mwave) {
+      v4 z0, z1 = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-    for (int v = 0; v < 4; ++v) c[v] = ((yok >> v) & 1u) ? T(yraw[v]) : T(0);
-    const T yv = yvok ? T(yvraw) : T(0);  // this panel's, before the next fetch
-    if (p > 0) {
-      fetch_panel(p - 1);
-      fetch_y(p - 1);
-    }
-    // Z = Y1 - L21^T X2 over K = b (the offsets t = 4 s2 + lk, s2 < KS), split
-    // so that all four waves take part: with up to two column tiles, wave w
-    // takes tile w & 1 over half w >> 1 of K; with three, waves 0-2 take
-    // tile w over the first three quarters of K and wave 3 the last quarter
-    // of all three tiles.  The first part (with Y1) goes to Zs, the second
-    // to Zp; X1 adds them.  Each part runs as independent MFMA chains with
-    // all its operands loaded first.
-    {
-      // one K range [s0, s0 + NS) of the sum for column tile ct, into acc, in
-      // batches of at most 14 steps (operands of a batch loaded first)
-      auto zpart = [&](auto ns_c, int s0, int ct, typename M::v4 &acc) {
-        constexpr int NS = decltype(ns_c)::value;
-        constexpr int KB = 14;
-        // lane-derived offsets recomputed per panel: hoisted out of the
-        // panel loop they would hold dozens of registers across it
-        int lkk = lk, lrr = lr;
-        asm volatile("" : "+v"(lkk), "+v"(lrr));
-        const typename M::v4 z = {T(0), T(0), T(0), T(0)};
-        typename M::v4 p1 = z, p2 = z, p3 = z;
+      for (int v = 0; v < 4; ++v) z0[v] = ((yok >> v) & 1u) ? T(yraw[v]) : T(0);
+      if (has_prev) fetch_y(p - 1);
+      // Z = Y1 - L21^T X2: tile ti, k-step s: A = L[k + 16 + 16 ti + crow(s, lane)][k + lr]
 #pragma unroll
-        for (int q = 0; q < (NS + KB - 1) / KB; ++q) {
-          T a[KB], bb[KB];
+      for (int ti = 0; ti < NRT; ++ti) {
+        T a[4];
 #pragma unroll
-          for (int s3 = 0; s3 < KB; ++s3) {
-            if (q * KB + s3 < NS) {
-              const int t = 4 * (s0 + q * KB + s3) + lkk;
-              // offsets clamped into the panel row; entries past the band
-              // meet a zero operand
-              a[s3] = lp[lrr * ldb + (kNB + min(t, b - 1) - lrr)];
-              bb[s3] = (t < b) ? Y[wrap(sk + kNB + min(t, b - 1), W) * CP + ct * 16 + lrr] : T(0);
-            }
-          }
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int s3 = 0; s3 < KB; s3 += 4) {
-            if (q * KB + s3 < NS) acc = M::mma(-a[s3], bb[s3], acc);
-            if (q * KB + s3 + 1 < NS && s3 + 1 < KB) p1 = M::mma(-a[s3 + 1], bb[s3 + 1], p1);
-            if (q * KB + s3 + 2 < NS && s3 + 2 < KB) p2 = M::mma(-a[s3 + 2], bb[s3 + 2], p2);
-            if (q * KB + s3 + 3 < NS && s3 + 3 < KB) p3 = M::mma(-a[s3 + 3], bb[s3 + 3], p3);
-          }
+        for (int s = 0; s < 4; ++s) {
+          a[s] = lp[lr * kLdl + 16 + 16 * ti + M::crow(s, lane) - lr];
         }
-        acc = (acc + p1) + (p2 + p3);
-        __builtin_amdgcn_sched_barrier(0);
-      };
-      auto zstore = [&](T *dst, int ct, const typename M::v4 &acc) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) dst[M::crow(v, lane) * CP + ct * 16 + lr] = acc[v];
-      };
-      const typename M::v4 z = {T(0), T(0), T(0), T(0)};
-      if (nct <= 2) {
-        constexpr int KH = (KS + 1) / 2;
-        const int ct = wave & 1, h = wave >> 1;
-        if (ct < nct) {
-          typename M::v4 acc = h ? z : c;
-          zpart(std::integral_constant<int, KH>{}, h * KH, ct, acc);
-          zstore(h ? Zp : Zs, ct, acc);
-        }
-      } else {
-        constexpr int K1 = (3 * KS + 3) / 4, K2 = KS - K1;
-        if (wave < 3) {
-          typename M::v4 acc = c;
-          zpart(std::integral_constant<int, K1>{}, 0, wave, acc);
-          zstore(Zs, wave, acc);
-        } else {
-#pragma unroll
-          for (int ct = 0; ct < 3; ++ct) {
-            typename M::v4 acc = z;
-            zpart(std::integral_constant<int, K2>{}, K1, ct, acc);
-            zstore(Zp, ct, acc);
-          }
-        }
+        z0 = M::mma(-a[0], X[ti][0], z0);
+        z1 = M::mma(-a[1], X[ti][1], z1);
+        z0 = M::mma(-a[2], X[ti][2], z0);
+        z1 = M::mma(-a[3], X[ti][3], z1);
       }
-    }
-    // the vector column's L21^T X2: row i = tid & 15 of the block, offsets
-    // t of part tid >> 4 (16 parts of kPer offsets cover 4 KS >= b)
-    if (vcol) {
-      constexpr int kPer = (4 * KS + 15) / 16;
-      const int i = tid & 15, part = tid >> 4;
-      T sv = T(0);
-#pragma unroll 4
-      for (int q = 0; q < kPer; ++q) {
-        const int t = part * kPer + q;
-        if (t < b) sv += lp[i * ldb + (kNB + t - i)] * Y[wrap(sk + kNB + t, W) * CP + vc];
-      }
-      Vp[part * kNB + i] = sv;
-    }
-    __syncthreads();
-    // X1 = inv(L11)^T Z
-    if (wave < nct) {
-      typename M::v4 acc = {0, 0, 0, 0};
-      T a[4], bb[4];
+      const v4 z = z0 + z1;
+      // X1 = inv(L11)^T Z (two chains)
+      v4 xa = {T(0), T(0), T(0), T(0)}, xb = xa;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int jj = 4 * s + lk;
-        a[s] = dp[jj * kNB + lr];
-        bb[s] = Zs[jj * CP + wave * 16 + lr] + Zp[jj * CP + wave * 16 + lr];
+      for (int s = 0; s < 4; s += 2) {
+        xa = M::mma(dp[M::crow(s, lane) * kDStride + lr], z[s], xa);
+        xb = M::mma(dp[M::crow(s + 1, lane) * kDStride + lr], z[s + 1], xb);
       }
-      acc = mma16_split<T>(a, bb, acc);
+      v4 x = xa + xb;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = M::crow(v, lane), col = wave * 16 + lr;
-        if (row < kb) {
-          Y[wrap(sk + row, W) * CP + col] = acc[v];
-          if (col < cw) {
-            const double s = scaled ? sc[k + row] : 1.0;
-            const double xv = s * (double)acc[v];
-            double *dst = Xo + (size_t)(k + row) * m + c0 + col;
-            if ((mode & 1) == 0) *dst = xv;
-            else *dst += xv;
-          }
+        const int row = M::crow(v, lane);
+        x[v] = row < kb ? x[v] : T(0);
+        if (colok && row < kb) {
+          const double s = scaled ? sc[k + row] : 1.0;
+          double *dst = Xc + (size_t)(k + row) * m;
+          if ((mode & 1) == 0) *dst = s * (double)x[v];
+          else *dst += s * (double)x[v];
         }
       }
+#pragma unroll
+      for (int i = NRT - 1; i > 0; --i) X[i] = X[i - 1];
+      X[0] = x;
     }
-    // the vector column on wave 3: z = y1 - (sum of the parts), then
-    // x = inv(L11)^T z with z gathered across lanes 0-15
-    if (vcol && wave == 3) {
-      T zi = T(0);
-      if (lane < kNB) {
-        T sv = T(0);
+    if (vwave) {
+      const T ycur = vyok ? T(vyraw) : T(0);
+      if (has_prev) fetch_vy(p - 1);
+      // lanes (i, g): sum over the window rows t = g + 4 q of L[k+16+t][k+i] X2[t]
+      const int i = lane & 15, gq = lane >> 4;
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < kWB; ++j) {
 #pragma unroll 4
-        for (int part = 0; part < 16; ++part) sv += Vp[part * kNB + lane];
-        zi = yv - sv;
+        for (int q = 0; q < 16; ++q) {
+          const int tl = gq + 4 * q, t = 64 * j + tl;
+          const T xt = __shfl(vw[j], tl, 64);
+          // slots t >= 16 NRT lie past the window: the clamp reads a zero
+          acc += lp[i * kLdl + min(16 + t - i, kLdl - 1)] * xt;
+        }
       }
-      const int i = lane & 15;
-      T xv = T(0);
+      acc += __shfl_xor(acc, 16, 64);
+      acc += __shfl_xor(acc, 32, 64);
+      const T z = ycur - acc;  // lanes 0-15
+      T x = T(0);
 #pragma unroll 4
-      for (int j = 0; j < kNB; ++j) xv += dp[j * kNB + i] * __shfl(zi, j, 64);
+      for (int j = 0; j < kNB; ++j) x += dp[j * kDStride + i] * __shfl(z, j, 64);
+      if (i >= kb) x = T(0);
       if (lane < kb) {
-        Y[wrap(sk + lane, W) * CP + vc] = xv;
         const double s = scaled ? sc[k + lane] : 1.0;
-        double *dst = Xo + (size_t)(k + lane) * m + c0 + vc;
-        if ((mode & 1) == 0) *dst = s * (double)xv;
-        else *dst += s * (double)xv;
+        double *dst = Xv + (size_t)(k + lane) * m;
+        if ((mode & 1) == 0) *dst = s * (double)x;
+        else *dst += s * (double)x;
       }
+      // the new rows enter at the start of the window: row t takes row t - 16
+      const int src = (lane - 16) & 63;
+      T sh[kWB];
+#pragma unroll
+      for (int j = 0; j < kWB; ++j) sh[j] = __shfl(vw[j], src, 64);
+#pragma unroll
+      for (int j = 0; j < kWB; ++j) vw[j] = lane >= 16 ? sh[j] : (j == 0 ? x : sh[j - 1]);
     }
-    __syncthreads();
+    if (has_prev) store_panel((p - 1) & 1);
   }
 }
 
@@ -1477,13 +1397,11 @@ size_t factor_lds_bytes(int fp32, int bmax) {
 }
 
 // Column stride of the solve's panel buffers: operand offsets reach b + 31.
-int solve_ldb(int bmax) { return bmax + 33; }
-
 size_t solve_lds_bytes(int fp32, int bmax, int mmax) {
   (void)mmax;
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
-  return ((size_t)kNB * solve_ldb(bmax) + kNB * kNB + (size_t)(bmax + kNB) * kMaxChunk +
-          (size_t)2 * kNB * kMaxChunk + (size_t)kNB * kNB) * es;
+  const int nrt = bmax <= 112 ? 7 : (kMaxBand32 + 15) / 16;
+  return (2 * (size_t)kNB * 16 * (nrt + 1) + 2 * (size_t)kNB * kDStride) * es;
 }
 
 int solve_chunk_max() { return kMaxChunk; }
@@ -1517,29 +1435,31 @@ hipError_t launch_factor(int fp32, const SubDesc *subs, const int *order, int n_
                          (double *)L, (double *)Dg, st, bmax, s);
 }
 
-template <typename T, int mode, int NBT, int KS>
+template <typename T, int mode, int NRT>
 static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, const double *scal,
                                  const T *L, const T *Dg, double *B, double *X, int bmax, int scaled,
                                  hipStream_t s, const double *coef, const double *rhs0) {
   const size_t lds = solve_lds_bytes(sizeof(T) == 4, bmax, 0);
-  hipError_t e = hipFuncSetAttribute((const void *)k_solve<T, mode, NBT, KS>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_solve<T, mode, NRT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_solve<T, mode, NBT, KS>), dim3(n_work), dim3(256), lds, s, g, work, scal, L, Dg, B,
-                     X, scaled, solve_ldb(bmax), bmax + kNB, coef, rhs0);
+  hipLaunchKernelGGL((k_solve<T, mode, NRT>), dim3(n_work), dim3(kBsThreads), lds, s, g, work, scal, L, Dg, B,
+                     X, scaled, coef, rhs0);
   return hipGetLastError();
 }
 
-// NBT: tiles per MFMA batch, three, which keeps the registers within two
-// workgroups per CU; KS = ceil(b/4) for the largest band the instantiation
-// serves.
+// NRT = 7 serves bands up to 112 (FP64, and FP32 up to there); FP32 takes
+// bands up to 176 with NRT = 11.
 template <typename T, int mode>
 static hipError_t launch_solve_m(const Geom &g, const int4 *work, int n_work, const double *scal,
                                  const T *L, const T *Dg, double *B, double *X, int bmax, hipStream_t s,
                                  const double *coef, const double *rhs0) {
   if (bmax <= 112)
-    return launch_solve_t<T, mode, sizeof(T) == 8 ? 4 : 3, 28>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef, rhs0);
-  return launch_solve_t<T, mode, 3, (kMaxBand32 + 3) / 4>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef, rhs0);
+    return launch_solve_t<T, mode, 7>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef, rhs0);
+  if constexpr (sizeof(T) == 4)
+    return launch_solve_t<T, mode, (kMaxBand32 + 15) / 16>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef,
+                                                             rhs0);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, const double *scal,
@@ -1590,13 +1510,12 @@ int factor32_blocks_per_cu(int bmax) {
 // Workgroups of the solve that one CU holds at once.
 int solve_blocks_per_cu(int fp32, int bmax) {
   const size_t lds = solve_lds_bytes(fp32, bmax, 0);
-  const void *k = fp32 ? (bmax <= 112 ? (const void *)k_solve<float, 0, 3, 28>
-                                      : (const void *)k_solve<float, 0, 3, (kMaxBand32 + 3) / 4>)
-                       : (bmax <= 112 ? (const void *)k_solve<double, 0, 4, 28>
-                                      : (const void *)k_solve<double, 0, 3, (kMaxBand32 + 3) / 4>);
+  const void *k = fp32 ? (bmax <= 112 ? (const void *)k_solve<float, 0, 7>
+                                      : (const void *)k_solve<float, 0, (kMaxBand32 + 15) / 16>)
+                       : (const void *)k_solve<double, 0, 7>;
   if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kBsThreads, lds) != hipSuccess) return 0;
   return nb;
 }
 
