@@ -15,8 +15,12 @@
 //     transposed above the diagonal: W[i][c] at column i, row k0 + c;
 //   the update matrix (Schur complement) in the trailing r x r block.
 // Levels are processed bottom-up, each as one extend-add per child slot, the
-// factorisation of every node's first block, and one launch per 16-column
-// step over all the level's nodes that still have a block there.
+// factorisation of every node's first block, then panel by panel (kMfPanel
+// blocks of 16 columns): one launch per block over the row tiles below it,
+// which forms W and updates the rest of the panel only, and one rank-64
+// update of the trailing tiles past the panel, with W read back from its
+// transposed store.  The trailing matrix is thus read and written once per
+// 64 columns rather than once per 16.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -216,15 +220,37 @@ __global__ __launch_bounds__(64) void k_mf_first(const MfNode *__restrict__ node
     set_status(st, kStatusSingular, k, 0.0);
 }
 
+// LDL^T of diagonal block t of every node listed (one wave each): the first
+// block of a panel, once the trailing update has reached it.
+__global__ __launch_bounds__(64) void k_mf_diag(const MfNode *__restrict__ nodes, const int2 *__restrict__ blocks,
+                                                int t, double *__restrict__ fronts, double *__restrict__ inv,
+                                                DevStatus *st) {
+  __shared__ double blk[2 * kLB * (kLB + 1)];
+  __shared__ double T[kInvStride];
+  const int k = blocks[blockIdx.x].x;
+  const MfNode nd = nodes[k];
+  const int lane = threadIdx.x, f = nd.f, k0 = kLB * t;
+  double *A = fronts + nd.off;
+  for (int e = lane; e < kLB * kLB; e += 64) {
+    const int r = e / kLB, c = e % kLB;
+    blk[r * (kLB + 1) + c] = (c <= r) ? A[(int64_t)(k0 + c) * f + k0 + r] : 0.0;
+  }
+  __syncthreads();
+  auto store = [&](int tt, int i, double v) { A[(int64_t)(k0 + tt) * f + k0 + i] = v; };
+  if (ldl_diag16(blk, kLB, lane, store, inv + nd.inv_off + (int64_t)t * kInvStride, blk, T) && lane == 0)
+    set_status(st, kStatusSingular, k, 0.0);
+}
+
 // Step t of the partial factorisation, for every node of a level with a
-// block t: the trailing rows and columns r0 = 16 (t + 1) .. f - 1 of each
-// front in lower 64x64 tiles, one workgroup (four waves of 16 rows) per tile,
-// plus a fifth wave that, in the tile holding the node's next diagonal block
-// (when the separator has one), factors that block while the other waves
-// finish the tile.  W = A21 L11^{-T} and C -= W D^{-1} W^T are MFMA products.
-// Diagonal tiles store W^T above the diagonal for their 64 rows; the panel's
-// A21 entries below the diagonal are left as they are, so every tile of this
-// launch reads the same A21 whatever the order in which they run.
+// block t: the rows r0 = 16 (t + 1) .. f - 1 in 64-row tiles, one workgroup
+// (four waves of 16 rows) per tile.  Each tile forms W = A21 L11^{-T} for its
+// rows and stores W^T above the diagonal (column i, rows 16 t .. 16 t + 15),
+// and applies C -= W D^{-1} W^T to the columns r0 .. pe - 1 that remain in
+// the block's panel (pe its end); the columns past the panel receive the
+// panel's blocks together in k_mf_trailing.  A fifth wave, in the first tile
+// of a node whose next block lies in the same panel, factors that block while
+// the other waves finish.  The A21 entries below the diagonal are left as
+// they are, so every tile reads the same A21 whatever the order of the tiles.
 constexpr int kMfStepThreads = 320;
 
 __global__ __launch_bounds__(kMfStepThreads) void k_mf_step(const MfNode *__restrict__ nodes,
@@ -245,12 +271,9 @@ __global__ __launch_bounds__(kMfStepThreads) void k_mf_step(const MfNode *__rest
   const int r0 = k0 + kLB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  int ti = 0, tj = bt.y;
-  while (tj > ti) {
-    tj -= ti + 1;
-    ++ti;
-  }
-  const int i0 = r0 + 64 * ti, j0 = r0 + 64 * tj;
+  const int ti = bt.y, tj = 0;
+  const int pe = kLB * min(t - t % kMfPanel + kMfPanel, nd.sp / kLB);  // end of the panel
+  const int i0 = r0 + 64 * ti, j0 = r0;
   auto a21 = [&](int i, int c) -> double { return i < f ? A[(int64_t)(k0 + c) * f + i] : 0.0; };
   const bool rows = wave < 4;
   double ai[4] = {0.0, 0.0, 0.0, 0.0}, aj[4] = {0.0, 0.0, 0.0, 0.0};
@@ -269,7 +292,7 @@ __global__ __launch_bounds__(kMfStepThreads) void k_mf_step(const MfNode *__rest
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + 16 * wave + M::crow(v, lane), j = j0 + 16 * tc + lr;
-        const bool ok = i < f && j < f && i >= j;
+        const bool ok = i < f && j < pe && i >= j;
         c[tc][v] = ok ? A[(int64_t)j * f + i] : 0.0;
       }
     }
@@ -287,7 +310,7 @@ __global__ __launch_bounds__(kMfStepThreads) void k_mf_step(const MfNode *__rest
       Wj[(16 * wave + M::crow(v, lane)) * (kLB + 1) + lr] = wj[v];
     }
   }
-  const bool has_next = ti == 0 && tj == 0 && r0 < nd.sp;
+  const bool has_next = ti == 0 && r0 < pe;
   double a[4] = {0.0, 0.0, 0.0, 0.0};
   if (rows) {
 #pragma unroll
@@ -321,25 +344,96 @@ __global__ __launch_bounds__(kMfStepThreads) void k_mf_step(const MfNode *__rest
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = i0 + 16 * wave + M::crow(v, lane), j = j0 + 16 * tc + lr;
-          if (i < f && j < f && i >= j) A[(int64_t)j * f + i] = c[tc][v];
+          if (i < f && j < pe && i >= j) A[(int64_t)j * f + i] = c[tc][v];
         }
       }
     };
-    const int ntc = (ti == tj) ? wave + 1 : 4;
-    if (ntc == 4)
-      update_cols(std::integral_constant<int, 4>{});
-    else if (ntc == 3)
+    // column tiles of the panel past r0 (at most three)
+    const int lim = (pe - r0) / 16;
+    const int ntc = ti == 0 ? min(wave + 1, lim) : lim;
+    if (ntc == 3)
       update_cols(std::integral_constant<int, 3>{});
     else if (ntc == 2)
       update_cols(std::integral_constant<int, 2>{});
-    else
+    else if (ntc == 1)
       update_cols(std::integral_constant<int, 1>{});
   }
-  if (ti == tj && rows) {
+  if (rows) {
     for (int e = tid; e < 64 * kLB; e += 256) {
       const int rr = e / kLB, cc = e % kLB;
       const int i = i0 + rr;
       if (i < f) A[(int64_t)i * f + (k0 + cc)] = Wi[rr * (kLB + 1) + cc];
+    }
+  }
+}
+
+// Trailing update past the panel of blocks t0 .. t0 + nb - 1 (nb <= kMfPanel):
+// C -= W D^{-1} W^T on the lower 64x64 tiles of the rows and columns
+// R0 = 16 (t0 + nb) .. f - 1, K = 16 nb.  The tile stays in accumulators
+// while W of its rows i and columns j comes block by block (16 columns of K)
+// from its transposed store (column i, rows 16 t .. 16 t + 15, contiguous)
+// through 17 KB of LDS, so that eight workgroups fit on a CU; 1/D comes from
+// the blocks' inverses.  Each wave computes C^T for 16 columns j by the
+// tile's 64 rows i, so that the lanes of the accumulator layout run along i,
+// contiguous in the column-major front.
+constexpr int kMfTrailThreads = 256;
+constexpr int kMfTrailStride = kLB + 1;
+
+__global__ __launch_bounds__(kMfTrailThreads) void k_mf_trailing(const MfNode *__restrict__ nodes,
+                                                                 const int2 *__restrict__ blocks, int t0,
+                                                                 double *__restrict__ fronts,
+                                                                 const double *__restrict__ inv) {
+  using M = Mma<double>;
+  constexpr int LS = kMfTrailStride;
+  __shared__ double Wi[64 * LS];  // W D^{-1} of rows i0 .. i0 + 63, one block
+  __shared__ double Wj[64 * LS];  // W of rows j0 .. j0 + 63, one block
+  const int2 bt = blocks[blockIdx.x];
+  const MfNode nd = nodes[bt.x];
+  const int f = nd.f;
+  const int nb = min(kMfPanel, nd.sp / kLB - t0);
+  const int R0 = kLB * (t0 + nb);
+  int ti = 0, tj = bt.y;
+  while (tj > ti) {
+    tj -= ti + 1;
+    ++ti;
+  }
+  const int i0 = R0 + 64 * ti, j0 = R0 + 64 * tj;
+  double *A = fronts + nd.off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
+  typename M::v4 c[4];
+#pragma unroll
+  for (int tc = 0; tc < 4; ++tc) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = j0 + 16 * wave + M::crow(v, lane), i = i0 + 16 * tc + lr;
+      c[tc][v] = (i < f && j < f && i >= j) ? A[(int64_t)j * f + i] : 0.0;
+    }
+  }
+  for (int b = 0; b < nb; ++b) {
+    const int kb0 = kLB * (t0 + b);
+    const double *iv = inv + nd.inv_off + (int64_t)(t0 + b) * kInvStride + kLB * kLB;
+    if (b > 0) __syncthreads();  // the previous block's operands are consumed
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + kMfTrailThreads * q, r = e >> 4, cc = e & 15;
+      const int ii = i0 + r, jj = j0 + r;
+      Wi[r * LS + cc] = ii < f ? A[(int64_t)ii * f + kb0 + cc] * iv[cc] : 0.0;
+      Wj[r * LS + cc] = jj < f ? A[(int64_t)jj * f + kb0 + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double a = Wj[(16 * wave + lr) * LS + 4 * s + lk];
+#pragma unroll
+      for (int tc = 0; tc < 4; ++tc) c[tc] = M::mma(-a, Wi[(16 * tc + lr) * LS + 4 * s + lk], c[tc]);
+    }
+  }
+#pragma unroll
+  for (int tc = 0; tc < 4; ++tc) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = j0 + 16 * wave + M::crow(v, lane), i = i0 + 16 * tc + lr;
+      if (i < f && j < f && i >= j) A[(int64_t)j * f + i] = c[tc][v];
     }
   }
 }
@@ -515,8 +609,15 @@ hipError_t launch_mf_factor(const NdPlan &plan, const MfDevPlan &dp, double *fro
     hipLaunchKernelGGL(k_mf_first, dim3(nn), dim3(64), 0, s, dp.nodes, list, fronts, inv, st);
     for (; si < plan.steps.size() && plan.steps[si].level == h; ++si) {
       const MfStepLaunch &L = plan.steps[si];
-      hipLaunchKernelGGL(k_mf_step, dim3(L.n_blocks), dim3(kMfStepThreads), 0, s, dp.nodes,
-                         dp.step_blocks + L.blk_off, L.t, fronts, inv, st);
+      const int2 *bl = dp.step_blocks + L.blk_off;
+      if (L.kind == kMfPanelStep)
+        hipLaunchKernelGGL(k_mf_step, dim3(L.n_blocks), dim3(kMfStepThreads), 0, s, dp.nodes, bl, L.t, fronts, inv,
+                           st);
+      else if (L.kind == kMfTrailing)
+        hipLaunchKernelGGL(k_mf_trailing, dim3(L.n_blocks), dim3(kMfTrailThreads), 0, s, dp.nodes, bl, L.t, fronts,
+                           inv);
+      else
+        hipLaunchKernelGGL(k_mf_diag, dim3(L.n_blocks), dim3(64), 0, s, dp.nodes, bl, L.t, fronts, inv, st);
     }
   }
   return hipGetLastError();

@@ -207,27 +207,40 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
       return "an interface front of " + std::to_string(plan.level_fmax[h]) +
              " unknowns exceeds the sweep kernels' LDS";
 
-  // factorisation launches: per level, per block index t, every node with a
-  // block t; the workgroups are the lower 64x64 tiles of each node's trailing
-  // rows and columns past block t
+  // factorisation launches, per level, per panel of kMfPanel blocks starting
+  // at block t0: the LDL^T of block t0 (t0 > 0; block 0 is factored by the
+  // level's first launch), then per block t of the panel its step over the
+  // row tiles below it, then the trailing update past the panel
   for (int h = 0; h < H; ++h) {
     int tmax = 0;
     for (int k : lv[h]) tmax = std::max(tmax, plan.nodes[k].sp / kNB);
-    for (int t = 0; t < tmax; ++t) {
+    auto push = [&](int kind, int t, auto tiles) {
       MfStepLaunch L;
       L.level = h;
+      L.kind = kind;
       L.t = t;
       L.blk_off = (int64_t)plan.step_blocks.size();
       for (int k : lv[h]) {
-        const MfNode &M = plan.nodes[k];
-        if (M.sp / kNB <= t) continue;
-        const int nr = M.f - kNB * (t + 1);
-        if (nr <= 0) continue;
-        const int tt = (nr + 63) / 64;
-        for (int q = 0; q < tt * (tt + 1) / 2; ++q) plan.step_blocks.push_back(make_int2(k, q));
+        const int n = tiles(plan.nodes[k]);
+        for (int q = 0; q < n; ++q) plan.step_blocks.push_back(make_int2(k, q));
       }
       L.n_blocks = (int)(plan.step_blocks.size() - L.blk_off);
       if (L.n_blocks > 0) plan.steps.push_back(L);
+    };
+    for (int t0 = 0; t0 < tmax; t0 += kMfPanel) {
+      if (t0 > 0) push(kMfDiag, t0, [&](const MfNode &M) { return M.sp / kNB > t0 ? 1 : 0; });
+      for (int t = t0; t < t0 + kMfPanel; ++t)
+        push(kMfPanelStep, t, [&](const MfNode &M) {
+          if (M.sp / kNB <= t) return 0;
+          const int nr = M.f - kNB * (t + 1);
+          return nr > 0 ? (nr + 63) / 64 : 0;
+        });
+      push(kMfTrailing, t0, [&](const MfNode &M) {
+        if (M.sp / kNB <= t0) return 0;
+        const int nr = M.f - kNB * std::min(t0 + kMfPanel, M.sp / kNB);
+        const int tt = nr > 0 ? (nr + 63) / 64 : 0;
+        return tt * (tt + 1) / 2;
+      });
     }
   }
 

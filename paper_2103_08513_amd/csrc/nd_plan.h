@@ -28,10 +28,18 @@ struct MfNode {
   int32_t child0, child1;  // child nodes or -1
 };
 
-// One launch of the factorisation's panel step: the nodes of one level that
-// still have a 16-column block at this step, and their trailing tiles.
+// The factorisation proceeds per level in panels of kMfPanel 16-column
+// blocks.  One launch of it: the nodes of one level that have the block or
+// panel concerned, one workgroup per (node, tile) entry of the table.
+constexpr int kMfPanel = 4;
+enum MfLaunchKind {
+  kMfPanelStep = 0,  // block t: W of every row below it, the update of the panel's later columns
+  kMfTrailing = 1,   // the panel starting at block t: rank-(16 kMfPanel) update of the trailing tiles
+  kMfDiag = 2,       // LDL^T of the diagonal block t (the first block of a panel)
+};
 struct MfStepLaunch {
   int level;
+  int kind;          // MfLaunchKind
   int t;             // block index within each node's separator
   int64_t blk_off;   // offset of this launch's (node, tile) table
   int n_blocks;      // workgroups
