@@ -593,7 +593,7 @@ struct mrcm_interface {
   // multifrontal form (nested dissection of the patch graph), always built
   NdPlan plan;
   MfDevPlan dp;
-  double *fronts = nullptr, *minv = nullptr, *zbuf = nullptr;
+  double *fronts = nullptr, *minv = nullptr, *zbuf = nullptr, *pbuf = nullptr;
   double *xv = nullptr, *rv = nullptr, *bv = nullptr, *dv = nullptr;
   bool fronts_fresh = false;  // fronts hold the assembled entries (not yet factored)
   // band form, built on its first use
@@ -631,8 +631,9 @@ void free_mbfs(mrcm_mbfs *h) {
 void free_iface(mrcm_interface *h) {
   if (!h) return;
   void *ptrs[] = {h->d_pos, h->AB, h->AB0, h->b, h->b0, h->inv, h->r, h->y, h->scalar, h->st,
-                  h->fronts, h->minv, h->zbuf, h->xv, h->rv, h->bv, h->dv,
-                  h->dp.nodes, h->dp.idx, h->dp.map, h->dp.level_nodes, h->dp.step_blocks, h->dp.pair_off,
+                  h->fronts, h->minv, h->zbuf, h->pbuf, h->xv, h->rv, h->bv, h->dv,
+                  h->dp.nodes, h->dp.idx, h->dp.map, h->dp.level_nodes, h->dp.step_blocks, h->dp.fwd_bnd,
+                  h->dp.bwd_bnd, h->dp.pair_off,
                   h->dp.sub_pair_off, h->dp.pair_ld, h->dp.pinfo};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -662,19 +663,23 @@ mrcm_status init_mf(mrcm_interface *h) {
   HIP_TRY(upload(&dp.map, P.map));
   HIP_TRY(upload(&dp.level_nodes, P.level_nodes));
   HIP_TRY(upload(&dp.step_blocks, P.step_blocks));
+  HIP_TRY(upload(&dp.fwd_bnd, P.fwd_bnd));
+  HIP_TRY(upload(&dp.bwd_bnd, P.bwd_bnd));
   HIP_TRY(upload(&dp.pair_off, P.pair_off));
   HIP_TRY(upload(&dp.sub_pair_off, P.sub_pair_off));
   HIP_TRY(upload(&dp.pair_ld, P.pair_ld));
   HIP_TRY(upload(&dp.pinfo, pinfo));
   const bool ok = dev_alloc(&h->fronts, (size_t)P.front_doubles) == hipSuccess &&
                   dev_alloc(&h->minv, (size_t)P.inv_doubles) == hipSuccess &&
-                  dev_alloc(&h->zbuf, (size_t)P.z_doubles) == hipSuccess && dev_alloc(&h->xv, h->n) == hipSuccess &&
+                  dev_alloc(&h->zbuf, (size_t)P.z_doubles) == hipSuccess &&
+                  dev_alloc(&h->pbuf, (size_t)P.part_doubles) == hipSuccess && dev_alloc(&h->xv, h->n) == hipSuccess &&
                   dev_alloc(&h->rv, h->n) == hipSuccess && dev_alloc(&h->bv, h->n) == hipSuccess &&
                   dev_alloc(&h->dv, h->n) == hipSuccess;
   if (!ok) return fail(MRCM_ENOMEM, "device allocation of the interface fronts failed");
-  h->bytes += 8 * (P.front_doubles + P.inv_doubles + P.z_doubles + 4LL * h->n) +
+  h->bytes += 8 * (P.front_doubles + P.inv_doubles + P.z_doubles + P.part_doubles + 4LL * h->n) +
               (int64_t)sizeof(MfNode) * P.nodes.size() + 4LL * (P.idx.size() + P.map.size()) +
-              12LL * (int64_t)P.pair_off.size() + 8LL * (int64_t)P.step_blocks.size();
+              12LL * (int64_t)P.pair_off.size() +
+              8LL * (int64_t)(P.step_blocks.size() + P.fwd_bnd.size() + P.bwd_bnd.size());
   return MRCM_OK;
 }
 
@@ -1212,7 +1217,7 @@ mrcm_status solve_mf(mrcm_interface *h, double rtol, int max_refine, hipStream_t
   iters = 0;
   {
     Stage t(MRCM_STAGE_SWEEP, s);
-    HIP_TRY(launch_mf_solve(h->plan, h->dp, h->fronts, h->minv, h->zbuf, h->bv, h->xv, s));
+    HIP_TRY(launch_mf_solve(h->plan, h->dp, h->fronts, h->minv, h->zbuf, h->pbuf, h->bv, h->xv, s));
     for (; iters < max_refine; ++iters) {
       HIP_TRY(launch_mf_residual(mb->g, mb->d_patches, mb->F, mb->Fb, mb->SAb, h->dp.pinfo, h->nv, h->xv, h->rv,
                                  nullptr, s));
@@ -1222,7 +1227,7 @@ mrcm_status solve_mf(mrcm_interface *h, double rtol, int max_refine, hipStream_t
         if (st != MRCM_OK) return st;
         if (rel <= rtol) break;
       }
-      HIP_TRY(launch_mf_solve(h->plan, h->dp, h->fronts, h->minv, h->zbuf, h->rv, h->dv, s));
+      HIP_TRY(launch_mf_solve(h->plan, h->dp, h->fronts, h->minv, h->zbuf, h->pbuf, h->rv, h->dv, s));
       HIP_TRY(launch_axpy(h->xv, h->dv, h->n, s));
     }
     HIP_TRY(launch_mf_deinterleave(h->xv, h->nv, X, s));

@@ -453,8 +453,8 @@ static_assert(kMfSweepThreads / 64 == kLB, "one wave per block row");
 // the node's right-hand side (its separator's entries of rhs, sign-flipped on
 // the pressure rows) plus its children's boundary parts; then block by block
 // y_k = L11^{-1} (z_k - sum_{j<k} W_kj D_j^{-1} y_j) with one wave per row of
-// the block, and the boundary rows z_b -= W_b D^{-1} y.  The node's vector
-// (y on the separator, z_b on the boundary) goes to zbuf.
+// the block.  The node's vector (y on the separator, the boundary part before
+// z_b -= W_b D^{-1} y, which k_mf_fwd_bnd applies) goes to zbuf.
 __global__ __launch_bounds__(kMfSweepThreads) void k_mf_fwd(const MfNode *__restrict__ nodes,
                                                             const int *__restrict__ list, const int *__restrict__ idx,
                                                             const int *__restrict__ map,
@@ -508,27 +508,103 @@ __global__ __launch_bounds__(kMfSweepThreads) void k_mf_fwd(const MfNode *__rest
     }
     __syncthreads();
   }
-  for (int i = sp + wave; i < f; i += kMfSweepThreads / 64) {
-    const double *row = A + (int64_t)i * f;
-    double acc = 0.0;
-    for (int cidx = lane; cidx < sp; cidx += 64) acc = fma(row[cidx], u[cidx], acc);
-    acc = wave_sum(acc);
-    if (lane == 0) z[i] -= acc;
-  }
-  __syncthreads();
   double *zo = zbuf + nd.z_off;
   for (int p = tid; p < f; p += kMfSweepThreads) zo[p] = z[p];
 }
 
+// The forward sweep's boundary rows, kMfFwdRows of one node per workgroup:
+// z_b -= W_b D^{-1} y, with y from zbuf and W_b^T read from the upper part of
+// the front (column i, rows 0 .. sp - 1, contiguous).  Each wave takes 16
+// rows, four at a time.
+constexpr int kMfBndThreads = 256;
+
+__global__ __launch_bounds__(kMfBndThreads) void k_mf_fwd_bnd(const MfNode *__restrict__ nodes,
+                                                              const int2 *__restrict__ list,
+                                                              const double *__restrict__ fronts,
+                                                              const double *__restrict__ inv,
+                                                              double *__restrict__ zbuf) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *u = reinterpret_cast<double *>(smem_raw);  // sp entries: D^{-1} y
+  const int2 e = list[blockIdx.x];
+  const MfNode nd = nodes[e.x];
+  const int f = nd.f, sp = nd.sp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double *zo = zbuf + nd.z_off;
+  const double *iv = inv + nd.inv_off;
+  for (int c = tid; c < sp; c += kMfBndThreads) u[c] = zo[c] * iv[(int64_t)(c >> 4) * kInvStride + kLB * kLB + (c & 15)];
+  __syncthreads();
+  const double *A = fronts + nd.off;
+  const int ib = sp + kMfFwdRows * e.y + 16 * wave;
+  for (int q = 0; q < 16; q += 4) {
+    const int i0 = ib + q;
+    const double *r0 = A + (int64_t)min(i0, f - 1) * f;
+    const double *r1 = A + (int64_t)min(i0 + 1, f - 1) * f;
+    const double *r2 = A + (int64_t)min(i0 + 2, f - 1) * f;
+    const double *r3 = A + (int64_t)min(i0 + 3, f - 1) * f;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int c = lane; c < sp; c += 64) {
+      const double uc = u[c];
+      a0 = fma(r0[c], uc, a0);
+      a1 = fma(r1[c], uc, a1);
+      a2 = fma(r2[c], uc, a2);
+      a3 = fma(r3[c], uc, a3);
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    a3 = wave_sum(a3);
+    if (lane == 0) {
+      if (i0 < f) zo[i0] -= a0;
+      if (i0 + 1 < f) zo[i0 + 1] -= a1;
+      if (i0 + 2 < f) zo[i0 + 2] -= a2;
+      if (i0 + 3 < f) zo[i0 + 3] -= a3;
+    }
+  }
+}
+
+// The backward sweep's boundary product in pieces of kMfBwdCols separator
+// columns by kMfBwdRows boundary rows, one piece per workgroup: the partial
+// sums of W_b^T x_b over the piece's rows, for k_mf_bwd to subtract.
+__global__ __launch_bounds__(kMfBwdCols) void k_mf_bwd_part(const MfNode *__restrict__ nodes,
+                                                            const int2 *__restrict__ list,
+                                                            const int *__restrict__ idx,
+                                                            const double *__restrict__ fronts,
+                                                            const double *__restrict__ x,
+                                                            double *__restrict__ pbuf) {
+  __shared__ double xs[kMfBwdRows];
+  const int2 e = list[blockIdx.x];
+  const MfNode nd = nodes[e.x];
+  const int f = nd.f, sp = nd.sp;
+  const int ncc = (sp + kMfBwdCols - 1) / kMfBwdCols;
+  const int cc = e.y % ncc, rc = e.y / ncc;
+  const int i0 = sp + kMfBwdRows * rc, i1 = min(f, i0 + kMfBwdRows);
+  const int *id = idx + nd.idx_off;
+  for (int q = threadIdx.x; q < i1 - i0; q += kMfBwdCols) xs[q] = x[id[i0 + q]];
+  __syncthreads();
+  const int cidx = kMfBwdCols * cc + threadIdx.x;
+  if (cidx >= sp) return;
+  const double *A = fronts + nd.off + cidx;
+  double a0 = 0.0, a1 = 0.0;
+  int i = i0;
+  for (; i + 1 < i1; i += 2) {
+    a0 = fma(A[(int64_t)i * f], xs[i - i0], a0);
+    a1 = fma(A[(int64_t)(i + 1) * f], xs[i + 1 - i0], a1);
+  }
+  if (i < i1) a0 = fma(A[(int64_t)i * f], xs[i - i0], a0);
+  pbuf[nd.part_off + (int64_t)rc * sp + cidx] = a0 + a1;
+}
+
 // Backward sweep of one level (top-down), one workgroup per node: with the
-// boundary unknowns x_b solved by the ancestors, t = y - W_b^T x_b; then from
+// boundary unknowns x_b solved by the ancestors, t = y - W_b^T x_b (the
+// product summed from k_mf_bwd_part's pieces in order); then from
 // the last block down, x_k = L11^{-T} D_k^{-1} t_k and t_j -= W_kj^T x_k for
 // the earlier blocks.  The separator's unknowns go to x.
 __global__ __launch_bounds__(kMfSweepThreads) void k_mf_bwd(const MfNode *__restrict__ nodes,
                                                             const int *__restrict__ list, const int *__restrict__ idx,
                                                             const double *__restrict__ fronts,
                                                             const double *__restrict__ inv,
-                                                            const double *__restrict__ zbuf, double *__restrict__ x) {
+                                                            const double *__restrict__ zbuf,
+                                                            const double *__restrict__ pbuf, double *__restrict__ x) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int k = list[blockIdx.x];
   const MfNode nd = nodes[k];
@@ -539,11 +615,11 @@ __global__ __launch_bounds__(kMfSweepThreads) void k_mf_bwd(const MfNode *__rest
   const int *id = idx + nd.idx_off;
   const double *A = fronts + nd.off;
   const double *zo = zbuf + nd.z_off;
-  for (int p = sp + tid; p < f; p += kMfSweepThreads) xs[p] = x[id[p]];
-  __syncthreads();
+  const int nrc = (nd.r + kMfBwdRows - 1) / kMfBwdRows;
+  const double *pp = pbuf + nd.part_off;
   for (int cidx = tid; cidx < sp; cidx += kMfSweepThreads) {
     double acc = zo[cidx];
-    for (int i = sp; i < f; ++i) acc = fma(-A[(int64_t)i * f + cidx], xs[i], acc);
+    for (int rc = 0; rc < nrc; ++rc) acc -= pp[(int64_t)rc * sp + cidx];
     tv[cidx] = acc;
   }
   __syncthreads();
@@ -624,7 +700,7 @@ hipError_t launch_mf_factor(const NdPlan &plan, const MfDevPlan &dp, double *fro
 }
 
 hipError_t launch_mf_solve(const NdPlan &plan, const MfDevPlan &dp, const double *fronts, const double *inv,
-                           double *zbuf, const double *rhs, double *x, hipStream_t s) {
+                           double *zbuf, double *pbuf, const double *rhs, double *x, hipStream_t s) {
   const int H = (int)plan.level_off.size() - 1;
   // the plan keeps every level's (f + sp) within kMfSweepLdsMax, which
   // mf_init_kernels has allowed
@@ -633,12 +709,20 @@ hipError_t launch_mf_solve(const NdPlan &plan, const MfDevPlan &dp, const double
     const size_t lds = (size_t)plan.level_lds[h] * sizeof(double);
     hipLaunchKernelGGL(k_mf_fwd, dim3(nn), dim3(kMfSweepThreads), lds, s, dp.nodes, dp.level_nodes + n0, dp.idx,
                        dp.map, fronts, inv, rhs, zbuf);
+    const int nfb = plan.level_fb_off[h + 1] - plan.level_fb_off[h];
+    if (nfb > 0)
+      hipLaunchKernelGGL(k_mf_fwd_bnd, dim3(nfb), dim3(kMfBndThreads), (size_t)plan.level_spmax[h] * sizeof(double),
+                         s, dp.nodes, dp.fwd_bnd + plan.level_fb_off[h], fronts, inv, zbuf);
   }
   for (int h = H - 1; h >= 0; --h) {
     const int n0 = plan.level_off[h], nn = plan.level_off[h + 1] - n0;
     const size_t lds = (size_t)plan.level_lds[h] * sizeof(double);
+    const int nbb = plan.level_bb_off[h + 1] - plan.level_bb_off[h];
+    if (nbb > 0)
+      hipLaunchKernelGGL(k_mf_bwd_part, dim3(nbb), dim3(kMfBwdCols), 0, s, dp.nodes, dp.bwd_bnd + plan.level_bb_off[h],
+                         dp.idx, fronts, x, pbuf);
     hipLaunchKernelGGL(k_mf_bwd, dim3(nn), dim3(kMfSweepThreads), lds, s, dp.nodes, dp.level_nodes + n0, dp.idx,
-                       fronts, inv, zbuf, x);
+                       fronts, inv, zbuf, pbuf, x);
   }
   return hipGetLastError();
 }
@@ -648,6 +732,9 @@ hipError_t mf_init_kernels() {
                                      (int)kMfSweepLdsMax);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_mf_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMfSweepLdsMax);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_mf_fwd_bnd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kMfSweepLdsMax);
   return e;
 }
 

@@ -147,7 +147,7 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
   };
   visit(0);
   plan.nodes.resize(nn);
-  int64_t off = 0, ioff = 0, zoff = 0;
+  int64_t off = 0, ioff = 0, zoff = 0, poff = 0;
   for (int k = 0; k < nn; ++k) {
     const TmpNode &T = tn[order[k]];
     MfNode &M = plan.nodes[k];
@@ -158,6 +158,7 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
     M.off = off;
     M.inv_off = ioff;
     M.z_off = zoff;
+    M.part_off = poff;
     M.idx_off = (int)plan.idx.size();
     M.map_off = (int)plan.map.size();
     M.child0 = T.child[0] >= 0 ? post[T.child[0]] : -1;
@@ -167,6 +168,7 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
     off += (int64_t)M.f * M.f;
     ioff += (int64_t)(M.sp / kNB) * (kNB * kNB + kNB);
     zoff += M.f;
+    poff += (int64_t)((M.r + kMfBwdRows - 1) / kMfBwdRows) * M.sp;
     plan.max_f = std::max(plan.max_f, M.f);
     for (int k2 = 0; k2 < M.s; ++k2) {
       const double t = M.f - 1 - k2;
@@ -176,6 +178,7 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
   plan.front_doubles = off;
   plan.inv_doubles = ioff;
   plan.z_doubles = zoff;
+  plan.part_doubles = poff;
   if (plan.idx.size() > (size_t)INT32_MAX || plan.map.size() > (size_t)INT32_MAX)
     return "nested-dissection index lists exceed 2^31 entries";
 
@@ -189,6 +192,7 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
   plan.level_rmax.assign(H, 0);
   plan.level_child_rmax.assign(H, 0);
   plan.level_lds.assign(H, 0);
+  plan.level_spmax.assign(H, 0);
   for (int h = 0; h < H; ++h) {
     plan.level_off[h] = (int)plan.level_nodes.size();
     for (int k : lv[h]) {
@@ -197,6 +201,7 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
       plan.level_fmax[h] = std::max(plan.level_fmax[h], M.f);
       plan.level_rmax[h] = std::max(plan.level_rmax[h], M.r);
       plan.level_lds[h] = std::max(plan.level_lds[h], M.f + M.sp);
+      plan.level_spmax[h] = std::max(plan.level_spmax[h], M.sp);
       for (int c : {M.child0, M.child1})
         if (c >= 0) plan.level_child_rmax[h] = std::max(plan.level_child_rmax[h], plan.nodes[c].r);
     }
@@ -206,6 +211,23 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
     if ((size_t)plan.level_lds[h] * sizeof(double) > kMfSweepLdsMax)
       return "an interface front of " + std::to_string(plan.level_fmax[h]) +
              " unknowns exceeds the sweep kernels' LDS";
+
+  // pieces of the sweeps' boundary products, level by level
+  plan.level_fb_off.assign(H + 1, 0);
+  plan.level_bb_off.assign(H + 1, 0);
+  for (int h = 0; h < H; ++h) {
+    plan.level_fb_off[h] = (int)plan.fwd_bnd.size();
+    plan.level_bb_off[h] = (int)plan.bwd_bnd.size();
+    for (int k : lv[h]) {
+      const MfNode &M = plan.nodes[k];
+      if (M.r <= 0 || M.sp <= 0) continue;
+      for (int c = 0; c < (M.r + kMfFwdRows - 1) / kMfFwdRows; ++c) plan.fwd_bnd.push_back(make_int2(k, c));
+      const int nq = ((M.r + kMfBwdRows - 1) / kMfBwdRows) * ((M.sp + kMfBwdCols - 1) / kMfBwdCols);
+      for (int q = 0; q < nq; ++q) plan.bwd_bnd.push_back(make_int2(k, q));
+    }
+  }
+  plan.level_fb_off[H] = (int)plan.fwd_bnd.size();
+  plan.level_bb_off[H] = (int)plan.bwd_bnd.size();
 
   // factorisation launches, per level, per panel of kMfPanel blocks starting
   // at block t0: the LDL^T of block t0 (t0 > 0; block 0 is factored by the

@@ -19,6 +19,8 @@ struct MfNode {
   int64_t off;      // offset (doubles) of the f x f column-major front
   int64_t inv_off;  // offset (doubles) of the per-16-block L11^{-1}, 1/D (272 each)
   int64_t z_off;    // offset (doubles) of the node's f-entry vector of the sweeps
+  int64_t part_off; // offset (doubles) of the backward sweep's partial boundary sums
+                    // [ceil(r / kMfBwdRows)][sp]
   int32_t f;        // front size: sp + r
   int32_t sp;       // separator unknowns rounded up to 16 (pad rows are identity)
   int32_t s;        // separator unknowns (two per patch: pi^p, pi^u)
@@ -45,6 +47,15 @@ struct MfStepLaunch {
   int n_blocks;      // workgroups
 };
 
+// The sweeps' boundary products W_b^T and W_b, (f - sp) x sp per node, run
+// beside the sequential triangular part over many workgroups: forward in
+// chunks of kMfFwdRows boundary rows, backward in pieces of kMfBwdCols
+// separator columns by kMfBwdRows boundary rows whose partial sums the
+// triangular part adds in a fixed order.
+constexpr int kMfFwdRows = 64;
+constexpr int kMfBwdRows = 512;
+constexpr int kMfBwdCols = 256;
+
 struct NdPlan {
   int n_unknowns = 0;                 // 2 * patches
   std::vector<MfNode> nodes;          // in elimination order (children first)
@@ -64,6 +75,10 @@ struct NdPlan {
   std::vector<int> pair_ld;
   std::vector<int64_t> sub_pair_off;  // per subdomain: offset of its pairs
   std::vector<int> level_lds;         // largest (f + sp) per level: the sweeps' LDS doubles
+  std::vector<int> level_spmax;       // largest sp per level
+  std::vector<int2> fwd_bnd, bwd_bnd; // (node, piece) of the sweeps' boundary launches, level by level
+  std::vector<int> level_fb_off, level_bb_off;  // [H + 1] offsets into fwd_bnd, bwd_bnd
+  int64_t part_doubles = 0;
   int64_t front_doubles = 0, inv_doubles = 0, z_doubles = 0;
   double flops = 0.0;                 // sum over nodes of the partial LDL^T flops
   int max_f = 0;
@@ -75,6 +90,7 @@ struct MfDevPlan {
   int n_nodes = 0;
   int *idx = nullptr, *map = nullptr, *level_nodes = nullptr;
   int2 *step_blocks = nullptr;
+  int2 *fwd_bnd = nullptr, *bwd_bnd = nullptr;
   int64_t *pair_off = nullptr, *sub_pair_off = nullptr;
   int *pair_ld = nullptr;
   int4 *pinfo = nullptr;  // per patch: interface, local index on its lower and upper side
@@ -103,7 +119,7 @@ hipError_t launch_mf_assemble(const Geom &g, int n_sub, const int *patches, cons
 hipError_t launch_mf_factor(const NdPlan &plan, const MfDevPlan &dp, double *fronts, double *inv, DevStatus *st,
                             hipStream_t s);
 hipError_t launch_mf_solve(const NdPlan &plan, const MfDevPlan &dp, const double *fronts, const double *inv,
-                           double *zbuf, const double *rhs, double *x, hipStream_t s);
+                           double *zbuf, double *pbuf, const double *rhs, double *x, hipStream_t s);
 hipError_t launch_mf_residual(const Geom &g, const int *patches, const double *F, const double *Fb,
                               const double *SAb, const int4 *pinfo, int nv, const double *x, double *r, double *b,
                               hipStream_t s);
