@@ -185,6 +185,10 @@ typedef struct {
  *              build forms every MBF either way (the flux blocks reduce them),
  *              so the handle's memory does not change.  The conjugate-gradient
  *              form keeps no factors and needs MRCM_KEEP_MBFS.
+ * iface_panel  16-column blocks per panel of the multifrontal interface
+ *              factorisation, 1 to 4 (0: 4): each panel's trailing update is
+ *              one rank-(16 iface_panel) product.  Set by mrcm_autotune; an
+ *              interface handle takes the value of its MBF handle.
  */
 typedef struct {
   double alpha;
@@ -199,6 +203,7 @@ typedef struct {
   int32_t solve_group;
   int32_t beta_mode;
   uint32_t keep;
+  int32_t iface_panel;
 } mrcm_options;
 
 typedef struct mrcm_mbfs mrcm_mbfs;           /* local factors, MBFs, Gamma-flux blocks */
@@ -427,18 +432,38 @@ mrcm_status mrcm_profile_get(mrcm_profile *out /* [host] */);
  *  same handles race.
  */
 /*
- * Autotuner: times mrcm_build_mbfs on the given problem for candidate values
- * of solve_tiles and solve_group (each candidate on a handle of its own:
- * one untimed and three timed builds, synchronised, the fastest counted) and
- * writes into *best a copy of *base with the fastest pair; a candidate
- * replaces the current choice only when it is at least 2% faster, so that
- * near-ties keep base's pair.  *best_ms and
- * *rule_ms (either may be NULL): the fastest build and that of base's own
- * pair.  Allocates and frees one handle per candidate.
+ * Autotuner (orchestration, Algorithm 2 as a whole): times mrcm_build_mbfs on
+ * the given problem for candidate values of solve_tiles and solve_group (each
+ * candidate on a handle of its own: one untimed and three timed builds,
+ * synchronised, the fastest counted), then, with the winning pair and when
+ * the problem has interface unknowns, the interface assembly and solve
+ * (mrcm_assemble_interface + mrcm_solve_interface, no refinement) for
+ * iface_panel 1, 2 and 4.  Writes into *best a copy of *base with the fastest
+ * values; a candidate replaces the current choice only when it is at least
+ * 2% faster, so that near-ties keep base's values.  *best_ms and *rule_ms
+ * (either may be NULL): the fastest build and that of base's own pair.
+ * Allocates and frees one handle per candidate.
  */
 mrcm_status mrcm_autotune(const mrcm_problem *problem, const mrcm_partition *partition,
                           const mrcm_iface_space *iface_space, const mrcm_options *base, void *stream,
                           mrcm_options *best, double *best_ms, double *rule_ms);
+
+/*
+ * mrcm_autotune with a per-shape cache in the text file cache_path [host]
+ * (created when missing; one line per entry: "mrcm-tune-1", the key, then
+ * solve_tiles, solve_group, iface_panel, best_ms, rule_ms).  The key is a
+ * 64-bit FNV-1a hash of what the tuned values depend on: grid and cell
+ * sizes, partition cuts, interface splits, wall types, precision, beta_mode,
+ * keep and the device's architecture name and compute-unit count -- not the
+ * coefficient values.  On a hit *best is *base with the cached values and no
+ * kernel runs; on a miss mrcm_autotune runs and its result is appended.
+ * *from_cache [host] (may be NULL): 1 on a hit, else 0.  An unreadable or
+ * unwritable file is an error (MRCM_EINVAL); malformed lines are skipped.
+ */
+mrcm_status mrcm_autotune_cached(const mrcm_problem *problem, const mrcm_partition *partition,
+                                 const mrcm_iface_space *iface_space, const mrcm_options *base, void *stream,
+                                 const char *cache_path, mrcm_options *best, double *best_ms, double *rule_ms,
+                                 int32_t *from_cache);
 
 typedef struct mrcm_graph mrcm_graph;
 mrcm_status mrcm_graph_capture(const mrcm_problem *problem, const mrcm_partition *partition,

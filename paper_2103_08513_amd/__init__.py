@@ -9,6 +9,7 @@ kernels; importing this package does not need a GPU, but every call does.
 from __future__ import annotations
 
 import ctypes
+import os
 from ctypes import byref, c_double, c_int32, c_void_p
 
 import numpy as np
@@ -101,7 +102,7 @@ class MRCM:
 
     def __init__(self, problem, partition, iface, alpha=1.0, precision=FP64, ir_tol=1e-13,
                  ir_max_iter=30, fp64_refine=1, pcg_max_iter=50, solve_tiles=0, solve_group=0, device="cuda",
-                 beta_mode=BETA_PER_SIDE, keep=KEEP_FACTORS | KEEP_MBFS):
+                 beta_mode=BETA_PER_SIDE, keep=KEEP_FACTORS | KEEP_MBFS, iface_panel=0):
         import torch
         self.lib = library()
         self.device = torch.device(device)
@@ -160,6 +161,7 @@ class MRCM:
         opt.solve_group = int(solve_group)
         opt.beta_mode = int(beta_mode)
         opt.keep = int(keep)
+        opt.iface_panel = int(iface_panel)
         opt.pcg_x0 = None
         self._opt = opt
 
@@ -260,24 +262,34 @@ class MRCM:
         X = self.solve_interface(refine=refine, stream=stream, method=method)
         return self.reconstruct(X, stream=stream) + (X,)
 
-    def autotune(self, kx, ky, kz, q, stream=None):
-        """Time the build for candidate solve_tiles / solve_group values on
-        these inputs (mrcm_autotune) and keep the fastest for the following
-        builds.  Existing handles are released (their geometry includes the
-        tunables).  Returns the chosen values and the build times."""
+    def autotune(self, kx, ky, kz, q, stream=None, cache=None):
+        """Time the build for candidate solve_tiles / solve_group values and
+        the interface solve for candidate iface_panel values on these inputs
+        (mrcm_autotune) and keep the fastest for the following builds; with
+        ``cache`` (a file path) the per-shape cache of mrcm_autotune_cached is
+        consulted first and the result recorded.  Existing handles are
+        released (their geometry includes the tunables).  Returns the chosen
+        values, the build times and whether they came from the cache."""
         cp = self._cp
         self._set_fields(kx, ky, kz, q)
         self._opt.pcg_x0 = None
         best = COptions()
         t_best, t_rule = c_double(0.0), c_double(0.0)
-        code = self.lib.mrcm_autotune(byref(cp), byref(self._part), byref(self._ifs), byref(self._opt),
-                                      _stream_ptr(stream), byref(best), byref(t_best), byref(t_rule))
+        hit = c_int32(0)
+        if cache is None:
+            code = self.lib.mrcm_autotune(byref(cp), byref(self._part), byref(self._ifs), byref(self._opt),
+                                          _stream_ptr(stream), byref(best), byref(t_best), byref(t_rule))
+        else:
+            code = self.lib.mrcm_autotune_cached(byref(cp), byref(self._part), byref(self._ifs), byref(self._opt),
+                                                 _stream_ptr(stream), os.fsencode(cache), byref(best), byref(t_best),
+                                                 byref(t_rule), byref(hit))
         _lib.check(code, "mrcm_autotune")
         self.close()
         self._opt.solve_tiles = best.solve_tiles
         self._opt.solve_group = best.solve_group
-        return {"solve_tiles": best.solve_tiles, "solve_group": best.solve_group,
-                "build_ms": t_best.value, "build_ms_default": t_rule.value}
+        self._opt.iface_panel = best.iface_panel
+        return {"solve_tiles": best.solve_tiles, "solve_group": best.solve_group, "iface_panel": best.iface_panel,
+                "build_ms": t_best.value, "build_ms_default": t_rule.value, "from_cache": bool(hit.value)}
 
     def capture(self, kx, ky, kz, q, X, p, U, refine=0, stream=None):
         """Record one whole MRCM step (build, assembly, interface solve,

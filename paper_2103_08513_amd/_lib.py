@@ -17,7 +17,7 @@ EXPORTS = [
     "mrcm_query", "mrcm_get_subdomain", "mrcm_copy_mbfs", "mrcm_copy_flux", "mrcm_copy_factor",
     "mrcm_interface_dims", "mrcm_copy_interface", "mrcm_interface_query", "mrcm_mbfs_destroy", "mrcm_interface_destroy",
     "mrcm_status_string", "mrcm_last_error", "mrcm_profile_enable", "mrcm_profile_reset",
-    "mrcm_profile_get", "mrcm_autotune", "mrcm_graph_capture", "mrcm_graph_launch", "mrcm_graph_check", "mrcm_graph_destroy",
+    "mrcm_profile_get", "mrcm_autotune", "mrcm_autotune_cached", "mrcm_graph_capture", "mrcm_graph_launch", "mrcm_graph_check", "mrcm_graph_destroy",
     # mrcm_nn.h
     "mrcm_conv3d_max_channels", "mrcm_conv3d_forward", "mrcm_conv3d_backward", "mrcm_mse", "mrcm_mse_noalloc",
     "mrcm_adam_step",
@@ -51,7 +51,7 @@ class COptions(ctypes.Structure):
     _fields_ = [("alpha", c_double), ("precision", c_int32), ("ir_tol", c_double),
                 ("ir_max_iter", c_int32), ("fp64_refine", c_int32), ("pcg_max_iter", c_int32),
                 ("pcg_x0", ctypes.c_void_p), ("pcg_x0_scale", c_int32), ("solve_tiles", c_int32),
-                ("solve_group", c_int32), ("beta_mode", c_int32), ("keep", c_uint32)]
+                ("solve_group", c_int32), ("beta_mode", c_int32), ("keep", c_uint32), ("iface_panel", c_int32)]
 
 
 class CIfaceInfo(ctypes.Structure):
@@ -116,6 +116,8 @@ def load(path: str = LIB_PATH):
         "mrcm_profile_get": ([P(CProfile)], c_int32),
         "mrcm_autotune": ([P(CProblem), P(CPartition), P(CIfaceSpace), P(COptions), c_void_p, P(COptions),
                            P(c_double), P(c_double)], c_int32),
+        "mrcm_autotune_cached": ([P(CProblem), P(CPartition), P(CIfaceSpace), P(COptions), c_void_p, ctypes.c_char_p,
+                                  P(COptions), P(c_double), P(c_double), P(c_int32)], c_int32),
         "mrcm_graph_capture": ([P(CProblem), P(CPartition), P(CIfaceSpace), P(COptions), c_void_p, c_void_p,
                                 c_int32, c_void_p, c_void_p, c_void_p, c_void_p, P(c_void_p)], c_int32),
         "mrcm_graph_launch": ([c_void_p, c_void_p], c_int32),

@@ -74,6 +74,7 @@ struct HostGeom {
   int n_patch = 0;
   int solve_tiles = 0;   // 16-column tiles per solve work item (0: the largest chunk)
   int solve_group = 0;   // FP64 pipeline: solve group 0's size (0: occupancy rule, -1: none)
+  int iface_panel = kMfPanelMax;  // blocks per panel of the multifrontal interface factorisation
   int bmax = 0, mmax = 0, max_cells = 0;
   long long max_nm = 0;
   int64_t totL = 0, totD = 0, totX = 0, totF = 0, totCells = 0;
@@ -93,7 +94,7 @@ struct ConfigKey {
   int32_t beta_mode = 0;
   uint32_t keep = 0;
   int32_t precision = 0;
-  int32_t solve_tiles = 0, solve_group = 0;
+  int32_t solve_tiles = 0, solve_group = 0, iface_panel = 0;
   std::vector<int32_t> cuts[3];
   int32_t us[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   std::vector<int32_t> split;
@@ -105,7 +106,8 @@ struct ConfigKey {
     for (int f = 0; f < 6; ++f)
       if (wall_type[f] != o.wall_type[f]) return false;
     return pin == o.pin && alpha == o.alpha && beta_mode == o.beta_mode && keep == o.keep && precision == o.precision &&
-           split == o.split && solve_tiles == o.solve_tiles && solve_group == o.solve_group;
+           split == o.split && solve_tiles == o.solve_tiles && solve_group == o.solve_group &&
+           iface_panel == o.iface_panel;
   }
 };
 
@@ -127,6 +129,7 @@ bool make_key(const mrcm_problem *pb, const mrcm_partition *part, const mrcm_ifa
   k.precision = opt->precision;
   k.solve_tiles = opt->solve_tiles;
   k.solve_group = opt->solve_group;
+  k.iface_panel = opt->iface_panel;
   const int nd[3] = {part->ndx, part->ndy, part->ndz};
   const int32_t *cut_in[3] = {part->cut_x, part->cut_y, part->cut_z};
   for (int d = 0; d < 3; ++d) {
@@ -190,6 +193,9 @@ mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
   if (opt->solve_group < -1) return fail(MRCM_EINVAL, "solve_group must be -1, 0 or a positive count");
   G.solve_tiles = opt->solve_tiles;
   G.solve_group = opt->solve_group;
+  if (opt->iface_panel < 0 || opt->iface_panel > kMfPanelMax)
+    return fail(MRCM_EINVAL, "iface_panel must be in [0, " + std::to_string(kMfPanelMax) + "]");
+  G.iface_panel = opt->iface_panel > 0 ? opt->iface_panel : kMfPanelMax;
   if (G.precision != MRCM_FP64 && G.precision != MRCM_FP32_IR && G.precision != MRCM_PCG)
     return fail(MRCM_EINVAL, "precision must be MRCM_FP64, MRCM_FP32_IR or MRCM_PCG");
   G.keep = opt->keep ? opt->keep : (MRCM_KEEP_FACTORS | MRCM_KEEP_MBFS);
@@ -646,7 +652,7 @@ mrcm_status init_mf(mrcm_interface *h) {
   const mrcm_mbfs *mb = h->mb;
   const HostGeom &G = mb->G;
   const int nd[3] = {(int)G.cuts[0].size() - 1, (int)G.cuts[1].size() - 1, (int)G.cuts[2].size() - 1};
-  const std::string err = build_nd_plan(nd, G.subs, G.ifcs, G.patches, G.n_patch, h->plan);
+  const std::string err = build_nd_plan(nd, G.subs, G.ifcs, G.patches, G.n_patch, G.iface_panel, h->plan);
   if (!err.empty()) return fail(MRCM_EUNSUPPORTED, err);
   const NdPlan &P = h->plan;
   std::vector<int4> pinfo(G.n_patch);
@@ -1593,9 +1599,142 @@ mrcm_status mrcm_autotune(const mrcm_problem *pb, const mrcm_partition *part, co
     for (int dg : {-128, -64, 64, 128})
       if (st == MRCM_OK && nf + dg > 0) st = consider(win.solve_tiles, nf + dg);
   if (st != MRCM_OK) return st;
+  // the interface factorisation's panel width, on assembly and solve with
+  // the winning build: one interface handle per candidate, one untimed and
+  // three timed runs, the fastest counted, the same 2% rule
+  {
+    mrcm_mbfs *h = nullptr;
+    st = mrcm_build_mbfs(pb, part, ifs, &win, stream, &h);
+    if (st != MRCM_OK) return st;
+    const int nv = h->G.n_patch;
+    double *X = nullptr;
+    if (nv > 0 && hipMalloc((void **)&X, 2 * (size_t)nv * sizeof(double)) != hipSuccess) {
+      mrcm_mbfs_destroy(h);
+      return fail(MRCM_ENOMEM, "autotune: allocation of the interface vector failed");
+    }
+    const int p0 = win.iface_panel > 0 ? win.iface_panel : kMfPanelMax;
+    double t_p0 = 0.0, t_pbest = 0.0;
+    int p_best = p0;
+    for (int P : {p0, 4, 2, 1}) {
+      if (nv == 0 || st != MRCM_OK) break;
+      if (P == p0 && t_p0 > 0.0) continue;
+      h->G.iface_panel = P;  // the plan of a new interface handle takes it
+      mrcm_interface *ih = nullptr;
+      double ms = 1e300;
+      for (int r = 0; r < 4 && st == MRCM_OK; ++r) {
+        const auto t0 = std::chrono::steady_clock::now();
+        st = mrcm_assemble_interface(h, stream, &ih);
+        if (st == MRCM_OK) st = mrcm_solve_interface(ih, MRCM_IFACE_AUTO, 0.0, 0, stream, X, nullptr, nullptr);
+        if (st == MRCM_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+          st = fail(MRCM_EHIP, "autotune: stream synchronisation failed");
+        const auto t1 = std::chrono::steady_clock::now();
+        if (r > 0) ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+      }
+      if (ih) mrcm_interface_destroy(ih);
+      if (st != MRCM_OK) break;
+      if (t_p0 == 0.0) {
+        t_p0 = t_pbest = ms;
+      } else if (ms < 0.98 * t_pbest) {
+        t_pbest = ms;
+        p_best = P;
+      }
+    }
+    if (X) (void)hipFree(X);
+    mrcm_mbfs_destroy(h);
+    if (st != MRCM_OK) return st;
+    win.iface_panel = nv > 0 ? p_best : win.iface_panel;
+  }
   *best = win;
   if (best_ms) *best_ms = t_best;
   if (rule_ms) *rule_ms = t_rule;
+  return MRCM_OK;
+}
+
+namespace {
+// What the tuned values depend on, as text: the shapes of the problem and of
+// its partition and interface spaces, the form, and the device.
+std::string tune_signature(const mrcm_problem *pb, const mrcm_partition *part, const mrcm_iface_space *ifs,
+                           const mrcm_options *base, const ConfigKey &k) {
+  std::string sig = "n";
+  for (int d = 0; d < 3; ++d) sig += " " + std::to_string(k.n[d]);
+  char buf[64];
+  for (int d = 0; d < 3; ++d) {
+    std::snprintf(buf, sizeof buf, " %.17g", k.h[d]);
+    sig += buf;
+  }
+  for (int d = 0; d < 3; ++d) {
+    sig += "|c";
+    for (int c : k.cuts[d]) sig += " " + std::to_string(c);
+    sig += "|u " + std::to_string(k.us[d][0]) + " " + std::to_string(k.us[d][1]);
+  }
+  sig += "|s";
+  for (int v : k.split) sig += " " + std::to_string(v);
+  sig += "|w";
+  for (int f = 0; f < 6; ++f) sig += " " + std::to_string(k.wall_type[f]);
+  sig += "|p " + std::to_string(base->precision) + " b " + std::to_string(base->beta_mode) + " k " +
+         std::to_string(base->keep);
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    sig += std::string("|d ") + prop.gcnArchName + " " + std::to_string(prop.multiProcessorCount);
+  (void)pb;
+  (void)part;
+  (void)ifs;
+  return sig;
+}
+
+uint64_t fnv1a64(const std::string &s) {
+  uint64_t h = 1469598103934665603ull;
+  for (unsigned char c : s) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+}  // namespace
+
+mrcm_status mrcm_autotune_cached(const mrcm_problem *pb, const mrcm_partition *part, const mrcm_iface_space *ifs,
+                                 const mrcm_options *base, void *stream, const char *cache_path, mrcm_options *best,
+                                 double *best_ms, double *rule_ms, int32_t *from_cache) {
+  if (!pb || !part || !ifs || !base || !best || !cache_path) return fail(MRCM_EINVAL, "null argument");
+  if (from_cache) *from_cache = 0;
+  ConfigKey k;
+  if (!make_key(pb, part, ifs, base, k))  // malformed input: the full check reports it
+    return mrcm_autotune(pb, part, ifs, base, stream, best, best_ms, rule_ms);
+  char key[32];
+  std::snprintf(key, sizeof key, "%016llx", (unsigned long long)fnv1a64(tune_signature(pb, part, ifs, base, k)));
+  if (FILE *f = std::fopen(cache_path, "r")) {
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+      char tag[32], kk[32];
+      int tiles = 0, group = 0, panel = 0;
+      double bm = 0.0, rm = 0.0;
+      if (std::sscanf(line, "%31s %31s %d %d %d %lf %lf", tag, kk, &tiles, &group, &panel, &bm, &rm) != 7) continue;
+      if (std::strcmp(tag, "mrcm-tune-1") != 0 || std::strcmp(kk, key) != 0) continue;
+      if (tiles < 0 || tiles > solve_chunk_max() / 16 || group < -1 || panel < 0 || panel > kMfPanelMax) continue;
+      std::fclose(f);
+      *best = *base;
+      best->solve_tiles = tiles;
+      best->solve_group = group;
+      best->iface_panel = panel;
+      if (best_ms) *best_ms = bm;
+      if (rule_ms) *rule_ms = rm;
+      if (from_cache) *from_cache = 1;
+      return MRCM_OK;
+    }
+    std::fclose(f);
+  }
+  double bm = 0.0, rm = 0.0;
+  const mrcm_status st = mrcm_autotune(pb, part, ifs, base, stream, best, &bm, &rm);
+  if (st != MRCM_OK) return st;
+  if (best_ms) *best_ms = bm;
+  if (rule_ms) *rule_ms = rm;
+  FILE *f = std::fopen(cache_path, "a");
+  if (!f) return fail(MRCM_EINVAL, std::string("autotune cache not writable: ") + cache_path);
+  const int ok = std::fprintf(f, "mrcm-tune-1 %s %d %d %d %.6f %.6f\n", key, best->solve_tiles, best->solve_group,
+                              best->iface_panel, bm, rm);
+  const int closed = std::fclose(f);
+  if (ok < 0 || closed != 0) return fail(MRCM_EINVAL, std::string("autotune cache not writable: ") + cache_path);
   return MRCM_OK;
 }
 

@@ -15,8 +15,8 @@
 //     transposed above the diagonal: W[i][c] at column i, row k0 + c;
 //   the update matrix (Schur complement) in the trailing r x r block.
 // Levels are processed bottom-up, each as one extend-add per child slot, the
-// factorisation of every node's first block, then panel by panel (kMfPanel
-// blocks of 16 columns): one launch per block over the row tiles below it,
+// factorisation of every node's first block, then panel by panel (up to
+// kMfPanelMax blocks of 16 columns): one launch per block over the row tiles below it,
 // which forms W and updates the rest of the panel only, and one rank-64
 // update of the trailing tiles past the panel, with W read back from its
 // transposed store.  The trailing matrix is thus read and written once per
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(64) void k_mf_diag(const MfNode *__restrict__ nodes
 constexpr int kMfStepThreads = 320;
 
 __global__ __launch_bounds__(kMfStepThreads) void k_mf_step(const MfNode *__restrict__ nodes,
-                                                            const int2 *__restrict__ blocks, int t,
+                                                            const int2 *__restrict__ blocks, int t, int panel,
                                                             double *__restrict__ fronts, double *__restrict__ inv,
                                                             DevStatus *st) {
   using M = Mma<double>;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kMfStepThreads) void k_mf_step(const MfNode *__rest
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int ti = bt.y, tj = 0;
-  const int pe = kLB * min(t - t % kMfPanel + kMfPanel, nd.sp / kLB);  // end of the panel
+  const int pe = kLB * min(t - t % panel + panel, nd.sp / kLB);  // end of the panel
   const int i0 = r0 + 64 * ti, j0 = r0;
   auto a21 = [&](int i, int c) -> double { return i < f ? A[(int64_t)(k0 + c) * f + i] : 0.0; };
   const bool rows = wave < 4;
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(kMfStepThreads) void k_mf_step(const MfNode *__rest
   }
 }
 
-// Trailing update past the panel of blocks t0 .. t0 + nb - 1 (nb <= kMfPanel):
+// Trailing update past the panel of blocks t0 .. t0 + nb - 1 (nb <= panel):
 // C -= W D^{-1} W^T on the lower 64x64 tiles of the rows and columns
 // R0 = 16 (t0 + nb) .. f - 1, K = 16 nb.  The tile stays in accumulators
 // while W of its rows i and columns j comes block by block (16 columns of K)
@@ -380,7 +380,7 @@ constexpr int kMfTrailThreads = 256;
 constexpr int kMfTrailStride = kLB + 1;
 
 __global__ __launch_bounds__(kMfTrailThreads) void k_mf_trailing(const MfNode *__restrict__ nodes,
-                                                                 const int2 *__restrict__ blocks, int t0,
+                                                                 const int2 *__restrict__ blocks, int t0, int panel,
                                                                  double *__restrict__ fronts,
                                                                  const double *__restrict__ inv) {
   using M = Mma<double>;
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(kMfTrailThreads) void k_mf_trailing(const MfNode *_
   const int2 bt = blocks[blockIdx.x];
   const MfNode nd = nodes[bt.x];
   const int f = nd.f;
-  const int nb = min(kMfPanel, nd.sp / kLB - t0);
+  const int nb = min(panel, nd.sp / kLB - t0);
   const int R0 = kLB * (t0 + nb);
   int ti = 0, tj = bt.y;
   while (tj > ti) {
@@ -687,11 +687,11 @@ hipError_t launch_mf_factor(const NdPlan &plan, const MfDevPlan &dp, double *fro
       const MfStepLaunch &L = plan.steps[si];
       const int2 *bl = dp.step_blocks + L.blk_off;
       if (L.kind == kMfPanelStep)
-        hipLaunchKernelGGL(k_mf_step, dim3(L.n_blocks), dim3(kMfStepThreads), 0, s, dp.nodes, bl, L.t, fronts, inv,
-                           st);
+        hipLaunchKernelGGL(k_mf_step, dim3(L.n_blocks), dim3(kMfStepThreads), 0, s, dp.nodes, bl, L.t, plan.panel,
+                           fronts, inv, st);
       else if (L.kind == kMfTrailing)
-        hipLaunchKernelGGL(k_mf_trailing, dim3(L.n_blocks), dim3(kMfTrailThreads), 0, s, dp.nodes, bl, L.t, fronts,
-                           inv);
+        hipLaunchKernelGGL(k_mf_trailing, dim3(L.n_blocks), dim3(kMfTrailThreads), 0, s, dp.nodes, bl, L.t,
+                           plan.panel, fronts, inv);
       else
         hipLaunchKernelGGL(k_mf_diag, dim3(L.n_blocks), dim3(64), 0, s, dp.nodes, bl, L.t, fronts, inv, st);
     }

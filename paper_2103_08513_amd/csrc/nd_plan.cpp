@@ -22,7 +22,10 @@ struct TmpNode {
 }  // namespace
 
 std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, const std::vector<IfaceDesc> &ifcs,
-                          const std::vector<int> &patches, int n_patch, NdPlan &plan) {
+                          const std::vector<int> &patches, int n_patch, int panel, NdPlan &plan) {
+  if (panel < 1 || panel > kMfPanelMax)
+    return "the interface panel must hold 1 to " + std::to_string(kMfPanelMax) + " blocks";
+  plan.panel = panel;
   plan = NdPlan();
   plan.n_unknowns = 2 * n_patch;
   if (n_patch == 0) return "";
@@ -229,7 +232,7 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
   plan.level_fb_off[H] = (int)plan.fwd_bnd.size();
   plan.level_bb_off[H] = (int)plan.bwd_bnd.size();
 
-  // factorisation launches, per level, per panel of kMfPanel blocks starting
+  // factorisation launches, per level, per panel of plan.panel blocks starting
   // at block t0: the LDL^T of block t0 (t0 > 0; block 0 is factored by the
   // level's first launch), then per block t of the panel its step over the
   // row tiles below it, then the trailing update past the panel
@@ -249,9 +252,10 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
       L.n_blocks = (int)(plan.step_blocks.size() - L.blk_off);
       if (L.n_blocks > 0) plan.steps.push_back(L);
     };
-    for (int t0 = 0; t0 < tmax; t0 += kMfPanel) {
+    const int P = plan.panel;
+    for (int t0 = 0; t0 < tmax; t0 += P) {
       if (t0 > 0) push(kMfDiag, t0, [&](const MfNode &M) { return M.sp / kNB > t0 ? 1 : 0; });
-      for (int t = t0; t < t0 + kMfPanel; ++t)
+      for (int t = t0; t < t0 + P; ++t)
         push(kMfPanelStep, t, [&](const MfNode &M) {
           if (M.sp / kNB <= t) return 0;
           const int nr = M.f - kNB * (t + 1);
@@ -259,7 +263,7 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
         });
       push(kMfTrailing, t0, [&](const MfNode &M) {
         if (M.sp / kNB <= t0) return 0;
-        const int nr = M.f - kNB * std::min(t0 + kMfPanel, M.sp / kNB);
+        const int nr = M.f - kNB * std::min(t0 + P, M.sp / kNB);
         const int tt = nr > 0 ? (nr + 63) / 64 : 0;
         return tt * (tt + 1) / 2;
       });

@@ -30,13 +30,14 @@ struct MfNode {
   int32_t child0, child1;  // child nodes or -1
 };
 
-// The factorisation proceeds per level in panels of kMfPanel 16-column
-// blocks.  One launch of it: the nodes of one level that have the block or
-// panel concerned, one workgroup per (node, tile) entry of the table.
-constexpr int kMfPanel = 4;
+// The factorisation proceeds per level in panels of `panel` 16-column blocks
+// (1 .. kMfPanelMax; a panel of one block is the plain right-looking step).
+// One launch of it: the nodes of one level that have the block or panel
+// concerned, one workgroup per (node, tile) entry of the table.
+constexpr int kMfPanelMax = 4;
 enum MfLaunchKind {
   kMfPanelStep = 0,  // block t: W of every row below it, the update of the panel's later columns
-  kMfTrailing = 1,   // the panel starting at block t: rank-(16 kMfPanel) update of the trailing tiles
+  kMfTrailing = 1,   // the panel starting at block t: rank-(16 panel) update of the trailing tiles
   kMfDiag = 2,       // LDL^T of the diagonal block t (the first block of a panel)
 };
 struct MfStepLaunch {
@@ -58,6 +59,7 @@ constexpr int kMfBwdCols = 256;
 
 struct NdPlan {
   int n_unknowns = 0;                 // 2 * patches
+  int panel = kMfPanelMax;            // 16-column blocks per panel of the factorisation
   std::vector<MfNode> nodes;          // in elimination order (children first)
   std::vector<int> idx, map;          // concatenated per node
   std::vector<int> level_off;         // nodes of level h: [level_off[h], level_off[h+1]) (levels bottom-up)
@@ -104,7 +106,7 @@ constexpr size_t kMfSweepLdsMax = 150 * 1024;
 // interface descriptors and concatenated patch lists.  Returns an empty
 // string on success, else a message.
 std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, const std::vector<IfaceDesc> &ifcs,
-                          const std::vector<int> &patches, int n_patch, NdPlan &plan);
+                          const std::vector<int> &patches, int n_patch, int panel, NdPlan &plan);
 
 // Launchers (mf_kernels.hip).  Vectors in the interleaved unknown order
 // (2p: pi^p of patch p, 2p+1: pi^u), unflipped.

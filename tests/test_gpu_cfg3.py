@@ -182,3 +182,46 @@ def test_cfg3_shaped_block_against_the_whole_oracle(precision):
     assert e_a < 1e-10 and e_b < 1e-10
     assert epi < 1e-8 and ep < 1e-8 and eu < 1e-8
     m.close()
+
+
+def test_cfg3_autotune_cache_and_recorded_step(case3, tmp_path):
+    """Orchestration at the cfg3 size: the autotuner (build tunables and the
+    interface panel width) with its per-shape cache -- a second call is a
+    hit with the same values -- and the tuned step recorded as a HIP graph,
+    whose replays equal the eager step bitwise."""
+    import paper_2103_08513_amd as lib
+    pb = case3.problem
+    stream = torch.cuda.Stream()
+    cache = tmp_path / "tune.txt"
+    with torch.cuda.stream(stream):
+        kx, ky, kz, q = (_dev(a) for a in (pb.kx, pb.ky, pb.kz, pb.q))
+        m = lib.MRCM(pb, case3.partition, case3.iface, alpha=case3.alpha, precision=lib.FP64)
+        t0 = time.perf_counter()
+        first = m.autotune(kx, ky, kz, q, stream=stream, cache=str(cache))
+        t1 = time.perf_counter()
+        again = m.autotune(kx, ky, kz, q, stream=stream, cache=str(cache))
+        t2 = time.perf_counter()
+        print(f"cfg3 autotune {first} in {t1 - t0:.1f} s; cached {again['from_cache']} in {t2 - t1:.3f} s",
+              flush=True)
+        assert not first["from_cache"] and again["from_cache"]
+        for key in ("solve_tiles", "solve_group", "iface_panel"):
+            assert again[key] == first[key]
+        assert 1 <= first["iface_panel"] <= 4
+        assert len(cache.read_text().splitlines()) == 1
+        m.solve(kx, ky, kz, q, refine=1)  # handles with the tuned values
+        nv = m.info().n_patch
+        X = torch.empty(2 * nv, dtype=torch.float64, device="cuda")
+        p = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+        U = torch.empty(6 * pb.n, dtype=torch.float64, device="cuda")
+        g = m.capture(kx, ky, kz, q, X, p, U, refine=1, stream=stream)
+        for k in range(3):
+            g.launch(stream=stream)
+            g.check(stream=stream)
+            p_g, U_g, X_g = p.clone(), U.clone(), X.clone()
+            p_e, U_e, X_e = m.solve(kx, ky, kz, q, refine=1)
+            stream.synchronize()
+            assert torch.equal(p_g, p_e), k
+            assert torch.equal(U_g, U_e.reshape(-1)), k
+            assert torch.equal(X_g, X_e), k
+        g.close()
+        m.close()

@@ -51,3 +51,54 @@ def test_autotune_and_tunables_keep_the_solution():
         m.close()
     tuned.close()
     ref.close()
+
+
+def test_autotune_cache_keys_on_shapes(tmp_path):
+    """The per-shape cache: a second call on the same shapes is a hit with the
+    same values, whatever the coefficients (alpha, the field); another
+    partition is a miss that adds its own line."""
+    import paper_2103_08513_amd as lib
+    from mrcm_inputs import config1, small_case
+    cache = str(tmp_path / "tune.txt")
+    c = config1()
+    pb = c.problem
+    args = [_dev(a) for a in (pb.kx, pb.ky, pb.kz, pb.q)]
+    m = lib.MRCM(pb, c.partition, c.iface, alpha=c.alpha)
+    a = m.autotune(*args, cache=cache)
+    c2 = config1(seed=1)
+    m2 = lib.MRCM(c2.problem, c2.partition, c2.iface, alpha=2.0)
+    b = m2.autotune(*[_dev(x) for x in (c2.problem.kx, c2.problem.ky, c2.problem.kz, c2.problem.q)], cache=cache)
+    assert not a["from_cache"] and b["from_cache"]
+    assert (a["solve_tiles"], a["solve_group"], a["iface_panel"]) == (b["solve_tiles"], b["solve_group"],
+                                                                       b["iface_panel"])
+    s = small_case((20, 10, 8), (2, 1, 1), split=((2, 2), (1, 1), (1, 1)), seed=3)
+    m3 = lib.MRCM(s.problem, s.partition, s.iface, alpha=s.alpha)
+    c3 = m3.autotune(*[_dev(x) for x in (s.problem.kx, s.problem.ky, s.problem.kz, s.problem.q)], cache=cache)
+    assert not c3["from_cache"]
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 2 and all(ln.startswith("mrcm-tune-1 ") for ln in lines)
+    for x in (m, m2, m3):
+        x.close()
+
+
+def test_interface_panel_widths_agree():
+    """The interface factorisation in panels of 1, 2 and 4 blocks (one
+    rank-16 step per block, or one rank-32/64 trailing update per panel)
+    gives bitwise the same interface solution: every entry receives the same
+    FP64 MFMA accumulations in the same block and k order, whether it passes
+    through memory between blocks or stays in the accumulators."""
+    import paper_2103_08513_amd as lib
+    case = config2()
+    pb = case.problem
+    args = [_dev(a) for a in (pb.kx, pb.ky, pb.kz, pb.q)]
+    ref = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha)
+    p_ref, _, X_ref = ref.solve(*args, refine=1)
+    for panel in (1, 2, 4):
+        m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, iface_panel=panel)
+        p, _, X = m.solve(*args, refine=1)
+        torch.cuda.synchronize()
+        ex, ep = _rel_l2(X, X_ref), _rel_l2(p, p_ref)
+        print(f"iface_panel {panel}: pi differs by {ex:.2g}, p by {ep:.2g}", flush=True)
+        assert torch.equal(X, X_ref) and torch.equal(p, p_ref), (ex, ep)
+        m.close()
+    ref.close()
