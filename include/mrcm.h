@@ -72,6 +72,10 @@ enum { MRCM_BETA_PER_SIDE = 0,  /* each side its own: alpha H_own / K_d(own cell
 enum { MRCM_KEEP_FACTORS = 1,   /* the local band factors */
        MRCM_KEEP_MBFS = 2 };    /* the MBFs X_l (reconstruction by combination) */
 
+/* How the ragged launches of loop 1 take their subdomains (mrcm_options.launch_mode). */
+enum { MRCM_LAUNCH_GRID = 0,    /* one workgroup per subdomain or work item */
+       MRCM_LAUNCH_QUEUE = 1 }; /* persistent workgroups over a device work queue */
+
 /*
  * The Darcy problem (Sec. 2.1).  All arrays have N = nx*ny*nz entries.
  *  kx, ky, kz  [dev] diagonal of K-hat per cell; must be positive and finite.
@@ -189,6 +193,13 @@ typedef struct {
  *              factorisation, 1 to 4 (0: 4): each panel's trailing update is
  *              one rank-(16 iface_panel) product.  Set by mrcm_autotune; an
  *              interface handle takes the value of its MBF handle.
+ * launch_mode  MRCM_LAUNCH_GRID (0, the default): the ragged launches of the
+ *              direct forms' factorisation and band solves run one workgroup
+ *              per subdomain or work item; MRCM_LAUNCH_QUEUE (1): a
+ *              persistent grid of resident workgroups takes the same items,
+ *              in the same cost order, from a device work queue (one atomic
+ *              counter per XCD); no workgroup waits on another.  The results
+ *              are bitwise the same.  Set by mrcm_autotune.
  */
 typedef struct {
   double alpha;
@@ -204,6 +215,7 @@ typedef struct {
   int32_t beta_mode;
   uint32_t keep;
   int32_t iface_panel;
+  int32_t launch_mode;
 } mrcm_options;
 
 typedef struct mrcm_mbfs mrcm_mbfs;           /* local factors, MBFs, Gamma-flux blocks */
@@ -433,9 +445,10 @@ mrcm_status mrcm_profile_get(mrcm_profile *out /* [host] */);
  */
 /*
  * Autotuner (orchestration, Algorithm 2 as a whole): times mrcm_build_mbfs on
- * the given problem for candidate values of solve_tiles and solve_group (each
- * candidate on a handle of its own: one untimed and three timed builds,
- * synchronised, the fastest counted), then, with the winning pair and when
+ * the given problem for candidate values of solve_tiles and solve_group, then
+ * the other launch_mode with the winners (each candidate on a handle of its
+ * own: one untimed and three timed builds, synchronised, the fastest
+ * counted), then, with the winning values and when
  * the problem has interface unknowns, the interface assembly and solve
  * (mrcm_assemble_interface + mrcm_solve_interface, no refinement) for
  * iface_panel 1, 2 and 4.  Writes into *best a copy of *base with the fastest
@@ -450,8 +463,8 @@ mrcm_status mrcm_autotune(const mrcm_problem *problem, const mrcm_partition *par
 
 /*
  * mrcm_autotune with a per-shape cache in the text file cache_path [host]
- * (created when missing; one line per entry: "mrcm-tune-1", the key, then
- * solve_tiles, solve_group, iface_panel, best_ms, rule_ms).  The key is a
+ * (created when missing; one line per entry: "mrcm-tune-2", the key, then
+ * solve_tiles, solve_group, iface_panel, launch_mode, best_ms, rule_ms).  The key is a
  * 64-bit FNV-1a hash of what the tuned values depend on: grid and cell
  * sizes, partition cuts, interface splits, wall types, precision, beta_mode,
  * keep and the device's architecture name and compute-unit count -- not the

@@ -28,6 +28,8 @@ KEEP_FACTORS = 1
 KEEP_MBFS = 2
 
 # interface solvers (mrcm_solve_interface)
+LAUNCH_GRID = 0
+LAUNCH_QUEUE = 1
 IFACE_AUTO = 0
 IFACE_BAND = 1
 IFACE_MULTIFRONTAL = 2
@@ -102,7 +104,7 @@ class MRCM:
 
     def __init__(self, problem, partition, iface, alpha=1.0, precision=FP64, ir_tol=1e-13,
                  ir_max_iter=30, fp64_refine=1, pcg_max_iter=50, solve_tiles=0, solve_group=0, device="cuda",
-                 beta_mode=BETA_PER_SIDE, keep=KEEP_FACTORS | KEEP_MBFS, iface_panel=0):
+                 beta_mode=BETA_PER_SIDE, keep=KEEP_FACTORS | KEEP_MBFS, iface_panel=0, launch_mode=0):
         import torch
         self.lib = library()
         self.device = torch.device(device)
@@ -162,6 +164,7 @@ class MRCM:
         opt.beta_mode = int(beta_mode)
         opt.keep = int(keep)
         opt.iface_panel = int(iface_panel)
+        opt.launch_mode = int(launch_mode)
         opt.pcg_x0 = None
         self._opt = opt
 
@@ -288,7 +291,9 @@ class MRCM:
         self._opt.solve_tiles = best.solve_tiles
         self._opt.solve_group = best.solve_group
         self._opt.iface_panel = best.iface_panel
+        self._opt.launch_mode = best.launch_mode
         return {"solve_tiles": best.solve_tiles, "solve_group": best.solve_group, "iface_panel": best.iface_panel,
+                "launch_mode": best.launch_mode,
                 "build_ms": t_best.value, "build_ms_default": t_rule.value, "from_cache": bool(hit.value)}
 
     def capture(self, kx, ky, kz, q, X, p, U, refine=0, stream=None):

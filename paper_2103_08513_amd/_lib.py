@@ -51,7 +51,8 @@ class COptions(ctypes.Structure):
     _fields_ = [("alpha", c_double), ("precision", c_int32), ("ir_tol", c_double),
                 ("ir_max_iter", c_int32), ("fp64_refine", c_int32), ("pcg_max_iter", c_int32),
                 ("pcg_x0", ctypes.c_void_p), ("pcg_x0_scale", c_int32), ("solve_tiles", c_int32),
-                ("solve_group", c_int32), ("beta_mode", c_int32), ("keep", c_uint32), ("iface_panel", c_int32)]
+                ("solve_group", c_int32), ("beta_mode", c_int32), ("keep", c_uint32), ("iface_panel", c_int32),
+                ("launch_mode", c_int32)]
 
 
 class CIfaceInfo(ctypes.Structure):

@@ -75,6 +75,7 @@ struct HostGeom {
   int solve_tiles = 0;   // 16-column tiles per solve work item (0: the largest chunk)
   int solve_group = 0;   // FP64 pipeline: solve group 0's size (0: occupancy rule, -1: none)
   int iface_panel = kMfPanelMax;  // blocks per panel of the multifrontal interface factorisation
+  int launch_mode = MRCM_LAUNCH_GRID;  // ragged launches: grid, or persistent over a work queue
   int bmax = 0, mmax = 0, max_cells = 0;
   long long max_nm = 0;
   int64_t totL = 0, totD = 0, totX = 0, totF = 0, totCells = 0;
@@ -94,7 +95,7 @@ struct ConfigKey {
   int32_t beta_mode = 0;
   uint32_t keep = 0;
   int32_t precision = 0;
-  int32_t solve_tiles = 0, solve_group = 0, iface_panel = 0;
+  int32_t solve_tiles = 0, solve_group = 0, iface_panel = 0, launch_mode = 0;
   std::vector<int32_t> cuts[3];
   int32_t us[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   std::vector<int32_t> split;
@@ -107,7 +108,7 @@ struct ConfigKey {
       if (wall_type[f] != o.wall_type[f]) return false;
     return pin == o.pin && alpha == o.alpha && beta_mode == o.beta_mode && keep == o.keep && precision == o.precision &&
            split == o.split && solve_tiles == o.solve_tiles && solve_group == o.solve_group &&
-           iface_panel == o.iface_panel;
+           iface_panel == o.iface_panel && launch_mode == o.launch_mode;
   }
 };
 
@@ -130,6 +131,7 @@ bool make_key(const mrcm_problem *pb, const mrcm_partition *part, const mrcm_ifa
   k.solve_tiles = opt->solve_tiles;
   k.solve_group = opt->solve_group;
   k.iface_panel = opt->iface_panel;
+  k.launch_mode = opt->launch_mode;
   const int nd[3] = {part->ndx, part->ndy, part->ndz};
   const int32_t *cut_in[3] = {part->cut_x, part->cut_y, part->cut_z};
   for (int d = 0; d < 3; ++d) {
@@ -196,6 +198,9 @@ mrcm_status build_host_geom(const mrcm_problem *pb, const mrcm_partition *part,
   if (opt->iface_panel < 0 || opt->iface_panel > kMfPanelMax)
     return fail(MRCM_EINVAL, "iface_panel must be in [0, " + std::to_string(kMfPanelMax) + "]");
   G.iface_panel = opt->iface_panel > 0 ? opt->iface_panel : kMfPanelMax;
+  if (opt->launch_mode != MRCM_LAUNCH_GRID && opt->launch_mode != MRCM_LAUNCH_QUEUE)
+    return fail(MRCM_EINVAL, "launch_mode must be MRCM_LAUNCH_GRID or MRCM_LAUNCH_QUEUE");
+  G.launch_mode = opt->launch_mode;
   if (G.precision != MRCM_FP64 && G.precision != MRCM_FP32_IR && G.precision != MRCM_PCG)
     return fail(MRCM_EINVAL, "precision must be MRCM_FP64, MRCM_FP32_IR or MRCM_PCG");
   G.keep = opt->keep ? opt->keep : (MRCM_KEEP_FACTORS | MRCM_KEEP_MBFS);
@@ -541,6 +546,7 @@ struct mrcm_mbfs {
   IfaceDesc *d_ifc = nullptr;
   int *d_order = nullptr;
   int4 *d_work = nullptr;
+  int *d_queue = nullptr;  // work-queue counters: eight per stream (slot 0 the caller's, 1 the second)
   // FP64 path: when the solve work exceeds one round of resident workgroups,
   // the first n_first items form group 0 and the rest group 1 (whole
   // subdomains each); group 0's refinement overlaps group 1's first solve on
@@ -625,7 +631,7 @@ void free_mbfs(mrcm_mbfs *h) {
                   h->d_subof[2], h->coef, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, h->R0, h->F, h->Fb, h->SAb,
                   h->norms, h->scalar, h->st, h->d_grp_subs[0], h->d_grp_subs[1], h->d_order_split,
                   h->d_colsub, h->d_iters, h->d_conv, h->d_fb_order, h->d_fb_work, h->d_nn_sel, h->d_nn_s0,
-                  h->d_sub_rs, h->d_work_rs, h->Brs, h->Xrs, h->Rrs};
+                  h->d_sub_rs, h->d_work_rs, h->Brs, h->Xrs, h->Rrs, h->d_queue};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
@@ -719,6 +725,7 @@ mrcm_status alloc_mbfs(mrcm_mbfs *h) {
   HIP_TRY(upload(&h->d_ifc, G.ifcs));
   HIP_TRY(upload(&h->d_order, G.order));
   HIP_TRY(upload(&h->d_work, G.work));
+  HIP_TRY(upload(&h->d_queue, std::vector<int>(16, 0)));
   HIP_TRY(upload(&h->d_patches, G.patches));
   for (int d = 0; d < 3; ++d) HIP_TRY(upload(&h->d_subof[d], subof[d]));
   ALLOC(h->coef, 4 * G.totCells, double);
@@ -945,6 +952,9 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   const bool split = !pcg && h->n_first > 0 && (fp32 || h->refine64 > 0);
   const int nsweep = fp32 ? std::min(3, h->ir_max) : h->refine64;
   const int n_work = (int)H.work.size();
+  // the work-queue counters of a stream (slot 0: the caller's, 1: the
+  // second), or null for the plain grid launches
+  auto queue = [&](int slot) -> int * { return H.launch_mode == MRCM_LAUNCH_QUEUE ? h->d_queue + 8 * slot : nullptr; };
   h->ir_iters = 0;
   h->ir_res = 0.0;
   h->pcg_fallback = 0;
@@ -1025,22 +1035,23 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       Stage t(MRCM_STAGE_FACTOR, s);
       const int nm = h->n_fac_main;
       ENQ(launch_factor(fp32, h->d_sub, h->d_order_split, nm, h->coef, h->scal, h->L, h->Dinv, h->st,
-                        H.bmax, s));
+                        H.bmax, s, queue(0)));
       ENQ(hipEventRecord(h->ev_fork, s));
       if (h->n_sub > nm)
         ENQ(launch_factor(fp32, h->d_sub, h->d_order_split + nm, h->n_sub - nm, h->coef, h->scal, h->L, h->Dinv,
-                          h->st, H.bmax, s));
+                          h->st, H.bmax, s, queue(0)));
     }
     ENQ(hipStreamWaitEvent(h->s2, h->ev_fork, 0));
     {
       Stage t(MRCM_STAGE_SOLVE, h->s2);
-      ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->X, h->X, 0, H.bmax, h->s2));
+      ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->X, h->X, 0, H.bmax, h->s2,
+                       nullptr, nullptr, queue(1)));
     }
     for (int it = 0; it < nsweep; ++it) {
       if (!own_res)
         ENQ(launch_residual(g, n0, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, h->s2, h->d_grp_subs[0]));
       ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->R, h->X, 1, H.bmax, h->s2,
-                       own_res ? h->coef : nullptr, rhs0));
+                       own_res ? h->coef : nullptr, rhs0, queue(1)));
     }
     ENQ(hipEventRecord(h->ev_join, h->s2));
     Stage t(MRCM_STAGE_REFINE, s);
@@ -1048,13 +1059,14 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     const int n1 = n_work - h->n_first;
     {
       Stage t1(MRCM_STAGE_SOLVE_REST, s);
-      ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->X, h->X, 2, H.bmax, s));
+      ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->X, h->X, 2, H.bmax, s, nullptr, nullptr,
+                       queue(0)));
     }
     for (int it = 0; it < nsweep; ++it) {
       if (!own_res)
         ENQ(launch_residual(g, n1s, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s, h->d_grp_subs[1]));
       ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->R, h->X, 3, H.bmax, s,
-                       own_res ? h->coef : nullptr, rhs0));
+                       own_res ? h->coef : nullptr, rhs0, queue(0)));
     }
     ENQ(hipStreamWaitEvent(s, h->ev_join, 0));
     h->ir_iters = nsweep;
@@ -1062,11 +1074,12 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     {
       Stage t(MRCM_STAGE_FACTOR, s);
       ENQ(launch_factor(fp32, h->d_sub, h->d_order, h->n_sub, h->coef, h->scal, h->L, h->Dinv, h->st,
-                        H.bmax, s));
+                        H.bmax, s, queue(0)));
     }
     {
       Stage t(MRCM_STAGE_SOLVE, s);
-      ENQ(launch_solve(fp32, g, h->d_work, n_work, h->scal, h->L, h->Dinv, h->X, h->X, 0, H.bmax, s));
+      ENQ(launch_solve(fp32, g, h->d_work, n_work, h->scal, h->L, h->Dinv, h->X, h->X, 0, H.bmax, s, nullptr,
+                       nullptr, queue(0)));
     }
   }
   if (split || pcg) {
@@ -1079,7 +1092,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       }
       Stage t(MRCM_STAGE_REFINE, s);
       ENQ(launch_solve(fp32, g, h->d_work, (int)H.work.size(), h->scal, h->L, h->Dinv, h->R, h->X,
-                       1, H.bmax, s));
+                       1, H.bmax, s, nullptr, nullptr, queue(0)));
     }
     h->ir_iters = h->refine64;
   }
@@ -1573,11 +1586,12 @@ mrcm_status mrcm_autotune(const mrcm_problem *pb, const mrcm_partition *part, co
   if (st != MRCM_OK) return st;
   mrcm_options win = cur;
   double t_best = t_rule;
-  auto consider = [&](int tiles, int group) -> mrcm_status {
-    if (tiles == cur.solve_tiles && group == cur.solve_group) return MRCM_OK;
+  auto consider = [&](int tiles, int group, int lm) -> mrcm_status {
+    if (tiles == cur.solve_tiles && group == cur.solve_group && lm == cur.launch_mode) return MRCM_OK;
     mrcm_options o = cur;
     o.solve_tiles = tiles;
     o.solve_group = group;
+    o.launch_mode = lm;
     double t = 0.0;
     mrcm_status e = time_opts(o, t, nullptr);
     if (e != MRCM_OK) return e;
@@ -1591,13 +1605,16 @@ mrcm_status mrcm_autotune(const mrcm_problem *pb, const mrcm_partition *part, co
   };
   const int tmax = solve_chunk_max() / 16;
   for (int tiles = 0; tiles <= tmax && st == MRCM_OK; ++tiles) {
-    st = consider(tiles, 0);
-    if (st == MRCM_OK && base->precision == MRCM_FP64) st = consider(tiles, -1);
+    st = consider(tiles, 0, cur.launch_mode);
+    if (st == MRCM_OK && base->precision == MRCM_FP64) st = consider(tiles, -1, cur.launch_mode);
   }
   // the size of the pipeline's first group around the occupancy rule's
   if (st == MRCM_OK && nf > 0)
     for (int dg : {-128, -64, 64, 128})
-      if (st == MRCM_OK && nf + dg > 0) st = consider(win.solve_tiles, nf + dg);
+      if (st == MRCM_OK && nf + dg > 0) st = consider(win.solve_tiles, nf + dg, cur.launch_mode);
+  // the persistent work-queue form of the ragged launches, with the winners
+  if (st == MRCM_OK && base->precision != MRCM_PCG)
+    st = consider(win.solve_tiles, win.solve_group, 1 - cur.launch_mode);
   if (st != MRCM_OK) return st;
   // the interface factorisation's panel width, on assembly and solve with
   // the winning build: one interface handle per candidate, one untimed and
@@ -1707,16 +1724,20 @@ mrcm_status mrcm_autotune_cached(const mrcm_problem *pb, const mrcm_partition *p
     char line[512];
     while (std::fgets(line, sizeof line, f)) {
       char tag[32], kk[32];
-      int tiles = 0, group = 0, panel = 0;
+      int tiles = 0, group = 0, panel = 0, lm = 0;
       double bm = 0.0, rm = 0.0;
-      if (std::sscanf(line, "%31s %31s %d %d %d %lf %lf", tag, kk, &tiles, &group, &panel, &bm, &rm) != 7) continue;
-      if (std::strcmp(tag, "mrcm-tune-1") != 0 || std::strcmp(kk, key) != 0) continue;
-      if (tiles < 0 || tiles > solve_chunk_max() / 16 || group < -1 || panel < 0 || panel > kMfPanelMax) continue;
+      if (std::sscanf(line, "%31s %31s %d %d %d %d %lf %lf", tag, kk, &tiles, &group, &panel, &lm, &bm, &rm) != 8)
+        continue;
+      if (std::strcmp(tag, "mrcm-tune-2") != 0 || std::strcmp(kk, key) != 0) continue;
+      if (tiles < 0 || tiles > solve_chunk_max() / 16 || group < -1 || panel < 0 || panel > kMfPanelMax ||
+          (lm != MRCM_LAUNCH_GRID && lm != MRCM_LAUNCH_QUEUE))
+        continue;
       std::fclose(f);
       *best = *base;
       best->solve_tiles = tiles;
       best->solve_group = group;
       best->iface_panel = panel;
+      best->launch_mode = lm;
       if (best_ms) *best_ms = bm;
       if (rule_ms) *rule_ms = rm;
       if (from_cache) *from_cache = 1;
@@ -1731,8 +1752,8 @@ mrcm_status mrcm_autotune_cached(const mrcm_problem *pb, const mrcm_partition *p
   if (rule_ms) *rule_ms = rm;
   FILE *f = std::fopen(cache_path, "a");
   if (!f) return fail(MRCM_EINVAL, std::string("autotune cache not writable: ") + cache_path);
-  const int ok = std::fprintf(f, "mrcm-tune-1 %s %d %d %d %.6f %.6f\n", key, best->solve_tiles, best->solve_group,
-                              best->iface_panel, bm, rm);
+  const int ok = std::fprintf(f, "mrcm-tune-2 %s %d %d %d %d %.6f %.6f\n", key, best->solve_tiles,
+                              best->solve_group, best->iface_panel, best->launch_mode, bm, rm);
   const int closed = std::fclose(f);
   if (ok < 0 || closed != 0) return fail(MRCM_EINVAL, std::string("autotune cache not writable: ") + cache_path);
   return MRCM_OK;

@@ -12,15 +12,18 @@ hipError_t launch_check_perm(const double *kx, const double *ky, const double *k
                              DevStatus *st, hipStream_t s);
 hipError_t launch_coef(const Geom &g, int n_sub, int max_cells, double *coef, double *r0,
                        double *scal, hipStream_t s);
+// queue non-null: the persistent form over a device work queue (eight
+// counters, zeroed by the launcher on the stream); else one workgroup per item
 hipError_t launch_factor(int fp32, const SubDesc *subs, const int *order, int n_sub,
                          const double *coef, const double *scal, void *L, void *Dg, DevStatus *st,
-                         int bmax, hipStream_t s);
+                         int bmax, hipStream_t s, int *queue = nullptr);
 // coef non-null with a correction mode: each workgroup forms its item's
 // residual into B before solving, from the right-hand sides in rhs0 (or in B
 // itself when rhs0 is null, which then serves a single sweep)
 hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, const double *scal,
                         const void *L, const void *Dg, double *B, double *X, int mode, int bmax,
-                        hipStream_t s, const double *coef = nullptr, const double *rhs0 = nullptr);
+                        hipStream_t s, const double *coef = nullptr, const double *rhs0 = nullptr,
+                        int *queue = nullptr);
 // B2: a second copy of the right-hand sides, or null
 hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, const double *r0, double *B,
                       hipStream_t s, double *B2 = nullptr);

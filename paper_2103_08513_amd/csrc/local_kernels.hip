@@ -472,10 +472,11 @@ __device__ __forceinline__ ColFetch fetch_column_entry(const double *cf, const d
 
 template <typename T, int kMaxT, int NW>
 __device__ __forceinline__ void factor_body(const SubDesc *__restrict__ subs, const int *__restrict__ order,
-                                            const double *__restrict__ coef, const double *__restrict__ scal,
-                                            T *__restrict__ Lg, T *__restrict__ Dg, DevStatus *st, int ldb,
-                                            unsigned char *smem_raw, int &tile_ctr) {
-  const int sub = order[blockIdx.x];
+                                            int slot, const double *__restrict__ coef,
+                                            const double *__restrict__ scal, T *__restrict__ Lg,
+                                            T *__restrict__ Dg, DevStatus *st, int ldb, unsigned char *smem_raw,
+                                            int &tile_ctr) {
+  const int sub = order[slot];
   const SubDesc &D = subs[sub];
   const int N = D.N, b = D.b, n0 = D.n0, bp1 = b + 1;
   const int W = max(b, kNB) + kNB;
@@ -692,7 +693,7 @@ __global__ __launch_bounds__(512, 1) void k_factor64(const SubDesc *__restrict__
                                                      DevStatus *st, int ldb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int tile_ctr;
-  factor_body<double, kMaxT, 8>(subs, order, coef, scal, Lg, Dg, st, ldb, smem_raw, tile_ctr);
+  factor_body<double, kMaxT, 8>(subs, order, blockIdx.x, coef, scal, Lg, Dg, st, ldb, smem_raw, tile_ctr);
 }
 template <int kMaxT>
 __global__ __launch_bounds__(256, 2) void k_factor32(const SubDesc *__restrict__ subs,
@@ -703,7 +704,56 @@ __global__ __launch_bounds__(256, 2) void k_factor32(const SubDesc *__restrict__
                                                      DevStatus *st, int ldb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int tile_ctr;
-  factor_body<float, kMaxT, 4>(subs, order, coef, scal, Lg, Dg, st, ldb, smem_raw, tile_ctr);
+  factor_body<float, kMaxT, 4>(subs, order, blockIdx.x, coef, scal, Lg, Dg, st, ldb, smem_raw, tile_ctr);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form of a ragged launch: a fixed grid of resident workgroups
+// takes the items from a device work queue, one atomic counter per XCD
+// (workgroup i runs on XCD i mod 8 and takes the items 8 k + i mod 8, as the
+// plain launch would place them), until the counter passes the item count.
+// No workgroup waits on another; every one exits once its XCD's queue is
+// empty.  The caller zeroes the eight counters on the stream first.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int queue_next(int *queue, int n) {
+  __shared__ int item;
+  const int xcd = blockIdx.x & 7;
+  __syncthreads();  // the previous item is done by every thread
+  if (threadIdx.x == 0) {
+    const int k = atomicAdd(queue + xcd, 1);
+    item = 8 * k + xcd;
+  }
+  __syncthreads();
+  return item < n ? item : -1;
+}
+
+__global__ void k_zero_queue(int *queue) {
+  if (threadIdx.x < 8) queue[threadIdx.x] = 0;
+}
+
+template <int kMaxT>
+__global__ __launch_bounds__(512, 1) void k_factor64_q(const SubDesc *__restrict__ subs,
+                                                       const int *__restrict__ order, int n, int *queue,
+                                                       const double *__restrict__ coef,
+                                                       const double *__restrict__ scal,
+                                                       double *__restrict__ Lg, double *__restrict__ Dg,
+                                                       DevStatus *st, int ldb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int tile_ctr;
+  for (int it = queue_next(queue, n); it >= 0; it = queue_next(queue, n))
+    factor_body<double, kMaxT, 8>(subs, order, it, coef, scal, Lg, Dg, st, ldb, smem_raw, tile_ctr);
+}
+template <int kMaxT>
+__global__ __launch_bounds__(256, 2) void k_factor32_q(const SubDesc *__restrict__ subs,
+                                                       const int *__restrict__ order, int n, int *queue,
+                                                       const double *__restrict__ coef,
+                                                       const double *__restrict__ scal,
+                                                       float *__restrict__ Lg, float *__restrict__ Dg,
+                                                       DevStatus *st, int ldb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int tile_ctr;
+  for (int it = queue_next(queue, n); it >= 0; it = queue_next(queue, n))
+    factor_body<float, kMaxT, 4>(subs, order, it, coef, scal, Lg, Dg, st, ldb, smem_raw, tile_ctr);
 }
 
 // ---------------------------------------------------------------------------
@@ -795,13 +845,11 @@ __device__ __forceinline__ void item_residual(const Geom &g, const int4 item, co
 // NRT: most 16-row tiles of the band below a panel (b <= 16 NRT).  coef
 // non-null (corrections only): form the item's FP64 residual into Bg first,
 // from the right-hand sides in rhs0 (or in Bg itself when rhs0 is null).
-// Three waves per SIMD (four workgroups per CU).
 template <typename T, int mode, int NRT>
-__global__ __launch_bounds__(kBsThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_solve(Geom g, const int4 *__restrict__ work,
-                                                         const double *__restrict__ scal,
-                                                         const T *__restrict__ Lg, const T *__restrict__ Dg,
-                                                         double *Bg, double *Xg, int scaled,
-                                                         const double *__restrict__ coef, const double *rhs0) {
+__device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const double *__restrict__ scal,
+                                           const T *__restrict__ Lg, const T *__restrict__ Dg, double *Bg,
+                                           double *Xg, int scaled, const double *__restrict__ coef,
+                                           const double *rhs0, unsigned char *smem_raw) {
   using M = Mma<T>;
   using v4 = typename M::v4;
   constexpr int kLPer = (kNB * (16 * NRT + 1) + kBsThreads - 1) / kBsThreads;  // L entries per thread
@@ -813,8 +861,6 @@ __global__ __launch_bounds__(kBsThreads) __attribute__((amdgpu_waves_per_eu(3, 3
   constexpr int kWF = 16 * (NRT + 1) / 64;      // vector column: forward window rows per lane
   constexpr int kWB = (16 * NRT + 63) / 64;     // backward window rows per lane
   static_assert(16 * (NRT + 1) % 64 == 0, "the forward window spans whole waves");
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int4 item = work[blockIdx.x];
   if (item.x < 0) return;
   if constexpr ((mode & 1) != 0) {
     if (coef) {
@@ -1132,6 +1178,27 @@ __global__ __launch_bounds__(kBsThreads) __attribute__((amdgpu_waves_per_eu(3, 3
   }
 }
 
+// Three waves per SIMD (four workgroups per CU).
+template <typename T, int mode, int NRT>
+__global__ __launch_bounds__(kBsThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_solve(
+    Geom g, const int4 *__restrict__ work, const double *__restrict__ scal, const T *__restrict__ Lg,
+    const T *__restrict__ Dg, double *Bg, double *Xg, int scaled, const double *__restrict__ coef,
+    const double *rhs0) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  solve_item<T, mode, NRT>(g, work[blockIdx.x], scal, Lg, Dg, Bg, Xg, scaled, coef, rhs0, smem_raw);
+}
+
+// The same over the persistent work queue (queue_next).
+template <typename T, int mode, int NRT>
+__global__ __launch_bounds__(kBsThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_solve_q(
+    Geom g, const int4 *__restrict__ work, int n, int *queue, const double *__restrict__ scal,
+    const T *__restrict__ Lg, const T *__restrict__ Dg, double *Bg, double *Xg, int scaled,
+    const double *__restrict__ coef, const double *rhs0) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  for (int it = queue_next(queue, n); it >= 0; it = queue_next(queue, n))
+    solve_item<T, mode, NRT>(g, work[it], scal, Lg, Dg, Bg, Xg, scaled, coef, rhs0, smem_raw);
+}
+
 // ---------------------------------------------------------------------------
 // FP64 residual of all right-hand sides, Rb = R - A^H_l X, matrix-free from
 // the coefficients.  Unless norms is null (a fixed number of refinement
@@ -1406,13 +1473,47 @@ size_t solve_lds_bytes(int fp32, int bmax, int mmax) {
 
 int solve_chunk_max() { return kMaxChunk; }
 
+// Compute units of the current device (the persistent grids' size).
+static int device_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                               hipSuccess)
+    return 0;
+  return n;
+}
+
+// Resident workgroups of a kernel on one CU at the given LDS.
+static int blocks_per_cu(const void *k, int threads, size_t lds) {
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, threads, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+// A persistent grid: every CU full, a multiple of 8 workgroups (one queue per
+// XCD), and no more workgroups than items (rounded up to a multiple of 8).
+static int persistent_grid(const void *k, int threads, size_t lds, int n_items) {
+  const int g = device_cus() * std::max(1, blocks_per_cu(k, threads, lds));
+  return std::max(8, std::min(g, ((n_items + 7) / 8) * 8) / 8 * 8);
+}
+
 // kMaxT: most tiles in one tile column of the trailing update, nT - 1
-template <typename T, typename K>
-static hipError_t launch_factor_t(K kern, int threads, const SubDesc *subs, const int *order, int n_sub,
+template <typename T, typename K, typename KQ>
+static hipError_t launch_factor_t(K kern, KQ kern_q, int threads, const SubDesc *subs, const int *order, int n_sub,
                                   const double *coef, const double *scal, T *L, T *Dg,
-                                  DevStatus *st, int bmax, hipStream_t s) {
+                                  DevStatus *st, int bmax, hipStream_t s, int *queue) {
   const int fp32 = sizeof(T) == 4;
   const size_t lds = factor_lds_bytes(fp32, bmax);
+  if (n_sub <= 0) return hipSuccess;
+  if (queue) {
+    hipError_t e = hipFuncSetAttribute((const void *)kern_q, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, s, queue);
+    const int grid = persistent_grid((const void *)kern_q, threads, lds, n_sub);
+    hipLaunchKernelGGL(kern_q, dim3(grid), dim3(threads), lds, s, subs, order, n_sub, queue, coef, scal, L, Dg, st,
+                       factor_ldb(fp32, bmax));
+    return hipGetLastError();
+  }
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(n_sub), dim3(threads), lds, s, subs, order, coef, scal, L, Dg, st,
@@ -1422,24 +1523,35 @@ static hipError_t launch_factor_t(K kern, int threads, const SubDesc *subs, cons
 
 hipError_t launch_factor(int fp32, const SubDesc *subs, const int *order, int n_sub,
                          const double *coef, const double *scal, void *L, void *Dg, DevStatus *st,
-                         int bmax, hipStream_t s) {
+                         int bmax, hipStream_t s, int *queue) {
   const int nT = (bmax + 15) / 16;
   if (fp32) {
     if (nT <= 7)
-      return launch_factor_t(k_factor32<6>, 256, subs, order, n_sub, coef, scal, (float *)L, (float *)Dg, st,
-                             bmax, s);
-    return launch_factor_t(k_factor32<(kMaxBand32 + 15) / 16 - 1>, 256, subs, order, n_sub, coef, scal,
-                           (float *)L, (float *)Dg, st, bmax, s);
+      return launch_factor_t(k_factor32<6>, k_factor32_q<6>, 256, subs, order, n_sub, coef, scal, (float *)L,
+                             (float *)Dg, st, bmax, s, queue);
+    return launch_factor_t(k_factor32<(kMaxBand32 + 15) / 16 - 1>, k_factor32_q<(kMaxBand32 + 15) / 16 - 1>, 256,
+                           subs, order, n_sub, coef, scal, (float *)L, (float *)Dg, st, bmax, s, queue);
   }
-  return launch_factor_t(k_factor64<(kMaxBand64 + 15) / 16 - 1>, 512, subs, order, n_sub, coef, scal,
-                         (double *)L, (double *)Dg, st, bmax, s);
+  return launch_factor_t(k_factor64<(kMaxBand64 + 15) / 16 - 1>, k_factor64_q<(kMaxBand64 + 15) / 16 - 1>, 512,
+                         subs, order, n_sub, coef, scal, (double *)L, (double *)Dg, st, bmax, s, queue);
 }
 
 template <typename T, int mode, int NRT>
 static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, const double *scal,
                                  const T *L, const T *Dg, double *B, double *X, int bmax, int scaled,
-                                 hipStream_t s, const double *coef, const double *rhs0) {
+                                 hipStream_t s, const double *coef, const double *rhs0, int *queue) {
   const size_t lds = solve_lds_bytes(sizeof(T) == 4, bmax, 0);
+  if (n_work <= 0) return hipSuccess;
+  if (queue) {
+    const void *kq = (const void *)k_solve_q<T, mode, NRT>;
+    hipError_t e = hipFuncSetAttribute(kq, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, s, queue);
+    const int grid = persistent_grid(kq, kBsThreads, lds, n_work);
+    hipLaunchKernelGGL((k_solve_q<T, mode, NRT>), dim3(grid), dim3(kBsThreads), lds, s, g, work, n_work, queue,
+                       scal, L, Dg, B, X, scaled, coef, rhs0);
+    return hipGetLastError();
+  }
   hipError_t e = hipFuncSetAttribute((const void *)k_solve<T, mode, NRT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -1453,36 +1565,36 @@ static hipError_t launch_solve_t(const Geom &g, const int4 *work, int n_work, co
 template <typename T, int mode>
 static hipError_t launch_solve_m(const Geom &g, const int4 *work, int n_work, const double *scal,
                                  const T *L, const T *Dg, double *B, double *X, int bmax, hipStream_t s,
-                                 const double *coef, const double *rhs0) {
+                                 const double *coef, const double *rhs0, int *queue) {
   if (bmax <= 112)
-    return launch_solve_t<T, mode, 7>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef, rhs0);
+    return launch_solve_t<T, mode, 7>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef, rhs0, queue);
   if constexpr (sizeof(T) == 4)
     return launch_solve_t<T, mode, (kMaxBand32 + 15) / 16>(g, work, n_work, scal, L, Dg, B, X, bmax, 1, s, coef,
-                                                             rhs0);
+                                                             rhs0, queue);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, const double *scal,
                         const void *L, const void *Dg, double *B, double *X, int mode, int bmax,
-                        hipStream_t s, const double *coef, const double *rhs0) {
+                        hipStream_t s, const double *coef, const double *rhs0, int *queue) {
   // Separate instantiations per mode, so that profiles tell them apart: bit 0
   // set for a correction (X += ...), bit 1 set for the second group of work
   // items when the first solve is split.
   if (fp32) {
     const float *Lf = (const float *)L, *Df = (const float *)Dg;
     switch (mode) {
-      case 0: return launch_solve_m<float, 0>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef, rhs0);
-      case 1: return launch_solve_m<float, 1>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef, rhs0);
-      case 2: return launch_solve_m<float, 2>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef, rhs0);
-      default: return launch_solve_m<float, 3>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef, rhs0);
+      case 0: return launch_solve_m<float, 0>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef, rhs0, queue);
+      case 1: return launch_solve_m<float, 1>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef, rhs0, queue);
+      case 2: return launch_solve_m<float, 2>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef, rhs0, queue);
+      default: return launch_solve_m<float, 3>(g, work, n_work, scal, Lf, Df, B, X, bmax, s, coef, rhs0, queue);
     }
   }
   const double *Ld = (const double *)L, *Dd = (const double *)Dg;
   switch (mode) {
-    case 0: return launch_solve_m<double, 0>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef, rhs0);
-    case 1: return launch_solve_m<double, 1>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef, rhs0);
-    case 2: return launch_solve_m<double, 2>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef, rhs0);
-    default: return launch_solve_m<double, 3>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef, rhs0);
+    case 0: return launch_solve_m<double, 0>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef, rhs0, queue);
+    case 1: return launch_solve_m<double, 1>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef, rhs0, queue);
+    case 2: return launch_solve_m<double, 2>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef, rhs0, queue);
+    default: return launch_solve_m<double, 3>(g, work, n_work, scal, Ld, Dd, B, X, bmax, s, coef, rhs0, queue);
   }
 }
 

@@ -92,7 +92,7 @@ int main(void) {{
   printf("%zu %zu %zu %zu %zu\\n", offsetof(mrcm_options, pcg_max_iter), offsetof(mrcm_options, pcg_x0), offsetof(mrcm_options, pcg_x0_scale), offsetof(mrcm_options, solve_tiles), offsetof(mrcm_options, solve_group));
   printf("%zu %zu %zu %zu %zu\\n", sizeof(mrcm_info), offsetof(mrcm_info, ir_residual), offsetof(mrcm_info, device_bytes), offsetof(mrcm_info, pcg_fallback), offsetof(mrcm_info, pcg_iters));
   printf("%zu %zu %zu\\n", sizeof(mrcm_subdomain_info), offsetof(mrcm_subdomain_info, pin_local), offsetof(mrcm_subdomain_info, solve_group));
-  printf("%zu %zu %zu\\n", offsetof(mrcm_options, beta_mode), offsetof(mrcm_options, keep), offsetof(mrcm_options, iface_panel));
+  printf("%zu %zu %zu %zu\\n", offsetof(mrcm_options, beta_mode), offsetof(mrcm_options, keep), offsetof(mrcm_options, iface_panel), offsetof(mrcm_options, launch_mode));
   printf("%zu %zu %zu %zu %zu\\n", sizeof(mrcm_interface_info), offsetof(mrcm_interface_info, front_bytes), offsetof(mrcm_interface_info, factor_flops), offsetof(mrcm_interface_info, device_bytes), offsetof(mrcm_interface_info, rel_residual));
   return 0;
 }}
@@ -111,7 +111,7 @@ int main(void) {{
         [ctypes.sizeof(CInfo), CInfo.ir_residual.offset, CInfo.device_bytes.offset, CInfo.pcg_fallback.offset,
          CInfo.pcg_iters.offset],
         [ctypes.sizeof(CSubInfo), CSubInfo.pin_local.offset, CSubInfo.solve_group.offset],
-        [COptions.beta_mode.offset, COptions.keep.offset, COptions.iface_panel.offset],
+        [COptions.beta_mode.offset, COptions.keep.offset, COptions.iface_panel.offset, COptions.launch_mode.offset],
         [ctypes.sizeof(CIfaceInfo), CIfaceInfo.front_bytes.offset, CIfaceInfo.factor_flops.offset,
          CIfaceInfo.device_bytes.offset, CIfaceInfo.rel_residual.offset],
     ]
@@ -150,6 +150,9 @@ def test_host_validation_of_the_forms_and_tunables():
     opt.iface_panel = -1
     assert build() == -1 and b"iface_panel" in lib.mrcm_last_error()
     opt.iface_panel = 0
+    opt.launch_mode = 2
+    assert build() == -1 and b"launch_mode" in lib.mrcm_last_error()
+    opt.launch_mode = 0
     opt.beta_mode = 2
     assert build() == -1 and b"beta_mode" in lib.mrcm_last_error()
     opt.beta_mode = 1

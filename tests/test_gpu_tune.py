@@ -76,7 +76,7 @@ def test_autotune_cache_keys_on_shapes(tmp_path):
     c3 = m3.autotune(*[_dev(x) for x in (s.problem.kx, s.problem.ky, s.problem.kz, s.problem.q)], cache=cache)
     assert not c3["from_cache"]
     lines = open(cache).read().splitlines()
-    assert len(lines) == 2 and all(ln.startswith("mrcm-tune-1 ") for ln in lines)
+    assert len(lines) == 2 and all(ln.startswith("mrcm-tune-2 ") for ln in lines)
     for x in (m, m2, m3):
         x.close()
 
@@ -102,3 +102,28 @@ def test_interface_panel_widths_agree():
         assert torch.equal(X, X_ref) and torch.equal(p, p_ref), (ex, ep)
         m.close()
     ref.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_work_queue_launches_give_bitwise_the_grid_result(precision):
+    """launch_mode MRCM_LAUNCH_QUEUE (persistent workgroups over per-XCD work
+    queues) against the plain grid launches, on the 60x220x85 workload (the
+    FP64 form's two-stream pipeline, and the FP32 form) and on a ragged
+    small case: every item is computed the same way whichever workgroup takes
+    it, so the MBFs and the pressure are bitwise equal."""
+    import paper_2103_08513_amd as lib
+    from mrcm_inputs import small_case
+    for case in (config2(), small_case((37, 23, 11), (3, 2, 2), split=((2, 1), (1, 2), (2, 2)), seed=5)):
+        pb = case.problem
+        args = [_dev(a) for a in (pb.kx, pb.ky, pb.kz, pb.q)]
+        out = []
+        for lm in (lib.LAUNCH_GRID, lib.LAUNCH_QUEUE):
+            m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision, launch_mode=lm)
+            p, U, X = m.solve(*args, refine=1)
+            torch.cuda.synchronize()
+            n_sub = m.info().n_sub
+            out.append((p.clone(), U.clone(), [m.copy_mbfs(l) for l in range(0, n_sub, max(1, n_sub // 7))]))
+            m.close()
+        (p0, U0, X0), (p1, U1, X1) = out
+        assert torch.equal(p0, p1) and torch.equal(U0, U1)
+        assert all(np.array_equal(a, b) for a, b in zip(X0, X1))
