@@ -52,11 +52,12 @@ def _stages(L, _lib, steps):
 
 
 def run_gpu(case, precision, steps, warmup, refine, graph=False, tune=False, net=None, pcg_max_iter=1000,
-            profile=True):
+            profile=True, mean=False):
     """K timed whole solves of `case` in the given form (0 FP64, 1 FP32 with
     FP64 refinement, 2 conjugate gradients started from the network `net`),
     then the same K steps with stage profiling, then (FP64) the step replayed
-    from a recorded HIP graph."""
+    from a recorded HIP graph, then (mean) K timed Mean post-processings of
+    the last step's velocity."""
     import torch
     import paper_2103_08513_amd as lib
     from paper_2103_08513_amd import _lib
@@ -128,6 +129,9 @@ def run_gpu(case, precision, steps, warmup, refine, graph=False, tune=False, net
         graph_ms = (time.perf_counter() - t0) * 1e3 / steps
         g.check(stream=gs)
         g.close()
+    mean_out = None
+    if mean:
+        mean_out = time_mean(model, pb, case.partition, U, steps)
     # residual and mass balance once, outside the timed and profiled loops
     model.solve_interface(X, refine=refine, residual=True)
     torch.cuda.synchronize()
@@ -144,10 +148,47 @@ def run_gpu(case, precision, steps, warmup, refine, graph=False, tune=False, net
         shapes.append((si.n_cells, si.band, si.n_rhs, si.solve_group))
     out = dict(ms_step=ms_step, graph_ms=graph_ms, tuned=tuned, stages=stages, info=info, iinfo=iinfo,
                interface_residual=model.interface_residual, refine_iters=model.interface_iters,
-               mass_imbalance=imbalance, sub_shapes=shapes)
+               mass_imbalance=imbalance, sub_shapes=shapes, mean=mean_out)
     model.close()
     del p, U, X, kx, ky, kz, q
     torch.cuda.empty_cache()
+    return out
+
+
+def time_mean(model, pb, part, U, steps):
+    """The Mean post-processing (mrcm_postprocess_mean) of the step's velocity:
+    one untimed call (it sets up its buffers), then K calls timed with HIP
+    events on the stream they run on, and the balance of the result."""
+    import torch
+    N = pb.n
+    pt = torch.empty(N, dtype=torch.float64, device=U.device)
+    Ut = torch.empty(6 * N, dtype=torch.float64, device=U.device)
+    model.postprocess_mean(U, pt=pt, Ut=Ut)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        model.postprocess_mean(U, pt=pt, Ut=Ut)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    A = torch.tensor([pb.hy * pb.hz] * 2 + [pb.hx * pb.hz] * 2 + [pb.hx * pb.hy] * 2, dtype=torch.float64,
+                     device=U.device)
+    Q = Ut.view(6, N) * A[:, None]
+    bal = (Q.sum(dim=0) - torch.as_tensor(pb.q, device=U.device)).abs()
+    qmax = float(Q.abs().max())
+    del Q
+    nx, ny, _ = pb.dims
+    lo = [torch.as_tensor(np.asarray(c[:-1], dtype=np.int64), device=U.device) for c in part.cuts]
+    pinned = torch.zeros(N, dtype=torch.bool, device=U.device)
+    pinned[(lo[0][None, None, :] + nx * (lo[1][None, :, None] + ny * lo[2][:, None, None])).reshape(-1)] = True
+    out = {"ms": ms, "mcells_per_s": N / (ms * 1e-3) / 1e6,
+           "balance_free_cells": float(bal[~pinned].max()) / qmax,
+           "balance_pinned_cells": float(bal[pinned].max()) / qmax,
+           "what": "Mean post-processing of the step's velocity (unique Gamma flux, one Neumann problem per "
+                   "subdomain by FP64 band Cholesky and one refinement sweep, factors chunked through an 8 GiB "
+                   "scratch); balances relative to the largest face flux"}
+    del pt, Ut, bal, pinned
     return out
 
 
@@ -363,6 +404,7 @@ def main():
     ap.add_argument("--no-block", action="store_true", help="skip the oracle comparison on the corner block")
     ap.add_argument("--no-graph", action="store_true", help="skip the replay of the recorded step")
     ap.add_argument("--tune", action="store_true", help="run the autotuner first (a handle per candidate)")
+    ap.add_argument("--no-mean", action="store_true", help="skip the Mean post-processing measurement")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="subdomains in the oracle's timed sample")
     ap.add_argument("--copy-calibration", type=float, default=None, metavar="MB",
                     help="only run a device copy of this many MB (counter calibration) and exit")
@@ -385,7 +427,8 @@ def main():
     pb = case.problem
     log(f"workload {WORKLOAD}: inputs in {time.perf_counter() - t:.1f} s; steps {args.steps}, warmup {args.warmup}")
     prec = 1 if args.precision == "fp32ir" else 0
-    res = run_gpu(case, prec, args.steps, args.warmup, args.refine, graph=not args.no_graph, tune=args.tune)
+    res = run_gpu(case, prec, args.steps, args.warmup, args.refine, graph=not args.no_graph, tune=args.tune,
+                  mean=not args.no_mean)
     info = res["info"]
     log(f"{args.precision}: ms/step {res['ms_step']:.1f}; stages " +
         ", ".join(f"{k} {v['ms_per_step']:.1f}" for k, v in res["stages"].items()))
@@ -448,6 +491,7 @@ def main():
         "roofline_factor": roofline_factor(res, prec),
         "roofline_interface": roofline_interface(res),
         "cpu_baseline": cpu,
+        "mean_postprocess": res["mean"],
     }
     if secondary is not None:
         line["other_precision"] = _form_line(secondary, info.n_mbfs, pb.n, 1 - prec,

@@ -353,6 +353,37 @@ mrcm_status mrcm_reconstruct(const mrcm_mbfs *mbfs, const double *X, void *strea
                              double *p, double *U);
 
 /*
+ * The "Mean" post-processing of a multiscale velocity (Sec. 6, eq.
+ * (locprob_submean)), which makes it conservative cell by cell for a
+ * transport step.  On every fine face of Gamma between cells c and n the
+ * normal velocity becomes the mean of the two sides' values, outward from c
+ * (U[f][c] - U[f^1][n]) / 2.  Each subdomain then solves its Neumann problem:
+ * the TPFA operator of (2.10) on its own cell pairs, the source q, and as
+ * boundary data those Gamma velocities and, on the domain walls, U itself.
+ * The problem fixes the pressure only up to a constant: the subdomain's
+ * lowest-corner cell is set to zero (its row becomes the identity; the
+ * multiscale solution's weak flux continuity leaves that row's balance with a
+ * defect at the rounding of the interface solve).  Output: pt, the Neumann
+ * pressures in that gauge, and Ut, the velocity from pt on faces inside a
+ * subdomain and from the data on Gamma and the walls.
+ * Arithmetic: the FP64 band Cholesky of the Jacobi-scaled local matrices and
+ * one FP64 refinement sweep, whatever the handle's precision; the factors go
+ * to a scratch of at most 8 GiB (less when the environment variable
+ * MRCM_MEAN_SCRATCH_BYTES, read at the first call on a handle, asks for less)
+ * that holds a chunk of subdomains at a time.  The chunking does not change
+ * the result.
+ * U [dev] 6*N face-major (the layout mrcm_reconstruct writes); pt [dev] N;
+ * Ut [dev] 6*N, which must not overlap U.  The build's permeability and
+ * source arrays must still be valid.  The first call allocates 64 bytes per
+ * cell and the scratch, kept until mrcm_mbfs_destroy, and is not allowed
+ * under graph capture.  Synchronises the stream (it reads the factor's
+ * status).  Returns MRCM_EUNSUPPORTED when the largest subdomain's band
+ * exceeds 112, MRCM_ENOTSPD on a non-positive pivot.
+ */
+mrcm_status mrcm_postprocess_mean(const mrcm_mbfs *mbfs, const double *U, void *stream, double *pt,
+                                  double *Ut);
+
+/*
  * Sizes and counts of a built handle.  n_patch counts the patches of the
  * interface space (each carries two unknowns, so 2 n_patch is the interface
  * system's size, the N_Gamma of eq. (2.24) for one patch per interface);
@@ -412,12 +443,13 @@ mrcm_status mrcm_copy_interface(const mrcm_interface *iface, double *A, double *
  * subdomains it left (factor and solve stages stay empty).  'solve_rest' is
  * the single launch of group 1's first solve, inside 'refine'.  Interface
  * stages: 'assemble' the scatter into the fronts (band form: into the band),
- * 'lu' the factorisation, 'sweep' the solves and refinement steps.
+ * 'lu' the factorisation, 'sweep' the solves and refinement steps.  'mean'
+ * is the whole of mrcm_postprocess_mean.
  */
 enum { MRCM_STAGE_COEF = 0, MRCM_STAGE_FACTOR, MRCM_STAGE_RHS, MRCM_STAGE_SOLVE,
        MRCM_STAGE_RESIDUAL, MRCM_STAGE_REFINE, MRCM_STAGE_FLUX, MRCM_STAGE_ASSEMBLE,
        MRCM_STAGE_LU, MRCM_STAGE_SWEEP, MRCM_STAGE_RECONSTRUCT, MRCM_STAGE_PCG,
-       MRCM_STAGE_FALLBACK, MRCM_STAGE_SOLVE_REST, MRCM_STAGE_COUNT };
+       MRCM_STAGE_FALLBACK, MRCM_STAGE_SOLVE_REST, MRCM_STAGE_MEAN, MRCM_STAGE_COUNT };
 typedef struct {
   double ms[16];        /* accumulated milliseconds per stage */
   int64_t count[16];    /* occurrences per stage */

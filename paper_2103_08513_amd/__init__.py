@@ -2,8 +2,8 @@
 
 Python binding of the C ABI in ``include/mrcm.h``: it marshals torch device
 tensors (FP64, contiguous) and the current HIP stream into the library calls
-``mrcm_build_mbfs``, ``mrcm_assemble_interface``, ``mrcm_solve_interface``
-and ``mrcm_reconstruct``.  Every step of the method runs in the library's
+``mrcm_build_mbfs``, ``mrcm_assemble_interface``, ``mrcm_solve_interface``,
+``mrcm_reconstruct`` and ``mrcm_postprocess_mean``.  Every step of the method runs in the library's
 kernels; importing this package does not need a GPU, but every call does.
 """
 from __future__ import annotations
@@ -37,7 +37,7 @@ IFACE_MULTIFRONTAL = 2
 __all__ = ["MRCM", "MRCMError", "FP64", "FP32_IR", "PCG", "IFACE_AUTO", "IFACE_BAND", "IFACE_MULTIFRONTAL",
            "BETA_PER_SIDE", "BETA_FACE", "KEEP_FACTORS", "KEEP_MBFS",
            "build_mbfs", "assemble_interface",
-           "solve_interface", "reconstruct", "library"]
+           "solve_interface", "reconstruct", "postprocess_mean", "library"]
 
 
 def library():
@@ -258,6 +258,20 @@ class MRCM:
         _lib.check(code, "mrcm_reconstruct")
         return p, U.view(6, N)
 
+    def postprocess_mean(self, U, pt=None, Ut=None, stream=None):
+        """The Mean post-processing of a velocity U[6][N] (mrcm_postprocess_mean):
+        returns (pt[N], Ut[6][N])."""
+        import torch
+        N = self.n_cells
+        if pt is None:
+            pt = torch.empty(N, dtype=torch.float64, device=self.device)
+        if Ut is None:
+            Ut = torch.empty(6 * N, dtype=torch.float64, device=self.device)
+        code = self.lib.mrcm_postprocess_mean(self._mbfs, _dev_ptr(U, "U", 6 * N, self.device), _stream_ptr(stream),
+                                              _dev_ptr(pt, "pt", N, self.device), _dev_ptr(Ut, "Ut", 6 * N, self.device))
+        _lib.check(code, "mrcm_postprocess_mean")
+        return pt, Ut.view(6, N)
+
     def solve(self, kx, ky, kz, q, refine=0, stream=None, method=IFACE_AUTO):
         """Whole MRCM: MBFs, interface assembly and solve, reconstruction."""
         self.build_mbfs(kx, ky, kz, q, stream)
@@ -422,3 +436,7 @@ def solve_interface(model: MRCM, refine=0, stream=None, method=IFACE_AUTO, rtol=
 
 def reconstruct(model: MRCM, X, stream=None):
     return model.reconstruct(X, stream=stream)
+
+
+def postprocess_mean(model: MRCM, U, stream=None):
+    return model.postprocess_mean(U, stream=stream)

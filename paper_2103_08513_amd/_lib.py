@@ -15,7 +15,7 @@ STATUS = {0: "MRCM_OK", -1: "MRCM_EINVAL", -2: "MRCM_ENOMEM", -3: "MRCM_ENOTSPD"
 EXPORTS = [
     "mrcm_build_mbfs", "mrcm_assemble_interface", "mrcm_solve_interface", "mrcm_reconstruct",
     "mrcm_query", "mrcm_get_subdomain", "mrcm_copy_mbfs", "mrcm_copy_flux", "mrcm_copy_factor",
-    "mrcm_interface_dims", "mrcm_copy_interface", "mrcm_interface_query", "mrcm_mbfs_destroy", "mrcm_interface_destroy",
+    "mrcm_interface_dims", "mrcm_copy_interface", "mrcm_interface_query", "mrcm_postprocess_mean", "mrcm_mbfs_destroy", "mrcm_interface_destroy",
     "mrcm_status_string", "mrcm_last_error", "mrcm_profile_enable", "mrcm_profile_reset",
     "mrcm_profile_get", "mrcm_autotune", "mrcm_autotune_cached", "mrcm_graph_capture", "mrcm_graph_launch", "mrcm_graph_check", "mrcm_graph_destroy",
     # mrcm_nn.h
@@ -27,7 +27,7 @@ EXPORTS = [
 ]
 
 STAGES = ["coef", "factor", "rhs", "solve", "residual", "refine", "flux", "assemble", "lu", "sweep",
-          "reconstruct", "pcg", "fallback", "solve_rest"]
+          "reconstruct", "pcg", "fallback", "solve_rest", "mean"]
 
 
 class CProblem(ctypes.Structure):
@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
                                   P(c_double)], c_int32),
         "mrcm_interface_query": ([c_void_p, P(CIfaceInfo)], c_int32),
         "mrcm_reconstruct": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
+        "mrcm_postprocess_mean": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
         "mrcm_query": ([c_void_p, P(CInfo)], c_int32),
         "mrcm_get_subdomain": ([c_void_p, c_int32, P(CSubInfo)], c_int32),
         "mrcm_copy_mbfs": ([c_void_p, c_int32, c_void_p], c_int32),

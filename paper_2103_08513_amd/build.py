@@ -56,7 +56,9 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
         if verbose and text.strip():
             sys.stderr.write(_filter_warnings(text))
     tmp = LIB + ".tmp"
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    # export the C ABI only (mrcm_*), nothing of the library's internals
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC",
+           "-Wl,--version-script=" + os.path.join(CSRC, "exports.map"), "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <string>
@@ -583,6 +584,15 @@ struct mrcm_mbfs {
   SubDesc *d_sub_rs = nullptr;
   int4 *d_work_rs = nullptr;
   double *Brs = nullptr, *Xrs = nullptr, *Rrs = nullptr;
+  // Mean post-processing, set up on its first use: descriptors of one column
+  // per subdomain whose factor offsets are relative to the start of their
+  // chunk, the factor order cut into chunks that fit the factor scratch
+  // (mean_chunk holds the boundaries), the Neumann coefficients and vectors
+  SubDesc *d_sub_mean = nullptr;
+  int *d_order_mean = nullptr;
+  int4 *d_work_mean = nullptr;
+  std::vector<int> mean_chunk;
+  double *mcoef = nullptr, *mscal = nullptr, *mB = nullptr, *mX = nullptr, *mR = nullptr, *mfac = nullptr;
   double *coef = nullptr, *r0 = nullptr, *scal = nullptr;
   void *L = nullptr, *Dinv = nullptr;
   double *X = nullptr, *R = nullptr;
@@ -631,7 +641,8 @@ void free_mbfs(mrcm_mbfs *h) {
                   h->d_subof[2], h->coef, h->r0, h->scal, h->L, h->Dinv, h->X, h->R, h->R0, h->F, h->Fb, h->SAb,
                   h->norms, h->scalar, h->st, h->d_grp_subs[0], h->d_grp_subs[1], h->d_order_split,
                   h->d_colsub, h->d_iters, h->d_conv, h->d_fb_order, h->d_fb_work, h->d_nn_sel, h->d_nn_s0,
-                  h->d_sub_rs, h->d_work_rs, h->Brs, h->Xrs, h->Rrs, h->d_queue};
+                  h->d_sub_rs, h->d_work_rs, h->Brs, h->Xrs, h->Rrs, h->d_queue, h->d_sub_mean,
+                  h->d_order_mean, h->d_work_mean, h->mcoef, h->mscal, h->mB, h->mX, h->mR, h->mfac};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
@@ -1407,7 +1418,108 @@ mrcm_status reconstruct_resolve(const mrcm_mbfs *cmb, const double *X, hipStream
   return MRCM_OK;
 }
 
+// Largest factor scratch of the Mean post-processing: the subdomains are
+// factored in chunks whose factors fit it.
+constexpr int64_t kMeanScratchBytes = 8LL << 30;
+
+int64_t round_up256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+mrcm_status init_mean(mrcm_mbfs *mb) {
+  const HostGeom &G = mb->G;
+  std::vector<SubDesc> ms(G.subs);
+  int64_t total = 0, largest = 0;
+  auto need = [](const SubDesc &S) {
+    return round_up256((int64_t)S.N * (S.b + 1)) + round_up256((int64_t)((S.N + kNB - 1) / kNB) * kNB * kNB);
+  };
+  for (const SubDesc &S : ms) {
+    total += need(S);
+    largest = std::max(largest, need(S));
+  }
+  // the scratch: the whole factor when it is small, else the cap (the
+  // environment's MRCM_MEAN_SCRATCH_BYTES when set), halved while the
+  // allocation fails, down to one subdomain's factor
+  int64_t cap_bytes = kMeanScratchBytes;
+  if (const char *e = getenv("MRCM_MEAN_SCRATCH_BYTES")) {
+    const long long v = atoll(e);
+    if (v > 0) cap_bytes = std::min<int64_t>(v, kMeanScratchBytes);
+  }
+  int64_t cap = std::max(largest, std::min(total, cap_bytes / 8));
+  while (dev_alloc(&mb->mfac, (size_t)cap) != hipSuccess) {
+    (void)hipGetLastError();
+    if (cap == largest) return fail(MRCM_ENOMEM, "device allocation of the Mean factor scratch failed");
+    cap = std::max(largest, cap / 2);
+  }
+  std::vector<int> order;
+  std::vector<int4> work;
+  mb->mean_chunk.assign(1, 0);
+  int64_t off = 0;
+  for (int l : G.order) {
+    SubDesc &S = ms[l];
+    if (off + need(S) > cap) {
+      mb->mean_chunk.push_back((int)order.size());
+      off = 0;
+    }
+    S.m = 1;
+    S.X_off = S.cell_off;
+    S.pin_local = 0;
+    S.L_off = off;
+    S.D_off = off + round_up256((int64_t)S.N * (S.b + 1));
+    off += need(S);
+    order.push_back(l);
+    work.push_back(make_int4(l, 0, 1, 0));
+  }
+  mb->mean_chunk.push_back((int)order.size());
+  HIP_TRY(upload(&mb->d_sub_mean, ms));
+  HIP_TRY(upload(&mb->d_order_mean, order));
+  HIP_TRY(upload(&mb->d_work_mean, work));
+  const int64_t n = G.totCells;
+  if (dev_alloc(&mb->mcoef, (size_t)(4 * n)) != hipSuccess || dev_alloc(&mb->mscal, (size_t)n) != hipSuccess ||
+      dev_alloc(&mb->mB, (size_t)n) != hipSuccess || dev_alloc(&mb->mX, (size_t)n) != hipSuccess ||
+      dev_alloc(&mb->mR, (size_t)n) != hipSuccess)
+    return fail(MRCM_ENOMEM, "device allocation of the Mean coefficients failed");
+  mb->bytes += 8 * (8 * n + cap) + (int64_t)(sizeof(SubDesc) + 4 + sizeof(int4)) * (int64_t)ms.size();
+  return MRCM_OK;
+}
+
 }  // namespace
+
+mrcm_status mrcm_postprocess_mean(const mrcm_mbfs *cmb, const double *U, void *stream, double *pt, double *Ut) {
+  if (!cmb || !U || !pt || !Ut) return fail(MRCM_EINVAL, "null argument");
+  mrcm_mbfs *mb = const_cast<mrcm_mbfs *>(cmb);  // lazily allocated Mean buffers
+  const HostGeom &G = mb->G;
+  if (G.bmax > kMaxBand64)
+    return fail(MRCM_EUNSUPPORTED, "the Mean post-processing factors in FP64, whose band limit is 112");
+  hipStream_t s = (hipStream_t)stream;
+  if (!mb->d_sub_mean) {
+    if (g_capturing) return fail(MRCM_EUNSUPPORTED, "the Mean post-processing allocates on its first use: not under capture");
+    const mrcm_status st = init_mean(mb);
+    if (st != MRCM_OK) return st;
+  }
+  Geom gm = mb->g;
+  gm.sub = mb->d_sub_mean;
+  {
+    Stage t(MRCM_STAGE_MEAN, s);
+    HIP_TRY(launch_reset_status(mb->st, s));
+    HIP_TRY(launch_mean_coef(gm, mb->n_sub, G.max_cells, U, mb->mcoef, mb->mB, mb->mX, mb->mscal, s));
+    for (size_t k = 0; k + 1 < mb->mean_chunk.size(); ++k) {
+      const int c0 = mb->mean_chunk[k], nc = mb->mean_chunk[k + 1] - c0;
+      HIP_TRY(launch_factor(0, mb->d_sub_mean, mb->d_order_mean + c0, nc, mb->mcoef, mb->mscal, mb->mfac, mb->mfac,
+                            mb->st, G.bmax, s));
+      HIP_TRY(launch_solve(0, gm, mb->d_work_mean + c0, nc, mb->mscal, mb->mfac, mb->mfac, mb->mX, mb->mX, 0, G.bmax,
+                           s));
+      // one FP64 refinement sweep: residual from the kept right-hand side,
+      // then the correction
+      HIP_TRY(launch_solve(0, gm, mb->d_work_mean + c0, nc, mb->mscal, mb->mfac, mb->mfac, mb->mR, mb->mX, 1,
+                           G.bmax, s, mb->mcoef, mb->mB));
+    }
+    HIP_TRY(launch_mean_velocity(gm, U, mb->mX, pt, Ut, s));
+  }
+  if (g_prof.on && !g_capturing) {
+    HIP_TRY(hipStreamSynchronize(s));
+    profile_flush();
+  }
+  return read_status(mb->st, s, "mrcm_postprocess_mean");
+}
 
 mrcm_status mrcm_reconstruct(const mrcm_mbfs *mb, const double *X, void *stream, double *p,
                              double *U) {

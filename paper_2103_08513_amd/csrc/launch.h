@@ -51,6 +51,14 @@ hipError_t launch_resolve_residual(const Geom &g, int n_sub, int max_cells, cons
 hipError_t launch_resolve_scatter(const Geom &g, int n_sub, int max_cells, const double *X, double *p,
                                   hipStream_t s);
 
+// Mean post-processing: the per-subdomain Neumann coefficients and
+// right-hand side (B, and a copy in X for the in-place solve) from the
+// multiscale velocity U, and the post-processed pressure and velocity.
+hipError_t launch_mean_coef(const Geom &g, int n_sub, int max_cells, const double *U, double *coef, double *B,
+                            double *X, double *scal, hipStream_t s);
+hipError_t launch_mean_velocity(const Geom &g, const double *U, const double *P, double *pt, double *Ut,
+                                hipStream_t s);
+
 // Conjugate-gradient form of the local solves (pcg_kernels.hip).  One
 // workgroup per column (subdomain by col_sub); X0 null for a zero start.
 int pcg_max_cells();

@@ -1417,6 +1417,105 @@ __global__ void k_resolve_scatter(Geom g, const double *__restrict__ X, double *
   p[cell_index(g, local_to_global(S, r))] = X[S.cell_off + r];
 }
 
+// ---------------------------------------------------------------------------
+// "Mean" post-processing of the multiscale velocity (Sec. 6, eq.
+// (locprob_submean)): one Neumann problem per subdomain with a unique normal
+// velocity on Gamma, the mean of the two sides' values.  Outward from cell c
+// across face f towards cell n the unique value is (U[f][c] - U[f^1][n]) / 2;
+// on the walls the multiscale velocity U[f][c] itself is the data.  The
+// subdomain's lowest-corner cell (local row 0) is fixed at zero: its row is
+// the identity, its column is removed, its neighbours keep their diagonals.
+// ---------------------------------------------------------------------------
+__global__ void k_mean_coef(Geom g, const double *__restrict__ U, double *__restrict__ coef,
+                            double *__restrict__ B, double *__restrict__ X, double *__restrict__ scal) {
+  const SubDesc &S = g.sub[blockIdx.y];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= S.N) return;
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  const I3 x = local_to_global(S, r);
+  const long long c = cell_index(g, x);
+  const double kc0 = g.k[0][c], kc1 = g.k[1][c], kc2 = g.k[2][c];
+  const int a0 = S.ax[0], a1 = S.ax[1];
+  double diag = 0.0, rhs = g.q[c];
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1;
+    const int side = (f & 1) ? 1 : -1;
+    const double kd = d == 0 ? kc0 : (d == 1 ? kc1 : kc2);
+    const int xn = x[d] + side;
+    const double hd = hdir(g, d), ad = adir(g, d);
+    I3 y = x;
+    y.set(d, xn);
+    if (xn >= S.lo[d] && xn < S.lo[d] + S.ext[d]) {
+      const double kn = kdir(g, d)[cell_index(g, y)];
+      const double T = ad * (2.0 * kd * kn / (kd + kn)) / hd;
+      diag += T;
+      if (side > 0) {
+        const int p = (d == a0) ? 0 : ((d == a1) ? 1 : 2);
+        t0 = (p == 0) ? T : t0;
+        t1 = (p == 1) ? T : t1;
+        t2 = (p == 2) ? T : t2;
+      }
+    } else if (xn >= 0 && xn < ndir(g, d)) {
+      rhs -= ad * 0.5 * (U[f * N + c] - U[(f ^ 1) * N + cell_index(g, y)]);
+    } else {
+      rhs -= ad * U[f * N + c];
+    }
+  }
+  if (r == 0) {
+    diag = 1.0;
+    t0 = t1 = t2 = 0.0;
+    rhs = 0.0;
+  }
+  const long long o = S.cell_off + r;
+  coef[4 * o + 0] = diag;
+  coef[4 * o + 1] = t0;
+  coef[4 * o + 2] = t1;
+  coef[4 * o + 3] = t2;
+  B[o] = rhs;
+  X[o] = rhs;
+  scal[o] = 1.0 / sqrt(diag);
+}
+
+// The post-processed pressure pt and velocity Ut per global cell: faces
+// inside the cell's subdomain from the Neumann solution P (per subdomain, at
+// its cell offset), Gamma faces from the two sides' mean, walls from U.
+__global__ void k_mean_velocity(Geom g, const double *__restrict__ U, const double *__restrict__ P,
+                                double *__restrict__ pt, double *__restrict__ Ut) {
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  I3 x;
+  x.v0 = (int)(c % g.nx);
+  x.v1 = (int)((c / g.nx) % g.ny);
+  x.v2 = (int)(c / ((long long)g.nx * g.ny));
+  const int l = g.sub_of[0][x.v0] + g.nd[0] * (g.sub_of[1][x.v1] + g.nd[1] * g.sub_of[2][x.v2]);
+  const SubDesc &S = g.sub[l];
+  const double *Pl = P + S.cell_off;
+  const double pc = Pl[local_row(S, x)];
+  pt[c] = pc;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1;
+    const int side = (f & 1) ? 1 : -1;
+    const int xn = x[d] + side;
+    I3 y = x;
+    y.set(d, xn);
+    double u;
+    if (xn >= S.lo[d] && xn < S.lo[d] + S.ext[d]) {
+      const double *karr = kdir(g, d);
+      const double kd = karr[c], kn = karr[cell_index(g, y)];
+      u = (2.0 * kd * kn / (kd + kn)) * (pc - Pl[local_row(S, y)]) / hdir(g, d);
+    } else if (xn >= 0 && xn < ndir(g, d)) {
+      u = 0.5 * (U[f * N + c] - U[(f ^ 1) * N + cell_index(g, y)]);
+    } else {
+      u = U[f * N + c];
+    }
+    Ut[f * N + c] = u;
+  }
+}
+
 }  // namespace mrcm
 
 // ---------------------------------------------------------------------------
@@ -1676,6 +1775,20 @@ hipError_t launch_resolve_scatter(const Geom &g, int n_sub, int max_cells, const
                                   hipStream_t s) {
   dim3 grid((max_cells + 255) / 256, n_sub);
   hipLaunchKernelGGL(k_resolve_scatter, grid, dim3(256), 0, s, g, X, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean_coef(const Geom &g, int n_sub, int max_cells, const double *U, double *coef, double *B,
+                            double *X, double *scal, hipStream_t s) {
+  dim3 grid((max_cells + 255) / 256, n_sub);
+  hipLaunchKernelGGL(k_mean_coef, grid, dim3(256), 0, s, g, U, coef, B, X, scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean_velocity(const Geom &g, const double *U, const double *P, double *pt, double *Ut,
+                                hipStream_t s) {
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL(k_mean_velocity, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g, U, P, pt, Ut);
   return hipGetLastError();
 }
 

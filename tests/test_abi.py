@@ -34,6 +34,21 @@ def test_library_exports_every_declared_symbol():
     assert sorted(_lib.EXPORTS) == _declared_functions()
 
 
+def test_library_exports_nothing_but_the_declared_abi():
+    """The dynamic symbol table holds the declared entry points and no
+    internal symbol (launchers, kernel stubs, host helpers)."""
+    import shutil
+    import subprocess
+    from paper_2103_08513_amd import _lib
+    nm = shutil.which("nm") or shutil.which("llvm-nm")
+    if nm is None:
+        pytest.skip("no nm on this host")
+    out = subprocess.run([nm, "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    names = sorted(ln.split()[-1] for ln in out.splitlines() if ln.strip())
+    assert names == _declared_functions()
+
+
 def test_status_strings_without_gpu():
     from paper_2103_08513_amd import _lib
     lib = _lib.load()
