@@ -987,7 +987,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
   const double *rhs0 = own_res && fp32 ? h->R0 : nullptr;
   {
     Stage t(MRCM_STAGE_RHS, s);
-    ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, pcg ? h->R : h->X, s,
+    ENQ(launch_rhs(g, h->n_sub, H.max_cells, H.mmax, h->r0, pcg ? h->R : h->X, s,
                    own_res ? (fp32 ? h->R0 : h->R) : nullptr));
   }
   if (pcg) {
@@ -1140,7 +1140,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
         std::vector<int> its(H.totCols);
         {
           Stage t(MRCM_STAGE_PCG, s);
-          ENQ(launch_rhs(g, h->n_sub, H.max_cells, h->r0, h->R, s));
+          ENQ(launch_rhs(g, h->n_sub, H.max_cells, H.mmax, h->r0, h->R, s));
           ENQ(launch_pcg(g, h->d_colsub, H.totCols, H.max_cells, h->coef, h->scal, h->R, h->X, h->X, 1000,
                          h->ir_tol, 0, h->d_iters, h->d_conv, s));
           ENQ(hipMemcpyAsync(its.data(), h->d_iters, its.size() * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -2146,7 +2146,7 @@ mrcm_status mrcm_nn_features(mrcm_mbfs *h, const int32_t *subs, int32_t n_subs, 
   }
   // the right-hand sides of the current build, formed once for all calls
   if (!h->nn_rhs_ready) {
-    HIP_TRY(launch_rhs(h->g, h->n_sub, H.max_cells, h->r0, h->R, s));
+    HIP_TRY(launch_rhs(h->g, h->n_sub, H.max_cells, H.mmax, h->r0, h->R, s));
     h->nn_rhs_ready = true;
   }
   HIP_TRY(launch_nn_features(h->g, h->d_nn_sel, h->d_nn_s0, n_subs, mmax, h->R, h->X, V, inp, tgt, s));

@@ -25,7 +25,8 @@ hipError_t launch_solve(int fp32, const Geom &g, const int4 *work, int n_work, c
                         hipStream_t s, const double *coef = nullptr, const double *rhs0 = nullptr,
                         int *queue = nullptr);
 // B2: a second copy of the right-hand sides, or null
-hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, const double *r0, double *B,
+// mmax: the largest column count m over the subdomains
+hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, int mmax, const double *r0, double *B,
                       hipStream_t s, double *B2 = nullptr);
 int solve_chunk_max();
 size_t factor_lds_bytes(int fp32, int bmax);

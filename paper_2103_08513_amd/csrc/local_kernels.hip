@@ -131,7 +131,7 @@ __device__ __forceinline__ void rhs_row_faces(const Geom &g, const SubDesc &S, i
 // Right-hand sides of rows rbase .. rbase + kRowsPB - 1 of subdomain S into
 // the LDS tile (row-major, stride m): one thread per row finds the row's
 // Robin entries once, the rest of the tile is zero.  Ends with a barrier.
-constexpr int kRowsPB = 32;
+constexpr int kRowsPB = 64;
 
 __device__ __forceinline__ void rhs_tile(const Geom &g, const SubDesc &S, const double *__restrict__ r0,
                                          int rbase, double *tile) {
@@ -148,10 +148,13 @@ __device__ __forceinline__ void rhs_tile(const Geom &g, const SubDesc &S, const 
 }
 
 // Dense right-hand sides R (row-major, N_l x m_l) of every subdomain,
-// kRowsPB rows per workgroup, written out as one contiguous run.
+// kRowsPB rows per workgroup, written out as one contiguous run.  The tile
+// (kRowsPB rows of the largest column count, in dynamic LDS) is sized to the
+// launch, so that small column counts leave room for more workgroups per CU
+// to cover the latency of the coefficient loads.
 __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ r0,
                                              double *__restrict__ B, double *__restrict__ B2) {
-  __shared__ double tile[kRowsPB * kMaxRhs];
+  extern __shared__ double tile[];
   const SubDesc &S = g.sub[blockIdx.y];
   const int rbase = blockIdx.x * kRowsPB;
   if (rbase >= S.N) return;
@@ -1730,10 +1733,11 @@ int solve_blocks_per_cu(int fp32, int bmax) {
   return nb;
 }
 
-hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, const double *r0, double *B,
+hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, int mmax, const double *r0, double *B,
                       hipStream_t s, double *B2) {
   dim3 grid((unsigned)((max_cells + kRowsPB - 1) / kRowsPB), n_sub);
-  hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, g, r0, B, B2);
+  const size_t lds = (size_t)kRowsPB * mmax * sizeof(double);
+  hipLaunchKernelGGL(k_rhs, grid, dim3(256), lds, s, g, r0, B, B2);
   return hipGetLastError();
 }
 
