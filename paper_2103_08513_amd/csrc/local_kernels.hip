@@ -855,7 +855,10 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
                                            const double *rhs0, unsigned char *smem_raw) {
   using M = Mma<T>;
   using v4 = typename M::v4;
-  constexpr int kLPer = (kNB * (16 * NRT + 1) + kBsThreads - 1) / kBsThreads;  // L entries per thread
+  // a staged panel of L is read by column: kPThr threads per column, each
+  // taking rows prow + kPThr j, j < kLPer
+  constexpr int kPThr = kBsThreads / kNB;
+  constexpr int kLPer = (16 * NRT + 1 + kPThr - 1) / kPThr;
   // LDS column length of a staged panel: every offset a product reads,
   // 1 .. 16 NRT + 15, lies inside the column, and those past b hold zeros,
   // so that the A operands are read without masks
@@ -897,26 +900,22 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
   double *Xv = Xo + c0 + (vwave ? 16 * nct : 0);
 
   // the next panel of L and of the inverses, loaded without arithmetic or
-  // branches on the loaded values (masks are applied when they are stored)
+  // branches on the loaded values (masks are applied when they are stored);
+  // this thread's entries are rows prow + kPThr j of column pcol, so that
+  // their LDS positions follow from one base
   T lreg[kLPer], dreg[2];
   unsigned lok = 0u;
-  // LDS position of this thread's entries e = tid + 192 j of a panel
-  int ldst[kLPer];
-#pragma unroll
-  for (int j = 0; j < kLPer; ++j) {
-    const int e = tid + kBsThreads * j, col = e / bp1;
-    ldst[j] = col * kLdl + (e - col * bp1);
-  }
+  const int pcol = tid / kPThr, prow = tid - pcol * kPThr;
+  const int lsrc0 = pcol * bp1 + prow, ldst0 = pcol * kLdl + prow;
   for (int e = tid; e < 2 * kLBuf; e += kBsThreads) Lb[e] = T(0);
   auto fetch_panel = [&](int p) {
     const T *src = L + (size_t)p * lsz;
-    const int lim = min(kNB, N - p * kNB) * bp1;  // columns past the last row stay zero
+    const bool colv = pcol < N - p * kNB;  // columns past the last row stay zero
     lok = 0u;
 #pragma unroll
     for (int j = 0; j < kLPer; ++j) {
-      const int e = tid + kBsThreads * j;
-      const bool ok = e < lim;
-      lreg[j] = src[ok ? e : 0];
+      const bool ok = colv && prow + kPThr * j < bp1;
+      lreg[j] = src[ok ? lsrc0 + kPThr * j : 0];
       lok |= ok ? (1u << j) : 0u;
     }
     const T *dsrc = Dinv + (size_t)p * kNB * kNB;
@@ -927,8 +926,7 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
     T *lp = Lb + buf * kLBuf;
 #pragma unroll
     for (int j = 0; j < kLPer; ++j) {
-      const int e = tid + kBsThreads * j;
-      if (e < lsz) lp[ldst[j]] = ((lok >> j) & 1u) ? lreg[j] : T(0);
+      if (prow + kPThr * j < bp1) lp[ldst0 + kPThr * j] = ((lok >> j) & 1u) ? lreg[j] : T(0);
     }
     T *dp = Db + buf * (kNB * kDStride);
     dp[(tid >> 4) * kDStride + (tid & 15)] = dreg[0];
@@ -993,7 +991,10 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
     const T *dp = Db + (p & 1) * (kNB * kDStride);
     const bool has_next = p + 1 < nP;
     __syncthreads();  // panel p staged; panel p - 1's buffer free
-    if (has_next) fetch_panel(p + 1);
+    // the next panel (the last panel loads itself again, unused): no branch,
+    // so that the counts of loads in flight stay known to the compiler and
+    // a wait for an older load does not wait for these
+    fetch_panel(has_next ? p + 1 : p);
     if (mwave) {
       // Y1 = inv(L11) R1 (two chains)
       v4 ya = {T(0), T(0), T(0), T(0)}, yb = ya;
@@ -1028,7 +1029,6 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
 #pragma unroll
       for (int i = 0; i < NRT; ++i) R[i] = R[i + 1];
       R[NRT] = rows_tile();
-      if (has_next) fetch_rows(k + kNB + 16 * (NRT + 1));
     }
     if (vwave) {
       const int i = lane & 15;
@@ -1057,8 +1057,13 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
       const T nv = __shfl(vnew, src, 64);
 #pragma unroll
       for (int j = 0; j < kWF; ++j) vw[j] = lane < 48 ? sh[j] : (j + 1 < kWF ? sh[j + 1] : nv);
-      if (has_next) fetch_vrow(k + kNB + 16 * (NRT + 1));
     }
+    // The rows entering after the next panel, loaded by every wave at every
+    // panel (past the end or outside the wave's columns the addresses clamp
+    // and the values go unused): outside any branch, the loads stay in flight
+    // across the next panel instead of being waited on where branches join.
+    fetch_rows(k + kNB + 16 * (NRT + 1));
+    fetch_vrow(k + kNB + 16 * (NRT + 1));
     if (has_next) store_panel((p + 1) & 1);
   }
 
@@ -1068,7 +1073,10 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
   v4 X[NRT];
 #pragma unroll
   for (int i = 0; i < NRT; ++i) X[i] = (v4){T(0), T(0), T(0), T(0)};
-  double yraw[4];
+  // the forward values of a panel, loaded a panel ahead; the rows' scaling
+  // and, for a correction, the current X, loaded at the start of the panel
+  // that stores them, so that no store waits on a load
+  double yraw[4], scur[4], xcur[4];
   unsigned yok = 0u;
   auto fetch_y = [&](int p) {
     yok = 0u;
@@ -1080,29 +1088,50 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
       yok |= ok ? (1u << v) : 0u;
     }
   };
+  auto fetch_sx = [&](int p) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = p * kNB + M::crow(v, lane);
+      const int rr = colok && r < N ? r : 0;
+      scur[v] = sc[rr];
+      xcur[v] = (mode & 1) ? Xc[(size_t)rr * m] : 0.0;
+    }
+  };
   // vector wave: window row (below the panel) lane + 64 j in vw[j]
 #pragma unroll
   for (int j = 0; j < (kWF > kWB ? kWF : kWB); ++j) vw[j] = T(0);
-  double vyraw = 0.0;
+  double vyraw = 0.0, vscur = 1.0, vxcur = 0.0;
   bool vyok = false;
   auto fetch_vy = [&](int p) {
     vyok = lane < kNB && p * kNB + lane < N;
     vyraw = Bv[(size_t)(vyok ? p * kNB + lane : 0) * m];
   };
-  if (mwave) fetch_y(nP - 1);
-  if (vwave) fetch_vy(nP - 1);
+  auto fetch_vsx = [&](int p) {
+    const int rr = lane < kNB && p * kNB + lane < N ? p * kNB + lane : 0;
+    vscur = sc[rr];
+    vxcur = (mode & 1) ? Xv[(size_t)rr * m] : 0.0;
+  };
+  fetch_y(nP - 1);
+  fetch_vy(nP - 1);
   for (int p = nP - 1; p >= 0; --p) {
     const int k = p * kNB, kb = min(kNB, N - k);
     const T *lp = Lb + (p & 1) * kLBuf;
     const T *dp = Db + (p & 1) * (kNB * kDStride);
     const bool has_prev = p > 0;
     if (p < nP - 1) __syncthreads();  // panel p staged
-    if (has_prev) fetch_panel(p - 1);
-    if (mwave) {
-      v4 z0, z1 = {T(0), T(0), T(0), T(0)};
+    fetch_panel(has_prev ? p - 1 : p);
+    // this panel's forward values (prefetched), then, by every wave outside
+    // any branch, the next panel's (panel 0 loads itself again at the end,
+    // unused) and this panel's scaling and current X
+    v4 z0, z1 = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int v = 0; v < 4; ++v) z0[v] = ((yok >> v) & 1u) ? T(yraw[v]) : T(0);
-      if (has_prev) fetch_y(p - 1);
+    for (int v = 0; v < 4; ++v) z0[v] = ((yok >> v) & 1u) ? T(yraw[v]) : T(0);
+    const T vycur = vyok ? T(vyraw) : T(0);
+    fetch_y(max(p - 1, 0));
+    fetch_vy(max(p - 1, 0));
+    fetch_sx(p);
+    fetch_vsx(p);
+    if (mwave) {
       // Z = Y1 - L21^T X2: tile ti, k-step s: A = L[k + 16 + 16 ti + crow(s, lane)][k + lr]
 #pragma unroll
       for (int ti = 0; ti < NRT; ++ti) {
@@ -1130,10 +1159,10 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
         const int row = M::crow(v, lane);
         x[v] = row < kb ? x[v] : T(0);
         if (colok && row < kb) {
-          const double s = scaled ? sc[k + row] : 1.0;
+          const double s = scaled ? scur[v] : 1.0;
           double *dst = Xc + (size_t)(k + row) * m;
           if ((mode & 1) == 0) *dst = s * (double)x[v];
-          else *dst += s * (double)x[v];
+          else *dst = xcur[v] + s * (double)x[v];
         }
       }
 #pragma unroll
@@ -1141,8 +1170,7 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
       X[0] = x;
     }
     if (vwave) {
-      const T ycur = vyok ? T(vyraw) : T(0);
-      if (has_prev) fetch_vy(p - 1);
+      const T ycur = vycur;
       // lanes (i, g): sum over the window rows t = g + 4 q of L[k+16+t][k+i] X2[t]
       const int i = lane & 15, gq = lane >> 4;
       T acc = T(0);
@@ -1164,10 +1192,10 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
       for (int j = 0; j < kNB; ++j) x += dp[j * kDStride + i] * __shfl(z, j, 64);
       if (i >= kb) x = T(0);
       if (lane < kb) {
-        const double s = scaled ? sc[k + lane] : 1.0;
+        const double s = scaled ? vscur : 1.0;
         double *dst = Xv + (size_t)(k + lane) * m;
         if ((mode & 1) == 0) *dst = s * (double)x;
-        else *dst += s * (double)x;
+        else *dst = vxcur + s * (double)x;
       }
       // the new rows enter at the start of the window: row t takes row t - 16
       const int src = (lane - 16) & 63;
