@@ -929,8 +929,12 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
       if (prow + kPThr * j < bp1) lp[ldst0 + kPThr * j] = ((lok >> j) & 1u) ? lreg[j] : T(0);
     }
     T *dp = Db + buf * (kNB * kDStride);
-    dp[(tid >> 4) * kDStride + (tid & 15)] = dreg[0];
-    const int e1 = tid + kBsThreads;
+    // the thread index made opaque, so that the two positions are formed
+    // here rather than held (and spilled) across the sweep
+    int t0 = tid;
+    asm volatile("" : "+v"(t0));
+    dp[(t0 >> 4) * kDStride + (t0 & 15)] = dreg[0];
+    const int e1 = t0 + kBsThreads;
     if (e1 < kNB * kNB) dp[(e1 >> 4) * kDStride + (e1 & 15)] = dreg[1];
   };
 
@@ -1073,10 +1077,11 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
   v4 X[NRT];
 #pragma unroll
   for (int i = 0; i < NRT; ++i) X[i] = (v4){T(0), T(0), T(0), T(0)};
-  // the forward values of a panel, loaded a panel ahead; the rows' scaling
-  // and, for a correction, the current X, loaded at the start of the panel
-  // that stores them, so that no store waits on a load
-  double yraw[4], scur[4], xcur[4];
+  // the forward values of a panel, loaded a panel ahead; the rows' scaling,
+  // loaded at the start of the panel that stores them, so that no store
+  // waits on a load (a correction adds to X with atomic adds, which return
+  // nothing: one lane owns each entry, so the sum is X + s x as written)
+  double yraw[4], scur[4];
   unsigned yok = 0u;
   auto fetch_y = [&](int p) {
     yok = 0u;
@@ -1092,25 +1097,19 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = p * kNB + M::crow(v, lane);
-      const int rr = colok && r < N ? r : 0;
-      scur[v] = sc[rr];
-      xcur[v] = (mode & 1) ? Xc[(size_t)rr * m] : 0.0;
+      scur[v] = sc[colok && r < N ? r : 0];
     }
   };
   // vector wave: window row (below the panel) lane + 64 j in vw[j]
 #pragma unroll
   for (int j = 0; j < (kWF > kWB ? kWF : kWB); ++j) vw[j] = T(0);
-  double vyraw = 0.0, vscur = 1.0, vxcur = 0.0;
+  double vyraw = 0.0, vscur = 1.0;
   bool vyok = false;
   auto fetch_vy = [&](int p) {
     vyok = lane < kNB && p * kNB + lane < N;
     vyraw = Bv[(size_t)(vyok ? p * kNB + lane : 0) * m];
   };
-  auto fetch_vsx = [&](int p) {
-    const int rr = lane < kNB && p * kNB + lane < N ? p * kNB + lane : 0;
-    vscur = sc[rr];
-    vxcur = (mode & 1) ? Xv[(size_t)rr * m] : 0.0;
-  };
+  auto fetch_vsx = [&](int p) { vscur = sc[lane < kNB && p * kNB + lane < N ? p * kNB + lane : 0]; };
   fetch_y(nP - 1);
   fetch_vy(nP - 1);
   for (int p = nP - 1; p >= 0; --p) {
@@ -1122,7 +1121,7 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
     fetch_panel(has_prev ? p - 1 : p);
     // this panel's forward values (prefetched), then, by every wave outside
     // any branch, the next panel's (panel 0 loads itself again at the end,
-    // unused) and this panel's scaling and current X
+    // unused) and this panel's scaling
     v4 z0, z1 = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int v = 0; v < 4; ++v) z0[v] = ((yok >> v) & 1u) ? T(yraw[v]) : T(0);
@@ -1162,7 +1161,7 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
           const double s = scaled ? scur[v] : 1.0;
           double *dst = Xc + (size_t)(k + row) * m;
           if ((mode & 1) == 0) *dst = s * (double)x[v];
-          else *dst = xcur[v] + s * (double)x[v];
+          else atomicAdd(dst, s * (double)x[v]);
         }
       }
 #pragma unroll
@@ -1195,7 +1194,7 @@ __device__ __forceinline__ void solve_item(const Geom &g, const int4 item, const
         const double s = scaled ? vscur : 1.0;
         double *dst = Xv + (size_t)(k + lane) * m;
         if ((mode & 1) == 0) *dst = s * (double)x;
-        else *dst = vxcur + s * (double)x;
+        else atomicAdd(dst, s * (double)x);
       }
       // the new rows enter at the start of the window: row t takes row t - 16
       const int src = (lane - 16) & 63;
