@@ -1027,7 +1027,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
                        s));
       // the FP64 refinement sweeps of the direct form, on the same subdomains
       for (int it = 0; it < h->refine64; ++it) {
-        ENQ(launch_residual(g, h->pcg_fallback, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s,
+        ENQ(launch_residual(g, h->pcg_fallback, H.max_cells, H.mmax, h->coef, h->r0, h->X, h->R, nullptr, s,
                             h->d_fb_order));
         ENQ(launch_solve(0, g, h->d_fb_work, (int)h->fb_work.size(), h->scal, h->L, h->Dinv, h->R, h->X, 1,
                          H.bmax, s));
@@ -1060,7 +1060,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     }
     for (int it = 0; it < nsweep; ++it) {
       if (!own_res)
-        ENQ(launch_residual(g, n0, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, h->s2, h->d_grp_subs[0]));
+        ENQ(launch_residual(g, n0, H.max_cells, H.mmax, h->coef, h->r0, h->X, h->R, nullptr, h->s2, h->d_grp_subs[0]));
       ENQ(launch_solve(fp32, g, h->d_work, h->n_first, h->scal, h->L, h->Dinv, h->R, h->X, 1, H.bmax, h->s2,
                        own_res ? h->coef : nullptr, rhs0, queue(1)));
     }
@@ -1075,7 +1075,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     }
     for (int it = 0; it < nsweep; ++it) {
       if (!own_res)
-        ENQ(launch_residual(g, n1s, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s, h->d_grp_subs[1]));
+        ENQ(launch_residual(g, n1s, H.max_cells, H.mmax, h->coef, h->r0, h->X, h->R, nullptr, s, h->d_grp_subs[1]));
       ENQ(launch_solve(fp32, g, w1, n1, h->scal, h->L, h->Dinv, h->R, h->X, 3, H.bmax, s,
                        own_res ? h->coef : nullptr, rhs0, queue(0)));
     }
@@ -1099,7 +1099,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
     for (int it = 0; it < h->refine64; ++it) {
       {
         Stage t(MRCM_STAGE_RESIDUAL, s);
-        ENQ(launch_residual(g, h->n_sub, H.max_cells, h->coef, h->r0, h->X, h->R, nullptr, s));
+        ENQ(launch_residual(g, h->n_sub, H.max_cells, H.mmax, h->coef, h->r0, h->X, h->R, nullptr, s));
       }
       Stage t(MRCM_STAGE_REFINE, s);
       ENQ(launch_solve(fp32, g, h->d_work, (int)H.work.size(), h->scal, h->L, h->Dinv, h->R, h->X,
@@ -1117,7 +1117,10 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       {
         Stage t(MRCM_STAGE_RESIDUAL, s);
         ENQ(launch_fill(h->norms, 3LL * H.totCols, 0.0, s));
-        ENQ(launch_residual(g, h->n_sub, H.max_cells, h->coef, h->r0, h->X, h->R, h->norms, s));
+        // with the pipelined sweeps a further sweep forms its own residual
+        // from the kept right-hand sides, so the check writes no residual
+        ENQ(launch_residual(g, h->n_sub, H.max_cells, H.mmax, h->coef, h->r0, h->X, own_res ? nullptr : h->R,
+                            h->norms, s));
         ENQ(launch_ir_check(h->norms, H.totCols, h->scalar, s));
       }
       // res: the largest relative residual of the columns still above the
@@ -1160,7 +1163,7 @@ mrcm_status mrcm_build_mbfs(const mrcm_problem *pb, const mrcm_partition *part,
       {
         Stage t(MRCM_STAGE_REFINE, s);
         ENQ(launch_solve(fp32, g, h->d_work, (int)H.work.size(), h->scal, h->L, h->Dinv, h->R, h->X,
-                         1, H.bmax, s));
+                         1, H.bmax, s, own_res ? h->coef : nullptr, own_res ? h->R0 : nullptr));
       }
     }
   }

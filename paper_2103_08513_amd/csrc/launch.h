@@ -32,7 +32,7 @@ int solve_chunk_max();
 size_t factor_lds_bytes(int fp32, int bmax);
 size_t solve_lds_bytes(int fp32, int bmax, int mmax);
 // subs: the subdomains to take (n_sub of them), or null for 0 .. n_sub-1
-hipError_t launch_residual(const Geom &g, int n_sub, int max_cells, const double *coef,
+hipError_t launch_residual(const Geom &g, int n_sub, int max_cells, int mmax, const double *coef,
                            const double *r0, const double *X, double *R, double *norms,
                            hipStream_t s, const int *subs = nullptr);
 int solve_blocks_per_cu(int fp32, int bmax);

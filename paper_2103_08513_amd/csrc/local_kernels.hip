@@ -1238,14 +1238,20 @@ __global__ __launch_bounds__(kBsThreads) __attribute__((amdgpu_waves_per_eu(3, 3
 // gamma_8 s_r (eight terms summed), gamma_8 = 8u / (1 - 8u) with the unit
 // roundoff u = 2^-53.
 // ---------------------------------------------------------------------------
+// Rbuf null: the norms only (a check whose next sweep forms its own residual).
+// Thread t of a workgroup takes column t mod m of rows t / m, t / m + T, ...
+// (T = 256 / m threads per column, the rest idle), so that its norms
+// accumulate in registers and only T partial sums per column meet in LDS;
+// consecutive threads read consecutive entries of a row.  The tile of the
+// right-hand sides and the column sums take (kRowsPB + 3) m doubles of dynamic
+// LDS, sized to the launch's largest m.
 __global__ __launch_bounds__(256) void k_residual(Geom g, const double *__restrict__ coef,
                                                   const double *__restrict__ r0,
                                                   const double *__restrict__ Xg,
                                                   double *__restrict__ Rbuf,
                                                   double *__restrict__ norms, int ntile, int n_sub,
                                                   const int *__restrict__ subs) {
-  __shared__ double tile[kRowsPB * kMaxRhs];
-  __shared__ double red[3 * kMaxRhs];
+  extern __shared__ double tile[];
   // XCD-aware order: workgroups go round-robin to the eight XCDs, so XCD x
   // gets subdomains x, x + 8, ... with all their row tiles in sequence, and
   // the stencil's neighbour rows come from that XCD's L2
@@ -1256,6 +1262,7 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, const double *__restri
   const int m = S.m, N = S.N;
   const int rbase = (slot % ntile) * kRowsPB;
   if (rbase >= N) return;
+  double *red = tile + kRowsPB * m;
   const bool acc_norms = norms != nullptr;
   if (acc_norms)
     for (int i = threadIdx.x; i < 3 * m; i += blockDim.x) red[i] = 0.0;
@@ -1263,32 +1270,39 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, const double *__restri
   const double *cf = coef + 4 * S.cell_off;
   const double *X = Xg + S.X_off;
   const int n0 = S.n0, b = S.b;
-  const int ne = min(kRowsPB, N - rbase) * m;
-  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-    const int r = rbase + e / m, c = e % m;
-    double t = cf[4 * r] * X[(size_t)r * m + c];
-    double ax = t, ab = fabs(t);
-    auto sub = [&](double v) {
-      ax -= v;
-      ab += fabs(v);
-    };
-    if (r + 1 < N) sub(cf[4 * r + 1] * X[(size_t)(r + 1) * m + c]);
-    if (r >= 1) sub(cf[4 * (r - 1) + 1] * X[(size_t)(r - 1) * m + c]);
-    if (r + n0 < N) sub(cf[4 * r + 2] * X[(size_t)(r + n0) * m + c]);
-    if (r >= n0) sub(cf[4 * (r - n0) + 2] * X[(size_t)(r - n0) * m + c]);
-    if (r + b < N) sub(cf[4 * r + 3] * X[(size_t)(r + b) * m + c]);
-    if (r >= b) sub(cf[4 * (r - b) + 3] * X[(size_t)(r - b) * m + c]);
-    const double rhs = tile[e];
-    const double res = rhs - ax;
-    Rbuf[S.X_off + (size_t)r * m + c] = res;
-    if (acc_norms) {
+  const int rows = min(kRowsPB, N - rbase);
+  const int tpc = blockDim.x / m, c = threadIdx.x % m, j0 = threadIdx.x / m;
+  double nr = 0.0, nR = 0.0, ns = 0.0;
+  if (j0 < tpc) {
+    for (int j = j0; j < rows; j += tpc) {
+      const int r = rbase + j;
+      double t = cf[4 * r] * X[(size_t)r * m + c];
+      double ax = t, ab = fabs(t);
+      auto sub = [&](double v) {
+        ax -= v;
+        ab += fabs(v);
+      };
+      if (r + 1 < N) sub(cf[4 * r + 1] * X[(size_t)(r + 1) * m + c]);
+      if (r >= 1) sub(cf[4 * (r - 1) + 1] * X[(size_t)(r - 1) * m + c]);
+      if (r + n0 < N) sub(cf[4 * r + 2] * X[(size_t)(r + n0) * m + c]);
+      if (r >= n0) sub(cf[4 * (r - n0) + 2] * X[(size_t)(r - n0) * m + c]);
+      if (r + b < N) sub(cf[4 * r + 3] * X[(size_t)(r + b) * m + c]);
+      if (r >= b) sub(cf[4 * (r - b) + 3] * X[(size_t)(r - b) * m + c]);
+      const double rhs = tile[j * m + c];
+      const double res = rhs - ax;
+      if (Rbuf) Rbuf[S.X_off + (size_t)r * m + c] = res;
       ab += fabs(rhs);
-      atomicAdd(&red[3 * c], res * res);
-      atomicAdd(&red[3 * c + 1], rhs * rhs);
-      atomicAdd(&red[3 * c + 2], ab * ab);
+      nr += res * res;
+      nR += rhs * rhs;
+      ns += ab * ab;
     }
   }
   if (!acc_norms) return;
+  if (j0 < tpc) {
+    atomicAdd(&red[3 * c], nr);
+    atomicAdd(&red[3 * c + 1], nR);
+    atomicAdd(&red[3 * c + 2], ns);
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < 3 * m; i += blockDim.x) {
     if (red[i] != 0.0) atomicAdd(&norms[3 * (long long)S.col_off + i], red[i]);
@@ -1768,12 +1782,16 @@ hipError_t launch_rhs(const Geom &g, int n_sub, int max_cells, int mmax, const d
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const Geom &g, int n_sub, int max_cells, const double *coef,
+hipError_t launch_residual(const Geom &g, int n_sub, int max_cells, int mmax, const double *coef,
                            const double *r0, const double *X, double *R, double *norms,
                            hipStream_t s, const int *subs) {
   const int ntile = (max_cells + kRowsPB - 1) / kRowsPB;
   const long long nblk = 8LL * ntile * ((n_sub + 7) / 8);
-  hipLaunchKernelGGL(k_residual, dim3((unsigned)nblk), dim3(256), 0, s, g, coef, r0, X, R, norms, ntile, n_sub, subs);
+  const size_t lds = (size_t)(kRowsPB + 3) * mmax * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void *)k_residual, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_residual, dim3((unsigned)nblk), dim3(256), lds, s, g, coef, r0, X, R, norms, ntile, n_sub,
+                     subs);
   return hipGetLastError();
 }
 
