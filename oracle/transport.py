@@ -31,7 +31,12 @@ Readings (the printed scheme leaves them open):
   Dt q (1 - phi(S_c)) / V.
 * T4, CFL (eq. CFL): Dt = cfl * min(h) / max_c( |phi'(S_c)| max_f |U[f][c]| ),
   cfl = 1 the paper's bound; a cell with inflow on several faces keeps S in
-  [0, 1] for cfl <= 1/6 (the sum over six faces).
+  [0, 1] for cfl <= 1/6 (the sum over six faces).  The loop of the
+  implementation section takes the step Dt_s as an input that satisfies the
+  bound, and the text speaks of adapting it: the step is min(Dt_s, bound),
+  with Dt_s = dt_max given by the caller.  The bound sees the face flows only
+  (at S = 0 everywhere phi' vanishes and it is infinite); a source cell's own
+  rate is the caller's to bound through dt_max.
 """
 from __future__ import annotations
 
@@ -93,13 +98,15 @@ def transport_step(dims, h, U, q, S, dt, mu_w, mu_o):
     return out
 
 
-def cfl_dt(dims, h, U, S, mu_w, mu_o, cfl=1.0):
-    """Time step of reading T4 (eq. CFL); inf when nothing moves."""
+def cfl_dt(dims, h, U, S, mu_w, mu_o, cfl=1.0, dt_max=np.inf):
+    """Time step of reading T4 (eq. CFL): min(dt_max, the CFL bound); the
+    bound is inf when nothing moves."""
     N = dims[0] * dims[1] * dims[2]
     U = np.asarray(U, dtype=np.float64).reshape(6, N)
     speed = np.abs(frac_flow_deriv(S, mu_o / mu_w)) * np.abs(U).max(axis=0)
     m = float(speed.max()) if N else 0.0
-    return np.inf if m == 0.0 else cfl * min(h) / m
+    bound = np.inf if m == 0.0 else cfl * min(h) / m
+    return min(float(dt_max), bound)
 
 
 def water_volume(h, S):

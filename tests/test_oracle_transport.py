@@ -10,6 +10,9 @@
   the water volume changes by exactly the injected water minus the water the
   producers take.
 * Under the CFL step with cfl = 1/6 the saturation stays in [0, 1].
+* From an all-oil state phi' vanishes and the CFL bound is infinite: the step
+  is the caller's dt_max, and one step puts exactly dt q / V of water into
+  the injector cell and nothing anywhere else (every phi is 0).
 * phi' against central differences; the limits of phi and lambda.
 """
 import numpy as np
@@ -139,3 +142,21 @@ def test_frac_flow_derivative_and_limits():
     assert frac_flow(0.0, M) == 0.0 and frac_flow(1.0, M) == 1.0
     assert abs(frac_flow(0.5, M) - M / (M + 1.0)) < 1e-15
     assert mobility(0.0, 2.0, 5.0) == 1.0 / 5.0 and mobility(1.0, 2.0, 5.0) == 1.0 / 2.0
+
+
+def test_all_oil_start_takes_the_callers_step_and_fills_the_injector_only():
+    pb, U = _closed_box_with_wells(2)
+    S = np.zeros(pb.n)
+    assert cfl_dt(pb.dims, pb.h, U, S, 1.0, 5.0, cfl=1.0 / 6.0) == np.inf
+    dt = cfl_dt(pb.dims, pb.h, U, S, 1.0, 5.0, cfl=1.0 / 6.0, dt_max=0.3)
+    assert dt == 0.3
+    S1 = transport_step(pb.dims, pb.h, U, pb.q, S, dt, 1.0, 5.0)
+    q = np.asarray(pb.q)
+    V = pb.h[0] * pb.h[1] * pb.h[2]
+    expect = np.where(q > 0, dt * q / V, 0.0)
+    assert np.array_equal(S1, expect)
+    # a bound below the caller's step wins
+    S = np.random.default_rng(1).uniform(0.0, 1.0, pb.n)
+    b = cfl_dt(pb.dims, pb.h, U, S, 1.0, 5.0)
+    assert cfl_dt(pb.dims, pb.h, U, S, 1.0, 5.0, dt_max=2 * b) == b
+    assert cfl_dt(pb.dims, pb.h, U, S, 1.0, 5.0, dt_max=0.5 * b) == 0.5 * b
