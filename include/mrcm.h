@@ -384,6 +384,65 @@ mrcm_status mrcm_postprocess_mean(const mrcm_mbfs *mbfs, const double *U, void *
                                   double *Ut);
 
 /*
+ * Two-phase saturation step (IMPES, Sec. 5 and the implementation section:
+ * eqs. (transporte_discreto), (flux_disc_up), (CFL)).  Water saturation S,
+ * viscosity ratio M = mu_o / mu_w, fractional flow
+ * phi(S) = M S^2 / (M S^2 + (1 - S)^2), total mobility
+ * lambda(S) = S^2 / mu_w + (1 - S)^2 / mu_o.  Grid of nx x ny x nz cells of
+ * hx x hy x hz, cells x fastest; porosity absorbed into time, as the paper does.
+ */
+typedef struct {
+  int32_t nx, ny, nz;
+  double hx, hy, hz;
+  double mu_w, mu_o;   /* water and oil viscosities, > 0 */
+} mrcm_twophase;
+
+/*
+ * One saturation step.  With U[6][N] the outward normal velocities per cell
+ * and face (-x, +x, .., +z; face-major U[f*N + c], the layout mrcm_reconstruct
+ * and mrcm_postprocess_mean write), the upwind update with the divergence
+ * compensation reads
+ *   S'_c = S_c - dt sum_f (phi_f - phi(S_c)) U[f][c] / h_d(f),
+ * phi_f = phi(S_c) on an outflow face (U >= 0), the neighbour's phi on an
+ * inflow face, and 1 (water) for an inflow across a domain wall; an injector
+ * (q_c > 0) adds dt q_c (1 - phi(S_c)) / V.  (The printed update's signs and
+ * its divergence term without the 1/h factors are read this way; the term
+ * phi_c div u it removes includes div u = q / V in a well cell, which the
+ * injector term restores for the water injected.)
+ * U, S [dev] 6*N and N; q [dev] N total source rates (volume per time) or
+ * NULL; dt [dev] one double, the step (mrcm_transport_dt writes it); S_out
+ * [dev] N, which must not overlap S.  dt must be finite (an infinite one
+ * gives NaN where a face velocity is zero).
+ */
+mrcm_status mrcm_transport_step(const mrcm_twophase *tp /* [host] */, const double *U, const double *q,
+                                const double *S, const double *dt, void *stream, double *S_out);
+
+/*
+ * The saturation step for the current S and U under eq. (CFL), into dt
+ * [dev] (one double): dt = min(dt_max, cfl min(hx, hy, hz) / M) with
+ * M = max_c |phi'(S_c)| max_f |U[f][c]|, and dt = dt_max when M is zero.
+ * dt_max is the loop's own step (an input of the IMPES loop, which the bound
+ * may shorten); +inf leaves the bound alone.  The bound sees the face flows
+ * only: from an all-oil state (phi' = 0 everywhere) it is infinite, and an
+ * injector's own rate is bounded by dt_max (dt q / V <= 1 - S keeps its
+ * cell within [0, 1]).  cfl = 1 is the printed bound; cfl <= 1/6 keeps S
+ * within [0, 1] for any inflow pattern (six faces).  The value stays on the
+ * device, so that steps chain without a synchronisation; dt's eight bytes
+ * also serve as the reduction's accumulator.  cfl > 0 and finite, dt_max > 0.
+ */
+mrcm_status mrcm_transport_dt(const mrcm_twophase *tp /* [host] */, const double *U, const double *S, double cfl,
+                              double dt_max, void *stream, double *dt);
+
+/*
+ * The permeability of a Darcy solve of the two-phase run: K lambda(S) per
+ * cell (eq. sec2:darcy).  S, kx, ky, kz [dev] N in; kx_out, ky_out, kz_out
+ * [dev] N out (may be the inputs themselves).
+ */
+mrcm_status mrcm_mobility_scale(const mrcm_twophase *tp /* [host] */, const double *S, const double *kx,
+                                const double *ky, const double *kz, void *stream, double *kx_out, double *ky_out,
+                                double *kz_out);
+
+/*
  * Sizes and counts of a built handle.  n_patch counts the patches of the
  * interface space (each carries two unknowns, so 2 n_patch is the interface
  * system's size, the N_Gamma of eq. (2.24) for one patch per interface);

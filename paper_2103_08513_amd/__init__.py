@@ -3,7 +3,8 @@
 Python binding of the C ABI in ``include/mrcm.h``: it marshals torch device
 tensors (FP64, contiguous) and the current HIP stream into the library calls
 ``mrcm_build_mbfs``, ``mrcm_assemble_interface``, ``mrcm_solve_interface``,
-``mrcm_reconstruct`` and ``mrcm_postprocess_mean``.  Every step of the method runs in the library's
+``mrcm_reconstruct`` and ``mrcm_postprocess_mean``, and the two-phase saturation
+step ``mrcm_transport_dt``, ``mrcm_transport_step``, ``mrcm_mobility_scale``.  Every step of the method runs in the library's
 kernels; importing this package does not need a GPU, but every call does.
 """
 from __future__ import annotations
@@ -15,7 +16,7 @@ from ctypes import byref, c_double, c_int32, c_void_p
 import numpy as np
 
 from . import _lib
-from ._lib import CIfaceInfo, CInfo, CIfaceSpace, COptions, CPartition, CProblem, CSubInfo, MRCMError
+from ._lib import CIfaceInfo, CInfo, CIfaceSpace, COptions, CPartition, CProblem, CSubInfo, CTwoPhase, MRCMError
 
 FP64 = 0
 FP32_IR = 1
@@ -37,7 +38,8 @@ IFACE_MULTIFRONTAL = 2
 __all__ = ["MRCM", "MRCMError", "FP64", "FP32_IR", "PCG", "IFACE_AUTO", "IFACE_BAND", "IFACE_MULTIFRONTAL",
            "BETA_PER_SIDE", "BETA_FACE", "KEEP_FACTORS", "KEEP_MBFS",
            "build_mbfs", "assemble_interface",
-           "solve_interface", "reconstruct", "postprocess_mean", "library"]
+           "solve_interface", "reconstruct", "postprocess_mean", "TwoPhase", "transport_dt", "transport_step",
+           "mobility_scale", "library"]
 
 
 def library():
@@ -440,3 +442,68 @@ def reconstruct(model: MRCM, X, stream=None):
 
 def postprocess_mean(model: MRCM, U, stream=None):
     return model.postprocess_mean(U, stream=stream)
+
+
+class TwoPhase:
+    """The IMPES saturation step of a two-phase run on an nx x ny x nz grid of
+    hx x hy x hz cells (mrcm_transport_dt, mrcm_transport_step,
+    mrcm_mobility_scale).  Saturations, sources and velocities are float64
+    device tensors: S and q with N entries, U with 6 N (face-major)."""
+
+    def __init__(self, dims, h, mu_w, mu_o):
+        self.dims = tuple(int(d) for d in dims)
+        self.h = tuple(float(x) for x in h)
+        self.mu_w, self.mu_o = float(mu_w), float(mu_o)
+        self.n = self.dims[0] * self.dims[1] * self.dims[2]
+        self._c = CTwoPhase(self.dims[0], self.dims[1], self.dims[2], *self.h, self.mu_w, self.mu_o)
+        self.lib = _lib.load()
+
+    def dt(self, U, S, cfl=1.0, dt_max=float("inf"), out=None, stream=None):
+        """min(dt_max, the CFL bound of eq. CFL) into a one-entry device
+        tensor, which stays on the device; dt_max when nothing moves."""
+        import torch
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=S.device)
+        code = self.lib.mrcm_transport_dt(byref(self._c), _dev_ptr(U, "U", 6 * self.n), _dev_ptr(S, "S", self.n),
+                                          c_double(cfl), c_double(dt_max), _stream_ptr(stream),
+                                          _dev_ptr(out, "dt", 1))
+        _lib.check(code, "mrcm_transport_dt")
+        return out
+
+    def step(self, U, q, S, dt, out=None, stream=None):
+        """One saturation step; dt a one-entry device tensor (dt()) or a number."""
+        import torch
+        if not isinstance(dt, torch.Tensor):
+            dt = torch.full((1,), float(dt), dtype=torch.float64, device=S.device)
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=S.device)
+        qp = _dev_ptr(q, "q", self.n) if q is not None else None
+        code = self.lib.mrcm_transport_step(byref(self._c), _dev_ptr(U, "U", 6 * self.n), qp,
+                                            _dev_ptr(S, "S", self.n), _dev_ptr(dt, "dt", 1), _stream_ptr(stream),
+                                            _dev_ptr(out, "S_out", self.n))
+        _lib.check(code, "mrcm_transport_step")
+        return out
+
+    def mobility_scale(self, S, kx, ky, kz, out=None, stream=None):
+        """K lambda(S) per cell: returns (kx', ky', kz')."""
+        import torch
+        if out is None:
+            out = tuple(torch.empty(self.n, dtype=torch.float64, device=S.device) for _ in range(3))
+        ins = [_dev_ptr(t, n, self.n) for t, n in ((kx, "kx"), (ky, "ky"), (kz, "kz"))]
+        outs = [_dev_ptr(t, n, self.n) for t, n in zip(out, ("kx_out", "ky_out", "kz_out"))]
+        code = self.lib.mrcm_mobility_scale(byref(self._c), _dev_ptr(S, "S", self.n), *ins, _stream_ptr(stream),
+                                            *outs)
+        _lib.check(code, "mrcm_mobility_scale")
+        return tuple(out)
+
+
+def transport_dt(tp: TwoPhase, U, S, cfl=1.0, dt_max=float("inf"), stream=None):
+    return tp.dt(U, S, cfl, dt_max, stream=stream)
+
+
+def transport_step(tp: TwoPhase, U, q, S, dt, stream=None):
+    return tp.step(U, q, S, dt, stream=stream)
+
+
+def mobility_scale(tp: TwoPhase, S, kx, ky, kz, stream=None):
+    return tp.mobility_scale(S, kx, ky, kz, stream=stream)

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrcm.so")
 SOURCES = ["local_kernels.hip", "pcg_kernels.hip", "nn_kernels.hip", "unet_kernels.hip", "iface_kernels.hip",
-           "mf_kernels.hip",
+           "mf_kernels.hip", "transport_kernels.hip",
            "nd_plan.cpp", "capi.cpp"]
 
 HIP_FLAGS = [

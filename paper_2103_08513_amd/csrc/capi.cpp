@@ -1486,6 +1486,53 @@ mrcm_status init_mean(mrcm_mbfs *mb) {
 
 }  // namespace
 
+namespace {
+
+mrcm_status twophase_grid(const mrcm_twophase *tp, TwoPhaseGrid &t) {
+  if (!tp) return fail(MRCM_EINVAL, "null two-phase descriptor");
+  if (tp->nx <= 0 || tp->ny <= 0 || tp->nz <= 0) return fail(MRCM_EINVAL, "grid dimensions must be positive");
+  const double v[5] = {tp->hx, tp->hy, tp->hz, tp->mu_w, tp->mu_o};
+  for (double x : v)
+    if (!(x > 0.0) || !std::isfinite(x)) return fail(MRCM_EINVAL, "cell sizes and viscosities must be positive and finite");
+  t = TwoPhaseGrid{tp->nx, tp->ny, tp->nz, tp->hx, tp->hy, tp->hz, tp->mu_w, tp->mu_o};
+  return MRCM_OK;
+}
+
+}  // namespace
+
+mrcm_status mrcm_transport_step(const mrcm_twophase *tp, const double *U, const double *q, const double *S,
+                                const double *dt, void *stream, double *S_out) {
+  TwoPhaseGrid t;
+  const mrcm_status st = twophase_grid(tp, t);
+  if (st != MRCM_OK) return st;
+  if (!U || !S || !dt || !S_out) return fail(MRCM_EINVAL, "null argument");
+  if (S_out == S) return fail(MRCM_EINVAL, "S_out must not overlap S");
+  HIP_TRY(launch_transport(t, U, q, S, dt, S_out, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_transport_dt(const mrcm_twophase *tp, const double *U, const double *S, double cfl, double dt_max,
+                              void *stream, double *dt) {
+  TwoPhaseGrid t;
+  const mrcm_status st = twophase_grid(tp, t);
+  if (st != MRCM_OK) return st;
+  if (!U || !S || !dt) return fail(MRCM_EINVAL, "null argument");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(MRCM_EINVAL, "cfl must be positive and finite");
+  if (!(dt_max > 0.0)) return fail(MRCM_EINVAL, "dt_max must be positive (or +inf)");
+  HIP_TRY(launch_transport_dt(t, U, S, cfl, dt_max, dt, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
+mrcm_status mrcm_mobility_scale(const mrcm_twophase *tp, const double *S, const double *kx, const double *ky,
+                                const double *kz, void *stream, double *kx_out, double *ky_out, double *kz_out) {
+  TwoPhaseGrid t;
+  const mrcm_status st = twophase_grid(tp, t);
+  if (st != MRCM_OK) return st;
+  if (!S || !kx || !ky || !kz || !kx_out || !ky_out || !kz_out) return fail(MRCM_EINVAL, "null argument");
+  HIP_TRY(launch_mobility(t, S, kx, ky, kz, kx_out, ky_out, kz_out, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
 mrcm_status mrcm_postprocess_mean(const mrcm_mbfs *cmb, const double *U, void *stream, double *pt, double *Ut) {
   if (!cmb || !U || !pt || !Ut) return fail(MRCM_EINVAL, "null argument");
   mrcm_mbfs *mb = const_cast<mrcm_mbfs *>(cmb);  // lazily allocated Mean buffers

@@ -42,6 +42,13 @@ struct SubDesc {
   int64_t F_off;        // offset (elements) of F / Fb, npatch*m
 };
 
+// Grid and fluids of the two-phase saturation step.
+struct TwoPhaseGrid {
+  int32_t nx, ny, nz;
+  double hx, hy, hz;
+  double mu_w, mu_o;
+};
+
 // One interface between subdomains lo_sub < hi_sub along axis d; tangential
 // axes a < b with extents la, lb split into na x nb patches; first patch p0.
 struct IfaceDesc {

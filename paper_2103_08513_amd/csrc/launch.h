@@ -60,6 +60,15 @@ hipError_t launch_mean_coef(const Geom &g, int n_sub, int max_cells, const doubl
 hipError_t launch_mean_velocity(const Geom &g, const double *U, const double *P, double *pt, double *Ut,
                                 hipStream_t s);
 
+// Saturation step of the two-phase run (transport_kernels.hip): the step,
+// its CFL time step into a device scalar, and K lambda(S).
+hipError_t launch_transport(const TwoPhaseGrid &t, const double *U, const double *q, const double *S,
+                            const double *dt, double *Sout, hipStream_t s);
+hipError_t launch_transport_dt(const TwoPhaseGrid &t, const double *U, const double *S, double cfl, double dt_max,
+                               double *dt, hipStream_t s);
+hipError_t launch_mobility(const TwoPhaseGrid &t, const double *S, const double *kx, const double *ky,
+                           const double *kz, double *ox, double *oy, double *oz, hipStream_t s);
+
 // Conjugate-gradient form of the local solves (pcg_kernels.hip).  One
 // workgroup per column (subdomain by col_sub); X0 null for a zero start.
 int pcg_max_cells();
