@@ -52,12 +52,13 @@ def _stages(L, _lib, steps):
 
 
 def run_gpu(case, precision, steps, warmup, refine, graph=False, tune=False, net=None, pcg_max_iter=1000,
-            profile=True, mean=False):
+            profile=True, mean=False, transport=False, cpu=True):
     """K timed whole solves of `case` in the given form (0 FP64, 1 FP32 with
     FP64 refinement, 2 conjugate gradients started from the network `net`),
     then the same K steps with stage profiling, then (FP64) the step replayed
     from a recorded HIP graph, then (mean) K timed Mean post-processings of
-    the last step's velocity."""
+    the last step's velocity, then (transport) the two-phase saturation step
+    under the Mean velocity."""
     import torch
     import paper_2103_08513_amd as lib
     from paper_2103_08513_amd import _lib
@@ -129,9 +130,11 @@ def run_gpu(case, precision, steps, warmup, refine, graph=False, tune=False, net
         graph_ms = (time.perf_counter() - t0) * 1e3 / steps
         g.check(stream=gs)
         g.close()
-    mean_out = None
+    mean_out = transport_out = None
     if mean:
         mean_out = time_mean(model, pb, case.partition, U, steps)
+    if transport:
+        transport_out = time_transport(model, pb, U, max(50, 10 * steps), cpu)
     # residual and mass balance once, outside the timed and profiled loops
     model.solve_interface(X, refine=refine, residual=True)
     torch.cuda.synchronize()
@@ -148,7 +151,7 @@ def run_gpu(case, precision, steps, warmup, refine, graph=False, tune=False, net
         shapes.append((si.n_cells, si.band, si.n_rhs, si.solve_group))
     out = dict(ms_step=ms_step, graph_ms=graph_ms, tuned=tuned, stages=stages, info=info, iinfo=iinfo,
                interface_residual=model.interface_residual, refine_iters=model.interface_iters,
-               mass_imbalance=imbalance, sub_shapes=shapes, mean=mean_out)
+               mass_imbalance=imbalance, sub_shapes=shapes, mean=mean_out, transport=transport_out)
     model.close()
     del p, U, X, kx, ky, kz, q
     torch.cuda.empty_cache()
@@ -189,6 +192,105 @@ def time_mean(model, pb, part, U, steps):
                    "subdomain by FP64 band Cholesky and one refinement sweep, factors chunked through an 8 GiB "
                    "scratch); balances relative to the largest face flux"}
     del pt, Ut, bal, pinned
+    return out
+
+
+# HBM bytes per cell of one saturation step fused with the next step's CFL
+# speed (mrcm_transport_advance): U 48, S 8, q 8 read, S' 8 written; the
+# neighbours' saturations are re-reads of S served by the caches.
+TRANSPORT_BYTES_PER_CELL = 72
+# the CFL reduction alone (mrcm_transport_dt): U 48, S 8
+SPEED_BYTES_PER_CELL = 56
+# K lambda(S) (mrcm_mobility_scale): S 8, K 24 read, K' 24 written
+MOBILITY_BYTES_PER_CELL = 56
+
+
+def time_transport(model, pb, U, steps, cpu=True):
+    """The IMPES saturation step under the Mean velocity of the step's U: a
+    seeded saturation field (uniform in [0, 1]), mu_o / mu_w = 5, the
+    quarter-five-spot wells of the workload.  K timed mrcm_transport_advance
+    calls (ping-pong S and dt), the CFL reduction and the mobility, each with
+    HIP events on the stream they run on; and the oracle's step on a slab of
+    five z-planes, on the host."""
+    import torch
+    import paper_2103_08513_amd as lib
+    N = pb.n
+    dev = U.device
+    _, Ut = model.postprocess_mean(U)
+    tp = lib.TwoPhase(pb.dims, (pb.hx, pb.hy, pb.hz), 1.0, 5.0)
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    S = [torch.rand(N, dtype=torch.float64, device=dev, generator=g), torch.empty(N, dtype=torch.float64, device=dev)]
+    q = torch.as_tensor(pb.q, dtype=torch.float64, device=dev)
+    dts = [torch.empty(1, dtype=torch.float64, device=dev) for _ in range(2)]
+    V = pb.hx * pb.hy * pb.hz
+    dt_max = 0.2 * V / float(np.max(pb.q))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    ms_dt = timed(lambda: tp.dt(Ut, S[0], cfl=1.0 / 6.0, dt_max=dt_max, out=dts[0]), 10)
+    kx, ky, kz = (torch.as_tensor(a, dtype=torch.float64, device=dev) for a in (pb.kx, pb.ky, pb.kz))
+    kout = tuple(torch.empty(N, dtype=torch.float64, device=dev) for _ in range(3))
+    ms_mob = timed(lambda: tp.mobility_scale(S[0], kx, ky, kz, out=kout), 10)
+    del kx, ky, kz, kout
+    state = [0]
+
+    def adv():
+        i = state[0]
+        tp.advance(Ut, q, S[i], dts[i], cfl=1.0 / 6.0, dt_max=dt_max, out=S[1 - i], dt_next=dts[1 - i])
+        state[0] = 1 - i
+
+    tp.dt(Ut, S[0], cfl=1.0 / 6.0, dt_max=dt_max, out=dts[0])
+    ms_adv = timed(adv, steps)
+    Sf = S[state[0]]
+    lo, hi = float(Sf.min()), float(Sf.max())
+    prof = _summary("k_transport", WORKLOAD, "transport_kernels.hip")
+    traffic = None
+    if prof:
+        try:
+            traffic = float(prof["hbm_bytes_per_launch"])
+        except (KeyError, ValueError):
+            traffic = None
+    out = {"ms_per_step": ms_adv, "gcells_per_s": N / (ms_adv * 1e-3) / 1e9, "steps": steps,
+           "s_range": [lo, hi], "ms_cfl_reduction": ms_dt, "ms_mobility": ms_mob,
+           "roofline": {"kernel": "k_transport<true> (mrcm_transport_advance)", "bound": "hbm",
+                        "achieved": TRANSPORT_BYTES_PER_CELL * N / (ms_adv * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": TRANSPORT_BYTES_PER_CELL * N / (ms_adv * 1e-3) / 8e12,
+                        "traffic": traffic, "bytes_per_cell": TRANSPORT_BYTES_PER_CELL,
+                        "note": "event time of the whole call (the accumulator clear, the step, the finalising "
+                                "kernel)"},
+           "roofline_cfl": {"achieved": SPEED_BYTES_PER_CELL * N / (ms_dt * 1e-3) / 1e9, "unit": "GB/s",
+                            "frac": SPEED_BYTES_PER_CELL * N / (ms_dt * 1e-3) / 8e12},
+           "roofline_mobility": {"achieved": MOBILITY_BYTES_PER_CELL * N / (ms_mob * 1e-3) / 1e9, "unit": "GB/s",
+                                 "frac": MOBILITY_BYTES_PER_CELL * N / (ms_mob * 1e-3) / 8e12},
+           "what": "IMPES saturation step fused with the next step's CFL speed, velocity held (the inner loop "
+                   "between Darcy solves); seeded S uniform in [0, 1], mu_o / mu_w = 5, cfl 1/6"}
+    if cpu:
+        from oracle.transport import transport_step
+        nx, ny, nz = pb.dims
+        kz5 = 5
+        sd = (nx, ny, kz5)
+        Us = Ut.view(6, nz, ny * nx)[:, :kz5].cpu().numpy().reshape(6, -1)
+        Ss = S[0].view(nz, ny * nx)[:kz5].cpu().numpy().reshape(-1)
+        qs = np.asarray(pb.q).reshape(nz, -1)[:kz5].reshape(-1)
+        t = time.perf_counter()
+        transport_step(sd, (pb.hx, pb.hy, pb.hz), Us, qs, Ss, dt_max * 1e-3, 1.0, 5.0)
+        sec = time.perf_counter() - t
+        n5 = nx * ny * kz5
+        out["cpu_oracle"] = {"kind": "oracle", "cells": n5, "s": sec, "gcells_per_s": n5 / sec / 1e9, "cores": 1,
+                             "sample": f"oracle transport_step on the {nx}x{ny}x{kz5} slab of z-planes 0-4"}
+        del Us, Ss
+    del S, Ut, q
+    torch.cuda.empty_cache()
     return out
 
 
@@ -405,6 +507,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the replay of the recorded step")
     ap.add_argument("--tune", action="store_true", help="run the autotuner first (a handle per candidate)")
     ap.add_argument("--no-mean", action="store_true", help="skip the Mean post-processing measurement")
+    ap.add_argument("--no-transport", action="store_true", help="skip the saturation-step measurement")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="subdomains in the oracle's timed sample")
     ap.add_argument("--copy-calibration", type=float, default=None, metavar="MB",
                     help="only run a device copy of this many MB (counter calibration) and exit")
@@ -428,10 +531,15 @@ def main():
     log(f"workload {WORKLOAD}: inputs in {time.perf_counter() - t:.1f} s; steps {args.steps}, warmup {args.warmup}")
     prec = 1 if args.precision == "fp32ir" else 0
     res = run_gpu(case, prec, args.steps, args.warmup, args.refine, graph=not args.no_graph, tune=args.tune,
-                  mean=not args.no_mean)
+                  mean=not args.no_mean, transport=not (args.no_mean or args.no_transport),
+                  cpu=not args.no_cpu_baseline)
     info = res["info"]
     log(f"{args.precision}: ms/step {res['ms_step']:.1f}; stages " +
         ", ".join(f"{k} {v['ms_per_step']:.1f}" for k, v in res["stages"].items()))
+    if res["transport"]:
+        tr = res["transport"]
+        log(f"transport: {tr['ms_per_step']:.3f} ms/step ({tr['roofline']['achieved']:.0f} GB/s), CFL reduction "
+            f"{tr['ms_cfl_reduction']:.3f} ms, mobility {tr['ms_mobility']:.3f} ms")
     secondary = None
     if not args.no_secondary:
         secondary = run_gpu(case, 1 - prec, args.steps, args.warmup, args.refine)
@@ -492,6 +600,7 @@ def main():
         "roofline_interface": roofline_interface(res),
         "cpu_baseline": cpu,
         "mean_postprocess": res["mean"],
+        "transport": res["transport"],
     }
     if secondary is not None:
         line["other_precision"] = _form_line(secondary, info.n_mbfs, pb.n, 1 - prec,

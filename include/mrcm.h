@@ -434,6 +434,18 @@ mrcm_status mrcm_transport_dt(const mrcm_twophase *tp /* [host] */, const double
                               double dt_max, void *stream, double *dt);
 
 /*
+ * One saturation step (as mrcm_transport_step) and the next step under the
+ * same velocity (as mrcm_transport_dt on S_out, with cfl and dt_max) in one
+ * pass over U and S: the inner loop of the IMPES run, where the velocity is
+ * held for C steps between Darcy solves.  dt [dev] the step to take,
+ * dt_next [dev] the next one (must not be dt; ping-pong two doubles).
+ * S_out must not overlap S.  Results equal the two separate calls bitwise.
+ */
+mrcm_status mrcm_transport_advance(const mrcm_twophase *tp /* [host] */, const double *U, const double *q,
+                                   const double *S, const double *dt, double cfl, double dt_max, void *stream,
+                                   double *S_out, double *dt_next);
+
+/*
  * The permeability of a Darcy solve of the two-phase run: K lambda(S) per
  * cell (eq. sec2:darcy).  S, kx, ky, kz [dev] N in; kx_out, ky_out, kz_out
  * [dev] N out (may be the inputs themselves).

@@ -4,7 +4,8 @@ Python binding of the C ABI in ``include/mrcm.h``: it marshals torch device
 tensors (FP64, contiguous) and the current HIP stream into the library calls
 ``mrcm_build_mbfs``, ``mrcm_assemble_interface``, ``mrcm_solve_interface``,
 ``mrcm_reconstruct`` and ``mrcm_postprocess_mean``, and the two-phase saturation
-step ``mrcm_transport_dt``, ``mrcm_transport_step``, ``mrcm_mobility_scale``.  Every step of the method runs in the library's
+step ``mrcm_transport_dt``, ``mrcm_transport_step``, ``mrcm_transport_advance``,
+``mrcm_mobility_scale``.  Every step of the method runs in the library's
 kernels; importing this package does not need a GPU, but every call does.
 """
 from __future__ import annotations
@@ -38,7 +39,7 @@ IFACE_MULTIFRONTAL = 2
 __all__ = ["MRCM", "MRCMError", "FP64", "FP32_IR", "PCG", "IFACE_AUTO", "IFACE_BAND", "IFACE_MULTIFRONTAL",
            "BETA_PER_SIDE", "BETA_FACE", "KEEP_FACTORS", "KEEP_MBFS",
            "build_mbfs", "assemble_interface",
-           "solve_interface", "reconstruct", "postprocess_mean", "TwoPhase", "transport_dt", "transport_step",
+           "solve_interface", "reconstruct", "postprocess_mean", "TwoPhase", "transport_dt", "transport_step", "transport_advance",
            "mobility_scale", "library"]
 
 
@@ -484,6 +485,22 @@ class TwoPhase:
         _lib.check(code, "mrcm_transport_step")
         return out
 
+    def advance(self, U, q, S, dt, cfl=1.0, dt_max=float("inf"), out=None, dt_next=None, stream=None):
+        """One step with dt (a one-entry device tensor) and the next step's
+        dt under the same U: returns (S_out, dt_next)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=S.device)
+        if dt_next is None:
+            dt_next = torch.empty(1, dtype=torch.float64, device=S.device)
+        qp = _dev_ptr(q, "q", self.n) if q is not None else None
+        code = self.lib.mrcm_transport_advance(byref(self._c), _dev_ptr(U, "U", 6 * self.n), qp,
+                                               _dev_ptr(S, "S", self.n), _dev_ptr(dt, "dt", 1), c_double(cfl),
+                                               c_double(dt_max), _stream_ptr(stream), _dev_ptr(out, "S_out", self.n),
+                                               _dev_ptr(dt_next, "dt_next", 1))
+        _lib.check(code, "mrcm_transport_advance")
+        return out, dt_next
+
     def mobility_scale(self, S, kx, ky, kz, out=None, stream=None):
         """K lambda(S) per cell: returns (kx', ky', kz')."""
         import torch
@@ -503,6 +520,10 @@ def transport_dt(tp: TwoPhase, U, S, cfl=1.0, dt_max=float("inf"), stream=None):
 
 def transport_step(tp: TwoPhase, U, q, S, dt, stream=None):
     return tp.step(U, q, S, dt, stream=stream)
+
+
+def transport_advance(tp: TwoPhase, U, q, S, dt, cfl=1.0, dt_max=float("inf"), stream=None):
+    return tp.advance(U, q, S, dt, cfl, dt_max, stream=stream)
 
 
 def mobility_scale(tp: TwoPhase, S, kx, ky, kz, stream=None):

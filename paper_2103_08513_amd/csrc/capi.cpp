@@ -1511,6 +1511,21 @@ mrcm_status mrcm_transport_step(const mrcm_twophase *tp, const double *U, const 
   return MRCM_OK;
 }
 
+mrcm_status mrcm_transport_advance(const mrcm_twophase *tp, const double *U, const double *q, const double *S,
+                                   const double *dt, double cfl, double dt_max, void *stream, double *S_out,
+                                   double *dt_next) {
+  TwoPhaseGrid t;
+  const mrcm_status st = twophase_grid(tp, t);
+  if (st != MRCM_OK) return st;
+  if (!U || !S || !dt || !S_out || !dt_next) return fail(MRCM_EINVAL, "null argument");
+  if (S_out == S) return fail(MRCM_EINVAL, "S_out must not overlap S");
+  if (dt_next == dt) return fail(MRCM_EINVAL, "dt_next must not be dt");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(MRCM_EINVAL, "cfl must be positive and finite");
+  if (!(dt_max > 0.0)) return fail(MRCM_EINVAL, "dt_max must be positive (or +inf)");
+  HIP_TRY(launch_transport_advance(t, U, q, S, dt, cfl, dt_max, S_out, dt_next, (hipStream_t)stream));
+  return MRCM_OK;
+}
+
 mrcm_status mrcm_transport_dt(const mrcm_twophase *tp, const double *U, const double *S, double cfl, double dt_max,
                               void *stream, double *dt) {
   TwoPhaseGrid t;

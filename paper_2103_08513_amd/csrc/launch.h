@@ -64,6 +64,9 @@ hipError_t launch_mean_velocity(const Geom &g, const double *U, const double *P,
 // its CFL time step into a device scalar, and K lambda(S).
 hipError_t launch_transport(const TwoPhaseGrid &t, const double *U, const double *q, const double *S,
                             const double *dt, double *Sout, hipStream_t s);
+hipError_t launch_transport_advance(const TwoPhaseGrid &t, const double *U, const double *q, const double *S,
+                                    const double *dt, double cfl, double dt_max, double *Sout, double *dt_next,
+                                    hipStream_t s);
 hipError_t launch_transport_dt(const TwoPhaseGrid &t, const double *U, const double *S, double cfl, double dt_max,
                                double *dt, hipStream_t s);
 hipError_t launch_mobility(const TwoPhaseGrid &t, const double *S, const double *kx, const double *ky,

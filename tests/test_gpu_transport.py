@@ -16,6 +16,8 @@ mrcm_transport_dt, mrcm_mobility_scale; eqs. (transporte_discreto),
   cells.
 * Two Darcy calls of an IMPES loop on a small case (K lambda(S), MRCM, Mean,
   three CFL steps each) against the same loop on the oracle.
+* The step fused with the next step's CFL reduction (mrcm_transport_advance)
+  equals the two separate calls bitwise, and chains against the oracle.
 * Bad descriptors and arguments are refused.
 Tolerances: the step evaluates the oracle's operations but sums the six face
 terms before scaling by dt, and the compiler may contract a product into an
@@ -141,6 +143,42 @@ def test_step_matches_the_oracle(name, with_q):
         out = tp.step(Ud, None if q is None else _dev(q), prev, dtd)
         _check_step(dims, h, U, q, Sh, float(dtd.item()), out.cpu().numpy(), mu_w, mu_o)
         Sh = out.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["one-cell", "box", "ragged", "tall"])
+def test_advance_equals_the_step_then_the_cfl_step(name):
+    """mrcm_transport_advance against mrcm_transport_step followed by
+    mrcm_transport_dt on its result (bitwise), then four chained advances
+    against the oracle."""
+    dims = CASES[name]
+    N = int(np.prod(dims))
+    rng = np.random.default_rng(40 + list(CASES).index(name))
+    h = (1.0, 0.5, 2.0)
+    mu_w, mu_o = 1.0, 6.0
+    U = rng.standard_normal((6, N))
+    S = rng.uniform(0.0, 1.0, N)
+    q = np.zeros(N)
+    q[rng.integers(0, N, 2)] = 1.0
+    q[rng.integers(0, N, 2)] = -1.0
+    tp = _tp(dims, h, mu_w, mu_o)
+    Ud, Sd, qd = _dev(U), _dev(S), _dev(q)
+    dt_max = 0.05
+    dt0 = tp.dt(Ud, Sd, cfl=1.0 / 6.0, dt_max=dt_max)
+    s1, dt1 = tp.advance(Ud, qd, Sd, dt0, cfl=1.0 / 6.0, dt_max=dt_max)
+    s1b = tp.step(Ud, qd, Sd, dt0)
+    dt1b = tp.dt(Ud, s1b, cfl=1.0 / 6.0, dt_max=dt_max)
+    assert np.array_equal(s1.cpu().numpy(), s1b.cpu().numpy())
+    assert dt1.item() == dt1b.item()
+    Sh, dth = s1.cpu().numpy(), dt1.item()
+    cur, dcur = s1, dt1
+    for _ in range(4):
+        nxt, dnxt = tp.advance(Ud, qd, cur, dcur, cfl=1.0 / 6.0, dt_max=dt_max)
+        _check_step(dims, h, U, q, Sh, dth, nxt.cpu().numpy(), mu_w, mu_o)
+        Sh = nxt.cpu().numpy()
+        want = cfl_dt(dims, h, U, Sh, mu_w, mu_o, cfl=1.0 / 6.0, dt_max=dt_max)
+        dth = dnxt.item()
+        assert abs(dth - want) <= 8 * EPS * want
+        cur, dcur = nxt, dnxt
 
 
 def test_dt_is_infinite_when_nothing_moves_and_mobility_matches():
@@ -316,6 +354,20 @@ def test_bad_arguments_are_refused():
     assert lb.mrcm_transport_dt(ctypes.byref(good), p, p, 1.0, 0.0, None, p) == -1
     assert lb.mrcm_transport_dt(ctypes.byref(good), p, p, 1.0, float("nan"), None, p) == -1
     assert lb.mrcm_mobility_scale(ctypes.byref(good), p, None, p, p, None, p, p, p) == -1
+    d2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    adv = lb.mrcm_transport_advance
+    assert adv(ctypes.byref(good), p, None, s.data_ptr(), d.data_ptr(), 1.0, 1.0, None, o.data_ptr(),
+               d2.data_ptr()) == 0
+    assert adv(ctypes.byref(good), p, None, s.data_ptr(), d.data_ptr(), 1.0, 1.0, None, o.data_ptr(),
+               d.data_ptr()) == -1                                                          # dt_next == dt
+    assert adv(ctypes.byref(good), p, None, s.data_ptr(), d.data_ptr(), 1.0, 1.0, None, s.data_ptr(),
+               d2.data_ptr()) == -1                                                         # S_out == S
+    assert adv(ctypes.byref(good), p, None, s.data_ptr(), d.data_ptr(), -1.0, 1.0, None, o.data_ptr(),
+               d2.data_ptr()) == -1
+    assert adv(ctypes.byref(good), p, None, s.data_ptr(), d.data_ptr(), 1.0, 1.0, None, o.data_ptr(),
+               None) == -1
+    torch.cuda.synchronize()
+    assert d2.item() == 1.0       # all-zero S: nothing moves, the step is dt_max
     tp = lib.TwoPhase((4, 3, 2), (1.0, 1.0, 1.0), 1.0, 2.0)
     with pytest.raises(ValueError):
         tp.step(z[:5 * N], None, z[:N], 0.1)
