@@ -14,6 +14,8 @@ mrcm_transport_dt, mrcm_mobility_scale; eqs. (transporte_discreto),
   outside the domain), the CFL step against the oracle over z-slabs (the
   minimum of the slabs' steps is the whole grid's), the mobility on sampled
   cells.
+* A grid of 537.9M cells (8N > 2^32): the 64-bit index form against the
+  oracle on sub-boxes reaching the last plane.
 * Two Darcy calls of an IMPES loop on a small case (K lambda(S), MRCM, Mean,
   three CFL steps each) against the same loop on the oracle.
 * The step fused with the next step's CFL reduction (mrcm_transport_advance)
@@ -252,28 +254,7 @@ def test_full_size_grid_sampled():
     assert abs(got_dt - want) <= 8 * EPS * want
     boxes = [((0, 24), (0, 20), (0, 12)), ((nx - 20, nx), (ny - 30, ny), (nz - 9, nz)),
              ((281, 309), (1093, 1120), (40, 52)), ((nx - 16, nx), (0, 18), (30, 41)), ((0, 9), (ny - 12, ny), (0, nz))]
-    for box in boxes:
-        sd = tuple(b - a for a, b in box)
-        Ub, Sb, qb = _sub(U, dims, box), _sub(S, dims, box), _sub(q, dims, box)
-        want_s = transport_step(sd, h, Ub, qb, Sb, got_dt, mu_w, mu_o)
-        got_s = _sub(out, dims, box)
-        # keep the cells whose neighbours are in the box or outside the domain
-        keep = np.ones(sd[::-1], dtype=bool)
-        for d, (a, b) in enumerate(box):
-            ax = 2 - d
-            if a > 0:
-                idx = [slice(None)] * 3
-                idx[ax] = 0
-                keep[tuple(idx)] = False
-            if b < dims[d]:
-                idx = [slice(None)] * 3
-                idx[ax] = -1
-                keep[tuple(idx)] = False
-        keep = keep.reshape(-1)
-        err = np.abs(got_s - want_s)[keep]
-        bound = 16 * EPS * _scale(sd, h, Ub, qb, Sb, got_dt)[keep]
-        print(f"  box {box}: {keep.sum()} cells, max err {err.max():.2e}", flush=True)
-        assert np.all(err <= bound), box
+    _boxes_against_the_oracle(dims, h, U, q, S, out, got_dt, mu_w, mu_o, boxes)
     # the mobility on sampled cells
     k = torch.rand(N, dtype=torch.float64, device="cuda", generator=g) + 0.1
     kx, ky, kz = tp.mobility_scale(S, k, k, k)
@@ -281,6 +262,66 @@ def test_full_size_grid_sampled():
     lam = mobility(S[idx].cpu().numpy(), mu_w, mu_o) * k[idx].cpu().numpy()
     for t in (kx, ky, kz):
         assert np.all(np.abs(t[idx].cpu().numpy() - lam) <= 8 * EPS * lam)
+
+
+def _boxes_against_the_oracle(dims, h, U, q, S, out, dt, mu_w, mu_o, boxes):
+    for box in boxes:
+        sd = tuple(b - a for a, b in box)
+        Ub, Sb, qb = _sub(U, dims, box), _sub(S, dims, box), _sub(q, dims, box)
+        want_s = transport_step(sd, h, Ub, qb, Sb, dt, mu_w, mu_o)
+        got_s = _sub(out, dims, box)
+        keep = np.ones(sd[::-1], dtype=bool)
+        for d, (a, b) in enumerate(box):
+            idx = [slice(None)] * 3
+            if a > 0:
+                idx[2 - d] = 0
+                keep[tuple(idx)] = False
+            if b < dims[d]:
+                idx[2 - d] = -1
+                keep[tuple(idx)] = False
+        keep = keep.reshape(-1)
+        err = np.abs(got_s - want_s)[keep]
+        bound = 16 * EPS * _scale(sd, h, Ub, qb, Sb, dt)[keep]
+        print(f"  box {box}: {keep.sum()} cells, max err {err.max():.2e}", flush=True)
+        assert np.all(err <= bound), box
+
+
+def test_grid_beyond_32_bit_byte_offsets():
+    """1024x1024x513 cells (537.9M, 8N > 2^32): the 64-bit index form of the
+    step, fused and plain, against the oracle on sub-boxes that include the
+    last plane (byte offsets past 2^32), and the fused form's next step
+    against the CFL reduction on its result, bitwise."""
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
+    dims, h = (1024, 1024, 513), (1.0, 2.0, 0.5)
+    nx, ny, nz = dims
+    N = nx * ny * nz
+    assert 8 * N >= 2**32
+    mu_w, mu_o = 1.0, 3.0
+    g = torch.Generator(device="cuda")
+    g.manual_seed(77)
+    U = torch.randn(6 * N, dtype=torch.float64, device="cuda", generator=g)
+    S = torch.rand(N, dtype=torch.float64, device="cuda", generator=g)
+    q = torch.zeros(N, dtype=torch.float64, device="cuda")
+    q[0] = 1.0
+    q[N - 1] = -1.0
+    q[N - 2] = 0.5
+    tp = _tp(dims, h, mu_w, mu_o)
+    print("1024x1024x513: dt, advance, step", flush=True)
+    dt0 = tp.dt(U, S, cfl=1.0 / 6.0, dt_max=0.01)
+    out, dt1 = tp.advance(U, q, S, dt0, cfl=1.0 / 6.0, dt_max=0.01)
+    torch.cuda.synchronize()
+    assert dt1.item() == tp.dt(U, out, cfl=1.0 / 6.0, dt_max=0.01).item()
+    out2 = tp.step(U, q, S, dt0)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+    del out2
+    boxes = [((0, 16), (0, 12), (0, 10)), ((nx - 20, nx), (ny - 16, ny), (nz - 9, nz)),
+             ((500, 530), (700, 712), (505, nz)), ((0, 10), (ny - 10, ny), (nz - 3, nz))]
+    _boxes_against_the_oracle(dims, h, U, q, S, out, float(dt0.item()), mu_w, mu_o, boxes)
+    del U, S, q, out
+    torch.cuda.empty_cache()
 
 
 def test_impes_loop_matches_the_oracle():
