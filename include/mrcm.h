@@ -455,6 +455,53 @@ mrcm_status mrcm_mobility_scale(const mrcm_twophase *tp /* [host] */, const doub
                                 double *kz_out);
 
 /*
+ * The IMPES loop of the implementation section's overview algorithm: with
+ * t = 0 and n = 0, while t <= t_end (and n < max_steps when that is > 0):
+ * every skip-th saturation step (n mod C = 0, C the skipping constant) a
+ * Darcy solve under the current saturation -- the permeability scaled by
+ * lambda(S) (mrcm_mobility_scale), the MBFs rebuilt in place
+ * (mrcm_build_mbfs), the interface assembled and solved (multifrontal,
+ * `refine` refinement steps), the velocity reconstructed and post-processed
+ * by the Mean method (mrcm_postprocess_mean), and the CFL step of that
+ * velocity (mrcm_transport_dt) -- then one saturation step under the held
+ * velocity (mrcm_transport_advance, which also gives the next step), t += dt,
+ * n += 1.  The loop reads each step back to the host (one synchronisation
+ * per step) to advance t.
+ * problem, partition, iface, options: as for mrcm_build_mbfs; problem->kx,
+ * ky, kz are the permeability K without the mobility, problem->q the sources
+ * of both the Darcy solves and the saturation steps.  tp: the same grid and
+ * cell sizes, and the viscosities.  S [dev] N: the initial saturation in,
+ * the final one out.  stats [host] or NULL.
+ * Errors: as the calls above; MRCM_EINVAL also for a step that is not finite
+ * (nothing moves under the bound and dt_max is +inf), with S left at the
+ * last finite state.  The library allocates the loop's buffers (about 17
+ * doubles per cell, beside the MBF handle's) and frees them before it
+ * returns; the handles it creates are destroyed too.
+ */
+typedef struct {
+  int32_t skip;        /* C >= 1: saturation steps per Darcy solve */
+  int32_t max_steps;   /* stop after this many saturation steps; 0: no cap */
+  double t_end;        /* T: run while t <= T (+inf with max_steps > 0) */
+  double cfl;          /* the factor of eq. (CFL), > 0 */
+  double dt_max;       /* the loop's own step Dt_s (> 0; +inf: the bound alone) */
+  int32_t refine;      /* interface refinement steps per Darcy solve, 0 .. 20 */
+} mrcm_impes_options;
+
+typedef struct {
+  int32_t darcy_solves;   /* Darcy solves made */
+  int32_t steps;          /* saturation steps taken */
+  double t;               /* time reached */
+  double ms_darcy;        /* device time of the mobility, MBF build, interface and reconstruction */
+  double ms_mean;         /* device time of the Mean post-processing and the first CFL steps */
+  double ms_transport;    /* device time of the saturation steps */
+} mrcm_impes_stats;
+
+mrcm_status mrcm_impes_run(const mrcm_problem *problem, const mrcm_partition *partition,
+                           const mrcm_iface_space *iface, const mrcm_options *options,
+                           const mrcm_twophase *tp /* [host] */, const mrcm_impes_options *io /* [host] */,
+                           void *stream, double *S, mrcm_impes_stats *stats /* [host] */);
+
+/*
  * Sizes and counts of a built handle.  n_patch counts the patches of the
  * interface space (each carries two unknowns, so 2 n_patch is the interface
  * system's size, the N_Gamma of eq. (2.24) for one patch per interface);

@@ -5,7 +5,7 @@ tensors (FP64, contiguous) and the current HIP stream into the library calls
 ``mrcm_build_mbfs``, ``mrcm_assemble_interface``, ``mrcm_solve_interface``,
 ``mrcm_reconstruct`` and ``mrcm_postprocess_mean``, and the two-phase saturation
 step ``mrcm_transport_dt``, ``mrcm_transport_step``, ``mrcm_transport_advance``,
-``mrcm_mobility_scale``.  Every step of the method runs in the library's
+``mrcm_mobility_scale``, and the IMPES loop ``mrcm_impes_run``.  Every step of the method runs in the library's
 kernels; importing this package does not need a GPU, but every call does.
 """
 from __future__ import annotations
@@ -17,7 +17,8 @@ from ctypes import byref, c_double, c_int32, c_void_p
 import numpy as np
 
 from . import _lib
-from ._lib import CIfaceInfo, CInfo, CIfaceSpace, COptions, CPartition, CProblem, CSubInfo, CTwoPhase, MRCMError
+from ._lib import (CIfaceInfo, CImpesOptions, CImpesStats, CInfo, CIfaceSpace, COptions, CPartition, CProblem,
+                   CSubInfo, CTwoPhase, MRCMError)
 
 FP64 = 0
 FP32_IR = 1
@@ -274,6 +275,28 @@ class MRCM:
                                               _dev_ptr(pt, "pt", N, self.device), _dev_ptr(Ut, "Ut", 6 * N, self.device))
         _lib.check(code, "mrcm_postprocess_mean")
         return pt, Ut.view(6, N)
+
+    def impes_run(self, kx, ky, kz, q, S, mu_w, mu_o, skip, t_end=float("inf"), max_steps=0, cfl=1.0 / 6.0,
+                  dt_max=float("inf"), refine=1, stream=None):
+        """The IMPES loop (mrcm_impes_run) on this configuration: a Darcy
+        solve under K lambda(S) with the Mean post-processing every `skip`
+        saturation steps, while t <= t_end and fewer than max_steps (if > 0)
+        steps are taken.  S (float64 device tensor, N) holds the initial
+        saturation and receives the final one.  The run builds and frees its
+        own MBF handle.  Returns a dict of the loop's counts, time and device
+        milliseconds."""
+        N = self.n_cells
+        cp = CProblem.from_buffer_copy(self._cp)
+        for name, t in (("kx", kx), ("ky", ky), ("kz", kz), ("q", q)):
+            setattr(cp, name, _dev_ptr(t, name, N, self.device).value)
+        tp = CTwoPhase(self.pb.nx, self.pb.ny, self.pb.nz, self.pb.hx, self.pb.hy, self.pb.hz, float(mu_w),
+                       float(mu_o))
+        io = CImpesOptions(int(skip), int(max_steps), float(t_end), float(cfl), float(dt_max), int(refine))
+        st = CImpesStats()
+        code = self.lib.mrcm_impes_run(byref(cp), byref(self._part), byref(self._ifs), byref(self._opt), byref(tp),
+                                       byref(io), _stream_ptr(stream), _dev_ptr(S, "S", N, self.device), byref(st))
+        _lib.check(code, "mrcm_impes_run")
+        return {k: getattr(st, k) for k, _ in CImpesStats._fields_}
 
     def solve(self, kx, ky, kz, q, refine=0, stream=None, method=IFACE_AUTO):
         """Whole MRCM: MBFs, interface assembly and solve, reconstruction."""

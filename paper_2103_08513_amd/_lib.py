@@ -15,8 +15,9 @@ STATUS = {0: "MRCM_OK", -1: "MRCM_EINVAL", -2: "MRCM_ENOMEM", -3: "MRCM_ENOTSPD"
 EXPORTS = [
     "mrcm_build_mbfs", "mrcm_assemble_interface", "mrcm_solve_interface", "mrcm_reconstruct",
     "mrcm_query", "mrcm_get_subdomain", "mrcm_copy_mbfs", "mrcm_copy_flux", "mrcm_copy_factor",
-    "mrcm_interface_dims", "mrcm_copy_interface", "mrcm_interface_query", "mrcm_postprocess_mean", "mrcm_transport_step", "mrcm_transport_dt", "mrcm_transport_advance",
-    "mrcm_mobility_scale", "mrcm_mbfs_destroy", "mrcm_interface_destroy",
+    "mrcm_interface_dims", "mrcm_copy_interface", "mrcm_interface_query", "mrcm_postprocess_mean",
+    "mrcm_transport_step", "mrcm_transport_dt", "mrcm_transport_advance", "mrcm_mobility_scale", "mrcm_impes_run",
+    "mrcm_mbfs_destroy", "mrcm_interface_destroy",
     "mrcm_status_string", "mrcm_last_error", "mrcm_profile_enable", "mrcm_profile_reset",
     "mrcm_profile_get", "mrcm_autotune", "mrcm_autotune_cached", "mrcm_graph_capture", "mrcm_graph_launch", "mrcm_graph_check", "mrcm_graph_destroy",
     # mrcm_nn.h
@@ -59,6 +60,16 @@ class COptions(ctypes.Structure):
 class CTwoPhase(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("hx", c_double), ("hy", c_double),
                 ("hz", c_double), ("mu_w", c_double), ("mu_o", c_double)]
+
+
+class CImpesOptions(ctypes.Structure):
+    _fields_ = [("skip", c_int32), ("max_steps", c_int32), ("t_end", c_double), ("cfl", c_double),
+                ("dt_max", c_double), ("refine", c_int32)]
+
+
+class CImpesStats(ctypes.Structure):
+    _fields_ = [("darcy_solves", c_int32), ("steps", c_int32), ("t", c_double), ("ms_darcy", c_double),
+                ("ms_mean", c_double), ("ms_transport", c_double)]
 
 
 class CIfaceInfo(ctypes.Structure):
@@ -112,6 +123,8 @@ def load(path: str = LIB_PATH):
         "mrcm_transport_advance": ([P(CTwoPhase)] + [c_void_p] * 4 + [c_double, c_double] + [c_void_p] * 3, c_int32),
         "mrcm_transport_dt": ([P(CTwoPhase), c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p], c_int32),
         "mrcm_mobility_scale": ([P(CTwoPhase)] + [c_void_p] * 8, c_int32),
+        "mrcm_impes_run": ([P(CProblem), P(CPartition), P(CIfaceSpace), P(COptions), P(CTwoPhase), P(CImpesOptions),
+                            c_void_p, c_void_p, P(CImpesStats)], c_int32),
         "mrcm_query": ([c_void_p, P(CInfo)], c_int32),
         "mrcm_get_subdomain": ([c_void_p, c_int32, P(CSubInfo)], c_int32),
         "mrcm_copy_mbfs": ([c_void_p, c_int32, c_void_p], c_int32),

@@ -1586,6 +1586,123 @@ mrcm_status mrcm_postprocess_mean(const mrcm_mbfs *cmb, const double *U, void *s
   return read_status(mb->st, s, "mrcm_postprocess_mean");
 }
 
+namespace {
+
+// Device buffers, events and handles of one IMPES run, released on every
+// return path.
+struct ImpesState {
+  std::vector<double *> bufs;
+  std::vector<hipEvent_t> ev;
+  mrcm_mbfs *mb = nullptr;
+  mrcm_interface *ih = nullptr;
+  ~ImpesState() {
+    if (ih) mrcm_interface_destroy(ih);
+    if (mb) mrcm_mbfs_destroy(mb);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (double *p : bufs) (void)hipFree(p);
+  }
+  hipError_t alloc(double **p, size_t n) {
+    hipError_t e = dev_alloc(p, n);
+    if (e == hipSuccess) bufs.push_back(*p);
+    return e;
+  }
+};
+
+float elapsed_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.0f;
+  return hipEventElapsedTime(&ms, a, b) == hipSuccess ? ms : 0.0f;
+}
+
+}  // namespace
+
+mrcm_status mrcm_impes_run(const mrcm_problem *pb, const mrcm_partition *part, const mrcm_iface_space *ifs,
+                           const mrcm_options *opt, const mrcm_twophase *tp, const mrcm_impes_options *io,
+                           void *stream, double *S, mrcm_impes_stats *stats) {
+  if (!pb || !part || !ifs || !opt || !io || !S) return fail(MRCM_EINVAL, "null argument");
+  TwoPhaseGrid tg;
+  mrcm_status st = twophase_grid(tp, tg);
+  if (st != MRCM_OK) return st;
+  if (tp->nx != pb->nx || tp->ny != pb->ny || tp->nz != pb->nz || tp->hx != pb->hx || tp->hy != pb->hy ||
+      tp->hz != pb->hz)
+    return fail(MRCM_EINVAL, "the two-phase grid differs from the problem's");
+  if (!pb->kx || !pb->ky || !pb->kz || !pb->q) return fail(MRCM_EINVAL, "null permeability or sources");
+  if (io->skip < 1) return fail(MRCM_EINVAL, "skip must be at least 1");
+  if (io->max_steps < 0) return fail(MRCM_EINVAL, "max_steps must be non-negative");
+  if (std::isnan(io->t_end) || (io->max_steps == 0 && !std::isfinite(io->t_end)))
+    return fail(MRCM_EINVAL, "the loop needs a finite t_end or a step cap");
+  if (!(io->cfl > 0.0) || !std::isfinite(io->cfl)) return fail(MRCM_EINVAL, "cfl must be positive and finite");
+  if (!(io->dt_max > 0.0)) return fail(MRCM_EINVAL, "dt_max must be positive (or +inf)");
+  if (io->refine < 0 || io->refine > 20) return fail(MRCM_EINVAL, "refine must be within 0 .. 20");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t N = (size_t)pb->nx * pb->ny * pb->nz;
+  ImpesState W;
+  double *ke, *pr, *U, *Ut, *pt, *S2, *dts, *X = nullptr;
+  HIP_TRY(W.alloc(&ke, 3 * N));
+  HIP_TRY(W.alloc(&pr, N));
+  HIP_TRY(W.alloc(&U, 6 * N));
+  HIP_TRY(W.alloc(&Ut, 6 * N));
+  HIP_TRY(W.alloc(&pt, N));
+  HIP_TRY(W.alloc(&S2, N));
+  HIP_TRY(W.alloc(&dts, 2));
+  W.ev.resize(5);
+  for (auto &e : W.ev) HIP_TRY(hipEventCreate(&e));
+  mrcm_problem pe = *pb;  // the Darcy problem of each solve: K lambda(S)
+  pe.kx = ke;
+  pe.ky = ke + N;
+  pe.kz = ke + 2 * N;
+  double t = 0.0, ms_d = 0.0, ms_m = 0.0, ms_t = 0.0;
+  int32_t ns = 0, nd = 0;
+  double *Scur = S, *Snext = S2, *dcur = dts, *dnext = dts + 1;
+  auto finish = [&](mrcm_status code) -> mrcm_status {
+    // the caller's S holds the last finite state
+    if (Scur != S) {
+      if (hipMemcpyAsync(S, Scur, N * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail(MRCM_EHIP, "impes: copy of the final saturation failed");
+    }
+    if (stats) *stats = mrcm_impes_stats{nd, ns, t, ms_d, ms_m, ms_t};
+    return code;
+  };
+  while (t <= io->t_end && (io->max_steps == 0 || ns < io->max_steps)) {
+    const bool darcy = ns % io->skip == 0;
+    if (darcy) {
+      HIP_TRY(hipEventRecord(W.ev[0], s));
+      HIP_TRY(launch_mobility(tg, Scur, pb->kx, pb->ky, pb->kz, ke, ke + N, ke + 2 * N, s));
+      if ((st = mrcm_build_mbfs(&pe, part, ifs, opt, stream, &W.mb)) != MRCM_OK) return st;
+      if (!X) HIP_TRY(W.alloc(&X, 2 * (size_t)W.mb->G.n_patch));
+      if ((st = mrcm_assemble_interface(W.mb, stream, &W.ih)) != MRCM_OK) return st;
+      if ((st = mrcm_solve_interface(W.ih, MRCM_IFACE_AUTO, 0.0, io->refine, stream, X, nullptr, nullptr)) !=
+          MRCM_OK)
+        return st;
+      if ((st = mrcm_reconstruct(W.mb, X, stream, pr, U)) != MRCM_OK) return st;
+      HIP_TRY(hipEventRecord(W.ev[1], s));
+      if ((st = mrcm_postprocess_mean(W.mb, U, stream, pt, Ut)) != MRCM_OK) return st;
+      HIP_TRY(launch_transport_dt(tg, Ut, Scur, io->cfl, io->dt_max, dcur, s));
+      HIP_TRY(hipEventRecord(W.ev[2], s));
+      ++nd;
+    }
+    HIP_TRY(hipEventRecord(W.ev[3], s));
+    HIP_TRY(launch_transport_advance(tg, Ut, pb->q, Scur, dcur, io->cfl, io->dt_max, Snext, dnext, s));
+    HIP_TRY(hipEventRecord(W.ev[4], s));
+    double dt = 0.0;
+    HIP_TRY(hipMemcpyAsync(&dt, dcur, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (darcy) {
+      ms_d += elapsed_ms(W.ev[0], W.ev[1]);
+      ms_m += elapsed_ms(W.ev[1], W.ev[2]);
+    }
+    ms_t += elapsed_ms(W.ev[3], W.ev[4]);
+    if (!std::isfinite(dt))
+      return finish(fail(MRCM_EINVAL, "impes: the step is not finite (nothing moves under the CFL bound and dt_max "
+                                      "is infinite)"));
+    t += dt;
+    std::swap(Scur, Snext);
+    std::swap(dcur, dnext);
+    ++ns;
+  }
+  return finish(MRCM_OK);
+}
+
 mrcm_status mrcm_reconstruct(const mrcm_mbfs *mb, const double *X, void *stream, double *p,
                              double *U) {
   if (!mb || !p || !U) return fail(MRCM_EINVAL, "null argument");

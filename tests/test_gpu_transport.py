@@ -17,7 +17,8 @@ mrcm_transport_dt, mrcm_mobility_scale; eqs. (transporte_discreto),
 * A grid of 537.9M cells (8N > 2^32): the 64-bit index form against the
   oracle on sub-boxes reaching the last plane.
 * Two Darcy calls of an IMPES loop on a small case (K lambda(S), MRCM, Mean,
-  three CFL steps each) against the same loop on the oracle.
+  three CFL steps each) against the same loop on the oracle, from Python and
+  through the library's own loop (mrcm_impes_run, with its stop at t_end).
 * The step fused with the next step's CFL reduction (mrcm_transport_advance)
   equals the two separate calls bitwise, and chains against the oracle.
 * Bad descriptors and arguments are refused.
@@ -366,6 +367,67 @@ def test_impes_loop_matches_the_oracle():
     print(f"  S range [{S.min():.3f}, {S.max():.3f}], max err {np.max(np.abs(got - S)):.2e}", flush=True)
     assert S.max() > 0.05                     # water has entered
     assert np.max(np.abs(got - S)) <= 1e-8
+
+
+def _oracle_impes(case, geo, mu_w, mu_o, C, n_steps, dt_s):
+    """The overview algorithm's loop on the oracle: S after n_steps and the
+    step sizes taken."""
+    pb = case.problem
+    S = np.zeros(pb.n)
+    dts = []
+    Ut = None
+    for ns in range(n_steps):
+        if ns % C == 0:
+            lam = mobility(S, mu_w, mu_o)
+            c2 = copy.copy(case)
+            c2.problem = copy.copy(pb)
+            c2.problem.kx, c2.problem.ky, c2.problem.kz = pb.kx * lam, pb.ky * lam, pb.kz * lam
+            U = mrcm_solve(c2).U.reshape(6, -1)
+            _, Ut = mean_postprocess(c2.problem, geo, U)
+        dt = cfl_dt(pb.dims, pb.h, Ut, S, mu_w, mu_o, cfl=1.0 / 6.0, dt_max=dt_s)
+        S = transport_step(pb.dims, pb.h, Ut, pb.q, S, dt, mu_w, mu_o)
+        dts.append(dt)
+    return S, dts
+
+
+def test_impes_driver_matches_the_oracle_loop():
+    """mrcm_impes_run: seven steps with the skipping constant 3 (Darcy solves
+    before steps 0, 3 and 6) from an all-oil start, against the oracle's
+    loop; then the stop at t_end; then an infinite step refused."""
+    import paper_2103_08513_amd as lib
+    case = small_case((12, 10, 6), (2, 2, 2), seed=14)
+    pb = case.problem
+    geo = Geometry(pb.dims, case.partition, case.iface)
+    mu_w, mu_o, C = 1.0, 5.0, 3
+    dt_s = 0.2 * pb.h[0] * pb.h[1] * pb.h[2] / np.max(pb.q)
+    S_ref, dts = _oracle_impes(case, geo, mu_w, mu_o, C, 7, dt_s)
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha)
+    kx, ky, kz, q = _dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q)
+    S = torch.zeros(pb.n, dtype=torch.float64, device="cuda")
+    st = m.impes_run(kx, ky, kz, q, S, mu_w, mu_o, skip=C, max_steps=7, dt_max=dt_s)
+    got = S.cpu().numpy()
+    print(f"  {st}; max err {np.max(np.abs(got - S_ref)):.2e}", flush=True)
+    assert st["steps"] == 7 and st["darcy_solves"] == 3
+    assert abs(st["t"] - sum(dts)) <= 1e-10 * sum(dts)
+    assert S_ref.max() > 0.05 and np.max(np.abs(got - S_ref)) <= 1e-8
+    # t_end between the fourth and fifth step's start: four steps
+    T = sum(dts[:4]) * (1.0 - 1e-6)
+    S = torch.zeros(pb.n, dtype=torch.float64, device="cuda")
+    st = m.impes_run(kx, ky, kz, q, S, mu_w, mu_o, skip=C, t_end=T, dt_max=dt_s)
+    assert st["steps"] == 4 and st["darcy_solves"] == 2, st
+    S4, _ = _oracle_impes(case, geo, mu_w, mu_o, C, 4, dt_s)
+    assert np.max(np.abs(S.cpu().numpy() - S4)) <= 1e-8
+    # all oil and no cap on the step: the first step is infinite
+    S = torch.zeros(pb.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.MRCMError) as e:
+        m.impes_run(kx, ky, kz, q, S, mu_w, mu_o, skip=C, max_steps=2)
+    assert e.value.code == -1
+    assert torch.count_nonzero(S).item() == 0
+    for bad in (dict(skip=0, max_steps=2), dict(skip=C), dict(skip=C, max_steps=2, refine=21),
+                dict(skip=C, max_steps=2, cfl=0.0)):
+        with pytest.raises(lib.MRCMError):
+            m.impes_run(kx, ky, kz, q, S, mu_w, mu_o, **{"dt_max": dt_s, **bad})
+    m.close()
 
 
 def test_bad_arguments_are_refused():
