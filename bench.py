@@ -294,6 +294,43 @@ def time_transport(model, pb, U, steps, cpu=True):
     return out
 
 
+def time_impes(case, skip, n_darcy):
+    """The IMPES loop in the library (mrcm_impes_run) on the workload: from an
+    all-oil start, mu_o / mu_w = 5, cfl 1/6, the loop's own step
+    dt_max = 0.2 V / max q, `skip` saturation steps per Darcy solve (the
+    paper's skipping constant C), n_darcy Darcy solves.  Its own MBF handle
+    (created by the first Darcy solve, whose device time includes that)."""
+    import torch
+    import paper_2103_08513_amd as lib
+    pb = case.problem
+    dev = torch.device("cuda:0")
+    kx, ky, kz, q = (torch.as_tensor(a, dtype=torch.float64, device=dev) for a in (pb.kx, pb.ky, pb.kz, pb.q))
+    model = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha)
+    S = torch.zeros(pb.n, dtype=torch.float64, device=dev)
+    dt_max = 0.2 * pb.hx * pb.hy * pb.hz / float(np.max(pb.q))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = model.impes_run(kx, ky, kz, q, S, 1.0, 5.0, skip=skip, max_steps=skip * n_darcy, dt_max=dt_max, refine=1)
+    wall = time.perf_counter() - t0
+    water = float(S.sum()) * pb.hx * pb.hy * pb.hz
+    injected = st["t"] * float(np.sum(pb.q[pb.q > 0]))
+    model.close()
+    del kx, ky, kz, q, S
+    torch.cuda.empty_cache()
+    return {"skip": skip, "darcy_solves": st["darcy_solves"], "steps": st["steps"], "t": st["t"], "wall_s": wall,
+            "wall_s_per_darcy_period": wall / max(1, st["darcy_solves"]),
+            "ms_darcy_first": st["ms_darcy_first"],
+            "ms_darcy_per_later_solve": ((st["ms_darcy"] - st["ms_darcy_first"]) / (st["darcy_solves"] - 1)
+                                         if st["darcy_solves"] > 1 else None),
+            "ms_mean_per_solve": st["ms_mean"] / max(1, st["darcy_solves"]),
+            "ms_per_saturation_step": st["ms_transport"] / max(1, st["steps"]),
+            "water_in_place_over_injected": water / injected if injected > 0 else None,
+            "what": "mrcm_impes_run from an all-oil start: a Darcy solve (K lambda(S), MBFs rebuilt in place, "
+                    "interface, reconstruction) and the Mean post-processing every C saturation steps; device times "
+                    "from HIP events (the first Darcy solve creates the MBF and interface handles), wall time "
+                    "around the call (one synchronisation per saturation step)"}
+
+
 def block_errors(case5, precisions, procs, refine):
     """The workload's exact 60x220x85 corner block, laid out as the 60x220x85
     workload, solved on the GPU in each form and by the whole oracle."""
@@ -508,6 +545,8 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the autotuner first (a handle per candidate)")
     ap.add_argument("--no-mean", action="store_true", help="skip the Mean post-processing measurement")
     ap.add_argument("--no-transport", action="store_true", help="skip the saturation-step measurement")
+    ap.add_argument("--impes-skip", type=int, default=600, help="skipping constant C of the IMPES leg")
+    ap.add_argument("--impes-darcy", type=int, default=3, help="Darcy solves of the IMPES leg (0: skip it)")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="subdomains in the oracle's timed sample")
     ap.add_argument("--copy-calibration", type=float, default=None, metavar="MB",
                     help="only run a device copy of this many MB (counter calibration) and exit")
@@ -540,6 +579,13 @@ def main():
         tr = res["transport"]
         log(f"transport: {tr['ms_per_step']:.3f} ms/step ({tr['roofline']['achieved']:.0f} GB/s), CFL reduction "
             f"{tr['ms_cfl_reduction']:.3f} ms, mobility {tr['ms_mobility']:.3f} ms")
+    impes = None
+    if args.impes_darcy > 0 and not (args.no_mean or args.no_transport):
+        impes = time_impes(case, args.impes_skip, args.impes_darcy)
+        log(f"impes: C {impes['skip']}, {impes['darcy_solves']} Darcy solves, {impes['steps']} steps in "
+            f"{impes['wall_s']:.2f} s (Darcy: first {impes['ms_darcy_first']:.0f} ms, later "
+            f"{impes['ms_darcy_per_later_solve'] or 0:.0f} ms; Mean "
+            f"{impes['ms_mean_per_solve']:.0f} ms per solve, {impes['ms_per_saturation_step']:.3f} ms per step)")
     secondary = None
     if not args.no_secondary:
         secondary = run_gpu(case, 1 - prec, args.steps, args.warmup, args.refine)
@@ -601,6 +647,7 @@ def main():
         "cpu_baseline": cpu,
         "mean_postprocess": res["mean"],
         "transport": res["transport"],
+        "impes": impes,
     }
     if secondary is not None:
         line["other_precision"] = _form_line(secondary, info.n_mbfs, pb.n, 1 - prec,

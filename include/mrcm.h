@@ -492,6 +492,7 @@ typedef struct {
   int32_t steps;          /* saturation steps taken */
   double t;               /* time reached */
   double ms_darcy;        /* device time of the mobility, MBF build, interface and reconstruction */
+  double ms_darcy_first;  /* the part of ms_darcy spent in the first solve (which creates the handles) */
   double ms_mean;         /* device time of the Mean post-processing and the first CFL steps */
   double ms_transport;    /* device time of the saturation steps */
 } mrcm_impes_stats;

@@ -69,7 +69,7 @@ class CImpesOptions(ctypes.Structure):
 
 class CImpesStats(ctypes.Structure):
     _fields_ = [("darcy_solves", c_int32), ("steps", c_int32), ("t", c_double), ("ms_darcy", c_double),
-                ("ms_mean", c_double), ("ms_transport", c_double)]
+                ("ms_darcy_first", c_double), ("ms_mean", c_double), ("ms_transport", c_double)]
 
 
 class CIfaceInfo(ctypes.Structure):

@@ -1650,7 +1650,7 @@ mrcm_status mrcm_impes_run(const mrcm_problem *pb, const mrcm_partition *part, c
   pe.kx = ke;
   pe.ky = ke + N;
   pe.kz = ke + 2 * N;
-  double t = 0.0, ms_d = 0.0, ms_m = 0.0, ms_t = 0.0;
+  double t = 0.0, ms_d = 0.0, ms_d1 = 0.0, ms_m = 0.0, ms_t = 0.0;
   int32_t ns = 0, nd = 0;
   double *Scur = S, *Snext = S2, *dcur = dts, *dnext = dts + 1;
   auto finish = [&](mrcm_status code) -> mrcm_status {
@@ -1660,7 +1660,7 @@ mrcm_status mrcm_impes_run(const mrcm_problem *pb, const mrcm_partition *part, c
           hipStreamSynchronize(s) != hipSuccess)
         return fail(MRCM_EHIP, "impes: copy of the final saturation failed");
     }
-    if (stats) *stats = mrcm_impes_stats{nd, ns, t, ms_d, ms_m, ms_t};
+    if (stats) *stats = mrcm_impes_stats{nd, ns, t, ms_d, ms_d1, ms_m, ms_t};
     return code;
   };
   while (t <= io->t_end && (io->max_steps == 0 || ns < io->max_steps)) {
@@ -1688,6 +1688,7 @@ mrcm_status mrcm_impes_run(const mrcm_problem *pb, const mrcm_partition *part, c
     HIP_TRY(hipMemcpyAsync(&dt, dcur, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (darcy) {
+      if (nd == 1) ms_d1 = elapsed_ms(W.ev[0], W.ev[1]);
       ms_d += elapsed_ms(W.ev[0], W.ev[1]);
       ms_m += elapsed_ms(W.ev[1], W.ev[2]);
     }
