@@ -205,6 +205,85 @@ void check_validation() {
   for (int code = -8; code <= 0; ++code) CHECK(mrcm_status_string((mrcm_status)code) != nullptr);
 }
 
+// The two-phase calls' and the IMPES loop's argument checks, every one of
+// which returns before anything reaches the device.
+void check_twophase_validation() {
+  double *d = const_cast<double *>(kFake), *d2 = d + 1;
+  const mrcm_twophase good{4, 3, 2, 1.0, 1.0, 1.0, 1.0, 2.0};
+  auto expect = [&](mrcm_status st, const char *what) {
+    CHECK(st == MRCM_EINVAL);
+    CHECK(std::strstr(mrcm_last_error(), what) != nullptr);
+  };
+  const mrcm_twophase bad[] = {{0, 3, 2, 1.0, 1.0, 1.0, 1.0, 2.0},
+                               {4, 3, 2, -1.0, 1.0, 1.0, 1.0, 2.0},
+                               {4, 3, 2, 1.0, 1.0, 1.0, 0.0, 2.0},
+                               {4, 3, 2, 1.0, 1.0, 1.0, 1.0, std::numeric_limits<double>::infinity()},
+                               {4, 3, 2, 1.0, std::numeric_limits<double>::quiet_NaN(), 1.0, 1.0, 2.0}};
+  for (const mrcm_twophase &b : bad) {
+    CHECK(mrcm_transport_step(&b, d, nullptr, d, d, nullptr, d2) == MRCM_EINVAL);
+    CHECK(mrcm_transport_dt(&b, d, d, 1.0, 1.0, nullptr, d) == MRCM_EINVAL);
+    CHECK(mrcm_transport_advance(&b, d, nullptr, d, d, 1.0, 1.0, nullptr, d2, d2) == MRCM_EINVAL);
+    CHECK(mrcm_mobility_scale(&b, d, d, d, d, nullptr, d, d, d) == MRCM_EINVAL);
+  }
+  expect(mrcm_transport_step(nullptr, d, nullptr, d, d, nullptr, d2), "descriptor");
+  expect(mrcm_transport_step(&good, d, nullptr, d, d, nullptr, d), "overlap");
+  expect(mrcm_transport_step(&good, nullptr, nullptr, d, d, nullptr, d2), "null");
+  expect(mrcm_transport_dt(&good, d, d, 0.0, 1.0, nullptr, d), "cfl");
+  expect(mrcm_transport_dt(&good, d, d, 1.0, -1.0, nullptr, d), "dt_max");
+  expect(mrcm_transport_advance(&good, d, nullptr, d, d, 1.0, 1.0, nullptr, d2, d), "dt_next");
+  expect(mrcm_transport_advance(&good, d, nullptr, d, d, 1.0, 1.0, nullptr, d, d2), "overlap");
+  expect(mrcm_mobility_scale(&good, d, nullptr, d, d, nullptr, d, d, d), "null");
+  // the loop: a problem of the same grid
+  mrcm_problem pb{};
+  pb.nx = 4;
+  pb.ny = 3;
+  pb.nz = 2;
+  pb.hx = pb.hy = pb.hz = 1.0;
+  pb.kx = pb.ky = pb.kz = pb.q = kFake;
+  pb.pin_cell = 0;
+  int32_t cx[2] = {0, 4}, cy[2] = {0, 3}, cz[2] = {0, 2};
+  mrcm_partition part{};
+  part.ndx = part.ndy = part.ndz = 1;
+  part.cut_x = cx;
+  part.cut_y = cy;
+  part.cut_z = cz;
+  mrcm_iface_space ifs{};
+  mrcm_options opt{};
+  opt.alpha = 1.0;
+  const mrcm_impes_options io{3, 6, 1.0, 0.5, 1.0, 1};
+  mrcm_impes_stats stats{};
+  auto run = [&](const mrcm_twophase *tp, mrcm_impes_options o) {
+    return mrcm_impes_run(&pb, &part, &ifs, &opt, tp, &o, nullptr, d, &stats);
+  };
+  expect(mrcm_impes_run(&pb, &part, &ifs, &opt, &good, &io, nullptr, nullptr, &stats), "null");
+  const mrcm_twophase other{4, 3, 3, 1.0, 1.0, 1.0, 1.0, 2.0};
+  expect(run(&other, io), "differs");
+  mrcm_impes_options o = io;
+  o.skip = 0;
+  expect(run(&good, o), "skip");
+  o = io;
+  o.max_steps = -1;
+  expect(run(&good, o), "max_steps");
+  o = io;
+  o.max_steps = 0;
+  o.t_end = std::numeric_limits<double>::infinity();
+  expect(run(&good, o), "t_end");
+  o = io;
+  o.t_end = std::numeric_limits<double>::quiet_NaN();
+  expect(run(&good, o), "t_end");
+  o = io;
+  o.cfl = 0.0;
+  expect(run(&good, o), "cfl");
+  o = io;
+  o.dt_max = 0.0;
+  expect(run(&good, o), "dt_max");
+  o = io;
+  o.refine = 21;
+  expect(run(&good, o), "refine");
+  pb.q = nullptr;
+  expect(run(&good, io), "sources");
+}
+
 // The cache reader: malformed lines are skipped, the entry for the shapes'
 // key is a hit, and its values come back.
 void check_tune_cache(const char *path) {
@@ -260,6 +339,7 @@ int main(int argc, char **argv) {
   for (const Config &c : configs)
     for (int precision : {MRCM_FP64, MRCM_FP32_IR}) check_geometry_and_plan(c, precision);
   check_validation();
+  check_twophase_validation();
   check_tune_cache(argc > 1 ? argv[1] : "tune_cache.txt");
   std::printf("host ABI checks: %d failures\n", g_fails);
   return g_fails == 0 ? 0 : 1;
