@@ -2,7 +2,8 @@
 // volume Buckley-Leverett update with the divergence compensation (eqs.
 // (transporte_discreto), (flux_disc_up)), the CFL time step (eq. (CFL)) and
 // the total mobility that scales each Darcy solve's permeability (Sec. 5).
-// All three are streaming stencils, one thread per cell, bound by HBM.
+// All are bound by HBM: the step walks z-marching tiles, the CFL reduction
+// and the mobility are plain streams over the cells.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,8 +28,8 @@ __device__ __forceinline__ double frac_flow_deriv(double s, double M) {
 
 }  // namespace
 
-// Workgroups of 256 threads; the grids hold as many as are resident at once
-// (a multiple of 8) and stride over the work.
+// Workgroups of 256 threads; the grids of the step and of the CFL reduction
+// hold as many as are resident at once and stride over the work.
 constexpr int kTile = 256;
 
 // Largest speed of a workgroup into the bit pattern of a non-negative double
@@ -207,7 +208,6 @@ __global__ __launch_bounds__(256) void k_mobility(TwoPhaseGrid t, const double *
 }
 
 namespace {
-
 
 ZTiles transport_tiles(const TwoPhaseGrid &t) {
   return ZTiles{(t.nx + 15 + kZX - 1) / kZX, (t.ny + kZY - 1) / kZY, (t.nz + kZLen - 1) / kZLen};
