@@ -568,7 +568,7 @@ mrcm_status mrcm_copy_interface(const mrcm_interface *iface, double *A, double *
 enum { MRCM_STAGE_COEF = 0, MRCM_STAGE_FACTOR, MRCM_STAGE_RHS, MRCM_STAGE_SOLVE,
        MRCM_STAGE_RESIDUAL, MRCM_STAGE_REFINE, MRCM_STAGE_FLUX, MRCM_STAGE_ASSEMBLE,
        MRCM_STAGE_LU, MRCM_STAGE_SWEEP, MRCM_STAGE_RECONSTRUCT, MRCM_STAGE_PCG,
-       MRCM_STAGE_FALLBACK, MRCM_STAGE_SOLVE_REST, MRCM_STAGE_MEAN, MRCM_STAGE_COUNT };
+       MRCM_STAGE_FALLBACK, MRCM_STAGE_SOLVE_REST, MRCM_STAGE_MEAN, MRCM_STAGE_TRANSPORT, MRCM_STAGE_COUNT };
 typedef struct {
   double ms[16];        /* accumulated milliseconds per stage */
   int64_t count[16];    /* occurrences per stage */

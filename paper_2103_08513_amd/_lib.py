@@ -29,7 +29,7 @@ EXPORTS = [
 ]
 
 STAGES = ["coef", "factor", "rhs", "solve", "residual", "refine", "flux", "assemble", "lu", "sweep",
-          "reconstruct", "pcg", "fallback", "solve_rest", "mean"]
+          "reconstruct", "pcg", "fallback", "solve_rest", "mean", "transport"]
 
 
 class CProblem(ctypes.Structure):

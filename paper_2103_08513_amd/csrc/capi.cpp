@@ -1522,7 +1522,13 @@ mrcm_status mrcm_transport_advance(const mrcm_twophase *tp, const double *U, con
   if (dt_next == dt) return fail(MRCM_EINVAL, "dt_next must not be dt");
   if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(MRCM_EINVAL, "cfl must be positive and finite");
   if (!(dt_max > 0.0)) return fail(MRCM_EINVAL, "dt_max must be positive (or +inf)");
-  HIP_TRY(launch_transport_advance(t, U, q, S, dt, cfl, dt_max, S_out, dt_next, (hipStream_t)stream));
+  const hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_speed_clear(dt_next, s));
+  {
+    Stage st(MRCM_STAGE_TRANSPORT, s);
+    HIP_TRY(launch_transport_fused(t, U, q, S, dt, S_out, dt_next, s));
+  }
+  HIP_TRY(launch_speed_finish(t, cfl, dt_max, dt_next, s));
   return MRCM_OK;
 }
 
@@ -1644,6 +1650,11 @@ mrcm_status mrcm_impes_run(const mrcm_problem *pb, const mrcm_partition *part, c
   HIP_TRY(W.alloc(&pt, N));
   HIP_TRY(W.alloc(&S2, N));
   HIP_TRY(W.alloc(&dts, 2));
+  // q holds through the run: the step reads it only in the tiles it marks
+  double *marks = nullptr;
+  HIP_TRY(W.alloc(&marks, (size_t)(transport_tile_count(tg) + 7) / 8));
+  unsigned char *src_tiles = reinterpret_cast<unsigned char *>(marks);
+  HIP_TRY(launch_source_tiles(tg, pb->q, src_tiles, s));
   W.ev.resize(5);
   for (auto &e : W.ev) HIP_TRY(hipEventCreate(&e));
   mrcm_problem pe = *pb;  // the Darcy problem of each solve: K lambda(S)
@@ -1682,7 +1693,12 @@ mrcm_status mrcm_impes_run(const mrcm_problem *pb, const mrcm_partition *part, c
       ++nd;
     }
     HIP_TRY(hipEventRecord(W.ev[3], s));
-    HIP_TRY(launch_transport_advance(tg, Ut, pb->q, Scur, dcur, io->cfl, io->dt_max, Snext, dnext, s));
+    HIP_TRY(launch_speed_clear(dnext, s));
+    {
+      Stage stg(MRCM_STAGE_TRANSPORT, s);
+      HIP_TRY(launch_transport_fused(tg, Ut, pb->q, Scur, dcur, Snext, dnext, s, src_tiles));
+    }
+    HIP_TRY(launch_speed_finish(tg, io->cfl, io->dt_max, dnext, s));
     HIP_TRY(hipEventRecord(W.ev[4], s));
     double dt = 0.0;
     HIP_TRY(hipMemcpyAsync(&dt, dcur, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -64,9 +64,17 @@ hipError_t launch_mean_velocity(const Geom &g, const double *U, const double *P,
 // its CFL time step into a device scalar, and K lambda(S).
 hipError_t launch_transport(const TwoPhaseGrid &t, const double *U, const double *q, const double *S,
                             const double *dt, double *Sout, hipStream_t s);
-hipError_t launch_transport_advance(const TwoPhaseGrid &t, const double *U, const double *q, const double *S,
-                                    const double *dt, double cfl, double dt_max, double *Sout, double *dt_next,
-                                    hipStream_t s);
+// The fused step in three launches: clear dt_next's accumulator, the step
+// with the CFL speed of its result, turn the accumulator into the step.
+hipError_t launch_speed_clear(double *dt, hipStream_t s);
+hipError_t launch_transport_fused(const TwoPhaseGrid &t, const double *U, const double *q, const double *S,
+                                  const double *dt, double *Sout, double *dt_next, hipStream_t s,
+                                  const unsigned char *src_tiles = nullptr);
+hipError_t launch_speed_finish(const TwoPhaseGrid &t, double cfl, double dt_max, double *dt, hipStream_t s);
+// Tiles of the saturation step, and their marks where q has a source (for
+// launch_transport_fused's src_tiles: q is then read in those tiles only).
+long long transport_tile_count(const TwoPhaseGrid &t);
+hipError_t launch_source_tiles(const TwoPhaseGrid &t, const double *q, unsigned char *flags, hipStream_t s);
 hipError_t launch_transport_dt(const TwoPhaseGrid &t, const double *U, const double *S, double cfl, double dt_max,
                                double *dt, hipStream_t s);
 hipError_t launch_mobility(const TwoPhaseGrid &t, const double *S, const double *kx, const double *ky,

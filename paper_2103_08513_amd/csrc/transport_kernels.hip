@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "launch.h"
 
@@ -94,11 +95,14 @@ __device__ __forceinline__ void st(double *__restrict__ a, I i, double v) {
 }
 
 // I: the cell index type, uint32_t when 8 N < 2^32, else long long.
+// src_tiles: NULL, or one byte per tile, nonzero where q has a nonzero entry
+// (q is read in those tiles only).
 template <bool kSpeed, typename I>
 __global__ __launch_bounds__(kTile) void k_transport(TwoPhaseGrid t, ZTiles zt, const double *__restrict__ U,
-                                                     const double *__restrict__ q, const double *__restrict__ S,
-                                                     const double *__restrict__ dtp, double *__restrict__ Sout,
-                                                     unsigned long long *__restrict__ vmax) {
+                                                     const double *__restrict__ q,
+                                                     const unsigned char *__restrict__ src_tiles,
+                                                     const double *__restrict__ S, const double *__restrict__ dtp,
+                                                     double *__restrict__ Sout, unsigned long long *__restrict__ vmax) {
   const long long N = (long long)t.nx * t.ny * t.nz;
   const long long ntiles = (long long)zt.nxt * zt.nyt * zt.nzt;
   const double M = t.mu_o / t.mu_w;
@@ -117,6 +121,7 @@ __global__ __launch_bounds__(kTile) void k_transport(TwoPhaseGrid t, ZTiles zt, 
     const int z0 = (int)(r / zt.nyt) * kZLen, z1 = min(z0 + kZLen, t.nz);
     const int x = xt * kZX - (int)((sy * (I)y + sz * (I)z0) & 15) + lane;
     if (x < 0 || x >= t.nx || y >= t.ny) continue;
+    const bool tq = q != nullptr && (src_tiles == nullptr || src_tiles[tile] != 0);
     I c = (I)x + sy * (I)y + sz * (I)z0;
     // phi below the chunk (unused at z = 0: a wall) and at its first plane
     double pbelow = frac_flow(ld(S, z0 > 0 ? c - sz : c), M);
@@ -131,7 +136,7 @@ __global__ __launch_bounds__(kTile) void k_transport(TwoPhaseGrid t, ZTiles zt, 
       double u[6];
 #pragma unroll
       for (int f = 0; f < 6; ++f) u[f] = ld(Uf[f], c);
-      const double qc = q ? ld(q, c) : 0.0;
+      const double qc = tq ? ld(q, c) : 0.0;
       const double pabove = frac_flow(sabove, M);
       const double pe = frac_flow(se, M);
       const double pl = __shfl_up(pc, 1), pr = __shfl_down(pc, 1);
@@ -207,6 +212,27 @@ __global__ __launch_bounds__(256) void k_mobility(TwoPhaseGrid t, const double *
   oz[c] = lam * kz[c];
 }
 
+// Marks the tiles of k_transport that hold a cell with q != 0 (one thread
+// per cell; every writer stores 1).  The tile of cell (x, y, z): the
+// x-segment counts from the row's line offset on the tile's first plane.
+__global__ __launch_bounds__(256) void k_source_tiles(TwoPhaseGrid t, ZTiles zt, const double *__restrict__ q,
+                                                      unsigned char *__restrict__ flags) {
+  const long long N = (long long)t.nx * t.ny * t.nz;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N || q[c] == 0.0) return;
+  const long long sy = t.nx, sz = (long long)t.nx * t.ny;
+  const int x = (int)(c % t.nx), y = (int)((c / t.nx) % t.ny), z = (int)(c / sz);
+  const int z0 = z / kZLen * kZLen;
+  const int a = (int)((sy * y + sz * z0) & 15);
+  const long long tile = (long long)((x + a) / kZX) + zt.nxt * ((long long)(y / kZY) + (long long)zt.nyt * (z / kZLen));
+  flags[tile] = 1;
+}
+
+__global__ void k_fill_u8(unsigned char *p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
 namespace {
 
 ZTiles transport_tiles(const TwoPhaseGrid &t) {
@@ -216,13 +242,28 @@ ZTiles transport_tiles(const TwoPhaseGrid &t) {
 // Resident workgroups of kernel k over the whole device (the kernels stride
 // over their tiles, so the whole grid must be resident: a workgroup that
 // starts late would hold back the end), and no more than the tiles.
+// The queries run once per kernel and device (per host thread): the step is
+// launched thousands of times in a run.
 unsigned resident_grid(const void *k, long long ntiles) {
-  int dev = 0, cus = 0, nb = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                               hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kTile, 0) != hipSuccess)
-    cus = nb = 0;
-  const long long g = std::max(8LL, (long long)cus * std::max(nb, 1));
+  struct Entry {
+    const void *k;
+    int dev;
+    long long g;
+  };
+  thread_local std::vector<Entry> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  long long g = 0;
+  for (const Entry &e : cache)
+    if (e.k == k && e.dev == dev) g = e.g;
+  if (g == 0) {
+    int cus = 0, nb = 0;
+    if (dev < 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kTile, 0) != hipSuccess)
+      cus = nb = 0;
+    g = std::max(8LL, (long long)cus * std::max(nb, 1));
+    cache.push_back(Entry{k, dev, g});
+  }
   return (unsigned)std::max(1LL, std::min(g, ntiles));
 }
 
@@ -239,37 +280,46 @@ hipError_t launch_transport(const TwoPhaseGrid &t, const double *U, const double
   if (8 * N < (1LL << 32)) {
     const void *k = reinterpret_cast<const void *>(&k_transport<false, uint32_t>);
     hipLaunchKernelGGL((k_transport<false, uint32_t>), dim3(resident_grid(k, tile_count(zt))), dim3(kTile), 0, s, t,
-                       zt, U, q, S, dt, Sout, (unsigned long long *)nullptr);
+                       zt, U, q, (const unsigned char *)nullptr, S, dt, Sout, (unsigned long long *)nullptr);
   } else {
     const void *k = reinterpret_cast<const void *>(&k_transport<false, long long>);
     hipLaunchKernelGGL((k_transport<false, long long>), dim3(resident_grid(k, tile_count(zt))), dim3(kTile), 0, s, t,
-                       zt, U, q, S, dt, Sout, (unsigned long long *)nullptr);
+                       zt, U, q, (const unsigned char *)nullptr, S, dt, Sout, (unsigned long long *)nullptr);
   }
   return hipGetLastError();
 }
 
 // The step, and the next step's CFL speed of the new state reduced into
-// dt_next's eight bytes, which the last kernel turns into that step in place.
-hipError_t launch_transport_advance(const TwoPhaseGrid &t, const double *U, const double *q, const double *S,
-                                    const double *dt, double cfl, double dt_max, double *Sout, double *dt_next,
-                                    hipStream_t s) {
+// dt_next's eight bytes (launch_speed_clear first), which
+// launch_speed_finish then turns into that step in place.
+hipError_t launch_speed_clear(double *dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned long long *>(dt));
+  return hipGetLastError();
+}
+
+hipError_t launch_transport_fused(const TwoPhaseGrid &t, const double *U, const double *q, const double *S,
+                                  const double *dt, double *Sout, double *dt_next, hipStream_t s,
+                                  const unsigned char *src_tiles) {
   const long long N = (long long)t.nx * t.ny * t.nz;
+  if (N == 0) return hipSuccess;
   unsigned long long *work = reinterpret_cast<unsigned long long *>(dt_next);
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, work);
-  if (N > 0) {
-    const ZTiles zt = transport_tiles(t);
-    if (8 * N < (1LL << 32)) {
-      const void *k = reinterpret_cast<const void *>(&k_transport<true, uint32_t>);
-      hipLaunchKernelGGL((k_transport<true, uint32_t>), dim3(resident_grid(k, tile_count(zt))), dim3(kTile), 0, s,
-                         t, zt, U, q, S, dt, Sout, work);
-    } else {
-      const void *k = reinterpret_cast<const void *>(&k_transport<true, long long>);
-      hipLaunchKernelGGL((k_transport<true, long long>), dim3(resident_grid(k, tile_count(zt))), dim3(kTile), 0, s,
-                         t, zt, U, q, S, dt, Sout, work);
-    }
+  const ZTiles zt = transport_tiles(t);
+  if (8 * N < (1LL << 32)) {
+    const void *k = reinterpret_cast<const void *>(&k_transport<true, uint32_t>);
+    hipLaunchKernelGGL((k_transport<true, uint32_t>), dim3(resident_grid(k, tile_count(zt))), dim3(kTile), 0, s, t,
+                       zt, U, q, src_tiles, S, dt, Sout, work);
+  } else {
+    const void *k = reinterpret_cast<const void *>(&k_transport<true, long long>);
+    hipLaunchKernelGGL((k_transport<true, long long>), dim3(resident_grid(k, tile_count(zt))), dim3(kTile), 0, s, t,
+                       zt, U, q, src_tiles, S, dt, Sout, work);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_speed_finish(const TwoPhaseGrid &t, double cfl, double dt_max, double *dt, hipStream_t s) {
   const double hmin = std::fmin(t.hx, std::fmin(t.hy, t.hz));
-  hipLaunchKernelGGL(k_transport_dt, dim3(1), dim3(64), 0, s, work, hmin, cfl, dt_max, dt_next);
+  hipLaunchKernelGGL(k_transport_dt, dim3(1), dim3(64), 0, s, reinterpret_cast<const unsigned long long *>(dt), hmin,
+                     cfl, dt_max, dt);
   return hipGetLastError();
 }
 
@@ -279,13 +329,25 @@ hipError_t launch_transport_dt(const TwoPhaseGrid &t, const double *U, const dou
                                double *dt, hipStream_t s) {
   const long long N = (long long)t.nx * t.ny * t.nz;
   unsigned long long *work = reinterpret_cast<unsigned long long *>(dt);
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, work);
+  const hipError_t e = launch_speed_clear(dt, s);
+  if (e != hipSuccess) return e;
   if (N > 0)
     hipLaunchKernelGGL(k_transport_speed,
                        dim3(resident_grid(reinterpret_cast<const void *>(&k_transport_speed), (N + kTile - 1) / kTile)),
                        dim3(kTile), 0, s, t, U, S, work);
-  const double hmin = std::fmin(t.hx, std::fmin(t.hy, t.hz));
-  hipLaunchKernelGGL(k_transport_dt, dim3(1), dim3(64), 0, s, work, hmin, cfl, dt_max, dt);
+  return launch_speed_finish(t, cfl, dt_max, dt, s);
+}
+
+long long transport_tile_count(const TwoPhaseGrid &t) { return tile_count(transport_tiles(t)); }
+
+hipError_t launch_source_tiles(const TwoPhaseGrid &t, const double *q, unsigned char *flags, hipStream_t s) {
+  const long long N = (long long)t.nx * t.ny * t.nz;
+  const long long nt = transport_tile_count(t);
+  hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)std::min<long long>((nt + 255) / 256, 4096)), dim3(256), 0, s, flags,
+                     nt);
+  if (N > 0)
+    hipLaunchKernelGGL(k_source_tiles, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, t, transport_tiles(t), q,
+                       flags);
   return hipGetLastError();
 }
 
