@@ -465,8 +465,10 @@ mrcm_status mrcm_mobility_scale(const mrcm_twophase *tp /* [host] */, const doub
  * by the Mean method (mrcm_postprocess_mean), and the CFL step of that
  * velocity (mrcm_transport_dt) -- then one saturation step under the held
  * velocity (mrcm_transport_advance, which also gives the next step), t += dt,
- * n += 1.  The loop reads each step back to the host (one synchronisation
- * per step) to advance t.
+ * n += 1.  The steps run in batches of up to 64 with their dt logged on the
+ * device and read back once per batch (one synchronisation per batch); a run
+ * that ends inside a batch is taken back to the batch's start and redone to
+ * the step where it ends, with the same result as stepping one at a time.
  * problem, partition, iface, options: as for mrcm_build_mbfs; problem->kx,
  * ky, kz are the permeability K without the mobility, problem->q the sources
  * of both the Darcy solves and the saturation steps.  tp: the same grid and
@@ -474,7 +476,7 @@ mrcm_status mrcm_mobility_scale(const mrcm_twophase *tp /* [host] */, const doub
  * the final one out.  stats [host] or NULL.
  * Errors: as the calls above; MRCM_EINVAL also for a step that is not finite
  * (nothing moves under the bound and dt_max is +inf), with S left at the
- * last finite state.  The library allocates the loop's buffers (about 17
+ * last finite state.  The library allocates the loop's buffers (about 19
  * doubles per cell, beside the MBF handle's) and frees them before it
  * returns; the handles it creates are destroyed too.
  */

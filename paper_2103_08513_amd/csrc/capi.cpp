@@ -1601,7 +1601,9 @@ struct ImpesState {
   std::vector<hipEvent_t> ev;
   mrcm_mbfs *mb = nullptr;
   mrcm_interface *ih = nullptr;
+  double *host = nullptr;  // pinned: the batch's step sizes read back
   ~ImpesState() {
+    if (host) (void)hipHostFree(host);
     if (ih) mrcm_interface_destroy(ih);
     if (mb) mrcm_mbfs_destroy(mb);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -1674,6 +1676,28 @@ mrcm_status mrcm_impes_run(const mrcm_problem *pb, const mrcm_partition *part, c
     if (stats) *stats = mrcm_impes_stats{nd, ns, t, ms_d, ms_d1, ms_m, ms_t};
     return code;
   };
+  // Saturation steps go in batches of up to kImpesBatch (never past the next
+  // Darcy solve or the step cap), each step's dt logged on the device; one
+  // read-back per batch replays t on the host.  If the run ends inside a
+  // batch (t passes t_end, or a step is not finite), the batch's starting
+  // state is restored and exactly the steps that count are taken again: the
+  // kernels are deterministic, so the result is that of stepping one by one.
+  constexpr int kImpesBatch = 64;
+  double *Sa, *dlog;
+  HIP_TRY(W.alloc(&Sa, N));
+  HIP_TRY(W.alloc(&dlog, kImpesBatch));
+  HIP_TRY(hipHostMalloc((void **)&W.host, kImpesBatch * sizeof(double), hipHostMallocDefault));
+  auto step = [&]() -> mrcm_status {
+    HIP_TRY(launch_speed_clear(dnext, s));
+    {
+      Stage stg(MRCM_STAGE_TRANSPORT, s);
+      HIP_TRY(launch_transport_fused(tg, Ut, pb->q, Scur, dcur, Snext, dnext, s, src_tiles));
+    }
+    HIP_TRY(launch_speed_finish(tg, io->cfl, io->dt_max, dnext, s));
+    std::swap(Scur, Snext);
+    std::swap(dcur, dnext);
+    return MRCM_OK;
+  };
   while (t <= io->t_end && (io->max_steps == 0 || ns < io->max_steps)) {
     const bool darcy = ns % io->skip == 0;
     if (darcy) {
@@ -1692,16 +1716,16 @@ mrcm_status mrcm_impes_run(const mrcm_problem *pb, const mrcm_partition *part, c
       HIP_TRY(hipEventRecord(W.ev[2], s));
       ++nd;
     }
+    int kmax = std::min(kImpesBatch, io->skip - ns % io->skip);
+    if (io->max_steps > 0) kmax = std::min(kmax, io->max_steps - ns);
+    HIP_TRY(hipMemcpyAsync(Sa, Scur, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipEventRecord(W.ev[3], s));
-    HIP_TRY(launch_speed_clear(dnext, s));
-    {
-      Stage stg(MRCM_STAGE_TRANSPORT, s);
-      HIP_TRY(launch_transport_fused(tg, Ut, pb->q, Scur, dcur, Snext, dnext, s, src_tiles));
+    for (int j = 0; j < kmax; ++j) {
+      HIP_TRY(hipMemcpyAsync(dlog + j, dcur, sizeof(double), hipMemcpyDeviceToDevice, s));
+      if ((st = step()) != MRCM_OK) return st;
     }
-    HIP_TRY(launch_speed_finish(tg, io->cfl, io->dt_max, dnext, s));
     HIP_TRY(hipEventRecord(W.ev[4], s));
-    double dt = 0.0;
-    HIP_TRY(hipMemcpyAsync(&dt, dcur, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(W.host, dlog, kmax * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (darcy) {
       if (nd == 1) ms_d1 = elapsed_ms(W.ev[0], W.ev[1]);
@@ -1709,13 +1733,33 @@ mrcm_status mrcm_impes_run(const mrcm_problem *pb, const mrcm_partition *part, c
       ms_m += elapsed_ms(W.ev[1], W.ev[2]);
     }
     ms_t += elapsed_ms(W.ev[3], W.ev[4]);
-    if (!std::isfinite(dt))
-      return finish(fail(MRCM_EINVAL, "impes: the step is not finite (nothing moves under the CFL bound and dt_max "
-                                      "is infinite)"));
-    t += dt;
-    std::swap(Scur, Snext);
-    std::swap(dcur, dnext);
-    ++ns;
+    // the loop head of each step, replayed: t <= t_end, then the step
+    int taken = 0;
+    bool bad = false;
+    while (taken < kmax && t <= io->t_end) {
+      if (!std::isfinite(W.host[taken])) {
+        bad = true;
+        break;
+      }
+      t += W.host[taken];
+      ++taken;
+    }
+    ns += taken;
+    if (taken < kmax) {
+      HIP_TRY(hipMemcpyAsync(S, Sa, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      Scur = S;
+      Snext = S2;
+      dcur = dts;
+      dnext = dts + 1;
+      HIP_TRY(hipMemcpyAsync(dcur, dlog, sizeof(double), hipMemcpyDeviceToDevice, s));
+      for (int j = 0; j < taken; ++j)
+        if ((st = step()) != MRCM_OK) return st;
+      HIP_TRY(hipStreamSynchronize(s));
+      if (bad)
+        return finish(fail(MRCM_EINVAL, "impes: the step is not finite (nothing moves under the CFL bound and "
+                                        "dt_max is infinite)"));
+      break;
+    }
   }
   return finish(MRCM_OK);
 }

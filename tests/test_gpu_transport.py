@@ -430,6 +430,35 @@ def test_impes_driver_matches_the_oracle_loop():
     m.close()
 
 
+def test_impes_driver_stops_inside_a_batch():
+    """Skipping constant 100: one Darcy solve, a whole batch of 64 steps, and
+    a stop six steps into the next batch (t_end just below the time after 70
+    steps): the run is taken back to the batch's start and redone to step 70,
+    against the oracle's loop of 70 steps."""
+    import paper_2103_08513_amd as lib
+    case = small_case((12, 10, 6), (2, 2, 2), seed=14)
+    pb = case.problem
+    geo = Geometry(pb.dims, case.partition, case.iface)
+    mu_w, mu_o = 1.0, 5.0
+    dt_s = 0.05 * pb.h[0] * pb.h[1] * pb.h[2] / np.max(pb.q)
+    S70, dts = _oracle_impes(case, geo, mu_w, mu_o, 100, 70, dt_s)
+    T = sum(dts) * (1.0 - 1e-9)
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha)
+    args = [_dev(a) for a in (pb.kx, pb.ky, pb.kz, pb.q)]
+    S = torch.zeros(pb.n, dtype=torch.float64, device="cuda")
+    st = m.impes_run(*args, S, mu_w, mu_o, skip=100, t_end=T, dt_max=dt_s)
+    got = S.cpu().numpy()
+    print(f"  {st}; max err {np.max(np.abs(got - S70)):.2e}", flush=True)
+    assert st["steps"] == 70 and st["darcy_solves"] == 1
+    assert abs(st["t"] - sum(dts)) <= 1e-10 * sum(dts)
+    assert np.max(np.abs(got - S70)) <= 1e-8
+    # a cap of 70 steps gives the same state, bit for bit (no batch redone)
+    S2 = torch.zeros(pb.n, dtype=torch.float64, device="cuda")
+    st2 = m.impes_run(*args, S2, mu_w, mu_o, skip=100, max_steps=70, dt_max=dt_s)
+    assert st2["steps"] == 70 and torch.equal(S, S2)
+    m.close()
+
+
 def test_bad_arguments_are_refused():
     import ctypes
 
