@@ -196,9 +196,10 @@ def time_mean(model, pb, part, U, steps):
 
 
 # HBM bytes per cell of one saturation step fused with the next step's CFL
-# speed (mrcm_transport_advance): U 48, S 8, q 8 read, S' 8 written; the
+# speed (mrcm_transport_advance with the marks of q's sources): U 48, S 8
+# read, S' 8 written (q is read in the marked tiles only, a few of them); the
 # neighbours' saturations are re-reads of S served by the caches.
-TRANSPORT_BYTES_PER_CELL = 72
+TRANSPORT_BYTES_PER_CELL = 64
 # the CFL reduction alone (mrcm_transport_dt): U 48, S 8
 SPEED_BYTES_PER_CELL = 56
 # K lambda(S) (mrcm_mobility_scale): S 8, K 24 read, K' 24 written
@@ -209,9 +210,10 @@ def time_transport(model, pb, U, steps, cpu=True):
     """The IMPES saturation step under the Mean velocity of the step's U: a
     seeded saturation field (uniform in [0, 1]), mu_o / mu_w = 5, the
     quarter-five-spot wells of the workload.  K timed mrcm_transport_advance
-    calls (ping-pong S and dt), the CFL reduction and the mobility, each with
-    HIP events on the stream they run on; and the oracle's step on a slab of
-    five z-planes, on the host."""
+    calls (ping-pong S and dt) with the marks of q's sources, and K with the
+    dense q, the CFL reduction and the mobility, each with HIP events on the
+    stream they run on; and the oracle's step on a slab of five z-planes, on
+    the host."""
     import torch
     import paper_2103_08513_amd as lib
     N = pb.n
@@ -243,13 +245,18 @@ def time_transport(model, pb, U, steps, cpu=True):
     ms_mob = timed(lambda: tp.mobility_scale(S[0], kx, ky, kz, out=kout), 10)
     del kx, ky, kz, kout
     state = [0]
+    marks = tp.mark_sources(q)
+    use_marks = [None]
 
     def adv():
         i = state[0]
-        tp.advance(Ut, q, S[i], dts[i], cfl=1.0 / 6.0, dt_max=dt_max, out=S[1 - i], dt_next=dts[1 - i])
+        tp.advance(Ut, q, S[i], dts[i], cfl=1.0 / 6.0, dt_max=dt_max, out=S[1 - i], dt_next=dts[1 - i],
+                   marks=use_marks[0])
         state[0] = 1 - i
 
     tp.dt(Ut, S[0], cfl=1.0 / 6.0, dt_max=dt_max, out=dts[0])
+    ms_dense = timed(adv, steps)
+    use_marks[0] = marks
     ms_adv = timed(adv, steps)
     # the step kernel alone: HIP events around its launch (the library's stage
     # profiling) over the same number of steps again
@@ -272,20 +279,23 @@ def time_transport(model, pb, U, steps, cpu=True):
             traffic = float(prof["hbm_bytes_per_launch"])
         except (KeyError, ValueError):
             traffic = None
-    out = {"ms_per_step": ms_adv, "ms_kernel": ms_kernel, "gcells_per_s": N / (ms_adv * 1e-3) / 1e9, "steps": steps,
+    out = {"ms_per_step": ms_adv, "ms_kernel": ms_kernel, "ms_per_step_dense_q": ms_dense,
+           "gcells_per_s": N / (ms_adv * 1e-3) / 1e9, "steps": steps,
            "s_range": [lo, hi], "ms_cfl_reduction": ms_dt, "ms_mobility": ms_mob,
            "roofline": {"kernel": "k_transport<true> (mrcm_transport_advance)", "bound": "hbm",
                         "achieved": TRANSPORT_BYTES_PER_CELL * N / (ms_kernel * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
                         "unit": "GB/s", "frac": TRANSPORT_BYTES_PER_CELL * N / (ms_kernel * 1e-3) / 1e9 / PEAK_HBM_GBS,
                         "traffic": traffic, "bytes_per_cell": TRANSPORT_BYTES_PER_CELL, "ms_avg": ms_kernel,
-                        "note": "HIP events around the step kernel's launches (ms_per_step: the whole call, with "
-                                "the accumulator clear and the finalising kernel)"},
+                        "note": "HIP events around the step kernel's launches, q read in the marked tiles only "
+                                "(ms_per_step: the whole call, with the accumulator clear and the finalising kernel; "
+                                "ms_per_step_dense_q: the same calls without the marks)"},
            "roofline_cfl": {"achieved": SPEED_BYTES_PER_CELL * N / (ms_dt * 1e-3) / 1e9, "unit": "GB/s",
                             "frac": SPEED_BYTES_PER_CELL * N / (ms_dt * 1e-3) / 8e12},
            "roofline_mobility": {"achieved": MOBILITY_BYTES_PER_CELL * N / (ms_mob * 1e-3) / 1e9, "unit": "GB/s",
                                  "frac": MOBILITY_BYTES_PER_CELL * N / (ms_mob * 1e-3) / 8e12},
            "what": "IMPES saturation step fused with the next step's CFL speed, velocity held (the inner loop "
-                   "between Darcy solves); seeded S uniform in [0, 1], mu_o / mu_w = 5, cfl 1/6"}
+                   "between Darcy solves), q read in the tiles its marks name; seeded S uniform in [0, 1], "
+                   "mu_o / mu_w = 5, cfl 1/6"}
     if cpu:
         from oracle.transport import transport_step
         nx, ny, nz = pb.dims
@@ -589,7 +599,8 @@ def main():
         ", ".join(f"{k} {v['ms_per_step']:.1f}" for k, v in res["stages"].items()))
     if res["transport"]:
         tr = res["transport"]
-        log(f"transport: {tr['ms_per_step']:.3f} ms/step ({tr['roofline']['achieved']:.0f} GB/s), CFL reduction "
+        log(f"transport: {tr['ms_per_step']:.3f} ms/step ({tr['roofline']['achieved']:.0f} GB/s; dense q "
+            f"{tr['ms_per_step_dense_q']:.3f}), CFL reduction "
             f"{tr['ms_cfl_reduction']:.3f} ms, mobility {tr['ms_mobility']:.3f} ms")
     impes = None
     if args.impes_darcy > 0 and not (args.no_mean or args.no_transport):

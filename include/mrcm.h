@@ -439,11 +439,26 @@ mrcm_status mrcm_transport_dt(const mrcm_twophase *tp /* [host] */, const double
  * pass over U and S: the inner loop of the IMPES run, where the velocity is
  * held for C steps between Darcy solves.  dt [dev] the step to take,
  * dt_next [dev] the next one (must not be dt; ping-pong two doubles).
- * S_out must not overlap S.  Results equal the two separate calls bitwise.
+ * S_out must not overlap S.  marks [dev] or NULL: the marks of q made by
+ * mrcm_transport_mark_sources (q is then read only in the marked parts of
+ * the grid; 8 of the step's 72 bytes per cell otherwise).  Results equal the
+ * two separate calls bitwise, with or without the marks.
  */
 mrcm_status mrcm_transport_advance(const mrcm_twophase *tp /* [host] */, const double *U, const double *q,
-                                   const double *S, const double *dt, double cfl, double dt_max, void *stream,
-                                   double *S_out, double *dt_next);
+                                   const void *marks, const double *S, const double *dt, double cfl, double dt_max,
+                                   void *stream, double *S_out, double *dt_next);
+
+/*
+ * The marks of the cells where q is nonzero, for mrcm_transport_advance:
+ * one byte per tile of the step (64 cells along x by 4 rows by up to 32
+ * planes), nonzero where the tile holds a source.  They stay valid while q
+ * does (the sources of an IMPES run usually hold for the whole run).
+ * mrcm_transport_marks_bytes: the size of marks for the grid (0 on a bad
+ * descriptor).  marks [dev]: that many bytes, written.
+ */
+int64_t mrcm_transport_marks_bytes(const mrcm_twophase *tp /* [host] */);
+mrcm_status mrcm_transport_mark_sources(const mrcm_twophase *tp /* [host] */, const double *q, void *stream,
+                                        void *marks);
 
 /*
  * The permeability of a Darcy solve of the two-phase run: K lambda(S) per

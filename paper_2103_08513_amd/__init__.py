@@ -508,16 +508,34 @@ class TwoPhase:
         _lib.check(code, "mrcm_transport_step")
         return out
 
-    def advance(self, U, q, S, dt, cfl=1.0, dt_max=float("inf"), out=None, dt_next=None, stream=None):
+    def mark_sources(self, q, stream=None):
+        """The marks of q's sources (mrcm_transport_mark_sources): a uint8
+        device tensor for advance(marks=...), valid while q holds."""
+        import torch
+        nb = self.lib.mrcm_transport_marks_bytes(byref(self._c))
+        marks = torch.empty(max(int(nb), 1), dtype=torch.uint8, device=q.device)
+        code = self.lib.mrcm_transport_mark_sources(byref(self._c), _dev_ptr(q, "q", self.n), _stream_ptr(stream),
+                                                    c_void_p(marks.data_ptr()))
+        _lib.check(code, "mrcm_transport_mark_sources")
+        return marks
+
+    def advance(self, U, q, S, dt, cfl=1.0, dt_max=float("inf"), out=None, dt_next=None, stream=None, marks=None):
         """One step with dt (a one-entry device tensor) and the next step's
-        dt under the same U: returns (S_out, dt_next)."""
+        dt under the same U: returns (S_out, dt_next).  marks: from
+        mark_sources(q), or None (q read everywhere)."""
         import torch
         if out is None:
             out = torch.empty(self.n, dtype=torch.float64, device=S.device)
         if dt_next is None:
             dt_next = torch.empty(1, dtype=torch.float64, device=S.device)
         qp = _dev_ptr(q, "q", self.n) if q is not None else None
-        code = self.lib.mrcm_transport_advance(byref(self._c), _dev_ptr(U, "U", 6 * self.n), qp,
+        mp = None
+        if marks is not None:
+            nb = self.lib.mrcm_transport_marks_bytes(byref(self._c))
+            if marks.dtype != torch.uint8 or marks.device.type != "cuda" or marks.numel() < nb:
+                raise ValueError(f"marks must be a uint8 device tensor of {nb} entries from mark_sources")
+            mp = c_void_p(marks.data_ptr())
+        code = self.lib.mrcm_transport_advance(byref(self._c), _dev_ptr(U, "U", 6 * self.n), qp, mp,
                                                _dev_ptr(S, "S", self.n), _dev_ptr(dt, "dt", 1), c_double(cfl),
                                                c_double(dt_max), _stream_ptr(stream), _dev_ptr(out, "S_out", self.n),
                                                _dev_ptr(dt_next, "dt_next", 1))
@@ -545,8 +563,8 @@ def transport_step(tp: TwoPhase, U, q, S, dt, stream=None):
     return tp.step(U, q, S, dt, stream=stream)
 
 
-def transport_advance(tp: TwoPhase, U, q, S, dt, cfl=1.0, dt_max=float("inf"), stream=None):
-    return tp.advance(U, q, S, dt, cfl, dt_max, stream=stream)
+def transport_advance(tp: TwoPhase, U, q, S, dt, cfl=1.0, dt_max=float("inf"), stream=None, marks=None):
+    return tp.advance(U, q, S, dt, cfl, dt_max, stream=stream, marks=marks)
 
 
 def mobility_scale(tp: TwoPhase, S, kx, ky, kz, stream=None):

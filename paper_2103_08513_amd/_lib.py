@@ -16,7 +16,8 @@ EXPORTS = [
     "mrcm_build_mbfs", "mrcm_assemble_interface", "mrcm_solve_interface", "mrcm_reconstruct",
     "mrcm_query", "mrcm_get_subdomain", "mrcm_copy_mbfs", "mrcm_copy_flux", "mrcm_copy_factor",
     "mrcm_interface_dims", "mrcm_copy_interface", "mrcm_interface_query", "mrcm_postprocess_mean",
-    "mrcm_transport_step", "mrcm_transport_dt", "mrcm_transport_advance", "mrcm_mobility_scale", "mrcm_impes_run",
+    "mrcm_transport_step", "mrcm_transport_dt", "mrcm_transport_advance", "mrcm_transport_marks_bytes",
+    "mrcm_transport_mark_sources", "mrcm_mobility_scale", "mrcm_impes_run",
     "mrcm_mbfs_destroy", "mrcm_interface_destroy",
     "mrcm_status_string", "mrcm_last_error", "mrcm_profile_enable", "mrcm_profile_reset",
     "mrcm_profile_get", "mrcm_autotune", "mrcm_autotune_cached", "mrcm_graph_capture", "mrcm_graph_launch", "mrcm_graph_check", "mrcm_graph_destroy",
@@ -120,7 +121,9 @@ def load(path: str = LIB_PATH):
         "mrcm_reconstruct": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
         "mrcm_postprocess_mean": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
         "mrcm_transport_step": ([P(CTwoPhase), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
-        "mrcm_transport_advance": ([P(CTwoPhase)] + [c_void_p] * 4 + [c_double, c_double] + [c_void_p] * 3, c_int32),
+        "mrcm_transport_advance": ([P(CTwoPhase)] + [c_void_p] * 5 + [c_double, c_double] + [c_void_p] * 3, c_int32),
+        "mrcm_transport_marks_bytes": ([P(CTwoPhase)], c_int64),
+        "mrcm_transport_mark_sources": ([P(CTwoPhase), c_void_p, c_void_p, c_void_p], c_int32),
         "mrcm_transport_dt": ([P(CTwoPhase), c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p], c_int32),
         "mrcm_mobility_scale": ([P(CTwoPhase)] + [c_void_p] * 8, c_int32),
         "mrcm_impes_run": ([P(CProblem), P(CPartition), P(CIfaceSpace), P(COptions), P(CTwoPhase), P(CImpesOptions),

@@ -1511,9 +1511,9 @@ mrcm_status mrcm_transport_step(const mrcm_twophase *tp, const double *U, const 
   return MRCM_OK;
 }
 
-mrcm_status mrcm_transport_advance(const mrcm_twophase *tp, const double *U, const double *q, const double *S,
-                                   const double *dt, double cfl, double dt_max, void *stream, double *S_out,
-                                   double *dt_next) {
+mrcm_status mrcm_transport_advance(const mrcm_twophase *tp, const double *U, const double *q, const void *marks,
+                                   const double *S, const double *dt, double cfl, double dt_max, void *stream,
+                                   double *S_out, double *dt_next) {
   TwoPhaseGrid t;
   const mrcm_status st = twophase_grid(tp, t);
   if (st != MRCM_OK) return st;
@@ -1526,9 +1526,24 @@ mrcm_status mrcm_transport_advance(const mrcm_twophase *tp, const double *U, con
   HIP_TRY(launch_speed_clear(dt_next, s));
   {
     Stage st(MRCM_STAGE_TRANSPORT, s);
-    HIP_TRY(launch_transport_fused(t, U, q, S, dt, S_out, dt_next, s));
+    HIP_TRY(launch_transport_fused(t, U, q, S, dt, S_out, dt_next, s, static_cast<const unsigned char *>(marks)));
   }
   HIP_TRY(launch_speed_finish(t, cfl, dt_max, dt_next, s));
+  return MRCM_OK;
+}
+
+int64_t mrcm_transport_marks_bytes(const mrcm_twophase *tp) {
+  TwoPhaseGrid t;
+  if (twophase_grid(tp, t) != MRCM_OK) return 0;
+  return transport_tile_count(t);
+}
+
+mrcm_status mrcm_transport_mark_sources(const mrcm_twophase *tp, const double *q, void *stream, void *marks) {
+  TwoPhaseGrid t;
+  const mrcm_status st = twophase_grid(tp, t);
+  if (st != MRCM_OK) return st;
+  if (!q || !marks) return fail(MRCM_EINVAL, "null argument");
+  HIP_TRY(launch_source_tiles(t, q, static_cast<unsigned char *>(marks), (hipStream_t)stream));
   return MRCM_OK;
 }
 

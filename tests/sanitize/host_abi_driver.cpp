@@ -222,7 +222,9 @@ void check_twophase_validation() {
   for (const mrcm_twophase &b : bad) {
     CHECK(mrcm_transport_step(&b, d, nullptr, d, d, nullptr, d2) == MRCM_EINVAL);
     CHECK(mrcm_transport_dt(&b, d, d, 1.0, 1.0, nullptr, d) == MRCM_EINVAL);
-    CHECK(mrcm_transport_advance(&b, d, nullptr, d, d, 1.0, 1.0, nullptr, d2, d2) == MRCM_EINVAL);
+    CHECK(mrcm_transport_advance(&b, d, nullptr, nullptr, d, d, 1.0, 1.0, nullptr, d2, d2) == MRCM_EINVAL);
+    CHECK(mrcm_transport_marks_bytes(&b) == 0);
+    CHECK(mrcm_transport_mark_sources(&b, d, nullptr, d2) == MRCM_EINVAL);
     CHECK(mrcm_mobility_scale(&b, d, d, d, d, nullptr, d, d, d) == MRCM_EINVAL);
   }
   expect(mrcm_transport_step(nullptr, d, nullptr, d, d, nullptr, d2), "descriptor");
@@ -230,8 +232,10 @@ void check_twophase_validation() {
   expect(mrcm_transport_step(&good, nullptr, nullptr, d, d, nullptr, d2), "null");
   expect(mrcm_transport_dt(&good, d, d, 0.0, 1.0, nullptr, d), "cfl");
   expect(mrcm_transport_dt(&good, d, d, 1.0, -1.0, nullptr, d), "dt_max");
-  expect(mrcm_transport_advance(&good, d, nullptr, d, d, 1.0, 1.0, nullptr, d2, d), "dt_next");
-  expect(mrcm_transport_advance(&good, d, nullptr, d, d, 1.0, 1.0, nullptr, d, d2), "overlap");
+  expect(mrcm_transport_advance(&good, d, nullptr, nullptr, d, d, 1.0, 1.0, nullptr, d2, d), "dt_next");
+  expect(mrcm_transport_advance(&good, d, nullptr, nullptr, d, d, 1.0, 1.0, nullptr, d, d2), "overlap");
+  expect(mrcm_transport_mark_sources(&good, nullptr, nullptr, d2), "null");
+  CHECK(mrcm_transport_marks_bytes(&good) == 1);
   expect(mrcm_mobility_scale(&good, d, nullptr, d, d, nullptr, d, d, d), "null");
   // the loop: a problem of the same grid
   mrcm_problem pb{};

@@ -20,7 +20,8 @@ mrcm_transport_dt, mrcm_mobility_scale; eqs. (transporte_discreto),
   three CFL steps each) against the same loop on the oracle, from Python and
   through the library's own loop (mrcm_impes_run, with its stop at t_end).
 * The step fused with the next step's CFL reduction (mrcm_transport_advance)
-  equals the two separate calls bitwise, and chains against the oracle.
+  equals the two separate calls bitwise, with and without the marks of q's
+  sources, and chains against the oracle.
 * Bad descriptors and arguments are refused.
 Tolerances: the step evaluates the oracle's operations but sums the six face
 terms before scaling by dt, and the compiler may contract a product into an
@@ -172,6 +173,10 @@ def test_advance_equals_the_step_then_the_cfl_step(name):
     dt1b = tp.dt(Ud, s1b, cfl=1.0 / 6.0, dt_max=dt_max)
     assert np.array_equal(s1.cpu().numpy(), s1b.cpu().numpy())
     assert dt1.item() == dt1b.item()
+    # with the marks of q's sources: q read only in the marked tiles, the same bits
+    marks = tp.mark_sources(qd)
+    s1m, dt1m = tp.advance(Ud, qd, Sd, dt0, cfl=1.0 / 6.0, dt_max=dt_max, marks=marks)
+    assert torch.equal(s1m, s1) and dt1m.item() == dt1.item()
     Sh, dth = s1.cpu().numpy(), dt1.item()
     cur, dcur = s1, dt1
     for _ in range(4):
@@ -488,16 +493,19 @@ def test_bad_arguments_are_refused():
     assert lb.mrcm_mobility_scale(ctypes.byref(good), p, None, p, p, None, p, p, p) == -1
     d2 = torch.zeros(1, dtype=torch.float64, device="cuda")
     adv = lb.mrcm_transport_advance
-    assert adv(ctypes.byref(good), p, None, s.data_ptr(), d.data_ptr(), 1.0, 1.0, None, o.data_ptr(),
+    assert adv(ctypes.byref(good), p, None, None, s.data_ptr(), d.data_ptr(), 1.0, 1.0, None, o.data_ptr(),
                d2.data_ptr()) == 0
-    assert adv(ctypes.byref(good), p, None, s.data_ptr(), d.data_ptr(), 1.0, 1.0, None, o.data_ptr(),
+    assert adv(ctypes.byref(good), p, None, None, s.data_ptr(), d.data_ptr(), 1.0, 1.0, None, o.data_ptr(),
                d.data_ptr()) == -1                                                          # dt_next == dt
-    assert adv(ctypes.byref(good), p, None, s.data_ptr(), d.data_ptr(), 1.0, 1.0, None, s.data_ptr(),
+    assert adv(ctypes.byref(good), p, None, None, s.data_ptr(), d.data_ptr(), 1.0, 1.0, None, s.data_ptr(),
                d2.data_ptr()) == -1                                                         # S_out == S
-    assert adv(ctypes.byref(good), p, None, s.data_ptr(), d.data_ptr(), -1.0, 1.0, None, o.data_ptr(),
+    assert adv(ctypes.byref(good), p, None, None, s.data_ptr(), d.data_ptr(), -1.0, 1.0, None, o.data_ptr(),
                d2.data_ptr()) == -1
-    assert adv(ctypes.byref(good), p, None, s.data_ptr(), d.data_ptr(), 1.0, 1.0, None, o.data_ptr(),
+    assert adv(ctypes.byref(good), p, None, None, s.data_ptr(), d.data_ptr(), 1.0, 1.0, None, o.data_ptr(),
                None) == -1
+    assert lb.mrcm_transport_marks_bytes(None) == 0
+    assert lb.mrcm_transport_marks_bytes(ctypes.byref(good)) >= 1
+    assert lb.mrcm_transport_mark_sources(ctypes.byref(good), None, None, o.data_ptr()) == -1
     torch.cuda.synchronize()
     assert d2.item() == 1.0       # all-zero S: nothing moves, the step is dt_max
     tp = lib.TwoPhase((4, 3, 2), (1.0, 1.0, 1.0), 1.0, 2.0)
