@@ -395,10 +395,12 @@ def _oracle_impes(case, geo, mu_w, mu_o, C, n_steps, dt_s):
     return S, dts
 
 
-def test_impes_driver_matches_the_oracle_loop():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_impes_driver_matches_the_oracle_loop(precision):
     """mrcm_impes_run: seven steps with the skipping constant 3 (Darcy solves
     before steps 0, 3 and 6) from an all-oil start, against the oracle's
-    loop; then the stop at t_end; then an infinite step refused."""
+    loop; then the stop at t_end; then an infinite step refused.  With FP64
+    MBFs and with the FP32 factor refined in FP64."""
     import paper_2103_08513_amd as lib
     case = small_case((12, 10, 6), (2, 2, 2), seed=14)
     pb = case.problem
@@ -406,7 +408,7 @@ def test_impes_driver_matches_the_oracle_loop():
     mu_w, mu_o, C = 1.0, 5.0, 3
     dt_s = 0.2 * pb.h[0] * pb.h[1] * pb.h[2] / np.max(pb.q)
     S_ref, dts = _oracle_impes(case, geo, mu_w, mu_o, C, 7, dt_s)
-    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha)
+    m = lib.MRCM(pb, case.partition, case.iface, alpha=case.alpha, precision=precision)
     kx, ky, kz, q = _dev(pb.kx), _dev(pb.ky), _dev(pb.kz), _dev(pb.q)
     S = torch.zeros(pb.n, dtype=torch.float64, device="cuda")
     st = m.impes_run(kx, ky, kz, q, S, mu_w, mu_o, skip=C, max_steps=7, dt_max=dt_s)
