@@ -17,10 +17,12 @@
 // Levels are processed bottom-up, each as one extend-add per child slot, the
 // factorisation of every node's first block, then panel by panel (up to
 // kMfPanelMax blocks of 16 columns): one launch per block over the row tiles below it,
-// which forms W and updates the rest of the panel only, and one rank-64
-// update of the trailing tiles past the panel, with W read back from its
-// transposed store.  The trailing matrix is thus read and written once per
-// 64 columns rather than once per 16.
+// which forms W and updates the rest of the panel only, and the trailing
+// update past the panel, with W read back from its transposed store,
+// deferred over kMfDefer panels: a narrow launch brings the next panel's
+// columns up to date, and one launch per group of panels updates the tiles
+// past it.  The trailing matrix is thus read and written once per 128
+// columns rather than once per 16.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -367,9 +369,12 @@ __global__ __launch_bounds__(kMfStepThreads) void k_mf_step(const MfNode *__rest
   }
 }
 
-// Trailing update past the panel of blocks t0 .. t0 + nb - 1 (nb <= panel):
+// Trailing update past the blocks t0 .. t0 + nb - 1 (nb = min(nb_max, the
+// node's blocks from t0): one panel, or a group of deferred panels):
 // C -= W D^{-1} W^T on the lower 64x64 tiles of the rows and columns
-// R0 = 16 (t0 + nb) .. f - 1, K = 16 nb.  The tile stays in accumulators
+// R0 = 16 (t0 + nb) .. f - 1, K = 16 nb; with jend > 0 only the columns
+// below block min(jend, the separator's end) are written (the deferred
+// update of the next panel's columns).  The tile stays in accumulators
 // while W of its rows i and columns j comes block by block (16 columns of K)
 // from its transposed store (column i, rows 16 t .. 16 t + 15, contiguous)
 // through 17 KB of LDS, so that eight workgroups fit on a CU; 1/D comes from
@@ -380,8 +385,8 @@ constexpr int kMfTrailThreads = 256;
 constexpr int kMfTrailStride = kLB + 1;
 
 __global__ __launch_bounds__(kMfTrailThreads) void k_mf_trailing(const MfNode *__restrict__ nodes,
-                                                                 const int2 *__restrict__ blocks, int t0, int panel,
-                                                                 double *__restrict__ fronts,
+                                                                 const int2 *__restrict__ blocks, int t0, int nb_max,
+                                                                 int jend, double *__restrict__ fronts,
                                                                  const double *__restrict__ inv) {
   using M = Mma<double>;
   constexpr int LS = kMfTrailStride;
@@ -390,8 +395,9 @@ __global__ __launch_bounds__(kMfTrailThreads) void k_mf_trailing(const MfNode *_
   const int2 bt = blocks[blockIdx.x];
   const MfNode nd = nodes[bt.x];
   const int f = nd.f;
-  const int nb = min(panel, nd.sp / kLB - t0);
+  const int nb = min(nb_max, nd.sp / kLB - t0);
   const int R0 = kLB * (t0 + nb);
+  const int jmax = jend > 0 ? kLB * min(jend, nd.sp / kLB) : f;
   int ti = 0, tj = bt.y;
   while (tj > ti) {
     tj -= ti + 1;
@@ -433,7 +439,7 @@ __global__ __launch_bounds__(kMfTrailThreads) void k_mf_trailing(const MfNode *_
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int j = j0 + 16 * wave + M::crow(v, lane), i = i0 + 16 * tc + lr;
-      if (i < f && j < f && i >= j) A[(int64_t)j * f + i] = c[tc][v];
+      if (i < f && j < jmax && i >= j) A[(int64_t)j * f + i] = c[tc][v];
     }
   }
 }
@@ -690,8 +696,8 @@ hipError_t launch_mf_factor(const NdPlan &plan, const MfDevPlan &dp, double *fro
         hipLaunchKernelGGL(k_mf_step, dim3(L.n_blocks), dim3(kMfStepThreads), 0, s, dp.nodes, bl, L.t, plan.panel,
                            fronts, inv, st);
       else if (L.kind == kMfTrailing)
-        hipLaunchKernelGGL(k_mf_trailing, dim3(L.n_blocks), dim3(kMfTrailThreads), 0, s, dp.nodes, bl, L.t,
-                           plan.panel, fronts, inv);
+        hipLaunchKernelGGL(k_mf_trailing, dim3(L.n_blocks), dim3(kMfTrailThreads), 0, s, dp.nodes, bl, L.t, L.nb,
+                           L.jend, fronts, inv);
       else
         hipLaunchKernelGGL(k_mf_diag, dim3(L.n_blocks), dim3(64), 0, s, dp.nodes, bl, L.t, fronts, inv, st);
     }

@@ -239,7 +239,9 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
   for (int h = 0; h < H; ++h) {
     int tmax = 0;
     for (int k : lv[h]) tmax = std::max(tmax, plan.nodes[k].sp / kNB);
-    auto push = [&](int kind, int t, auto tiles) {
+    // one launch over the level's nodes, tiles(node) workgroups each with
+    // tile ids id(q); returns the launch, or null when it has no workgroup
+    auto push_ids = [&](int kind, int t, auto tiles, auto id) -> MfStepLaunch * {
       MfStepLaunch L;
       L.level = h;
       L.kind = kind;
@@ -247,11 +249,14 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
       L.blk_off = (int64_t)plan.step_blocks.size();
       for (int k : lv[h]) {
         const int n = tiles(plan.nodes[k]);
-        for (int q = 0; q < n; ++q) plan.step_blocks.push_back(make_int2(k, q));
+        for (int q = 0; q < n; ++q) plan.step_blocks.push_back(make_int2(k, id(q)));
       }
       L.n_blocks = (int)(plan.step_blocks.size() - L.blk_off);
-      if (L.n_blocks > 0) plan.steps.push_back(L);
+      if (L.n_blocks == 0) return nullptr;
+      plan.steps.push_back(L);
+      return &plan.steps.back();
     };
+    auto push = [&](int kind, int t, auto tiles) { return push_ids(kind, t, tiles, [](int q) { return q; }); };
     const int P = plan.panel;
     for (int t0 = 0; t0 < tmax; t0 += P) {
       if (t0 > 0) push(kMfDiag, t0, [&](const MfNode &M) { return M.sp / kNB > t0 ? 1 : 0; });
@@ -261,12 +266,35 @@ std::string build_nd_plan(const int nd[3], const std::vector<SubDesc> &subs, con
           const int nr = M.f - kNB * (t + 1);
           return nr > 0 ? (nr + 63) / 64 : 0;
         });
-      push(kMfTrailing, t0, [&](const MfNode &M) {
-        if (M.sp / kNB <= t0) return 0;
-        const int nr = M.f - kNB * std::min(t0 + P, M.sp / kNB);
-        const int tt = nr > 0 ? (nr + 63) / 64 : 0;
-        return tt * (tt + 1) / 2;
-      });
+      // the group of panels g .. t0 whose trailing update is deferred
+      const int g = t0 - ((t0 / P) % kMfDefer) * P;
+      const int nb = t0 + P - g;
+      const bool last = (t0 / P) % kMfDefer == kMfDefer - 1 || t0 + P >= tmax;
+      if (!last) {
+        // the next panel's columns, for the nodes whose separator goes on past
+        // this panel: tile column 0, whose tile (ti, 0) has the id
+        // ti (ti + 1) / 2 in the triangular numbering of the trailing tiles
+        MfStepLaunch *L = push_ids(
+            kMfTrailing, g,
+            [&](const MfNode &M) {
+              if (M.sp / kNB <= t0 + P) return 0;
+              const int nr = M.f - kNB * (t0 + P);
+              return nr > 0 ? (nr + 63) / 64 : 0;
+            },
+            [](int ti) { return ti * (ti + 1) / 2; });
+        if (L) {
+          L->nb = nb;
+          L->jend = t0 + 2 * P;
+        }
+      } else {
+        MfStepLaunch *L = push(kMfTrailing, g, [&](const MfNode &M) {
+          if (M.sp / kNB <= g) return 0;
+          const int nr = M.f - kNB * std::min(g + nb, M.sp / kNB);
+          const int tt = nr > 0 ? (nr + 63) / 64 : 0;
+          return tt * (tt + 1) / 2;
+        });
+        if (L) L->nb = nb;
+      }
     }
   }
 

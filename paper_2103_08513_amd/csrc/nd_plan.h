@@ -40,12 +40,22 @@ enum MfLaunchKind {
   kMfTrailing = 1,   // the panel starting at block t: rank-(16 panel) update of the trailing tiles
   kMfDiag = 2,       // LDL^T of the diagonal block t (the first block of a panel)
 };
+// The trailing update of a panel is deferred over kMfDefer panels: after
+// each panel but the group's last, a narrow launch brings the next panel's
+// columns (one tile column, up to the separator's end) up to date with the
+// group's panels so far; after the group's last panel one launch applies
+// all of them to the tiles past it, which are read and written once per
+// group rather than once per panel.  Each entry of the trailing matrix sees
+// the same updates in the same order as with no deferral.
+constexpr int kMfDefer = 4;
 struct MfStepLaunch {
   int level;
   int kind;          // MfLaunchKind
   int t;             // block index within each node's separator
   int64_t blk_off;   // offset of this launch's (node, tile) table
   int n_blocks;      // workgroups
+  int nb = 0;        // kMfTrailing: blocks t .. t + nb - 1 applied
+  int jend = 0;      // kMfTrailing: columns limited to blocks below jend (0: none)
 };
 
 // The sweeps' boundary products W_b^T and W_b, (f - sp) x sp per node, run
