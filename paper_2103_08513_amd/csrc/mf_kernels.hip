@@ -498,8 +498,17 @@ __global__ __launch_bounds__(kMfSweepThreads) void k_mf_fwd(const MfNode *__rest
     {
       // wave w: row k0 + w of the block against the solved prefix
       const double *row = A + (int64_t)(k0 + wave) * f;
-      double acc = 0.0;
-      for (int cidx = lane; cidx < k0; cidx += 64) acc = fma(row[cidx], u[cidx], acc);
+      // eight independent partial sums, so that eight loads of the row are
+      // in flight per lane (the large top separators stream their triangle
+      // through one workgroup)
+      double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int cidx = lane;
+      for (; cidx + 7 * 64 < k0; cidx += 8 * 64) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] = fma(row[cidx + 64 * q], u[cidx + 64 * q], a[q]);
+      }
+      for (; cidx < k0; cidx += 64) a[0] = fma(row[cidx], u[cidx], a[0]);
+      double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
       acc = wave_sum(acc);
       if (lane == 0) zk[wave] = z[k0 + wave] - acc;
     }
