@@ -192,12 +192,23 @@ __global__ __launch_bounds__(256) void k_mf_extend(const MfNode *__restrict__ no
   const int *cm = map + C.map_off;
   const double *src = fronts + C.off;
   double *dst = fronts + P.off;
-  const int j1 = min(C.r, j0 + 16);
-  for (int j = j0; j < j1; ++j) {
-    const int pj = cm[j];
-    const double *col = src + (int64_t)(C.sp + j) * C.f + C.sp;
-    double *pcol = dst + (int64_t)pj * P.f;
-    for (int i = j + threadIdx.x; i < C.r; i += blockDim.x) pcol[cm[i]] += col[i];
+  const int nj = min(C.r, j0 + 16) - j0;
+  // the block's 16 columns: the parent column offsets once, then each thread
+  // takes a row i and adds its entries of all the columns j <= i (sixteen
+  // independent updates in flight, each parent entry written by one thread)
+  __shared__ int64_t pcol[16];
+  if ((int)threadIdx.x < nj) pcol[threadIdx.x] = (int64_t)cm[j0 + threadIdx.x] * P.f;
+  __syncthreads();
+  const double *col0 = src + (int64_t)(C.sp + j0) * C.f + C.sp;
+  for (int i = j0 + threadIdx.x; i < C.r; i += blockDim.x) {
+    const int pi = cm[i];
+    const int jn = min(nj, i - j0 + 1);
+    if (jn == 16) {
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) dst[pcol[jj] + pi] += col0[(int64_t)jj * C.f + i];
+    } else {
+      for (int jj = 0; jj < jn; ++jj) dst[pcol[jj] + pi] += col0[(int64_t)jj * C.f + i];
+    }
   }
 }
 
