@@ -625,12 +625,78 @@ __global__ __launch_bounds__(kMfBwdCols) void k_mf_bwd_part(const MfNode *__rest
 // product summed from k_mf_bwd_part's pieces in order); then from
 // the last block down, x_k = L11^{-T} D_k^{-1} t_k and t_j -= W_kj^T x_k for
 // the earlier blocks.  The separator's unknowns go to x.
-__global__ __launch_bounds__(kMfSweepThreads) void k_mf_bwd(const MfNode *__restrict__ nodes,
-                                                            const int *__restrict__ list, const int *__restrict__ idx,
-                                                            const double *__restrict__ fronts,
-                                                            const double *__restrict__ inv,
-                                                            const double *__restrict__ zbuf,
-                                                            const double *__restrict__ pbuf, double *__restrict__ x) {
+// Levels whose separators hold at most kMfSmallSp unknowns take one
+// wavefront per node in the sweeps (the bottom of the tree has tens of
+// thousands of small fronts, each of which would otherwise hold a 1024-lane
+// workgroup).
+constexpr int kMfSmallSp = 64;
+
+// The forward sweep of k_mf_fwd with one wavefront per node: the block's 16
+// row products one after another, each the same lane products and wave sum.
+__global__ __launch_bounds__(64) void k_mf_fwd_small(const MfNode *__restrict__ nodes,
+                                                     const int *__restrict__ list, const int *__restrict__ idx,
+                                                     const int *__restrict__ map,
+                                                     const double *__restrict__ fronts,
+                                                     const double *__restrict__ inv,
+                                                     const double *__restrict__ rhs,
+                                                     double *__restrict__ zbuf) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double zk[kLB];
+  const int k = list[blockIdx.x];
+  const MfNode nd = nodes[k];
+  const int f = nd.f, sp = nd.sp;
+  double *z = reinterpret_cast<double *>(smem_raw);  // f entries
+  double *u = z + f;                                 // sp entries: D^{-1} y
+  const int lane = threadIdx.x;
+  const int *id = idx + nd.idx_off;
+  for (int p = lane; p < f; p += 64) {
+    const int q = id[p];
+    double v = 0.0;
+    if (p < sp && q >= 0) v = (q & 1) ? rhs[q] : -rhs[q];
+    z[p] = v;
+  }
+  __syncthreads();
+  for (int slot = 0; slot < 2; ++slot) {
+    const int c = slot ? nd.child1 : nd.child0;
+    if (c < 0) continue;
+    const MfNode C = nodes[c];
+    const double *zc = zbuf + C.z_off + C.sp;
+    for (int i = lane; i < C.r; i += 64) z[map[C.map_off + i]] += zc[i];
+    __syncthreads();
+  }
+  const double *A = fronts + nd.off;
+  const double *iv0 = inv + nd.inv_off;
+  for (int k0 = 0; k0 < sp; k0 += kLB) {
+    for (int w = 0; w < kLB; ++w) {
+      // row k0 + w of the block against the solved prefix (k0 < 64: one term a lane)
+      const double *row = A + (int64_t)(k0 + w) * f;
+      double acc = lane < k0 ? fma(row[lane], u[lane], 0.0) : 0.0;
+      acc = wave_sum(acc);
+      if (lane == 0) zk[w] = z[k0 + w] - acc;
+    }
+    __syncthreads();
+    if (lane < kLB) {
+      const double *iv = iv0 + (int64_t)(k0 / kLB) * kInvStride;
+      double y = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < kLB; ++cc) y = fma(iv[lane * kLB + cc], zk[cc], y);
+      z[k0 + lane] = y;
+      u[k0 + lane] = y * iv[kLB * kLB + lane];
+    }
+    __syncthreads();
+  }
+  double *zo = zbuf + nd.z_off;
+  for (int p = lane; p < f; p += 64) zo[p] = z[p];
+}
+
+// NT threads: kMfSweepThreads, or one wavefront for the levels whose
+// separators hold at most kMfSmallSp unknowns (the many small fronts at the
+// bottom of the tree); the arithmetic does not depend on NT.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_mf_bwd(const MfNode *__restrict__ nodes, const int *__restrict__ list,
+                                               const int *__restrict__ idx, const double *__restrict__ fronts,
+                                               const double *__restrict__ inv, const double *__restrict__ zbuf,
+                                               const double *__restrict__ pbuf, double *__restrict__ x) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int k = list[blockIdx.x];
   const MfNode nd = nodes[k];
@@ -643,7 +709,7 @@ __global__ __launch_bounds__(kMfSweepThreads) void k_mf_bwd(const MfNode *__rest
   const double *zo = zbuf + nd.z_off;
   const int nrc = (nd.r + kMfBwdRows - 1) / kMfBwdRows;
   const double *pp = pbuf + nd.part_off;
-  for (int cidx = tid; cidx < sp; cidx += kMfSweepThreads) {
+  for (int cidx = tid; cidx < sp; cidx += NT) {
     double acc = zo[cidx];
     for (int rc = 0; rc < nrc; ++rc) acc -= pp[(int64_t)rc * sp + cidx];
     tv[cidx] = acc;
@@ -659,7 +725,7 @@ __global__ __launch_bounds__(kMfSweepThreads) void k_mf_bwd(const MfNode *__rest
       xs[k0 + tid] = v;
     }
     __syncthreads();
-    for (int cidx = tid; cidx < k0; cidx += kMfSweepThreads) {
+    for (int cidx = tid; cidx < k0; cidx += NT) {
       double acc = tv[cidx];
 #pragma unroll
       for (int r = 0; r < kLB; ++r) acc = fma(-A[(int64_t)(k0 + r) * f + cidx], xs[k0 + r], acc);
@@ -667,7 +733,7 @@ __global__ __launch_bounds__(kMfSweepThreads) void k_mf_bwd(const MfNode *__rest
     }
     __syncthreads();
   }
-  for (int p = tid; p < sp; p += kMfSweepThreads) {
+  for (int p = tid; p < sp; p += NT) {
     const int q = id[p];
     if (q >= 0) x[q] = xs[p];
   }
@@ -733,8 +799,12 @@ hipError_t launch_mf_solve(const NdPlan &plan, const MfDevPlan &dp, const double
   for (int h = 0; h < H; ++h) {
     const int n0 = plan.level_off[h], nn = plan.level_off[h + 1] - n0;
     const size_t lds = (size_t)plan.level_lds[h] * sizeof(double);
-    hipLaunchKernelGGL(k_mf_fwd, dim3(nn), dim3(kMfSweepThreads), lds, s, dp.nodes, dp.level_nodes + n0, dp.idx,
-                       dp.map, fronts, inv, rhs, zbuf);
+    if (plan.level_spmax[h] <= kMfSmallSp)
+      hipLaunchKernelGGL(k_mf_fwd_small, dim3(nn), dim3(64), lds, s, dp.nodes, dp.level_nodes + n0, dp.idx, dp.map,
+                         fronts, inv, rhs, zbuf);
+    else
+      hipLaunchKernelGGL(k_mf_fwd, dim3(nn), dim3(kMfSweepThreads), lds, s, dp.nodes, dp.level_nodes + n0, dp.idx,
+                         dp.map, fronts, inv, rhs, zbuf);
     const int nfb = plan.level_fb_off[h + 1] - plan.level_fb_off[h];
     if (nfb > 0)
       hipLaunchKernelGGL(k_mf_fwd_bnd, dim3(nfb), dim3(kMfBndThreads), (size_t)plan.level_spmax[h] * sizeof(double),
@@ -747,8 +817,12 @@ hipError_t launch_mf_solve(const NdPlan &plan, const MfDevPlan &dp, const double
     if (nbb > 0)
       hipLaunchKernelGGL(k_mf_bwd_part, dim3(nbb), dim3(kMfBwdCols), 0, s, dp.nodes, dp.bwd_bnd + plan.level_bb_off[h],
                          dp.idx, fronts, x, pbuf);
-    hipLaunchKernelGGL(k_mf_bwd, dim3(nn), dim3(kMfSweepThreads), lds, s, dp.nodes, dp.level_nodes + n0, dp.idx,
-                       fronts, inv, zbuf, pbuf, x);
+    if (plan.level_spmax[h] <= kMfSmallSp)
+      hipLaunchKernelGGL((k_mf_bwd<64>), dim3(nn), dim3(64), lds, s, dp.nodes, dp.level_nodes + n0, dp.idx, fronts,
+                         inv, zbuf, pbuf, x);
+    else
+      hipLaunchKernelGGL((k_mf_bwd<kMfSweepThreads>), dim3(nn), dim3(kMfSweepThreads), lds, s, dp.nodes,
+                         dp.level_nodes + n0, dp.idx, fronts, inv, zbuf, pbuf, x);
   }
   return hipGetLastError();
 }
@@ -757,7 +831,14 @@ hipError_t mf_init_kernels() {
   hipError_t e = hipFuncSetAttribute((const void *)k_mf_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)kMfSweepLdsMax);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_mf_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMfSweepLdsMax);
+    e = hipFuncSetAttribute((const void *)k_mf_bwd<kMfSweepThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kMfSweepLdsMax);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_mf_bwd<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kMfSweepLdsMax);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_mf_fwd_small, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kMfSweepLdsMax);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_mf_fwd_bnd, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)kMfSweepLdsMax);
